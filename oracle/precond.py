@@ -1,0 +1,205 @@
+"""Oracle: the algebraic non-overlapping domain-decomposition preconditioner.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this module; only tests, the smoke check and the CPU-baseline leg of
+the benchmark do.
+
+Plain FP64, no blocking or fusion beyond what the paper states:
+
+* row scaling (section 5): every row of C (and of b) is divided by the
+  largest absolute value in that row;
+* blocks of P^T C P = [D E; F G] (section 3.3), D = blkDiag(A_11..A_mm)
+  (Algorithm 2);
+* interior factors: each A_jj by a LAPACK band LU with partial pivoting
+  (the section 4 remark that D_ii is factorised exactly, [L,U] = lu(D_ii));
+* mini Schur complements (section 3.1 steps 2-4; Algorithm 1):
+    MSCN      S_i = G_i - F_i D_{r_i}^{-1} E_i with the D-range of the
+              partition (interior velocity neighbours of the aggregate);
+    MSCN_LIT  the same with Algorithm 1's literal index-range pairing;
+    LUM       S_i = G_i (Definition of the LUM method);
+    EXACT_BJ  S_i = S(agg_i, agg_i), the diagonal blocks of the exact
+              Schur complement S = G - F D^{-1} E (a test reference and the
+              learned extension's target, not one of the paper's methods);
+  then Shat = blkDiag(S_i), each block LU-factorised with partial pivoting;
+* apply (Algorithm 2, with E and F placed as the block factorisation of the
+  MSCN definition requires):
+    z1 = D^{-1} y1;  x2 = Shat^{-1} (y2 - F z1);  x1 = z1 - D^{-1} (E x2).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+from scipy.linalg import lapack
+
+MSCN, MSCN_LITERAL, LUM, EXACT_BJ, LEARNED = 0, 1, 2, 3, 4
+
+
+class SingularBlock(RuntimeError):
+    pass
+
+
+def row_scale(rowptr, colidx, vals):
+    """R_ii = 1 / max_j |C_ij| (section 5); returns (R, scaled values)."""
+    rowptr = np.asarray(rowptr)
+    N = len(rowptr) - 1
+    if np.any(np.diff(rowptr) == 0):
+        raise ValueError("row scaling needs every row to hold an entry")
+    R = 1.0 / np.maximum.reduceat(np.abs(vals), rowptr[:-1])
+    rows = np.repeat(np.arange(N), np.diff(rowptr))
+    return R, vals * R[rows]
+
+
+class BandLU:
+    """LAPACK band LU with partial pivoting of one interior block."""
+
+    def __init__(self, A: sp.spmatrix):
+        A = sp.coo_matrix(A)
+        n = A.shape[0]
+        self.n = n
+        if n == 0:
+            return
+        kl = int(max(0, (A.row - A.col).max()))
+        ku = int(max(0, (A.col - A.row).max()))
+        ab = np.zeros((2 * kl + ku + 1, n))
+        ab[kl + ku + A.row - A.col, A.col] = A.data
+        lub, piv, info = lapack.dgbtrf(ab, kl, ku)
+        if info > 0:
+            raise SingularBlock(f"zero pivot at column {info - 1}")
+        self.kl, self.ku, self.lub, self.piv = kl, ku, lub, piv
+        d = np.abs(lub[kl + ku, :])
+        self.pivot_ratio = float(d.min() / max(np.abs(A.data).max(), 1e-300))
+
+    def solve(self, y):
+        if self.n == 0:
+            return np.zeros_like(y)
+        x, info = lapack.dgbtrs(self.lub, self.kl, self.ku, y, self.piv)
+        assert info == 0
+        return x
+
+
+class Preconditioner:
+    """B of the MSCN definition (section 3.3) built by Algorithm 1."""
+
+    def __init__(self, N, rowptr, colidx, vals, part, mode=MSCN, row_scaling=True,
+                 learned_S=None):
+        self.N = N
+        self.part = part
+        vals = np.asarray(vals, dtype=np.float64)
+        if row_scaling:
+            self.R, sv = row_scale(rowptr, colidx, vals)
+        else:
+            self.R, sv = np.ones(N), vals
+        self.C = sp.csr_matrix((sv, colidx, rowptr), shape=(N, N))
+        Cp = self.C[part.perm][:, part.perm].tocsr()
+        ni = part.n_int
+        self.ni = ni
+        self.E = Cp[:ni, ni:].tocsr()      # interiors x separator
+        self.F = Cp[ni:, :ni].tocsr()      # separator x interiors
+        self.G = Cp[ni:, ni:].tocsr()
+        self.blocks = []
+        for j in range(part.m):
+            a, b = part.int_offsets[j], part.int_offsets[j + 1]
+            self.blocks.append((a, b, BandLU(Cp[a:b, a:b])))
+        self.mode = mode
+        self.S_blocks = self._schur_blocks(mode, learned_S)
+        self.S_lu = []
+        for i, S in enumerate(self.S_blocks):
+            if S.shape[0] == 0:
+                self.S_lu.append(None)
+                continue
+            lu, piv = sla.lu_factor(S, check_finite=True)
+            d = np.abs(np.diag(lu))
+            if d.min() <= 1e-13 * max(np.abs(S).max(), 1e-300):
+                raise SingularBlock(f"interface block {i} is singular")
+            self.S_lu.append((lu, piv))
+
+    # ---- Algorithm 1 ----
+    def _schur_blocks(self, mode, learned_S):
+        part = self.part
+        C = self.C
+        pos = np.empty(self.N, dtype=np.int64)
+        pos[part.perm] = np.arange(self.N)
+        out = []
+        for i in range(part.k):
+            agg = part.aggregate(i)
+            Gi = C[agg][:, agg].toarray()
+            if mode == LUM:
+                out.append(Gi)
+            elif mode in (MSCN, MSCN_LITERAL):
+                dr = part.drange(i)
+                if len(dr) == 0:
+                    out.append(Gi)
+                    continue
+                Di = C[dr][:, dr].toarray()
+                Ei = C[dr][:, agg].toarray()
+                Fi = C[agg][:, dr].toarray()
+                lu, piv = sla.lu_factor(Di)
+                if np.abs(np.diag(lu)).min() <= 1e-13 * np.abs(Di).max():
+                    raise SingularBlock(f"D-range block {i} is singular")
+                out.append(Gi - Fi @ sla.lu_solve((lu, piv), Ei))
+            elif mode == EXACT_BJ:
+                cols = pos[agg] - self.ni
+                S = Gi.copy()
+                for (a, b, lu) in self.blocks:
+                    Ej = self.E[a:b][:, cols].toarray()
+                    if not Ej.any():
+                        continue
+                    Fj = self.F[cols][:, a:b].toarray()
+                    S -= Fj @ lu.solve(Ej)
+                out.append(S)
+            elif mode == LEARNED:
+                out.append(np.asarray(learned_S[i], dtype=np.float64))
+            else:
+                raise ValueError(mode)
+        return out
+
+    # ---- Algorithm 2 ----
+    def interior_solve(self, y1):
+        z = np.empty_like(y1)
+        for (a, b, lu) in self.blocks:
+            z[a:b] = lu.solve(y1[a:b])
+        return z
+
+    def schur_solve(self, t):
+        x = np.empty_like(t)
+        off = self.part.agg_offsets
+        for i, f in enumerate(self.S_lu):
+            a, b = off[i], off[i + 1]
+            if f is not None:
+                x[a:b] = sla.lu_solve(f, t[a:b])
+        return x
+
+    def apply_permuted(self, yp):
+        """x = B^{-1} y for vectors in the permuted order P^T."""
+        ni = self.ni
+        y1, y2 = yp[:ni], yp[ni:]
+        z1 = self.interior_solve(y1)
+        x2 = self.schur_solve(y2 - self.F @ z1)
+        x1 = z1 - self.interior_solve(self.E @ x2)
+        return np.concatenate([x1, x2])
+
+    def apply(self, y):
+        """x = B^{-1} y in the original numbering (y, x of the scaled system)."""
+        perm = self.part.perm
+        x = np.empty_like(y)
+        x[perm] = self.apply_permuted(y[perm])
+        return x
+
+    # ---- dense forms for small checks ----
+    def dense_blocks(self):
+        Cp = self.C[self.part.perm][:, self.part.perm].toarray()
+        ni = self.ni
+        D, E, F, G = Cp[:ni, :ni], Cp[:ni, ni:], Cp[ni:, :ni], Cp[ni:, ni:]
+        Shat = sla.block_diag(*self.S_blocks) if self.S_blocks else np.zeros((0, 0))
+        return D, E, F, G, Shat
+
+    def fill_factor(self):
+        """nnz(preconditioner factors) / nnz(C) (section 5, ff)."""
+        nz = 0
+        for (a, b, lu) in self.blocks:
+            if lu.n:
+                nz += np.count_nonzero(lu.lub)
+        nz += sum(S.size for S in self.S_blocks)
+        nz += self.E.nnz + self.F.nnz
+        return nz / self.C.nnz

@@ -1,0 +1,172 @@
+"""Pins of the oracle preconditioner against what the paper and the
+mathematics fix: the block-LU definition of B (MSCN definition, section 3.3),
+Banachiewicz's block inverse (the lemma of section 3.3), Theorem 2's spectrum,
+the LUM special case (section 5 remark that MSCN equals LUM when the coupling
+blocks vanish) and the worked example of section 3.2."""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from oracle.partition import Partition, build_partition
+from oracle.precond import EXACT_BJ, LUM, MSCN, MSCN_LITERAL, BandLU, Preconditioner, row_scale
+from workloads.mac_oseen import make_oseen_mac
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _system(n=16, nu=0.1, st=None, m=4, sz=64, seed=1001):
+    rp, ci, v, b, meta = make_oseen_mac(n, nu, stretch=st, seed=seed)
+    P = build_partition(meta["N"], rp, ci, v, m, sz)
+    return rp, ci, v, b, meta, P
+
+
+def test_row_scaling_unit_max():
+    rp, ci, v, b, meta = make_oseen_mac(10, 0.01, stretch=1.05, seed=1)
+    R, sv = row_scale(rp, ci, v)
+    for i in range(meta["N"]):
+        assert abs(np.abs(sv[rp[i]:rp[i + 1]]).max() - 1.0) < 1e-15
+
+
+def test_band_lu_matches_dense_solve():
+    rp, ci, v, b, meta, P = _system(12, 0.01, 1.05, 3, 16)
+    pre = Preconditioner(meta["N"], rp, ci, v, P, MSCN)
+    Cp = pre.C[P.perm][:, P.perm].toarray()
+    rng = np.random.default_rng(0)
+    for (a, bb, lu) in pre.blocks:
+        y = rng.standard_normal(bb - a)
+        x = lu.solve(y)
+        ref = np.linalg.solve(Cp[a:bb, a:bb], y)
+        assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("mode", [MSCN, LUM])
+def test_apply_equals_dense_block_factorisation(mode):
+    """x = B^{-1} y with B = [D 0; F S][D^-1 0; 0 S^-1][D E; 0 S] built densely."""
+    rp, ci, v, b, meta, P = _system(16, 0.1, None, 4, 24)
+    pre = Preconditioner(meta["N"], rp, ci, v, P, mode)
+    D, E, F, G, Sh = pre.dense_blocks()
+    ni, ns = D.shape[0], Sh.shape[0]
+    L = np.block([[D, np.zeros((ni, ns))], [F, Sh]])
+    M = sla.block_diag(np.linalg.inv(D), np.linalg.inv(Sh))
+    U = np.block([[D, E], [np.zeros((ns, ni)), Sh]])
+    B = L @ M @ U
+    rng = np.random.default_rng(1)
+    y = rng.standard_normal(meta["N"])
+    x = pre.apply_permuted(y)
+    ref = np.linalg.solve(B, y)
+    assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(ref)
+    # B reproduces C~ everywhere except in the separator block, where it holds
+    # G - F D^-1 E + Shat... i.e. B(2,2) = F D^-1 E + Shat
+    assert np.allclose(B[:ni, :], np.block([[D, E]]), atol=1e-12)
+    assert np.allclose(B[ni:, :ni], F, atol=1e-12)
+    assert np.allclose(B[ni:, ni:], F @ np.linalg.solve(D, E) + Sh, atol=1e-10)
+
+
+def test_exact_schur_gives_B_equal_C():
+    """Banachiewicz: with Shat = S the factorised B equals C~, so
+    apply(C~ x) = x and GMRES converges in one step."""
+    rp, ci, v, b, meta, P = _system(16, 0.1, None, 4, 10 ** 6)
+    assert P.k == 1
+    pre = Preconditioner(meta["N"], rp, ci, v, P, EXACT_BJ)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(meta["N"])
+    assert np.linalg.norm(pre.apply(pre.C @ x) - x) <= 1e-12 * np.linalg.norm(x)
+    from oracle.krylov import solve_system
+    res = solve_system(pre, b, restart=10, tol=1e-10)
+    assert res.iters == 1 and res.converged
+
+
+def test_theorem2_spectrum():
+    """B^{-1} C~ has |D| eigenvalues equal to one; the remaining ones are the
+    eigenvalues of Shat^{-1} S (Theorem 2)."""
+    rp, ci, v, b, meta, P = _system(16, 0.1, None, 4, 32)
+    pre = Preconditioner(meta["N"], rp, ci, v, P, MSCN)
+    D, E, F, G, Sh = pre.dense_blocks()
+    Cp = pre.C[P.perm][:, P.perm].toarray()
+    N = meta["N"]
+    BinvC = np.column_stack([pre.apply_permuted(Cp[:, j]) for j in range(N)])
+    ev = np.linalg.eigvals(BinvC)
+    ni = D.shape[0]
+    S = G - F @ np.linalg.solve(D, E)
+    evS = np.linalg.eigvals(np.linalg.solve(Sh, S))
+    near1 = np.abs(ev - 1.0) < 1e-8
+    assert near1.sum() >= ni
+    # the structure (expLeftPre): [[I, *], [0, Shat^-1 S]]
+    assert np.allclose(BinvC[:ni, :ni], np.eye(ni), atol=1e-9)
+    assert np.abs(BinvC[ni:, :ni]).max() < 1e-9
+    # remaining eigenvalues match those of Shat^{-1} S (as multisets)
+    rest = np.sort_complex(np.linalg.eigvals(BinvC[ni:, ni:]))
+    assert np.allclose(rest, np.sort_complex(evS), atol=1e-7)
+
+
+def test_lum_equals_mscn_when_coupling_vanishes():
+    """S_i = G_i - F_i D^-1 E_i reduces to G_i when E_i = F_i = 0."""
+    rp, ci, v, b, meta, P = _system(16, 0.1, None, 4, 24)
+    C = sp.csr_matrix((v, ci, rp)).tolil()
+    sep = set(P.separator().tolist())
+    dn = set(P.drange_nodes.tolist())
+    coo = sp.csr_matrix((v, ci, rp)).tocoo()
+    for r, c in zip(coo.row, coo.col):
+        if (r in sep and c in dn) or (r in dn and c in sep):
+            C[r, c] = 0.0
+    C = C.tocsr()
+    C.sort_indices()
+    p1 = Preconditioner(meta["N"], C.indptr, C.indices, C.data, P, MSCN)
+    p2 = Preconditioner(meta["N"], C.indptr, C.indices, C.data, P, LUM)
+    for a, bb in zip(p1.S_blocks, p2.S_blocks):
+        assert np.array_equal(a, bb)
+
+
+def test_single_subdomain_is_exact():
+    rp, ci, v, b, meta = make_oseen_mac(8, 0.1, seed=3)
+    P = build_partition(meta["N"], rp, ci, v, 1, 8)
+    pre = Preconditioner(meta["N"], rp, ci, v, P, MSCN)
+    x = np.random.default_rng(0).standard_normal(meta["N"])
+    assert np.linalg.norm(pre.apply(pre.C @ x) - x) <= 1e-12 * np.linalg.norm(x)
+
+
+def _read_fig1():
+    d = {}
+    with open(os.path.join(GOLDEN, "fig1_aggregates.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, *rest = line.split()
+            d[k] = rest
+    return d
+
+
+def test_fig1_block_extraction():
+    """Section 3.2 worked example: uneven consecutive aggregates of a 16-node
+    G, the 4th local matrix is C([10,11,26,27],[10,11,26,27])."""
+    g = _read_fig1()
+    nD, nG = int(g["n_D"][0]), int(g["n_G"][0])
+    aggs = [[int(t) for t in a.split(",")] for a in g["aggregates"]]
+    k4 = int(g["check_aggregate"][0]) - 1
+    want = [int(t) - 1 for t in g["local_matrix_global_indices"]]
+    N = nD + nG
+    rng = np.random.default_rng(5)
+    C = rng.standard_normal((N, N)) + 8 * N * np.eye(N)
+    Cs = sp.csr_matrix(C)
+    offs = np.concatenate([[0], np.cumsum([len(a) for a in aggs])])
+    assert offs[-1] == nG and [a[0] for a in aggs] == [o + 1 for o in offs[:-1]]
+    P = Partition(N=N, m=1, sz=0, perm=np.arange(N), part=np.r_[np.zeros(nD, int), -np.ones(nG, int)],
+                  int_offsets=np.array([0, nD]), sep_size=nG, agg_offsets=offs,
+                  drange_offsets=offs.copy(), drange_nodes=np.arange(nG), pair=-np.ones(nG, int))
+    pre = Preconditioner(N, Cs.indptr, Cs.indices, Cs.data, P, MSCN_LITERAL, row_scaling=False)
+    idx = [int(t) for t in P.drange(k4)] + [int(t) for t in P.aggregate(k4)]
+    assert idx == want
+    Cl = C[np.ix_(want, want)]
+    Dl, El, Fl, Gl = Cl[:2, :2], Cl[:2, 2:], Cl[2:, :2], Cl[2:, 2:]
+    assert np.allclose(pre.S_blocks[k4], Gl - Fl @ np.linalg.solve(Dl, El), rtol=0, atol=1e-13)
+
+
+def test_singular_interior_detected_without_closure():
+    """A pressure-only diagonal block (zero rows) must be reported singular."""
+    A = sp.csr_matrix(np.array([[0.0, 1.0], [1.0, 0.0]]))
+    BandLU(A)  # nonsingular with pivoting
+    with pytest.raises(Exception):
+        BandLU(sp.csr_matrix(np.array([[0.0, 0.0], [0.0, 1.0]])))
