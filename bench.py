@@ -1,0 +1,169 @@
+"""Benchmark: time to a 1e-8 true relative residual and preconditioner-apply
+bandwidth on one MI355X.
+
+One step = setup_precond + gmres_solve (FGMRES(50), tol 1e-8) on the
+128 x 128 uniform MAC Oseen cavity (nu = 1/100, 16 subdomains, FP32 interior
+and interface factors, FP64 outer solver), inputs resident in HBM.  The
+partition is built once beforehand and excluded, as in the paper's timings.
+
+Prints one JSON line.  --gpus above 1 is not supported (one GPU per box).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def _events_ms(fn, reps, torch):
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(cfg, its_gpu, budget_s=20.0):
+    """The oracle as it stands on the host: setup plus a bounded number of
+    FGMRES iterations, scaled to a full solve of its_gpu iterations."""
+    import numpy as np
+
+    from oracle.krylov import gmres
+    from oracle.partition import build_partition as oracle_partition
+    from oracle.precond import MSCN, Preconditioner
+
+    rp, ci, v, b, meta = cfg.build()
+    N = meta["N"]
+    P = oracle_partition(N, rp, ci, v, cfg.m, cfg.sz)
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    pre = Preconditioner(N, rp, ci, v, P, MSCN)
+    t_setup = time.perf_counter() - t0
+    # bounded sample: iterations until the budget is used
+    probe = 20
+    t1 = time.perf_counter()
+    gmres(lambda z: pre.C @ z, pre.apply, pre.R * b, restart=cfg.restart, tol=1e-300, maxit=probe,
+          flexible=cfg.flexible)
+    per_it = (time.perf_counter() - t1) / probe
+    k = int(max(probe, min(its_gpu, (budget_s - t_setup) / max(per_it, 1e-9))))
+    t2 = time.perf_counter()
+    gmres(lambda z: pre.C @ z, pre.apply, pre.R * b, restart=cfg.restart, tol=1e-300, maxit=k,
+          flexible=cfg.flexible)
+    t_it = (time.perf_counter() - t2) / k
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    est = t_setup + its_gpu * t_it
+    return {"value": round(est, 4), "unit": "s", "cores": max(1, int(round(cpu / wall))),
+            "kind": "oracle",
+            "sample": f"oracle setup ({t_setup:.2f} s) + {k + probe} FGMRES({cfg.restart}) iterations "
+                      f"({t_it * 1e3:.1f} ms each), scaled to the GPU's {its_gpu} iterations; "
+                      f"host cpus {os.cpu_count()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the multi-GPU path is a design, not a build "
+              "(every box here has one GPU)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1104_3349_amd import addns
+    from workloads.configs import CFG2 as cfg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rp, ci, v, b, meta = cfg.build()
+    N = meta["N"]
+    part = addns.build_partition(N, rp, ci, v, cfg.m, cfg.sz)
+    d_rp, d_ci, d_v = (torch.from_numpy(a).to(dev) for a in (rp, ci, v))
+    d_b = torch.from_numpy(b).to(dev)
+    d_x = torch.zeros(N, dtype=torch.float64, device=dev)
+    maxit = 20000
+
+    def step(iprec, sprec):
+        pc = addns.setup_precond(part, N, d_rp, d_ci, d_v, interior_prec=iprec, schur_prec=sprec)
+        d_x.zero_()
+        r = addns.gmres_solve(pc, d_b, d_x, restart=cfg.restart, maxit=maxit, tol=cfg.tol,
+                              flexible=cfg.flexible)
+        return pc, r
+
+    iprec, sprec = addns.F32, addns.F32
+    for _ in range(args.warmup):
+        step(iprec, sprec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(args.steps):
+        pc, r = step(iprec, sprec)
+        results.append(r)
+    torch.cuda.synchronize()
+    T = (time.perf_counter() - t0) / max(args.steps, 1)
+    r = results[-1]
+    info = pc.info()
+
+    # apply bandwidth and the dominant kernel (interior solve) by HIP events
+    d_y = torch.randn(N, dtype=torch.float64, device=dev)
+    d_o = torch.empty_like(d_y)
+    t_apply = _events_ms(lambda: addns.apply_precond(pc, d_y, d_o), 50, torch)
+    n_int = int(part.info()["n_interior"])
+    d_y1 = torch.randn(n_int, dtype=torch.float64, device=dev)
+    d_z1 = torch.empty_like(d_y1)
+    t_int = _events_ms(lambda: addns.interior_solve(pc, d_y1, d_z1), 50, torch)
+    sf = 4 if iprec == addns.F32 else 8
+    b_int = n_int * (2 * info["kl"] + info["ku"] + 1) * sf + 4 * n_int + 16 * n_int
+    peak = 8.0e12
+    achieved = b_int / (t_int * 1e-3)
+
+    plain = None
+    if not args.no_plain:
+        t1 = time.perf_counter()
+        _, rp64 = step(addns.F64, addns.F64)
+        torch.cuda.synchronize()
+        plain = {"seconds": round(time.perf_counter() - t1, 4), "iters": rp64["iters"],
+                 "true_relres": rp64["true_relres"]}
+
+    line = {
+        "metric": "time to 1e-8 rel. residual (s) + precond-apply GB/s; plain FP64 vs mixed/learned",
+        "value": round(T, 5), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(T * 1e3, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 outer / f32 factors", "data": "synthetic",
+        "config": {"workload": cfg.name, "N": N, "nnz": int(len(v)), "subdomains": cfg.m,
+                   "aggregate_size": cfg.sz, "krylov": f"FGMRES({cfg.restart})", "tol": cfg.tol,
+                   "factors": "f32/f32"},
+        "iters": r["iters"], "converged": r["converged"], "true_relres": r["true_relres"],
+        "apply_ms": round(t_apply, 4),
+        "apply_GBps": round(info["bytes_apply"] / (t_apply * 1e-3) / 1e9, 2),
+        "apply_frac_hbm": round(info["bytes_apply"] / (t_apply * 1e-3) / peak, 4),
+        "plain_f64": plain,
+        "roofline": {"bound": "hbm", "kernel": "k_interior_solve", "achieved": round(achieved / 1e9, 2),
+                     "peak": peak / 1e9, "unit": "GB/s", "frac": round(achieved / peak, 4),
+                     "traffic": None, "launch_ms": round(t_int, 4), "bytes_per_launch": int(b_int)},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, r["iters"])
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * libaddns -- algebraic non-overlapping domain decomposition preconditioner
+ * inside restarted (F)GMRES for block 2x2 saddle-point (Oseen) systems,
+ * native to AMD Instinct MI355X (gfx950).
+ *
+ * The method (Kumar, "Purely algebraic domain decomposition methods for the
+ * incompressible Navier-Stokes equations"):
+ *   - the matrix is the only input (section 1: the method takes the matrix
+ *     and right-hand side as its input); rows are scaled by their largest
+ *     absolute entry (section 5);
+ *   - a graph partition gives P^T C P = [D E; F G], D = blkDiag(A_11..A_mm)
+ *     (section 1; section 3.3);
+ *   - mini Schur complements S_i = G_i - F_i D_{r_i}^{-1} E_i on aggregates
+ *     of consecutively numbered interface nodes form Shat = blkDiag(S_i)
+ *     (section 3.1; Algorithm 1);
+ *   - B = [D 0; F Shat][D^-1 0; 0 Shat^-1][D E; 0 Shat] (MSCN definition,
+ *     section 3.3) is applied by Algorithm 2;
+ *   - B is used as a right preconditioner of restarted GMRES (section 5 and
+ *     the right-preconditioning remark of section 3.3).
+ *
+ * Conventions for every call:
+ *   - indices are int32, values float64 at the boundary;
+ *   - the caller owns every buffer it passes; the library owns its handles
+ *     and the device memory behind them (freed by the *_destroy calls);
+ *   - a call returns ADDNS_OK (0), a positive warning, or a negative error;
+ *     addns_last_error() then holds a message for the calling thread.  No C++
+ *     exception crosses this boundary;
+ *   - "device" pointers are HIP device allocations on the current device;
+ *     `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *   - a handle must not be used from two threads at once.
+ */
+#ifndef ADDNS_H
+#define ADDNS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct addns_partition* addns_partition_t;
+typedef struct addns_precond* addns_precond_t;
+
+enum {
+  ADDNS_OK = 0,
+  ADDNS_WARN_SHARED_PAIR = 1, /* a closure node shares its paired interface node */
+  ADDNS_ERR_ARG = -1,         /* invalid argument (message names it) */
+  ADDNS_ERR_SINGULAR = -2,    /* zero/tiny pivot; message names the block */
+  ADDNS_ERR_NOCONV = -3,      /* GMRES stopped at maxit above tol */
+  ADDNS_ERR_HIP = -4,         /* a HIP runtime call failed */
+  ADDNS_ERR_PARTITION = -5,   /* the graph could not be partitioned as asked */
+  ADDNS_ERR_NOMEM = -6        /* host or device allocation failed */
+};
+
+/* Interface (Schur) approximation, Algorithm 1. */
+enum {
+  ADDNS_SCHUR_MSCN = 0,         /* S_i = G_i - F_i D_{r_i}^-1 E_i, D-range = interior
+                                   velocity neighbours of the aggregate (section 3.1
+                                   step 2b: D_{r_i} "slightly larger" than G_i) */
+  ADDNS_SCHUR_MSCN_LITERAL = 1, /* D-range = the same positions of D (Algorithm 1) */
+  ADDNS_SCHUR_LUM = 2,          /* S_i = G_i (LUM definition, section 3.3) */
+  ADDNS_SCHUR_EXACT_BJ = 3,     /* diagonal blocks of the exact S = G - F D^-1 E */
+  ADDNS_SCHUR_LEARNED = 4       /* G_i plus a learned correction (opts.learned_model) */
+};
+
+/* Storage precision of the preconditioner's factors (arithmetic is FP64 for
+   the outer solver in every mode). */
+enum { ADDNS_F64 = 0, ADDNS_F32 = 1, ADDNS_F16_SCALED = 2 };
+
+/* ------------------------------------------------------------------------
+ * addns_build_partition -- substructuring of C (section 1, the graph
+ * partitioner paragraph; section 3.3).  Host-only integer work apart from
+ * one exact-zero floating-point test; deterministic.
+ *
+ *   N, rowptr[N+1], colidx[nnz], vals[nnz]: HOST CSR of C (int32 / float64).
+ *   m   : number of subdomains (>= 1), the nA of the paper's tables.
+ *   sz  : aggregate size (>= 1), the paper's "sz" (MSC size).
+ *   out : receives a new handle on success (unchanged on error).
+ * The partition (recursive level-set bisection with a velocity-only
+ * separator, closure of interior pressure components, reverse Cuthill-McKee
+ * interior orderings, consecutive aggregates of size sz and their D-ranges)
+ * keeps a copy of the pattern; the caller's arrays may be freed afterwards.
+ * Returns ADDNS_OK, ADDNS_WARN_SHARED_PAIR, ADDNS_ERR_ARG or ADDNS_ERR_NOMEM.
+ */
+int addns_build_partition(int32_t N, const int32_t* rowptr, const int32_t* colidx,
+                          const double* vals, int32_t m, int32_t sz, addns_partition_t* out);
+
+/* Sizes of a partition: any pointer may be NULL. */
+int addns_partition_info(addns_partition_t p, int32_t* N, int32_t* m, int32_t* n_interior,
+                         int32_t* sep_size, int32_t* k, int32_t* drange_total);
+
+/* ------------------------------------------------------------------------
+ * addns_partition_export -- copy the partition into caller-owned HOST
+ * arrays (any may be NULL):
+ *   perm[N]           new position -> original index ([int_0..int_m-1, Sigma])
+ *   part[N]           original index -> subdomain id, -1 = separator
+ *   int_offsets[m+1]  offsets of the interiors in perm
+ *   agg_offsets[k+1]  aggregate breakpoints r_i (0-based) in the separator order
+ *   drange_offsets[k+1], drange_nodes[drange_total]: D-ranges (original indices)
+ *   pair[sep_size]    per separator position: paired node (original) or -1
+ */
+int addns_partition_export(addns_partition_t p, int32_t* perm, int32_t* part,
+                           int32_t* int_offsets, int32_t* agg_offsets, int32_t* drange_offsets,
+                           int32_t* drange_nodes, int32_t* pair);
+
+typedef struct {
+  int32_t schur;          /* ADDNS_SCHUR_* */
+  int32_t interior_prec;  /* ADDNS_F64 or ADDNS_F32: storage of the A_jj factors */
+  int32_t schur_prec;     /* ADDNS_F64, ADDNS_F32 or ADDNS_F16_SCALED: Shat^-1 */
+  int32_t row_scale;      /* 1 = scale rows by their max |entry| (the paper's default) */
+  const double* learned_delta; /* LEARNED only: HOST array, one correction per
+                                  stored entry of G_i in aggregate order, row-major
+                                  per block (addns_precond_info gives the count) */
+} addns_precond_opts;
+
+/* ------------------------------------------------------------------------
+ * addns_setup_precond -- Algorithm 1 plus the exact interior factorisations
+ * ([L,U] = lu(A_jj), section 4).  All floating-point work runs on the GPU.
+ *
+ *   p      : partition built from the same pattern (rowptr/colidx equal).
+ *   N, d_rowptr, d_colidx, d_vals: DEVICE CSR of C (unscaled); read during
+ *            the call only.
+ *   opts   : NULL = MSCN, FP64 factors, row scaling on.
+ *   stream : hipStream_t as void*; the call returns after the setup work has
+ *            completed on that stream.
+ *   out    : receives a new handle.  The handle owns a scaled, permuted copy
+ *            of C and all factors.
+ * Errors: ADDNS_ERR_ARG (size mismatch), ADDNS_ERR_SINGULAR (an interior or
+ * interface block has a zero pivot; message names it), ADDNS_ERR_HIP,
+ * ADDNS_ERR_NOMEM.
+ */
+int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
+                        const int32_t* d_colidx, const double* d_vals,
+                        const addns_precond_opts* opts, void* stream, addns_precond_t* out);
+
+/* ------------------------------------------------------------------------
+ * addns_apply_precond -- Algorithm 2: x = B^{-1} y,
+ *   z1 = D^-1 y1;  x2 = Shat^-1 (y2 - F z1);  x1 = z1 - D^-1 (E x2),
+ * for DEVICE vectors of length N in the ORIGINAL numbering of the scaled
+ * system (y, x must not alias).  Asynchronous on `stream`.
+ */
+int addns_apply_precond(addns_precond_t pc, const double* d_y, double* d_x, void* stream);
+
+/* ------------------------------------------------------------------------
+ * addns_interior_solve -- the interior block solve of Algorithm 2 on its
+ * own: z1 = D^{-1} y1 with D = blkDiag(A_11..A_mm), for DEVICE vectors of
+ * length n_interior in the PERMUTED interior order (perm[0..n_interior) of
+ * addns_partition_export).  y1 and z1 must not alias.  Asynchronous on
+ * `stream`.  Runs the same kernel as the two interior sweeps of
+ * addns_apply_precond.
+ */
+int addns_interior_solve(addns_precond_t pc, const double* d_y1, double* d_z1, void* stream);
+
+typedef struct {
+  int32_t restart;   /* Krylov dimension per cycle (>= 1) */
+  int32_t maxit;     /* total inner iterations allowed */
+  double tol;        /* stop when ||b~ - C~ x|| / ||b~|| <= tol */
+  int32_t flexible;  /* 1 = FGMRES (store Z), 0 = GMRES (x += B^-1 V y) */
+  int32_t use_x0;    /* 1 = d_x holds the initial guess, 0 = start from zero */
+} addns_gmres_opts;
+
+typedef struct {
+  int32_t iters;         /* inner iterations taken */
+  int32_t cycles;        /* restart cycles */
+  int32_t converged;     /* 1 if the true relative residual <= tol */
+  double true_relres;    /* ||b~ - C~ x|| / ||b~|| of the returned x (scaled system) */
+  double est_relres;     /* |g_{j+1}| / ||b~|| at the last iteration */
+  double* resid_hist;    /* optional HOST array of maxit+1 entries (may be NULL):
+                            estimated relative residual after each iteration */
+} addns_gmres_result;
+
+/* ------------------------------------------------------------------------
+ * addns_gmres_solve -- restarted (F)GMRES with right preconditioning by B,
+ * modified Gram-Schmidt Arnoldi and Givens rotations, all in FP64 on the
+ * GPU (section 5 accelerator).  Solves C x = b through the row-scaled system.
+ *   d_b : DEVICE right-hand side of the unscaled system (length N).
+ *   d_x : DEVICE solution (length N); initial guess if opts.use_x0.
+ * Returns after completion.  ADDNS_ERR_NOCONV when maxit is reached above
+ * tol (x then holds the last iterate and res the true residual).
+ */
+int addns_gmres_solve(addns_precond_t pc, const double* d_b, double* d_x,
+                      const addns_gmres_opts* opts, addns_gmres_result* res, void* stream);
+
+/* Sizes of a preconditioner: any pointer may be NULL.  bytes_apply is the
+   number of bytes the apply reads from its stored factors per call. */
+int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb_lower,
+                       int32_t* nb_upper, int64_t* factor_bytes, int64_t* bytes_apply,
+                       int64_t* learned_count);
+
+/* Copy the dense interface blocks S_i (before inversion) into a HOST array
+   in aggregate order, row-major per block; `count` must equal the sum of
+   |agg_i|^2. */
+int addns_precond_schur_blocks(addns_precond_t pc, double* h_out, int64_t count);
+
+void addns_partition_destroy(addns_partition_t p);
+void addns_precond_destroy(addns_precond_t pc);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* addns_last_error(void);
+
+/* Library version string. */
+const char* addns_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADDNS_H */

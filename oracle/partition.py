@@ -235,14 +235,12 @@ def _closure(N, rowptr, colidx, vals, H, is_p, part, m):
         pn = nodes[is_p[nodes]]
         if pn.size == 0:
             continue
-        vn = nodes[~is_p[nodes]]
         # bipartite pressure/velocity graph inside the interior
         sub = H[nodes][:, nodes].tocoo()
         keep = is_p[nodes[sub.row]] != is_p[nodes[sub.col]]
         Bg = sp.csr_matrix((np.ones(int(keep.sum())), (sub.row[keep], sub.col[keep])),
                            shape=(len(nodes), len(nodes)))
         ncomp, lab = csg.connected_components(Bg, directed=False)
-        plab = lab[is_p[nodes]]
         comps = {}
         for q_local, q in zip(np.nonzero(is_p[nodes])[0], pn):
             comps.setdefault(lab[q_local], []).append(int(q))
@@ -318,7 +316,7 @@ def _rcm(H, nodes):
 # driver
 # --------------------------------------------------------------------------
 
-def build_partition(N, rowptr, colidx, vals, m, sz, literal_drange=False) -> Partition:
+def build_partition(N, rowptr, colidx, vals, m, sz) -> Partition:
     rowptr = np.asarray(rowptr, dtype=np.int64)
     colidx = np.asarray(colidx, dtype=np.int64)
     vals = np.asarray(vals, dtype=np.float64)
@@ -367,26 +365,18 @@ def build_partition(N, rowptr, colidx, vals, m, sz, literal_drange=False) -> Par
 
     # (vii) D-ranges
     n_int = offs[-1]
-    if literal_drange:
-        if n_int < nsep:
-            raise ValueError("literal D-range pairing needs |D| >= |Sigma|")
-        dn, do = [], [0]
-        for i in range(len(agg) - 1):
-            dn.extend(perm[agg[i]:agg[i + 1]].tolist())
-            do.append(len(dn))
-    else:
-        assigned = np.zeros(N, dtype=bool)
-        interior_vel = (part >= 0) & ~is_p
-        Hi, Hp = H.indices, H.indptr
-        dn, do = [], [0]
-        sep_nodes = perm[n_int:]
-        for i in range(len(agg) - 1):
-            for g in sep_nodes[agg[i]:agg[i + 1]]:
-                nb = Hi[Hp[g]:Hp[g + 1]]
-                nb = nb[interior_vel[nb] & ~assigned[nb]]
-                assigned[nb] = True
-                dn.extend(int(x) for x in nb)
-            do.append(len(dn))
+    assigned = np.zeros(N, dtype=bool)
+    interior_vel = (part >= 0) & ~is_p
+    Hi, Hp = H.indices, H.indptr
+    dn, do = [], [0]
+    sep_nodes = perm[n_int:]
+    for i in range(len(agg) - 1):
+        for g in sep_nodes[agg[i]:agg[i + 1]]:
+            nb = Hi[Hp[g]:Hp[g + 1]]
+            nb = nb[interior_vel[nb] & ~assigned[nb]]
+            assigned[nb] = True
+            dn.extend(int(x) for x in nb)
+        do.append(len(dn))
     return Partition(N=N, m=m, sz=sz, perm=perm.astype(np.int64), part=part,
                      int_offsets=np.array(offs, dtype=np.int64), sep_size=nsep,
                      agg_offsets=agg, drange_offsets=np.array(do, dtype=np.int64),

@@ -127,7 +127,13 @@ class Preconditioner:
             if mode == LUM:
                 out.append(Gi)
             elif mode in (MSCN, MSCN_LITERAL):
-                dr = part.drange(i)
+                if mode == MSCN_LITERAL:
+                    # Algorithm 1's pairing: the same local positions of D
+                    if part.n_int < part.sep_size:
+                        raise ValueError("literal D-range pairing needs |D| >= |Sigma|")
+                    dr = part.perm[part.agg_offsets[i]:part.agg_offsets[i + 1]]
+                else:
+                    dr = part.drange(i)
                 if len(dr) == 0:
                     out.append(Gi)
                     continue

@@ -1,0 +1,245 @@
+"""Thin ctypes binding of libaddns (argument marshalling only).
+
+Every function here has the name of the C entry point it wraps, minus the
+``addns_`` prefix.  No arithmetic of the method happens in Python: host
+arrays are passed as numpy buffers, device arrays as torch CUDA tensors
+(their data pointers), streams as torch.cuda.Stream handles.  If the shared
+library is missing the import fails loudly; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libaddns.so")
+
+OK, WARN_SHARED_PAIR = 0, 1
+ERR_ARG, ERR_SINGULAR, ERR_NOCONV, ERR_HIP, ERR_PARTITION, ERR_NOMEM = -1, -2, -3, -4, -5, -6
+SCHUR_MSCN, SCHUR_MSCN_LITERAL, SCHUR_LUM, SCHUR_EXACT_BJ, SCHUR_LEARNED = 0, 1, 2, 3, 4
+F64, F32, F16_SCALED = 0, 1, 2
+
+EXPORTED = [
+    "addns_build_partition", "addns_partition_info", "addns_partition_export",
+    "addns_setup_precond", "addns_apply_precond", "addns_interior_solve", "addns_gmres_solve", "addns_precond_info",
+    "addns_precond_schur_blocks", "addns_partition_destroy", "addns_precond_destroy",
+    "addns_last_error", "addns_version",
+]
+
+
+class AddnsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libaddns error {code}: {msg}")
+        self.code = code
+
+
+class PrecondOpts(C.Structure):
+    _fields_ = [("schur", C.c_int32), ("interior_prec", C.c_int32), ("schur_prec", C.c_int32),
+                ("row_scale", C.c_int32), ("learned_delta", C.POINTER(C.c_double))]
+
+
+class GmresOpts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("tol", C.c_double),
+                ("flexible", C.c_int32), ("use_x0", C.c_int32)]
+
+
+class GmresResult(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("cycles", C.c_int32), ("converged", C.c_int32),
+                ("true_relres", C.c_double), ("est_relres", C.c_double),
+                ("resid_hist", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libaddns.so not built at {LIB_PATH}; run "
+                          "`python -m paper_1104_3349_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    i32p, f64p, i64p = C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_int64)
+    sig = {
+        "addns_build_partition": (C.c_int, [C.c_int32, P, P, P, C.c_int32, C.c_int32, C.POINTER(P)]),
+        "addns_partition_info": (C.c_int, [P, i32p, i32p, i32p, i32p, i32p, i32p]),
+        "addns_partition_export": (C.c_int, [P, P, P, P, P, P, P, P]),
+        "addns_setup_precond": (C.c_int, [P, C.c_int32, P, P, P, C.POINTER(PrecondOpts), P,
+                                          C.POINTER(P)]),
+        "addns_apply_precond": (C.c_int, [P, P, P, P]),
+        "addns_interior_solve": (C.c_int, [P, P, P, P]),
+        "addns_gmres_solve": (C.c_int, [P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresResult), P]),
+        "addns_precond_info": (C.c_int, [P, i32p, i32p, i32p, i32p, i64p, i64p, i64p]),
+        "addns_precond_schur_blocks": (C.c_int, [P, P, C.c_int64]),
+        "addns_partition_destroy": (None, [P]),
+        "addns_precond_destroy": (None, [P]),
+        "addns_last_error": (C.c_char_p, []),
+        "addns_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(code, what):
+    if code < 0:
+        raise AddnsError(code, f"{what}: {lib().addns_last_error().decode()}")
+    return code
+
+
+def _ptr(a):
+    """Data pointer of a numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags.c_contiguous
+        return a.ctypes.data
+    assert a.is_contiguous()
+    return a.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return s.cuda_stream if hasattr(s, "cuda_stream") else s
+
+
+# --------------------------------------------------------------------------
+# partitions
+# --------------------------------------------------------------------------
+
+@dataclass
+class PartitionArrays:
+    perm: np.ndarray
+    part: np.ndarray
+    int_offsets: np.ndarray
+    agg_offsets: np.ndarray
+    drange_offsets: np.ndarray
+    drange_nodes: np.ndarray
+    pair: np.ndarray
+    status: int
+
+
+class Partition:
+    def __init__(self, handle, status):
+        self.handle = handle
+        self.status = status
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.addns_partition_destroy(self.handle)
+            self.handle = None
+
+    def info(self):
+        v = [C.c_int32() for _ in range(6)]
+        _check(lib().addns_partition_info(self.handle, *[C.byref(x) for x in v]), "partition_info")
+        return dict(zip(("N", "m", "n_interior", "sep_size", "k", "drange_total"),
+                        (x.value for x in v)))
+
+    def export(self) -> PartitionArrays:
+        inf = self.info()
+        N, m, k = inf["N"], inf["m"], inf["k"]
+        arr = dict(perm=np.empty(N, np.int32), part=np.empty(N, np.int32),
+                   int_offsets=np.empty(m + 1, np.int32), agg_offsets=np.empty(k + 1, np.int32),
+                   drange_offsets=np.empty(k + 1, np.int32),
+                   drange_nodes=np.empty(inf["drange_total"], np.int32),
+                   pair=np.empty(inf["sep_size"], np.int32))
+        _check(lib().addns_partition_export(self.handle, *[_ptr(arr[n]) for n in (
+            "perm", "part", "int_offsets", "agg_offsets", "drange_offsets", "drange_nodes",
+            "pair")]), "partition_export")
+        return PartitionArrays(status=self.status, **arr)
+
+
+def build_partition(N, rowptr, colidx, vals, m, sz) -> Partition:
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    colidx = np.ascontiguousarray(colidx, dtype=np.int32)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    h = C.c_void_p()
+    st = _check(lib().addns_build_partition(int(N), _ptr(rowptr), _ptr(colidx), _ptr(vals),
+                                            int(m), int(sz), C.byref(h)), "build_partition")
+    return Partition(h, st)
+
+
+# --------------------------------------------------------------------------
+# preconditioner and solver
+# --------------------------------------------------------------------------
+
+class Precond:
+    def __init__(self, handle, partition):
+        self.handle = handle
+        self.partition = partition  # keep alive
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.addns_precond_destroy(self.handle)
+            self.handle = None
+
+    def info(self):
+        i32 = [C.c_int32() for _ in range(4)]
+        i64 = [C.c_int64() for _ in range(3)]
+        _check(lib().addns_precond_info(self.handle, *[C.byref(x) for x in i32 + i64]),
+               "precond_info")
+        return dict(zip(("kl", "ku", "nb_lower", "nb_upper", "factor_bytes", "bytes_apply",
+                         "learned_count"), (x.value for x in i32 + i64)))
+
+    def schur_blocks(self, count):
+        out = np.empty(int(count), np.float64)
+        _check(lib().addns_precond_schur_blocks(self.handle, _ptr(out), int(count)),
+               "precond_schur_blocks")
+        return out
+
+
+def setup_precond(partition: Partition, N, d_rowptr, d_colidx, d_vals, schur=SCHUR_MSCN,
+                  interior_prec=F64, schur_prec=F64, row_scale=1, learned_delta=None,
+                  stream=None) -> Precond:
+    opts = PrecondOpts(int(schur), int(interior_prec), int(schur_prec), int(row_scale), None)
+    if learned_delta is not None:
+        ld = np.ascontiguousarray(learned_delta, dtype=np.float64)
+        opts.learned_delta = ld.ctypes.data_as(C.POINTER(C.c_double))
+    h = C.c_void_p()
+    _check(lib().addns_setup_precond(partition.handle, int(N), _ptr(d_rowptr), _ptr(d_colidx),
+                                     _ptr(d_vals), C.byref(opts), _stream(stream), C.byref(h)),
+           "setup_precond")
+    return Precond(h, partition)
+
+
+def apply_precond(pc: Precond, d_y, d_x, stream=None):
+    _check(lib().addns_apply_precond(pc.handle, _ptr(d_y), _ptr(d_x), _stream(stream)),
+           "apply_precond")
+
+
+def interior_solve(pc: Precond, d_y1, d_z1, stream=None):
+    _check(lib().addns_interior_solve(pc.handle, _ptr(d_y1), _ptr(d_z1), _stream(stream)),
+           "interior_solve")
+
+
+def gmres_solve(pc: Precond, d_b, d_x, restart=50, maxit=1000, tol=1e-8, flexible=True,
+                use_x0=False, history=False, stream=None, raise_noconv=False):
+    opts = GmresOpts(int(restart), int(maxit), float(tol), int(bool(flexible)), int(bool(use_x0)))
+    res = GmresResult()
+    hist = None
+    if history:
+        hist = np.zeros(int(maxit) + 1, np.float64)
+        res.resid_hist = hist.ctypes.data_as(C.POINTER(C.c_double))
+    code = lib().addns_gmres_solve(pc.handle, _ptr(d_b), _ptr(d_x), C.byref(opts), C.byref(res),
+                                   _stream(stream))
+    if code < 0 and (code != ERR_NOCONV or raise_noconv):
+        _check(code, "gmres_solve")
+    out = dict(iters=res.iters, cycles=res.cycles, converged=bool(res.converged),
+               true_relres=res.true_relres, est_relres=res.est_relres, code=code)
+    if history:
+        out["history"] = hist[:res.iters]
+    return out
+
+
+def version() -> str:
+    return lib().addns_version().decode()

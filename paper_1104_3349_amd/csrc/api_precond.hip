@@ -1,0 +1,450 @@
+// C-ABI entry points: setup_precond (Algorithm 1 + interior factorisation),
+// apply_precond (Algorithm 2) and gmres_solve (restarted right-preconditioned
+// (F)GMRES with MGS Arnoldi and Givens rotations).  Host code only orders
+// kernel launches, moves a few scalars and owns device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "precond.h"
+
+using namespace addns;
+
+namespace {
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+template <class F>
+int guarded(const char* what, F&& f) {
+  try {
+    return f();
+  } catch (const ArgError& e) {
+    set_error(std::string(what) + ": " + e.what());
+    return ADDNS_ERR_ARG;
+  } catch (const SingularError& e) {
+    set_error(std::string(what) + ": " + e.what());
+    return ADDNS_ERR_SINGULAR;
+  } catch (const HipError& e) {
+    set_error(std::string(what) + ": " + e.what());
+    return ADDNS_ERR_HIP;
+  } catch (const std::bad_alloc&) {
+    set_error(std::string(what) + ": out of host memory");
+    return ADDNS_ERR_NOMEM;
+  } catch (const std::exception& e) {
+    set_error(std::string(what) + ": " + e.what());
+    return ADDNS_ERR_HIP;
+  }
+}
+
+int prec_bytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
+
+// Factor and interface storage of one preconditioner.
+void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_rowptr, const int32_t* d_colidx,
+                  const double* d_vals, const addns_precond_opts& o, hipStream_t s) {
+  Plan& pl = pc->plan;
+  build_plan(P, pl, o.schur);
+  const int32_t N = pl.N;
+  const int64_t nnz = (int64_t)pl.cp_colidx.size();
+
+  // -- permuted, row-scaled C~
+  DevBuf d_src, d_orow;
+  d_src.upload(pl.cp_src, s);
+  d_orow.upload(pl.cp_orow, s);
+  pc->perm.upload(pl.perm, s);
+  pc->iperm.upload(pl.iperm, s);
+  pc->R.alloc(sizeof(double) * N);
+  launch_row_scale(d_rowptr, d_vals, N, o.row_scale, pc->R.as<double>(), s);
+  pc->cp_rowptr.upload(pl.cp_rowptr, s);
+  pc->cp_colidx.upload(pl.cp_colidx, s);
+  pc->cp_vals.alloc(sizeof(double) * nnz);
+  launch_gather_scaled(d_src.as<int32_t>(), d_orow.as<int32_t>(), d_vals, pc->R.as<double>(), nnz,
+                       pc->cp_vals.as<double>(), s);
+  const double* cpv = pc->cp_vals.as<double>();
+
+  // -- E and F
+  {
+    DevBuf es, fs;
+    es.upload(pl.e_src, s);
+    fs.upload(pl.f_src, s);
+    pc->e_rowptr.upload(pl.e_rowptr, s);
+    pc->e_colidx.upload(pl.e_colidx, s);
+    pc->e_vals.alloc(sizeof(double) * pl.e_src.size());
+    launch_gather(es.as<int32_t>(), cpv, (int64_t)pl.e_src.size(), pc->e_vals.as<double>(), s);
+    pc->f_rowptr.upload(pl.f_rowptr, s);
+    pc->f_colidx.upload(pl.f_colidx, s);
+    pc->f_vals.alloc(sizeof(double) * pl.f_src.size());
+    launch_gather(fs.as<int32_t>(), cpv, (int64_t)pl.f_src.size(), pc->f_vals.as<double>(), s);
+    ADDNS_HIP(hipStreamSynchronize(s));
+  }
+
+  // -- interior blocks: band LU, then block-bidiagonal sweep form
+  const int32_t m = pl.m;
+  std::vector<int32_t> int_off(P.int_offsets.begin(), P.int_offsets.end());
+  pc->sub_n.upload(pl.sub_n, s);
+  pc->sub_npad.upload(pl.sub_npad, s);
+  pc->sub_vec_off.upload(pl.sub_vec_off, s);
+  pc->sub_lblk0.upload(pl.sub_lblk0, s);
+  pc->sub_ublk0.upload(pl.sub_ublk0, s);
+  pc->sub_int_off.upload(int_off, s);
+  const int64_t npad_total = pl.sub_vec_off[m];
+  pc->ypad.alloc(sizeof(double) * std::max<int64_t>(npad_total, 1));
+  pc->zpad.alloc(sizeof(double) * std::max<int64_t>(npad_total, 1));
+  const int32_t nL = (int32_t)pl.lblk_sub.size(), nU = (int32_t)pl.ublk_sub.size();
+  const int fb = prec_bytes(o.interior_prec == ADDNS_F32 ? P32 : P64);
+  const int iprec = o.interior_prec == ADDNS_F32 ? P32 : P64;
+  DevBuf info;
+  info.alloc(sizeof(int32_t) * (m + 4));
+  ADDNS_HIP(hipMemsetAsync(info.p, 0, sizeof(int32_t) * (m + 4), s));
+  if (m > 0 && npad_total > 0) {
+    DevBuf ab, ipiv, band_off, bdst, bsrc, lsub, lidx, usub, uidx, work;
+    const int64_t ab_n = pl.sub_band_off[m];
+    ab.alloc(sizeof(double) * ab_n);
+    ADDNS_HIP(hipMemsetAsync(ab.p, 0, sizeof(double) * ab_n, s));
+    ipiv.alloc(sizeof(int32_t) * npad_total);
+    band_off.upload(pl.sub_band_off, s);
+    bdst.upload(pl.band_dst, s);
+    bsrc.upload(pl.band_src, s);
+    launch_scatter_band(bdst.as<int64_t>(), bsrc.as<int32_t>(), cpv, (int64_t)pl.band_dst.size(), ab.as<double>(), s);
+    launch_band_pad_identity(pc->sub_n.as<int32_t>(), pc->sub_npad.as<int32_t>(), band_off.as<int64_t>(), m, pl.ldab,
+                             pl.KL, pl.KU, ab.as<double>(), s);
+    launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), band_off.as<int64_t>(), pc->sub_npad.as<int32_t>(),
+                   pc->sub_vec_off.as<int32_t>(), m, pl.ldab, pl.KL, pl.KU, info.as<int32_t>(), s);
+    std::vector<int32_t> h_info(m + 4);
+    ADDNS_HIP(hipMemcpyAsync(h_info.data(), info.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
+    ADDNS_HIP(hipStreamSynchronize(s));
+    for (int32_t j = 0; j < m; ++j)
+      if (h_info[j] != 0)
+        throw SingularError("interior block " + std::to_string(j) + " has a zero pivot at column " +
+                            std::to_string(h_info[j] - 1));
+    const int32_t W = pl.nbL + pl.KL;
+    lsub.upload(pl.lblk_sub, s);
+    lidx.upload(pl.lblk_idx, s);
+    usub.upload(pl.ublk_sub, s);
+    uidx.upload(pl.ublk_idx, s);
+    pc->lperm.alloc(sizeof(int32_t) * (int64_t)nL * W);
+    pc->l11inv.alloc((int64_t)fb * nL * pl.nbL * pl.nbL);
+    pc->l21.alloc((int64_t)fb * nL * pl.KL * pl.nbL);
+    pc->uinv.alloc((int64_t)fb * nU * pl.nbU * pl.nbU);
+    pc->u12.alloc((int64_t)fb * nU * pl.nbU * pl.nbU);
+    const int64_t wl = (int64_t)nL * ((int64_t)W * pl.nbL + (int64_t)pl.nbL * pl.nbL);
+    const int64_t wu = (int64_t)nU * pl.nbU * pl.nbU;
+    work.alloc(sizeof(double) * std::max(wl, wu));
+    launch_convert_lower(ab.as<double>(), ipiv.as<int32_t>(), band_off.as<int64_t>(), pc->sub_vec_off.as<int32_t>(),
+                         lsub.as<int32_t>(), lidx.as<int32_t>(), nL, pl.ldab, pl.KL, pl.KU, pl.nbL, work.as<double>(),
+                         pc->lperm.as<int32_t>(), pc->l11inv.p, pc->l21.p, iprec, s);
+    launch_convert_upper(ab.as<double>(), band_off.as<int64_t>(), usub.as<int32_t>(), uidx.as<int32_t>(),
+                         pc->sub_npad.as<int32_t>(), nU, pl.ldab, pl.KL, pl.KU, pl.nbU, work.as<double>(), pc->uinv.p,
+                         pc->u12.p, iprec, info.as<int32_t>() + m, s);
+    ADDNS_HIP(hipMemcpyAsync(h_info.data(), info.as<int32_t>() + m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    ADDNS_HIP(hipStreamSynchronize(s));
+    if (h_info[0] != 0) throw SingularError("an interior U factor has a zero diagonal");
+  }
+
+  // -- interface: dense blocks, mini Schur complements, inverses
+  const int32_t k = pl.k;
+  pc->agg_off.upload(pl.agg_off, s);
+  pc->agg_s.upload(pl.agg_s, s);
+  pc->sinv_off.upload(pl.sinv_off, s);
+  const int sprec = o.schur_prec == ADDNS_F64 ? P64 : (o.schur_prec == ADDNS_F32 ? P32 : P16S);
+  pc->schur_prec = sprec;
+  pc->interior_prec = iprec;
+  if (k > 0) {
+    int32_t smax = 0;
+    for (int32_t i = 0; i < k; ++i) smax = std::max(smax, pl.agg_s[i]);
+    if (smax > 1024) throw ArgError("aggregates larger than 1024 nodes are not supported");
+    const int64_t dense_n = pl.g_total + pl.dd_total + pl.de_total + pl.df_total;
+    DevBuf dense, ddst, dsrc, agg_d, g_off, dd_off, de_off, df_off, work;
+    dense.alloc(sizeof(double) * dense_n);
+    ADDNS_HIP(hipMemsetAsync(dense.p, 0, sizeof(double) * dense_n, s));
+    ddst.upload(pl.dense_dst, s);
+    dsrc.upload(pl.dense_src, s);
+    launch_dense_scatter(ddst.as<int64_t>(), dsrc.as<int32_t>(), cpv, (int64_t)pl.dense_dst.size(), dense.as<double>(),
+                         s);
+    agg_d.upload(pl.agg_d, s);
+    g_off.upload(pl.g_off, s);
+    dd_off.upload(pl.dd_off, s);
+    de_off.upload(pl.de_off, s);
+    df_off.upload(pl.df_off, s);
+    double* G = dense.as<double>();
+    if (o.schur == ADDNS_SCHUR_MSCN || o.schur == ADDNS_SCHUR_MSCN_LITERAL)
+      launch_schur_blocks(k, pc->agg_s.as<int32_t>(), agg_d.as<int32_t>(), g_off.as<int64_t>(), dd_off.as<int64_t>(),
+                          de_off.as<int64_t>(), df_off.as<int64_t>(), G, G + pl.g_total,
+                          G + pl.g_total + pl.dd_total, G + pl.g_total + pl.dd_total + pl.de_total,
+                          info.as<int32_t>() + m + 1, s);
+    pc->schur_S.alloc(sizeof(double) * pl.g_total);
+    ADDNS_HIP(hipMemcpyAsync(pc->schur_S.p, G, sizeof(double) * pl.g_total, hipMemcpyDeviceToDevice, s));
+    pc->sinv.alloc((int64_t)prec_bytes(sprec) * pl.g_total);
+    pc->sinv_scale.alloc(sizeof(float) * k);
+    work.alloc(sizeof(double) * 2 * pl.g_total);
+    launch_invert_dense(k, pc->agg_s.as<int32_t>(), g_off.as<int64_t>(), G, work.as<double>(),
+                        info.as<int32_t>() + m + 2, pc->sinv_off.as<int64_t>(), pc->sinv.p,
+                        pc->sinv_scale.as<float>(), sprec, s);
+    int32_t h2[2];
+    ADDNS_HIP(hipMemcpyAsync(h2, info.as<int32_t>() + m + 1, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
+    ADDNS_HIP(hipStreamSynchronize(s));
+    if (h2[0]) throw SingularError("a D-range block D_{r_i} is singular");
+    if (h2[1]) throw SingularError("an interface block S_i is singular");
+  }
+  ADDNS_HIP(hipStreamSynchronize(s));
+
+  // -- byte accounting
+  int64_t fbytes = 0;
+  fbytes += (int64_t)nL * (pl.nbL * pl.nbL + pl.KL * pl.nbL) * fb + (int64_t)nL * (pl.nbL + pl.KL) * 4;
+  fbytes += (int64_t)nU * 2 * pl.nbU * pl.nbU * fb;
+  fbytes += pl.g_total * prec_bytes(sprec);
+  pc->factor_bytes = fbytes;
+  // algorithmic bytes of one apply: band factors L (KL) and U (KL+KU+1) per
+  // interior row read twice, pivots, E and F (value + index), Shat^-1, and six
+  // vector passes
+  int64_t band = 0;
+  for (int32_t j = 0; j < m; ++j) band += (int64_t)pl.sub_n[j] * (2 * pl.KL + pl.KU + 1);
+  pc->bytes_apply = 2 * band * fb + 2 * 4 * (int64_t)pl.n_int +
+                    (int64_t)(pl.e_src.size() + pl.f_src.size()) * 12 + pl.g_total * prec_bytes(sprec) +
+                    6 * (int64_t)N * 8;
+}
+
+void apply_permuted(addns_precond* pc, const double* yp, double* xp, hipStream_t s) {
+  const Plan& pl = pc->plan;
+  // z1 = D^{-1} y1 (into the interior part of xp)
+  launch_interior_solve(pc, yp, xp, 0, nullptr, nullptr, s);
+  // x2 = Shat^{-1} (y2 - F z1)
+  launch_interface_solve(pc, yp, xp, xp, s);
+  // x1 = z1 - D^{-1} (E x2), in place
+  if (pl.k > 0) launch_interior_solve(pc, nullptr, xp, 1, xp + pl.n_int, xp, s);
+}
+
+struct GmresWork {
+  double *V, *Z, *w, *xp, *bp, *rp, *H, *g, *cs, *sn, *y, *pa, *pb, *scal;
+};
+
+GmresWork gmres_work(addns_precond* pc, int restart, int flexible) {
+  const int32_t N = pc->plan.N;
+  if (pc->gm_restart < restart || !pc->V.p) {
+    pc->V.alloc(sizeof(double) * (int64_t)(restart + 1) * N);
+    pc->Z.alloc(sizeof(double) * (int64_t)restart * N);
+    pc->w.alloc(sizeof(double) * N);
+    pc->xp.alloc(sizeof(double) * N);
+    pc->bp.alloc(sizeof(double) * N);
+    pc->rp.alloc(sizeof(double) * N);
+    const int ldh = restart + 1;
+    pc->Hd.alloc(sizeof(double) * ((int64_t)ldh * restart + 4 * ldh));
+    pc->partials.alloc(sizeof(double) * 2 * 1024);
+    pc->scal.alloc(sizeof(double) * 8);
+    pc->gm_restart = restart;
+    if (!pc->host_pinned) ADDNS_HIP(hipHostMalloc(&pc->host_pinned, 64, hipHostMallocDefault));
+  }
+  (void)flexible;
+  GmresWork g;
+  const int ldh = pc->gm_restart + 1;
+  g.V = pc->V.as<double>();
+  g.Z = pc->Z.as<double>();
+  g.w = pc->w.as<double>();
+  g.xp = pc->xp.as<double>();
+  g.bp = pc->bp.as<double>();
+  g.rp = pc->rp.as<double>();
+  g.H = pc->Hd.as<double>();
+  g.g = g.H + (int64_t)ldh * pc->gm_restart;
+  g.cs = g.g + ldh;
+  g.sn = g.cs + ldh;
+  g.y = g.sn + ldh;
+  g.pa = pc->partials.as<double>();
+  g.pb = g.pa + 1024;
+  g.scal = pc->scal.as<double>();
+  return g;
+}
+
+double read_scalar(addns_precond* pc, const double* d, hipStream_t s) {
+  double* h = static_cast<double*>(pc->host_pinned);
+  ADDNS_HIP(hipMemcpyAsync(h, d, sizeof(double), hipMemcpyDeviceToHost, s));
+  ADDNS_HIP(hipStreamSynchronize(s));
+  return h[0];
+}
+
+}  // namespace
+
+extern "C" {
+
+int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr, const int32_t* d_colidx,
+                        const double* d_vals, const addns_precond_opts* opts, void* stream, addns_precond_t* out) {
+  return guarded("addns_setup_precond", [&]() -> int {
+    if (!p || !out || !d_rowptr || !d_colidx || !d_vals) throw ArgError("null argument");
+    if (N != p->d.N) throw ArgError("N does not match the partition");
+    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr};
+    if (opts) o = *opts;
+    if (o.schur < 0 || o.schur > ADDNS_SCHUR_LEARNED) throw ArgError("unknown schur mode");
+    if (o.schur == ADDNS_SCHUR_EXACT_BJ) throw ArgError("EXACT_BJ is an oracle-side reference mode");
+    if (o.schur == ADDNS_SCHUR_LEARNED) throw ArgError("LEARNED mode is not available in this build");
+    if (o.interior_prec != ADDNS_F64 && o.interior_prec != ADDNS_F32) throw ArgError("interior_prec");
+    if (o.schur_prec < ADDNS_F64 || o.schur_prec > ADDNS_F16_SCALED) throw ArgError("schur_prec");
+    if (o.schur == ADDNS_SCHUR_MSCN_LITERAL && p->d.n_int() < p->d.sep_size())
+      throw ArgError("literal D-range pairing needs |D| >= |Sigma|");
+    std::unique_ptr<addns_precond> pc(new addns_precond());
+    pc->schur_mode = o.schur;
+    pc->row_scale = o.row_scale;
+    ADDNS_HIP(hipGetDevice(&pc->device));
+    setup_device(pc.get(), p->d, d_rowptr, d_colidx, d_vals, o, as_stream(stream));
+    *out = pc.release();
+    return ADDNS_OK;
+  });
+}
+
+int addns_apply_precond(addns_precond_t pc, const double* d_y, double* d_x, void* stream) {
+  return guarded("addns_apply_precond", [&]() -> int {
+    if (!pc || !d_y || !d_x) throw ArgError("null argument");
+    if (d_y == d_x) throw ArgError("y and x must not alias");
+    hipStream_t s = as_stream(stream);
+    const int32_t N = pc->plan.N;
+    if (!pc->vperm_in.p) {
+      pc->vperm_in.alloc(sizeof(double) * N);
+      pc->vperm_out.alloc(sizeof(double) * N);
+    }
+    launch_permute(pc->perm.as<int32_t>(), d_y, pc->vperm_in.as<double>(), N, 0, nullptr, s);
+    apply_permuted(pc, pc->vperm_in.as<double>(), pc->vperm_out.as<double>(), s);
+    launch_permute(pc->perm.as<int32_t>(), pc->vperm_out.as<double>(), d_x, N, 1, nullptr, s);
+    ADDNS_HIP(hipGetLastError());
+    return ADDNS_OK;
+  });
+}
+
+int addns_interior_solve(addns_precond_t pc, const double* d_y1, double* d_z1, void* stream) {
+  return guarded("addns_interior_solve", [&]() -> int {
+    if (!pc || !d_y1 || !d_z1) throw ArgError("null argument");
+    if (d_y1 == d_z1) throw ArgError("y1 and z1 must not alias");
+    launch_interior_solve(pc, d_y1, d_z1, 0, nullptr, nullptr, as_stream(stream));
+    ADDNS_HIP(hipGetLastError());
+    return ADDNS_OK;
+  });
+}
+
+int addns_gmres_solve(addns_precond_t pc, const double* d_b, double* d_x, const addns_gmres_opts* opts,
+                      addns_gmres_result* res, void* stream) {
+  return guarded("addns_gmres_solve", [&]() -> int {
+    if (!pc || !d_b || !d_x || !opts || !res) throw ArgError("null argument");
+    const int restart = opts->restart, maxit = opts->maxit;
+    if (restart < 1 || maxit < 0 || !(opts->tol > 0.0)) throw ArgError("restart >= 1, maxit >= 0, tol > 0");
+    hipStream_t s = as_stream(stream);
+    const int32_t N = pc->plan.N;
+    const Plan& pl = pc->plan;
+    GmresWork g = gmres_work(pc, restart, opts->flexible);
+    const int ldh = pc->gm_restart + 1;
+    const int nparts = krylov_grid(N);
+    const int32_t* rp = pc->cp_rowptr.as<int32_t>();
+    const int32_t* ci = pc->cp_colidx.as<int32_t>();
+    const double* cv = pc->cp_vals.as<double>();
+    double* hist = res->resid_hist;
+    res->iters = 0;
+    res->cycles = 0;
+    res->converged = 0;
+    res->true_relres = 0.0;
+    res->est_relres = 0.0;
+    // b~ = R b and x in the permuted numbering
+    launch_permute(pc->perm.as<int32_t>(), d_b, g.bp, N, 0, pc->R.as<double>(), s);
+    if (opts->use_x0) launch_permute(pc->perm.as<int32_t>(), d_x, g.xp, N, 0, nullptr, s);
+    else ADDNS_HIP(hipMemsetAsync(g.xp, 0, sizeof(double) * N, s));
+    launch_dot_partials(g.bp, g.bp, N, g.pa, s);
+    launch_norm_finalize(g.pa, nparts, g.scal, 2, s);
+    const double bnorm = read_scalar(pc, g.scal + 2, s);
+    if (bnorm == 0.0) {
+      ADDNS_HIP(hipMemsetAsync(d_x, 0, sizeof(double) * N, s));
+      res->converged = 1;
+      if (hist) hist[0] = 0.0;
+      ADDNS_HIP(hipStreamSynchronize(s));
+      return ADDNS_OK;
+    }
+    launch_residual(rp, ci, cv, g.xp, g.bp, g.rp, N, g.pa, s);
+    launch_norm_finalize(g.pa, nparts, g.scal, 3, s);
+    double beta = read_scalar(pc, g.scal + 3, s);
+    double relres = beta / bnorm;
+    int its = 0;
+    bool converged = relres <= opts->tol;
+    while (!converged && its < maxit) {
+      res->cycles++;
+      launch_scale_copy(g.rp, g.V, g.scal, 3, N, s);
+      ADDNS_HIP(hipMemsetAsync(g.g, 0, sizeof(double) * ldh, s));
+      ADDNS_HIP(hipMemcpyAsync(g.g, g.scal + 3, sizeof(double), hipMemcpyDeviceToDevice, s));
+      int jdone = 0;
+      for (int j = 0; j < restart; ++j) {
+        double* vj = g.V + (int64_t)j * N;
+        double* zj = opts->flexible ? g.Z + (int64_t)j * N : g.Z;
+        apply_permuted(pc, vj, zj, s);
+        launch_spmv_dot(rp, ci, cv, zj, g.w, g.V, N, g.pa, s);
+        double* pin = g.pa;
+        double* pout = g.pb;
+        for (int i = 0; i <= j; ++i) {
+          const double* vnext = i < j ? g.V + (int64_t)(i + 1) * N : nullptr;
+          launch_mgs_step(g.w, g.V + (int64_t)i * N, vnext, N, pin, pout, g.H + (int64_t)j * ldh + i, nparts, s);
+          std::swap(pin, pout);
+        }
+        launch_finalize(g.H, g.g, g.cs, g.sn, pin, nparts, j, ldh, g.scal, s);
+        launch_scale_copy(g.w, g.V + (int64_t)(j + 1) * N, g.scal, 0, N, s);
+        double* h = static_cast<double*>(pc->host_pinned);
+        ADDNS_HIP(hipMemcpyAsync(h, g.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        ADDNS_HIP(hipStreamSynchronize(s));
+        const double hn = h[0], est = h[1];
+        ++its;
+        jdone = j + 1;
+        res->est_relres = est / bnorm;
+        if (hist) hist[its - 1] = est / bnorm;
+        if (!std::isfinite(est)) throw HipError("non-finite residual estimate");
+        if (est <= opts->tol * bnorm || its >= maxit || hn == 0.0) break;
+      }
+      launch_backsolve(g.H, g.g, jdone, ldh, g.y, s);
+      if (opts->flexible) {
+        launch_combine(g.Z, N, g.y, jdone, N, g.xp, 1, s);
+      } else {
+        launch_combine(g.V, N, g.y, jdone, N, g.w, 0, s);
+        apply_permuted(pc, g.w, g.Z, s);
+        launch_combine(g.Z, N, nullptr, 1, N, g.xp, 1, s);
+      }
+      launch_residual(rp, ci, cv, g.xp, g.bp, g.rp, N, g.pa, s);
+      launch_norm_finalize(g.pa, nparts, g.scal, 3, s);
+      beta = read_scalar(pc, g.scal + 3, s);
+      relres = beta / bnorm;
+      converged = relres <= opts->tol;
+    }
+    launch_permute(pc->perm.as<int32_t>(), g.xp, d_x, N, 1, nullptr, s);
+    ADDNS_HIP(hipStreamSynchronize(s));
+    (void)pl;
+    res->iters = its;
+    res->converged = converged ? 1 : 0;
+    res->true_relres = relres;
+    if (!converged) {
+      set_error("GMRES reached maxit with relative residual " + std::to_string(relres));
+      return ADDNS_ERR_NOCONV;
+    }
+    return ADDNS_OK;
+  });
+}
+
+int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb_lower, int32_t* nb_upper,
+                       int64_t* factor_bytes, int64_t* bytes_apply, int64_t* learned_count) {
+  if (!pc) {
+    set_error("addns_precond_info: null handle");
+    return ADDNS_ERR_ARG;
+  }
+  if (kl) *kl = pc->plan.KL;
+  if (ku) *ku = pc->plan.KU;
+  if (nb_lower) *nb_lower = pc->plan.nbL;
+  if (nb_upper) *nb_upper = pc->plan.nbU;
+  if (factor_bytes) *factor_bytes = pc->factor_bytes;
+  if (bytes_apply) *bytes_apply = pc->bytes_apply;
+  if (learned_count) *learned_count = pc->plan.g_total;
+  return ADDNS_OK;
+}
+
+int addns_precond_schur_blocks(addns_precond_t pc, double* h_out, int64_t count) {
+  return guarded("addns_precond_schur_blocks", [&]() -> int {
+    if (!pc || !h_out) throw ArgError("null argument");
+    if (count != pc->plan.g_total) throw ArgError("count must equal the sum of |agg_i|^2");
+    if (count > 0) ADDNS_HIP(hipMemcpy(h_out, pc->schur_S.p, sizeof(double) * count, hipMemcpyDeviceToHost));
+    return ADDNS_OK;
+  });
+}
+
+void addns_precond_destroy(addns_precond_t pc) { delete pc; }
+
+}  // extern "C"

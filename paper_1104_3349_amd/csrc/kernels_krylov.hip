@@ -1,0 +1,235 @@
+// Krylov kernels of restarted (F)GMRES in FP64: CSR SpMV, fused
+// axpy + next-dot steps of modified Gram-Schmidt, Givens rotations and the
+// cycle-end update.  Dot products reduce per workgroup with wavefront
+// shuffles and write one partial per workgroup; the consumer of a dot
+// re-reduces all partials in a fixed order, so every result is bitwise
+// reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include "precond.h"
+
+namespace addns {
+namespace {
+
+constexpr int kKT = 256;          // threads per reduction workgroup
+constexpr int kPerThread = 4;     // elements per thread per grid pass
+constexpr int kMaxParts = 1024;
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Sum of v over the workgroup (every thread gets the result).
+__device__ inline double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += red[q];
+  return s;
+}
+
+// Fixed-order sum of nparts partials (identical in every workgroup).
+__device__ inline double reduce_parts(const double* __restrict__ parts, int nparts, double* red) {
+  double v = 0.0;
+  for (int q = threadIdx.x; q < nparts; q += blockDim.x) v += parts[q];
+  return block_sum(v, red);
+}
+
+// CSR row dot with 4 lanes per row would not pay at ~6 entries per row:
+// one thread per row, rows assigned so that a wavefront covers 64 rows.
+__device__ inline double row_dot(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+                                 const double* __restrict__ vals, const double* __restrict__ x, int32_t r) {
+  double s = 0.0;
+  for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) s += vals[e] * x[colidx[e]];
+  return s;
+}
+
+__global__ void __launch_bounds__(kKT) k_spmv(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+                                             const double* __restrict__ vals, const double* __restrict__ x,
+                                             double* __restrict__ y, int32_t n) {
+  int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) y[r] = row_dot(rowptr, colidx, vals, x, r);
+}
+
+// w = A z and the partial of <w, v0>.
+__global__ void __launch_bounds__(kKT)
+k_spmv_dot(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx, const double* __restrict__ vals,
+           const double* __restrict__ z, double* __restrict__ w, const double* __restrict__ v0, int32_t n,
+           double* __restrict__ partials) {
+  __shared__ double red[kKT / 64];
+  double acc = 0.0;
+  for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    double y = row_dot(rowptr, colidx, vals, z, r);
+    w[r] = y;
+    acc += y * v0[r];
+  }
+  double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// r = b - A x and the partial of <r, r>.
+__global__ void __launch_bounds__(kKT)
+k_residual(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx, const double* __restrict__ vals,
+           const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ r, int32_t n,
+           double* __restrict__ partials) {
+  __shared__ double red[kKT / 64];
+  double acc = 0.0;
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double y = b[i] - row_dot(rowptr, colidx, vals, x, i);
+    r[i] = y;
+    acc += y * y;
+  }
+  double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kKT)
+k_dot_partials(const double* __restrict__ a, const double* __restrict__ b, int32_t n, double* __restrict__ partials) {
+  __shared__ double red[kKT / 64];
+  double acc = 0.0;
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) acc += a[i] * b[i];
+  double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// One modified Gram-Schmidt step: h = <w, v_i> from the partials of the
+// previous kernel; w -= h v_i; partial of <w, v_next> (or <w, w> when
+// v_next is null).  Workgroup 0 stores h.
+__global__ void __launch_bounds__(kKT)
+k_mgs_step(double* __restrict__ w, const double* __restrict__ vi, const double* __restrict__ vnext, int32_t n,
+           const double* __restrict__ pin, double* __restrict__ pout, double* __restrict__ h_out, int nparts) {
+  __shared__ double red[kKT / 64];
+  const double h = reduce_parts(pin, nparts, red);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *h_out = h;
+  double acc = 0.0;
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double y = w[i] - h * vi[i];
+    w[i] = y;
+    acc += y * (vnext ? vnext[i] : y);
+  }
+  double s = block_sum(acc, red);
+  if (threadIdx.x == 0) pout[blockIdx.x] = s;
+}
+
+// h_{j+1,j} = ||w||; rotations 0..j-1 applied to column j of H; rotation j
+// from (h_jj, h_{j+1,j}) with t = hypot(a, b), c = a/t, s = b/t (b = 0 gives
+// c = 1, s = 0); g_{j+1} = -s g_j, g_j = c g_j.
+// scal[0] = h_{j+1,j}, scal[1] = |g_{j+1}|.
+__global__ void __launch_bounds__(kKT)
+k_finalize(double* __restrict__ H, double* __restrict__ g, double* __restrict__ cs, double* __restrict__ sn,
+           const double* __restrict__ partials, int nparts, int32_t j, int32_t ldh, double* __restrict__ scal) {
+  __shared__ double red[kKT / 64];
+  const double hn = sqrt(reduce_parts(partials, nparts, red));
+  if (threadIdx.x != 0) return;
+  double* col = H + (int64_t)j * ldh;
+  for (int32_t i = 0; i < j; ++i) {
+    double t = cs[i] * col[i] + sn[i] * col[i + 1];
+    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  double a = col[j], b = hn, c, s;
+  if (b == 0.0) {
+    c = 1.0;
+    s = 0.0;
+  } else {
+    double t = hypot(a, b);
+    c = a / t;
+    s = b / t;
+  }
+  cs[j] = c;
+  sn[j] = s;
+  col[j] = c * a + s * b;
+  col[j + 1] = 0.0;
+  g[j + 1] = -s * g[j];
+  g[j] = c * g[j];
+  scal[0] = hn;
+  scal[1] = fabs(g[j + 1]);
+}
+
+__global__ void k_norm_finalize(const double* __restrict__ partials, int nparts, double* __restrict__ scal, int idx) {
+  __shared__ double red[kKT / 64];
+  const double s = reduce_parts(partials, nparts, red);
+  if (threadIdx.x == 0) scal[idx] = sqrt(s);
+}
+
+// v = w / scal[idx] (unchanged copy when the norm is zero).
+__global__ void k_scale_copy(const double* __restrict__ w, double* __restrict__ v, const double* __restrict__ scal,
+                             int idx, int32_t n) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double d = scal[idx];
+  v[i] = d != 0.0 ? w[i] / d : w[i];
+}
+
+// y = R^{-1} g for the leading j x j triangle of H (one thread).
+__global__ void k_backsolve(const double* __restrict__ H, const double* __restrict__ g, int32_t j, int32_t ldh,
+                            double* __restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int32_t i = j - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int32_t q = i + 1; q < j; ++q) s -= H[(int64_t)q * ldh + i] * y[q];
+    y[i] = s / H[(int64_t)i * ldh + i];
+  }
+}
+
+// x (+)= sum_i y_i Z_i with the sum in ascending i (y == null: all ones).
+__global__ void k_combine(const double* __restrict__ Z, int64_t ldz, const double* __restrict__ y, int32_t j,
+                          int32_t n, double* __restrict__ x, int add) {
+  int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double s = 0.0;
+  for (int32_t i = 0; i < j; ++i) s += (y ? y[i] : 1.0) * Z[(int64_t)i * ldz + e];
+  x[e] = add ? x[e] + s : s;
+}
+
+inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+int krylov_grid(int32_t n) {
+  int g = (int)((n + kKT * kPerThread - 1) / (kKT * kPerThread));
+  return std::max(1, std::min(g, kMaxParts));
+}
+
+void launch_spmv(const int32_t* rowptr, const int32_t* colidx, const double* vals, const double* x, double* y,
+                 int32_t n, hipStream_t s) {
+  if (n > 0) k_spmv<<<nb(n, kKT), kKT, 0, s>>>(rowptr, colidx, vals, x, y, n);
+}
+void launch_spmv_dot(const int32_t* rowptr, const int32_t* colidx, const double* vals, const double* x, double* w,
+                     const double* v0, int32_t n, double* partials, hipStream_t s) {
+  k_spmv_dot<<<krylov_grid(n), kKT, 0, s>>>(rowptr, colidx, vals, x, w, v0, n, partials);
+}
+void launch_residual(const int32_t* rowptr, const int32_t* colidx, const double* vals, const double* x,
+                     const double* b, double* r, int32_t n, double* partials, hipStream_t s) {
+  k_residual<<<krylov_grid(n), kKT, 0, s>>>(rowptr, colidx, vals, x, b, r, n, partials);
+}
+void launch_dot_partials(const double* a, const double* b, int32_t n, double* partials, hipStream_t s) {
+  k_dot_partials<<<krylov_grid(n), kKT, 0, s>>>(a, b, n, partials);
+}
+void launch_mgs_step(double* w, const double* vi, const double* vnext, int32_t n, const double* pin, double* pout,
+                     double* h_out, int nparts, hipStream_t s) {
+  k_mgs_step<<<krylov_grid(n), kKT, 0, s>>>(w, vi, vnext, n, pin, pout, h_out, nparts);
+}
+void launch_finalize(double* H, double* g, double* cs, double* sn, const double* partials, int nparts, int32_t j,
+                     int32_t ldh, double* scal, hipStream_t s) {
+  k_finalize<<<1, kKT, 0, s>>>(H, g, cs, sn, partials, nparts, j, ldh, scal);
+}
+void launch_norm_finalize(const double* partials, int nparts, double* scal, int idx, hipStream_t s) {
+  k_norm_finalize<<<1, kKT, 0, s>>>(partials, nparts, scal, idx);
+}
+void launch_scale_copy(const double* w, double* v, const double* scal, int idx, int32_t n, hipStream_t s) {
+  if (n > 0) k_scale_copy<<<nb(n, 256), 256, 0, s>>>(w, v, scal, idx, n);
+}
+void launch_backsolve(const double* H, const double* g, int32_t j, int32_t ldh, double* y, hipStream_t s) {
+  k_backsolve<<<1, 64, 0, s>>>(H, g, j, ldh, y);
+}
+void launch_combine(const double* Z, int64_t ldz, const double* y, int32_t j, int32_t n, double* x, int add,
+                    hipStream_t s) {
+  if (n > 0) k_combine<<<nb(n, 256), 256, 0, s>>>(Z, ldz, y, j, n, x, add);
+}
+
+}  // namespace addns

@@ -1,0 +1,589 @@
+// Setup kernels (Algorithm 1 and the exact interior factorisations):
+//   - row scaling by the largest absolute entry (section 5);
+//   - gathers of C~ into its permuted CSR, band storage of each A_jj, and
+//     dense aggregate blocks;
+//   - band LU with partial pivoting of every A_jj (one workgroup each);
+//   - conversion of the band factors into block-bidiagonal sweeps whose
+//     diagonal blocks are stored inverted (the apply then runs dense
+//     triangular GEMVs instead of a row-by-row recurrence);
+//   - mini Schur complements S_i = G_i - F_i D_{r_i}^{-1} E_i: Gaussian
+//     elimination of [D_{r_i} | E_i], back substitution, and the product
+//     F_i X_i on FP64 matrix cores (MFMA); then S_i^{-1} by Gauss-Jordan
+//     with partial pivoting, stored in the requested precision.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "precond.h"
+
+namespace addns {
+namespace {
+
+constexpr int kSetupThreads = 1024;
+
+__global__ void k_row_scale(const int32_t* __restrict__ rowptr, const double* __restrict__ vals, int32_t N,
+                            int scale, double* __restrict__ R) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  if (!scale) {
+    R[i] = 1.0;
+    return;
+  }
+  double mx = 0.0;
+  for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) mx = fmax(mx, fabs(vals[e]));
+  R[i] = mx > 0.0 ? 1.0 / mx : 1.0;
+}
+
+__global__ void k_gather_scaled(const int32_t* __restrict__ src, const int32_t* __restrict__ orow,
+                                const double* __restrict__ vals, const double* __restrict__ R, int64_t n,
+                                double* __restrict__ out) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = R[orow[t]] * vals[src[t]];
+}
+
+__global__ void k_gather(const int32_t* __restrict__ src, const double* __restrict__ in, int64_t n,
+                         double* __restrict__ out) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = in[src[t]];
+}
+
+__global__ void k_scatter(const int64_t* __restrict__ dst, const int32_t* __restrict__ src,
+                          const double* __restrict__ cpv, int64_t n, double* __restrict__ out) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[dst[t]] = cpv[src[t]];
+}
+
+__global__ void k_band_pad_identity(const int32_t* sub_n, const int32_t* sub_npad, const int64_t* band_off,
+                                    int32_t ldab, int32_t KV, double* ab) {
+  int j = blockIdx.x;
+  for (int32_t c = sub_n[j] + threadIdx.x; c < sub_npad[j]; c += blockDim.x)
+    ab[band_off[j] + (int64_t)c * ldab + KV] = 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// Band LU with partial pivoting, one workgroup per interior block.  Band
+// storage is column-major with leading dimension ldab = 2KL+KU+1; entry
+// (r, c) lives at row KV + r - c of column c, KV = KL + KU, so the factor U
+// may fill KL extra superdiagonals.  ipiv[j] = row swapped with row j at
+// step j (subdomain-local).  info[sub] = first zero pivot + 1 (0 if none).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kSetupThreads)
+k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const int64_t* __restrict__ band_off,
+          const int32_t* __restrict__ sub_npad, const int32_t* __restrict__ sub_vec_off, int32_t ldab, int32_t KL,
+          int32_t KU, int32_t* __restrict__ info) {
+  const int sub = blockIdx.x;
+  const int32_t n = sub_npad[sub];
+  double* ab = ab_all + band_off[sub];
+  int32_t* ipiv = ipiv_all + sub_vec_off[sub];
+  const int32_t KV = KL + KU;
+  __shared__ double s_piv;
+  __shared__ double s_top;
+  __shared__ int32_t s_p;
+  __shared__ int32_t s_ju;
+  __shared__ int32_t s_info;
+  __shared__ double s_rv[16];
+  __shared__ int32_t s_ri[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) {
+    s_ju = 0;
+    s_info = 0;
+  }
+  __syncthreads();
+  for (int32_t j = 0; j < n; ++j) {
+    const int32_t km = min(KL, n - 1 - j);
+    double* colj = ab + (int64_t)j * ldab + KV;
+    // pivot search over rows j..j+km (first index of the largest magnitude)
+    if (wave == 0) {
+      double best = -1.0;
+      int32_t bi = 0;
+      for (int32_t i = lane; i <= km; i += 64) {
+        double a = fabs(colj[i]);
+        if (a > best) {
+          best = a;
+          bi = i;
+        }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        double ob = __shfl_xor(best, off);
+        int32_t oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        s_p = bi;
+        s_piv = colj[bi];
+        s_top = colj[0];
+        ipiv[j] = j + bi;
+        if (colj[bi] == 0.0 && s_info == 0) s_info = j + 1;
+        int32_t ju = max(s_ju, min(j + KU + bi, n - 1));
+        s_ju = ju;
+      }
+    }
+    __syncthreads();
+    const int32_t p = s_p;
+    const double piv = s_piv;
+    const int32_t ju = s_ju;
+    if (piv != 0.0) {
+      // multipliers of column j (after the row swap) and the swap of columns j+1..ju
+      const double rinv = 1.0 / piv;
+      for (int32_t i = tid; i <= km; i += blockDim.x) {
+        if (i == 0) continue;
+        double v = (i == p) ? s_top : colj[i];
+        colj[i] = v * rinv;
+      }
+      if (tid == 0) colj[0] = piv;
+      if (p != 0) {
+        for (int32_t c = j + 1 + tid; c <= ju; c += blockDim.x) {
+          double* col = ab + (int64_t)c * ldab + KV + j - c;
+          double a = col[0], b = col[p];
+          col[0] = b;
+          col[p] = a;
+        }
+      }
+    }
+    __syncthreads();
+    if (piv != 0.0 && km > 0) {
+      const int32_t ncols = ju - j;
+      const int64_t total = (int64_t)ncols * km;
+      for (int64_t t = tid; t < total; t += blockDim.x) {
+        int32_t c = j + 1 + (int32_t)(t / km);
+        int32_t i = 1 + (int32_t)(t % km);
+        double* col = ab + (int64_t)c * ldab + KV + j - c;
+        col[i] -= colj[i] * col[0];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) info[sub] = s_info;
+  (void)s_rv;
+  (void)s_ri;
+}
+
+template <class T>
+__device__ inline T to_store(double v) { return (T)v; }
+template <>
+__device__ inline __half to_store<__half>(double v) { return __float2half((float)v); }
+
+// ---------------------------------------------------------------------------
+// Lower sweep blocks.  For block b of subdomain sub (columns c0 = b*nbL ..
+// c0+nbL-1) the row operations of the band LU touch only the window rows
+// c0 .. c0+nbL+KL-1.  Their product is L~^{-1} P with P the window
+// permutation and L~ = [L11 0; L21 I] the multipliers after the later swaps
+// of the block.  Stored: the gather indices of P, inv(L11) (nbL x nbL,
+// column-major) and L21 (KL x nbL, column-major).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(kSetupThreads)
+k_convert_lower(const double* __restrict__ ab_all, const int32_t* __restrict__ ipiv_all,
+                const int64_t* __restrict__ band_off, const int32_t* __restrict__ sub_vec_off,
+                const int32_t* __restrict__ lblk_sub, const int32_t* __restrict__ lblk_idx, int32_t ldab,
+                int32_t KL, int32_t KU, int32_t nbL, double* __restrict__ work_all, int32_t* __restrict__ lperm_all,
+                T* __restrict__ l11inv_all, T* __restrict__ l21_all) {
+  const int blk = blockIdx.x;
+  const int sub = lblk_sub[blk];
+  const int32_t c0 = lblk_idx[blk] * nbL;
+  const int32_t W = nbL + KL;
+  const int32_t KV = KL + KU;
+  const double* ab = ab_all + band_off[sub];
+  const int32_t* ipiv = ipiv_all + sub_vec_off[sub];
+  double* Lw = work_all + (int64_t)blk * ((int64_t)W * nbL + (int64_t)nbL * nbL);  // W x nbL, col-major
+  double* X = Lw + (int64_t)W * nbL;                                                  // nbL x nbL, col-major
+  const int tid = threadIdx.x;
+  // multipliers of each column at their window rows (diagonal implicit)
+  for (int64_t t = tid; t < (int64_t)W * nbL; t += blockDim.x) {
+    int32_t c = (int32_t)(t / W), r = (int32_t)(t % W);
+    int32_t i = r - c;
+    Lw[t] = (i >= 1 && i <= KL) ? ab[(int64_t)(c0 + c) * ldab + KV + i] : 0.0;
+  }
+  __syncthreads();
+  // later swaps of the block act on earlier columns: one thread per column
+  for (int32_t c = tid; c < nbL; c += blockDim.x) {
+    double* col = Lw + (int64_t)c * W;
+    for (int32_t s = c + 1; s < nbL; ++s) {
+      int32_t p = ipiv[c0 + s] - c0;
+      if (p != s) {
+        double a = col[s];
+        col[s] = col[p];
+        col[p] = a;
+      }
+    }
+  }
+  if (tid == 0) {
+    int32_t* idx = lperm_all + (int64_t)blk * W;
+    for (int32_t r = 0; r < W; ++r) idx[r] = r;
+    for (int32_t s = 0; s < nbL; ++s) {
+      int32_t p = ipiv[c0 + s] - c0;
+      int32_t a = idx[s];
+      idx[s] = idx[p];
+      idx[p] = a;
+    }
+  }
+  // X = I
+  for (int64_t t = tid; t < (int64_t)nbL * nbL; t += blockDim.x) {
+    int32_t c = (int32_t)(t / nbL), r = (int32_t)(t % nbL);
+    X[t] = r == c ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // forward elimination of the unit lower L11: rows r > i receive -L(r,i) X(i,:)
+  for (int32_t i = 0; i < nbL - 1; ++i) {
+    const int32_t rows = nbL - 1 - i, cols = i + 1;
+    for (int32_t t = tid; t < rows * cols; t += blockDim.x) {
+      int32_t r = i + 1 + t % rows, c = t / rows;
+      X[(int64_t)c * nbL + r] -= Lw[(int64_t)i * W + r] * X[(int64_t)c * nbL + i];
+    }
+    __syncthreads();
+  }
+  T* l11 = l11inv_all + (int64_t)blk * nbL * nbL;
+  T* l21 = l21_all + (int64_t)blk * KL * nbL;
+  for (int64_t t = tid; t < (int64_t)nbL * nbL; t += blockDim.x) l11[t] = to_store<T>(X[t]);
+  for (int64_t t = tid; t < (int64_t)KL * nbL; t += blockDim.x) {
+    int32_t c = (int32_t)(t / KL), r = (int32_t)(t % KL);
+    l21[t] = to_store<T>(Lw[(int64_t)c * W + nbL + r]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Upper sweep blocks (rows r0 = b*nbU .. r0+nbU-1, nbU >= KL+KU so that U is
+// block bidiagonal): inv(U_bb) (column-major) and U_{b,b+1} (column-major).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(kSetupThreads)
+k_convert_upper(const double* __restrict__ ab_all, const int64_t* __restrict__ band_off,
+                const int32_t* __restrict__ ublk_sub, const int32_t* __restrict__ ublk_idx,
+                const int32_t* __restrict__ sub_npad, int32_t ldab, int32_t KL, int32_t KU, int32_t nbU,
+                double* __restrict__ work_all, T* __restrict__ uinv_all, T* __restrict__ u12_all,
+                int32_t* __restrict__ info) {
+  const int blk = blockIdx.x;
+  const int sub = ublk_sub[blk];
+  const int32_t r0 = ublk_idx[blk] * nbU;
+  const int32_t n = sub_npad[sub];
+  const int32_t KV = KL + KU;
+  const double* ab = ab_all + band_off[sub];
+  double* X = work_all + (int64_t)blk * nbU * nbU;  // column-major
+  const int tid = threadIdx.x;
+  auto U = [&](int32_t r, int32_t c) -> double {   // subdomain-local (r, c)
+    int32_t d = c - r;
+    return (d >= 0 && d <= KV && c < n) ? ab[(int64_t)c * ldab + KV + r - c] : 0.0;
+  };
+  for (int64_t t = tid; t < (int64_t)nbU * nbU; t += blockDim.x) {
+    int32_t c = (int32_t)(t / nbU), r = (int32_t)(t % nbU);
+    X[t] = r == c ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int32_t i = nbU - 1; i >= 0; --i) {
+    const double d = U(r0 + i, r0 + i);
+    if (d == 0.0) {
+      if (tid == 0) atomicMax(info, 1);
+      return;
+    }
+    const double dinv = 1.0 / d;
+    for (int32_t c = i + tid; c < nbU; c += blockDim.x) X[(int64_t)c * nbU + i] *= dinv;
+    __syncthreads();
+    const int32_t rows = i, cols = nbU - i;
+    for (int32_t t = tid; t < rows * cols; t += blockDim.x) {
+      int32_t r = t % rows, c = i + t / rows;
+      double u = U(r0 + r, r0 + i);
+      if (u != 0.0) X[(int64_t)c * nbU + r] -= u * X[(int64_t)c * nbU + i];
+    }
+    __syncthreads();
+  }
+  T* ui = uinv_all + (int64_t)blk * nbU * nbU;
+  T* u12 = u12_all + (int64_t)blk * nbU * nbU;
+  for (int64_t t = tid; t < (int64_t)nbU * nbU; t += blockDim.x) {
+    int32_t c = (int32_t)(t / nbU), r = (int32_t)(t % nbU);
+    ui[t] = to_store<T>(X[t]);
+    u12[t] = to_store<T>(U(r0 + r, r0 + nbU + c));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mini Schur complements, one workgroup per aggregate.
+//   G (s x s), D (d x d), E (d x s), F (s x d), all row-major FP64.
+// Gaussian elimination with partial pivoting of [D | E] turns E into
+// L^{-1} P E; back substitution with U gives X = D^{-1} E; then
+// G <- G - F X on MFMA (v_mfma_f64_16x16x4f64).
+// ---------------------------------------------------------------------------
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(kSetupThreads)
+k_schur_blocks(const int32_t* __restrict__ agg_s, const int32_t* __restrict__ agg_d,
+               const int64_t* __restrict__ g_off, const int64_t* __restrict__ dd_off,
+               const int64_t* __restrict__ de_off, const int64_t* __restrict__ df_off, double* __restrict__ Gall,
+               double* __restrict__ Dall, double* __restrict__ Eall, double* __restrict__ Fall,
+               int32_t* __restrict__ info) {
+  const int i = blockIdx.x;
+  const int32_t s = agg_s[i], d = agg_d[i];
+  if (d == 0) return;
+  double* G = Gall + g_off[i];
+  double* D = Dall + dd_off[i];
+  double* E = Eall + de_off[i];
+  double* F = Fall + df_off[i];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int32_t w = d + s;  // augmented row length
+  auto A = [&](int32_t r, int32_t c) -> double& { return c < d ? D[(int64_t)r * d + c] : E[(int64_t)r * s + (c - d)]; };
+  __shared__ int32_t s_p;
+  __shared__ double s_piv;
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int32_t c = 0; c < d; ++c) {
+    if (wave == 0) {
+      double best = -1.0;
+      int32_t bi = c;
+      for (int32_t r = c + lane; r < d; r += 64) {
+        double a = fabs(A(r, c));
+        if (a > best) {
+          best = a;
+          bi = r;
+        }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        double ob = __shfl_xor(best, off);
+        int32_t oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        s_p = bi;
+        s_piv = A(bi, c);
+        if (A(bi, c) == 0.0) s_bad = 1;
+      }
+    }
+    __syncthreads();
+    if (s_bad) break;
+    const int32_t p = s_p;
+    if (p != c)
+      for (int32_t q = c + tid; q < w; q += blockDim.x) {
+        double a = A(c, q);
+        A(c, q) = A(p, q);
+        A(p, q) = a;
+      }
+    __syncthreads();
+    const double rinv = 1.0 / s_piv;
+    const int32_t rows = d - 1 - c, cols = w - c - 1;
+    for (int64_t t = tid; t < (int64_t)rows * cols; t += blockDim.x) {
+      int32_t r = c + 1 + (int32_t)(t / cols), q = c + 1 + (int32_t)(t % cols);
+      double l = A(r, c) * rinv;
+      A(r, q) -= l * A(c, q);
+    }
+    __syncthreads();
+  }
+  if (s_bad) {
+    if (tid == 0) atomicMax(info, 1);
+    return;
+  }
+  // back substitution: E <- U^{-1} E (rows from the bottom)
+  for (int32_t r = d - 1; r >= 0; --r) {
+    const double dinv = 1.0 / A(r, r);
+    for (int32_t q = tid; q < s; q += blockDim.x) E[(int64_t)r * s + q] *= dinv;
+    __syncthreads();
+    for (int64_t t = tid; t < (int64_t)r * s; t += blockDim.x) {
+      int32_t rr = (int32_t)(t / s), q = (int32_t)(t % s);
+      E[(int64_t)rr * s + q] -= D[(int64_t)rr * d + r] * E[(int64_t)r * s + q];
+    }
+    __syncthreads();
+  }
+  // G <- G - F X with 16x16 output tiles, k in steps of 4 (FP64 MFMA).
+  // Lane layout of v_mfma_f64_16x16x4f64 (checked on gfx950): A operand lane
+  // l holds A(l%16, l/16), B operand lane l holds B(l/16, l%16), result
+  // register v of lane l holds C(4*v + l/16, l%16).
+  const int32_t tiles = ((s + 15) / 16);
+  for (int32_t tile = wave; tile < tiles * tiles; tile += blockDim.x / 64) {
+    const int32_t ti = tile / tiles, tj = tile % tiles;
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    const int32_t ar = ti * 16 + (lane & 15), bc = tj * 16 + (lane & 15), kk = lane >> 4;
+    for (int32_t k0 = 0; k0 < d; k0 += 4) {
+      int32_t k = k0 + kk;
+      double a = (ar < s && k < d) ? F[(int64_t)ar * d + k] : 0.0;
+      double b = (k < d && bc < s) ? E[(int64_t)k * s + bc] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    for (int v = 0; v < 4; ++v) {
+      int32_t r = ti * 16 + 4 * v + (lane >> 4), c = tj * 16 + (lane & 15);
+      if (r < s && c < s) G[(int64_t)r * s + c] -= acc[v];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// S_i^{-1} by Gauss-Jordan with partial pivoting on [S | I], stored
+// column-major in the requested precision (FP16 with one scale per block).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(kSetupThreads)
+k_invert_dense(const int32_t* __restrict__ agg_s, const int64_t* __restrict__ g_off, const double* __restrict__ Sall,
+               double* __restrict__ work_all, int32_t* __restrict__ info, const int64_t* __restrict__ sinv_off,
+               T* __restrict__ sinv_all, float* __restrict__ scale_all, int prec) {
+  const int i = blockIdx.x;
+  const int32_t s = agg_s[i];
+  const double* S = Sall + g_off[i];
+  double* A = work_all + 2 * g_off[i];  // s x 2s row-major
+  const int32_t w = 2 * s;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int64_t t = tid; t < (int64_t)s * w; t += blockDim.x) {
+    int32_t r = (int32_t)(t / w), c = (int32_t)(t % w);
+    A[t] = c < s ? S[(int64_t)r * s + c] : (c - s == r ? 1.0 : 0.0);
+  }
+  __shared__ int32_t s_p;
+  __shared__ double s_piv;
+  __shared__ int s_bad;
+  __shared__ double s_red[16];
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int32_t c = 0; c < s; ++c) {
+    if (wave == 0) {
+      double best = -1.0;
+      int32_t bi = c;
+      for (int32_t r = c + lane; r < s; r += 64) {
+        double a = fabs(A[(int64_t)r * w + c]);
+        if (a > best) {
+          best = a;
+          bi = r;
+        }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        double ob = __shfl_xor(best, off);
+        int32_t oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        s_p = bi;
+        s_piv = A[(int64_t)bi * w + c];
+        if (s_piv == 0.0) s_bad = 1;
+      }
+    }
+    __syncthreads();
+    if (s_bad) break;
+    const int32_t p = s_p;
+    if (p != c)
+      for (int32_t q = tid; q < w; q += blockDim.x) {
+        double a = A[(int64_t)c * w + q];
+        A[(int64_t)c * w + q] = A[(int64_t)p * w + q];
+        A[(int64_t)p * w + q] = a;
+      }
+    __syncthreads();
+    const double rinv = 1.0 / s_piv;
+    for (int32_t q = tid; q < w; q += blockDim.x) A[(int64_t)c * w + q] *= rinv;
+    __syncthreads();
+    for (int64_t t = tid; t < (int64_t)s * w; t += blockDim.x) {
+      int32_t r = (int32_t)(t / w), q = (int32_t)(t % w);
+      if (r == c || q == c) continue;
+      A[(int64_t)r * w + q] -= A[(int64_t)r * w + c] * A[(int64_t)c * w + q];
+    }
+    __syncthreads();
+    for (int32_t r = tid; r < s; r += blockDim.x)
+      if (r != c) A[(int64_t)r * w + c] = 0.0;
+    __syncthreads();
+  }
+  if (s_bad) {
+    if (tid == 0) atomicMax(info, 1);
+    return;
+  }
+  float scl = 1.0f;
+  if (prec == P16S) {
+    double mx = 0.0;
+    for (int64_t t = tid; t < (int64_t)s * s; t += blockDim.x) {
+      int32_t r = (int32_t)(t / s), c = (int32_t)(t % s);
+      mx = fmax(mx, fabs(A[(int64_t)r * w + s + c]));
+    }
+    for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if (lane == 0) s_red[wave] = mx;
+    __syncthreads();
+    if (tid == 0) {
+      double m = 0.0;
+      for (int q = 0; q < (int)(blockDim.x / 64); ++q) m = fmax(m, s_red[q]);
+      s_red[0] = m > 0.0 ? m : 1.0;
+      scale_all[i] = (float)s_red[0];
+    }
+    __syncthreads();
+    scl = (float)s_red[0];
+  }
+  T* out = sinv_all + sinv_off[i];
+  for (int64_t t = tid; t < (int64_t)s * s; t += blockDim.x) {
+    int32_t c = (int32_t)(t / s), r = (int32_t)(t % s);  // column-major output
+    double v = A[(int64_t)r * w + s + c];
+    if (prec == P16S) v /= (double)scl;
+    out[t] = to_store<T>(v);
+  }
+}
+
+
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+void launch_row_scale(const int32_t* rowptr, const double* vals, int32_t N, int scale, double* R, hipStream_t s) {
+  if (N > 0) k_row_scale<<<nblocks(N, 256), 256, 0, s>>>(rowptr, vals, N, scale, R);
+}
+void launch_gather_scaled(const int32_t* src, const int32_t* orow, const double* vals, const double* R, int64_t n,
+                          double* out, hipStream_t s) {
+  if (n > 0) k_gather_scaled<<<nblocks(n, 256), 256, 0, s>>>(src, orow, vals, R, n, out);
+}
+void launch_gather(const int32_t* src, const double* in, int64_t n, double* out, hipStream_t s) {
+  if (n > 0) k_gather<<<nblocks(n, 256), 256, 0, s>>>(src, in, n, out);
+}
+void launch_scatter_band(const int64_t* dst, const int32_t* src, const double* cpv, int64_t n, double* ab,
+                         hipStream_t s) {
+  if (n > 0) k_scatter<<<nblocks(n, 256), 256, 0, s>>>(dst, src, cpv, n, ab);
+}
+void launch_dense_scatter(const int64_t* dst, const int32_t* src, const double* cpv, int64_t n, double* out,
+                          hipStream_t s) {
+  if (n > 0) k_scatter<<<nblocks(n, 256), 256, 0, s>>>(dst, src, cpv, n, out);
+}
+void launch_band_pad_identity(const int32_t* sub_n, const int32_t* sub_npad, const int64_t* band_off, int32_t m,
+                              int32_t ldab, int32_t KL, int32_t KU, double* ab, hipStream_t s) {
+  if (m > 0) k_band_pad_identity<<<m, 256, 0, s>>>(sub_n, sub_npad, band_off, ldab, KL + KU, ab);
+}
+void launch_band_lu(double* ab, int32_t* ipiv, const int64_t* band_off, const int32_t* sub_npad,
+                    const int32_t* sub_vec_off, int32_t m, int32_t ldab, int32_t KL, int32_t KU, int32_t* info,
+                    hipStream_t s) {
+  if (m > 0) k_band_lu<<<m, kSetupThreads, 0, s>>>(ab, ipiv, band_off, sub_npad, sub_vec_off, ldab, KL, KU, info);
+}
+void launch_convert_lower(const double* ab, const int32_t* ipiv, const int64_t* band_off, const int32_t* sub_vec_off,
+                          const int32_t* lblk_sub, const int32_t* lblk_idx, int32_t nblk, int32_t ldab, int32_t KL,
+                          int32_t KU, int32_t nbL, double* work, int32_t* lperm, void* l11inv, void* l21, int prec,
+                          hipStream_t s) {
+  if (nblk == 0) return;
+  if (prec == P64)
+    k_convert_lower<double><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, band_off, sub_vec_off, lblk_sub, lblk_idx, ldab,
+                                                            KL, KU, nbL, work, lperm, (double*)l11inv, (double*)l21);
+  else
+    k_convert_lower<float><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, band_off, sub_vec_off, lblk_sub, lblk_idx, ldab,
+                                                           KL, KU, nbL, work, lperm, (float*)l11inv, (float*)l21);
+}
+void launch_convert_upper(const double* ab, const int64_t* band_off, const int32_t* ublk_sub, const int32_t* ublk_idx,
+                          const int32_t* sub_npad, int32_t nblk, int32_t ldab, int32_t KL, int32_t KU, int32_t nbU,
+                          double* work, void* uinv, void* u12, int prec, int32_t* info, hipStream_t s) {
+  if (nblk == 0) return;
+  if (prec == P64)
+    k_convert_upper<double><<<nblk, kSetupThreads, 0, s>>>(ab, band_off, ublk_sub, ublk_idx, sub_npad, ldab, KL, KU,
+                                                            nbU, work, (double*)uinv, (double*)u12, info);
+  else
+    k_convert_upper<float><<<nblk, kSetupThreads, 0, s>>>(ab, band_off, ublk_sub, ublk_idx, sub_npad, ldab, KL, KU,
+                                                           nbU, work, (float*)uinv, (float*)u12, info);
+}
+void launch_schur_blocks(int32_t k, const int32_t* agg_s, const int32_t* agg_d, const int64_t* g_off,
+                         const int64_t* dd_off, const int64_t* de_off, const int64_t* df_off, double* G, double* Dd,
+                         double* De, double* Df, int32_t* info, hipStream_t s) {
+  if (k > 0) k_schur_blocks<<<k, kSetupThreads, 0, s>>>(agg_s, agg_d, g_off, dd_off, de_off, df_off, G, Dd, De, Df, info);
+}
+void launch_invert_dense(int32_t k, const int32_t* agg_s, const int64_t* g_off, const double* S, double* work,
+                         int32_t* info, const int64_t* sinv_off, void* sinv, float* scale, int prec, hipStream_t s) {
+  if (k == 0) return;
+  if (prec == P64)
+    k_invert_dense<double><<<k, kSetupThreads, 0, s>>>(agg_s, g_off, S, work, info, sinv_off, (double*)sinv, scale,
+                                                        prec);
+  else if (prec == P32)
+    k_invert_dense<float><<<k, kSetupThreads, 0, s>>>(agg_s, g_off, S, work, info, sinv_off, (float*)sinv, scale, prec);
+  else
+    k_invert_dense<__half><<<k, kSetupThreads, 0, s>>>(agg_s, g_off, S, work, info, sinv_off, (__half*)sinv, scale,
+                                                        prec);
+}
+
+}  // namespace addns

@@ -1,0 +1,180 @@
+// Internal state of a preconditioner handle and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace addns {
+
+#define ADDNS_HIP(call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      throw HipError(std::string(#call) + ": " + hipGetErrorString(e_));             \
+    }                                                                                \
+  } while (0)
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct SingularError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct ArgError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+// Owning device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { reset(); }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t n) {
+    reset();
+    if (n == 0) n = 8;
+    ADDNS_HIP(hipMalloc(&p, n));
+    bytes = n;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+  template <class T>
+  void upload(const std::vector<T>& v, hipStream_t s) {
+    alloc(v.size() * sizeof(T));
+    if (!v.empty()) ADDNS_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+};
+
+// Host-side integer plan: every gather map the device setup needs.  Built
+// from the partition and the pattern only.
+struct Plan {
+  int32_t N = 0, m = 0, k = 0, n_int = 0, nsep = 0;
+  int32_t KL = 0, KU = 0;     // max lower / upper bandwidth of the interiors
+  int32_t nbL = 0, nbU = 0;   // block sizes of the lower / upper sweeps
+  int32_t ldab = 0;           // band storage leading dimension 2KL+KU+1
+  // permuted CSR of C~ (new numbering) and the source entry of each value
+  std::vector<int32_t> cp_rowptr, cp_colidx, cp_src, cp_orow;
+  std::vector<int32_t> perm, iperm;
+  // interior blocks
+  std::vector<int32_t> sub_n, sub_npad;          // m
+  std::vector<int64_t> sub_band_off;             // m+1 offsets (elements) into band storage
+  std::vector<int32_t> sub_vec_off;              // m+1 offsets into the padded scratch vector
+  std::vector<int64_t> band_dst;                 // band element index per interior C~p entry
+  std::vector<int32_t> band_src;                 //   ... and its C~p entry
+  std::vector<int32_t> lblk_sub, lblk_idx;       // per L-block: subdomain and block index
+  std::vector<int32_t> ublk_sub, ublk_idx;       // per U-block
+  std::vector<int32_t> sub_lblk0, sub_ublk0;     // m+1 first block of each subdomain
+  // E (interior rows x separator cols) and F (separator rows x interior cols), CSR
+  std::vector<int32_t> e_rowptr, e_colidx, e_src;
+  std::vector<int32_t> f_rowptr, f_colidx, f_src;
+  // dense Schur blocks (aggregate i: s_i = |agg|, d_i = |D-range|)
+  std::vector<int32_t> agg_off, agg_s, agg_d;    // agg_off: k+1 separator positions
+  std::vector<int64_t> g_off, dd_off, de_off, df_off, sinv_off;  // element offsets
+  std::vector<int64_t> dense_dst;                // scratch element index
+  std::vector<int32_t> dense_src;                // C~p entry
+  int64_t g_total = 0, dd_total = 0, de_total = 0, df_total = 0;
+};
+
+void build_plan(const PartitionData& P, Plan& pl, int schur_mode);
+
+// Storage precision tags
+enum Prec { P64 = 0, P32 = 1, P16S = 2 };
+
+}  // namespace addns
+
+struct addns_precond {
+  addns::Plan plan;
+  int schur_mode = 0, interior_prec = 0, schur_prec = 0, row_scale = 1;
+  int device = 0;
+  // vectors / matrices (device)
+  addns::DevBuf perm, iperm, R;                       // R in original numbering
+  addns::DevBuf cp_rowptr, cp_colidx, cp_vals;        // C~ permuted (fp64)
+  addns::DevBuf e_rowptr, e_colidx, e_vals, f_rowptr, f_colidx, f_vals;
+  // interior factors in block form
+  addns::DevBuf sub_n, sub_npad, sub_vec_off, sub_lblk0, sub_ublk0, sub_int_off;
+  addns::DevBuf lperm;                                // per L-block (nbL+KL) int32
+  addns::DevBuf l11inv, l21;                          // per L-block, storage precision
+  addns::DevBuf uinv, u12;                            // per U-block
+  // interface
+  addns::DevBuf agg_off, agg_s, sinv_off, sinv, sinv_scale, schur_S;
+  // scratch
+  addns::DevBuf ypad, zpad, z1, x2tmp;                // padded interior work vectors
+  addns::DevBuf vperm_in, vperm_out;                  // permuted apply in/out
+  int64_t factor_bytes = 0, bytes_apply = 0;
+  int64_t learned_count = 0;
+  // GMRES work space (grown on demand)
+  addns::DevBuf V, Z, w, xp, bp, rp, Hd, gd, partials, scal;
+  int gm_restart = 0;
+  void* host_pinned = nullptr;
+  ~addns_precond() {
+    if (host_pinned) (void)hipHostFree(host_pinned);
+  }
+};
+
+namespace addns {
+// launchers (kernels_*.hip)
+void launch_row_scale(const int32_t* rowptr, const double* vals, int32_t N, int scale, double* R,
+                      hipStream_t s);
+void launch_gather_scaled(const int32_t* src, const int32_t* orow, const double* vals, const double* R,
+                          int64_t n, double* out, hipStream_t s);
+void launch_gather(const int32_t* src, const double* in, int64_t n, double* out, hipStream_t s);
+void launch_scatter_band(const int64_t* dst, const int32_t* src, const double* cpv, int64_t n, double* ab,
+                         hipStream_t s);
+void launch_band_pad_identity(const int32_t* sub_n, const int32_t* sub_npad, const int64_t* band_off,
+                              int32_t m, int32_t ldab, int32_t KL, int32_t KU, double* ab, hipStream_t s);
+void launch_band_lu(double* ab, int32_t* ipiv, const int64_t* band_off, const int32_t* sub_npad,
+                    const int32_t* sub_vec_off, int32_t m, int32_t ldab, int32_t KL, int32_t KU, int32_t* info,
+                    hipStream_t s);
+void launch_convert_lower(const double* ab, const int32_t* ipiv, const int64_t* band_off,
+                          const int32_t* sub_vec_off, const int32_t* lblk_sub, const int32_t* lblk_idx,
+                          int32_t nblk, int32_t ldab, int32_t KL, int32_t KU, int32_t nbL, double* work,
+                          int32_t* lperm, void* l11inv, void* l21, int prec, hipStream_t s);
+void launch_convert_upper(const double* ab, const int64_t* band_off, const int32_t* ublk_sub,
+                          const int32_t* ublk_idx, const int32_t* sub_npad, int32_t nblk, int32_t ldab,
+                          int32_t KL, int32_t KU, int32_t nbU, double* work, void* uinv, void* u12, int prec,
+                          int32_t* info, hipStream_t s);
+void launch_dense_scatter(const int64_t* dst, const int32_t* src, const double* cpv, int64_t n, double* out,
+                          hipStream_t s);
+void launch_schur_blocks(int32_t k, const int32_t* agg_s, const int32_t* agg_d, const int64_t* g_off,
+                         const int64_t* dd_off, const int64_t* de_off, const int64_t* df_off, double* G,
+                         double* Dd, double* De, double* Df, int32_t* info, hipStream_t s);
+void launch_invert_dense(int32_t k, const int32_t* agg_s, const int64_t* g_off, const double* S,
+                         double* work, int32_t* info, const int64_t* sinv_off, void* sinv, float* scale,
+                         int prec, hipStream_t s);
+void launch_interior_solve(const addns_precond* pc, const double* yin, double* out, int second,
+                           const double* x2, const double* z1, hipStream_t s);
+void launch_interface_solve(const addns_precond* pc, const double* y, const double* z1, double* x2out,
+                            hipStream_t s);
+void launch_permute(const int32_t* perm, const double* in, double* out, int32_t n, int inverse,
+                    const double* scale, hipStream_t s);
+// krylov
+void launch_spmv(const int32_t* rowptr, const int32_t* colidx, const double* vals, const double* x,
+                 double* y, int32_t n, hipStream_t s);
+int krylov_grid(int32_t n);
+void launch_spmv_dot(const int32_t* rowptr, const int32_t* colidx, const double* vals, const double* x,
+                     double* w, const double* v0, int32_t n, double* partials, hipStream_t s);
+void launch_residual(const int32_t* rowptr, const int32_t* colidx, const double* vals, const double* x,
+                     const double* b, double* r, int32_t n, double* partials, hipStream_t s);
+void launch_mgs_step(double* w, const double* vi, const double* vnext, int32_t n, const double* partials_in,
+                     double* partials_out, double* h_out, int nparts, hipStream_t s);
+void launch_finalize(double* H, double* g, double* cs, double* sn, const double* partials, int nparts,
+                     int32_t j, int32_t ldh, double* scal, hipStream_t s);
+void launch_scale_copy(const double* w, double* v, const double* scal, int idx, int32_t n, hipStream_t s);
+void launch_norm_finalize(const double* partials, int nparts, double* scal, int idx, hipStream_t s);
+void launch_backsolve(const double* H, const double* g, int32_t j, int32_t ldh, double* y, hipStream_t s);
+void launch_combine(const double* Z, int64_t ldz, const double* y, int32_t j, int32_t n, double* x, int add,
+                    hipStream_t s);
+void launch_dot_partials(const double* a, const double* b, int32_t n, double* partials, hipStream_t s);
+}  // namespace addns

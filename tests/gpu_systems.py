@@ -1,0 +1,56 @@
+"""Shared set-up for GPU parity tests: one seeded system, prepared both by
+the oracle (CPU, FP64) and by libaddns (GPU), from the same generator call."""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from oracle.partition import build_partition as oracle_partition
+from oracle.precond import LUM, MSCN, MSCN_LITERAL, Preconditioner
+from paper_1104_3349_amd import addns
+from workloads.mac_oseen import Wind, make_oseen_mac
+
+ORACLE_MODE = {addns.SCHUR_MSCN: MSCN, addns.SCHUR_LUM: LUM, addns.SCHUR_MSCN_LITERAL: MSCN_LITERAL}
+
+
+@dataclass
+class System:
+    n: int
+    N: int
+    rp: np.ndarray
+    ci: np.ndarray
+    v: np.ndarray
+    b: np.ndarray
+    meta: dict
+    m: int
+    sz: int
+
+
+def make_system(n, nu, m, sz=64, stretch=None, seed=1, wind=None):
+    rp, ci, v, b, meta = make_oseen_mac(n, nu, wind=wind or Wind(), stretch=stretch, seed=seed)
+    return System(n, meta["N"], rp, ci, v, b, meta, m, sz)
+
+
+def oracle_precond(S: System, schur=addns.SCHUR_MSCN):
+    P = oracle_partition(S.N, S.rp, S.ci, S.v, S.m, S.sz)
+    return Preconditioner(S.N, S.rp, S.ci, S.v, P, ORACLE_MODE[schur])
+
+
+def gpu_precond(S: System, schur=addns.SCHUR_MSCN, iprec=addns.F64, sprec=addns.F64):
+    import torch
+    part = addns.build_partition(S.N, S.rp, S.ci, S.v, S.m, S.sz)
+    d_rp = torch.from_numpy(S.rp).cuda()
+    d_ci = torch.from_numpy(S.ci).cuda()
+    d_v = torch.from_numpy(S.v).cuda()
+    pc = addns.setup_precond(part, S.N, d_rp, d_ci, d_v, schur=schur, interior_prec=iprec,
+                             schur_prec=sprec)
+    torch.cuda.synchronize()
+    return part, pc
+
+
+def relerr(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    d = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (d if d > 0 else 1.0))
