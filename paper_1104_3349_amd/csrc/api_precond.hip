@@ -126,8 +126,7 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
     usub.upload(pl.ublk_sub, s);
     uidx.upload(pl.ublk_idx, s);
     pc->lperm.alloc(sizeof(int32_t) * (int64_t)nL * W);
-    pc->l11inv.alloc((int64_t)fb * nL * pl.nbL * pl.nbL);
-    pc->l21.alloc((int64_t)fb * nL * pl.KL * pl.nbL);
+    pc->lmat.alloc((int64_t)fb * nL * W * pl.nbL);
     pc->uinv.alloc((int64_t)fb * nU * pl.nbU * pl.nbU);
     pc->u12.alloc((int64_t)fb * nU * pl.nbU * pl.nbU);
     const int64_t wl = (int64_t)nL * ((int64_t)W * pl.nbL + (int64_t)pl.nbL * pl.nbL);
@@ -135,7 +134,7 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
     work.alloc(sizeof(double) * std::max(wl, wu));
     launch_convert_lower(ab.as<double>(), ipiv.as<int32_t>(), band_off.as<int64_t>(), pc->sub_vec_off.as<int32_t>(),
                          lsub.as<int32_t>(), lidx.as<int32_t>(), nL, pl.ldab, pl.KL, pl.KU, pl.nbL, work.as<double>(),
-                         pc->lperm.as<int32_t>(), pc->l11inv.p, pc->l21.p, iprec, s);
+                         pc->lperm.as<int32_t>(), pc->lmat.p, iprec, s);
     launch_convert_upper(ab.as<double>(), band_off.as<int64_t>(), usub.as<int32_t>(), uidx.as<int32_t>(),
                          pc->sub_npad.as<int32_t>(), nU, pl.ldab, pl.KL, pl.KU, pl.nbU, work.as<double>(), pc->uinv.p,
                          pc->u12.p, iprec, info.as<int32_t>() + m, s);
@@ -193,7 +192,7 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
 
   // -- byte accounting
   int64_t fbytes = 0;
-  fbytes += (int64_t)nL * (pl.nbL * pl.nbL + pl.KL * pl.nbL) * fb + (int64_t)nL * (pl.nbL + pl.KL) * 4;
+  fbytes += (int64_t)nL * (pl.nbL + pl.KL) * pl.nbL * fb + (int64_t)nL * (pl.nbL + pl.KL) * 4;
   fbytes += (int64_t)nU * 2 * pl.nbU * pl.nbU * fb;
   fbytes += pl.g_total * prec_bytes(sprec);
   pc->factor_bytes = fbytes;

@@ -27,46 +27,83 @@ __device__ inline double ld(const T* p) { return (double)(*p); }
 template <>
 __device__ inline double ld<__half>(const __half* p) { return (double)__half2float(*p); }
 
-// y[r] = sum_k M(r,k) v[k] for r < R, k restricted per row to
-// [lo(r), hi(r)), M column-major with leading dimension R.
-// kind 0: full; 1: lower (k <= r); 2: upper (k >= r); 3: k <= r + shift.
-// Result into out[0..R) (LDS).  part: LDS scratch of kWaves * R doubles.
+// Partial GEMV of one block step: part[w*R + r] = sum over the columns k of
+// wave w of M(r, k) vec(k), M column-major with leading dimension R.  Each
+// wave owns a contiguous column chunk and every row slot (lane + 64 s, s <
+// S), so a batch issues CB columns x S slots of independent coalesced loads
+// before any FMA (memory-level parallelism is what bounds a single CU).
+// Structural zeros are never fetched:
+//   kind 2: upper        M(r,k) = 0 for k < r
+//   kind 3: band-shifted M(r,k) = 0 for k > r + par
+//   kind 4: [lower; full] M(r,k) = 0 for k > r when r < par
+// vec(k) = vin[gidx[k]] when gidx is given (the window permutation), else
+// vin[k].  The caller synchronises and reduces over waves.
+// Raw buffer loads: an offset at or beyond the resource's byte range returns
+// 0 without touching memory, so masked elements cost neither a branch nor a
+// fetch (the third descriptor dword is the gfx9-family raw-buffer format).
+constexpr int kBufFormatWord = 0x00020000;
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufFormatWord);
+}
+
 template <class T>
-__device__ void block_gemv(const T* __restrict__ M, int R, int K, const double* v, double* out, double* part,
-                           int kind, int shift) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int RT = (R + 63) >> 6;
-  const int CS = max(1, kWaves / RT);
-  if (wave < RT * CS) {
-    const int tile = wave % RT, cs = wave / RT;
-    const int r = tile * 64 + lane;
-    int kb = (int)((int64_t)K * cs / CS), ke = (int)((int64_t)K * (cs + 1) / CS);
-    const int rmin = tile * 64, rmax = min(R, rmin + 64) - 1;
-    if (kind == 1) ke = min(ke, rmax + 1);
-    else if (kind == 2) kb = max(kb, rmin);
-    else if (kind == 3) ke = min(ke, rmax + shift + 1);
-    int lo = 0, hi = K;
-    if (kind == 1) hi = r + 1;
-    else if (kind == 2) lo = r;
-    else if (kind == 3) hi = r + shift + 1;
-    double acc = 0.0;
-    if (r < R) {
-      const T* col = M + (int64_t)kb * R + r;
-      int k = kb;
-#pragma unroll 4
-      for (; k < ke; ++k, col += R) {
-        if (k >= lo && k < hi) acc += ld(col) * v[k];
+__device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ inline float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <>
+__device__ inline double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
+template <class T, int S, int kind>
+__device__ inline void gemv_cols(const T* __restrict__ M, int R, int K, int par, const double* vin,
+                                 const int32_t* __restrict__ gidx, double* part) {
+  constexpr int CB = (sizeof(T) == 4 && S <= 6) ? 8 : 4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int kb = K * w / kWaves, ke = K * (w + 1) / kWaves;
+  const uint32_t nbytes = (uint32_t)R * (uint32_t)K * (uint32_t)sizeof(T);
+  const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(M, nbytes);
+  double acc[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) acc[s] = 0.0;
+  for (int k0 = kb; k0 < ke; k0 += CB) {
+    T vals[CB][S];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int k = k0 + c;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int r = 64 * s + lane;
+        bool ok = k < ke && r < R;
+        if constexpr (kind == 2) ok = ok && k >= r;
+        else if constexpr (kind == 3) ok = ok && k <= r + par;
+        else if constexpr (kind == 4) ok = ok && (r >= par || k <= r);
+        vals[c][s] = buf_load<T>(rsrc, ok ? (uint32_t)(k * R + r) * (uint32_t)sizeof(T) : nbytes);
       }
     }
-    if (r < R) part[cs * R + r] = acc;
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int k = k0 + c;
+      const double vk = k < ke ? (gidx ? vin[gidx[k]] : vin[k]) : 0.0;
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc[s] += (double)vals[c][s] * vk;
+    }
   }
-  __syncthreads();
-  for (int r = tid; r < R; r += blockDim.x) {
-    double s = 0.0;
-    for (int c = 0; c < CS; ++c) s += part[c * R + r];
-    out[r] = s;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int r = 64 * s + lane;
+    if (r < R) part[w * R + r] = acc[s];
   }
-  __syncthreads();
+}
+
+__device__ inline double sum_parts(const double* part, int R, int r) {
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) s += part[w * R + r];
+  return s;
 }
 
 struct SweepArgs {
@@ -78,8 +115,7 @@ struct SweepArgs {
   const int32_t* sub_lblk0;
   const int32_t* sub_ublk0;
   const int32_t* lperm;
-  const void* l11inv;
-  const void* l21;
+  const void* lmat;
   const void* uinv;
   const void* u12;
   const int32_t* e_rowptr;
@@ -91,23 +127,29 @@ struct SweepArgs {
 // One workgroup per subdomain.  second == 0: out[int] = D^{-1} yin[int].
 // second == 1: input u = E x2 (x2 = separator part, CSR E), and
 // out[int] = z1[int] - D^{-1} u.
-template <class T>
+//
+// Lower sweep, block b (window rows b*nbL .. b*nbL+W-1, W = nbL+KL):
+//   v = P_b w;  [x_b; c] = [inv(L11); L21 inv(L11)] v_top;  carry = v_bot - c
+// Upper sweep, block b (rows b*nbU ..):  x_b = inv(U_bb) (y_b - U_b,b+1 x_b+1)
+template <class T, int S>
 __global__ void __launch_bounds__(kSweepThreads)
-k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* __restrict__ out, int second,
-                 const double* __restrict__ x2, const double* __restrict__ z1) {
+k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int second, const double* x2,
+                 const double* z1) {
   extern __shared__ double smem[];
   const int sub = blockIdx.x;
   const int32_t n = a.sub_n[sub], npad = a.sub_npad[sub];
   if (n == 0) return;
   const int32_t ioff = a.sub_int_off[sub], voff = a.sub_vec_off[sub];
   const int32_t KL = a.KL, nbL = a.nbL, nbU = a.nbU, W = nbL + KL;
+  const int32_t RM = max(W, nbU);
   const int tid = threadIdx.x;
-  double* w = smem;                 // W
-  double* v = w + W;                // W
-  double* xb = v + W;               // max(nbL, nbU)
-  double* t = xb + nbU;             // nbU
-  double* part = t + nbU;           // kWaves * max(W, nbU)
+  double* wA = smem;             // W
+  double* wB = wA + W;           // W
+  double* t = wB + W;            // nbU
+  double* xn = t + nbU;          // nbU
+  double* part = xn + nbU;       // kWaves * RM
   double* ypad = a.ypad + voff;
+  (void)RM;
   auto input = [&](int32_t r) -> double {
     if (r >= n) return 0.0;
     if (!second) return yin[ioff + r];
@@ -115,22 +157,28 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* __restrict
     for (int32_t e = a.e_rowptr[ioff + r]; e < a.e_rowptr[ioff + r + 1]; ++e) s += a.e_vals[e] * x2[a.e_colidx[e]];
     return s;
   };
-  // ---- forward sweep over lower blocks: window = [carry (KL); next nbL rows]
-  for (int32_t r = tid; r < KL; r += blockDim.x) w[r] = input(r);
+  // ---- forward sweep over lower blocks
+  double* wc = wA;
+  double* wn = wB;
+  for (int32_t r = tid; r < W; r += blockDim.x) wc[r] = input(r);
+  __syncthreads();
   const int32_t nL = npad / nbL;
   const int32_t lb0 = a.sub_lblk0[sub];
   for (int32_t b = 0; b < nL; ++b) {
     const int64_t blk = lb0 + b;
-    for (int32_t r = tid; r < nbL; r += blockDim.x) w[KL + r] = input(b * nbL + KL + r);
-    __syncthreads();
     const int32_t* idx = a.lperm + blk * W;
-    for (int32_t r = tid; r < W; r += blockDim.x) v[r] = w[idx[r]];
+    gemv_cols<T, S, 4>((const T*)a.lmat + blk * W * nbL, W, nbL, nbL, wc, idx, part);
     __syncthreads();
-    block_gemv<T>((const T*)a.l11inv + blk * nbL * nbL, nbL, nbL, v, xb, part, 1, 0);
-    for (int32_t r = tid; r < nbL; r += blockDim.x) ypad[b * nbL + r] = xb[r];
-    block_gemv<T>((const T*)a.l21 + blk * KL * nbL, KL, nbL, xb, t, part, 0, 0);
-    for (int32_t r = tid; r < KL; r += blockDim.x) w[r] = v[nbL + r] - t[r];
+    for (int32_t r = tid; r < W; r += blockDim.x) {
+      const double v = sum_parts(part, W, r);
+      if (r < nbL) ypad[b * nbL + r] = v;
+      else wn[r - nbL] = wc[idx[r]] - v;
+    }
+    for (int32_t r = tid; r < nbL; r += blockDim.x) wn[KL + r] = input((b + 1) * nbL + KL + r);
     __syncthreads();
+    double* tmp = wc;
+    wc = wn;
+    wn = tmp;
   }
   // ---- backward sweep over upper blocks
   const int32_t nU = npad / nbU;
@@ -138,18 +186,22 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* __restrict
   for (int32_t b = nU - 1; b >= 0; --b) {
     const int64_t blk = ub0 + b;
     if (b < nU - 1) {
-      block_gemv<T>((const T*)a.u12 + blk * nbU * nbU, nbU, nbU, xb, t, part, 3, a.KV - nbU);
-      for (int32_t r = tid; r < nbU; r += blockDim.x) t[r] = ypad[b * nbU + r] - t[r];
+      gemv_cols<T, S, 3>((const T*)a.u12 + blk * nbU * nbU, nbU, nbU, a.KV - nbU, xn, nullptr, part);
+      __syncthreads();
+      for (int32_t r = tid; r < nbU; r += blockDim.x) t[r] = ypad[b * nbU + r] - sum_parts(part, nbU, r);
     } else {
       for (int32_t r = tid; r < nbU; r += blockDim.x) t[r] = ypad[b * nbU + r];
     }
     __syncthreads();
-    block_gemv<T>((const T*)a.uinv + blk * nbU * nbU, nbU, nbU, t, xb, part, 2, 0);
+    gemv_cols<T, S, 2>((const T*)a.uinv + blk * nbU * nbU, nbU, nbU, 0, t, nullptr, part);
+    __syncthreads();
     for (int32_t r = tid; r < nbU; r += blockDim.x) {
-      int32_t row = b * nbU + r;
+      const double x = sum_parts(part, nbU, r);
+      xn[r] = x;
+      const int32_t row = b * nbU + r;
       if (row < n) {
-        if (second) out[ioff + row] = z1[ioff + row] - xb[r];
-        else out[ioff + row] = xb[r];
+        if (second) out[ioff + row] = z1[ioff + row] - x;
+        else out[ioff + row] = x;
       }
     }
     __syncthreads();
@@ -216,6 +268,31 @@ size_t sweep_smem_bytes(int32_t KL, int32_t nbL, int32_t nbU) {
   return sizeof(double) * (size_t)(2 * W + 2 * nbU + kWaves * std::max(W, nbU));
 }
 
+template <class T, int S>
+static void launch_sweep(const SweepArgs& a, int m, size_t smem, const double* yin, double* out, int second,
+                         const double* x2, const double* z1, hipStream_t s) {
+  if (smem > 64 * 1024)
+    ADDNS_HIP(hipFuncSetAttribute((const void*)k_interior_solve<T, S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)smem));
+  k_interior_solve<T, S><<<m, kSweepThreads, smem, s>>>(a, yin, out, second, x2, z1);
+}
+
+template <class T>
+static void dispatch_sweep(int S, const SweepArgs& a, int m, size_t smem, const double* yin, double* out, int second,
+                           const double* x2, const double* z1, hipStream_t s) {
+  switch (S) {
+    case 1: launch_sweep<T, 1>(a, m, smem, yin, out, second, x2, z1, s); break;
+    case 2: launch_sweep<T, 2>(a, m, smem, yin, out, second, x2, z1, s); break;
+    case 3: launch_sweep<T, 3>(a, m, smem, yin, out, second, x2, z1, s); break;
+    case 4: launch_sweep<T, 4>(a, m, smem, yin, out, second, x2, z1, s); break;
+    case 5: launch_sweep<T, 5>(a, m, smem, yin, out, second, x2, z1, s); break;
+    case 6: launch_sweep<T, 6>(a, m, smem, yin, out, second, x2, z1, s); break;
+    case 7: launch_sweep<T, 7>(a, m, smem, yin, out, second, x2, z1, s); break;
+    case 8: launch_sweep<T, 8>(a, m, smem, yin, out, second, x2, z1, s); break;
+    default: throw ArgError("interior bandwidth too large for the sweep kernel (block rows > 512)");
+  }
+}
+
 void launch_interior_solve(const addns_precond* pc, const double* yin, double* out, int second, const double* x2,
                            const double* z1, hipStream_t s) {
   const Plan& pl = pc->plan;
@@ -232,28 +309,18 @@ void launch_interior_solve(const addns_precond* pc, const double* yin, double* o
   a.sub_lblk0 = pc->sub_lblk0.as<int32_t>();
   a.sub_ublk0 = pc->sub_ublk0.as<int32_t>();
   a.lperm = pc->lperm.as<int32_t>();
-  a.l11inv = pc->l11inv.p;
-  a.l21 = pc->l21.p;
+  a.lmat = pc->lmat.p;
   a.uinv = pc->uinv.p;
   a.u12 = pc->u12.p;
   a.e_rowptr = pc->e_rowptr.as<int32_t>();
   a.e_colidx = pc->e_colidx.as<int32_t>();
   a.e_vals = pc->e_vals.as<double>();
   a.ypad = second ? pc->zpad.as<double>() : pc->ypad.as<double>();
-  size_t smem = sweep_smem_bytes(pl.KL, pl.nbL, pl.nbU);
+  const size_t smem = sweep_smem_bytes(pl.KL, pl.nbL, pl.nbU);
   if (smem > 160 * 1024) throw ArgError("interior bandwidth too large for the LDS-staged sweep");
-  if (smem > 64 * 1024) {
-    if (pc->interior_prec == P64)
-      ADDNS_HIP(hipFuncSetAttribute((const void*)k_interior_solve<double>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-    else
-      ADDNS_HIP(hipFuncSetAttribute((const void*)k_interior_solve<float>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-  }
-  if (pc->interior_prec == P64)
-    k_interior_solve<double><<<pl.m, kSweepThreads, smem, s>>>(a, yin, out, second, x2, z1);
-  else
-    k_interior_solve<float><<<pl.m, kSweepThreads, smem, s>>>(a, yin, out, second, x2, z1);
+  const int S = (std::max(pl.nbL + pl.KL, pl.nbU) + 63) / 64;
+  if (pc->interior_prec == P64) dispatch_sweep<double>(S, a, pl.m, smem, yin, out, second, x2, z1, s);
+  else dispatch_sweep<float>(S, a, pl.m, smem, yin, out, second, x2, z1, s);
 }
 
 void launch_interface_solve(const addns_precond* pc, const double* y, const double* z1, double* out, hipStream_t s) {

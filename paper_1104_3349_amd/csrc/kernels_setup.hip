@@ -170,8 +170,10 @@ __device__ inline __half to_store<__half>(double v) { return __float2half((float
 // c0+nbL-1) the row operations of the band LU touch only the window rows
 // c0 .. c0+nbL+KL-1.  Their product is L~^{-1} P with P the window
 // permutation and L~ = [L11 0; L21 I] the multipliers after the later swaps
-// of the block.  Stored: the gather indices of P, inv(L11) (nbL x nbL,
-// column-major) and L21 (KL x nbL, column-major).
+// of the block, so that for the permuted window v = P w
+//     x_b = inv(L11) v_top,   carry = v_bot - (L21 inv(L11)) v_top.
+// Stored per block: the gather indices of P (W = nbL+KL) and one column-major
+// W x nbL matrix [inv(L11); L21 inv(L11)], applied to v_top as one GEMV.
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ void __launch_bounds__(kSetupThreads)
@@ -179,7 +181,7 @@ k_convert_lower(const double* __restrict__ ab_all, const int32_t* __restrict__ i
                 const int64_t* __restrict__ band_off, const int32_t* __restrict__ sub_vec_off,
                 const int32_t* __restrict__ lblk_sub, const int32_t* __restrict__ lblk_idx, int32_t ldab,
                 int32_t KL, int32_t KU, int32_t nbL, double* __restrict__ work_all, int32_t* __restrict__ lperm_all,
-                T* __restrict__ l11inv_all, T* __restrict__ l21_all) {
+                T* __restrict__ lmat_all) {
   const int blk = blockIdx.x;
   const int sub = lblk_sub[blk];
   const int32_t c0 = lblk_idx[blk] * nbL;
@@ -234,12 +236,17 @@ k_convert_lower(const double* __restrict__ ab_all, const int32_t* __restrict__ i
     }
     __syncthreads();
   }
-  T* l11 = l11inv_all + (int64_t)blk * nbL * nbL;
-  T* l21 = l21_all + (int64_t)blk * KL * nbL;
-  for (int64_t t = tid; t < (int64_t)nbL * nbL; t += blockDim.x) l11[t] = to_store<T>(X[t]);
-  for (int64_t t = tid; t < (int64_t)KL * nbL; t += blockDim.x) {
-    int32_t c = (int32_t)(t / KL), r = (int32_t)(t % KL);
-    l21[t] = to_store<T>(Lw[(int64_t)c * W + nbL + r]);
+  T* lm = lmat_all + (int64_t)blk * W * nbL;
+  for (int64_t t = tid; t < (int64_t)W * nbL; t += blockDim.x) {
+    int32_t c = (int32_t)(t / W), r = (int32_t)(t % W);
+    double v;
+    if (r < nbL) {
+      v = X[(int64_t)c * nbL + r];
+    } else {  // (L21 inv(L11))(r - nbL, c), inv(L11) lower: k >= c
+      v = 0.0;
+      for (int32_t k = c; k < nbL; ++k) v += Lw[(int64_t)k * W + r] * X[(int64_t)c * nbL + k];
+    }
+    lm[t] = to_store<T>(v);
   }
 }
 
@@ -547,15 +554,14 @@ void launch_band_lu(double* ab, int32_t* ipiv, const int64_t* band_off, const in
 }
 void launch_convert_lower(const double* ab, const int32_t* ipiv, const int64_t* band_off, const int32_t* sub_vec_off,
                           const int32_t* lblk_sub, const int32_t* lblk_idx, int32_t nblk, int32_t ldab, int32_t KL,
-                          int32_t KU, int32_t nbL, double* work, int32_t* lperm, void* l11inv, void* l21, int prec,
-                          hipStream_t s) {
+                          int32_t KU, int32_t nbL, double* work, int32_t* lperm, void* lmat, int prec, hipStream_t s) {
   if (nblk == 0) return;
   if (prec == P64)
     k_convert_lower<double><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, band_off, sub_vec_off, lblk_sub, lblk_idx, ldab,
-                                                            KL, KU, nbL, work, lperm, (double*)l11inv, (double*)l21);
+                                                            KL, KU, nbL, work, lperm, (double*)lmat);
   else
     k_convert_lower<float><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, band_off, sub_vec_off, lblk_sub, lblk_idx, ldab,
-                                                           KL, KU, nbL, work, lperm, (float*)l11inv, (float*)l21);
+                                                           KL, KU, nbL, work, lperm, (float*)lmat);
 }
 void launch_convert_upper(const double* ab, const int64_t* band_off, const int32_t* ublk_sub, const int32_t* ublk_idx,
                           const int32_t* sub_npad, int32_t nblk, int32_t ldab, int32_t KL, int32_t KU, int32_t nbU,

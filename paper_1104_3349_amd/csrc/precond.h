@@ -105,7 +105,7 @@ struct addns_precond {
   // interior factors in block form
   addns::DevBuf sub_n, sub_npad, sub_vec_off, sub_lblk0, sub_ublk0, sub_int_off;
   addns::DevBuf lperm;                                // per L-block (nbL+KL) int32
-  addns::DevBuf l11inv, l21;                          // per L-block, storage precision
+  addns::DevBuf lmat;                                 // per L-block [inv(L11); L21 inv(L11)]
   addns::DevBuf uinv, u12;                            // per U-block
   // interface
   addns::DevBuf agg_off, agg_s, sinv_off, sinv, sinv_scale, schur_S;
@@ -140,7 +140,7 @@ void launch_band_lu(double* ab, int32_t* ipiv, const int64_t* band_off, const in
 void launch_convert_lower(const double* ab, const int32_t* ipiv, const int64_t* band_off,
                           const int32_t* sub_vec_off, const int32_t* lblk_sub, const int32_t* lblk_idx,
                           int32_t nblk, int32_t ldab, int32_t KL, int32_t KU, int32_t nbL, double* work,
-                          int32_t* lperm, void* l11inv, void* l21, int prec, hipStream_t s);
+                          int32_t* lperm, void* lmat, int prec, hipStream_t s);
 void launch_convert_upper(const double* ab, const int64_t* band_off, const int32_t* ublk_sub,
                           const int32_t* ublk_idx, const int32_t* sub_npad, int32_t nblk, int32_t ldab,
                           int32_t KL, int32_t KU, int32_t nbU, double* work, void* uinv, void* u12, int prec,
