@@ -111,6 +111,9 @@ typedef struct {
   const double* learned_delta; /* LEARNED only: HOST array, one correction per
                                   stored entry of G_i in aggregate order, row-major
                                   per block (addns_precond_info gives the count) */
+  int32_t block_mult;     /* interior sweep block size as a multiple of its minimum
+                             (1..4; 0 = 1).  A tile shape only: the factors are the
+                             same LU, regrouped; results agree to rounding */
 } addns_precond_opts;
 
 /* ------------------------------------------------------------------------

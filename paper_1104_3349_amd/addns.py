@@ -38,7 +38,8 @@ class AddnsError(RuntimeError):
 
 class PrecondOpts(C.Structure):
     _fields_ = [("schur", C.c_int32), ("interior_prec", C.c_int32), ("schur_prec", C.c_int32),
-                ("row_scale", C.c_int32), ("learned_delta", C.POINTER(C.c_double))]
+                ("row_scale", C.c_int32), ("learned_delta", C.POINTER(C.c_double)),
+                ("block_mult", C.c_int32)]
 
 
 class GmresOpts(C.Structure):
@@ -200,8 +201,9 @@ class Precond:
 
 def setup_precond(partition: Partition, N, d_rowptr, d_colidx, d_vals, schur=SCHUR_MSCN,
                   interior_prec=F64, schur_prec=F64, row_scale=1, learned_delta=None,
-                  stream=None) -> Precond:
-    opts = PrecondOpts(int(schur), int(interior_prec), int(schur_prec), int(row_scale), None)
+                  block_mult=1, stream=None) -> Precond:
+    opts = PrecondOpts(int(schur), int(interior_prec), int(schur_prec), int(row_scale), None,
+                       int(block_mult))
     if learned_delta is not None:
         ld = np.ascontiguousarray(learned_delta, dtype=np.float64)
         opts.learned_delta = ld.ctypes.data_as(C.POINTER(C.c_double))

@@ -46,7 +46,7 @@ int prec_bytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
 void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_rowptr, const int32_t* d_colidx,
                   const double* d_vals, const addns_precond_opts& o, hipStream_t s) {
   Plan& pl = pc->plan;
-  build_plan(P, pl, o.schur);
+  build_plan(P, pl, o.schur, o.block_mult);
   const int32_t N = pl.N;
   const int64_t nnz = (int64_t)pl.cp_colidx.size();
 
@@ -83,36 +83,28 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
 
   // -- interior blocks: band LU, then block-bidiagonal sweep form
   const int32_t m = pl.m;
-  std::vector<int32_t> int_off(P.int_offsets.begin(), P.int_offsets.end());
-  pc->sub_n.upload(pl.sub_n, s);
-  pc->sub_npad.upload(pl.sub_npad, s);
-  pc->sub_vec_off.upload(pl.sub_vec_off, s);
-  pc->sub_lblk0.upload(pl.sub_lblk0, s);
-  pc->sub_ublk0.upload(pl.sub_ublk0, s);
-  pc->sub_int_off.upload(int_off, s);
-  const int64_t npad_total = pl.sub_vec_off[m];
+  pc->subs.upload(pl.subs, s);
+  pc->lblks.upload(pl.lblks, s);
+  pc->ublks.upload(pl.ublks, s);
+  const int64_t npad_total = pl.npad_total;
   pc->ypad.alloc(sizeof(double) * std::max<int64_t>(npad_total, 1));
   pc->zpad.alloc(sizeof(double) * std::max<int64_t>(npad_total, 1));
-  const int32_t nL = (int32_t)pl.lblk_sub.size(), nU = (int32_t)pl.ublk_sub.size();
+  const int32_t nL = (int32_t)pl.lblks.size(), nU = (int32_t)pl.ublks.size();
   const int fb = prec_bytes(o.interior_prec == ADDNS_F32 ? P32 : P64);
   const int iprec = o.interior_prec == ADDNS_F32 ? P32 : P64;
   DevBuf info;
   info.alloc(sizeof(int32_t) * (m + 4));
   ADDNS_HIP(hipMemsetAsync(info.p, 0, sizeof(int32_t) * (m + 4), s));
   if (m > 0 && npad_total > 0) {
-    DevBuf ab, ipiv, band_off, bdst, bsrc, lsub, lidx, usub, uidx, work;
-    const int64_t ab_n = pl.sub_band_off[m];
-    ab.alloc(sizeof(double) * ab_n);
-    ADDNS_HIP(hipMemsetAsync(ab.p, 0, sizeof(double) * ab_n, s));
+    DevBuf ab, ipiv, bdst, bsrc, work;
+    ab.alloc(sizeof(double) * pl.band_total);
+    ADDNS_HIP(hipMemsetAsync(ab.p, 0, sizeof(double) * pl.band_total, s));
     ipiv.alloc(sizeof(int32_t) * npad_total);
-    band_off.upload(pl.sub_band_off, s);
     bdst.upload(pl.band_dst, s);
     bsrc.upload(pl.band_src, s);
     launch_scatter_band(bdst.as<int64_t>(), bsrc.as<int32_t>(), cpv, (int64_t)pl.band_dst.size(), ab.as<double>(), s);
-    launch_band_pad_identity(pc->sub_n.as<int32_t>(), pc->sub_npad.as<int32_t>(), band_off.as<int64_t>(), m, pl.ldab,
-                             pl.KL, pl.KU, ab.as<double>(), s);
-    launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), band_off.as<int64_t>(), pc->sub_npad.as<int32_t>(),
-                   pc->sub_vec_off.as<int32_t>(), m, pl.ldab, pl.KL, pl.KU, info.as<int32_t>(), s);
+    launch_band_pad_identity(pc->subs.as<SubInfo>(), m, ab.as<double>(), s);
+    launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), m, info.as<int32_t>(), s);
     std::vector<int32_t> h_info(m + 4);
     ADDNS_HIP(hipMemcpyAsync(h_info.data(), info.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
     ADDNS_HIP(hipStreamSynchronize(s));
@@ -120,24 +112,15 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
       if (h_info[j] != 0)
         throw SingularError("interior block " + std::to_string(j) + " has a zero pivot at column " +
                             std::to_string(h_info[j] - 1));
-    const int32_t W = pl.nbL + pl.KL;
-    lsub.upload(pl.lblk_sub, s);
-    lidx.upload(pl.lblk_idx, s);
-    usub.upload(pl.ublk_sub, s);
-    uidx.upload(pl.ublk_idx, s);
-    pc->lperm.alloc(sizeof(int32_t) * (int64_t)nL * W);
-    pc->lmat.alloc((int64_t)fb * nL * W * pl.nbL);
-    pc->uinv.alloc((int64_t)fb * nU * pl.nbU * pl.nbU);
-    pc->u12.alloc((int64_t)fb * nU * pl.nbU * pl.nbU);
-    const int64_t wl = (int64_t)nL * ((int64_t)W * pl.nbL + (int64_t)pl.nbL * pl.nbL);
-    const int64_t wu = (int64_t)nU * pl.nbU * pl.nbU;
-    work.alloc(sizeof(double) * std::max(wl, wu));
-    launch_convert_lower(ab.as<double>(), ipiv.as<int32_t>(), band_off.as<int64_t>(), pc->sub_vec_off.as<int32_t>(),
-                         lsub.as<int32_t>(), lidx.as<int32_t>(), nL, pl.ldab, pl.KL, pl.KU, pl.nbL, work.as<double>(),
-                         pc->lperm.as<int32_t>(), pc->lmat.p, iprec, s);
-    launch_convert_upper(ab.as<double>(), band_off.as<int64_t>(), usub.as<int32_t>(), uidx.as<int32_t>(),
-                         pc->sub_npad.as<int32_t>(), nU, pl.ldab, pl.KL, pl.KU, pl.nbU, work.as<double>(), pc->uinv.p,
-                         pc->u12.p, iprec, info.as<int32_t>() + m, s);
+    pc->lperm.alloc(sizeof(int32_t) * pl.lperm_total);
+    pc->lmat.alloc((int64_t)fb * pl.lmat_total);
+    pc->uinv.alloc((int64_t)fb * pl.u_total);
+    pc->u12.alloc((int64_t)fb * pl.u_total);
+    work.alloc(sizeof(double) * std::max(pl.lwork_total, pl.u_total));
+    launch_convert_lower(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), pc->lblks.as<LBlk>(), nL,
+                         work.as<double>(), pc->lperm.as<int32_t>(), pc->lmat.p, iprec, s);
+    launch_convert_upper(ab.as<double>(), pc->subs.as<SubInfo>(), pc->ublks.as<UBlk>(), nU, work.as<double>(),
+                         pc->uinv.p, pc->u12.p, iprec, info.as<int32_t>() + m, s);
     ADDNS_HIP(hipMemcpyAsync(h_info.data(), info.as<int32_t>() + m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     ADDNS_HIP(hipStreamSynchronize(s));
     if (h_info[0] != 0) throw SingularError("an interior U factor has a zero diagonal");
@@ -192,15 +175,15 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
 
   // -- byte accounting
   int64_t fbytes = 0;
-  fbytes += (int64_t)nL * (pl.nbL + pl.KL) * pl.nbL * fb + (int64_t)nL * (pl.nbL + pl.KL) * 4;
-  fbytes += (int64_t)nU * 2 * pl.nbU * pl.nbU * fb;
+  fbytes += pl.lmat_total * fb + pl.lperm_total * 4;
+  fbytes += 2 * pl.u_total * fb;
   fbytes += pl.g_total * prec_bytes(sprec);
   pc->factor_bytes = fbytes;
   // algorithmic bytes of one apply: band factors L (KL) and U (KL+KU+1) per
   // interior row read twice, pivots, E and F (value + index), Shat^-1, and six
   // vector passes
   int64_t band = 0;
-  for (int32_t j = 0; j < m; ++j) band += (int64_t)pl.sub_n[j] * (2 * pl.KL + pl.KU + 1);
+  for (int32_t j = 0; j < m; ++j) band += (int64_t)pl.subs[j].n * (2 * pl.subs[j].kl + pl.subs[j].ku + 1);
   pc->bytes_apply = 2 * band * fb + 2 * 4 * (int64_t)pl.n_int +
                     (int64_t)(pl.e_src.size() + pl.f_src.size()) * 12 + pl.g_total * prec_bytes(sprec) +
                     6 * (int64_t)N * 8;
@@ -272,9 +255,11 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
   return guarded("addns_setup_precond", [&]() -> int {
     if (!p || !out || !d_rowptr || !d_colidx || !d_vals) throw ArgError("null argument");
     if (N != p->d.N) throw ArgError("N does not match the partition");
-    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr};
+    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1};
     if (opts) o = *opts;
     if (o.schur < 0 || o.schur > ADDNS_SCHUR_LEARNED) throw ArgError("unknown schur mode");
+    if (o.block_mult < 0 || o.block_mult > 4) throw ArgError("block_mult must be 0..4");
+    if (o.block_mult == 0) o.block_mult = 1;
     if (o.schur == ADDNS_SCHUR_EXACT_BJ) throw ArgError("EXACT_BJ is an oracle-side reference mode");
     if (o.schur == ADDNS_SCHUR_LEARNED) throw ArgError("LEARNED mode is not available in this build");
     if (o.interior_prec != ADDNS_F64 && o.interior_prec != ADDNS_F32) throw ArgError("interior_prec");

@@ -59,61 +59,65 @@ __device__ inline double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off
 }
 
 template <class T, int S, int kind>
-__device__ inline void gemv_cols(const T* __restrict__ M, int R, int K, int par, const double* vin,
-                                 const int32_t* __restrict__ gidx, double* part) {
+__device__ inline int gemv_cols(const T* __restrict__ M, int R, int K, int par, const double* vin,
+                                const int32_t* __restrict__ gidx, double* part) {
   constexpr int CB = (sizeof(T) == 4 && S <= 6) ? 8 : 4;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int kb = K * w / kWaves, ke = K * (w + 1) / kWaves;
+  // waves = RG row groups (64 S rows each) x CG column groups
+  const int RG = (R + 64 * S - 1) / (64 * S);
+  const int CG = max(1, kWaves / RG);
   const uint32_t nbytes = (uint32_t)R * (uint32_t)K * (uint32_t)sizeof(T);
-  const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(M, nbytes);
-  double acc[S];
+  if (w < RG * CG) {
+    const int rg = w % RG, cg = w / RG;
+    const int kb = K * cg / CG, ke = K * (cg + 1) / CG;
+    const int r0 = rg * 64 * S;
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(M, nbytes);
+    double acc[S];
 #pragma unroll
-  for (int s = 0; s < S; ++s) acc[s] = 0.0;
-  for (int k0 = kb; k0 < ke; k0 += CB) {
-    T vals[CB][S];
+    for (int s = 0; s < S; ++s) acc[s] = 0.0;
+    for (int k0 = kb; k0 < ke; k0 += CB) {
+      T vals[CB][S];
 #pragma unroll
-    for (int c = 0; c < CB; ++c) {
-      const int k = k0 + c;
+      for (int c = 0; c < CB; ++c) {
+        const int k = k0 + c;
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int r = 64 * s + lane;
-        bool ok = k < ke && r < R;
-        if constexpr (kind == 2) ok = ok && k >= r;
-        else if constexpr (kind == 3) ok = ok && k <= r + par;
-        else if constexpr (kind == 4) ok = ok && (r >= par || k <= r);
-        vals[c][s] = buf_load<T>(rsrc, ok ? (uint32_t)(k * R + r) * (uint32_t)sizeof(T) : nbytes);
+        for (int s = 0; s < S; ++s) {
+          const int r = r0 + 64 * s + lane;
+          bool ok = k < ke && r < R;
+          if constexpr (kind == 2) ok = ok && k >= r;
+          else if constexpr (kind == 3) ok = ok && k <= r + par;
+          else if constexpr (kind == 4) ok = ok && (r >= par || k <= r);
+          vals[c][s] = buf_load<T>(rsrc, ok ? (uint32_t)(k * R + r) * (uint32_t)sizeof(T) : nbytes);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const int k = k0 + c;
+        const double vk = k < ke ? (gidx ? vin[gidx[k]] : vin[k]) : 0.0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc[s] += (double)vals[c][s] * vk;
       }
     }
 #pragma unroll
-    for (int c = 0; c < CB; ++c) {
-      const int k = k0 + c;
-      const double vk = k < ke ? (gidx ? vin[gidx[k]] : vin[k]) : 0.0;
-#pragma unroll
-      for (int s = 0; s < S; ++s) acc[s] += (double)vals[c][s] * vk;
+    for (int s = 0; s < S; ++s) {
+      const int r = r0 + 64 * s + lane;
+      if (r < R) part[cg * R + r] = acc[s];
     }
   }
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int r = 64 * s + lane;
-    if (r < R) part[w * R + r] = acc[s];
-  }
+  return CG;
 }
 
-__device__ inline double sum_parts(const double* part, int R, int r) {
+__device__ inline double sum_parts(const double* part, int R, int CG, int r) {
   double s = 0.0;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) s += part[w * R + r];
+  for (int c = 0; c < CG; ++c) s += part[c * R + r];
   return s;
 }
 
 struct SweepArgs {
-  int32_t KL, nbL, nbU, KV;
-  const int32_t* sub_n;
-  const int32_t* sub_npad;
-  const int32_t* sub_int_off;
-  const int32_t* sub_vec_off;
-  const int32_t* sub_lblk0;
-  const int32_t* sub_ublk0;
+  int32_t maxW, maxU;
+  const SubInfo* subs;
+  const LBlk* lb;
+  const UBlk* ub;
   const int32_t* lperm;
   const void* lmat;
   const void* uinv;
@@ -128,28 +132,26 @@ struct SweepArgs {
 // second == 1: input u = E x2 (x2 = separator part, CSR E), and
 // out[int] = z1[int] - D^{-1} u.
 //
-// Lower sweep, block b (window rows b*nbL .. b*nbL+W-1, W = nbL+KL):
+// Lower sweep, block b (window rows b*nbl .. b*nbl+W-1, W = nbl+kl):
 //   v = P_b w;  [x_b; c] = [inv(L11); L21 inv(L11)] v_top;  carry = v_bot - c
-// Upper sweep, block b (rows b*nbU ..):  x_b = inv(U_bb) (y_b - U_b,b+1 x_b+1)
+// Upper sweep, block b (rows b*nbu ..):  x_b = inv(U_bb) (y_b - U_b,b+1 x_b+1)
 template <class T, int S>
 __global__ void __launch_bounds__(kSweepThreads)
 k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int second, const double* x2,
                  const double* z1) {
   extern __shared__ double smem[];
-  const int sub = blockIdx.x;
-  const int32_t n = a.sub_n[sub], npad = a.sub_npad[sub];
+  const SubInfo q = a.subs[blockIdx.x];
+  const int32_t n = q.n, npad = q.npad;
   if (n == 0) return;
-  const int32_t ioff = a.sub_int_off[sub], voff = a.sub_vec_off[sub];
-  const int32_t KL = a.KL, nbL = a.nbL, nbU = a.nbU, W = nbL + KL;
-  const int32_t RM = max(W, nbU);
+  const int32_t ioff = q.int_off, voff = q.vec_off;
+  const int32_t KL = q.kl, nbL = q.nbl, nbU = q.nbu, W = nbL + KL, KV = q.kl + q.ku;
   const int tid = threadIdx.x;
-  double* wA = smem;             // W
-  double* wB = wA + W;           // W
-  double* t = wB + W;            // nbU
-  double* xn = t + nbU;          // nbU
-  double* part = xn + nbU;       // kWaves * RM
+  double* wA = smem;             // maxW
+  double* wB = wA + a.maxW;      // maxW
+  double* t = wB + a.maxW;       // maxU
+  double* xn = t + a.maxU;       // maxU
+  double* part = xn + a.maxU;    // kWaves * max(maxW, maxU)
   double* ypad = a.ypad + voff;
-  (void)RM;
   auto input = [&](int32_t r) -> double {
     if (r >= n) return 0.0;
     if (!second) return yin[ioff + r];
@@ -163,14 +165,13 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int s
   for (int32_t r = tid; r < W; r += blockDim.x) wc[r] = input(r);
   __syncthreads();
   const int32_t nL = npad / nbL;
-  const int32_t lb0 = a.sub_lblk0[sub];
   for (int32_t b = 0; b < nL; ++b) {
-    const int64_t blk = lb0 + b;
-    const int32_t* idx = a.lperm + blk * W;
-    gemv_cols<T, S, 4>((const T*)a.lmat + blk * W * nbL, W, nbL, nbL, wc, idx, part);
+    const int32_t* idx = a.lperm + q.lperm_off + (int64_t)b * W;
+    const int CG = gemv_cols<T, S, 4>((const T*)a.lmat + q.lmat_off + (int64_t)b * W * nbL, W, nbL, nbL, wc, idx,
+                                      part);
     __syncthreads();
     for (int32_t r = tid; r < W; r += blockDim.x) {
-      const double v = sum_parts(part, W, r);
+      const double v = sum_parts(part, W, CG, r);
       if (r < nbL) ypad[b * nbL + r] = v;
       else wn[r - nbL] = wc[idx[r]] - v;
     }
@@ -182,21 +183,20 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int s
   }
   // ---- backward sweep over upper blocks
   const int32_t nU = npad / nbU;
-  const int32_t ub0 = a.sub_ublk0[sub];
   for (int32_t b = nU - 1; b >= 0; --b) {
-    const int64_t blk = ub0 + b;
+    const int64_t uoff = q.u_off + (int64_t)b * nbU * nbU;
     if (b < nU - 1) {
-      gemv_cols<T, S, 3>((const T*)a.u12 + blk * nbU * nbU, nbU, nbU, a.KV - nbU, xn, nullptr, part);
+      const int CG = gemv_cols<T, S, 3>((const T*)a.u12 + uoff, nbU, nbU, KV - nbU, xn, nullptr, part);
       __syncthreads();
-      for (int32_t r = tid; r < nbU; r += blockDim.x) t[r] = ypad[b * nbU + r] - sum_parts(part, nbU, r);
+      for (int32_t r = tid; r < nbU; r += blockDim.x) t[r] = ypad[b * nbU + r] - sum_parts(part, nbU, CG, r);
     } else {
       for (int32_t r = tid; r < nbU; r += blockDim.x) t[r] = ypad[b * nbU + r];
     }
     __syncthreads();
-    gemv_cols<T, S, 2>((const T*)a.uinv + blk * nbU * nbU, nbU, nbU, 0, t, nullptr, part);
+    const int CG = gemv_cols<T, S, 2>((const T*)a.uinv + uoff, nbU, nbU, 0, t, nullptr, part);
     __syncthreads();
     for (int32_t r = tid; r < nbU; r += blockDim.x) {
-      const double x = sum_parts(part, nbU, r);
+      const double x = sum_parts(part, nbU, CG, r);
       xn[r] = x;
       const int32_t row = b * nbU + r;
       if (row < n) {
@@ -263,9 +263,8 @@ __global__ void k_permute(const int32_t* __restrict__ perm, const double* __rest
 
 }  // namespace
 
-size_t sweep_smem_bytes(int32_t KL, int32_t nbL, int32_t nbU) {
-  int32_t W = nbL + KL;
-  return sizeof(double) * (size_t)(2 * W + 2 * nbU + kWaves * std::max(W, nbU));
+size_t sweep_smem_bytes(int32_t maxW, int32_t maxU) {
+  return sizeof(double) * (size_t)(2 * maxW + 2 * maxU + kWaves * std::max(maxW, maxU));
 }
 
 template <class T, int S>
@@ -286,10 +285,7 @@ static void dispatch_sweep(int S, const SweepArgs& a, int m, size_t smem, const 
     case 3: launch_sweep<T, 3>(a, m, smem, yin, out, second, x2, z1, s); break;
     case 4: launch_sweep<T, 4>(a, m, smem, yin, out, second, x2, z1, s); break;
     case 5: launch_sweep<T, 5>(a, m, smem, yin, out, second, x2, z1, s); break;
-    case 6: launch_sweep<T, 6>(a, m, smem, yin, out, second, x2, z1, s); break;
-    case 7: launch_sweep<T, 7>(a, m, smem, yin, out, second, x2, z1, s); break;
-    case 8: launch_sweep<T, 8>(a, m, smem, yin, out, second, x2, z1, s); break;
-    default: throw ArgError("interior bandwidth too large for the sweep kernel (block rows > 512)");
+    default: throw ArgError("sweep row slots out of range");
   }
 }
 
@@ -298,16 +294,11 @@ void launch_interior_solve(const addns_precond* pc, const double* yin, double* o
   const Plan& pl = pc->plan;
   if (pl.m == 0 || pl.n_int == 0) return;
   SweepArgs a;
-  a.KL = pl.KL;
-  a.nbL = pl.nbL;
-  a.nbU = pl.nbU;
-  a.KV = pl.KL + pl.KU;
-  a.sub_n = pc->sub_n.as<int32_t>();
-  a.sub_npad = pc->sub_npad.as<int32_t>();
-  a.sub_int_off = pc->sub_int_off.as<int32_t>();
-  a.sub_vec_off = pc->sub_vec_off.as<int32_t>();
-  a.sub_lblk0 = pc->sub_lblk0.as<int32_t>();
-  a.sub_ublk0 = pc->sub_ublk0.as<int32_t>();
+  a.maxW = pl.maxW;
+  a.maxU = pl.nbU;
+  a.subs = pc->subs.as<SubInfo>();
+  a.lb = pc->lblks.as<LBlk>();
+  a.ub = pc->ublks.as<UBlk>();
   a.lperm = pc->lperm.as<int32_t>();
   a.lmat = pc->lmat.p;
   a.uinv = pc->uinv.p;
@@ -316,9 +307,9 @@ void launch_interior_solve(const addns_precond* pc, const double* yin, double* o
   a.e_colidx = pc->e_colidx.as<int32_t>();
   a.e_vals = pc->e_vals.as<double>();
   a.ypad = second ? pc->zpad.as<double>() : pc->ypad.as<double>();
-  const size_t smem = sweep_smem_bytes(pl.KL, pl.nbL, pl.nbU);
+  const size_t smem = sweep_smem_bytes(pl.maxW, pl.nbU);
   if (smem > 160 * 1024) throw ArgError("interior bandwidth too large for the LDS-staged sweep");
-  const int S = (std::max(pl.nbL + pl.KL, pl.nbU) + 63) / 64;
+  const int S = std::min(5, (std::max(pl.maxW, pl.nbU) + 63) / 64);
   if (pc->interior_prec == P64) dispatch_sweep<double>(S, a, pl.m, smem, yin, out, second, x2, z1, s);
   else dispatch_sweep<float>(S, a, pl.m, smem, yin, out, second, x2, z1, s);
 }

@@ -52,11 +52,10 @@ __global__ void k_scatter(const int64_t* __restrict__ dst, const int32_t* __rest
   if (t < n) out[dst[t]] = cpv[src[t]];
 }
 
-__global__ void k_band_pad_identity(const int32_t* sub_n, const int32_t* sub_npad, const int64_t* band_off,
-                                    int32_t ldab, int32_t KV, double* ab) {
-  int j = blockIdx.x;
-  for (int32_t c = sub_n[j] + threadIdx.x; c < sub_npad[j]; c += blockDim.x)
-    ab[band_off[j] + (int64_t)c * ldab + KV] = 1.0;
+__global__ void k_band_pad_identity(const SubInfo* subs, double* ab) {
+  const SubInfo q = subs[blockIdx.x];
+  for (int32_t c = q.n + threadIdx.x; c < q.npad; c += blockDim.x)
+    ab[q.band_off + (int64_t)c * q.ldab + q.kl + q.ku] = 1.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -67,13 +66,13 @@ __global__ void k_band_pad_identity(const int32_t* sub_n, const int32_t* sub_npa
 // step j (subdomain-local).  info[sub] = first zero pivot + 1 (0 if none).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kSetupThreads)
-k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const int64_t* __restrict__ band_off,
-          const int32_t* __restrict__ sub_npad, const int32_t* __restrict__ sub_vec_off, int32_t ldab, int32_t KL,
-          int32_t KU, int32_t* __restrict__ info) {
+k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const SubInfo* __restrict__ subs,
+          int32_t* __restrict__ info) {
   const int sub = blockIdx.x;
-  const int32_t n = sub_npad[sub];
-  double* ab = ab_all + band_off[sub];
-  int32_t* ipiv = ipiv_all + sub_vec_off[sub];
+  const SubInfo q = subs[sub];
+  const int32_t n = q.npad, ldab = q.ldab, KL = q.kl, KU = q.ku;
+  double* ab = ab_all + q.band_off;
+  int32_t* ipiv = ipiv_all + q.vec_off;
   const int32_t KV = KL + KU;
   __shared__ double s_piv;
   __shared__ double s_top;
@@ -178,18 +177,17 @@ __device__ inline __half to_store<__half>(double v) { return __float2half((float
 template <class T>
 __global__ void __launch_bounds__(kSetupThreads)
 k_convert_lower(const double* __restrict__ ab_all, const int32_t* __restrict__ ipiv_all,
-                const int64_t* __restrict__ band_off, const int32_t* __restrict__ sub_vec_off,
-                const int32_t* __restrict__ lblk_sub, const int32_t* __restrict__ lblk_idx, int32_t ldab,
-                int32_t KL, int32_t KU, int32_t nbL, double* __restrict__ work_all, int32_t* __restrict__ lperm_all,
-                T* __restrict__ lmat_all) {
-  const int blk = blockIdx.x;
-  const int sub = lblk_sub[blk];
-  const int32_t c0 = lblk_idx[blk] * nbL;
+                const SubInfo* __restrict__ subs, const LBlk* __restrict__ lb, double* __restrict__ work_all,
+                int32_t* __restrict__ lperm_all, T* __restrict__ lmat_all) {
+  const LBlk B = lb[blockIdx.x];
+  const SubInfo q = subs[B.sub];
+  const int32_t nbL = q.nbl, KL = q.kl, ldab = q.ldab;
+  const int32_t c0 = B.idx * nbL;
   const int32_t W = nbL + KL;
-  const int32_t KV = KL + KU;
-  const double* ab = ab_all + band_off[sub];
-  const int32_t* ipiv = ipiv_all + sub_vec_off[sub];
-  double* Lw = work_all + (int64_t)blk * ((int64_t)W * nbL + (int64_t)nbL * nbL);  // W x nbL, col-major
+  const int32_t KV = q.kl + q.ku;
+  const double* ab = ab_all + q.band_off;
+  const int32_t* ipiv = ipiv_all + q.vec_off;
+  double* Lw = work_all + B.woff;  // W x nbL, col-major
   double* X = Lw + (int64_t)W * nbL;                                                  // nbL x nbL, col-major
   const int tid = threadIdx.x;
   // multipliers of each column at their window rows (diagonal implicit)
@@ -212,7 +210,7 @@ k_convert_lower(const double* __restrict__ ab_all, const int32_t* __restrict__ i
     }
   }
   if (tid == 0) {
-    int32_t* idx = lperm_all + (int64_t)blk * W;
+    int32_t* idx = lperm_all + B.poff;
     for (int32_t r = 0; r < W; ++r) idx[r] = r;
     for (int32_t s = 0; s < nbL; ++s) {
       int32_t p = ipiv[c0 + s] - c0;
@@ -236,7 +234,7 @@ k_convert_lower(const double* __restrict__ ab_all, const int32_t* __restrict__ i
     }
     __syncthreads();
   }
-  T* lm = lmat_all + (int64_t)blk * W * nbL;
+  T* lm = lmat_all + B.moff;
   for (int64_t t = tid; t < (int64_t)W * nbL; t += blockDim.x) {
     int32_t c = (int32_t)(t / W), r = (int32_t)(t % W);
     double v;
@@ -256,18 +254,17 @@ k_convert_lower(const double* __restrict__ ab_all, const int32_t* __restrict__ i
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ void __launch_bounds__(kSetupThreads)
-k_convert_upper(const double* __restrict__ ab_all, const int64_t* __restrict__ band_off,
-                const int32_t* __restrict__ ublk_sub, const int32_t* __restrict__ ublk_idx,
-                const int32_t* __restrict__ sub_npad, int32_t ldab, int32_t KL, int32_t KU, int32_t nbU,
+k_convert_upper(const double* __restrict__ ab_all, const SubInfo* __restrict__ subs, const UBlk* __restrict__ ub,
                 double* __restrict__ work_all, T* __restrict__ uinv_all, T* __restrict__ u12_all,
                 int32_t* __restrict__ info) {
-  const int blk = blockIdx.x;
-  const int sub = ublk_sub[blk];
-  const int32_t r0 = ublk_idx[blk] * nbU;
-  const int32_t n = sub_npad[sub];
-  const int32_t KV = KL + KU;
-  const double* ab = ab_all + band_off[sub];
-  double* X = work_all + (int64_t)blk * nbU * nbU;  // column-major
+  const UBlk B = ub[blockIdx.x];
+  const SubInfo q = subs[B.sub];
+  const int32_t nbU = q.nbu, ldab = q.ldab;
+  const int32_t r0 = B.idx * nbU;
+  const int32_t n = q.npad;
+  const int32_t KV = q.kl + q.ku;
+  const double* ab = ab_all + q.band_off;
+  double* X = work_all + B.off;  // column-major
   const int tid = threadIdx.x;
   auto U = [&](int32_t r, int32_t c) -> double {   // subdomain-local (r, c)
     int32_t d = c - r;
@@ -295,8 +292,8 @@ k_convert_upper(const double* __restrict__ ab_all, const int64_t* __restrict__ b
     }
     __syncthreads();
   }
-  T* ui = uinv_all + (int64_t)blk * nbU * nbU;
-  T* u12 = u12_all + (int64_t)blk * nbU * nbU;
+  T* ui = uinv_all + B.off;
+  T* u12 = u12_all + B.off;
   for (int64_t t = tid; t < (int64_t)nbU * nbU; t += blockDim.x) {
     int32_t c = (int32_t)(t / nbU), r = (int32_t)(t % nbU);
     ui[t] = to_store<T>(X[t]);
@@ -543,36 +540,27 @@ void launch_dense_scatter(const int64_t* dst, const int32_t* src, const double* 
                           hipStream_t s) {
   if (n > 0) k_scatter<<<nblocks(n, 256), 256, 0, s>>>(dst, src, cpv, n, out);
 }
-void launch_band_pad_identity(const int32_t* sub_n, const int32_t* sub_npad, const int64_t* band_off, int32_t m,
-                              int32_t ldab, int32_t KL, int32_t KU, double* ab, hipStream_t s) {
-  if (m > 0) k_band_pad_identity<<<m, 256, 0, s>>>(sub_n, sub_npad, band_off, ldab, KL + KU, ab);
+void launch_band_pad_identity(const SubInfo* subs, int32_t m, double* ab, hipStream_t s) {
+  if (m > 0) k_band_pad_identity<<<m, 256, 0, s>>>(subs, ab);
 }
-void launch_band_lu(double* ab, int32_t* ipiv, const int64_t* band_off, const int32_t* sub_npad,
-                    const int32_t* sub_vec_off, int32_t m, int32_t ldab, int32_t KL, int32_t KU, int32_t* info,
-                    hipStream_t s) {
-  if (m > 0) k_band_lu<<<m, kSetupThreads, 0, s>>>(ab, ipiv, band_off, sub_npad, sub_vec_off, ldab, KL, KU, info);
+void launch_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, hipStream_t s) {
+  if (m > 0) k_band_lu<<<m, kSetupThreads, 0, s>>>(ab, ipiv, subs, info);
 }
-void launch_convert_lower(const double* ab, const int32_t* ipiv, const int64_t* band_off, const int32_t* sub_vec_off,
-                          const int32_t* lblk_sub, const int32_t* lblk_idx, int32_t nblk, int32_t ldab, int32_t KL,
-                          int32_t KU, int32_t nbL, double* work, int32_t* lperm, void* lmat, int prec, hipStream_t s) {
+void launch_convert_lower(const double* ab, const int32_t* ipiv, const SubInfo* subs, const LBlk* lb, int32_t nblk,
+                          double* work, int32_t* lperm, void* lmat, int prec, hipStream_t s) {
   if (nblk == 0) return;
   if (prec == P64)
-    k_convert_lower<double><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, band_off, sub_vec_off, lblk_sub, lblk_idx, ldab,
-                                                            KL, KU, nbL, work, lperm, (double*)lmat);
+    k_convert_lower<double><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, subs, lb, work, lperm, (double*)lmat);
   else
-    k_convert_lower<float><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, band_off, sub_vec_off, lblk_sub, lblk_idx, ldab,
-                                                           KL, KU, nbL, work, lperm, (float*)lmat);
+    k_convert_lower<float><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, subs, lb, work, lperm, (float*)lmat);
 }
-void launch_convert_upper(const double* ab, const int64_t* band_off, const int32_t* ublk_sub, const int32_t* ublk_idx,
-                          const int32_t* sub_npad, int32_t nblk, int32_t ldab, int32_t KL, int32_t KU, int32_t nbU,
-                          double* work, void* uinv, void* u12, int prec, int32_t* info, hipStream_t s) {
+void launch_convert_upper(const double* ab, const SubInfo* subs, const UBlk* ub, int32_t nblk, double* work,
+                          void* uinv, void* u12, int prec, int32_t* info, hipStream_t s) {
   if (nblk == 0) return;
   if (prec == P64)
-    k_convert_upper<double><<<nblk, kSetupThreads, 0, s>>>(ab, band_off, ublk_sub, ublk_idx, sub_npad, ldab, KL, KU,
-                                                            nbU, work, (double*)uinv, (double*)u12, info);
+    k_convert_upper<double><<<nblk, kSetupThreads, 0, s>>>(ab, subs, ub, work, (double*)uinv, (double*)u12, info);
   else
-    k_convert_upper<float><<<nblk, kSetupThreads, 0, s>>>(ab, band_off, ublk_sub, ublk_idx, sub_npad, ldab, KL, KU,
-                                                           nbU, work, (float*)uinv, (float*)u12, info);
+    k_convert_upper<float><<<nblk, kSetupThreads, 0, s>>>(ab, subs, ub, work, (float*)uinv, (float*)u12, info);
 }
 void launch_schur_blocks(int32_t k, const int32_t* agg_s, const int32_t* agg_d, const int64_t* g_off,
                          const int64_t* dd_off, const int64_t* de_off, const int64_t* df_off, double* G, double* Dd,

@@ -11,7 +11,7 @@ namespace addns {
 
 static int32_t round_up(int32_t a, int32_t b) { return (a + b - 1) / b * b; }
 
-void build_plan(const PartitionData& P, Plan& pl, int schur_mode) {
+void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult) {
   const int32_t N = P.N;
   pl.N = N;
   pl.m = P.m;
@@ -47,67 +47,86 @@ void build_plan(const PartitionData& P, Plan& pl, int schur_mode) {
   const std::vector<int32_t>& rp = pl.cp_rowptr;
   const std::vector<int32_t>& ci = pl.cp_colidx;
 
-  // interior bandwidths
+  // interior bandwidths, per subdomain
   const int32_t m = P.m;
   std::vector<int32_t> sub_of(N, -1);
   for (int32_t j = 0; j < m; ++j)
     for (int32_t r = P.int_offsets[j]; r < P.int_offsets[j + 1]; ++r) sub_of[r] = j;
-  int32_t KL = 0, KU = 0;
+  std::vector<int32_t> kl(m, 0), ku(m, 0);
   for (int32_t r = 0; r < pl.n_int; ++r)
     for (int32_t t = rp[r]; t < rp[r + 1]; ++t) {
       int32_t c = ci[t];
       if (c < pl.n_int && sub_of[c] == sub_of[r]) {
-        KL = std::max(KL, r - c);
-        KU = std::max(KU, c - r);
+        kl[sub_of[r]] = std::max(kl[sub_of[r]], r - c);
+        ku[sub_of[r]] = std::max(ku[sub_of[r]], c - r);
       }
     }
-  pl.KL = KL;
-  pl.KU = KU;
-  // lower blocks must hold at least KL columns (the window carry comes only
-  // from the previous block), upper blocks at least KL + KU (U is then
-  // block bidiagonal); nbU = 2 nbL keeps one padding for both sweeps
-  pl.nbL = round_up(std::max({KL, (KL + KU + 1) / 2, 1}), 8);
-  pl.nbU = 2 * pl.nbL;
-  pl.ldab = 2 * KL + KU + 1;
-
-  pl.sub_n.resize(m);
-  pl.sub_npad.resize(m);
-  pl.sub_band_off.assign(m + 1, 0);
-  pl.sub_vec_off.assign(m + 1, 0);
-  pl.sub_lblk0.assign(m + 1, 0);
-  pl.sub_ublk0.assign(m + 1, 0);
-  pl.lblk_sub.clear();
-  pl.lblk_idx.clear();
-  pl.ublk_sub.clear();
-  pl.ublk_idx.clear();
+  // lower blocks hold at least kl columns (the window carry then comes only
+  // from the previous block), upper blocks at least kl + ku rows (U is then
+  // block bidiagonal); nbu = 2 nbl lets one padding serve both sweeps
+  // One block size for every subdomain: each sweep step costs about one
+  // memory round trip whatever its size, so a subdomain with a narrower band
+  // must not get more (smaller) steps than the widest one.
+  pl.block_mult = std::max(1, block_mult);
+  int32_t nbl_all = 1;
+  for (int32_t j = 0; j < m; ++j) nbl_all = std::max({nbl_all, kl[j], (kl[j] + ku[j] + 1) / 2});
+  nbl_all = round_up(nbl_all, 8) * pl.block_mult;
+  pl.subs.assign(m, SubInfo{});
+  pl.lblks.clear();
+  pl.ublks.clear();
+  pl.KL = pl.KU = pl.nbL = pl.nbU = pl.maxW = 0;
+  int64_t band = 0, vec = 0, lm = 0, lp = 0, lw = 0, uo = 0;
   for (int32_t j = 0; j < m; ++j) {
-    int32_t n = P.int_offsets[j + 1] - P.int_offsets[j];
-    int32_t npad = n == 0 ? 0 : round_up(n, pl.nbU);
-    pl.sub_n[j] = n;
-    pl.sub_npad[j] = npad;
-    pl.sub_band_off[j + 1] = pl.sub_band_off[j] + (int64_t)pl.ldab * npad;
-    pl.sub_vec_off[j + 1] = pl.sub_vec_off[j] + npad;
-    for (int32_t b = 0; b < npad / pl.nbL; ++b) {
-      pl.lblk_sub.push_back(j);
-      pl.lblk_idx.push_back(b);
+    SubInfo& q = pl.subs[j];
+    q.n = P.int_offsets[j + 1] - P.int_offsets[j];
+    q.kl = kl[j];
+    q.ku = ku[j];
+    q.nbl = nbl_all;
+    q.nbu = 2 * q.nbl;
+    q.npad = q.n == 0 ? 0 : round_up(q.n, q.nbu);
+    q.ldab = 2 * q.kl + q.ku + 1;
+    q.vec_off = (int32_t)vec;
+    q.int_off = P.int_offsets[j];
+    q.band_off = band;
+    q.lblk0 = (int32_t)pl.lblks.size();
+    q.ublk0 = (int32_t)pl.ublks.size();
+    q.lmat_off = lm;
+    q.lperm_off = lp;
+    q.u_off = uo;
+    const int32_t W = q.nbl + q.kl;
+    for (int32_t b = 0; b < q.npad / q.nbl; ++b) {
+      pl.lblks.push_back(LBlk{j, b, lm, lp, lw});
+      lm += (int64_t)W * q.nbl;
+      lp += W;
+      lw += (int64_t)W * q.nbl + (int64_t)q.nbl * q.nbl;
     }
-    for (int32_t b = 0; b < npad / pl.nbU; ++b) {
-      pl.ublk_sub.push_back(j);
-      pl.ublk_idx.push_back(b);
+    for (int32_t b = 0; b < q.npad / q.nbu; ++b) {
+      pl.ublks.push_back(UBlk{j, b, uo});
+      uo += (int64_t)q.nbu * q.nbu;
     }
-    pl.sub_lblk0[j + 1] = (int32_t)pl.lblk_sub.size();
-    pl.sub_ublk0[j + 1] = (int32_t)pl.ublk_sub.size();
+    band += (int64_t)q.ldab * q.npad;
+    vec += q.npad;
+    pl.KL = std::max(pl.KL, q.kl);
+    pl.KU = std::max(pl.KU, q.ku);
+    pl.nbL = std::max(pl.nbL, q.nbl);
+    pl.nbU = std::max(pl.nbU, q.nbu);
+    pl.maxW = std::max(pl.maxW, W);
   }
+  pl.band_total = band;
+  pl.npad_total = vec;
+  pl.lmat_total = lm;
+  pl.lperm_total = lp;
+  pl.lwork_total = lw;
+  pl.u_total = uo;
   pl.band_dst.clear();
   pl.band_src.clear();
   for (int32_t r = 0; r < pl.n_int; ++r) {
-    int32_t j = sub_of[r];
-    int32_t off = P.int_offsets[j];
+    const SubInfo& q = pl.subs[sub_of[r]];
     for (int32_t t = rp[r]; t < rp[r + 1]; ++t) {
       int32_t c = ci[t];
-      if (c >= pl.n_int || sub_of[c] != j) continue;
-      int32_t lr = r - off, lc = c - off;
-      pl.band_dst.push_back(pl.sub_band_off[j] + (int64_t)lc * pl.ldab + (KL + KU + lr - lc));
+      if (c >= pl.n_int || sub_of[c] != sub_of[r]) continue;
+      int32_t lr = r - q.int_off, lc = c - q.int_off;
+      pl.band_dst.push_back(q.band_off + (int64_t)lc * q.ldab + (q.kl + q.ku + lr - lc));
       pl.band_src.push_back(t);
     }
   }

@@ -57,25 +57,50 @@ struct DevBuf {
   }
 };
 
+// Per-subdomain sweep geometry (POD, shared by host and device).
+struct SubInfo {
+  int32_t n, npad;        // interior size and padded size (multiple of nbu)
+  int32_t kl, ku;         // lower / upper bandwidth of A_jj
+  int32_t nbl, nbu;       // lower / upper block sizes (nbu = 2 nbl >= kl + ku, nbl >= kl)
+  int32_t ldab;           // band storage leading dimension 2 kl + ku + 1
+  int32_t vec_off;        // offset into padded work vectors (and pivots)
+  int32_t int_off;        // offset of the interior in the permuted numbering
+  int32_t lblk0, ublk0;   // first lower / upper block
+  int32_t pad_;
+  int64_t band_off;       // offset of the band storage (elements)
+  int64_t lmat_off;       // first lower block matrix (elements); blocks are W x nbl each
+  int64_t lperm_off;      // first lower block gather indices; W each
+  int64_t u_off;          // first upper block (elements); nbu x nbu each
+};
+struct LBlk {             // one lower block: W = nbl + kl window rows
+  int32_t sub, idx;
+  int64_t moff;           // offset of [inv(L11); L21 inv(L11)] (W x nbl, elements)
+  int64_t poff;           // offset of the window gather indices (W)
+  int64_t woff;           // conversion work offset (W nbl + nbl nbl doubles)
+};
+struct UBlk {             // one upper block: nbu x nbu inverse and coupling
+  int32_t sub, idx;
+  int64_t off;            // offset into inv(U_bb) and U_{b,b+1} (elements); also work offset
+};
+
 // Host-side integer plan: every gather map the device setup needs.  Built
 // from the partition and the pattern only.
 struct Plan {
   int32_t N = 0, m = 0, k = 0, n_int = 0, nsep = 0;
-  int32_t KL = 0, KU = 0;     // max lower / upper bandwidth of the interiors
-  int32_t nbL = 0, nbU = 0;   // block sizes of the lower / upper sweeps
-  int32_t ldab = 0;           // band storage leading dimension 2KL+KU+1
+  int32_t KL = 0, KU = 0;     // largest interior bandwidths (reported)
+  int32_t nbL = 0, nbU = 0;   // largest block sizes
+  int32_t maxW = 0;           // largest lower window nbl + kl
+  int32_t block_mult = 1;     // lower block size = block_mult x its minimum
   // permuted CSR of C~ (new numbering) and the source entry of each value
   std::vector<int32_t> cp_rowptr, cp_colidx, cp_src, cp_orow;
   std::vector<int32_t> perm, iperm;
   // interior blocks
-  std::vector<int32_t> sub_n, sub_npad;          // m
-  std::vector<int64_t> sub_band_off;             // m+1 offsets (elements) into band storage
-  std::vector<int32_t> sub_vec_off;              // m+1 offsets into the padded scratch vector
+  std::vector<SubInfo> subs;
+  std::vector<LBlk> lblks;
+  std::vector<UBlk> ublks;
+  int64_t band_total = 0, npad_total = 0, lmat_total = 0, lperm_total = 0, lwork_total = 0, u_total = 0;
   std::vector<int64_t> band_dst;                 // band element index per interior C~p entry
   std::vector<int32_t> band_src;                 //   ... and its C~p entry
-  std::vector<int32_t> lblk_sub, lblk_idx;       // per L-block: subdomain and block index
-  std::vector<int32_t> ublk_sub, ublk_idx;       // per U-block
-  std::vector<int32_t> sub_lblk0, sub_ublk0;     // m+1 first block of each subdomain
   // E (interior rows x separator cols) and F (separator rows x interior cols), CSR
   std::vector<int32_t> e_rowptr, e_colidx, e_src;
   std::vector<int32_t> f_rowptr, f_colidx, f_src;
@@ -87,7 +112,7 @@ struct Plan {
   int64_t g_total = 0, dd_total = 0, de_total = 0, df_total = 0;
 };
 
-void build_plan(const PartitionData& P, Plan& pl, int schur_mode);
+void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult);
 
 // Storage precision tags
 enum Prec { P64 = 0, P32 = 1, P16S = 2 };
@@ -103,8 +128,8 @@ struct addns_precond {
   addns::DevBuf cp_rowptr, cp_colidx, cp_vals;        // C~ permuted (fp64)
   addns::DevBuf e_rowptr, e_colidx, e_vals, f_rowptr, f_colidx, f_vals;
   // interior factors in block form
-  addns::DevBuf sub_n, sub_npad, sub_vec_off, sub_lblk0, sub_ublk0, sub_int_off;
-  addns::DevBuf lperm;                                // per L-block (nbL+KL) int32
+  addns::DevBuf subs, lblks, ublks;                   // SubInfo / LBlk / UBlk tables
+  addns::DevBuf lperm;                                // per L-block window gather indices
   addns::DevBuf lmat;                                 // per L-block [inv(L11); L21 inv(L11)]
   addns::DevBuf uinv, u12;                            // per U-block
   // interface
@@ -132,19 +157,12 @@ void launch_gather_scaled(const int32_t* src, const int32_t* orow, const double*
 void launch_gather(const int32_t* src, const double* in, int64_t n, double* out, hipStream_t s);
 void launch_scatter_band(const int64_t* dst, const int32_t* src, const double* cpv, int64_t n, double* ab,
                          hipStream_t s);
-void launch_band_pad_identity(const int32_t* sub_n, const int32_t* sub_npad, const int64_t* band_off,
-                              int32_t m, int32_t ldab, int32_t KL, int32_t KU, double* ab, hipStream_t s);
-void launch_band_lu(double* ab, int32_t* ipiv, const int64_t* band_off, const int32_t* sub_npad,
-                    const int32_t* sub_vec_off, int32_t m, int32_t ldab, int32_t KL, int32_t KU, int32_t* info,
-                    hipStream_t s);
-void launch_convert_lower(const double* ab, const int32_t* ipiv, const int64_t* band_off,
-                          const int32_t* sub_vec_off, const int32_t* lblk_sub, const int32_t* lblk_idx,
-                          int32_t nblk, int32_t ldab, int32_t KL, int32_t KU, int32_t nbL, double* work,
-                          int32_t* lperm, void* lmat, int prec, hipStream_t s);
-void launch_convert_upper(const double* ab, const int64_t* band_off, const int32_t* ublk_sub,
-                          const int32_t* ublk_idx, const int32_t* sub_npad, int32_t nblk, int32_t ldab,
-                          int32_t KL, int32_t KU, int32_t nbU, double* work, void* uinv, void* u12, int prec,
-                          int32_t* info, hipStream_t s);
+void launch_band_pad_identity(const SubInfo* subs, int32_t m, double* ab, hipStream_t s);
+void launch_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, hipStream_t s);
+void launch_convert_lower(const double* ab, const int32_t* ipiv, const SubInfo* subs, const LBlk* lb, int32_t nblk,
+                          double* work, int32_t* lperm, void* lmat, int prec, hipStream_t s);
+void launch_convert_upper(const double* ab, const SubInfo* subs, const UBlk* ub, int32_t nblk, double* work,
+                          void* uinv, void* u12, int prec, int32_t* info, hipStream_t s);
 void launch_dense_scatter(const int64_t* dst, const int32_t* src, const double* cpv, int64_t n, double* out,
                           hipStream_t s);
 void launch_schur_blocks(int32_t k, const int32_t* agg_s, const int32_t* agg_d, const int64_t* g_off,

@@ -111,6 +111,23 @@ def test_apply(case, schur):
     assert np.array_equal(d_x2.cpu().numpy(), x1)
 
 
+@pytest.mark.parametrize("mult", [2, 3])
+def test_block_multiplier_same_operator(case, mult):
+    """Larger sweep blocks regroup the same LU factors: the apply agrees with
+    the oracle to the FP64 bound for every tile shape."""
+    name, S = case
+    ora = oracle_precond(S)
+    part = addns.build_partition(S.N, S.rp, S.ci, S.v, S.m, S.sz)
+    pc = addns.setup_precond(part, S.N, _cuda(S.rp), _cuda(S.ci), _cuda(S.v), block_mult=mult)
+    y = np.random.default_rng(9).standard_normal(S.N)
+    d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+    addns.apply_precond(pc, _cuda(y), d_x)
+    torch.cuda.synchronize()
+    e = relerr(d_x.cpu().numpy(), ora.apply(y))
+    MEASURED[f"apply_mult{mult}_{name}"] = e
+    assert e <= 1e-9
+
+
 @pytest.mark.parametrize("iprec,sprec,tol", [(addns.F32, addns.F32, 1e-4),
                                              (addns.F32, addns.F16_SCALED, 5e-2)])
 def test_apply_mixed(case, iprec, sprec, tol):
