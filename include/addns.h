@@ -103,6 +103,18 @@ int addns_partition_export(addns_partition_t p, int32_t* perm, int32_t* part,
                            int32_t* int_offsets, int32_t* agg_offsets, int32_t* drange_offsets,
                            int32_t* drange_nodes, int32_t* pair);
 
+/* ------------------------------------------------------------------------
+ * addns_partition_concat -- partition of the block-diagonal matrix
+ * diag(C_0, ..., C_{nsys-1}) from the partitions of its independent blocks
+ * (the batched form: every phase of setup and apply then runs as one launch
+ * over the subdomains and aggregates of all systems).  Node s of system q is
+ * node offset_q + s, offset_q = N_0 + ... + N_{q-1}; subdomains and
+ * aggregates keep their system order; interiors of all systems come first
+ * in perm, then all separators.  The inputs are not modified and stay owned
+ * by the caller.  Returns ADDNS_OK, ADDNS_ERR_ARG or ADDNS_ERR_NOMEM.
+ */
+int addns_partition_concat(const addns_partition_t* parts, int32_t nsys, addns_partition_t* out);
+
 typedef struct {
   int32_t schur;          /* ADDNS_SCHUR_* */
   int32_t interior_prec;  /* ADDNS_F64 or ADDNS_F32: storage of the A_jj factors */
@@ -183,6 +195,24 @@ typedef struct {
  */
 int addns_gmres_solve(addns_precond_t pc, const double* d_b, double* d_x,
                       const addns_gmres_opts* opts, addns_gmres_result* res, void* stream);
+
+/* ------------------------------------------------------------------------
+ * addns_gmres_solve_batched -- one independent restarted FGMRES per system
+ * of a block-diagonal matrix (preconditioner built on an
+ * addns_partition_concat partition), all systems advanced in lockstep:
+ * every kernel launch serves all systems still iterating; each system has its
+ * own Krylov basis segment, Hessenberg matrix, rotations, stopping test and
+ * iteration count, and stops (is frozen) on its own.  Mathematically each
+ * system follows addns_gmres_solve with opts.flexible = 1.
+ *   sys_offsets : HOST, nsys+1 increasing row offsets of the systems in the
+ *                 original numbering (0 .. N).
+ *   d_b, d_x    : DEVICE, length N (x: initial guess if opts.use_x0).
+ *   res         : HOST array of nsys results (resid_hist pointers optional).
+ * Returns ADDNS_ERR_NOCONV if any system stops at maxit above tol.
+ */
+int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* sys_offsets,
+                              const double* d_b, double* d_x, const addns_gmres_opts* opts,
+                              addns_gmres_result* res, void* stream);
 
 /* Sizes of a preconditioner: any pointer may be NULL.  bytes_apply is the
    number of bytes the apply reads from its stored factors per call. */

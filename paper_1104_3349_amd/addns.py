@@ -24,6 +24,7 @@ F64, F32, F16_SCALED = 0, 1, 2
 
 EXPORTED = [
     "addns_build_partition", "addns_partition_info", "addns_partition_export",
+    "addns_partition_concat", "addns_gmres_solve_batched",
     "addns_setup_precond", "addns_apply_precond", "addns_interior_solve", "addns_gmres_solve", "addns_precond_info",
     "addns_precond_schur_blocks", "addns_partition_destroy", "addns_precond_destroy",
     "addns_last_error", "addns_version",
@@ -70,6 +71,9 @@ def lib():
         "addns_build_partition": (C.c_int, [C.c_int32, P, P, P, C.c_int32, C.c_int32, C.POINTER(P)]),
         "addns_partition_info": (C.c_int, [P, i32p, i32p, i32p, i32p, i32p, i32p]),
         "addns_partition_export": (C.c_int, [P, P, P, P, P, P, P, P]),
+        "addns_partition_concat": (C.c_int, [C.POINTER(P), C.c_int32, C.POINTER(P)]),
+        "addns_gmres_solve_batched": (C.c_int, [P, C.c_int32, P, P, P, C.POINTER(GmresOpts),
+                                                C.POINTER(GmresResult), P]),
         "addns_setup_precond": (C.c_int, [P, C.c_int32, P, P, P, C.POINTER(PrecondOpts), P,
                                           C.POINTER(P)]),
         "addns_apply_precond": (C.c_int, [P, P, P, P]),
@@ -170,6 +174,19 @@ def build_partition(N, rowptr, colidx, vals, m, sz) -> Partition:
     return Partition(h, st)
 
 
+class ConcatPartition(Partition):
+    def __init__(self, handle, status, parts):
+        super().__init__(handle, status)
+        self.parts = parts  # keep the inputs alive with the concatenation
+
+
+def partition_concat(parts) -> Partition:
+    arr = (C.c_void_p * len(parts))(*[p.handle for p in parts])
+    h = C.c_void_p()
+    _check(lib().addns_partition_concat(arr, len(parts), C.byref(h)), "partition_concat")
+    return ConcatPartition(h, max(p.status for p in parts), list(parts))
+
+
 # --------------------------------------------------------------------------
 # preconditioner and solver
 # --------------------------------------------------------------------------
@@ -241,6 +258,33 @@ def gmres_solve(pc: Precond, d_b, d_x, restart=50, maxit=1000, tol=1e-8, flexibl
     if history:
         out["history"] = hist[:res.iters]
     return out
+
+
+def gmres_solve_batched(pc: Precond, sys_offsets, d_b, d_x, restart=50, maxit=1000, tol=1e-8,
+                        use_x0=False, history=False, stream=None):
+    offs = np.ascontiguousarray(sys_offsets, dtype=np.int32)
+    nsys = len(offs) - 1
+    opts = GmresOpts(int(restart), int(maxit), float(tol), 1, int(bool(use_x0)))
+    res = (GmresResult * nsys)()
+    hists = []
+    if history:
+        for q in range(nsys):
+            h = np.zeros(int(maxit) + 1, np.float64)
+            hists.append(h)
+            res[q].resid_hist = h.ctypes.data_as(C.POINTER(C.c_double))
+    code = lib().addns_gmres_solve_batched(pc.handle, nsys, _ptr(offs), _ptr(d_b), _ptr(d_x),
+                                           C.byref(opts), res, _stream(stream))
+    if code < 0 and code != ERR_NOCONV:
+        _check(code, "gmres_solve_batched")
+    out = []
+    for q in range(nsys):
+        r = res[q]
+        d = dict(iters=r.iters, cycles=r.cycles, converged=bool(r.converged),
+                 true_relres=r.true_relres, est_relres=r.est_relres)
+        if history:
+            d["history"] = hists[q][:r.iters]
+        out.append(d)
+    return out, code
 
 
 def version() -> str:

@@ -404,6 +404,156 @@ int addns_gmres_solve(addns_precond_t pc, const double* d_b, double* d_x, const 
   });
 }
 
+int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* sys_offsets, const double* d_b,
+                              double* d_x, const addns_gmres_opts* opts, addns_gmres_result* res, void* stream) {
+  return guarded("addns_gmres_solve_batched", [&]() -> int {
+    if (!pc || !sys_offsets || !d_b || !d_x || !opts || !res || nsys < 1) throw ArgError("null argument");
+    const int restart = opts->restart, maxit = opts->maxit;
+    if (restart < 1 || maxit < 0 || !(opts->tol > 0.0)) throw ArgError("restart >= 1, maxit >= 0, tol > 0");
+    if (!opts->flexible) throw ArgError("the batched solver is flexible GMRES only");
+    const Plan& pl = pc->plan;
+    const int32_t N = pl.N;
+    if (sys_offsets[0] != 0 || sys_offsets[nsys] != N) throw ArgError("sys_offsets must run from 0 to N");
+    for (int32_t q = 0; q < nsys; ++q)
+      if (sys_offsets[q + 1] <= sys_offsets[q]) throw ArgError("sys_offsets must be increasing");
+    hipStream_t s = as_stream(stream);
+    // rows of every system in the permuted numbering, as contiguous chunks
+    std::vector<int32_t> sys_of(N);
+    for (int32_t q = 0; q < nsys; ++q)
+      for (int32_t o = sys_offsets[q]; o < sys_offsets[q + 1]; ++o) sys_of[pl.iperm[o]] = q;
+    std::vector<std::vector<Chunk>> per(nsys);
+    const int32_t cmax = seg_chunk_rows();
+    for (int32_t r = 0; r < N;) {
+      int32_t q = sys_of[r], e = r;
+      while (e < N && sys_of[e] == q && e - r < cmax) ++e;
+      per[q].push_back(Chunk{r, e, q});
+      r = e;
+    }
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> coff(1, 0);
+    for (int32_t q = 0; q < nsys; ++q) {
+      chunks.insert(chunks.end(), per[q].begin(), per[q].end());
+      coff.push_back((int32_t)chunks.size());
+    }
+    const int nch = (int)chunks.size();
+    DevBuf d_ch, d_coff, d_live, d_jdone, state, parts, scal;
+    d_ch.upload(chunks, s);
+    d_coff.upload(coff, s);
+    d_live.alloc(sizeof(int32_t) * nsys);
+    d_jdone.alloc(sizeof(int32_t) * nsys);
+    const int ldh = restart + 1;
+    const int64_t st = (int64_t)ldh * restart + 4 * ldh;
+    state.alloc(sizeof(double) * st * nsys);
+    ADDNS_HIP(hipMemsetAsync(state.p, 0, sizeof(double) * st * nsys, s));
+    parts.alloc(sizeof(double) * 2 * nch);
+    scal.alloc(sizeof(double) * 4 * nsys);
+    GmresWork g = gmres_work(pc, restart, 1);
+    double* pa = parts.as<double>();
+    double* pb = pa + nch;
+    double* sc = scal.as<double>();
+    const int32_t* rp = pc->cp_rowptr.as<int32_t>();
+    const int32_t* ci = pc->cp_colidx.as<int32_t>();
+    const double* cv = pc->cp_vals.as<double>();
+    std::vector<int32_t> live(nsys, 1), active(nsys, 0), jdone(nsys, 0), its(nsys, 0), conv(nsys, 0), cyc(nsys, 0);
+    std::vector<double> h_sc(4 * nsys), bnorm(nsys), relres(nsys);
+    auto put = [&](DevBuf& d, const std::vector<int32_t>& h) {
+      ADDNS_HIP(hipMemcpyAsync(d.p, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, s));
+    };
+    auto get_scal = [&]() {
+      ADDNS_HIP(hipMemcpyAsync(h_sc.data(), sc, sizeof(double) * 4 * nsys, hipMemcpyDeviceToHost, s));
+      ADDNS_HIP(hipStreamSynchronize(s));
+    };
+    launch_permute(pc->perm.as<int32_t>(), d_b, g.bp, N, 0, pc->R.as<double>(), s);
+    if (opts->use_x0) launch_permute(pc->perm.as<int32_t>(), d_x, g.xp, N, 0, nullptr, s);
+    else ADDNS_HIP(hipMemsetAsync(g.xp, 0, sizeof(double) * N, s));
+    put(d_live, live);
+    launch_seg_dot(g.bp, g.bp, d_ch.as<Chunk>(), nch, pa, s);
+    launch_seg_norm(pa, d_coff.as<int32_t>(), nullptr, nsys, sc, 2, s);
+    launch_seg_residual(rp, ci, cv, g.xp, g.bp, g.rp, d_ch.as<Chunk>(), nch, d_live.as<int32_t>(), pa, s);
+    launch_seg_norm(pa, d_coff.as<int32_t>(), nullptr, nsys, sc, 3, s);
+    get_scal();
+    for (int32_t q = 0; q < nsys; ++q) {
+      bnorm[q] = h_sc[4 * q + 2];
+      relres[q] = bnorm[q] > 0.0 ? h_sc[4 * q + 3] / bnorm[q] : 0.0;
+      conv[q] = relres[q] <= opts->tol;
+      active[q] = !conv[q] && maxit > 0;
+    }
+    auto any = [](const std::vector<int32_t>& v) {
+      for (int32_t x : v)
+        if (x) return true;
+      return false;
+    };
+    while (any(active)) {
+      put(d_live, active);
+      for (int32_t q = 0; q < nsys; ++q) {
+        jdone[q] = 0;
+        if (active[q]) cyc[q]++;
+      }
+      launch_seg_scale_copy(g.rp, g.V, sc, 3, d_ch.as<Chunk>(), nch, d_live.as<int32_t>(), s);
+      launch_seg_init_g(state.as<double>(), st, d_live.as<int32_t>(), nsys, ldh, restart, sc, 3, s);
+      std::vector<int32_t> lv = active;
+      for (int j = 0; j < restart && any(lv); ++j) {
+        put(d_live, lv);
+        double* vj = g.V + (int64_t)j * N;
+        double* zj = g.Z + (int64_t)j * N;
+        apply_permuted(pc, vj, zj, s);
+        launch_seg_spmv_dot(rp, ci, cv, zj, g.w, g.V, d_ch.as<Chunk>(), nch, d_live.as<int32_t>(), pa, s);
+        double* pin = pa;
+        double* pout = pb;
+        for (int i = 0; i <= j; ++i) {
+          const double* vnext = i < j ? g.V + (int64_t)(i + 1) * N : nullptr;
+          launch_seg_mgs_step(g.w, g.V + (int64_t)i * N, vnext, d_ch.as<Chunk>(), nch, d_coff.as<int32_t>(),
+                              d_live.as<int32_t>(), pin, pout, state.as<double>(), st, (int64_t)j * ldh + i, s);
+          std::swap(pin, pout);
+        }
+        launch_seg_finalize(state.as<double>(), st, pin, d_coff.as<int32_t>(), d_live.as<int32_t>(), nsys, j, ldh,
+                            restart, sc, s);
+        launch_seg_scale_copy(g.w, g.V + (int64_t)(j + 1) * N, sc, 0, d_ch.as<Chunk>(), nch, d_live.as<int32_t>(), s);
+        get_scal();
+        for (int32_t q = 0; q < nsys; ++q) {
+          if (!lv[q]) continue;
+          const double hn = h_sc[4 * q], est = h_sc[4 * q + 1];
+          its[q]++;
+          jdone[q] = j + 1;
+          res[q].est_relres = est / bnorm[q];
+          if (res[q].resid_hist) res[q].resid_hist[its[q] - 1] = est / bnorm[q];
+          if (!std::isfinite(est)) throw HipError("non-finite residual estimate in system " + std::to_string(q));
+          if (est <= opts->tol * bnorm[q] || its[q] >= maxit || hn == 0.0) lv[q] = 0;
+        }
+      }
+      put(d_jdone, jdone);
+      put(d_live, active);
+      launch_seg_backsolve(state.as<double>(), st, d_jdone.as<int32_t>(), nsys, ldh, restart, s);
+      launch_seg_combine(g.Z, N, state.as<double>(), st, d_jdone.as<int32_t>(), ldh, restart, d_ch.as<Chunk>(), nch,
+                         g.xp, s);
+      launch_seg_residual(rp, ci, cv, g.xp, g.bp, g.rp, d_ch.as<Chunk>(), nch, d_live.as<int32_t>(), pa, s);
+      launch_seg_norm(pa, d_coff.as<int32_t>(), d_live.as<int32_t>(), nsys, sc, 3, s);
+      get_scal();
+      for (int32_t q = 0; q < nsys; ++q) {
+        if (!active[q]) continue;
+        relres[q] = h_sc[4 * q + 3] / bnorm[q];
+        conv[q] = relres[q] <= opts->tol;
+        if (conv[q] || its[q] >= maxit) active[q] = 0;
+      }
+    }
+    launch_permute(pc->perm.as<int32_t>(), g.xp, d_x, N, 1, nullptr, s);
+    ADDNS_HIP(hipStreamSynchronize(s));
+    bool all = true;
+    for (int32_t q = 0; q < nsys; ++q) {
+      res[q].iters = its[q];
+      res[q].cycles = cyc[q];
+      res[q].converged = conv[q];
+      res[q].true_relres = relres[q];
+      all = all && conv[q];
+    }
+    if (!all) {
+      set_error("some systems reached maxit above tol");
+      return ADDNS_ERR_NOCONV;
+    }
+    return ADDNS_OK;
+  });
+}
+
 int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb_lower, int32_t* nb_upper,
                        int64_t* factor_bytes, int64_t* bytes_apply, int64_t* learned_count) {
   if (!pc) {

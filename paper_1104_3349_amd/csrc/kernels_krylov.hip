@@ -186,6 +186,183 @@ __global__ void k_combine(const double* __restrict__ Z, int64_t ldz, const doubl
   x[e] = add ? x[e] + s : s;
 }
 
+// ---------------------------------------------------------------------------
+// Segmented forms for many independent systems solved in lockstep.  Rows of
+// every system are split into chunks of at most kKT * kPerThread rows, one
+// workgroup each; a system's scalars are fixed-order sums over its chunks'
+// partials.  live[sys] == 0 freezes a system (its chunks do nothing).
+// Per-system Krylov state: H (ldh x restart, column-major), then g, cs, sn,
+// y (ldh each), stride st = ldh * restart + 4 ldh.
+// ---------------------------------------------------------------------------
+__device__ inline double seg_sum(const double* __restrict__ parts, const int32_t* __restrict__ coff, int sys,
+                                 double* red) {
+  double v = 0.0;
+  for (int q = coff[sys] + threadIdx.x; q < coff[sys + 1]; q += blockDim.x) v += parts[q];
+  return block_sum(v, red);
+}
+
+__device__ inline double seg_sum_serial(const double* __restrict__ parts, const int32_t* __restrict__ coff, int sys) {
+  double v = 0.0;
+  for (int q = coff[sys]; q < coff[sys + 1]; ++q) v += parts[q];
+  return v;
+}
+
+__global__ void __launch_bounds__(kKT)
+k_seg_spmv_dot(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx, const double* __restrict__ vals,
+               const double* __restrict__ z, double* __restrict__ w, const double* __restrict__ v0,
+               const Chunk* __restrict__ ch, const int32_t* __restrict__ live, double* __restrict__ partials) {
+  __shared__ double red[kKT / 64];
+  const Chunk c = ch[blockIdx.x];
+  if (!live[c.sys]) return;
+  double acc = 0.0;
+  for (int32_t r = c.start + threadIdx.x; r < c.end; r += blockDim.x) {
+    double y = row_dot(rowptr, colidx, vals, z, r);
+    w[r] = y;
+    acc += y * v0[r];
+  }
+  double sm = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = sm;
+}
+
+__global__ void __launch_bounds__(kKT)
+k_seg_residual(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx, const double* __restrict__ vals,
+               const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ r,
+               const Chunk* __restrict__ ch, const int32_t* __restrict__ live, double* __restrict__ partials) {
+  __shared__ double red[kKT / 64];
+  const Chunk c = ch[blockIdx.x];
+  if (!live[c.sys]) return;
+  double acc = 0.0;
+  for (int32_t i = c.start + threadIdx.x; i < c.end; i += blockDim.x) {
+    double y = b[i] - row_dot(rowptr, colidx, vals, x, i);
+    r[i] = y;
+    acc += y * y;
+  }
+  double sm = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = sm;
+}
+
+__global__ void __launch_bounds__(kKT)
+k_seg_dot(const double* __restrict__ a, const double* __restrict__ b, const Chunk* __restrict__ ch,
+          double* __restrict__ partials) {
+  __shared__ double red[kKT / 64];
+  const Chunk c = ch[blockIdx.x];
+  double acc = 0.0;
+  for (int32_t i = c.start + threadIdx.x; i < c.end; i += blockDim.x) acc += a[i] * b[i];
+  double sm = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = sm;
+}
+
+__global__ void __launch_bounds__(kKT)
+k_seg_mgs_step(double* __restrict__ w, const double* __restrict__ vi, const double* __restrict__ vnext,
+               const Chunk* __restrict__ ch, const int32_t* __restrict__ coff, const int32_t* __restrict__ live,
+               const double* __restrict__ pin, double* __restrict__ pout, double* __restrict__ state, int64_t st,
+               int64_t hidx) {
+  __shared__ double red[kKT / 64];
+  const Chunk c = ch[blockIdx.x];
+  if (!live[c.sys]) return;
+  const double h = seg_sum(pin, coff, c.sys, red);
+  if (blockIdx.x == coff[c.sys] && threadIdx.x == 0) state[c.sys * st + hidx] = h;
+  double acc = 0.0;
+  for (int32_t i = c.start + threadIdx.x; i < c.end; i += blockDim.x) {
+    double y = w[i] - h * vi[i];
+    w[i] = y;
+    acc += y * (vnext ? vnext[i] : y);
+  }
+  double sm = block_sum(acc, red);
+  if (threadIdx.x == 0) pout[blockIdx.x] = sm;
+}
+
+// one thread per system: norm, rotations, new rotation, g update
+__global__ void k_seg_finalize(double* __restrict__ state, int64_t st, const double* __restrict__ partials,
+                               const int32_t* __restrict__ coff, const int32_t* __restrict__ live, int nsys,
+                               int32_t j, int32_t ldh, int32_t restart, double* __restrict__ scal) {
+  const int sys = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sys >= nsys || !live[sys]) return;
+  double* H = state + sys * st;
+  double* g = H + (int64_t)ldh * restart;
+  double* cs = g + ldh;
+  double* sn = cs + ldh;
+  const double hn = sqrt(seg_sum_serial(partials, coff, sys));
+  double* col = H + (int64_t)j * ldh;
+  for (int32_t i = 0; i < j; ++i) {
+    double t = cs[i] * col[i] + sn[i] * col[i + 1];
+    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  double a = col[j], b = hn, c, sv;
+  if (b == 0.0) {
+    c = 1.0;
+    sv = 0.0;
+  } else {
+    double t = hypot(a, b);
+    c = a / t;
+    sv = b / t;
+  }
+  cs[j] = c;
+  sn[j] = sv;
+  col[j] = c * a + sv * b;
+  col[j + 1] = 0.0;
+  g[j + 1] = -sv * g[j];
+  g[j] = c * g[j];
+  scal[4 * sys + 0] = hn;
+  scal[4 * sys + 1] = fabs(g[j + 1]);
+}
+
+__global__ void k_seg_norm(const double* __restrict__ partials, const int32_t* __restrict__ coff,
+                           const int32_t* __restrict__ live, int nsys, double* __restrict__ scal, int idx) {
+  const int sys = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sys >= nsys || (live && !live[sys])) return;
+  scal[4 * sys + idx] = sqrt(seg_sum_serial(partials, coff, sys));
+}
+
+// start of a cycle: g = beta e_1 with beta = scal[4 sys + idx]
+__global__ void k_seg_init_g(double* __restrict__ state, int64_t st, const int32_t* __restrict__ live, int nsys,
+                             int32_t ldh, int32_t restart, const double* __restrict__ scal, int idx) {
+  const int sys = blockIdx.x;
+  if (sys >= nsys || !live[sys]) return;
+  double* g = state + sys * st + (int64_t)ldh * restart;
+  for (int32_t q = threadIdx.x; q < ldh; q += blockDim.x) g[q] = q == 0 ? scal[4 * sys + idx] : 0.0;
+}
+
+__global__ void __launch_bounds__(kKT)
+k_seg_scale_copy(const double* __restrict__ w, double* __restrict__ v, const double* __restrict__ scal, int idx,
+                 const Chunk* __restrict__ ch, const int32_t* __restrict__ live) {
+  const Chunk c = ch[blockIdx.x];
+  if (!live[c.sys]) return;
+  const double d = scal[4 * c.sys + idx];
+  for (int32_t i = c.start + threadIdx.x; i < c.end; i += blockDim.x) v[i] = d != 0.0 ? w[i] / d : w[i];
+}
+
+__global__ void k_seg_backsolve(double* __restrict__ state, int64_t st, const int32_t* __restrict__ jdone, int nsys,
+                                int32_t ldh, int32_t restart) {
+  const int sys = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sys >= nsys) return;
+  const int32_t j = jdone[sys];
+  double* H = state + sys * st;
+  const double* g = H + (int64_t)ldh * restart;
+  double* y = H + (int64_t)ldh * restart + 3 * ldh;
+  for (int32_t i = j - 1; i >= 0; --i) {
+    double sm = g[i];
+    for (int32_t q = i + 1; q < j; ++q) sm -= H[(int64_t)q * ldh + i] * y[q];
+    y[i] = sm / H[(int64_t)i * ldh + i];
+  }
+}
+
+__global__ void __launch_bounds__(kKT)
+k_seg_combine(const double* __restrict__ Z, int64_t ldz, const double* __restrict__ state, int64_t st,
+              const int32_t* __restrict__ jdone, int32_t ldh, int32_t restart, const Chunk* __restrict__ ch,
+              double* __restrict__ x) {
+  const Chunk c = ch[blockIdx.x];
+  const int32_t j = jdone[c.sys];
+  if (j == 0) return;
+  const double* y = state + c.sys * st + (int64_t)ldh * restart + 3 * ldh;
+  for (int32_t e = c.start + threadIdx.x; e < c.end; e += blockDim.x) {
+    double sm = 0.0;
+    for (int32_t i = 0; i < j; ++i) sm += y[i] * Z[(int64_t)i * ldz + e];
+    x[e] += sm;
+  }
+}
+
 inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -232,4 +409,48 @@ void launch_combine(const double* Z, int64_t ldz, const double* y, int32_t j, in
   if (n > 0) k_combine<<<nb(n, 256), 256, 0, s>>>(Z, ldz, y, j, n, x, add);
 }
 
+}  // namespace addns
+
+namespace addns {
+int seg_chunk_rows() { return kKT * kPerThread; }
+void launch_seg_spmv_dot(const int32_t* rp, const int32_t* ci, const double* cv, const double* z, double* w,
+                         const double* v0, const Chunk* ch, int nch, const int32_t* live, double* parts, hipStream_t s) {
+  k_seg_spmv_dot<<<nch, kKT, 0, s>>>(rp, ci, cv, z, w, v0, ch, live, parts);
+}
+void launch_seg_residual(const int32_t* rp, const int32_t* ci, const double* cv, const double* x, const double* b,
+                         double* r, const Chunk* ch, int nch, const int32_t* live, double* parts, hipStream_t s) {
+  k_seg_residual<<<nch, kKT, 0, s>>>(rp, ci, cv, x, b, r, ch, live, parts);
+}
+void launch_seg_dot(const double* a, const double* b, const Chunk* ch, int nch, double* parts, hipStream_t s) {
+  k_seg_dot<<<nch, kKT, 0, s>>>(a, b, ch, parts);
+}
+void launch_seg_mgs_step(double* w, const double* vi, const double* vnext, const Chunk* ch, int nch,
+                         const int32_t* coff, const int32_t* live, const double* pin, double* pout, double* state,
+                         int64_t st, int64_t hidx, hipStream_t s) {
+  k_seg_mgs_step<<<nch, kKT, 0, s>>>(w, vi, vnext, ch, coff, live, pin, pout, state, st, hidx);
+}
+void launch_seg_finalize(double* state, int64_t st, const double* parts, const int32_t* coff, const int32_t* live,
+                         int nsys, int32_t j, int32_t ldh, int32_t restart, double* scal, hipStream_t s) {
+  k_seg_finalize<<<(nsys + 63) / 64, 64, 0, s>>>(state, st, parts, coff, live, nsys, j, ldh, restart, scal);
+}
+void launch_seg_norm(const double* parts, const int32_t* coff, const int32_t* live, int nsys, double* scal, int idx,
+                     hipStream_t s) {
+  k_seg_norm<<<(nsys + 63) / 64, 64, 0, s>>>(parts, coff, live, nsys, scal, idx);
+}
+void launch_seg_init_g(double* state, int64_t st, const int32_t* live, int nsys, int32_t ldh, int32_t restart,
+                       const double* scal, int idx, hipStream_t s) {
+  k_seg_init_g<<<nsys, 64, 0, s>>>(state, st, live, nsys, ldh, restart, scal, idx);
+}
+void launch_seg_scale_copy(const double* w, double* v, const double* scal, int idx, const Chunk* ch, int nch,
+                           const int32_t* live, hipStream_t s) {
+  k_seg_scale_copy<<<nch, kKT, 0, s>>>(w, v, scal, idx, ch, live);
+}
+void launch_seg_backsolve(double* state, int64_t st, const int32_t* jdone, int nsys, int32_t ldh, int32_t restart,
+                          hipStream_t s) {
+  k_seg_backsolve<<<(nsys + 63) / 64, 64, 0, s>>>(state, st, jdone, nsys, ldh, restart);
+}
+void launch_seg_combine(const double* Z, int64_t ldz, const double* state, int64_t st, const int32_t* jdone,
+                        int32_t ldh, int32_t restart, const Chunk* ch, int nch, double* x, hipStream_t s) {
+  k_seg_combine<<<nch, kKT, 0, s>>>(Z, ldz, state, st, jdone, ldh, restart, ch, x);
+}
 }  // namespace addns

@@ -83,6 +83,11 @@ struct UBlk {             // one upper block: nbu x nbu inverse and coupling
   int64_t off;            // offset into inv(U_bb) and U_{b,b+1} (elements); also work offset
 };
 
+// A contiguous row range of one system (segmented Krylov reductions).
+struct Chunk {
+  int32_t start, end, sys;
+};
+
 // Host-side integer plan: every gather map the device setup needs.  Built
 // from the partition and the pattern only.
 struct Plan {
@@ -195,4 +200,26 @@ void launch_backsolve(const double* H, const double* g, int32_t j, int32_t ldh, 
 void launch_combine(const double* Z, int64_t ldz, const double* y, int32_t j, int32_t n, double* x, int add,
                     hipStream_t s);
 void launch_dot_partials(const double* a, const double* b, int32_t n, double* partials, hipStream_t s);
+// segmented Krylov (batched systems)
+int seg_chunk_rows();
+void launch_seg_spmv_dot(const int32_t* rp, const int32_t* ci, const double* cv, const double* z, double* w,
+                         const double* v0, const Chunk* ch, int nch, const int32_t* live, double* parts, hipStream_t s);
+void launch_seg_residual(const int32_t* rp, const int32_t* ci, const double* cv, const double* x, const double* b,
+                         double* r, const Chunk* ch, int nch, const int32_t* live, double* parts, hipStream_t s);
+void launch_seg_dot(const double* a, const double* b, const Chunk* ch, int nch, double* parts, hipStream_t s);
+void launch_seg_mgs_step(double* w, const double* vi, const double* vnext, const Chunk* ch, int nch,
+                         const int32_t* coff, const int32_t* live, const double* pin, double* pout, double* state,
+                         int64_t st, int64_t hidx, hipStream_t s);
+void launch_seg_finalize(double* state, int64_t st, const double* parts, const int32_t* coff, const int32_t* live,
+                         int nsys, int32_t j, int32_t ldh, int32_t restart, double* scal, hipStream_t s);
+void launch_seg_norm(const double* parts, const int32_t* coff, const int32_t* live, int nsys, double* scal, int idx,
+                     hipStream_t s);
+void launch_seg_init_g(double* state, int64_t st, const int32_t* live, int nsys, int32_t ldh, int32_t restart,
+                       const double* scal, int idx, hipStream_t s);
+void launch_seg_scale_copy(const double* w, double* v, const double* scal, int idx, const Chunk* ch, int nch,
+                           const int32_t* live, hipStream_t s);
+void launch_seg_backsolve(double* state, int64_t st, const int32_t* jdone, int nsys, int32_t ldh, int32_t restart,
+                          hipStream_t s);
+void launch_seg_combine(const double* Z, int64_t ldz, const double* state, int64_t st, const int32_t* jdone,
+                        int32_t ldh, int32_t restart, const Chunk* ch, int nch, double* x, hipStream_t s);
 }  // namespace addns

@@ -298,3 +298,67 @@ def test_setup_argument_errors():
     d = torch.zeros(S.N, dtype=torch.float64, device="cuda")
     with pytest.raises(addns.AddnsError):
         addns.apply_precond(pc, d, d)
+
+
+# ---------------------------------------------------------------------------
+# batched systems (block-diagonal concatenation, lockstep FGMRES)
+# ---------------------------------------------------------------------------
+BATCH = [dict(n=12, nu=0.05, m=3, sz=16, seed=41), dict(n=20, nu=0.01, m=5, sz=24, seed=42),
+         dict(n=8, nu=0.2, m=2, sz=8, seed=43), dict(n=16, nu=0.02, m=4, sz=32, stretch=1.05, seed=44)]
+
+
+def _batched():
+    import scipy.sparse as sp
+    systems = [make_system(**c) for c in BATCH]
+    parts = [addns.build_partition(S.N, S.rp, S.ci, S.v, S.m, S.sz) for S in systems]
+    cat = addns.partition_concat(parts)
+    big = sp.block_diag([sp.csr_matrix((S.v, S.ci, S.rp), shape=(S.N, S.N)) for S in systems]).tocsr()
+    big.sort_indices()
+    b = np.concatenate([S.b for S in systems])
+    offs = np.concatenate([[0], np.cumsum([S.N for S in systems])])
+    pc = addns.setup_precond(cat, big.shape[0], _cuda(big.indptr.astype(np.int32)),
+                             _cuda(big.indices.astype(np.int32)), _cuda(big.data))
+    return systems, pc, b, offs
+
+
+def test_batched_apply_is_blockwise():
+    systems, pc, b, offs = _batched()
+    y = np.random.default_rng(3).standard_normal(offs[-1])
+    d_x = torch.zeros(offs[-1], dtype=torch.float64, device="cuda")
+    addns.apply_precond(pc, _cuda(y), d_x)
+    torch.cuda.synchronize()
+    x = d_x.cpu().numpy()
+    for q, S in enumerate(systems):
+        ref = oracle_precond(S).apply(y[offs[q]:offs[q + 1]])
+        assert relerr(x[offs[q]:offs[q + 1]], ref) <= 1e-9
+
+
+def test_batched_gmres_equal_iterations():
+    systems, pc, b, offs = _batched()
+    k, restart = 9, 4
+    d_x = torch.zeros(offs[-1], dtype=torch.float64, device="cuda")
+    res, code = addns.gmres_solve_batched(pc, offs, _cuda(b), d_x, restart=restart, maxit=k, tol=1e-300,
+                                          history=True)
+    x = d_x.cpu().numpy()
+    for q, S in enumerate(systems):
+        ora = oracle_precond(S)
+        ref = gmres(lambda z: ora.C @ z, ora.apply, ora.R * S.b, restart=restart, tol=1e-300, maxit=k)
+        assert res[q]["iters"] == k
+        e = relerr(x[offs[q]:offs[q + 1]], ref.x)
+        MEASURED[f"batched_equal_its_{q}"] = e
+        assert e <= 1e-10
+        np.testing.assert_allclose(res[q]["history"], ref.est_history, rtol=1e-8)
+
+
+def test_batched_converges_per_system():
+    systems, pc, b, offs = _batched()
+    d_x = torch.zeros(offs[-1], dtype=torch.float64, device="cuda")
+    res, code = addns.gmres_solve_batched(pc, offs, _cuda(b), d_x, restart=20, maxit=2000, tol=1e-8)
+    assert code == addns.OK
+    for q, S in enumerate(systems):
+        part, p1 = gpu_precond(S)
+        d1 = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+        r1 = addns.gmres_solve(p1, _cuda(S.b), d1, restart=20, maxit=2000, tol=1e-8, flexible=True)
+        assert res[q]["converged"] and res[q]["true_relres"] <= 1e-8
+        assert abs(res[q]["iters"] - r1["iters"]) <= 1
+    MEASURED["batched_its"] = [r["iters"] for r in res]
