@@ -124,8 +124,10 @@ typedef struct {
                                   stored entry of G_i in aggregate order, row-major
                                   per block (addns_precond_info gives the count) */
   int32_t block_mult;     /* interior sweep block size as a multiple of its minimum
-                             (1..4; 0 = 1).  A tile shape only: the factors are the
-                             same LU, regrouped; results agree to rounding */
+                             (1..4), or 0: the autotuner builds the sweep at 1 and 2,
+                             times the interior solve on these factors and keeps the
+                             faster.  A tile shape only: the factors are the same
+                             LU, regrouped; results agree to rounding */
 } addns_precond_opts;
 
 /* ------------------------------------------------------------------------
@@ -215,10 +217,13 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
                               addns_gmres_result* res, void* stream);
 
 /* Sizes of a preconditioner: any pointer may be NULL.  bytes_apply is the
-   number of bytes the apply reads from its stored factors per call. */
+   algorithmic byte count of one apply (band factors read once per sweep,
+   pivots, coupling blocks, interface inverses, vector passes); block_mult
+   is the sweep tile multiplier in use (chosen by the autotuner when the
+   options asked for 0). */
 int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb_lower,
                        int32_t* nb_upper, int64_t* factor_bytes, int64_t* bytes_apply,
-                       int64_t* learned_count);
+                       int64_t* learned_count, int32_t* block_mult);
 
 /* Copy the dense interface blocks S_i (before inversion) into a HOST array
    in aggregate order, row-major per block; `count` must equal the sum of

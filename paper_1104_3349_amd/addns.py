@@ -79,7 +79,7 @@ def lib():
         "addns_apply_precond": (C.c_int, [P, P, P, P]),
         "addns_interior_solve": (C.c_int, [P, P, P, P]),
         "addns_gmres_solve": (C.c_int, [P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresResult), P]),
-        "addns_precond_info": (C.c_int, [P, i32p, i32p, i32p, i32p, i64p, i64p, i64p]),
+        "addns_precond_info": (C.c_int, [P, i32p, i32p, i32p, i32p, i64p, i64p, i64p, i32p]),
         "addns_precond_schur_blocks": (C.c_int, [P, P, C.c_int64]),
         "addns_partition_destroy": (None, [P]),
         "addns_precond_destroy": (None, [P]),
@@ -204,10 +204,13 @@ class Precond:
     def info(self):
         i32 = [C.c_int32() for _ in range(4)]
         i64 = [C.c_int64() for _ in range(3)]
-        _check(lib().addns_precond_info(self.handle, *[C.byref(x) for x in i32 + i64]),
+        bm = C.c_int32()
+        _check(lib().addns_precond_info(self.handle, *[C.byref(x) for x in i32 + i64], C.byref(bm)),
                "precond_info")
-        return dict(zip(("kl", "ku", "nb_lower", "nb_upper", "factor_bytes", "bytes_apply",
-                         "learned_count"), (x.value for x in i32 + i64)))
+        d = dict(zip(("kl", "ku", "nb_lower", "nb_upper", "factor_bytes", "bytes_apply",
+                      "learned_count"), (x.value for x in i32 + i64)))
+        d["block_mult"] = bm.value
+        return d
 
     def schur_blocks(self, count):
         out = np.empty(int(count), np.float64)

@@ -199,6 +199,30 @@ void apply_permuted(addns_precond* pc, const double* yp, double* xp, hipStream_t
   if (pl.k > 0) launch_interior_solve(pc, nullptr, xp, 1, xp + pl.n_int, xp, s);
 }
 
+// Mean duration (ms) of a few interior solves on the handle's own factors.
+float time_interior_solve(addns_precond* pc, hipStream_t s) {
+  const Plan& pl = pc->plan;
+  if (pl.n_int == 0 || pl.m == 0) return 0.0f;
+  DevBuf y, z;
+  y.alloc(sizeof(double) * pl.n_int);
+  z.alloc(sizeof(double) * pl.n_int);
+  ADDNS_HIP(hipMemsetAsync(y.p, 0, sizeof(double) * pl.n_int, s));
+  hipEvent_t e0, e1;
+  ADDNS_HIP(hipEventCreate(&e0));
+  ADDNS_HIP(hipEventCreate(&e1));
+  launch_interior_solve(pc, y.as<double>(), z.as<double>(), 0, nullptr, nullptr, s);
+  ADDNS_HIP(hipEventRecord(e0, s));
+  const int reps = 3;
+  for (int r = 0; r < reps; ++r) launch_interior_solve(pc, y.as<double>(), z.as<double>(), 0, nullptr, nullptr, s);
+  ADDNS_HIP(hipEventRecord(e1, s));
+  ADDNS_HIP(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  ADDNS_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / reps;
+}
+
 struct GmresWork {
   double *V, *Z, *w, *xp, *bp, *rp, *H, *g, *cs, *sn, *y, *pa, *pb, *scal;
 };
@@ -259,19 +283,41 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
     if (opts) o = *opts;
     if (o.schur < 0 || o.schur > ADDNS_SCHUR_LEARNED) throw ArgError("unknown schur mode");
     if (o.block_mult < 0 || o.block_mult > 4) throw ArgError("block_mult must be 0..4");
-    if (o.block_mult == 0) o.block_mult = 1;
+    const bool autotune = o.block_mult == 0;
     if (o.schur == ADDNS_SCHUR_EXACT_BJ) throw ArgError("EXACT_BJ is an oracle-side reference mode");
     if (o.schur == ADDNS_SCHUR_LEARNED) throw ArgError("LEARNED mode is not available in this build");
     if (o.interior_prec != ADDNS_F64 && o.interior_prec != ADDNS_F32) throw ArgError("interior_prec");
     if (o.schur_prec < ADDNS_F64 || o.schur_prec > ADDNS_F16_SCALED) throw ArgError("schur_prec");
     if (o.schur == ADDNS_SCHUR_MSCN_LITERAL && p->d.n_int() < p->d.sep_size())
       throw ArgError("literal D-range pairing needs |D| >= |Sigma|");
-    std::unique_ptr<addns_precond> pc(new addns_precond());
-    pc->schur_mode = o.schur;
-    pc->row_scale = o.row_scale;
-    ADDNS_HIP(hipGetDevice(&pc->device));
-    setup_device(pc.get(), p->d, d_rowptr, d_colidx, d_vals, o, as_stream(stream));
-    *out = pc.release();
+    auto make = [&](int mult) {
+      std::unique_ptr<addns_precond> pc(new addns_precond());
+      pc->schur_mode = o.schur;
+      pc->row_scale = o.row_scale;
+      ADDNS_HIP(hipGetDevice(&pc->device));
+      addns_precond_opts oo = o;
+      oo.block_mult = mult;
+      setup_device(pc.get(), p->d, d_rowptr, d_colidx, d_vals, oo, as_stream(stream));
+      return pc;
+    };
+    if (!autotune) {
+      *out = make(o.block_mult).release();
+      return ADDNS_OK;
+    }
+    // Autotuner: the sweep block size is a tile shape (the same LU factors,
+    // regrouped), chosen by timing the interior solve on these factors.
+    std::unique_ptr<addns_precond> best;
+    float best_ms = 0.0f;
+    for (int mult : {1, 2}) {
+      std::unique_ptr<addns_precond> pc = make(mult);
+      const float ms = time_interior_solve(pc.get(), as_stream(stream));
+      pc->tuned_ms = ms;
+      if (!best || ms < best_ms) {
+        best = std::move(pc);
+        best_ms = ms;
+      }
+    }
+    *out = best.release();
     return ADDNS_OK;
   });
 }
@@ -555,7 +601,7 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
 }
 
 int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb_lower, int32_t* nb_upper,
-                       int64_t* factor_bytes, int64_t* bytes_apply, int64_t* learned_count) {
+                       int64_t* factor_bytes, int64_t* bytes_apply, int64_t* learned_count, int32_t* block_mult) {
   if (!pc) {
     set_error("addns_precond_info: null handle");
     return ADDNS_ERR_ARG;
@@ -567,6 +613,7 @@ int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb
   if (factor_bytes) *factor_bytes = pc->factor_bytes;
   if (bytes_apply) *bytes_apply = pc->bytes_apply;
   if (learned_count) *learned_count = pc->plan.g_total;
+  if (block_mult) *block_mult = pc->plan.block_mult;
   return ADDNS_OK;
 }
 

@@ -144,6 +144,7 @@ struct addns_precond {
   addns::DevBuf vperm_in, vperm_out;                  // permuted apply in/out
   int64_t factor_bytes = 0, bytes_apply = 0;
   int64_t learned_count = 0;
+  float tuned_ms = 0.0f;                              // autotuner timing of the interior solve
   // GMRES work space (grown on demand)
   addns::DevBuf V, Z, w, xp, bp, rp, Hd, gd, partials, scal;
   int gm_restart = 0;
