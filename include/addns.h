@@ -120,14 +120,15 @@ typedef struct {
   int32_t interior_prec;  /* ADDNS_F64 or ADDNS_F32: storage of the A_jj factors */
   int32_t schur_prec;     /* ADDNS_F64, ADDNS_F32 or ADDNS_F16_SCALED: Shat^-1 */
   int32_t row_scale;      /* 1 = scale rows by their max |entry| (the paper's default) */
-  const double* learned_delta; /* LEARNED only: HOST array, one correction per
-                                  stored entry of G_i in aggregate order, row-major
-                                  per block (addns_precond_info gives the count) */
+  const float* learned_model; /* LEARNED only: HOST array of addns_dtn_param_count()
+                                  FP32 network weights (addns_dtn_train output) */
   int32_t block_mult;     /* interior sweep block size as a multiple of its minimum
                              (1..4), or 0: the autotuner builds the sweep at 1 and 2,
                              times the interior solve on these factors and keeps the
                              faster.  A tile shape only: the factors are the same
                              LU, regrouped; results agree to rounding */
+  int32_t learned_bf16;   /* LEARNED only: 1 = run the network with BF16-rounded
+                             weights and activations, 0 = FP32 */
 } addns_precond_opts;
 
 /* ------------------------------------------------------------------------
@@ -220,7 +221,8 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
    algorithmic byte count of one apply (band factors read once per sweep,
    pivots, coupling blocks, interface inverses, vector passes); block_mult
    is the sweep tile multiplier in use (chosen by the autotuner when the
-   options asked for 0). */
+   options asked for 0); learned_count is the number of learned-correction
+   samples (separator velocity rows) in EXACT_BJ and LEARNED modes, else 0. */
 int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb_lower,
                        int32_t* nb_upper, int64_t* factor_bytes, int64_t* bytes_apply,
                        int64_t* learned_count, int32_t* block_mult);
@@ -229,6 +231,81 @@ int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb
    in aggregate order, row-major per block; `count` must equal the sum of
    |agg_i|^2. */
 int addns_precond_schur_blocks(addns_precond_t pc, double* h_out, int64_t count);
+
+/* ========================================================================
+ * Learned interface correction -- an extension, not a method of the paper.
+ * The exact interface Schur complement S = G - F D^-1 E (section 1; the
+ * algebraic Dirichlet-to-Neumann map) is approximated blockwise by the MSCN
+ * blocks of section 3.1.  Here a small network predicts, for each separator
+ * velocity row, corrections on G's own stencil pattern:
+ *   S_i ~ G_i + Delta_i,
+ * trained on the diagonal blocks of the exact S (ADDNS_SCHUR_EXACT_BJ).
+ *   features (7, FP32): the five scaled stencil coefficients of the row in
+ *     the slots [far lower, near lower, diagonal, near upper, far upper]
+ *     (neighbours ordered by distance in the original numbering, velocity
+ *     unknowns only) and the skew (convective) differences near and far;
+ *   network: 7 -> 64 -> 64 -> 5, ReLU, row-major W1[64][7] b1[64] W2[64][64]
+ *     b2[64] W3[5][64] b3[5];
+ *   targets: S - G on the slots whose neighbour lies in the same aggregate
+ *     (mask 1), else 0 (mask 0); loss (1/count) sum mask (p - y)^2.
+ * Because a learned form is not exact, solves with it go through
+ * addns_gmres_solve_judged, which accepts it only when the FP64 true residual
+ * reaches the tolerance.
+ * ====================================================================== */
+
+/* Number of FP32 network parameters (4997). */
+int addns_dtn_param_count(void);
+
+/* Training samples of an ADDNS_SCHUR_EXACT_BJ preconditioner, one per
+   separator velocity row, into DEVICE arrays X[count][7], Y[count][5],
+   M[count][5] (FP32).  With all three NULL only *count is set (a size
+   query; 0 unless the mode is EXACT_BJ or LEARNED).  cap: capacity in samples.  Asynchronous on
+   `stream`.  ADDNS_ERR_ARG if pc is not EXACT_BJ or cap < count. */
+int addns_dtn_samples(addns_precond_t pc, float* d_X, float* d_Y, float* d_M, int64_t cap,
+                      int64_t* count, void* stream);
+
+/* Network output P[count][5] for DEVICE features X[count][7]; weights on the
+   HOST (param_count FP32).  bf16 = 1 rounds weights, inputs and hidden
+   activations to BF16 (round to nearest even), accumulating in FP32.
+   Returns after completion. */
+int addns_dtn_forward(const float* h_weights, const float* d_X, float* d_P, int64_t count,
+                      int32_t bf16, void* stream);
+
+/* Full-batch gradient of the loss in FP32 (fixed reduction order) into the
+   HOST array h_grad[param_count]; *loss receives the loss (may be NULL).
+   Returns after completion. */
+int addns_dtn_grad(const float* h_weights, const float* d_X, const float* d_Y, const float* d_M,
+                   int64_t count, float* h_grad, double* loss, void* stream);
+
+typedef struct {
+  int32_t epochs;     /* passes over the samples (>= 0) */
+  int32_t batch;      /* minibatch size (>= 1) */
+  float lr;           /* Adam step size (> 0) */
+  float beta1, beta2, eps; /* Adam moments and guard */
+  int64_t seed;       /* initialisation and shuffling (host mt19937_64) */
+  int32_t init_given; /* 1 = start from h_weights, 0 = seeded He-uniform init */
+} addns_dtn_params;
+
+/* Minibatch Adam training on the GPU in FP32 over DEVICE samples.  The
+   weights are returned in h_weights (HOST, param_count).  h_loss (HOST,
+   epochs entries, may be NULL) receives the full-data loss after each
+   epoch.  Deterministic for a given seed.  Returns after completion. */
+int addns_dtn_train(const float* d_X, const float* d_Y, const float* d_M, int64_t count,
+                    const addns_dtn_params* hp, float* h_weights, double* h_loss, void* stream);
+
+/* Weights file: 8-byte tag "ADDNSDTN", int32 parameter count, FP32 weights
+   (little endian).  ADDNS_ERR_ARG on a missing file, a wrong tag or count. */
+int addns_dtn_save(const char* path, const float* h_weights);
+int addns_dtn_load(const char* path, float* h_weights);
+
+/* Judged solve: addns_gmres_solve with `learned`; if it does not reach
+   opts.tol in FP64 true relative residual within opts.maxit, the same solve
+   is run again with `plain` from the caller's initial guess.  *accepted = 1
+   when the learned result was kept.  The two handles must be set up on the
+   same matrix. */
+int addns_gmres_solve_judged(addns_precond_t learned, addns_precond_t plain, const double* d_b,
+                             double* d_x, const addns_gmres_opts* opts, addns_gmres_result* res,
+                             int32_t* accepted, void* stream);
 
 void addns_partition_destroy(addns_partition_t p);
 void addns_precond_destroy(addns_precond_t pc);

@@ -28,6 +28,8 @@ EXPORTED = [
     "addns_setup_precond", "addns_apply_precond", "addns_interior_solve", "addns_gmres_solve", "addns_precond_info",
     "addns_precond_schur_blocks", "addns_partition_destroy", "addns_precond_destroy",
     "addns_last_error", "addns_version",
+    "addns_dtn_param_count", "addns_dtn_samples", "addns_dtn_forward", "addns_dtn_grad",
+    "addns_dtn_train", "addns_dtn_save", "addns_dtn_load", "addns_gmres_solve_judged",
 ]
 
 
@@ -39,13 +41,19 @@ class AddnsError(RuntimeError):
 
 class PrecondOpts(C.Structure):
     _fields_ = [("schur", C.c_int32), ("interior_prec", C.c_int32), ("schur_prec", C.c_int32),
-                ("row_scale", C.c_int32), ("learned_delta", C.POINTER(C.c_double)),
-                ("block_mult", C.c_int32)]
+                ("row_scale", C.c_int32), ("learned_model", C.POINTER(C.c_float)),
+                ("block_mult", C.c_int32), ("learned_bf16", C.c_int32)]
 
 
 class GmresOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("tol", C.c_double),
                 ("flexible", C.c_int32), ("use_x0", C.c_int32)]
+
+
+class DtnParams(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("seed", C.c_int64), ("init_given", C.c_int32)]
 
 
 class GmresResult(C.Structure):
@@ -85,6 +93,15 @@ def lib():
         "addns_precond_destroy": (None, [P]),
         "addns_last_error": (C.c_char_p, []),
         "addns_version": (C.c_char_p, []),
+        "addns_dtn_param_count": (C.c_int, []),
+        "addns_dtn_samples": (C.c_int, [P, P, P, P, C.c_int64, i64p, P]),
+        "addns_dtn_forward": (C.c_int, [P, P, P, C.c_int64, C.c_int32, P]),
+        "addns_dtn_grad": (C.c_int, [P, P, P, P, C.c_int64, P, f64p, P]),
+        "addns_dtn_train": (C.c_int, [P, P, P, C.c_int64, C.POINTER(DtnParams), P, P, P]),
+        "addns_dtn_save": (C.c_int, [C.c_char_p, P]),
+        "addns_dtn_load": (C.c_int, [C.c_char_p, P]),
+        "addns_gmres_solve_judged": (C.c_int, [P, P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresResult),
+                                               i32p, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -220,13 +237,13 @@ class Precond:
 
 
 def setup_precond(partition: Partition, N, d_rowptr, d_colidx, d_vals, schur=SCHUR_MSCN,
-                  interior_prec=F64, schur_prec=F64, row_scale=1, learned_delta=None,
-                  block_mult=1, stream=None) -> Precond:
+                  interior_prec=F64, schur_prec=F64, row_scale=1, learned_model=None,
+                  block_mult=1, learned_bf16=True, stream=None) -> Precond:
     opts = PrecondOpts(int(schur), int(interior_prec), int(schur_prec), int(row_scale), None,
-                       int(block_mult))
-    if learned_delta is not None:
-        ld = np.ascontiguousarray(learned_delta, dtype=np.float64)
-        opts.learned_delta = ld.ctypes.data_as(C.POINTER(C.c_double))
+                       int(block_mult), int(bool(learned_bf16)))
+    if learned_model is not None:
+        lm = np.ascontiguousarray(learned_model, dtype=np.float32)
+        opts.learned_model = lm.ctypes.data_as(C.POINTER(C.c_float))
     h = C.c_void_p()
     _check(lib().addns_setup_precond(partition.handle, int(N), _ptr(d_rowptr), _ptr(d_colidx),
                                      _ptr(d_vals), C.byref(opts), _stream(stream), C.byref(h)),
@@ -288,6 +305,88 @@ def gmres_solve_batched(pc: Precond, sys_offsets, d_b, d_x, restart=50, maxit=10
             d["history"] = hists[q][:r.iters]
         out.append(d)
     return out, code
+
+
+def _gmres_out(res, code, hist):
+    out = dict(iters=res.iters, cycles=res.cycles, converged=bool(res.converged),
+               true_relres=res.true_relres, est_relres=res.est_relres, code=code)
+    if hist is not None:
+        out["history"] = hist[:res.iters]
+    return out
+
+
+def gmres_solve_judged(learned: Precond, plain: Precond, d_b, d_x, restart=50, maxit=1000, tol=1e-8,
+                       flexible=True, use_x0=False, history=False, stream=None):
+    opts = GmresOpts(int(restart), int(maxit), float(tol), int(bool(flexible)), int(bool(use_x0)))
+    res = GmresResult()
+    hist = None
+    if history:
+        hist = np.zeros(int(maxit) + 1, np.float64)
+        res.resid_hist = hist.ctypes.data_as(C.POINTER(C.c_double))
+    acc = C.c_int32(0)
+    code = lib().addns_gmres_solve_judged(learned.handle, plain.handle, _ptr(d_b), _ptr(d_x),
+                                          C.byref(opts), C.byref(res), C.byref(acc), _stream(stream))
+    if code < 0 and code != ERR_NOCONV:
+        _check(code, "gmres_solve_judged")
+    out = _gmres_out(res, code, hist)
+    out["accepted"] = bool(acc.value)
+    return out
+
+
+# --------------------------------------------------------------------------
+# learned interface correction (extension)
+# --------------------------------------------------------------------------
+
+def dtn_param_count() -> int:
+    return int(lib().addns_dtn_param_count())
+
+
+def dtn_samples(pc: Precond, d_X=None, d_Y=None, d_M=None, stream=None) -> int:
+    """Sample count; with device tensors X[count,7], Y[count,5], M[count,5]
+    (float32) also writes the features, targets and masks."""
+    n = C.c_int64(0)
+    cap = 0 if d_X is None else int(d_X.shape[0])
+    _check(lib().addns_dtn_samples(pc.handle, _ptr(d_X), _ptr(d_Y), _ptr(d_M), cap, C.byref(n),
+                                   _stream(stream)), "dtn_samples")
+    return int(n.value)
+
+
+def dtn_forward(weights, d_X, d_P, bf16=False, stream=None):
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    _check(lib().addns_dtn_forward(_ptr(w), _ptr(d_X), _ptr(d_P), int(d_X.shape[0]), int(bool(bf16)),
+                                   _stream(stream)), "dtn_forward")
+
+
+def dtn_grad(weights, d_X, d_Y, d_M, stream=None):
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    g = np.empty(dtn_param_count(), np.float32)
+    loss = C.c_double(0.0)
+    _check(lib().addns_dtn_grad(_ptr(w), _ptr(d_X), _ptr(d_Y), _ptr(d_M), int(d_X.shape[0]), _ptr(g),
+                                C.byref(loss), _stream(stream)), "dtn_grad")
+    return g, loss.value
+
+
+def dtn_train(d_X, d_Y, d_M, epochs=10, batch=256, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+              seed=0, init=None, stream=None):
+    hp = DtnParams(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps),
+                   int(seed), int(init is not None))
+    w = (np.zeros(dtn_param_count(), np.float32) if init is None
+         else np.array(init, dtype=np.float32, copy=True))
+    loss = np.zeros(max(int(epochs), 1), np.float64)
+    _check(lib().addns_dtn_train(_ptr(d_X), _ptr(d_Y), _ptr(d_M), int(d_X.shape[0]), C.byref(hp),
+                                 _ptr(w), _ptr(loss), _stream(stream)), "dtn_train")
+    return w, loss[:int(epochs)]
+
+
+def dtn_save(path, weights):
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    _check(lib().addns_dtn_save(os.fsencode(path), _ptr(w)), "dtn_save")
+
+
+def dtn_load(path):
+    w = np.empty(dtn_param_count(), np.float32)
+    _check(lib().addns_dtn_load(os.fsencode(path), _ptr(w)), "dtn_load")
+    return w
 
 
 def version() -> str:

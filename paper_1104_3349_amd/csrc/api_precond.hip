@@ -18,28 +18,6 @@ namespace {
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
-template <class F>
-int guarded(const char* what, F&& f) {
-  try {
-    return f();
-  } catch (const ArgError& e) {
-    set_error(std::string(what) + ": " + e.what());
-    return ADDNS_ERR_ARG;
-  } catch (const SingularError& e) {
-    set_error(std::string(what) + ": " + e.what());
-    return ADDNS_ERR_SINGULAR;
-  } catch (const HipError& e) {
-    set_error(std::string(what) + ": " + e.what());
-    return ADDNS_ERR_HIP;
-  } catch (const std::bad_alloc&) {
-    set_error(std::string(what) + ": out of host memory");
-    return ADDNS_ERR_NOMEM;
-  } catch (const std::exception& e) {
-    set_error(std::string(what) + ": " + e.what());
-    return ADDNS_ERR_HIP;
-  }
-}
-
 int prec_bytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
 
 // Factor and interface storage of one preconditioner.
@@ -152,6 +130,51 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
     de_off.upload(pl.de_off, s);
     df_off.upload(pl.df_off, s);
     double* G = dense.as<double>();
+    const int64_t nsmp = (int64_t)pl.smp_row.size();
+    if (o.schur == ADDNS_SCHUR_EXACT_BJ || o.schur == ADDNS_SCHUR_LEARNED) {
+      pc->smp_row.upload(pl.smp_row, s);
+      pc->smp_nb.upload(pl.smp_nb, s);
+      pc->smp_loc.upload(pl.smp_loc, s);
+      pc->learned_count = nsmp;
+    }
+    if (o.schur == ADDNS_SCHUR_EXACT_BJ) {  // keep G for learning targets S - G
+      pc->g_copy.alloc(sizeof(double) * pl.g_total);
+      ADDNS_HIP(hipMemcpyAsync(pc->g_copy.p, G, sizeof(double) * pl.g_total, hipMemcpyDeviceToDevice, s));
+    }
+    if (o.schur == ADDNS_SCHUR_LEARNED && nsmp > 0) {
+      // S_i ~ G_i + Delta_i: features of each separator velocity row, the
+      // network's corrections on G's stencil slots inside the aggregate
+      const int np = mlp_param_count();
+      DevBuf wts, X, Dl;
+      wts.alloc(sizeof(float) * np);
+      ADDNS_HIP(hipMemcpyAsync(wts.p, o.learned_model, sizeof(float) * np, hipMemcpyHostToDevice, s));
+      X.alloc(sizeof(float) * 7 * nsmp);
+      Dl.alloc(sizeof(float) * 5 * nsmp);
+      launch_dtn_features(nsmp, pc->smp_row.as<int32_t>(), pc->smp_nb.as<int32_t>(), pc->cp_rowptr.as<int32_t>(),
+                          pc->cp_colidx.as<int32_t>(), cpv, pc->perm.as<int32_t>(), pc->R.as<double>(),
+                          X.as<float>(), s);
+      launch_mlp_forward(wts.as<float>(), X.as<float>(), Dl.as<float>(), nsmp, o.learned_bf16 ? 1 : 0, s);
+      launch_dtn_correct(nsmp, pc->smp_loc.as<int64_t>(), Dl.as<float>(), G, s);
+      ADDNS_HIP(hipStreamSynchronize(s));
+    }
+    if (o.schur == ADDNS_SCHUR_EXACT_BJ) {
+      const int32_t np = (int32_t)pl.pair_sub.size();
+      DevBuf psub, pcol, poff, pptr, aggof, U, scratch;
+      psub.upload(pl.pair_sub, s);
+      pcol.upload(pl.pair_col, s);
+      poff.upload(pl.pair_off, s);
+      pptr.upload(pl.pcol_ptr, s);
+      aggof.upload(pl.agg_of, s);
+      U.alloc(sizeof(double) * std::max<int64_t>(pl.pair_total, 1));
+      scratch.alloc(sizeof(double) * std::max<int64_t>(pl.pair_total, 1));
+      launch_column_solves(pc, np, psub.as<int32_t>(), pcol.as<int32_t>(), poff.as<int64_t>(), scratch.as<double>(),
+                           U.as<double>(), s);
+      launch_exact_schur_update(pl.nsep, pptr.as<int32_t>(), psub.as<int32_t>(), poff.as<int64_t>(),
+                                pc->subs.as<SubInfo>(), aggof.as<int32_t>(), pc->agg_off.as<int32_t>(),
+                                g_off.as<int64_t>(), pc->f_rowptr.as<int32_t>(), pc->f_colidx.as<int32_t>(),
+                                pc->f_vals.as<double>(), U.as<double>(), G, s);
+      ADDNS_HIP(hipStreamSynchronize(s));
+    }
     if (o.schur == ADDNS_SCHUR_MSCN || o.schur == ADDNS_SCHUR_MSCN_LITERAL)
       launch_schur_blocks(k, pc->agg_s.as<int32_t>(), agg_d.as<int32_t>(), g_off.as<int64_t>(), dd_off.as<int64_t>(),
                           de_off.as<int64_t>(), df_off.as<int64_t>(), G, G + pl.g_total,
@@ -279,13 +302,12 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
   return guarded("addns_setup_precond", [&]() -> int {
     if (!p || !out || !d_rowptr || !d_colidx || !d_vals) throw ArgError("null argument");
     if (N != p->d.N) throw ArgError("N does not match the partition");
-    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1};
+    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1, 0};
     if (opts) o = *opts;
     if (o.schur < 0 || o.schur > ADDNS_SCHUR_LEARNED) throw ArgError("unknown schur mode");
     if (o.block_mult < 0 || o.block_mult > 4) throw ArgError("block_mult must be 0..4");
     const bool autotune = o.block_mult == 0;
-    if (o.schur == ADDNS_SCHUR_EXACT_BJ) throw ArgError("EXACT_BJ is an oracle-side reference mode");
-    if (o.schur == ADDNS_SCHUR_LEARNED) throw ArgError("LEARNED mode is not available in this build");
+    if (o.schur == ADDNS_SCHUR_LEARNED && !o.learned_model) throw ArgError("LEARNED mode needs learned_model");
     if (o.interior_prec != ADDNS_F64 && o.interior_prec != ADDNS_F32) throw ArgError("interior_prec");
     if (o.schur_prec < ADDNS_F64 || o.schur_prec > ADDNS_F16_SCALED) throw ArgError("schur_prec");
     if (o.schur == ADDNS_SCHUR_MSCN_LITERAL && p->d.n_int() < p->d.sep_size())
@@ -612,7 +634,7 @@ int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb
   if (nb_upper) *nb_upper = pc->plan.nbU;
   if (factor_bytes) *factor_bytes = pc->factor_bytes;
   if (bytes_apply) *bytes_apply = pc->bytes_apply;
-  if (learned_count) *learned_count = pc->plan.g_total;
+  if (learned_count) *learned_count = pc->learned_count;
   if (block_mult) *block_mult = pc->plan.block_mult;
   return ADDNS_OK;
 }

@@ -126,21 +126,29 @@ struct SweepArgs {
   const int32_t* e_colidx;
   const double* e_vals;
   double* ypad;      // padded intermediate (after the lower sweep)
+  // mode 2 (column solves): workgroup p solves A_jj^{-1} E(int_j, c), j = pair_sub[p],
+  // c = pair_col[p]; scratch and output at pair_off[p] (padded length of j)
+  const int32_t* pair_sub;
+  const int32_t* pair_col;
+  const int64_t* pair_off;
 };
 
-// One workgroup per subdomain.  second == 0: out[int] = D^{-1} yin[int].
-// second == 1: input u = E x2 (x2 = separator part, CSR E), and
-// out[int] = z1[int] - D^{-1} u.
+// One workgroup per subdomain.  mode 0: out[int] = D^{-1} yin[int].
+// mode 1: input u = E x2 (x2 = separator part, CSR E), and
+// out[int] = z1[int] - D^{-1} u.  mode 2: one workgroup per (subdomain,
+// separator column) pair, out[pair_off + row] = (A_jj^{-1} E(int_j, c))(row).
 //
 // Lower sweep, block b (window rows b*nbl .. b*nbl+W-1, W = nbl+kl):
 //   v = P_b w;  [x_b; c] = [inv(L11); L21 inv(L11)] v_top;  carry = v_bot - c
 // Upper sweep, block b (rows b*nbu ..):  x_b = inv(U_bb) (y_b - U_b,b+1 x_b+1)
 template <class T, int S>
 __global__ void __launch_bounds__(kSweepThreads)
-k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int second, const double* x2,
+k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int mode, const double* x2,
                  const double* z1) {
   extern __shared__ double smem[];
-  const SubInfo q = a.subs[blockIdx.x];
+  const SubInfo q = a.subs[mode == 2 ? a.pair_sub[blockIdx.x] : blockIdx.x];
+  const int32_t pcol = mode == 2 ? a.pair_col[blockIdx.x] : -1;
+  const int64_t poff = mode == 2 ? a.pair_off[blockIdx.x] : 0;
   const int32_t n = q.n, npad = q.npad;
   if (n == 0) return;
   const int32_t ioff = q.int_off, voff = q.vec_off;
@@ -151,12 +159,15 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int s
   double* t = wB + a.maxW;       // maxU
   double* xn = t + a.maxU;       // maxU
   double* part = xn + a.maxU;    // kWaves * max(maxW, maxU)
-  double* ypad = a.ypad + voff;
+  double* ypad = a.ypad + (mode == 2 ? poff : (int64_t)voff);
   auto input = [&](int32_t r) -> double {
     if (r >= n) return 0.0;
-    if (!second) return yin[ioff + r];
+    if (mode == 0) return yin[ioff + r];
     double s = 0.0;
-    for (int32_t e = a.e_rowptr[ioff + r]; e < a.e_rowptr[ioff + r + 1]; ++e) s += a.e_vals[e] * x2[a.e_colidx[e]];
+    for (int32_t e = a.e_rowptr[ioff + r]; e < a.e_rowptr[ioff + r + 1]; ++e) {
+      if (mode == 1) s += a.e_vals[e] * x2[a.e_colidx[e]];
+      else if (a.e_colidx[e] == pcol) s += a.e_vals[e];
+    }
     return s;
   };
   // ---- forward sweep over lower blocks
@@ -200,7 +211,8 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int s
       xn[r] = x;
       const int32_t row = b * nbU + r;
       if (row < n) {
-        if (second) out[ioff + row] = z1[ioff + row] - x;
+        if (mode == 1) out[ioff + row] = z1[ioff + row] - x;
+        else if (mode == 2) out[poff + row] = x;
         else out[ioff + row] = x;
       }
     }
@@ -268,32 +280,30 @@ size_t sweep_smem_bytes(int32_t maxW, int32_t maxU) {
 }
 
 template <class T, int S>
-static void launch_sweep(const SweepArgs& a, int m, size_t smem, const double* yin, double* out, int second,
+static void launch_sweep(const SweepArgs& a, int m, size_t smem, const double* yin, double* out, int mode,
                          const double* x2, const double* z1, hipStream_t s) {
   if (smem > 64 * 1024)
     ADDNS_HIP(hipFuncSetAttribute((const void*)k_interior_solve<T, S>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)smem));
-  k_interior_solve<T, S><<<m, kSweepThreads, smem, s>>>(a, yin, out, second, x2, z1);
+  k_interior_solve<T, S><<<m, kSweepThreads, smem, s>>>(a, yin, out, mode, x2, z1);
 }
 
 template <class T>
-static void dispatch_sweep(int S, const SweepArgs& a, int m, size_t smem, const double* yin, double* out, int second,
+static void dispatch_sweep(int S, const SweepArgs& a, int m, size_t smem, const double* yin, double* out, int mode,
                            const double* x2, const double* z1, hipStream_t s) {
   switch (S) {
-    case 1: launch_sweep<T, 1>(a, m, smem, yin, out, second, x2, z1, s); break;
-    case 2: launch_sweep<T, 2>(a, m, smem, yin, out, second, x2, z1, s); break;
-    case 3: launch_sweep<T, 3>(a, m, smem, yin, out, second, x2, z1, s); break;
-    case 4: launch_sweep<T, 4>(a, m, smem, yin, out, second, x2, z1, s); break;
-    case 5: launch_sweep<T, 5>(a, m, smem, yin, out, second, x2, z1, s); break;
+    case 1: launch_sweep<T, 1>(a, m, smem, yin, out, mode, x2, z1, s); break;
+    case 2: launch_sweep<T, 2>(a, m, smem, yin, out, mode, x2, z1, s); break;
+    case 3: launch_sweep<T, 3>(a, m, smem, yin, out, mode, x2, z1, s); break;
+    case 4: launch_sweep<T, 4>(a, m, smem, yin, out, mode, x2, z1, s); break;
+    case 5: launch_sweep<T, 5>(a, m, smem, yin, out, mode, x2, z1, s); break;
     default: throw ArgError("sweep row slots out of range");
   }
 }
 
-void launch_interior_solve(const addns_precond* pc, const double* yin, double* out, int second, const double* x2,
-                           const double* z1, hipStream_t s) {
+static SweepArgs sweep_args(const addns_precond* pc) {
   const Plan& pl = pc->plan;
-  if (pl.m == 0 || pl.n_int == 0) return;
-  SweepArgs a;
+  SweepArgs a{};
   a.maxW = pl.maxW;
   a.maxU = pl.nbU;
   a.subs = pc->subs.as<SubInfo>();
@@ -306,12 +316,37 @@ void launch_interior_solve(const addns_precond* pc, const double* yin, double* o
   a.e_rowptr = pc->e_rowptr.as<int32_t>();
   a.e_colidx = pc->e_colidx.as<int32_t>();
   a.e_vals = pc->e_vals.as<double>();
-  a.ypad = second ? pc->zpad.as<double>() : pc->ypad.as<double>();
+  return a;
+}
+
+static void run_sweep(const addns_precond* pc, const SweepArgs& a, int grid, const double* yin, double* out, int mode,
+                      const double* x2, const double* z1, hipStream_t s) {
+  const Plan& pl = pc->plan;
   const size_t smem = sweep_smem_bytes(pl.maxW, pl.nbU);
   if (smem > 160 * 1024) throw ArgError("interior bandwidth too large for the LDS-staged sweep");
   const int S = std::min(5, (std::max(pl.maxW, pl.nbU) + 63) / 64);
-  if (pc->interior_prec == P64) dispatch_sweep<double>(S, a, pl.m, smem, yin, out, second, x2, z1, s);
-  else dispatch_sweep<float>(S, a, pl.m, smem, yin, out, second, x2, z1, s);
+  if (pc->interior_prec == P64) dispatch_sweep<double>(S, a, grid, smem, yin, out, mode, x2, z1, s);
+  else dispatch_sweep<float>(S, a, grid, smem, yin, out, mode, x2, z1, s);
+}
+
+void launch_interior_solve(const addns_precond* pc, const double* yin, double* out, int second, const double* x2,
+                           const double* z1, hipStream_t s) {
+  const Plan& pl = pc->plan;
+  if (pl.m == 0 || pl.n_int == 0) return;
+  SweepArgs a = sweep_args(pc);
+  a.ypad = second ? pc->zpad.as<double>() : pc->ypad.as<double>();
+  run_sweep(pc, a, pl.m, yin, out, second ? 1 : 0, x2, z1, s);
+}
+
+void launch_column_solves(const addns_precond* pc, int32_t npairs, const int32_t* pair_sub, const int32_t* pair_col,
+                          const int64_t* pair_off, double* scratch, double* out, hipStream_t s) {
+  if (npairs == 0) return;
+  SweepArgs a = sweep_args(pc);
+  a.ypad = scratch;
+  a.pair_sub = pair_sub;
+  a.pair_col = pair_col;
+  a.pair_off = pair_off;
+  run_sweep(pc, a, npairs, nullptr, out, 2, nullptr, nullptr, s);
 }
 
 void launch_interface_solve(const addns_precond* pc, const double* y, const double* z1, double* out, hipStream_t s) {

@@ -518,10 +518,48 @@ k_invert_dense(const int32_t* __restrict__ agg_s, const int64_t* __restrict__ g_
 }
 
 
+// ---------------------------------------------------------------------------
+// Exact block-Jacobi interface blocks: S(agg_i, agg_i) = G_ii - sum_j F(agg_i,
+// int_j) A_jj^{-1} E(int_j, agg_i).  One workgroup per separator column c;
+// its (subdomain, column) solves U_p = A_jj^{-1} E(int_j, c) are applied in
+// ascending subdomain order (deterministic), rows of the aggregate in
+// parallel.
+// ---------------------------------------------------------------------------
+__global__ void k_exact_schur_update(const int32_t* __restrict__ pcol_ptr, const int32_t* __restrict__ pair_sub,
+                                     const int64_t* __restrict__ pair_off, const SubInfo* __restrict__ subs,
+                                     const int32_t* __restrict__ agg_of, const int32_t* __restrict__ agg_off,
+                                     const int64_t* __restrict__ g_off, const int32_t* __restrict__ f_rowptr,
+                                     const int32_t* __restrict__ f_colidx, const double* __restrict__ f_vals,
+                                     const double* __restrict__ U, double* __restrict__ S) {
+  const int32_t c = blockIdx.x;
+  const int32_t i = agg_of[c];
+  const int32_t a0 = agg_off[i], s = agg_off[i + 1] - a0, b = c - a0;
+  for (int32_t a = threadIdx.x; a < s; a += blockDim.x) {
+    double acc = 0.0;
+    for (int32_t p = pcol_ptr[c]; p < pcol_ptr[c + 1]; ++p) {
+      const SubInfo q = subs[pair_sub[p]];
+      const double* u = U + pair_off[p];
+      for (int32_t e = f_rowptr[a0 + a]; e < f_rowptr[a0 + a + 1]; ++e) {
+        const int32_t col = f_colidx[e] - q.int_off;
+        if (col >= 0 && col < q.n) acc += f_vals[e] * u[col];
+      }
+    }
+    S[g_off[i] + (int64_t)a * s + b] -= acc;
+  }
+}
+
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
 
+void launch_exact_schur_update(int32_t nsep, const int32_t* pcol_ptr, const int32_t* pair_sub, const int64_t* pair_off,
+                               const SubInfo* subs, const int32_t* agg_of, const int32_t* agg_off, const int64_t* g_off,
+                               const int32_t* f_rowptr, const int32_t* f_colidx, const double* f_vals,
+                               const double* U, double* S, hipStream_t s) {
+  if (nsep > 0)
+    k_exact_schur_update<<<nsep, 64, 0, s>>>(pcol_ptr, pair_sub, pair_off, subs, agg_of, agg_off, g_off, f_rowptr,
+                                             f_colidx, f_vals, U, S);
+}
 void launch_row_scale(const int32_t* rowptr, const double* vals, int32_t N, int scale, double* R, hipStream_t s) {
   if (N > 0) k_row_scale<<<nblocks(N, 256), 256, 0, s>>>(rowptr, vals, N, scale, R);
 }

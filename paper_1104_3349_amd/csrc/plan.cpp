@@ -3,6 +3,7 @@
 // the coupling blocks E and F, and the dense gather maps of the aggregate
 // blocks G_i, D_{r_i}, E_i, F_i (Algorithm 1).  No floating-point work.
 #include <algorithm>
+#include <cstdlib>
 #include <numeric>
 
 #include "precond.h"
@@ -156,8 +157,35 @@ void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult
     pl.f_rowptr[s + 1] = (int32_t)pl.f_colidx.size();
   }
 
+  // (subdomain, separator column) couplings for the exact interface blocks
+  pl.pair_sub.clear();
+  pl.pair_col.clear();
+  pl.pair_off.clear();
+  pl.pcol_ptr.assign(1, 0);
+  pl.pair_total = 0;
+  if (schur_mode == ADDNS_SCHUR_EXACT_BJ) {
+    std::vector<std::vector<int32_t>> subs_of_col(pl.nsep);
+    for (int32_t r = 0; r < pl.n_int; ++r)
+      for (int32_t t = pl.e_rowptr[r]; t < pl.e_rowptr[r + 1]; ++t) subs_of_col[pl.e_colidx[t]].push_back(sub_of[r]);
+    for (int32_t c = 0; c < pl.nsep; ++c) {
+      std::vector<int32_t>& v = subs_of_col[c];
+      std::sort(v.begin(), v.end());
+      v.erase(std::unique(v.begin(), v.end()), v.end());
+      for (int32_t j : v) {
+        pl.pair_sub.push_back(j);
+        pl.pair_col.push_back(c);
+        pl.pair_off.push_back(pl.pair_total);
+        pl.pair_total += pl.subs[j].npad;
+      }
+      pl.pcol_ptr.push_back((int32_t)pl.pair_sub.size());
+    }
+  }
+
   // dense aggregate blocks
   const int32_t k = pl.k;
+  pl.agg_of.assign(pl.nsep, 0);
+  for (int32_t i = 0; i < k; ++i)
+    for (int32_t c = P.agg_offsets[i]; c < P.agg_offsets[i + 1]; ++c) pl.agg_of[c] = i;
   pl.agg_off = P.agg_offsets;
   pl.agg_s.resize(k);
   pl.agg_d.resize(k);
@@ -184,6 +212,41 @@ void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult
     pl.de_off[i + 1] = pl.de_off[i] + d * s;
     pl.df_off[i + 1] = pl.df_off[i] + s * d;
     pl.sinv_off[i + 1] = pl.sinv_off[i] + s * s;
+  }
+  // learned-correction samples: separator velocity rows, five stencil slots
+  pl.smp_row.clear();
+  pl.smp_nb.clear();
+  pl.smp_loc.clear();
+  if (schur_mode == ADDNS_SCHUR_EXACT_BJ || schur_mode == ADDNS_SCHUR_LEARNED) {
+    for (int32_t c = 0; c < pl.nsep; ++c) {
+      const int32_t r = pl.n_int + c;
+      const int32_t g = pl.perm[r];
+      if (P.is_p[g]) continue;
+      // velocity neighbours in the original numbering, nearest first on each side
+      std::vector<std::pair<int32_t, int32_t>> lo, hi;  // (distance, permuted column)
+      for (int32_t t = rp[r]; t < rp[r + 1]; ++t) {
+        const int32_t o = pl.perm[ci[t]];
+        if (o == g || P.is_p[o]) continue;
+        (o < g ? lo : hi).emplace_back(std::abs(o - g), ci[t]);
+      }
+      std::sort(lo.begin(), lo.end());
+      std::sort(hi.begin(), hi.end());
+      int32_t nb[5] = {lo.size() > 1 ? lo[1].second : -1, lo.size() > 0 ? lo[0].second : -1, r,
+                       hi.size() > 0 ? hi[0].second : -1, hi.size() > 1 ? hi[1].second : -1};
+      const int32_t i = pl.agg_of[c];
+      const int32_t a = c - P.agg_offsets[i], s = pl.agg_s[i];
+      pl.smp_row.push_back(r);
+      for (int q = 0; q < 5; ++q) {
+        pl.smp_nb.push_back(nb[q]);
+        int64_t loc = -1;
+        if (nb[q] >= pl.n_int) {
+          const int32_t cc = nb[q] - pl.n_int;
+          if (cc >= P.agg_offsets[i] && cc < P.agg_offsets[i + 1])
+            loc = pl.g_off[i] + (int64_t)a * s + (cc - P.agg_offsets[i]);
+        }
+        pl.smp_loc.push_back(loc);
+      }
+    }
   }
   pl.g_total = pl.g_off[k];
   pl.dd_total = pl.dd_off[k];

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -115,6 +117,16 @@ struct Plan {
   std::vector<int64_t> dense_dst;                // scratch element index
   std::vector<int32_t> dense_src;                // C~p entry
   int64_t g_total = 0, dd_total = 0, de_total = 0, df_total = 0;
+  // exact block-Jacobi interface blocks: (subdomain, separator column) solves
+  std::vector<int32_t> agg_of;                   // per separator position
+  std::vector<int32_t> pair_sub, pair_col, pcol_ptr;
+  std::vector<int64_t> pair_off;
+  int64_t pair_total = 0;
+  // learned interface correction: one sample per separator velocity row;
+  // five stencil slots [far lower, near lower, diagonal, near upper, far upper]
+  std::vector<int32_t> smp_row;                  // permuted row index
+  std::vector<int32_t> smp_nb;                   // 5 per sample: permuted column or -1
+  std::vector<int64_t> smp_loc;                  // 5 per sample: element of the dense G/S block or -1
 };
 
 void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult);
@@ -145,6 +157,8 @@ struct addns_precond {
   int64_t factor_bytes = 0, bytes_apply = 0;
   int64_t learned_count = 0;
   float tuned_ms = 0.0f;                              // autotuner timing of the interior solve
+  addns::DevBuf g_copy;                               // G blocks before the update (EXACT_BJ: learning targets)
+  addns::DevBuf smp_row, smp_nb, smp_loc;             // learned-correction sample table
   // GMRES work space (grown on demand)
   addns::DevBuf V, Z, w, xp, bp, rp, Hd, gd, partials, scal;
   int gm_restart = 0;
@@ -179,6 +193,12 @@ void launch_invert_dense(int32_t k, const int32_t* agg_s, const int64_t* g_off, 
                          int prec, hipStream_t s);
 void launch_interior_solve(const addns_precond* pc, const double* yin, double* out, int second,
                            const double* x2, const double* z1, hipStream_t s);
+void launch_column_solves(const addns_precond* pc, int32_t npairs, const int32_t* pair_sub, const int32_t* pair_col,
+                          const int64_t* pair_off, double* scratch, double* out, hipStream_t s);
+void launch_exact_schur_update(int32_t nsep, const int32_t* pcol_ptr, const int32_t* pair_sub, const int64_t* pair_off,
+                               const SubInfo* subs, const int32_t* agg_of, const int32_t* agg_off, const int64_t* g_off,
+                               const int32_t* f_rowptr, const int32_t* f_colidx, const double* f_vals,
+                               const double* U, double* S, hipStream_t s);
 void launch_interface_solve(const addns_precond* pc, const double* y, const double* z1, double* x2out,
                             hipStream_t s);
 void launch_permute(const int32_t* perm, const double* in, double* out, int32_t n, int inverse,
@@ -223,4 +243,42 @@ void launch_seg_backsolve(double* state, int64_t st, const int32_t* jdone, int n
                           hipStream_t s);
 void launch_seg_combine(const double* Z, int64_t ldz, const double* state, int64_t st, const int32_t* jdone,
                         int32_t ldh, int32_t restart, const Chunk* ch, int nch, double* x, hipStream_t s);
+// learned interface correction (kernels_dtn.hip)
+int mlp_param_count();
+int mlp_grad_group();
+void launch_dtn_features(int64_t count, const int32_t* smp_row, const int32_t* smp_nb, const int32_t* rp,
+                         const int32_t* ci, const double* cv, const int32_t* perm, const double* R, float* X,
+                         hipStream_t s);
+void launch_dtn_targets(int64_t count, const int64_t* smp_loc, const double* S, const double* G, float* Y, float* M,
+                        hipStream_t s);
+void launch_dtn_correct(int64_t count, const int64_t* smp_loc, const float* D, double* G, hipStream_t s);
+void launch_mlp_forward(const float* wts, const float* X, float* P, int64_t count, int bf16, hipStream_t s);
+void launch_mlp_grad(const float* wts, const float* X, const float* Y, const float* M, const int32_t* idx,
+                     int64_t count, float scale, float* gpart, float* lpart, hipStream_t s);
+void launch_mlp_reduce_adam(const float* gpart, int nwg, float* grad, float* wts, float* m1, float* m2, int adam,
+                            float lr, float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
+
+// Runs an entry point's body, turning exceptions into status codes and a
+// thread-local message: no C++ exception crosses the C boundary.
+template <class F>
+int guarded(const char* what, F&& f) {
+  try {
+    return f();
+  } catch (const ArgError& e) {
+    set_error(std::string(what) + ": " + e.what());
+    return ADDNS_ERR_ARG;
+  } catch (const SingularError& e) {
+    set_error(std::string(what) + ": " + e.what());
+    return ADDNS_ERR_SINGULAR;
+  } catch (const HipError& e) {
+    set_error(std::string(what) + ": " + e.what());
+    return ADDNS_ERR_HIP;
+  } catch (const std::bad_alloc&) {
+    set_error(std::string(what) + ": out of host memory");
+    return ADDNS_ERR_NOMEM;
+  } catch (const std::exception& e) {
+    set_error(std::string(what) + ": " + e.what());
+    return ADDNS_ERR_HIP;
+  }
+}
 }  // namespace addns

@@ -7,11 +7,12 @@ from dataclasses import dataclass
 import numpy as np
 
 from oracle.partition import build_partition as oracle_partition
-from oracle.precond import LUM, MSCN, MSCN_LITERAL, Preconditioner
+from oracle.precond import EXACT_BJ, LUM, MSCN, MSCN_LITERAL, Preconditioner
 from paper_1104_3349_amd import addns
 from workloads.mac_oseen import Wind, make_oseen_mac
 
-ORACLE_MODE = {addns.SCHUR_MSCN: MSCN, addns.SCHUR_LUM: LUM, addns.SCHUR_MSCN_LITERAL: MSCN_LITERAL}
+ORACLE_MODE = {addns.SCHUR_MSCN: MSCN, addns.SCHUR_LUM: LUM, addns.SCHUR_MSCN_LITERAL: MSCN_LITERAL,
+               addns.SCHUR_EXACT_BJ: EXACT_BJ}
 
 
 @dataclass
@@ -37,14 +38,16 @@ def oracle_precond(S: System, schur=addns.SCHUR_MSCN):
     return Preconditioner(S.N, S.rp, S.ci, S.v, P, ORACLE_MODE[schur])
 
 
-def gpu_precond(S: System, schur=addns.SCHUR_MSCN, iprec=addns.F64, sprec=addns.F64):
+def gpu_precond(S: System, schur=addns.SCHUR_MSCN, iprec=addns.F64, sprec=addns.F64, part=None,
+                **kw):
     import torch
-    part = addns.build_partition(S.N, S.rp, S.ci, S.v, S.m, S.sz)
+    if part is None:
+        part = addns.build_partition(S.N, S.rp, S.ci, S.v, S.m, S.sz)
     d_rp = torch.from_numpy(S.rp).cuda()
     d_ci = torch.from_numpy(S.ci).cuda()
     d_v = torch.from_numpy(S.v).cuda()
     pc = addns.setup_precond(part, S.N, d_rp, d_ci, d_v, schur=schur, interior_prec=iprec,
-                             schur_prec=sprec)
+                             schur_prec=sprec, **kw)
     torch.cuda.synchronize()
     return part, pc
 

@@ -85,3 +85,21 @@ def test_partition_info_consistent():
     assert inf["N"] == meta["N"] and inf["m"] == 5
     assert inf["n_interior"] + inf["sep_size"] == meta["N"]
     assert A.int_offsets[-1] == inf["n_interior"] and A.agg_offsets[-1] == inf["sep_size"]
+
+
+def test_dtn_weights_file_roundtrip(tmp_path):
+    """Host-only weight file I/O of the learned correction (no device work)."""
+    n = addns.dtn_param_count()
+    assert n == 4997
+    w = np.random.default_rng(0).standard_normal(n).astype(np.float32)
+    path = str(tmp_path / "dtn.bin")
+    addns.dtn_save(path, w)
+    assert os.path.getsize(path) == 8 + 4 + 4 * n
+    assert np.array_equal(addns.dtn_load(path), w)
+    with open(path, "r+b") as f:
+        f.write(b"X")
+    with pytest.raises(addns.AddnsError) as e:
+        addns.dtn_load(path)
+    assert e.value.code == addns.ERR_ARG
+    with pytest.raises(addns.AddnsError):
+        addns.dtn_load(str(tmp_path / "missing.bin"))

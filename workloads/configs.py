@@ -63,3 +63,19 @@ def batched_workloads(count: int = 96, base_seed: int = 4000):
         out.append(Workload(f"batch{s}_n{n}", n, nu, None, m, 64, 50, True, 1e-8, base_seed + s,
                             F32, F32, w.c, w.s))
     return out
+
+
+def training_workloads(count: int = 2000, base_seed: int = 5000):
+    """Instances for the learned interface correction: 64 x 64 cells, nu
+    log-uniform in [1/1000, 1/20], a random combination of the four wind
+    modes scaled to max |w| = 2, a uniform grid or a geometric stretching of
+    ratio U(1.01, 1.08), m = 4 subdomains, aggregates of 64."""
+    out = []
+    for t in range(count):
+        rng = np.random.default_rng(base_seed + t)
+        nu = float(np.exp(rng.uniform(np.log(1 / 1000), np.log(1 / 20))))
+        w = Wind.random_modes(rng)
+        st = None if rng.random() < 0.5 else float(rng.uniform(1.01, 1.08))
+        out.append(Workload(f"train{t}", 64, nu, st, 4, 64, 50, True, 1e-8, base_seed + t,
+                            F32, F32, w.c, w.s))
+    return out
