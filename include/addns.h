@@ -222,7 +222,7 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
    pivots, coupling blocks, interface inverses, vector passes); block_mult
    is the sweep tile multiplier in use (chosen by the autotuner when the
    options asked for 0); learned_count is the number of learned-correction
-   samples (separator velocity rows) in EXACT_BJ and LEARNED modes, else 0. */
+   samples (separator velocity rows). */
 int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb_lower,
                        int32_t* nb_upper, int64_t* factor_bytes, int64_t* bytes_apply,
                        int64_t* learned_count, int32_t* block_mult);
@@ -236,31 +236,35 @@ int addns_precond_schur_blocks(addns_precond_t pc, double* h_out, int64_t count)
  * Learned interface correction -- an extension, not a method of the paper.
  * The exact interface Schur complement S = G - F D^-1 E (section 1; the
  * algebraic Dirichlet-to-Neumann map) is approximated blockwise by the MSCN
- * blocks of section 3.1.  Here a small network predicts, for each separator
- * velocity row, corrections on G's own stencil pattern:
+ * blocks of section 3.1: exact Schur complements of the local systems on
+ * the aggregates' D-ranges.  Here a small network predicts, for each
+ * separator velocity row, corrections on G's own stencil pattern,
  *   S_i ~ G_i + Delta_i,
- * trained on the diagonal blocks of the exact S (ADDNS_SCHUR_EXACT_BJ).
+ * trained on the blocks of a teacher mode (MSCN by default; EXACT_BJ, the
+ * diagonal blocks of the exact S, is also available):
  *   features (7, FP32): the five scaled stencil coefficients of the row in
  *     the slots [far lower, near lower, diagonal, near upper, far upper]
  *     (neighbours ordered by distance in the original numbering, velocity
  *     unknowns only) and the skew (convective) differences near and far;
  *   network: 7 -> 64 -> 64 -> 5, ReLU, row-major W1[64][7] b1[64] W2[64][64]
  *     b2[64] W3[5][64] b3[5];
- *   targets: S - G on the slots whose neighbour lies in the same aggregate
- *     (mask 1), else 0 (mask 0); loss (1/count) sum mask (p - y)^2.
- * Because a learned form is not exact, solves with it go through
- * addns_gmres_solve_judged, which accepts it only when the FP64 true residual
- * reaches the tolerance.
+ *   targets: S_i - G_i on the slots whose neighbour lies in the same
+ *     aggregate (mask 1), else 0 (mask 0); loss (1/count) sum mask (p - y)^2.
+ * The learned blocks are sparse where the teacher's are dense, so solves
+ * with them go through addns_gmres_solve_judged, which accepts them only
+ * when the FP64 true residual reaches the tolerance.
  * ====================================================================== */
 
 /* Number of FP32 network parameters (4997). */
 int addns_dtn_param_count(void);
 
-/* Training samples of an ADDNS_SCHUR_EXACT_BJ preconditioner, one per
-   separator velocity row, into DEVICE arrays X[count][7], Y[count][5],
-   M[count][5] (FP32).  With all three NULL only *count is set (a size
-   query; 0 unless the mode is EXACT_BJ or LEARNED).  cap: capacity in samples.  Asynchronous on
-   `stream`.  ADDNS_ERR_ARG if pc is not EXACT_BJ or cap < count. */
+/* Training samples of a preconditioner (the teacher: any mode except
+   LEARNED), one per separator velocity row, into DEVICE arrays X[count][7]
+   and, optionally together, Y[count][5] and M[count][5] (FP32); the
+   targets are S_i - G_i of the teacher's interface blocks.  With all three
+   NULL only *count is set (a size query).  cap: capacity in samples.
+   Asynchronous on `stream`.  ADDNS_ERR_ARG for a LEARNED handle, Y without
+   M (or M without Y), or cap < count. */
 int addns_dtn_samples(addns_precond_t pc, float* d_X, float* d_Y, float* d_M, int64_t cap,
                       int64_t* count, void* stream);
 

@@ -9,8 +9,10 @@ S = G - F D^{-1} E (section 1; the algebraic Dirichlet-to-Neumann map) by the
 block diagonal Shat of mini Schur complements (section 3.1, Algorithm 1).
 The extension learns a correction of G_i instead:  S_i ~ G_i + Delta_i, with
 Delta_i on G's own stencil pattern, predicted per separator velocity row by
-a small network and trained on the diagonal blocks of the exact S (the
-EXACT_BJ blocks of oracle.precond).  Everything here is plain FP64 numpy.
+a small network and trained on the interface blocks of a teacher mode of
+oracle.precond (MSCN, whose blocks are exact Schur complements of the local
+D-range systems, or EXACT_BJ, the diagonal blocks of the exact S).
+Everything here is plain FP64 numpy.
 
 Samples.  One per separator position c (permuted order) whose node g is a
 velocity unknown (not pressure-like).  Its velocity neighbours o != g in
@@ -21,8 +23,8 @@ sorted by |o - g|, fill five slots
     x_q = C~(g, o_q)                         q = 0..4 (0 for empty slots)
     k_q = R_g (C(g, o_q) - C(o_q, g)) / 2    (skew, convective part)
     x_5 = k_3 - k_1,  x_6 = k_4 - k_0.
-Targets: y_q = S_i(g, o_q) - G_i(g, o_q) when o_q is a separator node of the
-same aggregate i (mask 1), else 0 (mask 0).
+Targets: y_q = S_i(g, o_q) - G_i(g, o_q), S_i the teacher's block, when o_q
+is a separator node of the same aggregate i (mask 1), else 0 (mask 0).
 
 Network: 7 -> 64 -> 64 -> 5 with ReLU, parameters packed as
 W1[64][7] b1[64] W2[64][64] b2[64] W3[5][64] b3[5] (4997 numbers).
@@ -115,8 +117,8 @@ class Samples:
 
 
 def samples(pre, with_targets=True):
-    """Samples of an oracle Preconditioner.  Targets need pre.mode EXACT_BJ
-    (its S_blocks are the diagonal blocks of the exact S)."""
+    """Samples of an oracle Preconditioner; the targets come from its
+    S_blocks (the teacher mode it was built with)."""
     part = pre.part
     C = pre.C.tocsr()                # row-scaled C~
     R = pre.R

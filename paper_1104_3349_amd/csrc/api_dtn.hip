@@ -51,14 +51,20 @@ int addns_dtn_samples(addns_precond_t pc, float* d_X, float* d_Y, float* d_M, in
     const int64_t n = (int64_t)pc->plan.smp_row.size();
     *count = n;
     if (!d_X && !d_Y && !d_M) return ADDNS_OK;  // size query
-    if (pc->schur_mode != ADDNS_SCHUR_EXACT_BJ) throw ArgError("samples need an EXACT_BJ preconditioner");
+    if (pc->schur_mode == ADDNS_SCHUR_LEARNED) throw ArgError("a LEARNED preconditioner has no teacher blocks");
+    if ((d_Y == nullptr) != (d_M == nullptr)) throw ArgError("Y and M go together");
     if (cap < n) throw ArgError("capacity smaller than the sample count");
     hipStream_t s = as_stream(stream);
+    if (n > 0 && !pc->smp_row.p) {  // sample table uploaded on first use
+      pc->smp_row.upload(pc->plan.smp_row, s);
+      pc->smp_nb.upload(pc->plan.smp_nb, s);
+      pc->smp_loc.upload(pc->plan.smp_loc, s);
+    }
     if (d_X)
       launch_dtn_features(n, pc->smp_row.as<int32_t>(), pc->smp_nb.as<int32_t>(), pc->cp_rowptr.as<int32_t>(),
                           pc->cp_colidx.as<int32_t>(), pc->cp_vals.as<double>(), pc->perm.as<int32_t>(),
                           pc->R.as<double>(), d_X, s);
-    if (d_Y && d_M)
+    if (d_Y)
       launch_dtn_targets(n, pc->smp_loc.as<int64_t>(), pc->schur_S.as<double>(), pc->g_copy.as<double>(), d_Y, d_M, s);
     ADDNS_HIP(hipGetLastError());
     return ADDNS_OK;

@@ -131,13 +131,12 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
     df_off.upload(pl.df_off, s);
     double* G = dense.as<double>();
     const int64_t nsmp = (int64_t)pl.smp_row.size();
-    if (o.schur == ADDNS_SCHUR_EXACT_BJ || o.schur == ADDNS_SCHUR_LEARNED) {
+    pc->learned_count = nsmp;
+    if (o.schur == ADDNS_SCHUR_LEARNED) {
       pc->smp_row.upload(pl.smp_row, s);
       pc->smp_nb.upload(pl.smp_nb, s);
       pc->smp_loc.upload(pl.smp_loc, s);
-      pc->learned_count = nsmp;
-    }
-    if (o.schur == ADDNS_SCHUR_EXACT_BJ) {  // keep G for learning targets S - G
+    } else {  // keep G: learning targets are S_i - G_i of this (teacher) mode
       pc->g_copy.alloc(sizeof(double) * pl.g_total);
       ADDNS_HIP(hipMemcpyAsync(pc->g_copy.p, G, sizeof(double) * pl.g_total, hipMemcpyDeviceToDevice, s));
     }

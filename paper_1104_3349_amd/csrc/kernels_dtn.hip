@@ -1,7 +1,7 @@
 // Learned interface correction (an extension, not a method of the paper):
 // a small MLP maps local stencil features of a separator velocity row to
-// corrections of that row of G_i on G's own pattern, trained on the exact
-// block-Jacobi interface blocks that the library computes.
+// corrections of that row of G_i on G's own pattern, trained on interface
+// blocks S_i that the library computes (a teacher mode, MSCN by default).
 //
 //   features (7): the five scaled stencil coefficients of the row in the slots
 //     [far lower, near lower, diagonal, near upper, far upper] and the two

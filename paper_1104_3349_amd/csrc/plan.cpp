@@ -217,7 +217,7 @@ void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult
   pl.smp_row.clear();
   pl.smp_nb.clear();
   pl.smp_loc.clear();
-  if (schur_mode == ADDNS_SCHUR_EXACT_BJ || schur_mode == ADDNS_SCHUR_LEARNED) {
+  {
     for (int32_t c = 0; c < pl.nsep; ++c) {
       const int32_t r = pl.n_int + c;
       const int32_t g = pl.perm[r];

@@ -79,12 +79,13 @@ def _gpu_samples(pc):
     return X, Y, M
 
 
-@pytest.mark.parametrize("stretch,nu", [(None, 0.05), (1.05, 0.002)])
-def test_samples_match_oracle(stretch, nu):
+@pytest.mark.parametrize("stretch,nu,teacher", [(None, 0.05, addns.SCHUR_MSCN), (1.05, 0.002, addns.SCHUR_MSCN),
+                                                (1.05, 0.002, addns.SCHUR_EXACT_BJ)])
+def test_samples_match_oracle(stretch, nu, teacher):
     S = _system(n=32, nu=nu, m=4, sz=24, stretch=stretch)
-    ora = oracle_precond(S, addns.SCHUR_EXACT_BJ)
+    ora = oracle_precond(S, teacher)
     smp = mlp.samples(ora)
-    part, pc = gpu_precond(S, addns.SCHUR_EXACT_BJ)
+    part, pc = gpu_precond(S, teacher)
     X, Y, M = _gpu_samples(pc)
     X, Y, M = X.cpu().numpy(), Y.cpu().numpy(), M.cpu().numpy()
     assert X.shape[0] == len(smp.rows) > 0
@@ -96,7 +97,7 @@ def test_samples_match_oracle(stretch, nu):
 
 def _oracle_data(seed=3):
     S = _system(n=40, nu=0.01, m=4, sz=24, stretch=1.05, seed=seed)
-    ora = oracle_precond(S, addns.SCHUR_EXACT_BJ)
+    ora = oracle_precond(S, addns.SCHUR_MSCN)
     return S, ora, mlp.samples(ora)
 
 
@@ -138,7 +139,7 @@ def test_gradient_matches_oracle_backprop():
 
 def test_training_deterministic_and_descends():
     S = _system(n=32, nu=0.01, m=4, sz=24)
-    part, pc = gpu_precond(S, addns.SCHUR_EXACT_BJ)
+    part, pc = gpu_precond(S, addns.SCHUR_MSCN)
     X, Y, M = _gpu_samples(pc)
     w1, l1 = addns.dtn_train(X, Y, M, epochs=8, batch=64, lr=3e-3, seed=9)
     w2, l2 = addns.dtn_train(X, Y, M, epochs=8, batch=64, lr=3e-3, seed=9)
@@ -209,17 +210,19 @@ def test_judged_solve_accepts_and_falls_back():
 def test_learned_argument_errors():
     S = _system(n=16, m=4, sz=16)
     with pytest.raises(addns.AddnsError) as e:
-        gpu_precond(S, addns.SCHUR_LEARNED)
+        gpu_precond(S, addns.SCHUR_LEARNED)  # no model
     assert e.value.code == addns.ERR_ARG
-    part, pc = gpu_precond(S, addns.SCHUR_MSCN)
-    assert addns.dtn_samples(pc) == 0  # no sample table outside EXACT_BJ / LEARNED
-    X = torch.zeros((8, 7), dtype=torch.float32, device="cuda")
-    with pytest.raises(addns.AddnsError):
-        addns.dtn_samples(pc, X, X, X)  # not EXACT_BJ
-    part, pe = gpu_precond(S, addns.SCHUR_EXACT_BJ)
-    n = addns.dtn_samples(pe)
+    zero = np.zeros(mlp.N_PARAM, np.float32)
+    part, pl = gpu_precond(S, addns.SCHUR_LEARNED, learned_model=zero)
+    n = addns.dtn_samples(pl)  # a size query works on any handle
     assert n > 1
+    X = torch.zeros((n, 7), dtype=torch.float32, device="cuda")
+    with pytest.raises(addns.AddnsError):
+        addns.dtn_samples(pl, X, X, X)  # a LEARNED handle has no teacher blocks
+    part, pe = gpu_precond(S, addns.SCHUR_MSCN)
     small = torch.zeros((n - 1, 7), dtype=torch.float32, device="cuda")
     with pytest.raises(addns.AddnsError) as e:
         addns.dtn_samples(pe, small, small, small)  # capacity too small
     assert e.value.code == addns.ERR_ARG
+    with pytest.raises(addns.AddnsError):
+        addns.dtn_samples(pe, X, X, None)  # targets without masks
