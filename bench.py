@@ -163,6 +163,64 @@ def bench_batched(args):
         "sequential_iters_max": max(seq_its), "speedup_vs_sequential": round(T_seq / T, 2)}))
 
 
+def bench_learned(args):
+    """Learned interface correction: samples from 2000 seeded 64 x 64 systems
+    (MSCN teacher), GPU training, then the judged FGMRES(50) on the 512 x 512
+    stretched cavity (nu = 1/500, 256 subdomains) against plain MSCN, and
+    on a held-out 64 x 64 system of the training distribution's kind."""
+    import numpy as np
+    import torch
+
+    from paper_1104_3349_amd import addns, learned
+    from workloads.configs import CFG5, F32, Workload, training_workloads
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    X, Y, M = learned.collect_samples(training_workloads(2000), 100)
+    t1 = time.perf_counter()
+    w, loss = addns.dtn_train(X, Y, M, epochs=30, batch=1024, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    held = Workload("uniform64_nu0.002_m4_heldout", 64, 1 / 500, None, 4, 64, 50, True, 1e-8, 78, F32, F32)
+    out = {}
+    for wl, maxit in ((held, 5000), (CFG5, args.learned_maxit)):
+        rp, ci, v, b, meta = wl.build()
+        N = meta["N"]
+        part = addns.build_partition(N, rp, ci, v, wl.m, wl.sz)
+        d = [torch.from_numpy(a).to(dev) for a in (rp, ci, v)]
+        d_b = torch.from_numpy(b).to(dev)
+        d_x = torch.zeros(N, dtype=torch.float64, device=dev)
+        res = {}
+        for name, kw in (("mscn", dict(schur=addns.SCHUR_MSCN)), ("lum", dict(schur=addns.SCHUR_LUM)),
+                         ("learned_bf16", dict(schur=addns.SCHUR_LEARNED, learned_model=w,
+                                               learned_bf16=True))):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            pc = addns.setup_precond(part, N, *d, interior_prec=F32, schur_prec=F32, block_mult=1, **kw)
+            d_x.zero_()
+            if name == "learned_bf16":
+                plain = addns.setup_precond(part, N, *d, interior_prec=F32, schur_prec=F32, block_mult=1)
+                r = addns.gmres_solve_judged(pc, plain, d_b, d_x, restart=wl.restart, maxit=maxit, tol=wl.tol)
+            else:
+                r = addns.gmres_solve(pc, d_b, d_x, restart=wl.restart, maxit=maxit, tol=wl.tol)
+            torch.cuda.synchronize()
+            res[name] = {"seconds": round(time.perf_counter() - ts, 4), "iters": r["iters"],
+                         "converged": r["converged"], "true_relres": r["true_relres"]}
+            if "accepted" in r:
+                res[name]["accepted"] = r["accepted"]
+        out[wl.name] = res
+    e = out[CFG5.name]["learned_bf16"]
+    print(json.dumps({
+        "metric": "time to 1e-8 rel. residual (s) + precond-apply GB/s; plain FP64 vs mixed/learned",
+        "value": e["seconds"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(e["seconds"] * 1e3, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 outer / f32 factors / bf16 network", "data": "synthetic",
+        "config": {"workload": "learned512", "eval": CFG5.name, "train_systems": 2000,
+                   "train_rows": int(X.shape[0]), "krylov": "FGMRES(50)", "maxit": args.learned_maxit},
+        "data_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
+        "loss_first": float(loss[0]), "loss_last": float(loss[-1]), "results": out}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,9 +232,11 @@ def main():
                     help="only the dominant kernel (interior solve) x reps, plus a 256 MiB device "
                          "copy of known size to calibrate memory counters")
     ap.add_argument("--reps", type=int, default=20)
-    ap.add_argument("--workload", default="cavity128", choices=["cavity128", "batched96"],
+    ap.add_argument("--workload", default="cavity128", choices=["cavity128", "batched96", "learned512"],
                     help="cavity128: the headline single system; batched96: 96 independent "
-                         "systems solved together (reported separately)")
+                         "systems solved together; learned512: train the interface network and "
+                         "judge it on the 512 x 512 stretched cavity (both reported separately)")
+    ap.add_argument("--learned-maxit", type=int, default=1000)
     ap.add_argument("--block-mult", type=int, default=None,
                     help="sweep tile multiplier; 0 = autotune (default for batched96), 1 = the "
                          "autotuner's choice for cavity128 (default there)")
@@ -192,6 +252,8 @@ def main():
     from paper_1104_3349_amd import addns
     from workloads.configs import CFG2 as cfg
 
+    if args.workload == "learned512":
+        return bench_learned(args)
     if args.workload == "batched96":
         if args.block_mult is None:
             args.block_mult = 0

@@ -91,9 +91,16 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
         throw SingularError("interior block " + std::to_string(j) + " has a zero pivot at column " +
                             std::to_string(h_info[j] - 1));
     pc->lperm.alloc(sizeof(int32_t) * pl.lperm_total);
-    pc->lmat.alloc((int64_t)fb * pl.lmat_total);
-    pc->uinv.alloc((int64_t)fb * pl.u_total);
-    pc->u12.alloc((int64_t)fb * pl.u_total);
+    // the sweep's last row slot may read up to 64 * 5 rows past a block's
+    // end; the zeroed tail keeps that overrun inside the allocation
+    const int64_t tail = kSweepOverrunBytes;
+    pc->lmat.alloc((int64_t)fb * pl.lmat_total + tail);
+    pc->uinv.alloc((int64_t)fb * pl.u_total + tail);
+    pc->u12.alloc((int64_t)fb * pl.u_total + tail);
+    for (DevBuf* d : {&pc->lmat, &pc->uinv, &pc->u12})
+      ADDNS_HIP(hipMemsetAsync(static_cast<char*>(d->p) + d->bytes - tail, 0, tail, s));
+    pc->zeros.alloc(512);
+    ADDNS_HIP(hipMemsetAsync(pc->zeros.p, 0, 512, s));
     work.alloc(sizeof(double) * std::max(pl.lwork_total, pl.u_total));
     launch_convert_lower(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), pc->lblks.as<LBlk>(), nL,
                          work.as<double>(), pc->lperm.as<int32_t>(), pc->lmat.p, iprec, s);

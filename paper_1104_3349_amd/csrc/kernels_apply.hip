@@ -58,53 +58,143 @@ __device__ inline double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
 
-template <class T, int S, int kind>
-__device__ inline int gemv_cols(const T* __restrict__ M, int R, int K, int par, const double* vin,
-                                const int32_t* __restrict__ gidx, double* part) {
-  constexpr int CB = (sizeof(T) == 4 && S <= 6) ? 8 : 4;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  // waves = RG row groups (64 S rows each) x CG column groups
+// Column chunk of one wave: CB columns x S row slots of a block, plus the
+// window-gather indices of those columns (lower sweep only).  Register
+// resident; a wave keeps two chunks so that the loads of the next chunk (or
+// of the next block, across the barriers of a step) are in flight while the
+// current one is consumed.
+template <class T>
+constexpr int chunk_cols(int S) {
+  // the widest chunks whose two copies fit in the registers of 1024 threads
+  return sizeof(T) == 4 ? (S <= 2 ? 12 : (S == 3 ? 9 : (S == 4 ? 7 : 5)))
+                        : (S <= 2 ? 4 : (S == 3 ? 3 : 2));
+}
+
+template <class T, int S>
+struct Chunk {
+  static constexpr int CB = chunk_cols<T>(S);
+  T v[CB][S];
+  int32_t gi[CB];
+};
+
+// Geometry of one wave in a GEMV with R rows and K columns: waves form RG
+// row groups (64 S rows each) x CG column groups; this wave owns the rows
+// r0 + 64 s + lane and the columns [kb, ke).  The same for every block of a
+// sweep, so it is computed once per sweep.
+struct Geo {
+  int R, K, CG, cg, kb, ke, r0;
+  bool act;
+};
+
+template <int S>
+__device__ __attribute__((always_inline)) inline Geo make_geo(int R, int K) {
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  Geo g;
+  g.R = R;
+  g.K = K;
   const int RG = (R + 64 * S - 1) / (64 * S);
-  const int CG = max(1, kWaves / RG);
-  const uint32_t nbytes = (uint32_t)R * (uint32_t)K * (uint32_t)sizeof(T);
-  if (w < RG * CG) {
-    const int rg = w % RG, cg = w / RG;
-    const int kb = K * cg / CG, ke = K * (cg + 1) / CG;
-    const int r0 = rg * 64 * S;
-    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(M, nbytes);
+  g.CG = max(1, kWaves / RG);
+  g.act = w < RG * g.CG;
+  const int rg = w % RG;
+  g.cg = w / RG;
+  g.kb = K * g.cg / g.CG;
+  g.ke = K * (g.cg + 1) / g.CG;
+  g.r0 = rg * 64 * S;
+  return g;
+}
+
+// Loads columns k0 .. k0+CB-1 of M (column-major, leading dimension R).
+// The blocks store their structural zeros, so no per-lane mask is needed:
+// every load is a wave-uniform base (scalar registers) plus the lane's row,
+// one vector register shared by all loads.  With FP64 factors a row slot
+// that lies wholly in a column's zero part reads a small zeroed buffer
+// instead (a uniform choice of base; the loaded value is used as is, so no
+// load is waited for early); with FP32 factors the bytes saved are worth
+// less than the scalar work and the narrower chunks, and every slot is read:
+//   kind 2: upper        M(r,k) = 0 for r > k
+//   kind 3: band-shifted M(r,k) = 0 for r < k - par
+//   kind 4: [lower; full] M(r,k) = 0 for r < min(k, par)
+// The last slot may run past row R - 1 (at most 64 S - 1 rows): those
+// products land in rows that are never stored, and every factor allocation
+// is padded so that the overrun stays inside it.  Columns past the wave's
+// range repeat its last column (their vector weight is 0).
+template <class T, int S, int kind>
+__device__ __attribute__((always_inline)) inline void load_chunk(Chunk<T, S>& c, const Geo& g, const T* M, int par,
+                                                                 const int32_t* gidx, const T* zeros, int k0) {
+  constexpr int CB = Chunk<T, S>::CB;
+  const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const int k = __builtin_amdgcn_readfirstlane(min(k0 + j, g.ke - 1));
+    const T* col = M + (int64_t)k * g.R;
+    const int hi = kind == 2 ? min(g.R, k + 1) : g.R;  // rows [lo, hi) may be nonzero
+    const int lo = kind == 3 ? max(0, k - par) : (kind == 4 ? min(k, par) : 0);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if constexpr (sizeof(T) == 4) {
+        c.v[j][s] = col[(uint32_t)g.r0 + lane + 64u * s];
+      } else {
+        const int rs0 = __builtin_amdgcn_readfirstlane(g.r0 + 64 * s);
+        const T* base = (rs0 < hi && rs0 + 64 > lo) ? col + rs0 : zeros;
+        c.v[j][s] = base[lane];
+      }
+    }
+    if (gidx) c.gi[j] = gidx[k];
+  }
+}
+
+template <class T, int S>
+__device__ __attribute__((always_inline)) inline void fma_chunk(const Chunk<T, S>& c, const Geo& g, int k0, const double* vin, bool gather,
+                                 double (&acc)[S]) {
+  constexpr int CB = Chunk<T, S>::CB;
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const int k = k0 + j;
+    const double vk = k < g.ke ? vin[gather ? c.gi[j] : k] : 0.0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] += (double)c.v[j][s] * vk;
+  }
+}
+
+// Issues the first two chunks of a GEMV (the rest follow inside run_gemv).
+template <class T, int S, int kind>
+__device__ __attribute__((always_inline)) inline void prefetch_gemv(Chunk<T, S>& A, Chunk<T, S>& B, const Geo& g, const T* M, int par,
+                                     const int32_t* gidx, const T* zeros) {
+  constexpr int CB = Chunk<T, S>::CB;
+  if (!g.act) return;
+  load_chunk<T, S, kind>(A, g, M, par, gidx, zeros, g.kb);
+  if (g.kb + CB < g.ke) load_chunk<T, S, kind>(B, g, M, par, gidx, zeros, g.kb + CB);
+}
+
+// part[cg * R + r] = sum over the wave's columns of M(r, k) vec(k); A and B
+// hold the first two chunks (prefetch_gemv), later chunks are loaded two
+// ahead of their use.  The caller synchronises and reduces over the CG
+// column groups in a fixed order.
+template <class T, int S, int kind>
+__device__ __attribute__((always_inline)) inline int run_gemv(Chunk<T, S>& A, Chunk<T, S>& B, const Geo& g, const T* M, int par,
+                               const int32_t* gidx, const T* zeros, const double* vin, double* part) {
+  constexpr int CB = Chunk<T, S>::CB;
+  if (g.act) {
     double acc[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) acc[s] = 0.0;
-    for (int k0 = kb; k0 < ke; k0 += CB) {
-      T vals[CB][S];
-#pragma unroll
-      for (int c = 0; c < CB; ++c) {
-        const int k = k0 + c;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const int r = r0 + 64 * s + lane;
-          bool ok = k < ke && r < R;
-          if constexpr (kind == 2) ok = ok && k >= r;
-          else if constexpr (kind == 3) ok = ok && k <= r + par;
-          else if constexpr (kind == 4) ok = ok && (r >= par || k <= r);
-          vals[c][s] = buf_load<T>(rsrc, ok ? (uint32_t)(k * R + r) * (uint32_t)sizeof(T) : nbytes);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < CB; ++c) {
-        const int k = k0 + c;
-        const double vk = k < ke ? (gidx ? vin[gidx[k]] : vin[k]) : 0.0;
-#pragma unroll
-        for (int s = 0; s < S; ++s) acc[s] += (double)vals[c][s] * vk;
+    const bool gather = gidx != nullptr;
+    for (int k0 = g.kb; k0 < g.ke; k0 += 2 * CB) {
+      fma_chunk<T, S>(A, g, k0, vin, gather, acc);
+      if (k0 + 2 * CB < g.ke) load_chunk<T, S, kind>(A, g, M, par, gidx, zeros, k0 + 2 * CB);
+      if (k0 + CB < g.ke) {
+        fma_chunk<T, S>(B, g, k0 + CB, vin, gather, acc);
+        if (k0 + 3 * CB < g.ke) load_chunk<T, S, kind>(B, g, M, par, gidx, zeros, k0 + 3 * CB);
       }
     }
+    const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const int r = r0 + 64 * s + lane;
-      if (r < R) part[cg * R + r] = acc[s];
+      const int r = g.r0 + 64 * s + lane;
+      if (r < g.R) part[g.cg * g.R + r] = acc[s];
     }
   }
-  return CG;
+  return g.CG;
 }
 
 __device__ inline double sum_parts(const double* part, int R, int CG, int r) {
@@ -131,6 +221,7 @@ struct SweepArgs {
   const int32_t* pair_sub;
   const int32_t* pair_col;
   const int64_t* pair_off;
+  const void* zeros;  // at least 64 zeroed FP64 words
 };
 
 // One workgroup per subdomain.  mode 0: out[int] = D^{-1} yin[int].
@@ -141,6 +232,12 @@ struct SweepArgs {
 // Lower sweep, block b (window rows b*nbl .. b*nbl+W-1, W = nbl+kl):
 //   v = P_b w;  [x_b; c] = [inv(L11); L21 inv(L11)] v_top;  carry = v_bot - c
 // Upper sweep, block b (rows b*nbu ..):  x_b = inv(U_bb) (y_b - U_b,b+1 x_b+1)
+//
+// The block matrices do not depend on the data, so the loads of the next
+// GEMV's first chunks are issued before the barriers and reductions of the
+// current step, and the next step's input rows are fetched before the
+// current GEMV: the sweep waits for memory once per step at most, not once
+// per chunk.
 template <class T, int S>
 __global__ void __launch_bounds__(kSweepThreads)
 k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int mode, const double* x2,
@@ -160,56 +257,77 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
   double* xn = t + a.maxU;       // maxU
   double* part = xn + a.maxU;    // kWaves * max(maxW, maxU)
   double* ypad = a.ypad + (mode == 2 ? poff : (int64_t)voff);
-  auto input = [&](int32_t r) -> double {
-    if (r >= n) return 0.0;
-    if (mode == 0) return yin[ioff + r];
-    double s = 0.0;
-    for (int32_t e = a.e_rowptr[ioff + r]; e < a.e_rowptr[ioff + r + 1]; ++e) {
-      if (mode == 1) s += a.e_vals[e] * x2[a.e_colidx[e]];
-      else if (a.e_colidx[e] == pcol) s += a.e_vals[e];
+  const T* lmat = (const T*)a.lmat + q.lmat_off;
+  const T* uinv = (const T*)a.uinv + q.u_off;
+  const T* u12 = (const T*)a.u12 + q.u_off;
+  const int32_t* lperm = a.lperm + q.lperm_off;
+  const T* zeros = (const T*)a.zeros;
+  const int32_t nL = npad / nbL, nU = npad / nbU;
+  const Geo gl = make_geo<S>(W, nbL);
+  const Geo gu = make_geo<S>(nbU, nbU);
+  Chunk<T, S> A, B;
+  // first GEMV of the sweep in flight while the input is prepared
+  if (nL > 0) prefetch_gemv<T, S, 4>(A, B, gl, lmat, nbL, lperm, zeros);
+  // modes 1 and 2: the sweep input (E x2, or column pcol of E) into ypad;
+  // the lower sweep writes ypad only below the rows it still has to read
+  if (mode != 0) {
+    for (int32_t r = tid; r < n; r += blockDim.x) {
+      double s = 0.0;
+      for (int32_t e = a.e_rowptr[ioff + r]; e < a.e_rowptr[ioff + r + 1]; ++e) {
+        if (mode == 1) s += a.e_vals[e] * x2[a.e_colidx[e]];
+        else if (a.e_colidx[e] == pcol) s += a.e_vals[e];
+      }
+      ypad[r] = s;
     }
-    return s;
-  };
+    __syncthreads();
+  }
+  const double* src = mode == 0 ? yin + ioff : ypad;
   // ---- forward sweep over lower blocks
   double* wc = wA;
   double* wn = wB;
-  for (int32_t r = tid; r < W; r += blockDim.x) wc[r] = input(r);
+  for (int32_t r = tid; r < W; r += blockDim.x) wc[r] = r < n ? src[r] : 0.0;
   __syncthreads();
-  const int32_t nL = npad / nbL;
   for (int32_t b = 0; b < nL; ++b) {
-    const int32_t* idx = a.lperm + q.lperm_off + (int64_t)b * W;
-    const int CG = gemv_cols<T, S, 4>((const T*)a.lmat + q.lmat_off + (int64_t)b * W * nbL, W, nbL, nbL, wc, idx,
-                                      part);
+    const int32_t* idx = lperm + (int64_t)b * W;
+    const T* M = lmat + (int64_t)b * W * nbL;
+    // next window's new rows, fetched before this step's GEMV
+    const int32_t rin = (b + 1) * nbL + KL + tid;
+    const double nin = (tid < nbL && rin < n) ? src[rin] : 0.0;
+    const int CG = run_gemv<T, S, 4>(A, B, gl, M, nbL, idx, zeros, wc, part);
+    if (b + 1 < nL) prefetch_gemv<T, S, 4>(A, B, gl, M + (int64_t)W * nbL, nbL, idx + W, zeros);
+    else if (nU > 0) prefetch_gemv<T, S, 2>(A, B, gu, uinv + (int64_t)(nU - 1) * nbU * nbU, 0, nullptr, zeros);
     __syncthreads();
     for (int32_t r = tid; r < W; r += blockDim.x) {
       const double v = sum_parts(part, W, CG, r);
       if (r < nbL) ypad[b * nbL + r] = v;
       else wn[r - nbL] = wc[idx[r]] - v;
     }
-    for (int32_t r = tid; r < nbL; r += blockDim.x) wn[KL + r] = input((b + 1) * nbL + KL + r);
+    if (tid < nbL) wn[KL + tid] = nin;
     __syncthreads();
     double* tmp = wc;
     wc = wn;
     wn = tmp;
   }
   // ---- backward sweep over upper blocks
-  const int32_t nU = npad / nbU;
   for (int32_t b = nU - 1; b >= 0; --b) {
-    const int64_t uoff = q.u_off + (int64_t)b * nbU * nbU;
+    const int64_t uoff = (int64_t)b * nbU * nbU;
+    const double yb = tid < nbU ? ypad[b * nbU + tid] : 0.0;
     if (b < nU - 1) {
-      const int CG = gemv_cols<T, S, 3>((const T*)a.u12 + uoff, nbU, nbU, KV - nbU, xn, nullptr, part);
+      const int CG = run_gemv<T, S, 3>(A, B, gu, u12 + uoff, KV - nbU, nullptr, zeros, xn, part);
+      prefetch_gemv<T, S, 2>(A, B, gu, uinv + uoff, 0, nullptr, zeros);
       __syncthreads();
-      for (int32_t r = tid; r < nbU; r += blockDim.x) t[r] = ypad[b * nbU + r] - sum_parts(part, nbU, CG, r);
+      if (tid < nbU) t[tid] = yb - sum_parts(part, nbU, CG, tid);
     } else {
-      for (int32_t r = tid; r < nbU; r += blockDim.x) t[r] = ypad[b * nbU + r];
+      if (tid < nbU) t[tid] = yb;
     }
     __syncthreads();
-    const int CG = gemv_cols<T, S, 2>((const T*)a.uinv + uoff, nbU, nbU, 0, t, nullptr, part);
+    const int CG = run_gemv<T, S, 2>(A, B, gu, uinv + uoff, 0, nullptr, zeros, t, part);
+    if (b > 0) prefetch_gemv<T, S, 3>(A, B, gu, u12 + uoff - (int64_t)nbU * nbU, KV - nbU, nullptr, zeros);
     __syncthreads();
-    for (int32_t r = tid; r < nbU; r += blockDim.x) {
-      const double x = sum_parts(part, nbU, CG, r);
-      xn[r] = x;
-      const int32_t row = b * nbU + r;
+    if (tid < nbU) {
+      const double x = sum_parts(part, nbU, CG, tid);
+      xn[tid] = x;
+      const int32_t row = b * nbU + tid;
       if (row < n) {
         if (mode == 1) out[ioff + row] = z1[ioff + row] - x;
         else if (mode == 2) out[poff + row] = x;
@@ -316,6 +434,7 @@ static SweepArgs sweep_args(const addns_precond* pc) {
   a.e_rowptr = pc->e_rowptr.as<int32_t>();
   a.e_colidx = pc->e_colidx.as<int32_t>();
   a.e_vals = pc->e_vals.as<double>();
+  a.zeros = pc->zeros.p;
   return a;
 }
 
@@ -323,7 +442,8 @@ static void run_sweep(const addns_precond* pc, const SweepArgs& a, int grid, con
                       const double* x2, const double* z1, hipStream_t s) {
   const Plan& pl = pc->plan;
   const size_t smem = sweep_smem_bytes(pl.maxW, pl.nbU);
-  if (smem > 160 * 1024) throw ArgError("interior bandwidth too large for the LDS-staged sweep");
+  if (smem > 160 * 1024 || pl.nbU > kSweepThreads)
+    throw ArgError("interior bandwidth too large for the LDS-staged sweep");
   const int S = std::min(5, (std::max(pl.maxW, pl.nbU) + 63) / 64);
   if (pc->interior_prec == P64) dispatch_sweep<double>(S, a, grid, smem, yin, out, mode, x2, z1, s);
   else dispatch_sweep<float>(S, a, grid, smem, yin, out, mode, x2, z1, s);

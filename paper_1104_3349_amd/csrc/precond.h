@@ -131,6 +131,10 @@ struct Plan {
 
 void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult);
 
+// Bytes past the end of each interior factor array that the sweep may read
+// (its last row slot can overrun a block by up to 64 * 5 - 1 FP64 rows).
+constexpr int64_t kSweepOverrunBytes = 4096;
+
 // Storage precision tags
 enum Prec { P64 = 0, P32 = 1, P16S = 2 };
 
@@ -149,6 +153,7 @@ struct addns_precond {
   addns::DevBuf lperm;                                // per L-block window gather indices
   addns::DevBuf lmat;                                 // per L-block [inv(L11); L21 inv(L11)]
   addns::DevBuf uinv, u12;                            // per U-block
+  addns::DevBuf zeros;                                // zeroed words the sweep reads for zero slots
   // interface
   addns::DevBuf agg_off, agg_s, sinv_off, sinv, sinv_scale, schur_S;
   // scratch
