@@ -99,8 +99,6 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
     pc->u12.alloc((int64_t)fb * pl.u_total + tail);
     for (DevBuf* d : {&pc->lmat, &pc->uinv, &pc->u12})
       ADDNS_HIP(hipMemsetAsync(static_cast<char*>(d->p) + d->bytes - tail, 0, tail, s));
-    pc->zeros.alloc(512);
-    ADDNS_HIP(hipMemsetAsync(pc->zeros.p, 0, 512, s));
     work.alloc(sizeof(double) * std::max(pl.lwork_total, pl.u_total));
     launch_convert_lower(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), pc->lblks.as<LBlk>(), nL,
                          work.as<double>(), pc->lperm.as<int32_t>(), pc->lmat.p, iprec, s);

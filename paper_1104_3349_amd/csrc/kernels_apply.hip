@@ -2,15 +2,16 @@
 //
 //   interior solve   z1 = D^{-1} y1           (one workgroup per subdomain)
 //   interface solve  x2 = Shat^{-1}(y2 - F z1) (one workgroup per aggregate)
-//   interior solve   x1 = z1 - D^{-1} (E x2)   (E x2 formed while loading)
+//   interior solve   x1 = z1 - D^{-1} (E x2)   (E x2 formed in a first pass)
 //
 // Each interior solve is a forward sweep over the lower blocks followed by a
 // backward sweep over the upper blocks.  Every block step is a gather plus
 // one or two dense GEMVs whose matrices are streamed from HBM column-major:
 // a wavefront reads 64 consecutive rows of one column per load (coalesced),
 // the vector operand sits in LDS and is read as a broadcast, and column
-// chunks are reduced through LDS in a fixed order.  Factors are stored in
-// FP64 or FP32; accumulation is always FP64.
+// groups are reduced through LDS in a fixed order.  The matrices do not
+// depend on the data, so their loads run ahead of the step that uses them.
+// Factors are stored in FP64 or FP32; accumulation is always FP64.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -26,37 +27,6 @@ template <class T>
 __device__ inline double ld(const T* p) { return (double)(*p); }
 template <>
 __device__ inline double ld<__half>(const __half* p) { return (double)__half2float(*p); }
-
-// Partial GEMV of one block step: part[w*R + r] = sum over the columns k of
-// wave w of M(r, k) vec(k), M column-major with leading dimension R.  Each
-// wave owns a contiguous column chunk and every row slot (lane + 64 s, s <
-// S), so a batch issues CB columns x S slots of independent coalesced loads
-// before any FMA (memory-level parallelism is what bounds a single CU).
-// Structural zeros are never fetched:
-//   kind 2: upper        M(r,k) = 0 for k < r
-//   kind 3: band-shifted M(r,k) = 0 for k > r + par
-//   kind 4: [lower; full] M(r,k) = 0 for k > r when r < par
-// vec(k) = vin[gidx[k]] when gidx is given (the window permutation), else
-// vin[k].  The caller synchronises and reduces over waves.
-// Raw buffer loads: an offset at or beyond the resource's byte range returns
-// 0 without touching memory, so masked elements cost neither a branch nor a
-// fetch (the third descriptor dword is the gfx9-family raw-buffer format).
-constexpr int kBufFormatWord = 0x00020000;
-
-__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufFormatWord);
-}
-
-template <class T>
-__device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
-template <>
-__device__ inline float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
-}
-template <>
-__device__ inline double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
-}
 
 // Column chunk of one wave: CB columns x S row slots of a block, plus the
 // window-gather indices of those columns (lower sweep only).  Register
@@ -105,22 +75,21 @@ __device__ __attribute__((always_inline)) inline Geo make_geo(int R, int K) {
 
 // Loads columns k0 .. k0+CB-1 of M (column-major, leading dimension R).
 // The blocks store their structural zeros, so no per-lane mask is needed:
-// every load is a wave-uniform base (scalar registers) plus the lane's row,
-// one vector register shared by all loads.  With FP64 factors a row slot
-// that lies wholly in a column's zero part reads a small zeroed buffer
-// instead (a uniform choice of base; the loaded value is used as is, so no
-// load is waited for early); with FP32 factors the bytes saved are worth
-// less than the scalar work and the narrower chunks, and every slot is read:
+// each column's base address is wave-uniform (scalar registers) and the
+// lane's row is the only per-lane part of an address.  With FP64 factors a
+// row slot that lies wholly in a column's structural zeros is skipped by a
+// wave-uniform branch; with FP32 factors every slot is read, because the
+// branches cost more issue time than the bytes they save (A/B measured):
 //   kind 2: upper        M(r,k) = 0 for r > k
 //   kind 3: band-shifted M(r,k) = 0 for r < k - par
 //   kind 4: [lower; full] M(r,k) = 0 for r < min(k, par)
-// The last slot may run past row R - 1 (at most 64 S - 1 rows): those
-// products land in rows that are never stored, and every factor allocation
-// is padded so that the overrun stays inside it.  Columns past the wave's
-// range repeat its last column (their vector weight is 0).
+// The last slot may run past row R - 1 (at most 63 rows): those products
+// land in rows that are never stored, and every factor allocation is padded
+// so that the overrun stays inside it.  Columns past the wave's range repeat
+// its last column (their vector weight is 0).
 template <class T, int S, int kind>
 __device__ __attribute__((always_inline)) inline void load_chunk(Chunk<T, S>& c, const Geo& g, const T* M, int par,
-                                                                 const int32_t* gidx, const T* zeros, int k0) {
+                                                                 const int32_t* gidx, int k0) {
   constexpr int CB = Chunk<T, S>::CB;
   const uint32_t lane = threadIdx.x & 63;
 #pragma unroll
@@ -135,8 +104,9 @@ __device__ __attribute__((always_inline)) inline void load_chunk(Chunk<T, S>& c,
         c.v[j][s] = col[(uint32_t)g.r0 + lane + 64u * s];
       } else {
         const int rs0 = __builtin_amdgcn_readfirstlane(g.r0 + 64 * s);
-        const T* base = (rs0 < hi && rs0 + 64 > lo) ? col + rs0 : zeros;
-        c.v[j][s] = base[lane];
+        T x = T(0);
+        if (rs0 < hi && rs0 + 64 > lo) x = col[(uint32_t)rs0 + lane];  // wave-uniform branch
+        c.v[j][s] = x;
       }
     }
     if (gidx) c.gi[j] = gidx[k];
@@ -159,11 +129,11 @@ __device__ __attribute__((always_inline)) inline void fma_chunk(const Chunk<T, S
 // Issues the first two chunks of a GEMV (the rest follow inside run_gemv).
 template <class T, int S, int kind>
 __device__ __attribute__((always_inline)) inline void prefetch_gemv(Chunk<T, S>& A, Chunk<T, S>& B, const Geo& g, const T* M, int par,
-                                     const int32_t* gidx, const T* zeros) {
+                                     const int32_t* gidx) {
   constexpr int CB = Chunk<T, S>::CB;
   if (!g.act) return;
-  load_chunk<T, S, kind>(A, g, M, par, gidx, zeros, g.kb);
-  if (g.kb + CB < g.ke) load_chunk<T, S, kind>(B, g, M, par, gidx, zeros, g.kb + CB);
+  load_chunk<T, S, kind>(A, g, M, par, gidx, g.kb);
+  if (g.kb + CB < g.ke) load_chunk<T, S, kind>(B, g, M, par, gidx, g.kb + CB);
 }
 
 // part[cg * R + r] = sum over the wave's columns of M(r, k) vec(k); A and B
@@ -172,7 +142,7 @@ __device__ __attribute__((always_inline)) inline void prefetch_gemv(Chunk<T, S>&
 // column groups in a fixed order.
 template <class T, int S, int kind>
 __device__ __attribute__((always_inline)) inline int run_gemv(Chunk<T, S>& A, Chunk<T, S>& B, const Geo& g, const T* M, int par,
-                               const int32_t* gidx, const T* zeros, const double* vin, double* part) {
+                               const int32_t* gidx, const double* vin, double* part) {
   constexpr int CB = Chunk<T, S>::CB;
   if (g.act) {
     double acc[S];
@@ -181,10 +151,10 @@ __device__ __attribute__((always_inline)) inline int run_gemv(Chunk<T, S>& A, Ch
     const bool gather = gidx != nullptr;
     for (int k0 = g.kb; k0 < g.ke; k0 += 2 * CB) {
       fma_chunk<T, S>(A, g, k0, vin, gather, acc);
-      if (k0 + 2 * CB < g.ke) load_chunk<T, S, kind>(A, g, M, par, gidx, zeros, k0 + 2 * CB);
+      if (k0 + 2 * CB < g.ke) load_chunk<T, S, kind>(A, g, M, par, gidx, k0 + 2 * CB);
       if (k0 + CB < g.ke) {
         fma_chunk<T, S>(B, g, k0 + CB, vin, gather, acc);
-        if (k0 + 3 * CB < g.ke) load_chunk<T, S, kind>(B, g, M, par, gidx, zeros, k0 + 3 * CB);
+        if (k0 + 3 * CB < g.ke) load_chunk<T, S, kind>(B, g, M, par, gidx, k0 + 3 * CB);
       }
     }
     const int lane = threadIdx.x & 63;
@@ -221,7 +191,6 @@ struct SweepArgs {
   const int32_t* pair_sub;
   const int32_t* pair_col;
   const int64_t* pair_off;
-  const void* zeros;  // at least 64 zeroed FP64 words
 };
 
 // One workgroup per subdomain.  mode 0: out[int] = D^{-1} yin[int].
@@ -261,13 +230,12 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
   const T* uinv = (const T*)a.uinv + q.u_off;
   const T* u12 = (const T*)a.u12 + q.u_off;
   const int32_t* lperm = a.lperm + q.lperm_off;
-  const T* zeros = (const T*)a.zeros;
   const int32_t nL = npad / nbL, nU = npad / nbU;
   const Geo gl = make_geo<S>(W, nbL);
   const Geo gu = make_geo<S>(nbU, nbU);
   Chunk<T, S> A, B;
   // first GEMV of the sweep in flight while the input is prepared
-  if (nL > 0) prefetch_gemv<T, S, 4>(A, B, gl, lmat, nbL, lperm, zeros);
+  if (nL > 0) prefetch_gemv<T, S, 4>(A, B, gl, lmat, nbL, lperm);
   // modes 1 and 2: the sweep input (E x2, or column pcol of E) into ypad;
   // the lower sweep writes ypad only below the rows it still has to read
   if (mode != 0) {
@@ -293,9 +261,9 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
     // next window's new rows, fetched before this step's GEMV
     const int32_t rin = (b + 1) * nbL + KL + tid;
     const double nin = (tid < nbL && rin < n) ? src[rin] : 0.0;
-    const int CG = run_gemv<T, S, 4>(A, B, gl, M, nbL, idx, zeros, wc, part);
-    if (b + 1 < nL) prefetch_gemv<T, S, 4>(A, B, gl, M + (int64_t)W * nbL, nbL, idx + W, zeros);
-    else if (nU > 0) prefetch_gemv<T, S, 2>(A, B, gu, uinv + (int64_t)(nU - 1) * nbU * nbU, 0, nullptr, zeros);
+    const int CG = run_gemv<T, S, 4>(A, B, gl, M, nbL, idx, wc, part);
+    if (b + 1 < nL) prefetch_gemv<T, S, 4>(A, B, gl, M + (int64_t)W * nbL, nbL, idx + W);
+    else if (nU > 0) prefetch_gemv<T, S, 2>(A, B, gu, uinv + (int64_t)(nU - 1) * nbU * nbU, 0, nullptr);
     __syncthreads();
     for (int32_t r = tid; r < W; r += blockDim.x) {
       const double v = sum_parts(part, W, CG, r);
@@ -313,16 +281,16 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
     const int64_t uoff = (int64_t)b * nbU * nbU;
     const double yb = tid < nbU ? ypad[b * nbU + tid] : 0.0;
     if (b < nU - 1) {
-      const int CG = run_gemv<T, S, 3>(A, B, gu, u12 + uoff, KV - nbU, nullptr, zeros, xn, part);
-      prefetch_gemv<T, S, 2>(A, B, gu, uinv + uoff, 0, nullptr, zeros);
+      const int CG = run_gemv<T, S, 3>(A, B, gu, u12 + uoff, KV - nbU, nullptr, xn, part);
+      prefetch_gemv<T, S, 2>(A, B, gu, uinv + uoff, 0, nullptr);
       __syncthreads();
       if (tid < nbU) t[tid] = yb - sum_parts(part, nbU, CG, tid);
     } else {
       if (tid < nbU) t[tid] = yb;
     }
     __syncthreads();
-    const int CG = run_gemv<T, S, 2>(A, B, gu, uinv + uoff, 0, nullptr, zeros, t, part);
-    if (b > 0) prefetch_gemv<T, S, 3>(A, B, gu, u12 + uoff - (int64_t)nbU * nbU, KV - nbU, nullptr, zeros);
+    const int CG = run_gemv<T, S, 2>(A, B, gu, uinv + uoff, 0, nullptr, t, part);
+    if (b > 0) prefetch_gemv<T, S, 3>(A, B, gu, u12 + uoff - (int64_t)nbU * nbU, KV - nbU, nullptr);
     __syncthreads();
     if (tid < nbU) {
       const double x = sum_parts(part, nbU, CG, tid);
@@ -434,7 +402,6 @@ static SweepArgs sweep_args(const addns_precond* pc) {
   a.e_rowptr = pc->e_rowptr.as<int32_t>();
   a.e_colidx = pc->e_colidx.as<int32_t>();
   a.e_vals = pc->e_vals.as<double>();
-  a.zeros = pc->zeros.p;
   return a;
 }
 

@@ -153,7 +153,6 @@ struct addns_precond {
   addns::DevBuf lperm;                                // per L-block window gather indices
   addns::DevBuf lmat;                                 // per L-block [inv(L11); L21 inv(L11)]
   addns::DevBuf uinv, u12;                            // per U-block
-  addns::DevBuf zeros;                                // zeroed words the sweep reads for zero slots
   // interface
   addns::DevBuf agg_off, agg_s, sinv_off, sinv, sinv_scale, schur_S;
   // scratch
