@@ -126,7 +126,10 @@ typedef struct {
                              (1..4), or 0: the autotuner builds the sweep at 1 and 2,
                              times the interior solve on these factors and keeps the
                              faster.  A tile shape only: the factors are the same
-                             LU, regrouped; results agree to rounding */
+                             LU, regrouped; results agree to rounding.  Whatever the
+                             value, every setup also times the sweep with and without
+                             skipping the blocks' structural-zero row slots and keeps
+                             the faster (the results are the same bit for bit) */
   int32_t learned_bf16;   /* LEARNED only: 1 = run the network with BF16-rounded
                              weights and activations, 0 = FP32 */
 } addns_precond_opts;

@@ -36,7 +36,7 @@ __device__ inline double ld<__half>(const __half* p) { return (double)__half2flo
 template <class T>
 constexpr int chunk_cols(int S) {
   // the widest chunks whose two copies fit in the registers of 1024 threads
-  return sizeof(T) == 4 ? (S <= 2 ? 12 : (S == 3 ? 9 : (S == 4 ? 7 : 5)))
+  return sizeof(T) == 4 ? (S <= 2 ? 12 : (S == 3 ? 9 : (S == 4 ? 6 : 5)))
                         : (S <= 2 ? 4 : (S == 3 ? 3 : 2));
 }
 
@@ -76,10 +76,11 @@ __device__ __attribute__((always_inline)) inline Geo make_geo(int R, int K) {
 // Loads columns k0 .. k0+CB-1 of M (column-major, leading dimension R).
 // The blocks store their structural zeros, so no per-lane mask is needed:
 // each column's base address is wave-uniform (scalar registers) and the
-// lane's row is the only per-lane part of an address.  With FP64 factors a
-// row slot that lies wholly in a column's structural zeros is skipped by a
-// wave-uniform branch; with FP32 factors every slot is read, because the
-// branches cost more issue time than the bytes they save (A/B measured):
+// lane's row is the only per-lane part of an address.  With Z, a row slot
+// that lies wholly in a column's structural zeros is skipped by a
+// wave-uniform branch: fewer bytes, more instructions.  Few subdomains leave
+// the sweep bound by per-CU issue and latency, many subdomains by HBM, so the
+// setup times both forms on the actual factors and keeps the faster:
 //   kind 2: upper        M(r,k) = 0 for r > k
 //   kind 3: band-shifted M(r,k) = 0 for r < k - par
 //   kind 4: [lower; full] M(r,k) = 0 for r < min(k, par)
@@ -87,7 +88,7 @@ __device__ __attribute__((always_inline)) inline Geo make_geo(int R, int K) {
 // land in rows that are never stored, and every factor allocation is padded
 // so that the overrun stays inside it.  Columns past the wave's range repeat
 // its last column (their vector weight is 0).
-template <class T, int S, int kind>
+template <class T, int S, int kind, bool Z>
 __device__ __attribute__((always_inline)) inline void load_chunk(Chunk<T, S>& c, const Geo& g, const T* M, int par,
                                                                  const int32_t* gidx, int k0) {
   constexpr int CB = Chunk<T, S>::CB;
@@ -100,14 +101,10 @@ __device__ __attribute__((always_inline)) inline void load_chunk(Chunk<T, S>& c,
     const int lo = kind == 3 ? max(0, k - par) : (kind == 4 ? min(k, par) : 0);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      if constexpr (sizeof(T) == 4) {
-        c.v[j][s] = col[(uint32_t)g.r0 + lane + 64u * s];
-      } else {
-        const int rs0 = __builtin_amdgcn_readfirstlane(g.r0 + 64 * s);
-        T x = T(0);
-        if (rs0 < hi && rs0 + 64 > lo) x = col[(uint32_t)rs0 + lane];  // wave-uniform branch
-        c.v[j][s] = x;
-      }
+      const int rs0 = g.r0 + 64 * s;
+      T x = T(0);
+      if (!Z || (rs0 < hi && rs0 + 64 > lo)) x = col[(uint32_t)g.r0 + lane + 64u * s];  // wave-uniform
+      c.v[j][s] = x;
     }
     if (gidx) c.gi[j] = gidx[k];
   }
@@ -127,20 +124,20 @@ __device__ __attribute__((always_inline)) inline void fma_chunk(const Chunk<T, S
 }
 
 // Issues the first two chunks of a GEMV (the rest follow inside run_gemv).
-template <class T, int S, int kind>
+template <class T, int S, int kind, bool Z>
 __device__ __attribute__((always_inline)) inline void prefetch_gemv(Chunk<T, S>& A, Chunk<T, S>& B, const Geo& g, const T* M, int par,
                                      const int32_t* gidx) {
   constexpr int CB = Chunk<T, S>::CB;
   if (!g.act) return;
-  load_chunk<T, S, kind>(A, g, M, par, gidx, g.kb);
-  if (g.kb + CB < g.ke) load_chunk<T, S, kind>(B, g, M, par, gidx, g.kb + CB);
+  load_chunk<T, S, kind, Z>(A, g, M, par, gidx, g.kb);
+  if (g.kb + CB < g.ke) load_chunk<T, S, kind, Z>(B, g, M, par, gidx, g.kb + CB);
 }
 
 // part[cg * R + r] = sum over the wave's columns of M(r, k) vec(k); A and B
 // hold the first two chunks (prefetch_gemv), later chunks are loaded two
 // ahead of their use.  The caller synchronises and reduces over the CG
 // column groups in a fixed order.
-template <class T, int S, int kind>
+template <class T, int S, int kind, bool Z>
 __device__ __attribute__((always_inline)) inline int run_gemv(Chunk<T, S>& A, Chunk<T, S>& B, const Geo& g, const T* M, int par,
                                const int32_t* gidx, const double* vin, double* part) {
   constexpr int CB = Chunk<T, S>::CB;
@@ -151,10 +148,10 @@ __device__ __attribute__((always_inline)) inline int run_gemv(Chunk<T, S>& A, Ch
     const bool gather = gidx != nullptr;
     for (int k0 = g.kb; k0 < g.ke; k0 += 2 * CB) {
       fma_chunk<T, S>(A, g, k0, vin, gather, acc);
-      if (k0 + 2 * CB < g.ke) load_chunk<T, S, kind>(A, g, M, par, gidx, k0 + 2 * CB);
+      if (k0 + 2 * CB < g.ke) load_chunk<T, S, kind, Z>(A, g, M, par, gidx, k0 + 2 * CB);
       if (k0 + CB < g.ke) {
         fma_chunk<T, S>(B, g, k0 + CB, vin, gather, acc);
-        if (k0 + 3 * CB < g.ke) load_chunk<T, S, kind>(B, g, M, par, gidx, k0 + 3 * CB);
+        if (k0 + 3 * CB < g.ke) load_chunk<T, S, kind, Z>(B, g, M, par, gidx, k0 + 3 * CB);
       }
     }
     const int lane = threadIdx.x & 63;
@@ -207,7 +204,7 @@ struct SweepArgs {
 // current step, and the next step's input rows are fetched before the
 // current GEMV: the sweep waits for memory once per step at most, not once
 // per chunk.
-template <class T, int S>
+template <class T, int S, bool Z>
 __global__ void __launch_bounds__(kSweepThreads)
 k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int mode, const double* x2,
                  const double* z1) {
@@ -235,7 +232,7 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
   const Geo gu = make_geo<S>(nbU, nbU);
   Chunk<T, S> A, B;
   // first GEMV of the sweep in flight while the input is prepared
-  if (nL > 0) prefetch_gemv<T, S, 4>(A, B, gl, lmat, nbL, lperm);
+  if (nL > 0) prefetch_gemv<T, S, 4, Z>(A, B, gl, lmat, nbL, lperm);
   // modes 1 and 2: the sweep input (E x2, or column pcol of E) into ypad;
   // the lower sweep writes ypad only below the rows it still has to read
   if (mode != 0) {
@@ -261,9 +258,9 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
     // next window's new rows, fetched before this step's GEMV
     const int32_t rin = (b + 1) * nbL + KL + tid;
     const double nin = (tid < nbL && rin < n) ? src[rin] : 0.0;
-    const int CG = run_gemv<T, S, 4>(A, B, gl, M, nbL, idx, wc, part);
-    if (b + 1 < nL) prefetch_gemv<T, S, 4>(A, B, gl, M + (int64_t)W * nbL, nbL, idx + W);
-    else if (nU > 0) prefetch_gemv<T, S, 2>(A, B, gu, uinv + (int64_t)(nU - 1) * nbU * nbU, 0, nullptr);
+    const int CG = run_gemv<T, S, 4, Z>(A, B, gl, M, nbL, idx, wc, part);
+    if (b + 1 < nL) prefetch_gemv<T, S, 4, Z>(A, B, gl, M + (int64_t)W * nbL, nbL, idx + W);
+    else if (nU > 0) prefetch_gemv<T, S, 2, Z>(A, B, gu, uinv + (int64_t)(nU - 1) * nbU * nbU, 0, nullptr);
     __syncthreads();
     for (int32_t r = tid; r < W; r += blockDim.x) {
       const double v = sum_parts(part, W, CG, r);
@@ -281,16 +278,16 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
     const int64_t uoff = (int64_t)b * nbU * nbU;
     const double yb = tid < nbU ? ypad[b * nbU + tid] : 0.0;
     if (b < nU - 1) {
-      const int CG = run_gemv<T, S, 3>(A, B, gu, u12 + uoff, KV - nbU, nullptr, xn, part);
-      prefetch_gemv<T, S, 2>(A, B, gu, uinv + uoff, 0, nullptr);
+      const int CG = run_gemv<T, S, 3, Z>(A, B, gu, u12 + uoff, KV - nbU, nullptr, xn, part);
+      prefetch_gemv<T, S, 2, Z>(A, B, gu, uinv + uoff, 0, nullptr);
       __syncthreads();
       if (tid < nbU) t[tid] = yb - sum_parts(part, nbU, CG, tid);
     } else {
       if (tid < nbU) t[tid] = yb;
     }
     __syncthreads();
-    const int CG = run_gemv<T, S, 2>(A, B, gu, uinv + uoff, 0, nullptr, t, part);
-    if (b > 0) prefetch_gemv<T, S, 3>(A, B, gu, u12 + uoff - (int64_t)nbU * nbU, KV - nbU, nullptr);
+    const int CG = run_gemv<T, S, 2, Z>(A, B, gu, uinv + uoff, 0, nullptr, t, part);
+    if (b > 0) prefetch_gemv<T, S, 3, Z>(A, B, gu, u12 + uoff - (int64_t)nbU * nbU, KV - nbU, nullptr);
     __syncthreads();
     if (tid < nbU) {
       const double x = sum_parts(part, nbU, CG, tid);
@@ -365,24 +362,24 @@ size_t sweep_smem_bytes(int32_t maxW, int32_t maxU) {
   return sizeof(double) * (size_t)(2 * maxW + 2 * maxU + kWaves * std::max(maxW, maxU));
 }
 
-template <class T, int S>
+template <class T, int S, bool Z>
 static void launch_sweep(const SweepArgs& a, int m, size_t smem, const double* yin, double* out, int mode,
                          const double* x2, const double* z1, hipStream_t s) {
   if (smem > 64 * 1024)
-    ADDNS_HIP(hipFuncSetAttribute((const void*)k_interior_solve<T, S>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)smem));
-  k_interior_solve<T, S><<<m, kSweepThreads, smem, s>>>(a, yin, out, mode, x2, z1);
+    ADDNS_HIP(hipFuncSetAttribute((const void*)k_interior_solve<T, S, Z>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  k_interior_solve<T, S, Z><<<m, kSweepThreads, smem, s>>>(a, yin, out, mode, x2, z1);
 }
 
-template <class T>
+template <class T, bool Z>
 static void dispatch_sweep(int S, const SweepArgs& a, int m, size_t smem, const double* yin, double* out, int mode,
                            const double* x2, const double* z1, hipStream_t s) {
   switch (S) {
-    case 1: launch_sweep<T, 1>(a, m, smem, yin, out, mode, x2, z1, s); break;
-    case 2: launch_sweep<T, 2>(a, m, smem, yin, out, mode, x2, z1, s); break;
-    case 3: launch_sweep<T, 3>(a, m, smem, yin, out, mode, x2, z1, s); break;
-    case 4: launch_sweep<T, 4>(a, m, smem, yin, out, mode, x2, z1, s); break;
-    case 5: launch_sweep<T, 5>(a, m, smem, yin, out, mode, x2, z1, s); break;
+    case 1: launch_sweep<T, 1, Z>(a, m, smem, yin, out, mode, x2, z1, s); break;
+    case 2: launch_sweep<T, 2, Z>(a, m, smem, yin, out, mode, x2, z1, s); break;
+    case 3: launch_sweep<T, 3, Z>(a, m, smem, yin, out, mode, x2, z1, s); break;
+    case 4: launch_sweep<T, 4, Z>(a, m, smem, yin, out, mode, x2, z1, s); break;
+    case 5: launch_sweep<T, 5, Z>(a, m, smem, yin, out, mode, x2, z1, s); break;
     default: throw ArgError("sweep row slots out of range");
   }
 }
@@ -412,8 +409,16 @@ static void run_sweep(const addns_precond* pc, const SweepArgs& a, int grid, con
   if (smem > 160 * 1024 || pl.nbU > kSweepThreads)
     throw ArgError("interior bandwidth too large for the LDS-staged sweep");
   const int S = std::min(5, (std::max(pl.maxW, pl.nbU) + 63) / 64);
-  if (pc->interior_prec == P64) dispatch_sweep<double>(S, a, grid, smem, yin, out, mode, x2, z1, s);
-  else dispatch_sweep<float>(S, a, grid, smem, yin, out, mode, x2, z1, s);
+  // zero-slot skipping is a tile choice of the autotuner: skipped slots hold
+  // exact zeros, so both forms give bitwise the same result
+  const bool z = pc->zero_skip != 0;
+  if (pc->interior_prec == P64) {
+    if (z) dispatch_sweep<double, true>(S, a, grid, smem, yin, out, mode, x2, z1, s);
+    else dispatch_sweep<double, false>(S, a, grid, smem, yin, out, mode, x2, z1, s);
+  } else {
+    if (z) dispatch_sweep<float, true>(S, a, grid, smem, yin, out, mode, x2, z1, s);
+    else dispatch_sweep<float, false>(S, a, grid, smem, yin, out, mode, x2, z1, s);
+  }
 }
 
 void launch_interior_solve(const addns_precond* pc, const double* yin, double* out, int second, const double* x2,

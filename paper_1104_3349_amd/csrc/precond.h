@@ -161,6 +161,7 @@ struct addns_precond {
   int64_t factor_bytes = 0, bytes_apply = 0;
   int64_t learned_count = 0;
   float tuned_ms = 0.0f;                              // autotuner timing of the interior solve
+  int zero_skip = 0;                                  // sweep skips structural-zero row slots (autotuned)
   addns::DevBuf g_copy;                               // G blocks before the update (learning targets S - G)
   addns::DevBuf smp_row, smp_nb, smp_loc;             // learned-correction sample table
   // GMRES work space (grown on demand)
