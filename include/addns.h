@@ -158,7 +158,10 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
  * addns_apply_precond -- Algorithm 2: x = B^{-1} y,
  *   z1 = D^-1 y1;  x2 = Shat^-1 (y2 - F z1);  x1 = z1 - D^-1 (E x2),
  * for DEVICE vectors of length N in the ORIGINAL numbering of the scaled
- * system (y, x must not alias).  Asynchronous on `stream`.
+ * system (y, x must not alias).  Asynchronous on `stream`.  It only launches
+ * kernels (no allocation, copy, memset or synchronisation), so a caller can
+ * capture it in a HIP graph and replay it; it works in the handle's own
+ * permuted vectors, so applies on one handle must not overlap.
  */
 int addns_apply_precond(addns_precond_t pc, const double* d_y, double* d_x, void* stream);
 

@@ -200,6 +200,11 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
   }
   ADDNS_HIP(hipStreamSynchronize(s));
 
+  // permuted in/out vectors of addns_apply_precond: allocated here so that
+  // an apply launches kernels only (and can be captured in a graph)
+  pc->vperm_in.alloc(sizeof(double) * N);
+  pc->vperm_out.alloc(sizeof(double) * N);
+
   // -- byte accounting
   int64_t fbytes = 0;
   fbytes += pl.lmat_total * fb + pl.lperm_total * 4;
@@ -362,10 +367,6 @@ int addns_apply_precond(addns_precond_t pc, const double* d_y, double* d_x, void
     if (d_y == d_x) throw ArgError("y and x must not alias");
     hipStream_t s = as_stream(stream);
     const int32_t N = pc->plan.N;
-    if (!pc->vperm_in.p) {
-      pc->vperm_in.alloc(sizeof(double) * N);
-      pc->vperm_out.alloc(sizeof(double) * N);
-    }
     launch_permute(pc->perm.as<int32_t>(), d_y, pc->vperm_in.as<double>(), N, 0, nullptr, s);
     apply_permuted(pc, pc->vperm_in.as<double>(), pc->vperm_out.as<double>(), s);
     launch_permute(pc->perm.as<int32_t>(), pc->vperm_out.as<double>(), d_x, N, 1, nullptr, s);

@@ -365,9 +365,14 @@ size_t sweep_smem_bytes(int32_t maxW, int32_t maxU) {
 template <class T, int S, bool Z>
 static void launch_sweep(const SweepArgs& a, int m, size_t smem, const double* yin, double* out, int mode,
                          const double* x2, const double* z1, hipStream_t s) {
-  if (smem > 64 * 1024)
+  // raise the kernel's dynamic-LDS limit once per size (the setup's own
+  // sweeps do it before any caller could capture an apply in a graph)
+  static size_t raised = 64 * 1024;
+  if (smem > raised) {
     ADDNS_HIP(hipFuncSetAttribute((const void*)k_interior_solve<T, S, Z>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    raised = smem;
+  }
   k_interior_solve<T, S, Z><<<m, kSweepThreads, smem, s>>>(a, yin, out, mode, x2, z1);
 }
 

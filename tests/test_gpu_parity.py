@@ -362,3 +362,35 @@ def test_batched_converges_per_system():
         assert res[q]["converged"] and res[q]["true_relres"] <= 1e-8
         assert abs(res[q]["iters"] - r1["iters"]) <= 1
     MEASURED["batched_its"] = [r["iters"] for r in res]
+
+
+def test_apply_captured_in_graph_replays_exactly():
+    """addns_apply_precond only launches kernels, so it can be captured in a
+    graph.  Every replay (with eager work and synchronisations in between)
+    must equal the eager apply of the same input bit for bit."""
+    S = make_system(**CASES["mid"])
+    part, pc = gpu_precond(S, iprec=addns.F32, sprec=addns.F32)
+    y = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(y)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        addns.apply_precond(pc, y, x)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        addns.apply_precond(pc, y, x)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    for rep in range(4):
+        yin = _cuda(rng.standard_normal(S.N))
+        y.copy_(yin)
+        g.replay()
+        torch.cuda.synchronize()
+        got = x.cpu().numpy().copy()
+        ref = torch.zeros_like(x)
+        addns.apply_precond(pc, yin, ref)
+        torch.cuda.synchronize()
+        assert np.array_equal(got, ref.cpu().numpy()), rep
+        x.zero_()  # eager work between replays
