@@ -176,7 +176,7 @@ int addns_apply_precond(addns_precond_t pc, const double* d_y, double* d_x, void
 int addns_interior_solve(addns_precond_t pc, const double* d_y1, double* d_z1, void* stream);
 
 typedef struct {
-  int32_t restart;   /* Krylov dimension per cycle (>= 1) */
+  int32_t restart;   /* Krylov dimension per cycle (1..1024) */
   int32_t maxit;     /* total inner iterations allowed */
   double tol;        /* stop when ||b~ - C~ x|| / ||b~|| <= tol */
   int32_t flexible;  /* 1 = FGMRES (store Z), 0 = GMRES (x += B^-1 V y) */

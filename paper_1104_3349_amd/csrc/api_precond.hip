@@ -390,7 +390,8 @@ int addns_gmres_solve(addns_precond_t pc, const double* d_b, double* d_x, const 
   return guarded("addns_gmres_solve", [&]() -> int {
     if (!pc || !d_b || !d_x || !opts || !res) throw ArgError("null argument");
     const int restart = opts->restart, maxit = opts->maxit;
-    if (restart < 1 || maxit < 0 || !(opts->tol > 0.0)) throw ArgError("restart >= 1, maxit >= 0, tol > 0");
+    if (restart < 1 || restart > 1024 || maxit < 0 || !(opts->tol > 0.0))
+      throw ArgError("1 <= restart <= 1024, maxit >= 0, tol > 0");
     hipStream_t s = as_stream(stream);
     const int32_t N = pc->plan.N;
     const Plan& pl = pc->plan;
@@ -490,7 +491,8 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
   return guarded("addns_gmres_solve_batched", [&]() -> int {
     if (!pc || !sys_offsets || !d_b || !d_x || !opts || !res || nsys < 1) throw ArgError("null argument");
     const int restart = opts->restart, maxit = opts->maxit;
-    if (restart < 1 || maxit < 0 || !(opts->tol > 0.0)) throw ArgError("restart >= 1, maxit >= 0, tol > 0");
+    if (restart < 1 || restart > 1024 || maxit < 0 || !(opts->tol > 0.0))
+      throw ArgError("1 <= restart <= 1024, maxit >= 0, tol > 0");
     if (!opts->flexible) throw ArgError("the batched solver is flexible GMRES only");
     const Plan& pl = pc->plan;
     const int32_t N = pl.N;

@@ -14,6 +14,7 @@ namespace {
 constexpr int kKT = 256;          // threads per reduction workgroup
 constexpr int kPerThread = 4;     // elements per thread per grid pass
 constexpr int kMaxParts = 1024;
+constexpr int kMaxRestart = 1024;  // Krylov dimension per cycle handled by k_finalize
 
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
@@ -103,11 +104,31 @@ __global__ void __launch_bounds__(kKT)
 k_mgs_step(double* __restrict__ w, const double* __restrict__ vi, const double* __restrict__ vnext, int32_t n,
            const double* __restrict__ pin, double* __restrict__ pout, double* __restrict__ h_out, int nparts) {
   __shared__ double red[kKT / 64];
+  // the vector loads do not depend on h: issue them before reducing the
+  // partials of <w, v_i>, so that the two memory latencies overlap
+  const int32_t stride = gridDim.x * blockDim.x, i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  double wv[kPerThread], vv[kPerThread], nv[kPerThread];
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int32_t i = i0 + k * stride;
+    wv[k] = i < n ? w[i] : 0.0;
+    vv[k] = i < n ? vi[i] : 0.0;
+    nv[k] = (i < n && vnext) ? vnext[i] : 0.0;
+  }
   const double h = reduce_parts(pin, nparts, red);
   if (blockIdx.x == 0 && threadIdx.x == 0) *h_out = h;
   double acc = 0.0;
-  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    double y = w[i] - h * vi[i];
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int32_t i = i0 + k * stride;
+    if (i < n) {
+      const double y = wv[k] - h * vv[k];
+      w[i] = y;
+      acc += y * (vnext ? nv[k] : y);
+    }
+  }
+  for (int32_t i = i0 + kPerThread * stride; i < n; i += stride) {  // grids capped at kMaxParts
+    const double y = w[i] - h * vi[i];
     w[i] = y;
     acc += y * (vnext ? vnext[i] : y);
   }
@@ -123,15 +144,26 @@ __global__ void __launch_bounds__(kKT)
 k_finalize(double* __restrict__ H, double* __restrict__ g, double* __restrict__ cs, double* __restrict__ sn,
            const double* __restrict__ partials, int nparts, int32_t j, int32_t ldh, double* __restrict__ scal) {
   __shared__ double red[kKT / 64];
-  const double hn = sqrt(reduce_parts(partials, nparts, red));
-  if (threadIdx.x != 0) return;
+  __shared__ double s_col[kMaxRestart + 1], s_cs[kMaxRestart], s_sn[kMaxRestart];
   double* col = H + (int64_t)j * ldh;
-  for (int32_t i = 0; i < j; ++i) {
-    double t = cs[i] * col[i] + sn[i] * col[i + 1];
-    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-    col[i] = t;
+  // stage column j and the rotations in LDS (parallel loads that overlap the
+  // reduction), so the serial rotation loop below reads no global memory
+  for (int32_t i = threadIdx.x; i <= j; i += blockDim.x) {
+    s_col[i] = col[i];
+    if (i < j) {
+      s_cs[i] = cs[i];
+      s_sn[i] = sn[i];
+    }
   }
-  double a = col[j], b = hn, c, s;
+  const double hn = sqrt(reduce_parts(partials, nparts, red));  // synchronises the block
+  if (threadIdx.x != 0) return;
+  for (int32_t i = 0; i < j; ++i) {
+    double t = s_cs[i] * s_col[i] + s_sn[i] * s_col[i + 1];
+    s_col[i + 1] = -s_sn[i] * s_col[i] + s_cs[i] * s_col[i + 1];
+    s_col[i] = t;
+  }
+  for (int32_t i = 0; i < j; ++i) col[i] = s_col[i];
+  double a = s_col[j], b = hn, c, s;
   if (b == 0.0) {
     c = 1.0;
     s = 0.0;
@@ -260,11 +292,29 @@ k_seg_mgs_step(double* __restrict__ w, const double* __restrict__ vi, const doub
   __shared__ double red[kKT / 64];
   const Chunk c = ch[blockIdx.x];
   if (!live[c.sys]) return;
+  // vector loads first (they do not depend on h), then the partials
+  double wv[kPerThread], vv[kPerThread], nv[kPerThread];
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int32_t i = c.start + threadIdx.x + k * blockDim.x;
+    wv[k] = i < c.end ? w[i] : 0.0;
+    vv[k] = i < c.end ? vi[i] : 0.0;
+    nv[k] = (i < c.end && vnext) ? vnext[i] : 0.0;
+  }
   const double h = seg_sum(pin, coff, c.sys, red);
   if (blockIdx.x == coff[c.sys] && threadIdx.x == 0) state[c.sys * st + hidx] = h;
   double acc = 0.0;
-  for (int32_t i = c.start + threadIdx.x; i < c.end; i += blockDim.x) {
-    double y = w[i] - h * vi[i];
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int32_t i = c.start + threadIdx.x + k * blockDim.x;
+    if (i < c.end) {
+      const double y = wv[k] - h * vv[k];
+      w[i] = y;
+      acc += y * (vnext ? nv[k] : y);
+    }
+  }
+  for (int32_t i = c.start + threadIdx.x + kPerThread * blockDim.x; i < c.end; i += blockDim.x) {
+    const double y = w[i] - h * vi[i];
     w[i] = y;
     acc += y * (vnext ? vnext[i] : y);
   }

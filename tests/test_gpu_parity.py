@@ -298,6 +298,13 @@ def test_setup_argument_errors():
     d = torch.zeros(S.N, dtype=torch.float64, device="cuda")
     with pytest.raises(addns.AddnsError):
         addns.apply_precond(pc, d, d)
+    x = torch.zeros_like(d)
+    for bad in (dict(restart=0), dict(restart=1025), dict(tol=0.0), dict(maxit=-1)):
+        kw = dict(restart=10, maxit=10, tol=1e-8)
+        kw.update(bad)
+        with pytest.raises(addns.AddnsError) as e:
+            addns.gmres_solve(pc, d, x, raise_noconv=True, **kw)
+        assert e.value.code == addns.ERR_ARG, bad
 
 
 # ---------------------------------------------------------------------------
