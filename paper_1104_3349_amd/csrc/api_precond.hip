@@ -73,6 +73,8 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
   DevBuf info;
   info.alloc(sizeof(int32_t) * (m + 4));
   ADDNS_HIP(hipMemsetAsync(info.p, 0, sizeof(int32_t) * (m + 4), s));
+  if (pl.KL + pl.KU > 1024 || pl.nbU > 1024)
+    throw ArgError("interior bandwidth too large (the band LU and the sweep take KL + KU up to 1024)");
   if (m > 0 && npad_total > 0) {
     DevBuf ab, ipiv, bdst, bsrc, work;
     ab.alloc(sizeof(double) * pl.band_total);

@@ -255,9 +255,11 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
   for (int32_t b = 0; b < nL; ++b) {
     const int32_t* idx = lperm + (int64_t)b * W;
     const T* M = lmat + (int64_t)b * W * nbL;
-    // next window's new rows, fetched before this step's GEMV
+    // next window's new rows and this block's carry gather indices, fetched
+    // before this step's GEMV so that the reduction below waits for neither
     const int32_t rin = (b + 1) * nbL + KL + tid;
     const double nin = (tid < nbL && rin < n) ? src[rin] : 0.0;
+    const int32_t cidx = (tid >= nbL && tid < W) ? idx[tid] : 0;
     const int CG = run_gemv<T, S, 4, Z>(A, B, gl, M, nbL, idx, wc, part);
     if (b + 1 < nL) prefetch_gemv<T, S, 4, Z>(A, B, gl, M + (int64_t)W * nbL, nbL, idx + W);
     else if (nU > 0) prefetch_gemv<T, S, 2, Z>(A, B, gu, uinv + (int64_t)(nU - 1) * nbU * nbU, 0, nullptr);
@@ -265,7 +267,7 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
     for (int32_t r = tid; r < W; r += blockDim.x) {
       const double v = sum_parts(part, W, CG, r);
       if (r < nbL) ypad[b * nbL + r] = v;
-      else wn[r - nbL] = wc[idx[r]] - v;
+      else wn[r - nbL] = wc[r == tid ? cidx : idx[r]] - v;
     }
     if (tid < nbL) wn[KL + tid] = nin;
     __syncthreads();

@@ -19,6 +19,7 @@ namespace addns {
 namespace {
 
 constexpr int kSetupThreads = 1024;
+constexpr int kMaxBandLU = 1024;  // KL + KU limit of k_band_lu (the sweep's own limit is the same)
 
 __global__ void k_row_scale(const int32_t* __restrict__ rowptr, const double* __restrict__ vals, int32_t N,
                             int scale, double* __restrict__ R) {
@@ -79,8 +80,8 @@ k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const Sub
   __shared__ int32_t s_p;
   __shared__ int32_t s_ju;
   __shared__ int32_t s_info;
-  __shared__ double s_rv[16];
-  __shared__ int32_t s_ri[16];
+  __shared__ double s_l[kMaxBandLU + 1];  // multipliers of the current column
+  __shared__ double s_u[kMaxBandLU];      // pivot row of U right of the diagonal
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) {
     s_ju = 0;
@@ -124,39 +125,53 @@ k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const Sub
     const double piv = s_piv;
     const int32_t ju = s_ju;
     if (piv != 0.0) {
-      // multipliers of column j (after the row swap) and the swap of columns j+1..ju
+      // multipliers of column j (after the row swap) and the swap of columns
+      // j+1..ju; both also go to LDS for the update below
       const double rinv = 1.0 / piv;
       for (int32_t i = tid; i <= km; i += blockDim.x) {
         if (i == 0) continue;
-        double v = (i == p) ? s_top : colj[i];
-        colj[i] = v * rinv;
+        const double l = ((i == p) ? s_top : colj[i]) * rinv;
+        colj[i] = l;
+        s_l[i] = l;
       }
       if (tid == 0) colj[0] = piv;
-      if (p != 0) {
-        for (int32_t c = j + 1 + tid; c <= ju; c += blockDim.x) {
-          double* col = ab + (int64_t)c * ldab + KV + j - c;
-          double a = col[0], b = col[p];
+      for (int32_t c = j + 1 + tid; c <= ju; c += blockDim.x) {
+        double* col = ab + (int64_t)c * ldab + KV + j - c;
+        double a = col[0];
+        if (p != 0) {
+          const double b = col[p];
           col[0] = b;
           col[p] = a;
+          a = b;
         }
+        s_u[c - j - 1] = a;
       }
     }
     __syncthreads();
     if (piv != 0.0 && km > 0) {
-      const int32_t ncols = ju - j;
-      const int64_t total = (int64_t)ncols * km;
-      for (int64_t t = tid; t < total; t += blockDim.x) {
-        int32_t c = j + 1 + (int32_t)(t / km);
-        int32_t i = 1 + (int32_t)(t % km);
-        double* col = ab + (int64_t)c * ldab + KV + j - c;
-        col[i] -= colj[i] * col[0];
+      // rank-1 update of rows 1..km of columns j+1..ju: every thread loads
+      // its Q elements before it stores any (independent addresses)
+      constexpr int Q = 24;  // two batches cover KL x (KL+KU) = 130 x 260 with 1024 threads
+      const int32_t total = (ju - j) * km;
+      for (int32_t base = 0; base < total; base += Q * (int32_t)blockDim.x) {
+        double v[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int32_t t = base + q * (int32_t)blockDim.x + tid;
+          const int32_t c = t / km, i = 1 + t % km;
+          v[q] = t < total ? ab[(int64_t)(j + 1 + c) * ldab + KV - 1 - c + i] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int32_t t = base + q * (int32_t)blockDim.x + tid;
+          const int32_t c = t / km, i = 1 + t % km;
+          if (t < total) ab[(int64_t)(j + 1 + c) * ldab + KV - 1 - c + i] = v[q] - s_l[i] * s_u[c];
+        }
       }
     }
     __syncthreads();
   }
   if (tid == 0) info[sub] = s_info;
-  (void)s_rv;
-  (void)s_ri;
 }
 
 template <class T>
