@@ -26,10 +26,13 @@ algorithm, so this module states one deterministic partitioner precisely:
        interior (pressure nodes joined through shared interior velocity
        nodes, ordered by smallest index) whose constant vector is in the null
        space of the interior block (sum over q in K of C(v, q) == 0.0 for all
-       adjacent interior velocity rows v), the first q of K (ascending) whose
-       smallest-index separator-velocity neighbour f is still unclaimed moves
-       to the separator and is paired with f.  If every such f is claimed the
-       first candidate is used and a shared-pair warning is returned;
+       adjacent interior velocity rows v), one pair (q in K, separator
+       velocity neighbour f) is chosen: ranked by |C(q,f)| / max|C(q,:)|,
+       then |C(f,q)| / max|C(f,:)| (larger first), then smaller q, then
+       smaller f, the best pair whose f is still unclaimed; q moves to the
+       separator, paired with f.  If every f is claimed the best pair is used
+       and a shared-pair warning is returned.  (A weakly coupled pair would
+       leave the interface block nearly singular on stretched grids);
  (v)   orderings: each interior by reverse Cuthill-McKee on H[int_j] per
        component (components by smallest index; CM children by (degree in
        H[int_j], index); each component's CM list reversed); the separator by
@@ -224,8 +227,21 @@ def _recursive_bisection(H, is_p, N, m):
 # (iv) closure of interior pressure components
 # --------------------------------------------------------------------------
 
+def _coef(rowptr, colidx, vals, r, c):
+    """|C(r, c)| (0.0 when the entry is absent)."""
+    for e in range(rowptr[r], rowptr[r + 1]):
+        if colidx[e] == c:
+            return abs(float(vals[e]))
+    return 0.0
+
+
 def _closure(N, rowptr, colidx, vals, H, is_p, part, m):
     status = 0
+    rowmax = np.zeros(N)
+    nonempty = np.diff(rowptr) > 0
+    if nonempty.any():
+        rowmax[nonempty] = np.maximum.reduceat(np.abs(vals), rowptr[:-1][nonempty])
+    rel = lambda r, c: _coef(rowptr, colidx, vals, r, c) / rowmax[r] if rowmax[r] > 0 else 0.0
     in_sep = part < 0
     pair_of = {}          # moved q -> f
     claimed = np.zeros(N, dtype=bool)
@@ -263,14 +279,17 @@ def _closure(N, rowptr, colidx, vals, H, is_p, part, m):
             cand = []
             for q in K:
                 nb = Hi[Hp[q]:Hp[q + 1]]
-                nb = nb[in_sep[nb] & ~is_p[nb]]
-                if nb.size:
-                    cand.append((q, int(nb.min())))
+                for f in nb[in_sep[nb] & ~is_p[nb]]:
+                    f = int(f)
+                    s1 = rel(q, f)
+                    s2 = rel(f, q)
+                    cand.append((-s1, -s2, q, f))
             if not cand:
                 continue
-            pick = next(((q, f) for q, f in cand if not claimed[f]), None)
+            cand.sort()
+            pick = next(((q, f) for _, _, q, f in cand if not claimed[f]), None)
             if pick is None:
-                pick = cand[0]
+                pick = (cand[0][2], cand[0][3])
                 status = WARN_SHARED_PAIR
             q, f = pick
             part[q] = -1

@@ -174,6 +174,20 @@ k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const Sub
   if (tid == 0) info[sub] = s_info;
 }
 
+// max |x_t| over n contiguous doubles, in every thread of the block (ends
+// with a barrier)
+__device__ inline double block_absmax(const double* x, int64_t n, double* s_wmax) {
+  double m = 0.0;
+  for (int64_t t = threadIdx.x; t < n; t += blockDim.x) m = fmax(m, fabs(x[t]));
+  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, s_wmax[w]);
+  __syncthreads();
+  return r;
+}
+
 template <class T>
 __device__ inline T to_store(double v) { return (T)v; }
 template <>
@@ -344,8 +358,10 @@ k_schur_blocks(const int32_t* __restrict__ agg_s, const int32_t* __restrict__ ag
   __shared__ int32_t s_p;
   __shared__ double s_piv;
   __shared__ int s_bad;
+  __shared__ double s_wmax[kSetupThreads / 64];
   if (tid == 0) s_bad = 0;
-  __syncthreads();
+  // a pivot at or below 1e-13 max|D_r| marks the block singular
+  const double tiny = 1e-13 * block_absmax(D, (int64_t)d * d, s_wmax);
   for (int32_t c = 0; c < d; ++c) {
     if (wave == 0) {
       double best = -1.0;
@@ -368,7 +384,7 @@ k_schur_blocks(const int32_t* __restrict__ agg_s, const int32_t* __restrict__ ag
       if (lane == 0) {
         s_p = bi;
         s_piv = A(bi, c);
-        if (A(bi, c) == 0.0) s_bad = 1;
+        if (fabs(s_piv) <= tiny) s_bad = 1;
       }
     }
     __syncthreads();
@@ -450,8 +466,10 @@ k_invert_dense(const int32_t* __restrict__ agg_s, const int64_t* __restrict__ g_
   __shared__ double s_piv;
   __shared__ int s_bad;
   __shared__ double s_red[16];
+  __shared__ double s_wmax[kSetupThreads / 64];
   if (tid == 0) s_bad = 0;
-  __syncthreads();
+  // a pivot at or below 1e-13 max|S_i| marks the block singular
+  const double tiny = 1e-13 * block_absmax(S, (int64_t)s * s, s_wmax);
   for (int32_t c = 0; c < s; ++c) {
     if (wave == 0) {
       double best = -1.0;
@@ -474,7 +492,7 @@ k_invert_dense(const int32_t* __restrict__ agg_s, const int64_t* __restrict__ g_
       if (lane == 0) {
         s_p = bi;
         s_piv = A[(int64_t)bi * w + c];
-        if (s_piv == 0.0) s_bad = 1;
+        if (fabs(s_piv) <= tiny) s_bad = 1;
       }
     }
     __syncthreads();

@@ -19,7 +19,9 @@
 //      in the null space of its interior block (sum over the component of
 //      C(v, q) is exactly 0.0 for every adjacent interior velocity row v)
 //      gives up one node to the separator, paired with an interface velocity
-//      neighbour;
+//      neighbour: the unclaimed pair with the strongest coupling relative to
+//      the rows' largest entries (a weakly coupled pair leaves the interface
+//      block nearly singular);
 //   5. reverse Cuthill-McKee per interior component; separator in ascending
 //      index with each closure node right after its pair;
 //   6. aggregates of sz consecutive separator positions, never separating a
@@ -32,6 +34,7 @@
 // Only integer work, apart from the exact zero test of step 4.
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <numeric>
 #include <vector>
@@ -302,6 +305,9 @@ int build_partition(int32_t N, const int32_t* rowptr, const int32_t* colidx, con
   std::vector<int32_t>& part = P.part;
 
   // 4. closure of interior pressure components
+  std::vector<double> rowmax(N, 0.0);
+  for (int32_t r = 0; r < N; ++r)
+    for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) rowmax[r] = std::max(rowmax[r], std::fabs(vals[e]));
   std::vector<int32_t> pair_of(N, -1);
   std::vector<uint8_t> claimed(N, 0);
   {
@@ -353,31 +359,44 @@ int build_partition(int32_t N, const int32_t* rowptr, const int32_t* colidx, con
         }
         for (int32_t q : K) inK[q] = 0;
         if (!closed) continue;
-        int32_t first_q = -1, first_f = -1, pick_q = -1, pick_f = -1;
+        // candidate pairs (q in K, separator velocity neighbour f), ranked by
+        // the strength of their coupling relative to each row's largest
+        // entry, |C(q,f)|/max|C(q,:)| then |C(f,q)|/max|C(f,:)|, ties to the
+        // smaller q, then the smaller f; the best unclaimed f wins
+        struct Cand {
+          double s1, s2;
+          int32_t q, f;
+        };
+        auto better = [](const Cand& a, const Cand& b) {
+          if (a.s1 != b.s1) return a.s1 > b.s1;
+          if (a.s2 != b.s2) return a.s2 > b.s2;
+          if (a.q != b.q) return a.q < b.q;
+          return a.f < b.f;
+        };
+        auto coef = [&](int32_t r, int32_t c) {
+          for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e)
+            if (colidx[e] == c) return std::fabs(vals[e]);
+          return 0.0;
+        };
+        bool any = false, any_free = false;
+        Cand best{}, best_free{};
         for (int32_t q : K) {
-          int32_t f = -1;
           for (int32_t e = g.ptr[q]; e < g.ptr[q + 1]; ++e) {
-            int32_t w = g.adj[e];
-            if (part[w] < 0 && !is_p[w]) {
-              f = w;  // adjacency is sorted: first hit is the smallest
-              break;
-            }
-          }
-          if (f < 0) continue;
-          if (first_q < 0) {
-            first_q = q;
-            first_f = f;
-          }
-          if (!claimed[f]) {
-            pick_q = q;
-            pick_f = f;
-            break;
+            const int32_t f = g.adj[e];
+            if (part[f] >= 0 || is_p[f]) continue;
+            const Cand c{rowmax[q] > 0.0 ? coef(q, f) / rowmax[q] : 0.0,
+                         rowmax[f] > 0.0 ? coef(f, q) / rowmax[f] : 0.0, q, f};
+            if (!any || better(c, best)) best = c;
+            any = true;
+            if (!claimed[f] && (!any_free || better(c, best_free))) best_free = c;
+            any_free = any_free || !claimed[f];
           }
         }
-        if (first_q < 0) continue;
-        if (pick_q < 0) {
-          pick_q = first_q;
-          pick_f = first_f;
+        if (!any) continue;
+        int32_t pick_q = best_free.q, pick_f = best_free.f;
+        if (!any_free) {
+          pick_q = best.q;
+          pick_f = best.f;
           P.status = ADDNS_WARN_SHARED_PAIR;
         }
         part[pick_q] = -1;
