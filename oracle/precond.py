@@ -17,6 +17,11 @@ Plain FP64, no blocking or fusion beyond what the paper states:
               partition (interior velocity neighbours of the aggregate);
     MSCN_LIT  the same with Algorithm 1's literal index-range pairing;
     LUM       S_i = G_i (Definition of the LUM method);
+    MSCNR     the rowsum variant (section 3.1 step 2; Algorithm 1): with
+              MSCN's D-range, S_i = G_i - diag(F_i D_{r_i}^{-1} E_i 1), 1 the
+              all-ones vector; the printed expression subtracts a vector
+              from a matrix, read here as lumping each row's sum of the
+              correction onto the diagonal;
     EXACT_BJ  S_i = S(agg_i, agg_i), the diagonal blocks of the exact
               Schur complement S = G - F D^{-1} E (a test reference and the
               learned extension's target, not one of the paper's methods);
@@ -32,7 +37,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 from scipy.linalg import lapack
 
-MSCN, MSCN_LITERAL, LUM, EXACT_BJ, LEARNED = 0, 1, 2, 3, 4
+MSCN, MSCN_LITERAL, LUM, EXACT_BJ, LEARNED, MSCNR = 0, 1, 2, 3, 4, 5
 
 
 class SingularBlock(RuntimeError):
@@ -144,6 +149,20 @@ class Preconditioner:
                 if np.abs(np.diag(lu)).min() <= 1e-13 * np.abs(Di).max():
                     raise SingularBlock(f"D-range block {i} is singular")
                 out.append(Gi - Fi @ sla.lu_solve((lu, piv), Ei))
+            elif mode == MSCNR:
+                dr = part.drange(i)
+                if len(dr) == 0:
+                    out.append(Gi)
+                    continue
+                Di = C[dr][:, dr].toarray()
+                Ei = C[dr][:, agg].toarray()
+                Fi = C[agg][:, dr].toarray()
+                lu, piv = sla.lu_factor(Di)
+                if np.abs(np.diag(lu)).min() <= 1e-13 * np.abs(Di).max():
+                    raise SingularBlock(f"D-range block {i} is singular")
+                e = Ei @ np.ones(len(agg))                  # E_i 1
+                c = Fi @ sla.lu_solve((lu, piv), e)         # F_i D_{r_i}^{-1} E_i 1
+                out.append(Gi - np.diag(c))
             elif mode == EXACT_BJ:
                 cols = pos[agg] - self.ni
                 S = Gi.copy()

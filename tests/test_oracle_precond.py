@@ -11,7 +11,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from oracle.partition import Partition, build_partition
-from oracle.precond import EXACT_BJ, LUM, MSCN, MSCN_LITERAL, BandLU, Preconditioner, row_scale
+from oracle.precond import EXACT_BJ, LUM, MSCN, MSCN_LITERAL, MSCNR, BandLU, Preconditioner, row_scale
 from workloads.mac_oseen import make_oseen_mac
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -42,7 +42,7 @@ def test_band_lu_matches_dense_solve():
         assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("mode", [MSCN, LUM])
+@pytest.mark.parametrize("mode", [MSCN, LUM, MSCNR])
 def test_apply_equals_dense_block_factorisation(mode):
     """x = B^{-1} y with B = [D 0; F S][D^-1 0; 0 S^-1][D E; 0 S] built densely."""
     rp, ci, v, b, meta, P = _system(16, 0.1, None, 4, 24)
@@ -115,6 +115,43 @@ def test_lum_equals_mscn_when_coupling_vanishes():
     C = C.tocsr()
     C.sort_indices()
     p1 = Preconditioner(meta["N"], C.indptr, C.indices, C.data, P, MSCN)
+    p2 = Preconditioner(meta["N"], C.indptr, C.indices, C.data, P, LUM)
+    for a, bb in zip(p1.S_blocks, p2.S_blocks):
+        assert np.array_equal(a, bb)
+
+
+def test_mscnr_keeps_mscn_row_sums():
+    """The rowsum variant (section 3.1 step 2; Algorithm 1): S_i 1 equals the
+    full mini Schur complement's S_i 1, the off-diagonal entries are G_i's,
+    and the lumped correction is not trivially zero on this workload."""
+    rp, ci, v, b, meta, P = _system(16, 0.05, 1.05, 4, 24)
+    full = Preconditioner(meta["N"], rp, ci, v, P, MSCN)
+    lum = Preconditioner(meta["N"], rp, ci, v, P, LUM)
+    rs = Preconditioner(meta["N"], rp, ci, v, P, MSCNR)
+    moved = 0.0
+    for Sf, G, Sr in zip(full.S_blocks, lum.S_blocks, rs.S_blocks):
+        one = np.ones(Sf.shape[0])
+        scale = np.abs(Sf).sum(axis=1) + 1e-300
+        assert np.all(np.abs(Sr @ one - Sf @ one) <= 1e-12 * scale)
+        off = ~np.eye(Sf.shape[0], dtype=bool)
+        assert np.array_equal(Sr[off], G[off])
+        moved = max(moved, float(np.abs(np.diag(Sr) - np.diag(G)).max(initial=0.0)))
+    assert moved > 1e-3
+
+
+def test_mscnr_equals_lum_when_coupling_vanishes():
+    """With E_i = F_i = 0 the lumped correction vanishes: S_i = G_i."""
+    rp, ci, v, b, meta, P = _system(16, 0.1, None, 4, 24)
+    C = sp.csr_matrix((v, ci, rp)).tolil()
+    sep = set(P.separator().tolist())
+    dn = set(P.drange_nodes.tolist())
+    coo = sp.csr_matrix((v, ci, rp)).tocoo()
+    for r, c in zip(coo.row, coo.col):
+        if (r in sep and c in dn) or (r in dn and c in sep):
+            C[r, c] = 0.0
+    C = C.tocsr()
+    C.sort_indices()
+    p1 = Preconditioner(meta["N"], C.indptr, C.indices, C.data, P, MSCNR)
     p2 = Preconditioner(meta["N"], C.indptr, C.indices, C.data, P, LUM)
     for a, bb in zip(p1.S_blocks, p2.S_blocks):
         assert np.array_equal(a, bb)
