@@ -193,6 +193,7 @@ def bench_learned(args):
         res = {}
         plain = None
         for name, kw in (("mscn", dict(schur=addns.SCHUR_MSCN)), ("lum", dict(schur=addns.SCHUR_LUM)),
+                         ("mscnr", dict(schur=addns.SCHUR_MSCNR)),
                          ("learned_bf16", dict(schur=addns.SCHUR_LEARNED, learned_model=w,
                                                learned_bf16=True))):
             torch.cuda.synchronize()

@@ -56,11 +56,14 @@ enum {
 enum {
   ADDNS_SCHUR_MSCN = 0,         /* S_i = G_i - F_i D_{r_i}^-1 E_i, D-range = interior
                                    velocity neighbours of the aggregate (section 3.1
-                                   step 2b: D_{r_i} "slightly larger" than G_i) */
+                                   step 2b lets D_{r_i} exceed G_i in size) */
   ADDNS_SCHUR_MSCN_LITERAL = 1, /* D-range = the same positions of D (Algorithm 1) */
   ADDNS_SCHUR_LUM = 2,          /* S_i = G_i (LUM definition, section 3.3) */
   ADDNS_SCHUR_EXACT_BJ = 3,     /* diagonal blocks of the exact S = G - F D^-1 E */
-  ADDNS_SCHUR_LEARNED = 4       /* G_i plus a learned correction (opts.learned_model) */
+  ADDNS_SCHUR_LEARNED = 4,      /* G_i plus a learned correction (opts.learned_model) */
+  ADDNS_SCHUR_MSCNR = 5         /* rowsum variant (section 3.1 step 2; Algorithm 1):
+                                   S_i = G_i - diag(F_i D_{r_i}^-1 E_i 1), MSCN's
+                                   D-range; row sums of S_i equal MSCN's */
 };
 
 /* Storage precision of the preconditioner's factors (arithmetic is FP64 for

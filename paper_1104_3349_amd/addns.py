@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libaddns.so")
 
 OK, WARN_SHARED_PAIR = 0, 1
 ERR_ARG, ERR_SINGULAR, ERR_NOCONV, ERR_HIP, ERR_PARTITION, ERR_NOMEM = -1, -2, -3, -4, -5, -6
-SCHUR_MSCN, SCHUR_MSCN_LITERAL, SCHUR_LUM, SCHUR_EXACT_BJ, SCHUR_LEARNED = 0, 1, 2, 3, 4
+SCHUR_MSCN, SCHUR_MSCN_LITERAL, SCHUR_LUM, SCHUR_EXACT_BJ, SCHUR_LEARNED, SCHUR_MSCNR = 0, 1, 2, 3, 4, 5
 F64, F32, F16_SCALED = 0, 1, 2
 
 EXPORTED = [

@@ -181,11 +181,11 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
                                 pc->f_vals.as<double>(), U.as<double>(), G, s);
       ADDNS_HIP(hipStreamSynchronize(s));
     }
-    if (o.schur == ADDNS_SCHUR_MSCN || o.schur == ADDNS_SCHUR_MSCN_LITERAL)
+    if (o.schur == ADDNS_SCHUR_MSCN || o.schur == ADDNS_SCHUR_MSCN_LITERAL || o.schur == ADDNS_SCHUR_MSCNR)
       launch_schur_blocks(k, pc->agg_s.as<int32_t>(), agg_d.as<int32_t>(), g_off.as<int64_t>(), dd_off.as<int64_t>(),
                           de_off.as<int64_t>(), df_off.as<int64_t>(), G, G + pl.g_total,
                           G + pl.g_total + pl.dd_total, G + pl.g_total + pl.dd_total + pl.de_total,
-                          info.as<int32_t>() + m + 1, s);
+                          info.as<int32_t>() + m + 1, o.schur == ADDNS_SCHUR_MSCNR ? 1 : 0, s);
     pc->schur_S.alloc(sizeof(double) * pl.g_total);
     ADDNS_HIP(hipMemcpyAsync(pc->schur_S.p, G, sizeof(double) * pl.g_total, hipMemcpyDeviceToDevice, s));
     pc->sinv.alloc((int64_t)prec_bytes(sprec) * pl.g_total);
@@ -315,7 +315,7 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
     if (N != p->d.N) throw ArgError("N does not match the partition");
     addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1, 0};
     if (opts) o = *opts;
-    if (o.schur < 0 || o.schur > ADDNS_SCHUR_LEARNED) throw ArgError("unknown schur mode");
+    if (o.schur < 0 || o.schur > ADDNS_SCHUR_MSCNR) throw ArgError("unknown schur mode");
     if (o.block_mult < 0 || o.block_mult > 4) throw ArgError("block_mult must be 0..4");
     const bool autotune = o.block_mult == 0;
     if (o.schur == ADDNS_SCHUR_LEARNED && !o.learned_model) throw ArgError("LEARNED mode needs learned_model");

@@ -336,6 +336,11 @@ k_convert_upper(const double* __restrict__ ab_all, const SubInfo* __restrict__ s
 // Gaussian elimination with partial pivoting of [D | E] turns E into
 // L^{-1} P E; back substitution with U gives X = D^{-1} E; then
 // G <- G - F X on MFMA (v_mfma_f64_16x16x4f64).
+// rowsum != 0 (the rowsum variant of section 3.1): E is first collapsed to
+// its row sums e = E 1 (kept in E's column 0), the elimination carries that
+// one column, and the correction c = F D^{-1} e is subtracted from G's
+// diagonal, so each row of S_i keeps the row sum of the full mini Schur
+// complement.
 // ---------------------------------------------------------------------------
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
@@ -344,7 +349,7 @@ k_schur_blocks(const int32_t* __restrict__ agg_s, const int32_t* __restrict__ ag
                const int64_t* __restrict__ g_off, const int64_t* __restrict__ dd_off,
                const int64_t* __restrict__ de_off, const int64_t* __restrict__ df_off, double* __restrict__ Gall,
                double* __restrict__ Dall, double* __restrict__ Eall, double* __restrict__ Fall,
-               int32_t* __restrict__ info) {
+               int32_t* __restrict__ info, int rowsum) {
   const int i = blockIdx.x;
   const int32_t s = agg_s[i], d = agg_d[i];
   if (d == 0) return;
@@ -353,7 +358,17 @@ k_schur_blocks(const int32_t* __restrict__ agg_s, const int32_t* __restrict__ ag
   double* E = Eall + de_off[i];
   double* F = Fall + df_off[i];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int32_t w = d + s;  // augmented row length
+  const int32_t se = rowsum ? 1 : s;  // right-hand sides carried through the elimination
+  const int32_t w = d + se;           // augmented row length
+  if (rowsum) {
+    // one thread per row: its sum in column order, stored over column 0
+    for (int32_t r = tid; r < d; r += blockDim.x) {
+      double a = 0.0;
+      for (int32_t q = 0; q < s; ++q) a += E[(int64_t)r * s + q];
+      E[(int64_t)r * s] = a;
+    }
+    __syncthreads();
+  }
   auto A = [&](int32_t r, int32_t c) -> double& { return c < d ? D[(int64_t)r * d + c] : E[(int64_t)r * s + (c - d)]; };
   __shared__ int32_t s_p;
   __shared__ double s_piv;
@@ -413,13 +428,22 @@ k_schur_blocks(const int32_t* __restrict__ agg_s, const int32_t* __restrict__ ag
   // back substitution: E <- U^{-1} E (rows from the bottom)
   for (int32_t r = d - 1; r >= 0; --r) {
     const double dinv = 1.0 / A(r, r);
-    for (int32_t q = tid; q < s; q += blockDim.x) E[(int64_t)r * s + q] *= dinv;
+    for (int32_t q = tid; q < se; q += blockDim.x) E[(int64_t)r * s + q] *= dinv;
     __syncthreads();
-    for (int64_t t = tid; t < (int64_t)r * s; t += blockDim.x) {
-      int32_t rr = (int32_t)(t / s), q = (int32_t)(t % s);
+    for (int64_t t = tid; t < (int64_t)r * se; t += blockDim.x) {
+      int32_t rr = (int32_t)(t / se), q = (int32_t)(t % se);
       E[(int64_t)rr * s + q] -= D[(int64_t)rr * d + r] * E[(int64_t)r * s + q];
     }
     __syncthreads();
+  }
+  if (rowsum) {
+    // G(r, r) <- G(r, r) - sum_k F(r, k) x(k), x = D^{-1} e in E's column 0
+    for (int32_t r = tid; r < s; r += blockDim.x) {
+      double a = 0.0;
+      for (int32_t k = 0; k < d; ++k) a += F[(int64_t)r * d + k] * E[(int64_t)k * s];
+      G[(int64_t)r * s + r] -= a;
+    }
+    return;
   }
   // G <- G - F X with 16x16 output tiles, k in steps of 4 (FP64 MFMA).
   // Lane layout of v_mfma_f64_16x16x4f64 (checked on gfx950): A operand lane
@@ -635,8 +659,10 @@ void launch_convert_upper(const double* ab, const SubInfo* subs, const UBlk* ub,
 }
 void launch_schur_blocks(int32_t k, const int32_t* agg_s, const int32_t* agg_d, const int64_t* g_off,
                          const int64_t* dd_off, const int64_t* de_off, const int64_t* df_off, double* G, double* Dd,
-                         double* De, double* Df, int32_t* info, hipStream_t s) {
-  if (k > 0) k_schur_blocks<<<k, kSetupThreads, 0, s>>>(agg_s, agg_d, g_off, dd_off, de_off, df_off, G, Dd, De, Df, info);
+                         double* De, double* Df, int32_t* info, int rowsum, hipStream_t s) {
+  if (k > 0)
+    k_schur_blocks<<<k, kSetupThreads, 0, s>>>(agg_s, agg_d, g_off, dd_off, de_off, df_off, G, Dd, De, Df, info,
+                                              rowsum);
 }
 void launch_invert_dense(int32_t k, const int32_t* agg_s, const int64_t* g_off, const double* S, double* work,
                          int32_t* info, const int64_t* sinv_off, void* sinv, float* scale, int prec, hipStream_t s) {

@@ -192,7 +192,7 @@ void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult
   std::vector<std::vector<int32_t>> drange(k);  // new numbering
   for (int32_t i = 0; i < k; ++i) {
     pl.agg_s[i] = P.agg_offsets[i + 1] - P.agg_offsets[i];
-    if (schur_mode == ADDNS_SCHUR_MSCN) {
+    if (schur_mode == ADDNS_SCHUR_MSCN || schur_mode == ADDNS_SCHUR_MSCNR) {
       for (int32_t t = P.drange_offsets[i]; t < P.drange_offsets[i + 1]; ++t)
         drange[i].push_back(pl.iperm[P.drange_nodes[t]]);
     } else if (schur_mode == ADDNS_SCHUR_MSCN_LITERAL) {

@@ -192,7 +192,7 @@ void launch_dense_scatter(const int64_t* dst, const int32_t* src, const double* 
                           hipStream_t s);
 void launch_schur_blocks(int32_t k, const int32_t* agg_s, const int32_t* agg_d, const int64_t* g_off,
                          const int64_t* dd_off, const int64_t* de_off, const int64_t* df_off, double* G,
-                         double* Dd, double* De, double* Df, int32_t* info, hipStream_t s);
+                         double* Dd, double* De, double* Df, int32_t* info, int rowsum, hipStream_t s);
 void launch_invert_dense(int32_t k, const int32_t* agg_s, const int64_t* g_off, const double* S,
                          double* work, int32_t* info, const int64_t* sinv_off, void* sinv, float* scale,
                          int prec, hipStream_t s);

@@ -7,12 +7,12 @@ from dataclasses import dataclass
 import numpy as np
 
 from oracle.partition import build_partition as oracle_partition
-from oracle.precond import EXACT_BJ, LUM, MSCN, MSCN_LITERAL, Preconditioner
+from oracle.precond import EXACT_BJ, LUM, MSCN, MSCN_LITERAL, MSCNR, Preconditioner
 from paper_1104_3349_amd import addns
 from workloads.mac_oseen import Wind, make_oseen_mac
 
 ORACLE_MODE = {addns.SCHUR_MSCN: MSCN, addns.SCHUR_LUM: LUM, addns.SCHUR_MSCN_LITERAL: MSCN_LITERAL,
-               addns.SCHUR_EXACT_BJ: EXACT_BJ}
+               addns.SCHUR_EXACT_BJ: EXACT_BJ, addns.SCHUR_MSCNR: MSCNR}
 
 
 @dataclass

@@ -57,7 +57,7 @@ def case(request):
     return request.param, S
 
 
-@pytest.mark.parametrize("schur", [addns.SCHUR_MSCN, addns.SCHUR_LUM])
+@pytest.mark.parametrize("schur", [addns.SCHUR_MSCN, addns.SCHUR_LUM, addns.SCHUR_MSCNR])
 def test_schur_blocks(case, schur):
     name, S = case
     ora = oracle_precond(S, schur)
@@ -89,7 +89,7 @@ def test_interior_solve(case):
     assert e <= 1e-9
 
 
-@pytest.mark.parametrize("schur", [addns.SCHUR_MSCN, addns.SCHUR_LUM])
+@pytest.mark.parametrize("schur", [addns.SCHUR_MSCN, addns.SCHUR_LUM, addns.SCHUR_MSCNR])
 def test_apply(case, schur):
     name, S = case
     ora = oracle_precond(S, schur)
@@ -144,12 +144,13 @@ def test_apply_mixed(case, iprec, sprec, tol):
     assert e <= tol
 
 
-@pytest.mark.parametrize("flexible", [True, False])
-def test_gmres_equal_iterations(case, flexible):
+@pytest.mark.parametrize("flexible,schur", [(True, addns.SCHUR_MSCN), (False, addns.SCHUR_MSCN),
+                                            (True, addns.SCHUR_MSCNR)])
+def test_gmres_equal_iterations(case, flexible, schur):
     """Iterates after the same number of steps agree to 1e-10 relative."""
     name, S = case
-    ora = oracle_precond(S)
-    part, pc = gpu_precond(S)
+    ora = oracle_precond(S, schur)
+    part, pc = gpu_precond(S, schur)
     k = 12 if name != "cfg2" else 8
     restart = 5
     bt = ora.R * S.b
@@ -160,7 +161,7 @@ def test_gmres_equal_iterations(case, flexible):
                           history=True)
     assert r["iters"] == k and not r["converged"]
     e = relerr(d_x.cpu().numpy(), ref.x)
-    MEASURED[f"gmres_equal_its_{name}_{flexible}"] = e
+    MEASURED[f"gmres_equal_its_{name}_{flexible}_{schur}"] = e
     assert e <= 1e-10
     assert abs(r["true_relres"] - ref.true_relres) <= 1e-8 * max(ref.true_relres, 1e-300) + 1e-14
     np.testing.assert_allclose(r["history"], ref.est_history, rtol=1e-8, atol=0)
@@ -233,7 +234,8 @@ def _generic_system(n=20, seed=3):
     return System(n, N, A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data, b, {}, 4, 10)
 
 
-@pytest.mark.parametrize("schur", [addns.SCHUR_MSCN, addns.SCHUR_MSCN_LITERAL, addns.SCHUR_LUM])
+@pytest.mark.parametrize("schur", [addns.SCHUR_MSCN, addns.SCHUR_MSCN_LITERAL, addns.SCHUR_LUM,
+                                   addns.SCHUR_MSCNR])
 def test_generic_matrix(schur):
     """The method is purely algebraic: a matrix without saddle-point
     structure goes through the same path (literal Algorithm-1 pairing is
@@ -294,6 +296,10 @@ def test_setup_argument_errors():
     with pytest.raises(addns.AddnsError) as e:
         addns.setup_precond(part, S.N + 1, _cuda(S.rp), _cuda(S.ci), _cuda(S.v))
     assert e.value.code == addns.ERR_ARG
+    for mode in (-1, addns.SCHUR_MSCNR + 1):
+        with pytest.raises(addns.AddnsError) as e:
+            addns.setup_precond(part, S.N, _cuda(S.rp), _cuda(S.ci), _cuda(S.v), schur=mode)
+        assert e.value.code == addns.ERR_ARG and "schur mode" in str(e.value)
     part2, pc = gpu_precond(S)
     d = torch.zeros(S.N, dtype=torch.float64, device="cuda")
     with pytest.raises(addns.AddnsError):
