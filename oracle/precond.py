@@ -26,6 +26,17 @@ Plain FP64, no blocking or fusion beyond what the paper states:
               Schur complement S = G - F D^{-1} E (a test reference and the
               learned extension's target, not one of the paper's methods);
   then Shat = blkDiag(S_i), each block LU-factorised with partial pivoting;
+* overlapped aggregates (the overlap Remark of section 3.1; Algorithm 1's
+  overlapped branch; OMSCN / OMSCNR / OLUM): aggregate i is extended by
+  the first w_i separator positions of aggregate i+1, with
+  w_i = min(w, s_i - 1, s_{i+1}) (Algorithm 1 requires w_i < s_i; the
+  second bound keeps the extension inside aggregate i+1) and w_k = 0.  The
+  extended block S_i^e is formed by the mode's formula on the extended node
+  set, with the D-range of aggregate i followed by that of aggregate i+1.
+  Assembly (section 3.1 step 4, read column-wise): the columns of S_i^e that
+  belong to aggregate i's own nodes, all of their rows, are written into
+  those columns of Shat, which is then block lower bidiagonal; it is
+  factorised as one sparse matrix;
 * apply (Algorithm 2, with E and F placed as the block factorisation of the
   MSCN definition requires):
     z1 = D^{-1} y1;  x2 = Shat^{-1} (y2 - F z1);  x1 = z1 - D^{-1} (E x2).
@@ -35,6 +46,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 from scipy.linalg import lapack
 
 MSCN, MSCN_LITERAL, LUM, EXACT_BJ, LEARNED, MSCNR = 0, 1, 2, 3, 4, 5
@@ -87,7 +99,11 @@ class Preconditioner:
     """B of the MSCN definition (section 3.3) built by Algorithm 1."""
 
     def __init__(self, N, rowptr, colidx, vals, part, mode=MSCN, row_scaling=True,
-                 learned_S=None):
+                 learned_S=None, overlap=0):
+        if overlap < 0:
+            raise ValueError("overlap must be >= 0")
+        if overlap > 0 and mode not in (MSCN, MSCNR, LUM):
+            raise ValueError("overlapped aggregates are defined for MSCN, MSCNR and LUM")
         self.N = N
         self.part = part
         vals = np.asarray(vals, dtype=np.float64)
@@ -107,8 +123,18 @@ class Preconditioner:
             a, b = part.int_offsets[j], part.int_offsets[j + 1]
             self.blocks.append((a, b, BandLU(Cp[a:b, a:b])))
         self.mode = mode
+        self.overlap = overlap
+        k = part.k
+        s = np.diff(part.agg_offsets)
+        self.widths = np.zeros(k, dtype=np.int64)
+        if overlap > 0:
+            for i in range(k - 1):
+                self.widths[i] = min(overlap, s[i] - 1, s[i + 1])
         self.S_blocks = self._schur_blocks(mode, learned_S)
         self.S_lu = []
+        if overlap > 0:
+            self._assemble_overlapped()
+            return
         for i, S in enumerate(self.S_blocks):
             if S.shape[0] == 0:
                 self.S_lu.append(None)
@@ -119,15 +145,43 @@ class Preconditioner:
                 raise SingularBlock(f"interface block {i} is singular")
             self.S_lu.append((lu, piv))
 
+    def _assemble_overlapped(self):
+        """Shat from the extended blocks, column-wise (section 3.1 step 4).
+        Its diagonal blocks are the leading s_i x s_i parts of the S_i^e;
+        each must be nonsingular (Shat is block lower triangular)."""
+        off = self.part.agg_offsets
+        ns = self.part.sep_size
+        rows, cols, vals = [], [], []
+        for i, Se in enumerate(self.S_blocks):
+            a, b = off[i], off[i + 1]
+            A = Se[:b - a, :b - a]
+            if A.size:
+                lu, piv = sla.lu_factor(A)
+                if np.abs(np.diag(lu)).min() <= 1e-13 * max(np.abs(A).max(), 1e-300):
+                    raise SingularBlock(f"interface block {i} is singular")
+            rr, cc = np.meshgrid(np.arange(Se.shape[0]), np.arange(b - a), indexing="ij")
+            rows.append((a + rr).ravel())
+            cols.append((a + cc).ravel())
+            vals.append(Se[:, :b - a].ravel())
+        r = np.concatenate(rows) if rows else np.zeros(0, np.int64)
+        c = np.concatenate(cols) if cols else np.zeros(0, np.int64)
+        v = np.concatenate(vals) if vals else np.zeros(0)
+        self.Shat = sp.csc_matrix((v, (r, c)), shape=(ns, ns))
+        self.Shat_lu = spla.splu(self.Shat) if ns else None
+
     # ---- Algorithm 1 ----
     def _schur_blocks(self, mode, learned_S):
         part = self.part
         C = self.C
         pos = np.empty(self.N, dtype=np.int64)
         pos[part.perm] = np.arange(self.N)
+        sep = part.perm[part.n_int:]
         out = []
         for i in range(part.k):
             agg = part.aggregate(i)
+            w = int(self.widths[i])
+            if w > 0:
+                agg = sep[part.agg_offsets[i]:part.agg_offsets[i + 1] + w]
             Gi = C[agg][:, agg].toarray()
             if mode == LUM:
                 out.append(Gi)
@@ -139,6 +193,8 @@ class Preconditioner:
                     dr = part.perm[part.agg_offsets[i]:part.agg_offsets[i + 1]]
                 else:
                     dr = part.drange(i)
+                    if w > 0:
+                        dr = np.concatenate([dr, part.drange(i + 1)])
                 if len(dr) == 0:
                     out.append(Gi)
                     continue
@@ -151,6 +207,8 @@ class Preconditioner:
                 out.append(Gi - Fi @ sla.lu_solve((lu, piv), Ei))
             elif mode == MSCNR:
                 dr = part.drange(i)
+                if w > 0:
+                    dr = np.concatenate([dr, part.drange(i + 1)])
                 if len(dr) == 0:
                     out.append(Gi)
                     continue
@@ -187,6 +245,8 @@ class Preconditioner:
         return z
 
     def schur_solve(self, t):
+        if self.overlap > 0:
+            return self.Shat_lu.solve(t) if len(t) else np.zeros_like(t)
         x = np.empty_like(t)
         off = self.part.agg_offsets
         for i, f in enumerate(self.S_lu):
@@ -216,7 +276,10 @@ class Preconditioner:
         Cp = self.C[self.part.perm][:, self.part.perm].toarray()
         ni = self.ni
         D, E, F, G = Cp[:ni, :ni], Cp[:ni, ni:], Cp[ni:, :ni], Cp[ni:, ni:]
-        Shat = sla.block_diag(*self.S_blocks) if self.S_blocks else np.zeros((0, 0))
+        if self.overlap > 0:
+            Shat = self.Shat.toarray()
+        else:
+            Shat = sla.block_diag(*self.S_blocks) if self.S_blocks else np.zeros((0, 0))
         return D, E, F, G, Shat
 
     def fill_factor(self):

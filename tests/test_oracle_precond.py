@@ -42,11 +42,12 @@ def test_band_lu_matches_dense_solve():
         assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("mode", [MSCN, LUM, MSCNR])
-def test_apply_equals_dense_block_factorisation(mode):
+@pytest.mark.parametrize("mode,overlap", [(MSCN, 0), (LUM, 0), (MSCNR, 0), (MSCN, 23), (MSCNR, 5),
+                                          (LUM, 23)])
+def test_apply_equals_dense_block_factorisation(mode, overlap):
     """x = B^{-1} y with B = [D 0; F S][D^-1 0; 0 S^-1][D E; 0 S] built densely."""
     rp, ci, v, b, meta, P = _system(16, 0.1, None, 4, 24)
-    pre = Preconditioner(meta["N"], rp, ci, v, P, mode)
+    pre = Preconditioner(meta["N"], rp, ci, v, P, mode, overlap=overlap)
     D, E, F, G, Sh = pre.dense_blocks()
     ni, ns = D.shape[0], Sh.shape[0]
     L = np.block([[D, np.zeros((ni, ns))], [F, Sh]])
@@ -155,6 +156,77 @@ def test_mscnr_equals_lum_when_coupling_vanishes():
     p2 = Preconditioner(meta["N"], C.indptr, C.indices, C.data, P, LUM)
     for a, bb in zip(p1.S_blocks, p2.S_blocks):
         assert np.array_equal(a, bb)
+
+
+def _ext_sets(P, i, w):
+    sep = P.perm[P.n_int:]
+    a, b = P.agg_offsets[i], P.agg_offsets[i + 1]
+    dr = P.drange(i) if w == 0 else np.concatenate([P.drange(i), P.drange(i + 1)])
+    return sep[a:b + w], dr
+
+
+def test_overlap_widths():
+    """w_i = min(w, s_i - 1, s_{i+1}) for i < k and w_k = 0 (Algorithm 1:
+    w_i below the aggregate's own size; the extension stays in aggregate i+1)."""
+    rp, ci, v, b, meta, P = _system(16, 0.1, None, 4, 24)
+    s = np.diff(P.agg_offsets)
+    assert s[-1] < s[0]      # a short remainder aggregate at the end
+    for w in (1, 7, 23, 100):
+        pre = Preconditioner(meta["N"], rp, ci, v, P, LUM, overlap=w)
+        want = [min(w, s[i] - 1, s[i + 1]) for i in range(P.k - 1)] + [0]
+        assert pre.widths.tolist() == want
+
+
+def test_overlapped_block_is_local_schur_complement():
+    """Each extended block is the Schur complement of its local system
+    [D_e E_e; F_e G_e]: its inverse is the trailing block of the local
+    inverse (block-inverse identity, independent of how S_i^e is formed)."""
+    rp, ci, v, b, meta, P = _system(16, 0.05, 1.05, 4, 24)
+    pre = Preconditioner(meta["N"], rp, ci, v, P, MSCN, overlap=23)
+    C = pre.C
+    checked = 0
+    for i, Se in enumerate(pre.S_blocks):
+        nodes, dr = _ext_sets(P, i, int(pre.widths[i]))
+        assert Se.shape == (len(nodes), len(nodes))
+        if len(dr) == 0:
+            continue
+        idx = np.concatenate([dr, nodes])
+        loc = C[idx][:, idx].toarray()
+        tail = np.linalg.inv(loc)[len(dr):, len(dr):]
+        ref = np.linalg.inv(Se)
+        assert np.abs(tail - ref).max() <= 1e-9 * np.abs(ref).max()
+        checked += pre.widths[i] > 0
+    assert checked >= 2
+
+
+def test_olum_shat_is_g_on_the_column_pattern():
+    """With S_i^e = G_i^e the column-wise assembly gives Shat(r, c) = G(r, c)
+    for c in aggregate i and r in aggregate i or in the first w_i rows of
+    aggregate i+1, and zero everywhere else (block lower bidiagonal)."""
+    rp, ci, v, b, meta, P = _system(16, 0.1, None, 4, 24)
+    pre = Preconditioner(meta["N"], rp, ci, v, P, LUM, overlap=23)
+    D, E, F, G, Sh = pre.dense_blocks()
+    mask = np.zeros_like(G, dtype=bool)
+    off = P.agg_offsets
+    for i in range(P.k):
+        mask[off[i]:off[i + 1] + pre.widths[i], off[i]:off[i + 1]] = True
+    assert np.array_equal(Sh[mask], G[mask])
+    assert not Sh[~mask].any()
+    assert np.abs(G[~mask & np.tril(np.ones_like(mask), -1).astype(bool)]).max() > 0  # G is cut
+
+
+def test_overlap_lowers_iterations():
+    """The overlap Remark of section 3.1 (and the tables of section 5): the
+    overlapped method needs fewer iterations than the non-overlapped one."""
+    from oracle.krylov import solve_system
+    rp, ci, v, b, meta, P = _system(48, 0.005, 1.05, 6, 40, seed=1002)
+    its = {}
+    for w in (0, 39):
+        pre = Preconditioner(meta["N"], rp, ci, v, P, MSCN, overlap=w)
+        r = solve_system(pre, b, restart=50, tol=1e-8, maxit=2000, flexible=True)
+        assert r.converged
+        its[w] = r.iters
+    assert its[39] < 0.95 * its[0], its
 
 
 def test_single_subdomain_is_exact():
