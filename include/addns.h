@@ -135,6 +135,20 @@ typedef struct {
                              the faster (the results are the same bit for bit) */
   int32_t learned_bf16;   /* LEARNED only: 1 = run the network with BF16-rounded
                              weights and activations, 0 = FP32 */
+  int32_t overlap;        /* overlapped aggregates, w >= 0 (0 = none; the overlap
+                             Remark of section 3.1 and Algorithm 1's overlapped
+                             branch: OMSCN, OMSCNR, OLUM with schur = MSCN, MSCNR,
+                             LUM; any other mode gives ADDNS_ERR_ARG).  Aggregate i
+                             is extended by the first w_i = min(w, s_i - 1, s_{i+1})
+                             separator positions of aggregate i+1 (w_k = 0); its
+                             D-range is aggregate i's followed by aggregate i+1's.
+                             The columns of each extended block S_i^e that belong
+                             to aggregate i go, with all their rows, into Shat,
+                             which becomes block lower bidiagonal; the interface
+                             solve is then a forward substitution over the
+                             aggregates (k - 1 dependent steps in one workgroup).
+                             Needs every aggregate to hold at most 128 nodes
+                             and at most 12000 aggregates (else ADDNS_ERR_ARG) */
 } addns_precond_opts;
 
 /* ------------------------------------------------------------------------
@@ -238,7 +252,8 @@ int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb
 
 /* Copy the dense interface blocks S_i (before inversion) into a HOST array
    in aggregate order, row-major per block; `count` must equal the sum of
-   |agg_i|^2. */
+   |agg_i|^2.  With overlapped aggregates these are the extended blocks
+   S_i^e, (s_i + w_i)^2 numbers each. */
 int addns_precond_schur_blocks(addns_precond_t pc, double* h_out, int64_t count);
 
 /* ========================================================================
@@ -273,7 +288,8 @@ int addns_dtn_param_count(void);
    targets are S_i - G_i of the teacher's interface blocks.  With all three
    NULL only *count is set (a size query).  cap: capacity in samples.
    Asynchronous on `stream`.  ADDNS_ERR_ARG for a LEARNED handle, Y without
-   M (or M without Y), or cap < count. */
+   M (or M without Y), targets of a handle with overlapped aggregates, or
+   cap < count. */
 int addns_dtn_samples(addns_precond_t pc, float* d_X, float* d_Y, float* d_M, int64_t cap,
                       int64_t* count, void* stream);
 

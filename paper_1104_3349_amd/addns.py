@@ -42,7 +42,7 @@ class AddnsError(RuntimeError):
 class PrecondOpts(C.Structure):
     _fields_ = [("schur", C.c_int32), ("interior_prec", C.c_int32), ("schur_prec", C.c_int32),
                 ("row_scale", C.c_int32), ("learned_model", C.POINTER(C.c_float)),
-                ("block_mult", C.c_int32), ("learned_bf16", C.c_int32)]
+                ("block_mult", C.c_int32), ("learned_bf16", C.c_int32), ("overlap", C.c_int32)]
 
 
 class GmresOpts(C.Structure):
@@ -238,9 +238,9 @@ class Precond:
 
 def setup_precond(partition: Partition, N, d_rowptr, d_colidx, d_vals, schur=SCHUR_MSCN,
                   interior_prec=F64, schur_prec=F64, row_scale=1, learned_model=None,
-                  block_mult=1, learned_bf16=True, stream=None) -> Precond:
+                  block_mult=1, learned_bf16=True, overlap=0, stream=None) -> Precond:
     opts = PrecondOpts(int(schur), int(interior_prec), int(schur_prec), int(row_scale), None,
-                       int(block_mult), int(bool(learned_bf16)))
+                       int(block_mult), int(bool(learned_bf16)), int(overlap))
     if learned_model is not None:
         lm = np.ascontiguousarray(learned_model, dtype=np.float32)
         opts.learned_model = lm.ctypes.data_as(C.POINTER(C.c_float))

@@ -53,6 +53,7 @@ int addns_dtn_samples(addns_precond_t pc, float* d_X, float* d_Y, float* d_M, in
     if (!d_X && !d_Y && !d_M) return ADDNS_OK;  // size query
     if (pc->schur_mode == ADDNS_SCHUR_LEARNED) throw ArgError("a LEARNED preconditioner has no teacher blocks");
     if ((d_Y == nullptr) != (d_M == nullptr)) throw ArgError("Y and M go together");
+    if (d_Y && pc->plan.overlap > 0) throw ArgError("targets need non-overlapped teacher blocks");
     if (cap < n) throw ArgError("capacity smaller than the sample count");
     hipStream_t s = as_stream(stream);
     if (n > 0 && !pc->smp_row.p) {  // sample table uploaded on first use

@@ -24,7 +24,7 @@ int prec_bytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
 void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_rowptr, const int32_t* d_colidx,
                   const double* d_vals, const addns_precond_opts& o, hipStream_t s) {
   Plan& pl = pc->plan;
-  build_plan(P, pl, o.schur, o.block_mult);
+  build_plan(P, pl, o.schur, o.block_mult, o.overlap);
   const int32_t N = pl.N;
   const int64_t nnz = (int64_t)pl.cp_colidx.size();
 
@@ -123,6 +123,9 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
     int32_t smax = 0;
     for (int32_t i = 0; i < k; ++i) smax = std::max(smax, pl.agg_s[i]);
     if (smax > 1024) throw ArgError("aggregates larger than 1024 nodes are not supported");
+    if (o.overlap > 0 && smax > 128) throw ArgError("overlapped aggregates need aggregates of at most 128 nodes");
+    if (o.overlap > 0 && k > kMaxOverlapAggregates)
+      throw ArgError("overlapped aggregates: at most 12000 aggregates");
     const int64_t dense_n = pl.g_total + pl.dd_total + pl.de_total + pl.df_total;
     DevBuf dense, ddst, dsrc, agg_d, g_off, dd_off, de_off, df_off, work;
     dense.alloc(sizeof(double) * dense_n);
@@ -181,19 +184,45 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
                                 pc->f_vals.as<double>(), U.as<double>(), G, s);
       ADDNS_HIP(hipStreamSynchronize(s));
     }
+    DevBuf agg_e;  // extended aggregate sizes (= agg_s without overlap)
+    agg_e.upload(pl.agg_e, s);
     if (o.schur == ADDNS_SCHUR_MSCN || o.schur == ADDNS_SCHUR_MSCN_LITERAL || o.schur == ADDNS_SCHUR_MSCNR)
-      launch_schur_blocks(k, pc->agg_s.as<int32_t>(), agg_d.as<int32_t>(), g_off.as<int64_t>(), dd_off.as<int64_t>(),
+      launch_schur_blocks(k, agg_e.as<int32_t>(), agg_d.as<int32_t>(), g_off.as<int64_t>(), dd_off.as<int64_t>(),
                           de_off.as<int64_t>(), df_off.as<int64_t>(), G, G + pl.g_total,
                           G + pl.g_total + pl.dd_total, G + pl.g_total + pl.dd_total + pl.de_total,
                           info.as<int32_t>() + m + 1, o.schur == ADDNS_SCHUR_MSCNR ? 1 : 0, s);
     pc->schur_S.alloc(sizeof(double) * pl.g_total);
     ADDNS_HIP(hipMemcpyAsync(pc->schur_S.p, G, sizeof(double) * pl.g_total, hipMemcpyDeviceToDevice, s));
-    pc->sinv.alloc((int64_t)prec_bytes(sprec) * pl.g_total);
+    const int64_t a_total = pl.sinv_off[k];
+    pc->sinv.alloc((int64_t)prec_bytes(sprec) * a_total);
     pc->sinv_scale.alloc(sizeof(float) * k);
-    work.alloc(sizeof(double) * 2 * pl.g_total);
-    launch_invert_dense(k, pc->agg_s.as<int32_t>(), g_off.as<int64_t>(), G, work.as<double>(),
-                        info.as<int32_t>() + m + 2, pc->sinv_off.as<int64_t>(), pc->sinv.p,
-                        pc->sinv_scale.as<float>(), sprec, s);
+    work.alloc(sizeof(double) * 2 * a_total);
+    if (o.overlap == 0) {
+      launch_invert_dense(k, pc->agg_s.as<int32_t>(), g_off.as<int64_t>(), G, work.as<double>(),
+                          info.as<int32_t>() + m + 2, pc->sinv_off.as<int64_t>(), pc->sinv.p,
+                          pc->sinv_scale.as<float>(), sprec, s);
+    } else {
+      // Shat block lower bidiagonal: invert its diagonal blocks A_i, then
+      // form the chain matrices M_i from the FP64 inverses
+      DevBuf agg_w, l_off, A, L;
+      agg_w.upload(pl.agg_w, s);
+      l_off.upload(pl.l_off, s);
+      A.alloc(sizeof(double) * std::max<int64_t>(a_total, 1));
+      L.alloc(sizeof(double) * std::max<int64_t>(pl.l_off[k], 1));
+      launch_overlap_split(k, pc->agg_s.as<int32_t>(), agg_w.as<int32_t>(), g_off.as<int64_t>(),
+                           pc->sinv_off.as<int64_t>(), l_off.as<int64_t>(), G, A.as<double>(), L.as<double>(), s);
+      launch_invert_dense(k, pc->agg_s.as<int32_t>(), pc->sinv_off.as<int64_t>(), A.as<double>(), work.as<double>(),
+                          info.as<int32_t>() + m + 2, pc->sinv_off.as<int64_t>(), pc->sinv.p,
+                          pc->sinv_scale.as<float>(), sprec, s);
+      const int mdbl = sprec == P64 ? 1 : 0;
+      pc->ovl_moff.upload(pl.m_off, s);
+      pc->ovl_m.alloc((mdbl ? 8 : 4) * std::max<int64_t>(pl.m_off[k], 1));
+      launch_overlap_m(k, pc->agg_s.as<int32_t>(), agg_w.as<int32_t>(), pc->sinv_off.as<int64_t>(),
+                       l_off.as<int64_t>(), pc->ovl_moff.as<int64_t>(), pl.ovl_width, work.as<double>(),
+                       L.as<double>(), pc->ovl_m.p, mdbl, s);
+      pc->overlap_chain = k > 1 ? pl.ovl_width : 0;
+      ADDNS_HIP(hipStreamSynchronize(s));
+    }
     int32_t h2[2];
     ADDNS_HIP(hipMemcpyAsync(h2, info.as<int32_t>() + m + 1, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
     ADDNS_HIP(hipStreamSynchronize(s));
@@ -211,7 +240,9 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
   int64_t fbytes = 0;
   fbytes += pl.lmat_total * fb + pl.lperm_total * 4;
   fbytes += 2 * pl.u_total * fb;
-  fbytes += pl.g_total * prec_bytes(sprec);
+  const int64_t a_total = k > 0 ? pl.sinv_off[k] : 0;
+  const int64_t m_bytes = pc->overlap_chain ? pl.m_off[k] * (sprec == P64 ? 8 : 4) : 0;
+  fbytes += a_total * prec_bytes(sprec) + m_bytes;
   pc->factor_bytes = fbytes;
   // algorithmic bytes of one apply: band factors L (KL) and U (KL+KU+1) per
   // interior row read twice, pivots, E and F (value + index), Shat^-1, and six
@@ -219,7 +250,7 @@ void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_ro
   int64_t band = 0;
   for (int32_t j = 0; j < m; ++j) band += (int64_t)pl.subs[j].n * (2 * pl.subs[j].kl + pl.subs[j].ku + 1);
   pc->bytes_apply = 2 * band * fb + 2 * 4 * (int64_t)pl.n_int +
-                    (int64_t)(pl.e_src.size() + pl.f_src.size()) * 12 + pl.g_total * prec_bytes(sprec) +
+                    (int64_t)(pl.e_src.size() + pl.f_src.size()) * 12 + a_total * prec_bytes(sprec) + m_bytes +
                     6 * (int64_t)N * 8;
 }
 
@@ -227,8 +258,10 @@ void apply_permuted(addns_precond* pc, const double* yp, double* xp, hipStream_t
   const Plan& pl = pc->plan;
   // z1 = D^{-1} y1 (into the interior part of xp)
   launch_interior_solve(pc, yp, xp, 0, nullptr, nullptr, s);
-  // x2 = Shat^{-1} (y2 - F z1)
+  // x2 = Shat^{-1} (y2 - F z1): blockwise, then (overlapped aggregates) the
+  // forward substitution over Shat's lower blocks
   launch_interface_solve(pc, yp, xp, xp, s);
+  launch_overlap_chain(pc, xp + pl.n_int, s);
   // x1 = z1 - D^{-1} (E x2), in place
   if (pl.k > 0) launch_interior_solve(pc, nullptr, xp, 1, xp + pl.n_int, xp, s);
 }
@@ -313,9 +346,12 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
   return guarded("addns_setup_precond", [&]() -> int {
     if (!p || !out || !d_rowptr || !d_colidx || !d_vals) throw ArgError("null argument");
     if (N != p->d.N) throw ArgError("N does not match the partition");
-    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1, 0};
+    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1, 0, 0};
     if (opts) o = *opts;
     if (o.schur < 0 || o.schur > ADDNS_SCHUR_MSCNR) throw ArgError("unknown schur mode");
+    if (o.overlap < 0) throw ArgError("overlap must be >= 0");
+    if (o.overlap > 0 && o.schur != ADDNS_SCHUR_MSCN && o.schur != ADDNS_SCHUR_MSCNR && o.schur != ADDNS_SCHUR_LUM)
+      throw ArgError("overlapped aggregates are defined for MSCN, MSCNR and LUM");
     if (o.block_mult < 0 || o.block_mult > 4) throw ArgError("block_mult must be 0..4");
     const bool autotune = o.block_mult == 0;
     if (o.schur == ADDNS_SCHUR_LEARNED && !o.learned_model) throw ArgError("LEARNED mode needs learned_model");

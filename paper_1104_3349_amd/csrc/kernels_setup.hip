@@ -605,9 +605,73 @@ __global__ void k_exact_schur_update(const int32_t* __restrict__ pcol_ptr, const
   }
 }
 
+// ---------------------------------------------------------------------------
+// Overlapped aggregates.  The extended block S_i^e (e = s + w, row-major)
+// splits into its diagonal part A_i = S_i^e[0:s, 0:s] and the lower part
+// L_i = S_i^e[s:e, 0:s], which Shat holds below A_i in the first w rows of
+// aggregate i+1 (column-wise assembly).
+// ---------------------------------------------------------------------------
+__global__ void k_overlap_split(const int32_t* __restrict__ agg_s, const int32_t* __restrict__ agg_w,
+                                const int64_t* __restrict__ g_off, const int64_t* __restrict__ a_off,
+                                const int64_t* __restrict__ l_off, const double* __restrict__ Se_all,
+                                double* __restrict__ A_all, double* __restrict__ L_all) {
+  const int i = blockIdx.x;
+  const int32_t s = agg_s[i], w = agg_w[i], e = s + w;
+  const double* Se = Se_all + g_off[i];
+  double* A = A_all + a_off[i];
+  double* L = L_all + l_off[i];
+  for (int64_t t = threadIdx.x; t < (int64_t)e * s; t += blockDim.x) {
+    const int32_t r = (int32_t)(t / s), c = (int32_t)(t % s);
+    const double v = Se[(int64_t)r * e + c];
+    if (r < s) A[(int64_t)r * s + c] = v;
+    else L[(int64_t)(r - s) * s + c] = v;
+  }
+}
+
+// Chain matrices of the block forward substitution over Shat:
+//   x_i = A_i^{-1} t_i - M_i x_{i-1},  M_i = A_i^{-1}[:, 0:w_{i-1}] L_{i-1}
+// (s_i x s_{i-1}, row-major, rows `width` long with zeros past s_{i-1}),
+// from the FP64 inverse that k_invert_dense leaves in the right half of its
+// s x 2s work rows; FP64 sums in index order, stored as T.
+template <class T>
+__global__ void k_overlap_m(const int32_t* __restrict__ agg_s, const int32_t* __restrict__ agg_w,
+                            const int64_t* __restrict__ a_off, const int64_t* __restrict__ l_off,
+                            const int64_t* __restrict__ m_off, int32_t width, const double* __restrict__ work,
+                            const double* __restrict__ L_all, T* __restrict__ M_all) {
+  const int i = blockIdx.x + 1;
+  const int32_t s = agg_s[i], sp = agg_s[i - 1], wp = agg_w[i - 1];
+  const double* Winv = work + 2 * a_off[i];  // row r: [I | A_i^{-1}] of width 2s
+  const double* L = L_all + l_off[i - 1];      // wp x sp
+  const int32_t spp = width;
+  T* M = M_all + m_off[i];
+  for (int64_t t = threadIdx.x; t < (int64_t)s * spp; t += blockDim.x) {
+    const int32_t r = (int32_t)(t / spp), c = (int32_t)(t % spp);
+    double acc = 0.0;
+    if (c < sp)
+      for (int32_t q = 0; q < wp; ++q) acc += Winv[(int64_t)r * 2 * s + s + q] * L[(int64_t)q * sp + c];
+    M[t] = (T)acc;
+  }
+}
+
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
+
+void launch_overlap_split(int32_t k, const int32_t* agg_s, const int32_t* agg_w, const int64_t* g_off,
+                          const int64_t* a_off, const int64_t* l_off, const double* Se, double* A, double* L,
+                          hipStream_t s) {
+  if (k > 0) k_overlap_split<<<k, 256, 0, s>>>(agg_s, agg_w, g_off, a_off, l_off, Se, A, L);
+}
+
+void launch_overlap_m(int32_t k, const int32_t* agg_s, const int32_t* agg_w, const int64_t* a_off,
+                      const int64_t* l_off, const int64_t* m_off, int32_t width, const double* winv, const double* L,
+                      void* M, int m_double, hipStream_t s) {
+  if (k < 2) return;
+  if (m_double)
+    k_overlap_m<double><<<k - 1, 256, 0, s>>>(agg_s, agg_w, a_off, l_off, m_off, width, winv, L, (double*)M);
+  else
+    k_overlap_m<float><<<k - 1, 256, 0, s>>>(agg_s, agg_w, a_off, l_off, m_off, width, winv, L, (float*)M);
+}
 
 void launch_exact_schur_update(int32_t nsep, const int32_t* pcol_ptr, const int32_t* pair_sub, const int64_t* pair_off,
                                const SubInfo* subs, const int32_t* agg_of, const int32_t* agg_off, const int64_t* g_off,

@@ -12,7 +12,7 @@ namespace addns {
 
 static int32_t round_up(int32_t a, int32_t b) { return (a + b - 1) / b * b; }
 
-void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult) {
+void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult, int overlap) {
   const int32_t N = P.N;
   pl.N = N;
   pl.m = P.m;
@@ -189,12 +189,24 @@ void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult
   pl.agg_off = P.agg_offsets;
   pl.agg_s.resize(k);
   pl.agg_d.resize(k);
+  for (int32_t i = 0; i < k; ++i) pl.agg_s[i] = P.agg_offsets[i + 1] - P.agg_offsets[i];
+  // overlapped aggregates: aggregate i also takes the first w_i positions of
+  // aggregate i+1, w_i < s_i and w_i <= s_{i+1}; the last one takes none
+  pl.overlap = overlap;
+  pl.agg_w.assign(k, 0);
+  pl.agg_e.resize(k);
+  if (overlap > 0)
+    for (int32_t i = 0; i + 1 < k; ++i)
+      pl.agg_w[i] = std::max(0, std::min(overlap, std::min(pl.agg_s[i] - 1, pl.agg_s[i + 1])));
+  for (int32_t i = 0; i < k; ++i) pl.agg_e[i] = pl.agg_s[i] + pl.agg_w[i];
   std::vector<std::vector<int32_t>> drange(k);  // new numbering
   for (int32_t i = 0; i < k; ++i) {
-    pl.agg_s[i] = P.agg_offsets[i + 1] - P.agg_offsets[i];
     if (schur_mode == ADDNS_SCHUR_MSCN || schur_mode == ADDNS_SCHUR_MSCNR) {
-      for (int32_t t = P.drange_offsets[i]; t < P.drange_offsets[i + 1]; ++t)
-        drange[i].push_back(pl.iperm[P.drange_nodes[t]]);
+      // an extended aggregate's D-range: its own, then that of aggregate i+1
+      const int32_t last = pl.agg_w[i] > 0 ? i + 1 : i;
+      for (int32_t j = i; j <= last; ++j)
+        for (int32_t t = P.drange_offsets[j]; t < P.drange_offsets[j + 1]; ++t)
+          drange[i].push_back(pl.iperm[P.drange_nodes[t]]);
     } else if (schur_mode == ADDNS_SCHUR_MSCN_LITERAL) {
       for (int32_t s = P.agg_offsets[i]; s < P.agg_offsets[i + 1]; ++s) drange[i].push_back(s);
     }
@@ -205,13 +217,22 @@ void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult
   pl.de_off.assign(k + 1, 0);
   pl.df_off.assign(k + 1, 0);
   pl.sinv_off.assign(k + 1, 0);
+  pl.l_off.assign(k + 1, 0);
+  pl.m_off.assign(k + 1, 0);
+  {
+    int32_t smax = 0;
+    for (int32_t i = 0; i < k; ++i) smax = std::max(smax, pl.agg_s[i]);
+    pl.ovl_width = overlap > 0 ? overlap_chain_width(smax) : 0;
+  }
   for (int32_t i = 0; i < k; ++i) {
-    int64_t s = pl.agg_s[i], d = pl.agg_d[i];
-    pl.g_off[i + 1] = pl.g_off[i] + s * s;
+    int64_t s = pl.agg_s[i], e = pl.agg_e[i], d = pl.agg_d[i];
+    pl.g_off[i + 1] = pl.g_off[i] + e * e;
     pl.dd_off[i + 1] = pl.dd_off[i] + d * d;
-    pl.de_off[i + 1] = pl.de_off[i] + d * s;
-    pl.df_off[i + 1] = pl.df_off[i] + s * d;
+    pl.de_off[i + 1] = pl.de_off[i] + d * e;
+    pl.df_off[i + 1] = pl.df_off[i] + e * d;
     pl.sinv_off[i + 1] = pl.sinv_off[i] + s * s;
+    pl.l_off[i + 1] = pl.l_off[i] + (int64_t)pl.agg_w[i] * s;
+    pl.m_off[i + 1] = pl.m_off[i] + (i > 0 ? s * pl.ovl_width : 0);
   }
   // learned-correction samples: separator velocity rows, five stencil slots
   pl.smp_row.clear();
@@ -234,7 +255,7 @@ void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult
       int32_t nb[5] = {lo.size() > 1 ? lo[1].second : -1, lo.size() > 0 ? lo[0].second : -1, r,
                        hi.size() > 0 ? hi[0].second : -1, hi.size() > 1 ? hi[1].second : -1};
       const int32_t i = pl.agg_of[c];
-      const int32_t a = c - P.agg_offsets[i], s = pl.agg_s[i];
+      const int32_t a = c - P.agg_offsets[i], s = pl.agg_e[i];  // row stride of the dense block
       pl.smp_row.push_back(r);
       for (int q = 0; q < 5; ++q) {
         pl.smp_nb.push_back(nb[q]);
@@ -257,7 +278,7 @@ void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult
   pl.dense_src.clear();
   std::vector<int32_t> posA(N, -1), posD(N, -1);
   for (int32_t i = 0; i < k; ++i) {
-    const int32_t s = pl.agg_s[i], d = pl.agg_d[i];
+    const int32_t s = pl.agg_e[i], d = pl.agg_d[i];  // extended size (= s_i without overlap)
     for (int32_t a = 0; a < s; ++a) posA[pl.n_int + pl.agg_off[i] + a] = a;
     for (int32_t a = 0; a < d; ++a) posD[drange[i][a]] = a;
     // rows of the aggregate: G_i and F_i

@@ -114,6 +114,13 @@ struct Plan {
   // dense Schur blocks (aggregate i: s_i = |agg|, d_i = |D-range|)
   std::vector<int32_t> agg_off, agg_s, agg_d;    // agg_off: k+1 separator positions
   std::vector<int64_t> g_off, dd_off, de_off, df_off, sinv_off;  // element offsets
+  // overlapped aggregates: width w_i, extended size e_i = s_i + w_i (the
+  // dense G/E/F blocks are e_i wide), the lower blocks L_i (w_i x s_i) of
+  // Shat and the chain matrices M_i = A_i^{-1} [L_{i-1}; 0] (s_i x s_{i-1},
+  // rows stored ovl_width wide, zero-padded)
+  int32_t overlap = 0, ovl_width = 0;
+  std::vector<int32_t> agg_w, agg_e;
+  std::vector<int64_t> l_off, m_off;
   std::vector<int64_t> dense_dst;                // scratch element index
   std::vector<int32_t> dense_src;                // C~p entry
   int64_t g_total = 0, dd_total = 0, de_total = 0, df_total = 0;
@@ -129,11 +136,15 @@ struct Plan {
   std::vector<int64_t> smp_loc;                  // 5 per sample: element of the dense G/S block or -1
 };
 
-void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult);
+void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult, int overlap);
 
 // Bytes past the end of each interior factor array that the sweep may read
 // (its last row slot can overrun a block by up to 64 * 5 - 1 FP64 rows).
 constexpr int64_t kSweepOverrunBytes = 4096;
+
+// Largest aggregate count of the overlapped interface solve (its chain
+// keeps 12 bytes per aggregate in LDS).
+constexpr int32_t kMaxOverlapAggregates = 12000;
 
 // Storage precision tags
 enum Prec { P64 = 0, P32 = 1, P16S = 2 };
@@ -155,6 +166,10 @@ struct addns_precond {
   addns::DevBuf uinv, u12;                            // per U-block
   // interface
   addns::DevBuf agg_off, agg_s, sinv_off, sinv, sinv_scale, schur_S;
+  // overlapped aggregates: chain matrices M_i (FP64 with FP64 interface
+  // storage, else FP32) applied by the block forward substitution over Shat
+  addns::DevBuf ovl_m, ovl_moff;
+  int overlap_chain = 0;                              // 0: none, else the chain matrices' row width (64, 80, 128)
   // scratch
   addns::DevBuf ypad, zpad, z1, x2tmp;                // padded interior work vectors
   addns::DevBuf vperm_in, vperm_out;                  // permuted apply in/out
@@ -206,6 +221,14 @@ void launch_exact_schur_update(int32_t nsep, const int32_t* pcol_ptr, const int3
                                const double* U, double* S, hipStream_t s);
 void launch_interface_solve(const addns_precond* pc, const double* y, const double* z1, double* x2out,
                             hipStream_t s);
+void launch_overlap_split(int32_t k, const int32_t* agg_s, const int32_t* agg_w, const int64_t* g_off,
+                          const int64_t* a_off, const int64_t* l_off, const double* Se, double* A, double* L,
+                          hipStream_t s);
+void launch_overlap_m(int32_t k, const int32_t* agg_s, const int32_t* agg_w, const int64_t* a_off,
+                      const int64_t* l_off, const int64_t* m_off, int32_t width, const double* winv, const double* L,
+                      void* M, int m_double, hipStream_t s);
+void launch_overlap_chain(const addns_precond* pc, double* x2, hipStream_t s);
+int overlap_chain_width(int32_t smax);
 void launch_permute(const int32_t* perm, const double* in, double* out, int32_t n, int inverse,
                     const double* scale, hipStream_t s);
 // krylov
