@@ -238,6 +238,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the MSCNR/LUM/overlapped solves")
     ap.add_argument("--kernel-profile", action="store_true",
                     help="only the dominant kernel (interior solve) x reps, plus a 256 MiB device "
                          "copy of known size to calibrate memory counters")
@@ -281,9 +282,9 @@ def main():
     d_x = torch.zeros(N, dtype=torch.float64, device=dev)
     maxit = 20000
 
-    def step(iprec, sprec):
-        pc = addns.setup_precond(part, N, d_rp, d_ci, d_v, interior_prec=iprec, schur_prec=sprec,
-                                 block_mult=args.block_mult)
+    def step(iprec, sprec, schur=addns.SCHUR_MSCN, overlap=0):
+        pc = addns.setup_precond(part, N, d_rp, d_ci, d_v, schur=schur, interior_prec=iprec, schur_prec=sprec,
+                                 block_mult=args.block_mult, overlap=overlap)
         d_x.zero_()
         r = addns.gmres_solve(pc, d_b, d_x, restart=cfg.restart, maxit=maxit, tol=cfg.tol,
                               flexible=cfg.flexible)
@@ -341,6 +342,21 @@ def main():
         plain = {"seconds": round(time.perf_counter() - t1, 4), "iters": rp64["iters"],
                  "true_relres": rp64["true_relres"]}
 
+    # the other interface forms of the paper on the same workload, same
+    # factors (one timed solve each, setup included)
+    forms = None
+    if not args.no_forms:
+        forms = {}
+        for name, kw in (("mscnr", dict(schur=addns.SCHUR_MSCNR)), ("lum", dict(schur=addns.SCHUR_LUM)),
+                         ("omscn", dict(overlap=cfg.sz - 1)),
+                         ("omscnr", dict(schur=addns.SCHUR_MSCNR, overlap=cfg.sz - 1))):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, rf = step(iprec, sprec, **kw)
+            torch.cuda.synchronize()
+            forms[name] = {"seconds": round(time.perf_counter() - t1, 4), "iters": rf["iters"],
+                           "converged": rf["converged"]}
+
     line = {
         "metric": "time to 1e-8 rel. residual (s) + precond-apply GB/s; plain FP64 vs mixed/learned",
         "value": round(T, 5), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -354,6 +370,7 @@ def main():
         "apply_GBps": round(info["bytes_apply"] / (t_apply * 1e-3) / 1e9, 2),
         "apply_frac_hbm": round(info["bytes_apply"] / (t_apply * 1e-3) / peak, 4),
         "plain_f64": plain,
+        "interface_forms": forms,
         "roofline": {"bound": "hbm", "kernel": "k_interior_solve", "achieved": round(achieved / 1e9, 2),
                      "peak": peak / 1e9, "unit": "GB/s", "frac": round(achieved / peak, 4),
                      "traffic": measured_traffic(), "launch_ms": round(t_int, 4),
