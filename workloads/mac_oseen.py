@@ -108,6 +108,69 @@ class Wind:
         return Wind(c, max_speed / vmax if vmax > 0 else 1.0)
 
 
+    def cv_fluxes(self, g):
+        """Outward face fluxes of every velocity control volume, exact for
+        the stream function: psi(end) - psi(start) along each face."""
+        return _stream_fluxes(self.psi, g)
+
+
+class FaceWind:
+    """A discrete wind given by face velocities (a previous Picard iterate):
+    u on the interior vertical faces (array (n, n-1), [j, i-1]) and v on the
+    interior horizontal faces ((n-1, n), [j-1, i]), zero on the walls.
+    Control-volume face fluxes interpolate these linearly: a face through a
+    cell centre takes the mean of the cell's two face velocities times the
+    face length, and a face along a grid line takes the two half-faces'
+    velocities times their half-lengths."""
+
+    def __init__(self, u, v):
+        self.u = np.asarray(u, dtype=np.float64)
+        self.v = np.asarray(v, dtype=np.float64)
+
+    @staticmethod
+    def from_solution(x, n):
+        """The velocity part of a solution vector in the generator's order."""
+        nu_ = (n - 1) * n
+        return FaceWind(np.asarray(x[:nu_]).reshape(n, n - 1), np.asarray(x[nu_:2 * nu_]).reshape(n - 1, n))
+
+    def cv_fluxes(self, g):
+        n, dx, dy = g["n"], g["dx"], g["dy"]
+        if self.u.shape != (n, n - 1) or self.v.shape != (n - 1, n):
+            raise ValueError("face velocities do not match the grid")
+        Up = np.zeros((n, n + 1))     # Up[j, i] = u on vertical face i of row j
+        Up[:, 1:n] = self.u
+        Vp = np.zeros((n + 1, n))     # Vp[j, i] = v on horizontal face j of column i
+        Vp[1:n, :] = self.v
+        I, J = g["uI"], g["uJ"]
+        f = {}
+        f["uE"] = 0.5 * (Up[J, I] + Up[J, I + 1]) * dy[J]
+        f["uW"] = -0.5 * (Up[J, I - 1] + Up[J, I]) * dy[J]
+        f["uN"] = 0.5 * (Vp[J + 1, I - 1] * dx[I - 1] + Vp[J + 1, I] * dx[I])
+        f["uS"] = -0.5 * (Vp[J, I - 1] * dx[I - 1] + Vp[J, I] * dx[I])
+        I2, J2 = g["vI"], g["vJ"]
+        f["vN"] = 0.5 * (Vp[J2, I2] + Vp[J2 + 1, I2]) * dx[I2]
+        f["vS"] = -0.5 * (Vp[J2 - 1, I2] + Vp[J2, I2]) * dx[I2]
+        f["vE"] = 0.5 * (Up[J2 - 1, I2 + 1] * dy[J2 - 1] + Up[J2, I2 + 1] * dy[J2])
+        f["vW"] = -0.5 * (Up[J2 - 1, I2] * dy[J2 - 1] + Up[J2, I2] * dy[J2])
+        return f
+
+
+def _stream_fluxes(psi, g):
+    X, Y, xc, yc = g["X"], g["Y"], g["xc"], g["yc"]
+    I, J = g["uI"], g["uJ"]
+    I2, J2 = g["vI"], g["vJ"]
+    return {
+        "uE": psi(xc[I], Y[J]) - psi(xc[I], Y[J + 1]),
+        "uW": psi(xc[I - 1], Y[J + 1]) - psi(xc[I - 1], Y[J]),
+        "uN": psi(xc[I], Y[J + 1]) - psi(xc[I - 1], Y[J + 1]),
+        "uS": psi(xc[I - 1], Y[J]) - psi(xc[I], Y[J]),
+        "vN": psi(X[I2 + 1], yc[J2]) - psi(X[I2], yc[J2]),
+        "vS": psi(X[I2], yc[J2 - 1]) - psi(X[I2 + 1], yc[J2 - 1]),
+        "vE": psi(X[I2 + 1], yc[J2 - 1]) - psi(X[I2 + 1], yc[J2]),
+        "vW": psi(X[I2], yc[J2]) - psi(X[I2], yc[J2 - 1]),
+    }
+
+
 # --------------------------------------------------------------------------
 # assembly
 # --------------------------------------------------------------------------
@@ -145,10 +208,13 @@ class _Coo:
         return rowptr, cols, v[first]
 
 
-def make_oseen_mac(n: int, nu: float, wind: Wind | None = None, stretch: float | None = None,
+def make_oseen_mac(n: int, nu: float, wind: Wind | FaceWind | None = None, stretch: float | None = None,
                    seed: int | None = 0, lid: float = 1.0, forcing=None):
     """Assemble C (CSR, int32 indices, float64 values), b and metadata.
 
+    wind: a stream-function Wind (default Wind()) or a FaceWind (discrete
+          face velocities, e.g. the previous Picard iterate).  The sparsity
+          pattern does not depend on the wind.
     forcing: None -> f ~ N(0,1) per velocity unknown from default_rng(seed);
              callable (fu(x,y), fv(x,y)) -> point values at the unknowns.
     """
@@ -159,7 +225,9 @@ def make_oseen_mac(n: int, nu: float, wind: Wind | None = None, stretch: float |
     Y = face_coords(dy)
     xc = 0.5 * (X[:-1] + X[1:])
     yc = 0.5 * (Y[:-1] + Y[1:])
-    psi = wind.psi
+    uI, uJ = np.meshgrid(np.arange(1, n), np.arange(n), indexing="xy")
+    vI, vJ = np.meshgrid(np.arange(n), np.arange(1, n), indexing="xy")
+    flux = wind.cv_fluxes(dict(n=n, dx=dx, dy=dy, X=X, Y=Y, xc=xc, yc=yc, uI=uI, uJ=uJ, vI=vI, vJ=vJ))
 
     nu_ = (n - 1) * n
     nv_ = n * (n - 1)
@@ -188,13 +256,13 @@ def make_oseen_mac(n: int, nu: float, wind: Wind | None = None, stretch: float |
     lidv = np.zeros(I.shape)
     # east neighbour u(i+1, j), face at xc[i]
     a = nu * hu / dx[I]
-    F = psi(xc[I], Y[J]) - psi(xc[I], Y[J + 1])
+    F = flux["uE"]
     inner = I + 1 <= n - 1
     coo.add(rows, U(np.minimum(I + 1, n - 1), J), -a + 0.5 * F, inner)
     diag += a
     # west neighbour u(i-1, j), face at xc[i-1]
     a = nu * hu / dx[I - 1]
-    F = psi(xc[I - 1], Y[J + 1]) - psi(xc[I - 1], Y[J])
+    F = flux["uW"]
     inner = I - 1 >= 1
     coo.add(rows, U(np.maximum(I - 1, 1), J), -a + 0.5 * F, inner)
     diag += a
@@ -202,7 +270,7 @@ def make_oseen_mac(n: int, nu: float, wind: Wind | None = None, stretch: float |
     top = J + 1 == n
     dist = np.where(top, 0.5 * dy[J], yc[np.minimum(J + 1, n - 1)] - yc[J])
     a = nu * wu / dist
-    F = psi(xc[I], Y[J + 1]) - psi(xc[I - 1], Y[J + 1])
+    F = flux["uN"]
     coo.add(rows, U(I, np.minimum(J + 1, n - 1)), -a + 0.5 * F, ~top)
     diag += a
     lidv = np.where(top, lid, 0.0)
@@ -211,7 +279,7 @@ def make_oseen_mac(n: int, nu: float, wind: Wind | None = None, stretch: float |
     bot = J == 0
     dist = np.where(bot, 0.5 * dy[J], yc[J] - yc[np.maximum(J - 1, 0)])
     a = nu * wu / dist
-    F = psi(xc[I - 1], Y[J]) - psi(xc[I], Y[J])
+    F = flux["uS"]
     coo.add(rows, U(I, np.maximum(J - 1, 0)), -a + 0.5 * F, ~bot)
     diag += a
     coo.add(rows, rows, diag)
@@ -229,26 +297,26 @@ def make_oseen_mac(n: int, nu: float, wind: Wind | None = None, stretch: float |
     diag2 = np.zeros(I2.shape)
     # north v(i, j+1), face at yc[j]
     a = nu * wv / dy[J2]
-    F = psi(X[I2 + 1], yc[J2]) - psi(X[I2], yc[J2])
+    F = flux["vN"]
     coo.add(rows2, V(I2, np.minimum(J2 + 1, n - 1)), -a + 0.5 * F, J2 + 1 <= n - 1)
     diag2 += a
     # south v(i, j-1), face at yc[j-1]
     a = nu * wv / dy[J2 - 1]
-    F = psi(X[I2], yc[J2 - 1]) - psi(X[I2 + 1], yc[J2 - 1])
+    F = flux["vS"]
     coo.add(rows2, V(I2, np.maximum(J2 - 1, 1)), -a + 0.5 * F, J2 - 1 >= 1)
     diag2 += a
     # east v(i+1, j), face at X[i+1]
     right = I2 + 1 == n
     dist = np.where(right, 0.5 * dx[I2], xc[np.minimum(I2 + 1, n - 1)] - xc[I2])
     a = nu * hv / dist
-    F = psi(X[I2 + 1], yc[J2 - 1]) - psi(X[I2 + 1], yc[J2])
+    F = flux["vE"]
     coo.add(rows2, V(np.minimum(I2 + 1, n - 1), J2), -a + 0.5 * F, ~right)
     diag2 += a
     # west v(i-1, j), face at X[i]
     left = I2 == 0
     dist = np.where(left, 0.5 * dx[I2], xc[I2] - xc[np.maximum(I2 - 1, 0)])
     a = nu * hv / dist
-    F = psi(X[I2], yc[J2]) - psi(X[I2], yc[J2 - 1])
+    F = flux["vW"]
     coo.add(rows2, V(np.maximum(I2 - 1, 0), J2), -a + 0.5 * F, ~left)
     diag2 += a
     coo.add(rows2, rows2, diag2)
