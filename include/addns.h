@@ -172,6 +172,26 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
                         const addns_precond_opts* opts, void* stream, addns_precond_t* out);
 
 /* ------------------------------------------------------------------------
+ * addns_precond_refactor -- new values on the same sparsity pattern, as in
+ * an outer Picard iteration (section 1: every outer step is an Oseen system
+ * whose wind is the previous velocity).  Every numeric part of
+ * addns_setup_precond is recomputed for d_vals (row scaling, interior band
+ * LU and sweep blocks, mini Schur complements, inverses, chain matrices),
+ * keeping the handle's partition plan, options, sweep block size and
+ * zero-slot choice: no host planning and no autotuning.  Device buffers
+ * keep their sizes and addresses, so an apply captured in a HIP graph
+ * before the call uses the new factors when replayed after it.
+ *   d_rowptr, d_colidx: DEVICE CSR pattern, identical to the setup's (not
+ *            checked); d_vals: DEVICE values of C (unscaled).
+ * Returns after the work has completed on `stream`.  Errors as
+ * addns_setup_precond; after a failed refactor the handle holds no factors
+ * (apply, solve and block queries return ADDNS_ERR_ARG) until a refactor
+ * succeeds.
+ */
+int addns_precond_refactor(addns_precond_t pc, const int32_t* d_rowptr, const int32_t* d_colidx,
+                           const double* d_vals, void* stream);
+
+/* ------------------------------------------------------------------------
  * addns_apply_precond -- Algorithm 2: x = B^{-1} y,
  *   z1 = D^-1 y1;  x2 = Shat^-1 (y2 - F z1);  x1 = z1 - D^-1 (E x2),
  * for DEVICE vectors of length N in the ORIGINAL numbering of the scaled

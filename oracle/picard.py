@@ -12,7 +12,9 @@ the previous iterate, which gives an Oseen problem.  The outer loop, plainly:
     x_0 = 0 (the first system is the Stokes problem: no wind)
     for q = 0, 1, ...:
         assemble C_q = C(w(x_q)), b_q = b(w(x_q)), w(x) the velocity part of x
-        r_q = |b_q - C_q x_q| / |b_q|        (the discrete Navier-Stokes residual)
+        r_q = |R_q (b_q - C_q x_q)| / |R_q b_q|   (the discrete Navier-Stokes
+              residual of the row-scaled system, R_q the row scaling of C_q, so
+              that r_q is the residual the Krylov solver reports for x_q)
         stop if r_q <= tol
         x_{q+1} = the preconditioned (F)GMRES solution of C_q x = b_q,
                   started from x_q
@@ -31,7 +33,7 @@ import scipy.sparse as sp
 
 from oracle.krylov import solve_system
 from oracle.partition import build_partition
-from oracle.precond import MSCN, Preconditioner
+from oracle.precond import MSCN, Preconditioner, row_scale
 from workloads.mac_oseen import FaceWind, make_oseen_mac
 
 
@@ -41,11 +43,17 @@ def assemble(n, nu, x, stretch=None, seed=0, forcing=None):
                           forcing=forcing)
 
 
-def ns_residual(n, nu, x, stretch=None, seed=0, forcing=None):
-    """|b(x) - C(x) x| / |b(x)|: the discrete steady Navier-Stokes residual."""
-    rp, ci, v, b, meta = assemble(n, nu, x, stretch, seed, forcing)
+def scaled_residual(rp, ci, v, b, x):
+    """|R (b - C x)| / |R b| with R the row scaling of C (section 5)."""
+    R, _ = row_scale(rp, ci, v)
     C = sp.csr_matrix((v, ci, rp), shape=(len(b), len(b)))
-    return float(np.linalg.norm(b - C @ x) / np.linalg.norm(b))
+    return float(np.linalg.norm(R * (b - C @ x)) / np.linalg.norm(R * b))
+
+
+def ns_residual(n, nu, x, stretch=None, seed=0, forcing=None):
+    """The discrete steady Navier-Stokes residual of x (row-scaled)."""
+    rp, ci, v, b, meta = assemble(n, nu, x, stretch, seed, forcing)
+    return scaled_residual(rp, ci, v, b, x)
 
 
 @dataclass
@@ -64,8 +72,7 @@ def picard(n, nu, stretch=None, seed=0, m=4, sz=64, mode=MSCN, overlap=0, tol=1e
     out = PicardResult(x, False)
     for q in range(maxit + 1):
         rp, ci, v, b, meta = assemble(n, nu, x, stretch, seed, forcing)
-        C = sp.csr_matrix((v, ci, rp), shape=(N, N))
-        r = float(np.linalg.norm(b - C @ x) / np.linalg.norm(b))
+        r = scaled_residual(rp, ci, v, b, x)
         out.residuals.append(r)
         if r <= tol:
             out.converged = True

@@ -30,6 +30,7 @@ EXPORTED = [
     "addns_last_error", "addns_version",
     "addns_dtn_param_count", "addns_dtn_samples", "addns_dtn_forward", "addns_dtn_grad",
     "addns_dtn_train", "addns_dtn_save", "addns_dtn_load", "addns_gmres_solve_judged",
+    "addns_precond_refactor",
 ]
 
 
@@ -85,6 +86,7 @@ def lib():
         "addns_setup_precond": (C.c_int, [P, C.c_int32, P, P, P, C.POINTER(PrecondOpts), P,
                                           C.POINTER(P)]),
         "addns_apply_precond": (C.c_int, [P, P, P, P]),
+        "addns_precond_refactor": (C.c_int, [P, P, P, P, P]),
         "addns_interior_solve": (C.c_int, [P, P, P, P]),
         "addns_gmres_solve": (C.c_int, [P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresResult), P]),
         "addns_precond_info": (C.c_int, [P, i32p, i32p, i32p, i32p, i64p, i64p, i64p, i32p]),
@@ -249,6 +251,13 @@ def setup_precond(partition: Partition, N, d_rowptr, d_colidx, d_vals, schur=SCH
                                      _ptr(d_vals), C.byref(opts), _stream(stream), C.byref(h)),
            "setup_precond")
     return Precond(h, partition)
+
+
+def refactor_precond(pc: Precond, d_rowptr, d_colidx, d_vals, stream=None):
+    """New values on the setup's pattern: every numeric part of the setup is
+    recomputed on the handle's plan (addns_precond_refactor)."""
+    _check(lib().addns_precond_refactor(pc.handle, _ptr(d_rowptr), _ptr(d_colidx), _ptr(d_vals),
+                                        _stream(stream)), "precond_refactor")
 
 
 def apply_precond(pc: Precond, d_y, d_x, stream=None):

@@ -51,6 +51,7 @@ int addns_dtn_samples(addns_precond_t pc, float* d_X, float* d_Y, float* d_M, in
     const int64_t n = (int64_t)pc->plan.smp_row.size();
     *count = n;
     if (!d_X && !d_Y && !d_M) return ADDNS_OK;  // size query
+    require_factors(pc);
     if (pc->schur_mode == ADDNS_SCHUR_LEARNED) throw ArgError("a LEARNED preconditioner has no teacher blocks");
     if ((d_Y == nullptr) != (d_M == nullptr)) throw ArgError("Y and M go together");
     if (d_Y && pc->plan.overlap > 0) throw ArgError("targets need non-overlapped teacher blocks");
@@ -205,6 +206,8 @@ int addns_gmres_solve_judged(addns_precond_t learned, addns_precond_t plain, con
                              const addns_gmres_opts* opts, addns_gmres_result* res, int32_t* accepted, void* stream) {
   return guarded("addns_gmres_solve_judged", [&]() -> int {
     if (!learned || !plain || !d_b || !d_x || !opts || !res || !accepted) throw ArgError("null argument");
+    require_factors(learned);
+    require_factors(plain);
     if (learned->plan.N != plain->plan.N) throw ArgError("the two preconditioners differ in size");
     hipStream_t s = as_stream(stream);
     const int32_t N = plain->plan.N;

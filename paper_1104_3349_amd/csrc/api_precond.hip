@@ -21,10 +21,12 @@ hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 int prec_bytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
 
 // Factor and interface storage of one preconditioner.
-void setup_device(addns_precond* pc, const PartitionData& P, const int32_t* d_rowptr, const int32_t* d_colidx,
+// Builds the plan from P (or keeps the handle's plan when P is null: a
+// refactor) and computes every numeric part of the preconditioner.
+void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_rowptr, const int32_t* d_colidx,
                   const double* d_vals, const addns_precond_opts& o, hipStream_t s) {
   Plan& pl = pc->plan;
-  build_plan(P, pl, o.schur, o.block_mult, o.overlap);
+  if (P) build_plan(*P, pl, o.schur, o.block_mult, o.overlap);
   const int32_t N = pl.N;
   const int64_t nnz = (int64_t)pl.cp_colidx.size();
 
@@ -366,7 +368,12 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
       ADDNS_HIP(hipGetDevice(&pc->device));
       addns_precond_opts oo = o;
       oo.block_mult = mult;
-      setup_device(pc.get(), p->d, d_rowptr, d_colidx, d_vals, oo, as_stream(stream));
+      setup_device(pc.get(), &p->d, d_rowptr, d_colidx, d_vals, oo, as_stream(stream));
+      pc->opts = oo;
+      if (o.schur == ADDNS_SCHUR_LEARNED) {
+        pc->learned_w.assign(o.learned_model, o.learned_model + mlp_param_count());
+        pc->opts.learned_model = nullptr;  // the caller's array is not kept
+      }
       // the sweep's zero-slot skipping (bitwise the same result either way)
       // is chosen by timing both forms on these factors
       float ms[2];
@@ -399,9 +406,23 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
   });
 }
 
+int addns_precond_refactor(addns_precond_t pc, const int32_t* d_rowptr, const int32_t* d_colidx,
+                           const double* d_vals, void* stream) {
+  return guarded("addns_precond_refactor", [&]() -> int {
+    if (!pc || !d_rowptr || !d_colidx || !d_vals) throw ArgError("null argument");
+    addns_precond_opts o = pc->opts;
+    if (o.schur == ADDNS_SCHUR_LEARNED) o.learned_model = pc->learned_w.data();
+    pc->valid = 0;
+    setup_device(pc, nullptr, d_rowptr, d_colidx, d_vals, o, as_stream(stream));
+    pc->valid = 1;
+    return ADDNS_OK;
+  });
+}
+
 int addns_apply_precond(addns_precond_t pc, const double* d_y, double* d_x, void* stream) {
   return guarded("addns_apply_precond", [&]() -> int {
     if (!pc || !d_y || !d_x) throw ArgError("null argument");
+    require_factors(pc);
     if (d_y == d_x) throw ArgError("y and x must not alias");
     hipStream_t s = as_stream(stream);
     const int32_t N = pc->plan.N;
@@ -416,6 +437,7 @@ int addns_apply_precond(addns_precond_t pc, const double* d_y, double* d_x, void
 int addns_interior_solve(addns_precond_t pc, const double* d_y1, double* d_z1, void* stream) {
   return guarded("addns_interior_solve", [&]() -> int {
     if (!pc || !d_y1 || !d_z1) throw ArgError("null argument");
+    require_factors(pc);
     if (d_y1 == d_z1) throw ArgError("y1 and z1 must not alias");
     launch_interior_solve(pc, d_y1, d_z1, 0, nullptr, nullptr, as_stream(stream));
     ADDNS_HIP(hipGetLastError());
@@ -427,6 +449,7 @@ int addns_gmres_solve(addns_precond_t pc, const double* d_b, double* d_x, const 
                       addns_gmres_result* res, void* stream) {
   return guarded("addns_gmres_solve", [&]() -> int {
     if (!pc || !d_b || !d_x || !opts || !res) throw ArgError("null argument");
+    require_factors(pc);
     const int restart = opts->restart, maxit = opts->maxit;
     if (restart < 1 || restart > 1024 || maxit < 0 || !(opts->tol > 0.0))
       throw ArgError("1 <= restart <= 1024, maxit >= 0, tol > 0");
@@ -528,6 +551,7 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
                               double* d_x, const addns_gmres_opts* opts, addns_gmres_result* res, void* stream) {
   return guarded("addns_gmres_solve_batched", [&]() -> int {
     if (!pc || !sys_offsets || !d_b || !d_x || !opts || !res || nsys < 1) throw ArgError("null argument");
+    require_factors(pc);
     const int restart = opts->restart, maxit = opts->maxit;
     if (restart < 1 || restart > 1024 || maxit < 0 || !(opts->tol > 0.0))
       throw ArgError("1 <= restart <= 1024, maxit >= 0, tol > 0");
@@ -695,6 +719,7 @@ int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb
 int addns_precond_schur_blocks(addns_precond_t pc, double* h_out, int64_t count) {
   return guarded("addns_precond_schur_blocks", [&]() -> int {
     if (!pc || !h_out) throw ArgError("null argument");
+    require_factors(pc);
     if (count != pc->plan.g_total) throw ArgError("count must equal the sum of |agg_i|^2");
     if (count > 0) ADDNS_HIP(hipMemcpy(h_out, pc->schur_S.p, sizeof(double) * count, hipMemcpyDeviceToHost));
     return ADDNS_OK;

@@ -44,9 +44,12 @@ struct DevBuf {
     p = nullptr;
     bytes = 0;
   }
+  // keeps the allocation (and its address) when the size is unchanged, so
+  // that a refactor on the same plan leaves every device pointer in place
   void alloc(size_t n) {
-    reset();
     if (n == 0) n = 8;
+    if (p && bytes == n) return;
+    reset();
     ADDNS_HIP(hipMalloc(&p, n));
     bytes = n;
   }
@@ -154,6 +157,9 @@ enum Prec { P64 = 0, P32 = 1, P16S = 2 };
 struct addns_precond {
   addns::Plan plan;
   int schur_mode = 0, interior_prec = 0, schur_prec = 0, row_scale = 1;
+  addns_precond_opts opts{};                          // as set up (block_mult: the one in use)
+  std::vector<float> learned_w;                       // LEARNED: the network weights, for refactors
+  int valid = 1;                                      // 0 after a failed refactor: no usable factors
   int device = 0;
   // vectors / matrices (device)
   addns::DevBuf perm, iperm, R;                       // R in original numbering
@@ -189,6 +195,10 @@ struct addns_precond {
 };
 
 namespace addns {
+inline void require_factors(const addns_precond* pc) {
+  if (!pc->valid) throw ArgError("the handle holds no factors: its last refactor failed");
+}
+
 // launchers (kernels_*.hip)
 void launch_row_scale(const int32_t* rowptr, const double* vals, int32_t N, int scale, double* R,
                       hipStream_t s);
