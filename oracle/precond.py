@@ -11,7 +11,8 @@ Plain FP64, no blocking or fusion beyond what the paper states:
 * blocks of P^T C P = [D E; F G] (section 3.3), D = blkDiag(A_11..A_mm)
   (Algorithm 2);
 * interior factors: each A_jj by a LAPACK band LU with partial pivoting
-  (the section 4 remark that D_ii is factorised exactly, [L,U] = lu(D_ii));
+  (the section 4 remark that D_ii is factorised exactly, [L,U] = lu(D_ii)),
+  or by the threshold ILU of BandILU (section 5's inexact solver);
 * mini Schur complements (section 3.1 steps 2-4; Algorithm 1):
     MSCN      S_i = G_i - F_i D_{r_i}^{-1} E_i with the D-range of the
               partition (interior velocity neighbours of the aggregate);
@@ -95,11 +96,76 @@ class BandLU:
         return x
 
 
+class BandILU:
+    """Incomplete LU with threshold tau of one interior block (the inexact
+    interior solver of the experiments in section 5; Algorithm 2 allows an
+    inexact solve).  Reading: right-looking elimination with partial
+    pivoting inside the band, as the exact factorisation, where at step j
+      * a multiplier is dropped (not stored, its row not updated) when
+        |a_ij| < tau ||A(:, j)||_2, a_ij the entry before division by the
+        pivot (equivalently |l_ij u_jj| < tau ||A(:, j)||_2);
+      * an entry of the pivot row is dropped when |u_jk| < tau ||A(:, k)||_2;
+      * the pivot itself is never dropped;
+    with ||A(:, k)|| the column norms of the block before elimination.
+    Dense getrf-style storage (later swaps move earlier multipliers), so
+    P A = L U + R with R supported on the dropped positions.  tau = 0 gives
+    the exact band LU."""
+
+    def __init__(self, A: sp.spmatrix, tau: float):
+        A = sp.csr_matrix(A)
+        n = A.shape[0]
+        self.n = n
+        self.tau = float(tau)
+        if n == 0:
+            return
+        coo = A.tocoo()
+        kl = int(max(0, (coo.row - coo.col).max()))
+        ku = int(max(0, (coo.col - coo.row).max()))
+        W = A.toarray()
+        cn = np.sqrt((W * W).sum(axis=0))
+        perm = np.arange(n)
+        for j in range(n):
+            hi = min(n, j + kl + 1)            # rows that can hold column j
+            p = j + int(np.argmax(np.abs(W[j:hi, j])))
+            if W[p, j] == 0.0:
+                raise SingularBlock(f"zero pivot at column {j}")
+            if p != j:
+                W[[j, p], :] = W[[p, j], :]
+                perm[[j, p]] = perm[[p, j]]
+            cr = min(n, j + kl + ku + 1)       # columns of U row j (fill stays in the band)
+            u = W[j, j + 1:cr].copy()
+            drop_u = np.abs(u) < tau * cn[j + 1:cr]
+            u[drop_u] = 0.0
+            W[j, j + 1:cr] = u
+            a = W[j + 1:hi, j].copy()
+            drop_l = np.abs(a) < tau * cn[j]
+            l = a / W[j, j]
+            l[drop_l] = 0.0
+            W[j + 1:hi, j] = l
+            W[j + 1:hi, j + 1:cr] -= np.outer(l, u)
+        self.kl, self.ku = kl, ku
+        self.perm = perm
+        self.L = np.tril(W, -1) + np.eye(n)
+        self.U = np.triu(W)
+
+    def nnz(self):
+        """Stored entries of L (below the unit diagonal) and U."""
+        if self.n == 0:
+            return 0
+        return int(np.count_nonzero(np.tril(self.L, -1)) + np.count_nonzero(self.U))
+
+    def solve(self, y):
+        if self.n == 0:
+            return np.zeros_like(y)
+        z = sla.solve_triangular(self.L, np.asarray(y)[self.perm], lower=True, unit_diagonal=True)
+        return sla.solve_triangular(self.U, z, lower=False)
+
+
 class Preconditioner:
     """B of the MSCN definition (section 3.3) built by Algorithm 1."""
 
     def __init__(self, N, rowptr, colidx, vals, part, mode=MSCN, row_scaling=True,
-                 learned_S=None, overlap=0):
+                 learned_S=None, overlap=0, ilu_tol=0.0):
         if overlap < 0:
             raise ValueError("overlap must be >= 0")
         if overlap > 0 and mode not in (MSCN, MSCNR, LUM):
@@ -121,7 +187,8 @@ class Preconditioner:
         self.blocks = []
         for j in range(part.m):
             a, b = part.int_offsets[j], part.int_offsets[j + 1]
-            self.blocks.append((a, b, BandLU(Cp[a:b, a:b])))
+            blk = BandILU(Cp[a:b, a:b], ilu_tol) if ilu_tol > 0 else BandLU(Cp[a:b, a:b])
+            self.blocks.append((a, b, blk))
         self.mode = mode
         self.overlap = overlap
         k = part.k

@@ -11,7 +11,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from oracle.partition import Partition, build_partition
-from oracle.precond import EXACT_BJ, LUM, MSCN, MSCN_LITERAL, MSCNR, BandLU, Preconditioner, row_scale
+from oracle.precond import EXACT_BJ, LUM, MSCN, MSCN_LITERAL, MSCNR, BandILU, BandLU, Preconditioner, row_scale
 from workloads.mac_oseen import make_oseen_mac
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -42,13 +42,18 @@ def test_band_lu_matches_dense_solve():
         assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("mode,overlap", [(MSCN, 0), (LUM, 0), (MSCNR, 0), (MSCN, 23), (MSCNR, 5),
-                                          (LUM, 23)])
-def test_apply_equals_dense_block_factorisation(mode, overlap):
-    """x = B^{-1} y with B = [D 0; F S][D^-1 0; 0 S^-1][D E; 0 S] built densely."""
+@pytest.mark.parametrize("mode,overlap,tau", [(MSCN, 0, 0.0), (LUM, 0, 0.0), (MSCNR, 0, 0.0), (MSCN, 23, 0.0),
+                                              (MSCNR, 5, 0.0), (LUM, 23, 0.0), (MSCN, 0, 1e-2)])
+def test_apply_equals_dense_block_factorisation(mode, overlap, tau):
+    """x = B^{-1} y with B = [D 0; F S][D^-1 0; 0 S^-1][D E; 0 S] built densely
+    (with tau > 0, D is the product of the incomplete factors)."""
     rp, ci, v, b, meta, P = _system(16, 0.1, None, 4, 24)
-    pre = Preconditioner(meta["N"], rp, ci, v, P, mode, overlap=overlap)
+    pre = Preconditioner(meta["N"], rp, ci, v, P, mode, overlap=overlap, ilu_tol=tau)
     D, E, F, G, Sh = pre.dense_blocks()
+    if tau > 0:
+        D = D.copy()
+        for (a, bb, f) in pre.blocks:
+            D[a:bb, a:bb] = (f.L @ f.U)[np.argsort(f.perm)]
     ni, ns = D.shape[0], Sh.shape[0]
     L = np.block([[D, np.zeros((ni, ns))], [F, Sh]])
     M = sla.block_diag(np.linalg.inv(D), np.linalg.inv(Sh))
@@ -61,6 +66,8 @@ def test_apply_equals_dense_block_factorisation(mode, overlap):
     assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(ref)
     # B reproduces C~ everywhere except in the separator block, where it holds
     # G - F D^-1 E + Shat... i.e. B(2,2) = F D^-1 E + Shat
+    if tau > 0:
+        return
     assert np.allclose(B[:ni, :], np.block([[D, E]]), atol=1e-12)
     assert np.allclose(B[ni:, :ni], F, atol=1e-12)
     assert np.allclose(B[ni:, ni:], F @ np.linalg.solve(D, E) + Sh, atol=1e-10)
@@ -163,6 +170,44 @@ def _ext_sets(P, i, w):
     a, b = P.agg_offsets[i], P.agg_offsets[i + 1]
     dr = P.drange(i) if w == 0 else np.concatenate([P.drange(i), P.drange(i + 1)])
     return sep[a:b + w], dr
+
+
+def _interior_block(j=0, st=1.05, nu=0.05):
+    rp, ci, v, b, meta, P = _system(16, nu, st, 4, 24)
+    pre = Preconditioner(meta["N"], rp, ci, v, P, MSCN)
+    Cp = pre.C[P.perm][:, P.perm].tocsr()
+    a, bb = P.int_offsets[j], P.int_offsets[j + 1]
+    return Cp[a:bb, a:bb]
+
+
+def test_band_ilu_without_dropping_is_the_band_lu():
+    A = _interior_block()
+    y = np.random.default_rng(0).standard_normal(A.shape[0])
+    ref = BandLU(A).solve(y)
+    assert np.linalg.norm(BandILU(A, 0.0).solve(y) - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("tau", [1e-4, 1e-2])
+def test_band_ilu_error_lives_on_the_dropped_positions(tau):
+    """P A = L U + R: R vanishes wherever L or U keeps an entry and stays
+    below tau ||A(:, k)|| where an entry was dropped (the defining property
+    of a threshold incomplete factorisation)."""
+    A = _interior_block()
+    f = BandILU(A, tau)
+    Ad = A.toarray()
+    R = Ad[f.perm] - f.L @ f.U
+    kept = (np.tril(f.L, -1) != 0) | (f.U != 0)
+    scale = np.abs(Ad).max()
+    assert np.abs(R[kept]).max() <= 1e-13 * scale
+    cn = np.sqrt((Ad * Ad).sum(axis=0))
+    assert np.all(np.abs(R) <= tau * cn[None, :] * (1 + 1e-12) + 1e-13 * scale)
+    assert np.abs(R).max() > 0     # something was dropped
+
+
+def test_band_ilu_drops_more_with_larger_tau():
+    A = _interior_block()
+    nz = [BandILU(A, tau).nnz() for tau in (0.0, 1e-4, 1e-2, 1e-1)]
+    assert nz[0] > nz[1] >= nz[2] >= nz[3] and nz[0] > nz[2]
 
 
 def test_overlap_widths():
