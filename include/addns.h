@@ -149,6 +149,17 @@ typedef struct {
                              aggregates (k - 1 dependent steps in one workgroup).
                              Needs every aggregate to hold at most 128 nodes
                              and at most 12000 aggregates (else ADDNS_ERR_ARG) */
+  double ilu_tol;         /* 0: exact band LU of every interior block (section 4).
+                             tau in (0, 1): threshold ILU, the inexact interior
+                             solver of the experiments (section 5, tolerance 1e-4;
+                             Algorithm 2 allows an inexact solve): during the
+                             band elimination with partial pivoting, a multiplier
+                             whose entry before division is below
+                             tau ||A_jj(:,j)||_2 and a pivot-row entry u_jk below
+                             tau ||A_jj(:,k)||_2 are dropped (column norms of the
+                             scaled block before elimination); pivots are kept.
+                             The sweep applies the incomplete factors exactly.
+                             Outside [0, 1): ADDNS_ERR_ARG */
 } addns_precond_opts;
 
 /* ------------------------------------------------------------------------
@@ -265,10 +276,13 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
    pivots, coupling blocks, interface inverses, vector passes); block_mult
    is the sweep tile multiplier in use (chosen by the autotuner when the
    options asked for 0); learned_count is the number of learned-correction
-   samples (separator velocity rows). */
+   samples (separator velocity rows); interior_nnz is the number of stored
+   entries of the interior factors (multipliers below the unit diagonal and
+   U, real rows and columns), the numerator of the fill factor of section 5
+   with or without ILU dropping. */
 int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb_lower,
                        int32_t* nb_upper, int64_t* factor_bytes, int64_t* bytes_apply,
-                       int64_t* learned_count, int32_t* block_mult);
+                       int64_t* learned_count, int32_t* block_mult, int64_t* interior_nnz);
 
 /* Copy the dense interface blocks S_i (before inversion) into a HOST array
    in aggregate order, row-major per block; `count` must equal the sum of

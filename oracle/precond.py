@@ -107,9 +107,15 @@ class BandILU:
       * an entry of the pivot row is dropped when |u_jk| < tau ||A(:, k)||_2;
       * the pivot itself is never dropped;
     with ||A(:, k)|| the column norms of the block before elimination.
+    Partial pivoting picks the first row whose magnitude is within a
+    relative PIVOT_TIE of the column's largest (the paper does not say how
+    equal candidates are ordered; on the uniform grids exact and 1-ulp ties
+    are common, and this rule makes the choice independent of rounding).
     Dense getrf-style storage (later swaps move earlier multipliers), so
     P A = L U + R with R supported on the dropped positions.  tau = 0 gives
     the exact band LU."""
+
+    PIVOT_TIE = 1e-12
 
     def __init__(self, A: sp.spmatrix, tau: float):
         A = sp.csr_matrix(A)
@@ -126,7 +132,8 @@ class BandILU:
         perm = np.arange(n)
         for j in range(n):
             hi = min(n, j + kl + 1)            # rows that can hold column j
-            p = j + int(np.argmax(np.abs(W[j:hi, j])))
+            mag = np.abs(W[j:hi, j])
+            p = j + int(np.argmax(mag >= (1.0 - self.PIVOT_TIE) * mag.max()))
             if W[p, j] == 0.0:
                 raise SingularBlock(f"zero pivot at column {j}")
             if p != j:

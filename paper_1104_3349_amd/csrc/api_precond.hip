@@ -86,14 +86,26 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
     bsrc.upload(pl.band_src, s);
     launch_scatter_band(bdst.as<int64_t>(), bsrc.as<int32_t>(), cpv, (int64_t)pl.band_dst.size(), ab.as<double>(), s);
     launch_band_pad_identity(pc->subs.as<SubInfo>(), m, ab.as<double>(), s);
-    launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), m, info.as<int32_t>(), s);
+    DevBuf colnorm, nnz;
+    colnorm.alloc(sizeof(double) * npad_total);
+    int32_t npad_max = 0;
+    for (const SubInfo& q : pl.subs) npad_max = std::max(npad_max, q.npad);
+    launch_band_colnorm(ab.as<double>(), pc->subs.as<SubInfo>(), m, npad_max, colnorm.as<double>(), s);
+    launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), m, info.as<int32_t>(),
+                   colnorm.as<double>(), o.ilu_tol, s);
+    nnz.alloc(sizeof(int64_t) * m);
+    launch_band_nnz(ab.as<double>(), pc->subs.as<SubInfo>(), m, nnz.as<int64_t>(), s);
     std::vector<int32_t> h_info(m + 4);
+    std::vector<int64_t> h_nnz(m);
     ADDNS_HIP(hipMemcpyAsync(h_info.data(), info.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
+    ADDNS_HIP(hipMemcpyAsync(h_nnz.data(), nnz.p, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s));
     ADDNS_HIP(hipStreamSynchronize(s));
     for (int32_t j = 0; j < m; ++j)
       if (h_info[j] != 0)
         throw SingularError("interior block " + std::to_string(j) + " has a zero pivot at column " +
                             std::to_string(h_info[j] - 1));
+    pc->interior_nnz = 0;
+    for (int64_t c : h_nnz) pc->interior_nnz += c;
     pc->lperm.alloc(sizeof(int32_t) * pl.lperm_total);
     // the sweep's last row slot may read up to 64 * 5 rows past a block's
     // end; the zeroed tail keeps that overrun inside the allocation
@@ -348,13 +360,14 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
   return guarded("addns_setup_precond", [&]() -> int {
     if (!p || !out || !d_rowptr || !d_colidx || !d_vals) throw ArgError("null argument");
     if (N != p->d.N) throw ArgError("N does not match the partition");
-    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1, 0, 0};
+    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1, 0, 0, 0.0};
     if (opts) o = *opts;
     if (o.schur < 0 || o.schur > ADDNS_SCHUR_MSCNR) throw ArgError("unknown schur mode");
     if (o.overlap < 0) throw ArgError("overlap must be >= 0");
     if (o.overlap > 0 && o.schur != ADDNS_SCHUR_MSCN && o.schur != ADDNS_SCHUR_MSCNR && o.schur != ADDNS_SCHUR_LUM)
       throw ArgError("overlapped aggregates are defined for MSCN, MSCNR and LUM");
     if (o.block_mult < 0 || o.block_mult > 4) throw ArgError("block_mult must be 0..4");
+    if (!(o.ilu_tol >= 0.0 && o.ilu_tol < 1.0)) throw ArgError("ilu_tol must lie in [0, 1)");
     const bool autotune = o.block_mult == 0;
     if (o.schur == ADDNS_SCHUR_LEARNED && !o.learned_model) throw ArgError("LEARNED mode needs learned_model");
     if (o.interior_prec != ADDNS_F64 && o.interior_prec != ADDNS_F32) throw ArgError("interior_prec");
@@ -700,7 +713,8 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
 }
 
 int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb_lower, int32_t* nb_upper,
-                       int64_t* factor_bytes, int64_t* bytes_apply, int64_t* learned_count, int32_t* block_mult) {
+                       int64_t* factor_bytes, int64_t* bytes_apply, int64_t* learned_count, int32_t* block_mult,
+                       int64_t* interior_nnz) {
   if (!pc) {
     set_error("addns_precond_info: null handle");
     return ADDNS_ERR_ARG;
@@ -713,6 +727,7 @@ int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb
   if (bytes_apply) *bytes_apply = pc->bytes_apply;
   if (learned_count) *learned_count = pc->learned_count;
   if (block_mult) *block_mult = pc->plan.block_mult;
+  if (interior_nnz) *interior_nnz = pc->interior_nnz;
   return ADDNS_OK;
 }
 

@@ -20,6 +20,7 @@ namespace {
 
 constexpr int kSetupThreads = 1024;
 constexpr int kMaxBandLU = 1024;  // KL + KU limit of k_band_lu (the sweep's own limit is the same)
+constexpr double kPivotTie = 1e-12;  // band LU: candidates this close to the largest count as equal
 
 __global__ void k_row_scale(const int32_t* __restrict__ rowptr, const double* __restrict__ vals, int32_t N,
                             int scale, double* __restrict__ R) {
@@ -65,15 +66,22 @@ __global__ void k_band_pad_identity(const SubInfo* subs, double* ab) {
 // (r, c) lives at row KV + r - c of column c, KV = KL + KU, so the factor U
 // may fill KL extra superdiagonals.  ipiv[j] = row swapped with row j at
 // step j (subdomain-local).  info[sub] = first zero pivot + 1 (0 if none).
+// tau > 0 makes it the threshold ILU used as an inexact interior solver in
+// the experiments of section 5: at step j a multiplier whose entry before
+// division is below tau ||A(:,j)||_2 is dropped (stored as zero, its row not
+// updated), and so is an entry u_jk of the pivot row below tau ||A(:,k)||_2;
+// the pivot is never dropped.  colnorm holds the column norms of the blocks
+// before elimination (k_band_colnorm).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kSetupThreads)
 k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const SubInfo* __restrict__ subs,
-          int32_t* __restrict__ info) {
+          int32_t* __restrict__ info, const double* __restrict__ colnorm_all, double tau) {
   const int sub = blockIdx.x;
   const SubInfo q = subs[sub];
   const int32_t n = q.npad, ldab = q.ldab, KL = q.kl, KU = q.ku;
   double* ab = ab_all + q.band_off;
   int32_t* ipiv = ipiv_all + q.vec_off;
+  const double* cn = colnorm_all + q.vec_off;
   const int32_t KV = KL + KU;
   __shared__ double s_piv;
   __shared__ double s_top;
@@ -91,25 +99,22 @@ k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const Sub
   for (int32_t j = 0; j < n; ++j) {
     const int32_t km = min(KL, n - 1 - j);
     double* colj = ab + (int64_t)j * ldab + KV;
-    // pivot search over rows j..j+km (first index of the largest magnitude)
+    // pivot search over rows j..j+km: the first row whose magnitude is
+    // within a relative kPivotTie of the largest (a rounding-independent
+    // choice among equal candidates)
     if (wave == 0) {
-      double best = -1.0;
-      int32_t bi = 0;
-      for (int32_t i = lane; i <= km; i += 64) {
-        double a = fabs(colj[i]);
-        if (a > best) {
-          best = a;
+      double best = 0.0;
+      for (int32_t i = lane; i <= km; i += 64) best = fmax(best, fabs(colj[i]));
+      for (int off = 32; off >= 1; off >>= 1) best = fmax(best, __shfl_xor(best, off));
+      const double thr = (1.0 - kPivotTie) * best;
+      int32_t bi = km + 1;
+      for (int32_t i = lane; i <= km; i += 64)
+        if (fabs(colj[i]) >= thr) {
           bi = i;
+          break;
         }
-      }
-      for (int off = 32; off >= 1; off >>= 1) {
-        double ob = __shfl_xor(best, off);
-        int32_t oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
+      for (int off = 32; off >= 1; off >>= 1) bi = min(bi, __shfl_xor(bi, off));
+      if (bi > km) bi = 0;  // an all-zero column: a zero pivot at row j
       if (lane == 0) {
         s_p = bi;
         s_piv = colj[bi];
@@ -128,9 +133,11 @@ k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const Sub
       // multipliers of column j (after the row swap) and the swap of columns
       // j+1..ju; both also go to LDS for the update below
       const double rinv = 1.0 / piv;
+      const double drop_l = tau * cn[j];
       for (int32_t i = tid; i <= km; i += blockDim.x) {
         if (i == 0) continue;
-        const double l = ((i == p) ? s_top : colj[i]) * rinv;
+        const double a = (i == p) ? s_top : colj[i];
+        const double l = fabs(a) < drop_l ? 0.0 : a * rinv;
         colj[i] = l;
         s_l[i] = l;
       }
@@ -140,10 +147,11 @@ k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const Sub
         double a = col[0];
         if (p != 0) {
           const double b = col[p];
-          col[0] = b;
           col[p] = a;
           a = b;
         }
+        if (fabs(a) < tau * cn[c]) a = 0.0;
+        col[0] = a;
         s_u[c - j - 1] = a;
       }
     }
@@ -172,6 +180,43 @@ k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const Sub
     __syncthreads();
   }
   if (tid == 0) info[sub] = s_info;
+}
+
+// Column 2-norms of every padded interior block before elimination: column
+// c holds its original entries in band rows KL .. ldab-1.
+__global__ void k_band_colnorm(const double* __restrict__ ab_all, const SubInfo* __restrict__ subs,
+                               double* __restrict__ colnorm_all) {
+  const SubInfo q = subs[blockIdx.y];
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= q.npad) return;
+  const double* col = ab_all + q.band_off + (int64_t)c * q.ldab;
+  double acc = 0.0;
+  for (int32_t r = q.kl; r < q.ldab; ++r) acc += col[r] * col[r];
+  colnorm_all[q.vec_off + c] = sqrt(acc);
+}
+
+// Stored entries of the factors of every block (multipliers below the unit
+// diagonal and U, real rows and columns only): counts[sub].
+__global__ void __launch_bounds__(kSetupThreads)
+k_band_nnz(const double* __restrict__ ab_all, const SubInfo* __restrict__ subs, int64_t* __restrict__ counts) {
+  const SubInfo q = subs[blockIdx.x];
+  const int32_t n = q.n, ldab = q.ldab, KV = q.kl + q.ku;
+  const double* ab = ab_all + q.band_off;
+  int64_t cnt = 0;
+  for (int64_t t = threadIdx.x; t < (int64_t)n * ldab; t += blockDim.x) {
+    const int32_t c = (int32_t)(t / ldab), r = (int32_t)(t % ldab);
+    const int32_t row = c + r - KV;  // U rows r <= KV, multiplier rows r > KV
+    if (row >= 0 && row < n && (r <= KV || row <= c + q.kl) && ab[t] != 0.0) ++cnt;
+  }
+  __shared__ int64_t s_cnt[kSetupThreads / 64];
+  for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
+  if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t s = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += s_cnt[w];
+    counts[blockIdx.x] = s;
+  }
 }
 
 // max |x_t| over n contiguous doubles, in every thread of the block (ends
@@ -702,8 +747,16 @@ void launch_dense_scatter(const int64_t* dst, const int32_t* src, const double* 
 void launch_band_pad_identity(const SubInfo* subs, int32_t m, double* ab, hipStream_t s) {
   if (m > 0) k_band_pad_identity<<<m, 256, 0, s>>>(subs, ab);
 }
-void launch_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, hipStream_t s) {
-  if (m > 0) k_band_lu<<<m, kSetupThreads, 0, s>>>(ab, ipiv, subs, info);
+void launch_band_colnorm(const double* ab, const SubInfo* subs, int32_t m, int32_t npad_max, double* colnorm,
+                         hipStream_t s) {
+  if (m > 0 && npad_max > 0) k_band_colnorm<<<dim3((npad_max + 255) / 256, m), 256, 0, s>>>(ab, subs, colnorm);
+}
+void launch_band_nnz(const double* ab, const SubInfo* subs, int32_t m, int64_t* counts, hipStream_t s) {
+  if (m > 0) k_band_nnz<<<m, kSetupThreads, 0, s>>>(ab, subs, counts);
+}
+void launch_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, const double* colnorm,
+                    double tau, hipStream_t s) {
+  if (m > 0) k_band_lu<<<m, kSetupThreads, 0, s>>>(ab, ipiv, subs, info, colnorm, tau);
 }
 void launch_convert_lower(const double* ab, const int32_t* ipiv, const SubInfo* subs, const LBlk* lb, int32_t nblk,
                           double* work, int32_t* lperm, void* lmat, int prec, hipStream_t s) {

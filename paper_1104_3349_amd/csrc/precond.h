@@ -180,6 +180,7 @@ struct addns_precond {
   addns::DevBuf ypad, zpad, z1, x2tmp;                // padded interior work vectors
   addns::DevBuf vperm_in, vperm_out;                  // permuted apply in/out
   int64_t factor_bytes = 0, bytes_apply = 0;
+  int64_t interior_nnz = 0;                           // stored entries of the interior L and U factors
   int64_t learned_count = 0;
   float tuned_ms = 0.0f;                              // autotuner timing of the interior solve
   int zero_skip = 0;                                  // sweep skips structural-zero row slots (autotuned)
@@ -208,7 +209,11 @@ void launch_gather(const int32_t* src, const double* in, int64_t n, double* out,
 void launch_scatter_band(const int64_t* dst, const int32_t* src, const double* cpv, int64_t n, double* ab,
                          hipStream_t s);
 void launch_band_pad_identity(const SubInfo* subs, int32_t m, double* ab, hipStream_t s);
-void launch_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, hipStream_t s);
+void launch_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, const double* colnorm,
+                    double tau, hipStream_t s);
+void launch_band_colnorm(const double* ab, const SubInfo* subs, int32_t m, int32_t npad_max, double* colnorm,
+                         hipStream_t s);
+void launch_band_nnz(const double* ab, const SubInfo* subs, int32_t m, int64_t* counts, hipStream_t s);
 void launch_convert_lower(const double* ab, const int32_t* ipiv, const SubInfo* subs, const LBlk* lb, int32_t nblk,
                           double* work, int32_t* lperm, void* lmat, int prec, hipStream_t s);
 void launch_convert_upper(const double* ab, const SubInfo* subs, const UBlk* ub, int32_t nblk, double* work,

@@ -33,9 +33,9 @@ def make_system(n, nu, m, sz=64, stretch=None, seed=1, wind=None):
     return System(n, meta["N"], rp, ci, v, b, meta, m, sz)
 
 
-def oracle_precond(S: System, schur=addns.SCHUR_MSCN, overlap=0):
+def oracle_precond(S: System, schur=addns.SCHUR_MSCN, overlap=0, ilu_tol=0.0):
     P = oracle_partition(S.N, S.rp, S.ci, S.v, S.m, S.sz)
-    return Preconditioner(S.N, S.rp, S.ci, S.v, P, ORACLE_MODE[schur], overlap=overlap)
+    return Preconditioner(S.N, S.rp, S.ci, S.v, P, ORACLE_MODE[schur], overlap=overlap, ilu_tol=ilu_tol)
 
 
 def gpu_precond(S: System, schur=addns.SCHUR_MSCN, iprec=addns.F64, sprec=addns.F64, part=None,
