@@ -15,6 +15,8 @@ Gram-Schmidt and Givens rotations):
       z_j = B^{-1} v_j                      (kept for FGMRES)
       w = C z_j
       for i = 1 .. j:  h_ij = <w, v_i>;  w = w - h_ij v_i     (MGS)
+        or, with ortho = "cgs2", classical Gram-Schmidt applied twice:
+        h = V_j^T w; w = w - V_j h; c = V_j^T w; w = w - V_j c; h += c
       h_{j+1,j} = ||w||;  v_{j+1} = w / h_{j+1,j}
       apply rotations 1..j-1 to column j; new rotation from (h_jj, h_{j+1,j})
       with t = hypot(a, b), c = a/t, s = b/t (b = 0: c = 1, s = 0);
@@ -47,7 +49,9 @@ def givens(a: float, b: float):
     return a / t, b / t
 
 
-def gmres(matvec, precond, b, x0=None, restart=30, tol=1e-8, maxit=1000, flexible=True):
+def gmres(matvec, precond, b, x0=None, restart=30, tol=1e-8, maxit=1000, flexible=True, ortho="mgs"):
+    if ortho not in ("mgs", "cgs2"):
+        raise ValueError(ortho)
     b = np.asarray(b, dtype=np.float64)
     N = b.size
     x = np.zeros(N) if x0 is None else np.array(x0, dtype=np.float64)
@@ -77,9 +81,17 @@ def gmres(matvec, precond, b, x0=None, restart=30, tol=1e-8, maxit=1000, flexibl
             if flexible:
                 Z[j] = z
             w = matvec(z)
-            for i in range(j + 1):
-                H[i, j] = float(np.dot(w, V[i]))
-                w = w - H[i, j] * V[i]
+            if ortho == "mgs":
+                for i in range(j + 1):
+                    H[i, j] = float(np.dot(w, V[i]))
+                    w = w - H[i, j] * V[i]
+            else:
+                Vj = V[:j + 1]
+                h = Vj @ w
+                w = w - Vj.T @ h
+                c = Vj @ w
+                w = w - Vj.T @ c
+                H[:j + 1, j] = h + c
             H[j + 1, j] = float(np.linalg.norm(w))
             breakdown = H[j + 1, j] == 0.0
             if not breakdown:
@@ -113,11 +125,11 @@ def gmres(matvec, precond, b, x0=None, restart=30, tol=1e-8, maxit=1000, flexibl
     return GmresResult(x, its, False, relres, est_hist, true_hist)
 
 
-def solve_system(pre, b_unscaled, restart=30, tol=1e-8, maxit=1000, flexible=True, x0=None):
+def solve_system(pre, b_unscaled, restart=30, tol=1e-8, maxit=1000, flexible=True, x0=None, ortho="mgs"):
     """Solve the row-scaled system C~ x = R b with B from `pre` (right)."""
     bt = pre.R * b_unscaled
     return gmres(lambda v: pre.C @ v, pre.apply, bt, x0=x0, restart=restart, tol=tol,
-                 maxit=maxit, flexible=flexible)
+                 maxit=maxit, flexible=flexible, ortho=ortho)
 
 
 def exact_solve(rowptr, colidx, vals, b):
