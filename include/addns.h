@@ -229,7 +229,15 @@ typedef struct {
   double tol;        /* stop when ||b~ - C~ x|| / ||b~|| <= tol */
   int32_t flexible;  /* 1 = FGMRES (store Z), 0 = GMRES (x += B^-1 V y) */
   int32_t use_x0;    /* 1 = d_x holds the initial guess, 0 = start from zero */
+  int32_t ortho;     /* Arnoldi orthogonalisation (section 5 leaves it open):
+                        ADDNS_ORTHO_MGS, modified Gram-Schmidt, one launch per
+                        basis vector; ADDNS_ORTHO_CGS2, classical Gram-Schmidt
+                        applied twice, all inner products of a pass in one
+                        launch (5 launches per iteration whatever the basis
+                        size).  The batched solver takes MGS only. */
 } addns_gmres_opts;
+
+enum { ADDNS_ORTHO_MGS = 0, ADDNS_ORTHO_CGS2 = 1 };
 
 typedef struct {
   int32_t iters;         /* inner iterations taken */
@@ -243,7 +251,8 @@ typedef struct {
 
 /* ------------------------------------------------------------------------
  * addns_gmres_solve -- restarted (F)GMRES with right preconditioning by B,
- * modified Gram-Schmidt Arnoldi and Givens rotations, all in FP64 on the
+ * Arnoldi by modified or twice-applied classical Gram-Schmidt (opts.ortho)
+ * and Givens rotations, all in FP64 on the
  * GPU (section 5 accelerator).  Solves C x = b through the row-scaled system.
  *   d_b : DEVICE right-hand side of the unscaled system (length N).
  *   d_x : DEVICE solution (length N); initial guess if opts.use_x0.

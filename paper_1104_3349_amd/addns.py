@@ -49,7 +49,7 @@ class PrecondOpts(C.Structure):
 
 class GmresOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("tol", C.c_double),
-                ("flexible", C.c_int32), ("use_x0", C.c_int32)]
+                ("flexible", C.c_int32), ("use_x0", C.c_int32), ("ortho", C.c_int32)]
 
 
 class DtnParams(C.Structure):
@@ -273,9 +273,19 @@ def interior_solve(pc: Precond, d_y1, d_z1, stream=None):
            "interior_solve")
 
 
+ORTHO_MGS, ORTHO_CGS2 = 0, 1
+_ORTHO = {"mgs": ORTHO_MGS, "cgs2": ORTHO_CGS2}
+
+
+def _ortho(o):
+    """'mgs' / 'cgs2' or the integer code (passed through: the library checks it)."""
+    return _ORTHO[o] if isinstance(o, str) else int(o)
+
+
 def gmres_solve(pc: Precond, d_b, d_x, restart=50, maxit=1000, tol=1e-8, flexible=True,
-                use_x0=False, history=False, stream=None, raise_noconv=False):
-    opts = GmresOpts(int(restart), int(maxit), float(tol), int(bool(flexible)), int(bool(use_x0)))
+                use_x0=False, history=False, stream=None, raise_noconv=False, ortho="cgs2"):
+    opts = GmresOpts(int(restart), int(maxit), float(tol), int(bool(flexible)), int(bool(use_x0)),
+                     _ortho(ortho))
     res = GmresResult()
     hist = None
     if history:
@@ -296,7 +306,7 @@ def gmres_solve_batched(pc: Precond, sys_offsets, d_b, d_x, restart=50, maxit=10
                         use_x0=False, history=False, stream=None):
     offs = np.ascontiguousarray(sys_offsets, dtype=np.int32)
     nsys = len(offs) - 1
-    opts = GmresOpts(int(restart), int(maxit), float(tol), 1, int(bool(use_x0)))
+    opts = GmresOpts(int(restart), int(maxit), float(tol), 1, int(bool(use_x0)), ORTHO_MGS)
     res = (GmresResult * nsys)()
     hists = []
     if history:
@@ -328,8 +338,9 @@ def _gmres_out(res, code, hist):
 
 
 def gmres_solve_judged(learned: Precond, plain: Precond, d_b, d_x, restart=50, maxit=1000, tol=1e-8,
-                       flexible=True, use_x0=False, history=False, stream=None):
-    opts = GmresOpts(int(restart), int(maxit), float(tol), int(bool(flexible)), int(bool(use_x0)))
+                       flexible=True, use_x0=False, history=False, stream=None, ortho="cgs2"):
+    opts = GmresOpts(int(restart), int(maxit), float(tol), int(bool(flexible)), int(bool(use_x0)),
+                     _ortho(ortho))
     res = GmresResult()
     hist = None
     if history:

@@ -306,6 +306,7 @@ float time_interior_solve(addns_precond* pc, hipStream_t s) {
 
 struct GmresWork {
   double *V, *Z, *w, *xp, *bp, *rp, *H, *g, *cs, *sn, *y, *pa, *pb, *scal;
+  double *ca, *cb, *hc;  // CGS2 partial tables ((restart+1) x 1024 each) and coefficients
 };
 
 GmresWork gmres_work(addns_precond* pc, int restart, int flexible) {
@@ -320,6 +321,7 @@ GmresWork gmres_work(addns_precond* pc, int restart, int flexible) {
     const int ldh = restart + 1;
     pc->Hd.alloc(sizeof(double) * ((int64_t)ldh * restart + 4 * ldh));
     pc->partials.alloc(sizeof(double) * 2 * 1024);
+    pc->cgs.alloc(sizeof(double) * ((int64_t)2 * ldh * 1024 + ldh));
     pc->scal.alloc(sizeof(double) * 8);
     pc->gm_restart = restart;
     if (!pc->host_pinned) ADDNS_HIP(hipHostMalloc(&pc->host_pinned, 64, hipHostMallocDefault));
@@ -340,6 +342,9 @@ GmresWork gmres_work(addns_precond* pc, int restart, int flexible) {
   g.y = g.sn + ldh;
   g.pa = pc->partials.as<double>();
   g.pb = g.pa + 1024;
+  g.ca = pc->cgs.as<double>();
+  g.cb = g.ca + (int64_t)ldh * 1024;
+  g.hc = g.cb + (int64_t)ldh * 1024;
   g.scal = pc->scal.as<double>();
   return g;
 }
@@ -466,6 +471,7 @@ int addns_gmres_solve(addns_precond_t pc, const double* d_b, double* d_x, const 
     const int restart = opts->restart, maxit = opts->maxit;
     if (restart < 1 || restart > 1024 || maxit < 0 || !(opts->tol > 0.0))
       throw ArgError("1 <= restart <= 1024, maxit >= 0, tol > 0");
+    if (opts->ortho != ADDNS_ORTHO_MGS && opts->ortho != ADDNS_ORTHO_CGS2) throw ArgError("unknown ortho");
     hipStream_t s = as_stream(stream);
     const int32_t N = pc->plan.N;
     const Plan& pl = pc->plan;
@@ -511,15 +517,28 @@ int addns_gmres_solve(addns_precond_t pc, const double* d_b, double* d_x, const 
         double* vj = g.V + (int64_t)j * N;
         double* zj = opts->flexible ? g.Z + (int64_t)j * N : g.Z;
         apply_permuted(pc, vj, zj, s);
-        launch_spmv_dot(rp, ci, cv, zj, g.w, g.V, N, g.pa, s);
         double* pin = g.pa;
-        double* pout = g.pb;
-        for (int i = 0; i <= j; ++i) {
-          const double* vnext = i < j ? g.V + (int64_t)(i + 1) * N : nullptr;
-          launch_mgs_step(g.w, g.V + (int64_t)i * N, vnext, N, pin, pout, g.H + (int64_t)j * ldh + i, nparts, s);
-          std::swap(pin, pout);
+        int pnorm_parts = nparts;
+        if (opts->ortho == ADDNS_ORTHO_CGS2) {
+          // h = V^T w; w -= V h; c = V^T w; w -= V c; h += c (a fixed number of launches)
+          double* hcol = g.H + (int64_t)j * ldh;
+          const int cparts = cgs_parts(N);
+          launch_spmv_dots(rp, ci, cv, zj, g.w, g.V, j + 1, N, g.ca, s);
+          launch_cgs_coeffs(g.ca, cparts, j + 1, g.hc, hcol, 0, s);
+          launch_cgs_update(g.w, g.V, j + 1, g.hc, N, g.cb, 0, s);
+          launch_cgs_coeffs(g.cb, cparts, j + 1, g.hc, hcol, 1, s);
+          launch_cgs_update(g.w, g.V, j + 1, g.hc, N, g.pa, 1, s);
+          pnorm_parts = cparts;
+        } else {
+          launch_spmv_dot(rp, ci, cv, zj, g.w, g.V, N, g.pa, s);
+          double* pout = g.pb;
+          for (int i = 0; i <= j; ++i) {
+            const double* vnext = i < j ? g.V + (int64_t)(i + 1) * N : nullptr;
+            launch_mgs_step(g.w, g.V + (int64_t)i * N, vnext, N, pin, pout, g.H + (int64_t)j * ldh + i, nparts, s);
+            std::swap(pin, pout);
+          }
         }
-        launch_finalize(g.H, g.g, g.cs, g.sn, pin, nparts, j, ldh, g.scal, s);
+        launch_finalize(g.H, g.g, g.cs, g.sn, pin, pnorm_parts, j, ldh, g.scal, s);
         launch_scale_copy(g.w, g.V + (int64_t)(j + 1) * N, g.scal, 0, N, s);
         double* h = static_cast<double*>(pc->host_pinned);
         ADDNS_HIP(hipMemcpyAsync(h, g.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -569,6 +588,7 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
     if (restart < 1 || restart > 1024 || maxit < 0 || !(opts->tol > 0.0))
       throw ArgError("1 <= restart <= 1024, maxit >= 0, tol > 0");
     if (!opts->flexible) throw ArgError("the batched solver is flexible GMRES only");
+    if (opts->ortho != ADDNS_ORTHO_MGS) throw ArgError("the batched solver orthogonalises by MGS (ortho = 0)");
     const Plan& pl = pc->plan;
     const int32_t N = pl.N;
     if (sys_offsets[0] != 0 || sys_offsets[nsys] != N) throw ArgError("sys_offsets must run from 0 to N");

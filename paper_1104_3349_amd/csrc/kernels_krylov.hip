@@ -182,6 +182,150 @@ k_finalize(double* __restrict__ H, double* __restrict__ g, double* __restrict__ 
   scal[1] = fabs(g[j + 1]);
 }
 
+// ---------------------------------------------------------------------------
+// Classical Gram-Schmidt applied twice (CGS2): every basis vector's inner
+// product in one pass over the rows.  A workgroup's rows of w stay in
+// registers (kPerThread per thread, rows beyond that on a grid-stride tail);
+// per basis vector the wave partials meet in LDS, and partials[i * nparts +
+// workgroup] receives the workgroup's sum in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kDotChunk = 16;  // basis vectors per round: independent loads, then interleaved reductions
+constexpr int kCgsRows = 2;    // rows per thread held in registers by the CGS2 kernels
+
+// Grid of the CGS2 kernels: kCgsRows rows per thread, at most kMaxParts
+// workgroups (rows beyond that on a grid-stride tail).
+inline int cgs_grid(int32_t n) {
+  int g = (int)((n + kKT * kCgsRows - 1) / (kKT * kCgsRows));
+  return std::max(1, std::min(g, kMaxParts));
+}
+
+// Loads are unconditional (rows clamped to n-1, vectors past the chunk's
+// end clamped to its last one; the clamped products are zero or dropped) so
+// that the compiler issues a chunk's loads together.
+__device__ inline void basis_dots(const double (&wv)[kCgsRows], const double* __restrict__ w,
+                                  const double* __restrict__ V, int nvec, int32_t n, double* __restrict__ partials,
+                                  int nparts, double (*s_part)[kKT / 64]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int32_t stride = gridDim.x * blockDim.x, i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t rc[kCgsRows];
+#pragma unroll
+  for (int k = 0; k < kCgsRows; ++k) rc[k] = min(i0 + k * stride, n - 1);
+  for (int c0 = 0; c0 < nvec; c0 += kDotChunk) {
+    const int cn = min(kDotChunk, nvec - c0);
+    double acc[kDotChunk];
+#pragma unroll
+    for (int c = 0; c < kDotChunk; ++c) {
+      const double* vi = V + (int64_t)(c0 + min(c, cn - 1)) * n;
+      double a = 0.0;
+#pragma unroll
+      for (int k = 0; k < kCgsRows; ++k) a += wv[k] * vi[rc[k]];
+      acc[c] = a;
+    }
+    for (int32_t r = i0 + kCgsRows * stride; r < n; r += stride) {
+      const double y = w[r];
+#pragma unroll
+      for (int c = 0; c < kDotChunk; ++c) acc[c] += y * V[(int64_t)(c0 + min(c, cn - 1)) * n + r];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+      for (int c = 0; c < kDotChunk; ++c) acc[c] += __shfl_xor(acc[c], off);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < kDotChunk; ++c)
+        if (c < cn) s_part[c][wave] = acc[c];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < cn) {
+      double s = 0.0;
+      for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += s_part[threadIdx.x][q];
+      partials[(int64_t)(c0 + threadIdx.x) * nparts + blockIdx.x] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// w = A z and the partials of <w, V_i>, i < nvec.
+__global__ void __launch_bounds__(kKT)
+k_spmv_dots(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx, const double* __restrict__ vals,
+            const double* __restrict__ z, double* __restrict__ w, const double* __restrict__ V, int nvec, int32_t n,
+            double* __restrict__ partials) {
+  __shared__ double s_part[kDotChunk][kKT / 64];
+  const int32_t stride = gridDim.x * blockDim.x, i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  double wv[kCgsRows];
+#pragma unroll
+  for (int k = 0; k < kCgsRows; ++k) {
+    const int32_t r = i0 + k * stride;
+    wv[k] = r < n ? row_dot(rowptr, colidx, vals, z, r) : 0.0;
+    if (r < n) w[r] = wv[k];
+  }
+  for (int32_t r = i0 + kCgsRows * stride; r < n; r += stride) w[r] = row_dot(rowptr, colidx, vals, z, r);
+  basis_dots(wv, w, V, nvec, n, partials, gridDim.x, s_part);  // tail rows: re-read by their own thread
+}
+
+// h_i = sum of the partials of basis vector i, one workgroup per vector
+// (fixed-order tree); Hcol = h, or Hcol += h for the second pass.
+__global__ void __launch_bounds__(kKT)
+k_cgs_coeffs(const double* __restrict__ partials, int nparts, double* __restrict__ h, double* __restrict__ Hcol,
+             int add) {
+  __shared__ double red[kKT / 64];
+  const int i = blockIdx.x;
+  const double s = reduce_parts(partials + (int64_t)i * nparts, nparts, red);
+  if (threadIdx.x == 0) {
+    h[i] = s;
+    Hcol[i] = add ? Hcol[i] + s : s;
+  }
+}
+
+// w -= sum_i h_i V_i (i ascending), then the partials of <w, V_i> (mode 0)
+// or of <w, w> (mode 1, into partials[workgroup]).
+__global__ void __launch_bounds__(kKT)
+k_cgs_update(double* __restrict__ w, const double* __restrict__ V, int nvec, const double* __restrict__ h, int32_t n,
+             double* __restrict__ partials, int mode) {
+  __shared__ double s_h[kMaxRestart + 1];
+  __shared__ double s_part[kDotChunk][kKT / 64];
+  __shared__ double red[kKT / 64];
+  for (int i = threadIdx.x; i < nvec; i += blockDim.x) s_h[i] = h[i];
+  const int32_t stride = gridDim.x * blockDim.x, i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  double wv[kCgsRows];
+  int32_t rc[kCgsRows];
+#pragma unroll
+  for (int k = 0; k < kCgsRows; ++k) {
+    const int32_t r = i0 + k * stride;
+    rc[k] = min(r, n - 1);
+    wv[k] = r < n ? w[r] : 0.0;
+  }
+  __syncthreads();
+  for (int i = 0; i < nvec; ++i) {
+    const double* vi = V + (int64_t)i * n;
+    const double hi = s_h[i];
+#pragma unroll
+    for (int k = 0; k < kCgsRows; ++k) wv[k] -= hi * vi[rc[k]];
+  }
+#pragma unroll
+  for (int k = 0; k < kCgsRows; ++k) {
+    const int32_t r = i0 + k * stride;
+    if (r < n) w[r] = wv[k];
+    else wv[k] = 0.0;
+  }
+  for (int32_t r = i0 + kCgsRows * stride; r < n; r += stride) {
+    double y = w[r];
+    for (int i = 0; i < nvec; ++i) y -= s_h[i] * V[(int64_t)i * n + r];
+    w[r] = y;
+  }
+  if (mode == 0) {
+    basis_dots(wv, w, V, nvec, n, partials, gridDim.x, s_part);
+  } else {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kCgsRows; ++k) acc += wv[k] * wv[k];
+    for (int32_t r = i0 + kCgsRows * stride; r < n; r += stride) acc += w[r] * w[r];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  }
+}
+
 __global__ void k_norm_finalize(const double* __restrict__ partials, int nparts, double* __restrict__ scal, int idx) {
   __shared__ double red[kKT / 64];
   const double s = reduce_parts(partials, nparts, red);
@@ -444,6 +588,18 @@ void launch_mgs_step(double* w, const double* vi, const double* vnext, int32_t n
 void launch_finalize(double* H, double* g, double* cs, double* sn, const double* partials, int nparts, int32_t j,
                      int32_t ldh, double* scal, hipStream_t s) {
   k_finalize<<<1, kKT, 0, s>>>(H, g, cs, sn, partials, nparts, j, ldh, scal);
+}
+int cgs_parts(int32_t n) { return cgs_grid(n); }
+void launch_spmv_dots(const int32_t* rowptr, const int32_t* colidx, const double* vals, const double* z, double* w,
+                      const double* V, int nvec, int32_t n, double* partials, hipStream_t s) {
+  k_spmv_dots<<<cgs_grid(n), kKT, 0, s>>>(rowptr, colidx, vals, z, w, V, nvec, n, partials);
+}
+void launch_cgs_coeffs(const double* partials, int nparts, int nvec, double* h, double* Hcol, int add, hipStream_t s) {
+  if (nvec > 0) k_cgs_coeffs<<<nvec, kKT, 0, s>>>(partials, nparts, h, Hcol, add);
+}
+void launch_cgs_update(double* w, const double* V, int nvec, const double* h, int32_t n, double* partials, int mode,
+                       hipStream_t s) {
+  k_cgs_update<<<cgs_grid(n), kKT, 0, s>>>(w, V, nvec, h, n, partials, mode);
 }
 void launch_norm_finalize(const double* partials, int nparts, double* scal, int idx, hipStream_t s) {
   k_norm_finalize<<<1, kKT, 0, s>>>(partials, nparts, scal, idx);

@@ -188,6 +188,7 @@ struct addns_precond {
   addns::DevBuf smp_row, smp_nb, smp_loc;             // learned-correction sample table
   // GMRES work space (grown on demand)
   addns::DevBuf V, Z, w, xp, bp, rp, Hd, gd, partials, scal;
+  addns::DevBuf cgs;                                  // CGS2: two (restart+1) x 1024 partial tables and h
   int gm_restart = 0;
   void* host_pinned = nullptr;
   ~addns_precond() {
@@ -254,6 +255,12 @@ void launch_spmv_dot(const int32_t* rowptr, const int32_t* colidx, const double*
                      double* w, const double* v0, int32_t n, double* partials, hipStream_t s);
 void launch_residual(const int32_t* rowptr, const int32_t* colidx, const double* vals, const double* x,
                      const double* b, double* r, int32_t n, double* partials, hipStream_t s);
+int cgs_parts(int32_t n);  // partials per basis vector of the CGS2 kernels
+void launch_spmv_dots(const int32_t* rowptr, const int32_t* colidx, const double* vals, const double* z, double* w,
+                      const double* V, int nvec, int32_t n, double* partials, hipStream_t s);
+void launch_cgs_coeffs(const double* partials, int nparts, int nvec, double* h, double* Hcol, int add, hipStream_t s);
+void launch_cgs_update(double* w, const double* V, int nvec, const double* h, int32_t n, double* partials, int mode,
+                       hipStream_t s);
 void launch_mgs_step(double* w, const double* vi, const double* vnext, int32_t n, const double* partials_in,
                      double* partials_out, double* h_out, int nparts, hipStream_t s);
 void launch_finalize(double* H, double* g, double* cs, double* sn, const double* partials, int nparts,

@@ -144,10 +144,12 @@ def test_apply_mixed(case, iprec, sprec, tol):
     assert e <= tol
 
 
-@pytest.mark.parametrize("flexible,schur", [(True, addns.SCHUR_MSCN), (False, addns.SCHUR_MSCN),
-                                            (True, addns.SCHUR_MSCNR)])
-def test_gmres_equal_iterations(case, flexible, schur):
-    """Iterates after the same number of steps agree to 1e-10 relative."""
+@pytest.mark.parametrize("flexible,schur,ortho", [(True, addns.SCHUR_MSCN, "cgs2"), (False, addns.SCHUR_MSCN, "cgs2"),
+                                                  (True, addns.SCHUR_MSCNR, "cgs2"), (True, addns.SCHUR_MSCN, "mgs"),
+                                                  (False, addns.SCHUR_MSCN, "mgs")])
+def test_gmres_equal_iterations(case, flexible, schur, ortho):
+    """Iterates after the same number of steps agree to 1e-10 relative, for
+    either orthogonalisation (against the oracle's of the same kind)."""
     name, S = case
     ora = oracle_precond(S, schur)
     part, pc = gpu_precond(S, schur)
@@ -155,13 +157,13 @@ def test_gmres_equal_iterations(case, flexible, schur):
     restart = 5
     bt = ora.R * S.b
     ref = gmres(lambda x: ora.C @ x, ora.apply, bt, restart=restart, tol=1e-300, maxit=k,
-                flexible=flexible)
+                flexible=flexible, ortho=ortho)
     d_b, d_x = _cuda(S.b), torch.zeros(S.N, dtype=torch.float64, device="cuda")
     r = addns.gmres_solve(pc, d_b, d_x, restart=restart, maxit=k, tol=1e-300, flexible=flexible,
-                          history=True)
+                          history=True, ortho=ortho)
     assert r["iters"] == k and not r["converged"]
     e = relerr(d_x.cpu().numpy(), ref.x)
-    MEASURED[f"gmres_equal_its_{name}_{flexible}_{schur}"] = e
+    MEASURED[f"gmres_equal_its_{name}_{flexible}_{schur}_{ortho}"] = e
     assert e <= 1e-10
     assert abs(r["true_relres"] - ref.true_relres) <= 1e-8 * max(ref.true_relres, 1e-300) + 1e-14
     np.testing.assert_allclose(r["history"], ref.est_history, rtol=1e-8, atol=0)
@@ -305,7 +307,7 @@ def test_setup_argument_errors():
     with pytest.raises(addns.AddnsError):
         addns.apply_precond(pc, d, d)
     x = torch.zeros_like(d)
-    for bad in (dict(restart=0), dict(restart=1025), dict(tol=0.0), dict(maxit=-1)):
+    for bad in (dict(restart=0), dict(restart=1025), dict(tol=0.0), dict(maxit=-1), dict(ortho=7)):
         kw = dict(restart=10, maxit=10, tol=1e-8)
         kw.update(bad)
         with pytest.raises(addns.AddnsError) as e:
