@@ -306,42 +306,70 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
 }
 
 // One workgroup per aggregate: t = y2 - F z1 on the aggregate's rows, then
-// x2 = S_i^{-1} t with S_i^{-1} column-major.
+// x2 = S_i^{-1} t with S_i^{-1} column-major.  Thread (r, cs) owns row r of
+// the GEMV and column chunk cs (Rp rows, CS = 1024 / Rp chunks); up to 128
+// rows, a chunk fits kIfPref registers and is loaded before the gather of t
+// (it does not depend on t), so the two memory latencies overlap.  The
+// chunk partials meet in LDS in a fixed order.
+constexpr int kIfPref = 16;
+
 template <class T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_interface_solve(int32_t n_int, const int32_t* __restrict__ agg_off, const int32_t* __restrict__ f_rowptr,
                   const int32_t* __restrict__ f_colidx, const double* __restrict__ f_vals,
                   const int64_t* __restrict__ sinv_off, const T* __restrict__ sinv, const float* __restrict__ scale,
                   int scaled, const double* __restrict__ y, const double* __restrict__ z1, double* __restrict__ out) {
   __shared__ double t[1024];
-  __shared__ double part[4 * 256];
+  __shared__ double part[1024];
   const int i = blockIdx.x;
   const int32_t a0 = agg_off[i], s = agg_off[i + 1] - a0;
   const int tid = threadIdx.x;
-  for (int32_t r = tid; r < s; r += blockDim.x) {
-    int32_t row = a0 + r;
+  const T* M = sinv + sinv_off[i];
+  const int Rp = s <= 64 ? 64 : (s <= 128 ? 128 : (s <= 256 ? 256 : 1024));
+  const int CS = 1024 / Rp;
+  const int r = tid % Rp, cs = tid / Rp;
+  const int32_t kb = (int32_t)((int64_t)s * cs / CS), ke = (int32_t)((int64_t)s * (cs + 1) / CS);
+  const bool pref = s <= 128;  // then ke - kb <= 128 / 8 = kIfPref
+  double mv[kIfPref];
+  if (pref) {
+#pragma unroll
+    for (int q = 0; q < kIfPref; ++q) {
+      const int32_t k = kb + q;
+      mv[q] = (r < s && k < ke) ? ld(M + (int64_t)k * s + r) : 0.0;
+    }
+  }
+  for (int32_t q = tid; q < s; q += blockDim.x) {
+    const int32_t row = a0 + q;
     double acc = y[n_int + row];
     for (int32_t e = f_rowptr[row]; e < f_rowptr[row + 1]; ++e) acc -= f_vals[e] * z1[f_colidx[e]];
-    t[r] = acc;
+    t[q] = acc;
   }
   __syncthreads();
-  const T* M = sinv + sinv_off[i];
-  // rows r = tid % Rp, column chunk tid / Rp
-  const int Rp = s <= 64 ? 64 : (s <= 128 ? 128 : 256);
-  const int CS = 256 / Rp;
-  const int r = tid % Rp, cs = tid / Rp;
+  if (pref) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < kIfPref; ++q)
+      if (kb + q < ke) acc += mv[q] * t[kb + q];
+    part[cs * Rp + r] = acc;
+    __syncthreads();
+    if (cs == 0 && r < s) {
+      double acc2 = 0.0;
+      for (int c = 0; c < CS; ++c) acc2 += part[c * Rp + r];
+      if (scaled) acc2 *= (double)scale[i];
+      out[n_int + a0 + r] = acc2;
+    }
+    return;
+  }
   for (int32_t rb = 0; rb < s; rb += Rp) {
     const int32_t row = rb + r;
     double acc = 0.0;
-    if (row < s) {
-      int32_t kb = (int32_t)((int64_t)s * cs / CS), ke = (int32_t)((int64_t)s * (cs + 1) / CS);
+    if (row < s)
       for (int32_t k = kb; k < ke; ++k) acc += ld(M + (int64_t)k * s + row) * t[k];
-    }
-    part[cs * 256 + r] = acc;
+    part[cs * Rp + r] = acc;
     __syncthreads();
     if (cs == 0 && row < s) {
       double acc2 = 0.0;
-      for (int c = 0; c < CS; ++c) acc2 += part[c * 256 + r];
+      for (int c = 0; c < CS; ++c) acc2 += part[c * Rp + r];
       if (scaled) acc2 *= (double)scale[i];
       out[n_int + a0 + row] = acc2;
     }
@@ -457,13 +485,13 @@ void launch_interface_solve(const addns_precond* pc, const double* y, const doub
   const double* fv = pc->f_vals.as<double>();
   const int64_t* so = pc->sinv_off.as<int64_t>();
   if (pc->schur_prec == P64)
-    k_interface_solve<double><<<pl.k, 256, 0, s>>>(pl.n_int, ao, fr, fc, fv, so, pc->sinv.as<double>(), nullptr, 0, y,
+    k_interface_solve<double><<<pl.k, 1024, 0, s>>>(pl.n_int, ao, fr, fc, fv, so, pc->sinv.as<double>(), nullptr, 0, y,
                                                    z1, out);
   else if (pc->schur_prec == P32)
-    k_interface_solve<float><<<pl.k, 256, 0, s>>>(pl.n_int, ao, fr, fc, fv, so, pc->sinv.as<float>(), nullptr, 0, y,
+    k_interface_solve<float><<<pl.k, 1024, 0, s>>>(pl.n_int, ao, fr, fc, fv, so, pc->sinv.as<float>(), nullptr, 0, y,
                                                   z1, out);
   else
-    k_interface_solve<__half><<<pl.k, 256, 0, s>>>(pl.n_int, ao, fr, fc, fv, so, pc->sinv.as<__half>(),
+    k_interface_solve<__half><<<pl.k, 1024, 0, s>>>(pl.n_int, ao, fr, fc, fv, so, pc->sinv.as<__half>(),
                                                    pc->sinv_scale.as<float>(), 1, y, z1, out);
 }
 
