@@ -91,8 +91,13 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
     int32_t npad_max = 0;
     for (const SubInfo& q : pl.subs) npad_max = std::max(npad_max, q.npad);
     launch_band_colnorm(ab.as<double>(), pc->subs.as<SubInfo>(), m, npad_max, colnorm.as<double>(), s);
+    int32_t kl_max = 0, kv_max = 0;
+    for (const SubInfo& q : pl.subs) {
+      kl_max = std::max(kl_max, q.kl);
+      kv_max = std::max(kv_max, q.kl + q.ku);
+    }
     launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), m, info.as<int32_t>(),
-                   colnorm.as<double>(), o.ilu_tol, s);
+                   colnorm.as<double>(), o.ilu_tol, kl_max, kv_max, s);
     nnz.alloc(sizeof(int64_t) * m);
     launch_band_nnz(ab.as<double>(), pc->subs.as<SubInfo>(), m, nnz.as<int64_t>(), s);
     std::vector<int32_t> h_info(m + 4);

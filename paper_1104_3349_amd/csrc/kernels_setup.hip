@@ -182,6 +182,298 @@ k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const Sub
   if (tid == 0) info[sub] = s_info;
 }
 
+// ---------------------------------------------------------------------------
+// Blocked form of the same band LU (identical pivots and factor entries,
+// bit for bit): panels of kPanel columns.  One wave factors a panel (rows
+// j0 .. j0+KL+nb-1) with the rows in its registers and full-row interchanges
+// inside the panel (getrf style); the panel's interchanges are then applied
+// to the trailing columns j0+nb .. ju and the panel rows of those columns are
+// solved with the panel's unit lower triangle (one thread per column, with
+// the ILU drop of U entries); the rows below the panel receive one rank-nb
+// update, each entry's terms subtracted in the unblocked elimination's order
+// (a step that skipped a column contributes an exact zero).  Finally each
+// panel column's multipliers are returned to band storage order (the later
+// interchanges of the same panel undone), which is what the sweep conversion
+// reads.  The trailing window is read and written once per panel instead of
+// once per column.  Bands whose panel does not fit 3 x 64 rows per lane use
+// the unblocked kernel.
+// ---------------------------------------------------------------------------
+constexpr int kPanel = 8;
+
+__device__ inline double readlane_d(double x, int32_t l) {
+  const int64_t bits = __double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)bits, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(bits >> 32), l);
+  return __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+}
+
+// The same panel factorisation with the panel in registers: lane l holds
+// rows l + 64k (k < NS) of the nb columns, the pivot row and row c are
+// broadcast with readlane, and the pivot search uses one max reduction and
+// ballots.  Each entry sees the same operations in the same order as in the
+// LDS form, so the results are identical.
+template <int NS>
+__device__ void panel_regs(double* s_pan, int32_t prmax, int32_t prows, int32_t j0, int32_t nb, int32_t n,
+                           int32_t KL, int32_t KU, int lane, double tau, const double* cn, int32_t* ipiv,
+                           int32_t* s_pv, int32_t* s_ok, int32_t* s_juc, int32_t& s_ju, int32_t& s_info) {
+  double a[NS][kPanel];
+#pragma unroll
+  for (int k = 0; k < NS; ++k)
+#pragma unroll
+    for (int c = 0; c < kPanel; ++c) {
+      const int32_t r = lane + 64 * k;
+      a[k][c] = (c < nb && r < prows) ? s_pan[c * prmax + r] : 0.0;
+    }
+  // drop thresholds of the panel columns, loaded once
+  double dropc[kPanel];
+#pragma unroll
+  for (int c = 0; c < kPanel; ++c) dropc[c] = c < nb ? tau * cn[j0 + c] : 0.0;
+  int32_t ju = s_ju, info = s_info;
+#pragma unroll
+  for (int c = 0; c < kPanel; ++c) {
+    if (c >= nb) break;
+    const int32_t jj = j0 + c, km = min(KL, n - 1 - jj);
+    // pivot: the first row of c .. c+km within the tie tolerance of the largest
+    double best = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int32_t r = lane + 64 * k;
+      if (r >= c && r <= c + km) best = fmax(best, fabs(a[k][c]));
+    }
+    for (int off = 32; off >= 1; off >>= 1) best = fmax(best, __shfl_xor(best, off));
+    const double thr = (1.0 - kPivotTie) * best;
+    int32_t prow = c;
+    bool found = false;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int32_t r = lane + 64 * k;
+      const uint64_t msk = __ballot(r >= c && r <= c + km && fabs(a[k][c]) >= thr);
+      if (!found && msk != 0) {
+        prow = 64 * k + (int32_t)__builtin_ctzll(msk);
+        found = true;
+      }
+    }
+    const int32_t p = prow - c, pl = prow & 63, pk = prow >> 6;
+    double piv = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+      if (k == pk) piv = readlane_d(a[k][c], pl);
+    const double top = readlane_d(a[0][c], c);
+    const bool ok = piv != 0.0;
+    ju = max(ju, min(jj + KU + p, n - 1));
+    if (lane == 0) {
+      s_pv[c] = p;
+      s_ok[c] = ok;
+      s_juc[c] = ju;
+      ipiv[jj] = jj + p;
+    }
+    if (!ok) {
+      if (info == 0) info = jj + 1;
+      continue;
+    }
+    // the interchange of rows c and prow in the other panel columns; row c
+    // of the later columns becomes U (dropped below the threshold)
+    double u[kPanel];
+#pragma unroll
+    for (int cc = 0; cc < kPanel; ++cc) {
+      if (cc == c || cc >= nb) continue;
+      double rp = 0.0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (k == pk) rp = readlane_d(a[k][cc], pl);
+      const double rc = readlane_d(a[0][cc], c);
+      u[cc] = rp;
+      if (cc > c && j0 + cc <= ju && fabs(rp) < dropc[cc]) u[cc] = 0.0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+        if (k == pk && lane == pl) a[k][cc] = rc;
+      if (lane == c) a[0][cc] = u[cc];
+    }
+    // multipliers of column c from its values before the interchange
+    const double rinv = 1.0 / piv, drop_l = dropc[c];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int32_t r = lane + 64 * k;
+      if (r > c && r <= c + km) {
+        const double v = (r == prow) ? top : a[k][c];
+        a[k][c] = fabs(v) < drop_l ? 0.0 : v * rinv;
+      }
+    }
+    if (lane == c) a[0][c] = piv;
+    // rank-1 update of the later panel columns
+#pragma unroll
+    for (int cc = c + 1; cc < kPanel; ++cc) {
+      if (cc >= nb || j0 + cc > ju) continue;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const int32_t r = lane + 64 * k;
+        if (r > c && r <= c + km) a[k][cc] -= a[k][c] * u[cc];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k)
+#pragma unroll
+    for (int c = 0; c < kPanel; ++c) {
+      const int32_t r = lane + 64 * k;
+      if (c < nb && r < prows) s_pan[c * prmax + r] = a[k][c];
+    }
+  if (lane == 0) {
+    s_ju = ju;
+    s_info = info;
+  }
+}
+
+template <int NS>
+__global__ void __launch_bounds__(kSetupThreads)
+k_band_lu_blocked(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const SubInfo* __restrict__ subs,
+                  int32_t* __restrict__ info, const double* __restrict__ colnorm_all, double tau, int32_t prmax,
+                  int32_t ntmax) {
+  extern __shared__ double s_dyn[];
+  double* s_pan = s_dyn;                         // column c of the panel at c * prmax (rows j0 ..)
+  double* s_u12 = s_dyn + kPanel * prmax;        // U12 row c at c * ntmax (trailing column t)
+  __shared__ int32_t s_pv[kPanel], s_juc[kPanel], s_ok[kPanel];
+  __shared__ int32_t s_ju, s_info;
+  const int sub = blockIdx.x;
+  const SubInfo q = subs[sub];
+  const int32_t n = q.npad, ldab = q.ldab, KL = q.kl, KU = q.ku, KV = KL + KU;
+  double* ab = ab_all + q.band_off;
+  int32_t* ipiv = ipiv_all + q.vec_off;
+  const double* cn = colnorm_all + q.vec_off;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // entry (r, c) of the block lives at ab[c * ldab + KV + r - c] for -KV <= r - c <= KL
+  auto at = [&](int32_t r, int32_t c) -> double& { return ab[(int64_t)c * ldab + KV + r - c]; };
+  if (tid == 0) {
+    s_ju = 0;
+    s_info = 0;
+  }
+  for (int32_t j0 = 0; j0 < n; j0 += kPanel) {
+    const int32_t nb = min(kPanel, n - j0);
+    const int32_t prows = min(KL + nb, n - j0);
+    for (int32_t e = tid; e < nb * prows; e += blockDim.x) {
+      const int32_t c = e / prows, rr = e % prows, d = j0 + rr - (j0 + c);
+      s_pan[c * prmax + rr] = (d <= KL && d >= -KV) ? at(j0 + rr, j0 + c) : 0.0;
+    }
+    __syncthreads();
+    // ---- panel factorisation, by wave 0 alone
+    if (wave == 0)
+      panel_regs<NS>(s_pan, prmax, prows, j0, nb, n, KL, KU, lane, tau, cn, ipiv, s_pv, s_ok, s_juc, s_ju, s_info);
+    __syncthreads();
+    // ---- trailing columns j0+nb .. ju: interchanges, then the panel rows
+    // (unit lower triangular solve), in registers, one column per thread
+    const int32_t ju = s_ju, nt = ju - (j0 + nb) + 1;
+    for (int32_t tcol = tid; tcol < nt; tcol += blockDim.x) {
+      const int32_t jc = j0 + nb + tcol;
+      const double drop_u = tau * cn[jc];
+      double v[kPanel];
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) v[c] = (c < nb && jc <= s_juc[c]) ? at(j0 + c, jc) : 0.0;
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) {
+        if (c >= nb || !s_ok[c] || jc > s_juc[c]) continue;
+        const int32_t p = s_pv[c];
+        if (p == 0) continue;
+        if (c + p < nb) {
+          // both rows inside the panel
+#pragma unroll
+          for (int c2 = 0; c2 < kPanel; ++c2)
+            if (c2 == c + p) {
+              const double x = v[c2];
+              v[c2] = v[c];
+              v[c] = x;
+            }
+        } else {
+          double& g = at(j0 + c + p, jc);
+          const double x = g;
+          g = v[c];
+          v[c] = x;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) {
+        double u = 0.0;
+        if (c < nb && s_ok[c] && jc <= s_juc[c]) {
+          u = v[c];
+          if (fabs(u) < drop_u) u = 0.0;
+          v[c] = u;
+#pragma unroll
+          for (int i = 1; i < kPanel; ++i)
+            if (c + i < nb) v[c + i] -= s_pan[c * prmax + c + i] * u;
+        }
+        if (c < nb) s_u12[c * ntmax + tcol] = u;
+      }
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c)
+        if (c < nb && jc <= s_juc[c]) at(j0 + c, jc) = v[c];
+    }
+    __syncthreads();
+    // ---- rank-nb update of rows j0+nb .. rmax of the trailing columns: lane
+    // l keeps the multipliers of rows rc0 + l + 64k (k < 3) in registers, wave
+    // w takes columns w, w+16, ... four at a time; U12 of a column is a
+    // broadcast LDS read (its skipped steps hold zero).
+    const int32_t rmax = min(j0 + nb - 1 + KL, n - 1), nrows = rmax - (j0 + nb) + 1;
+    const int nwaves = (int)(blockDim.x >> 6);
+    for (int32_t rc0 = 0; rc0 < nrows && nt > 0; rc0 += 3 * 64) {
+      double L[3][kPanel];
+      int32_t rr[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        rr[k] = rc0 + lane + 64 * k;
+#pragma unroll
+        for (int c = 0; c < kPanel; ++c)
+          L[k][c] = (rr[k] < nrows && c < nb) ? s_pan[c * prmax + nb + rr[k]] : 0.0;
+      }
+      for (int32_t t0 = wave; t0 < nt; t0 += 4 * nwaves) {
+        double a[4][3];
+#pragma unroll
+        for (int bq = 0; bq < 4; ++bq) {
+          const int32_t tcol = t0 + bq * nwaves;
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            a[bq][k] = (tcol < nt && rr[k] < nrows) ? at(j0 + nb + rr[k], j0 + nb + tcol) : 0.0;
+        }
+#pragma unroll
+        for (int bq = 0; bq < 4; ++bq) {
+          const int32_t tcol = t0 + bq * nwaves;
+          if (tcol >= nt) continue;
+          double u[kPanel];
+#pragma unroll
+          for (int c = 0; c < kPanel; ++c) u[c] = c < nb ? s_u12[c * ntmax + tcol] : 0.0;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            if (rr[k] >= nrows) continue;
+            double x = a[bq][k];
+#pragma unroll
+            for (int c = 0; c < kPanel; ++c)
+              if (c < nb) x -= L[k][c] * u[c];
+            at(j0 + nb + rr[k], j0 + nb + tcol) = x;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- multipliers back to band storage order, then the panel to memory
+    if (tid < nb) {
+      double* pc = s_pan + tid * prmax;
+      for (int c2 = nb - 1; c2 > tid; --c2) {
+        const int32_t p2 = s_ok[c2] ? s_pv[c2] : 0;
+        if (p2 != 0) {
+          const double x = pc[c2];
+          pc[c2] = pc[c2 + p2];
+          pc[c2 + p2] = x;
+        }
+      }
+    }
+    __syncthreads();
+    for (int32_t e = tid; e < nb * prows; e += blockDim.x) {
+      const int32_t c = e / prows, rr = e % prows, d = rr - c;
+      if (d <= KL && d >= -KV) at(j0 + rr, j0 + c) = s_pan[c * prmax + rr];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) info[sub] = s_info;
+}
+
 // Column 2-norms of every padded interior block before elimination: column
 // c holds its original entries in band rows KL .. ldab-1.
 __global__ void k_band_colnorm(const double* __restrict__ ab_all, const SubInfo* __restrict__ subs,
@@ -754,9 +1046,30 @@ void launch_band_colnorm(const double* ab, const SubInfo* subs, int32_t m, int32
 void launch_band_nnz(const double* ab, const SubInfo* subs, int32_t m, int64_t* counts, hipStream_t s) {
   if (m > 0) k_band_nnz<<<m, kSetupThreads, 0, s>>>(ab, subs, counts);
 }
+template <int NS>
+void run_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, const double* colnorm,
+                 double tau, int32_t prmax, int32_t ntmax, hipStream_t s) {
+  const size_t smem = sizeof(double) * (size_t)kPanel * (prmax + ntmax);
+  static size_t raised = 64 * 1024;
+  if (smem > raised) {
+    ADDNS_HIP(hipFuncSetAttribute((const void*)k_band_lu_blocked<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)smem));
+    raised = smem;
+  }
+  k_band_lu_blocked<NS><<<m, kSetupThreads, smem, s>>>(ab, ipiv, subs, info, colnorm, tau, prmax, ntmax);
+}
 void launch_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, const double* colnorm,
-                    double tau, hipStream_t s) {
-  if (m > 0) k_band_lu<<<m, kSetupThreads, 0, s>>>(ab, ipiv, subs, info, colnorm, tau);
+                    double tau, int32_t kl_max, int32_t kv_max, hipStream_t s) {
+  if (m == 0) return;
+  const int32_t prmax = kl_max + kPanel, ntmax = std::max(kv_max, 1);
+  // panel rows per lane in registers (64 * NS >= prmax); wider bands take the
+  // unblocked elimination
+  switch ((prmax + 63) / 64) {
+    case 1: run_band_lu<1>(ab, ipiv, subs, m, info, colnorm, tau, prmax, ntmax, s); break;
+    case 2: run_band_lu<2>(ab, ipiv, subs, m, info, colnorm, tau, prmax, ntmax, s); break;
+    case 3: run_band_lu<3>(ab, ipiv, subs, m, info, colnorm, tau, prmax, ntmax, s); break;
+    default: k_band_lu<<<m, kSetupThreads, 0, s>>>(ab, ipiv, subs, info, colnorm, tau); break;
+  }
 }
 void launch_convert_lower(const double* ab, const int32_t* ipiv, const SubInfo* subs, const LBlk* lb, int32_t nblk,
                           double* work, int32_t* lperm, void* lmat, int prec, hipStream_t s) {

@@ -211,7 +211,7 @@ void launch_scatter_band(const int64_t* dst, const int32_t* src, const double* c
                          hipStream_t s);
 void launch_band_pad_identity(const SubInfo* subs, int32_t m, double* ab, hipStream_t s);
 void launch_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, const double* colnorm,
-                    double tau, hipStream_t s);
+                    double tau, int32_t kl_max, int32_t kv_max, hipStream_t s);
 void launch_band_colnorm(const double* ab, const SubInfo* subs, int32_t m, int32_t npad_max, double* colnorm,
                          hipStream_t s);
 void launch_band_nnz(const double* ab, const SubInfo* subs, int32_t m, int64_t* counts, hipStream_t s);
