@@ -160,6 +160,21 @@ typedef struct {
                              scaled block before elimination); pivots are kept.
                              The sweep applies the incomplete factors exactly.
                              Outside [0, 1): ADDNS_ERR_ARG */
+  int32_t sweep_chunks;   /* chunks p per subdomain of the interior sweep: the
+                             lower and upper block recurrences of every interior
+                             are cut at p - 1 upper-block boundaries, the chunks
+                             are swept side by side from a zero incoming carry
+                             (lower) or state (upper), and each chunk's result is
+                             then corrected by its precomputed response to the
+                             true carry or state, which a short recurrence over
+                             the chunks supplies.  The same L and U factors and
+                             the same solution, to rounding; more workgroups per
+                             interior at the price of p - 1 small GEMVs on the
+                             chunk boundaries and the response matrices' bytes.
+                             0 = choose p from the measured single-chunk sweep
+                             and keep it only if it times faster; 1 = never;
+                             p >= 2 = that many (ADDNS_ERR_ARG if an interior has
+                             fewer than p upper blocks) */
 } addns_precond_opts;
 
 /* ------------------------------------------------------------------------
@@ -288,10 +303,12 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
    samples (separator velocity rows); interior_nnz is the number of stored
    entries of the interior factors (multipliers below the unit diagonal and
    U, real rows and columns), the numerator of the fill factor of section 5
-   with or without ILU dropping. */
+   with or without ILU dropping; sweep_chunks is the chunk count p of the
+   interior sweep in use (1 = one workgroup per interior). */
 int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb_lower,
                        int32_t* nb_upper, int64_t* factor_bytes, int64_t* bytes_apply,
-                       int64_t* learned_count, int32_t* block_mult, int64_t* interior_nnz);
+                       int64_t* learned_count, int32_t* block_mult, int64_t* interior_nnz,
+                       int32_t* sweep_chunks);
 
 /* Copy the dense interface blocks S_i (before inversion) into a HOST array
    in aggregate order, row-major per block; `count` must equal the sum of

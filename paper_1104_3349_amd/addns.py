@@ -44,7 +44,7 @@ class PrecondOpts(C.Structure):
     _fields_ = [("schur", C.c_int32), ("interior_prec", C.c_int32), ("schur_prec", C.c_int32),
                 ("row_scale", C.c_int32), ("learned_model", C.POINTER(C.c_float)),
                 ("block_mult", C.c_int32), ("learned_bf16", C.c_int32), ("overlap", C.c_int32),
-                ("ilu_tol", C.c_double)]
+                ("ilu_tol", C.c_double), ("sweep_chunks", C.c_int32)]
 
 
 class GmresOpts(C.Structure):
@@ -90,7 +90,7 @@ def lib():
         "addns_precond_refactor": (C.c_int, [P, P, P, P, P]),
         "addns_interior_solve": (C.c_int, [P, P, P, P]),
         "addns_gmres_solve": (C.c_int, [P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresResult), P]),
-        "addns_precond_info": (C.c_int, [P, i32p, i32p, i32p, i32p, i64p, i64p, i64p, i32p, i64p]),
+        "addns_precond_info": (C.c_int, [P, i32p, i32p, i32p, i32p, i64p, i64p, i64p, i32p, i64p, i32p]),
         "addns_precond_schur_blocks": (C.c_int, [P, P, C.c_int64]),
         "addns_partition_destroy": (None, [P]),
         "addns_precond_destroy": (None, [P]),
@@ -226,12 +226,14 @@ class Precond:
         i64 = [C.c_int64() for _ in range(3)]
         bm = C.c_int32()
         nz = C.c_int64()
+        ch = C.c_int32()
         _check(lib().addns_precond_info(self.handle, *[C.byref(x) for x in i32 + i64], C.byref(bm),
-                                        C.byref(nz)), "precond_info")
+                                        C.byref(nz), C.byref(ch)), "precond_info")
         d = dict(zip(("kl", "ku", "nb_lower", "nb_upper", "factor_bytes", "bytes_apply",
                       "learned_count"), (x.value for x in i32 + i64)))
         d["block_mult"] = bm.value
         d["interior_nnz"] = nz.value
+        d["sweep_chunks"] = ch.value
         return d
 
     def schur_blocks(self, count):
@@ -243,9 +245,11 @@ class Precond:
 
 def setup_precond(partition: Partition, N, d_rowptr, d_colidx, d_vals, schur=SCHUR_MSCN,
                   interior_prec=F64, schur_prec=F64, row_scale=1, learned_model=None,
-                  block_mult=1, learned_bf16=True, overlap=0, ilu_tol=0.0, stream=None) -> Precond:
+                  block_mult=1, learned_bf16=True, overlap=0, ilu_tol=0.0, sweep_chunks=0,
+                  stream=None) -> Precond:
     opts = PrecondOpts(int(schur), int(interior_prec), int(schur_prec), int(row_scale), None,
-                       int(block_mult), int(bool(learned_bf16)), int(overlap), float(ilu_tol))
+                       int(block_mult), int(bool(learned_bf16)), int(overlap), float(ilu_tol),
+                       int(sweep_chunks))
     if learned_model is not None:
         lm = np.ascontiguousarray(learned_model, dtype=np.float32)
         opts.learned_model = lm.ctypes.data_as(C.POINTER(C.c_float))

@@ -309,6 +309,60 @@ float time_interior_solve(addns_precond* pc, hipStream_t s) {
   return ms / reps;
 }
 
+// Chunk count of the interior sweep.  requested 1: none; >= 2: that many;
+// 0: the p that minimises a model of the chunked solve built on the measured
+// single-chunk sweep T1 over nU upper blocks: the longest chunk's
+// ceil(nU / p) blocks at T1 / nU each, plus about 5 us per chunk boundary
+// for the two recurrences; at most one workgroup per CU.  It is kept only if
+// the chunked solve times faster (with the better zero-slot form).
+void choose_sweep_chunks(addns_precond* pc, int requested, hipStream_t s) {
+  const Plan& pl = pc->plan;
+  release_chunked_sweep(pc);
+  if (requested == 1 || pl.m == 0 || pl.n_int == 0) return;
+  const int pmax = max_sweep_chunks(pl);
+  if (requested >= 2) {
+    if (requested > pmax) throw ArgError("sweep_chunks exceeds the upper blocks of an interior");
+    build_chunked_sweep(pc, requested, s);
+    return;
+  }
+  hipDeviceProp_t prop;
+  ADDNS_HIP(hipGetDeviceProperties(&prop, pc->device));
+  int32_t nu = 1;
+  for (const SubInfo& q : pl.subs) nu = std::max(nu, q.npad / q.nbu);
+  const double per_block = 1000.0 * pc->tuned_ms / nu, per_boundary = 5.0;
+  const int pcap = std::min(pmax, std::max(1, prop.multiProcessorCount / pl.m));
+  int p = 1;
+  double best = 1000.0 * pc->tuned_ms;
+  for (int c = 2; c <= pcap; ++c) {
+    const double model = (double)((nu + c - 1) / c) * per_block + per_boundary * (c - 1);
+    if (model < best) {
+      best = model;
+      p = c;
+    }
+  }
+  if (p < 2) return;
+  const int z0 = pc->zero_skip;
+  const float t1 = pc->tuned_ms;
+  try {
+    build_chunked_sweep(pc, p, s);
+  } catch (const ArgError&) {
+    release_chunked_sweep(pc);
+    return;
+  }
+  float ms[2];
+  for (int z = 0; z < 2; ++z) {
+    pc->zero_skip = z;
+    ms[z] = time_interior_solve(pc, s);
+  }
+  if (std::min(ms[0], ms[1]) < t1) {
+    pc->zero_skip = ms[1] < ms[0] ? 1 : 0;
+    pc->tuned_ms = std::min(ms[0], ms[1]);
+  } else {
+    release_chunked_sweep(pc);
+    pc->zero_skip = z0;
+  }
+}
+
 struct GmresWork {
   double *V, *Z, *w, *xp, *bp, *rp, *H, *g, *cs, *sn, *y, *pa, *pb, *scal;
   double *ca, *cb, *hc;  // CGS2 partial tables ((restart+1) x 1024 each) and coefficients
@@ -370,7 +424,7 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
   return guarded("addns_setup_precond", [&]() -> int {
     if (!p || !out || !d_rowptr || !d_colidx || !d_vals) throw ArgError("null argument");
     if (N != p->d.N) throw ArgError("N does not match the partition");
-    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1, 0, 0, 0.0};
+    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1, 0, 0, 0.0, 0};
     if (opts) o = *opts;
     if (o.schur < 0 || o.schur > ADDNS_SCHUR_MSCNR) throw ArgError("unknown schur mode");
     if (o.overlap < 0) throw ArgError("overlap must be >= 0");
@@ -378,6 +432,7 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
       throw ArgError("overlapped aggregates are defined for MSCN, MSCNR and LUM");
     if (o.block_mult < 0 || o.block_mult > 4) throw ArgError("block_mult must be 0..4");
     if (!(o.ilu_tol >= 0.0 && o.ilu_tol < 1.0)) throw ArgError("ilu_tol must lie in [0, 1)");
+    if (o.sweep_chunks < 0) throw ArgError("sweep_chunks must be >= 0");
     const bool autotune = o.block_mult == 0;
     if (o.schur == ADDNS_SCHUR_LEARNED && !o.learned_model) throw ArgError("LEARNED mode needs learned_model");
     if (o.interior_prec != ADDNS_F64 && o.interior_prec != ADDNS_F32) throw ArgError("interior_prec");
@@ -406,6 +461,8 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
       }
       pc->zero_skip = ms[1] < ms[0] ? 1 : 0;
       pc->tuned_ms = std::min(ms[0], ms[1]);
+      choose_sweep_chunks(pc.get(), o.sweep_chunks, as_stream(stream));
+      pc->opts.sweep_chunks = pc->sweep_chunks;
       return pc;
     };
     if (!autotune) {
@@ -437,6 +494,8 @@ int addns_precond_refactor(addns_precond_t pc, const int32_t* d_rowptr, const in
     if (o.schur == ADDNS_SCHUR_LEARNED) o.learned_model = pc->learned_w.data();
     pc->valid = 0;
     setup_device(pc, nullptr, d_rowptr, d_colidx, d_vals, o, as_stream(stream));
+    // the chunk responses belong to the factors
+    if (pc->sweep_chunks > 1) build_chunked_sweep(pc, pc->sweep_chunks, as_stream(stream));
     pc->valid = 1;
     return ADDNS_OK;
   });
@@ -739,7 +798,7 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
 
 int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb_lower, int32_t* nb_upper,
                        int64_t* factor_bytes, int64_t* bytes_apply, int64_t* learned_count, int32_t* block_mult,
-                       int64_t* interior_nnz) {
+                       int64_t* interior_nnz, int32_t* sweep_chunks) {
   if (!pc) {
     set_error("addns_precond_info: null handle");
     return ADDNS_ERR_ARG;
@@ -753,6 +812,7 @@ int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb
   if (learned_count) *learned_count = pc->learned_count;
   if (block_mult) *block_mult = pc->plan.block_mult;
   if (interior_nnz) *interior_nnz = pc->interior_nnz;
+  if (sweep_chunks) *sweep_chunks = pc->sweep_chunks;
   return ADDNS_OK;
 }
 

@@ -15,6 +15,9 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <type_traits>
+
 #include "precond.h"
 
 namespace addns {
@@ -305,6 +308,258 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
   }
 }
 
+// ---------------------------------------------------------------------------
+// Chunked interior sweep.  The lower recurrence passes a KL-long carry from
+// block to block, the upper one the solution block x_{b+1}; both are linear.
+// Cutting every interior at p - 1 upper-block boundaries (chunk c holds upper
+// blocks [u_c, u_{c+1}), u_c = floor(nU c / p), and lower blocks [2u_c,
+// 2u_{c+1})), each chunk is swept side by side from a zero carry or state and
+// then corrected:
+//   lower  y_c = y0_c + X_c d_c,  d_1 = carry of chunk 0,
+//          d_{c+1} = g_c + T_c d_c  (g_c: zero-carry carry out of chunk c)
+//   upper  x_c = x0_c + Y_c s_c,  s_{p-2} = x0_{p-1}[top block],
+//          s_{c-1} = x0_c[first block] + Yt_c s_c
+// X_c, T_c (response of chunk c's outputs and carry out to a unit carry in)
+// and Y_c, Yt_c (response of its outputs and first block to a unit state
+// above) are swept once per factorisation (mode 3, one workgroup per unit).
+// Three launches per solve: zero-carry lower chunks; carry recurrence, lower
+// correction and zero-state upper chunk; state recurrence, upper correction
+// and output.  The chunk that starts a recurrence is exact and needs no
+// response.
+// ---------------------------------------------------------------------------
+struct ChunkArgs {
+  int32_t p, klmax;
+  const int64_t* off;  // per (subdomain, chunk): element offsets of X_c, T_c, Y_c, Yt_c
+  void* lx;
+  void* lt;
+  void* uy;
+  void* ut;
+  double* cz;          // zero-carry carry out of each chunk (klmax per (subdomain, chunk))
+  double* xs;          // zero-state upper outputs, padded interior numbering
+  double* uin;         // mode 1: the sweep input E x2, padded interior numbering
+  const int32_t* job;  // mode 3: (subdomain, chunk, unit) per workgroup
+};
+
+__device__ inline int32_t chunk_ub(int32_t nU, int32_t p, int32_t c) { return (int32_t)((int64_t)nU * c / p); }
+
+// Lower chunks.  mode 0: input yin; mode 1: input E x2 (each chunk forms the
+// rows it reads); mode 3: responses X_c, T_c to the unit carry `unit`.
+template <class T, int S, bool Z>
+__global__ void __launch_bounds__(kSweepThreads)
+k_chunk_lower(SweepArgs a, ChunkArgs ca, const double* __restrict__ yin, int mode, const double* __restrict__ x2) {
+  extern __shared__ double smem[];
+  const int32_t jb = blockIdx.x;
+  const int32_t j = mode == 3 ? ca.job[3 * jb] : jb / ca.p;
+  const int32_t c = mode == 3 ? ca.job[3 * jb + 1] : jb % ca.p;
+  const int32_t unit = mode == 3 ? ca.job[3 * jb + 2] : -1;
+  const SubInfo q = a.subs[j];
+  const int32_t n = q.n;
+  if (n == 0) return;
+  const int32_t ioff = q.int_off, voff = q.vec_off;
+  const int32_t KL = q.kl, nbL = q.nbl, W = nbL + KL, nU = q.npad / q.nbu;
+  const int32_t b0 = 2 * chunk_ub(nU, ca.p, c), b1 = 2 * chunk_ub(nU, ca.p, c + 1);
+  const int32_t r0 = b0 * nbL, r1 = b1 * nbL, rows = r1 - r0;
+  const int tid = threadIdx.x;
+  double* wA = smem;
+  double* wB = wA + a.maxW;
+  double* part = wB + a.maxW;  // kWaves * maxW
+  const T* lmat = (const T*)a.lmat + q.lmat_off;
+  const int32_t* lperm = a.lperm + q.lperm_off;
+  const int64_t* off = ca.off + 4 * ((int64_t)j * ca.p + c);
+  const Geo gl = make_geo<S>(W, nbL);
+  Chunk<T, S> A, B;
+  if (b0 < b1) prefetch_gemv<T, S, 4, Z>(A, B, gl, lmat + (int64_t)b0 * W * nbL, nbL, lperm + (int64_t)b0 * W);
+  const double* src = mode == 0 ? yin + ioff : ca.uin + voff;
+  if (mode == 1) {
+    // the rows this chunk reads: its own after the carry rows, and the
+    // carry rows of the next chunk (which enter through the last window)
+    const int32_t lo = c == 0 ? 0 : r0 + KL, hi = min(r1 + KL, n);
+    for (int32_t r = lo + tid; r < hi; r += blockDim.x) {
+      double s = 0.0;
+      for (int32_t e = a.e_rowptr[ioff + r]; e < a.e_rowptr[ioff + r + 1]; ++e) s += a.e_vals[e] * x2[a.e_colidx[e]];
+      ca.uin[voff + r] = s;
+    }
+    __syncthreads();
+  }
+  auto input = [&](int32_t row) -> double { return (mode == 3 || row >= n) ? 0.0 : src[row]; };
+  double* wc = wA;
+  double* wn = wB;
+  for (int32_t r = tid; r < W; r += blockDim.x)
+    wc[r] = (c == 0 || r >= KL) ? input(r0 + r) : (r == unit ? 1.0 : 0.0);
+  __syncthreads();
+  double* ypad = a.ypad + voff;
+  T* X = mode == 3 ? (T*)ca.lx + off[0] + (int64_t)unit * rows : nullptr;
+  for (int32_t b = b0; b < b1; ++b) {
+    const int32_t* idx = lperm + (int64_t)b * W;
+    const T* M = lmat + (int64_t)b * W * nbL;
+    const int32_t rin = (b + 1) * nbL + KL + tid;
+    const double nin = (tid < nbL && b + 1 < b1) ? input(rin) : 0.0;
+    const int32_t cidx = (tid >= nbL && tid < W) ? idx[tid] : 0;
+    const int CG = run_gemv<T, S, 4, Z>(A, B, gl, M, nbL, idx, wc, part);
+    if (b + 1 < b1) prefetch_gemv<T, S, 4, Z>(A, B, gl, M + (int64_t)W * nbL, nbL, idx + W);
+    __syncthreads();
+    for (int32_t r = tid; r < W; r += blockDim.x) {
+      const double v = sum_parts(part, W, CG, r);
+      if (r < nbL) {
+        if (mode == 3) X[b * nbL + r - r0] = (T)v;
+        else ypad[b * nbL + r] = v;
+      } else {
+        wn[r - nbL] = wc[r == tid ? cidx : idx[r]] - v;
+      }
+    }
+    if (tid < nbL) wn[KL + tid] = nin;
+    __syncthreads();
+    double* tmp = wc;
+    wc = wn;
+    wn = tmp;
+  }
+  // the carry out of the chunk (the first KL entries of the next window)
+  if (mode == 3) {
+    T* Tc = (T*)ca.lt + off[1] + (int64_t)unit * KL;
+    for (int32_t r = tid; r < KL; r += blockDim.x) Tc[r] = (T)wc[r];
+  } else if (c + 1 < ca.p) {
+    for (int32_t r = tid; r < KL; r += blockDim.x) ca.cz[((int64_t)j * ca.p + c) * ca.klmax + r] = wc[r];
+  }
+}
+
+// Carry recurrence and lower correction of chunk c (modes 0/1), then its
+// upper blocks from a zero state above; mode 3: responses Y_c, Yt_c to the
+// unit state `unit` above the chunk.
+template <class T, int S, bool Z>
+__global__ void __launch_bounds__(kSweepThreads)
+k_chunk_upper(SweepArgs a, ChunkArgs ca, int mode) {
+  extern __shared__ double smem[];
+  const int32_t jb = blockIdx.x;
+  const int32_t j = mode == 3 ? ca.job[3 * jb] : jb / ca.p;
+  const int32_t c = mode == 3 ? ca.job[3 * jb + 1] : jb % ca.p;
+  const int32_t unit = mode == 3 ? ca.job[3 * jb + 2] : -1;
+  const SubInfo q = a.subs[j];
+  if (q.n == 0) return;
+  const int32_t voff = q.vec_off, KL = q.kl, nbU = q.nbu, KV = q.kl + q.ku, nU = q.npad / nbU;
+  const int32_t u0 = chunk_ub(nU, ca.p, c), u1 = chunk_ub(nU, ca.p, c + 1);
+  const int32_t r0 = u0 * nbU, rows = (u1 - u0) * nbU;
+  const int tid = threadIdx.x;
+  double* t = smem;
+  double* xn = t + a.maxU;
+  double* dv = xn + a.maxU;
+  double* part = dv + a.maxW;
+  const int64_t* off = ca.off + 4 * ((int64_t)j * ca.p + c);
+  double* ypad = a.ypad + voff;
+  const T* uinv = (const T*)a.uinv + q.u_off;
+  const T* u12 = (const T*)a.u12 + q.u_off;
+  Chunk<T, S> A, B;
+  if (mode != 3 && c >= 1) {
+    const double* cz = ca.cz + (int64_t)j * ca.p * ca.klmax;
+    for (int32_t r = tid; r < KL; r += blockDim.x) dv[r] = cz[r];
+    __syncthreads();
+    const Geo gt = make_geo<S>(KL, KL);
+    for (int32_t c2 = 1; c2 < c; ++c2) {
+      const T* Tm = (const T*)ca.lt + ca.off[4 * ((int64_t)j * ca.p + c2) + 1];
+      prefetch_gemv<T, S, 0, false>(A, B, gt, Tm, 0, nullptr);
+      const int CG = run_gemv<T, S, 0, false>(A, B, gt, Tm, 0, nullptr, dv, part);
+      __syncthreads();
+      for (int32_t r = tid; r < KL; r += blockDim.x) dv[r] = cz[(int64_t)c2 * ca.klmax + r] + sum_parts(part, KL, CG, r);
+      __syncthreads();
+    }
+    const Geo gx = make_geo<S>(rows, KL);
+    const T* X = (const T*)ca.lx + off[0];
+    prefetch_gemv<T, S, 0, false>(A, B, gx, X, 0, nullptr);
+    const int CG = run_gemv<T, S, 0, false>(A, B, gx, X, 0, nullptr, dv, part);
+    __syncthreads();
+    for (int32_t r = tid; r < rows; r += blockDim.x) ypad[r0 + r] += sum_parts(part, rows, CG, r);
+    __syncthreads();
+  }
+  const Geo gu = make_geo<S>(nbU, nbU);
+  const bool state_in = mode == 3;
+  if (state_in) {
+    for (int32_t r = tid; r < nbU; r += blockDim.x) xn[r] = r == unit ? 1.0 : 0.0;
+    __syncthreads();
+  }
+  if (u0 < u1) {
+    const int64_t uoff = (int64_t)(u1 - 1) * nbU * nbU;
+    if (state_in) prefetch_gemv<T, S, 3, Z>(A, B, gu, u12 + uoff, KV - nbU, nullptr);
+    else prefetch_gemv<T, S, 2, Z>(A, B, gu, uinv + uoff, 0, nullptr);
+  }
+  T* Y = mode == 3 ? (T*)ca.uy + off[2] + (int64_t)unit * rows : nullptr;
+  T* Yt = mode == 3 ? (T*)ca.ut + off[3] + (int64_t)unit * nbU : nullptr;
+  double* xs = ca.xs + voff;
+  for (int32_t b = u1 - 1; b >= u0; --b) {
+    const int64_t uoff = (int64_t)b * nbU * nbU;
+    const double yb = (mode != 3 && tid < nbU) ? ypad[b * nbU + tid] : 0.0;
+    if (b < u1 - 1 || state_in) {
+      const int CG = run_gemv<T, S, 3, Z>(A, B, gu, u12 + uoff, KV - nbU, nullptr, xn, part);
+      prefetch_gemv<T, S, 2, Z>(A, B, gu, uinv + uoff, 0, nullptr);
+      __syncthreads();
+      if (tid < nbU) t[tid] = yb - sum_parts(part, nbU, CG, tid);
+    } else {
+      if (tid < nbU) t[tid] = yb;
+    }
+    __syncthreads();
+    const int CG = run_gemv<T, S, 2, Z>(A, B, gu, uinv + uoff, 0, nullptr, t, part);
+    if (b > u0) prefetch_gemv<T, S, 3, Z>(A, B, gu, u12 + uoff - (int64_t)nbU * nbU, KV - nbU, nullptr);
+    __syncthreads();
+    if (tid < nbU) {
+      const double x = sum_parts(part, nbU, CG, tid);
+      xn[tid] = x;
+      const int32_t row = b * nbU + tid;
+      if (mode == 3) {
+        Y[row - r0] = (T)x;
+        if (b == u0) Yt[tid] = (T)x;
+      } else {
+        xs[row] = x;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// State recurrence from the top chunk down to chunk c, upper correction and
+// the output: mode 0 out = x, mode 1 out = z1 - x (interior rows).
+template <class T, int S>
+__global__ void __launch_bounds__(kSweepThreads)
+k_chunk_fix(SweepArgs a, ChunkArgs ca, int mode, double* out, const double* z1) {
+  extern __shared__ double smem[];
+  const int32_t j = blockIdx.x / ca.p, c = blockIdx.x % ca.p, p = ca.p;
+  const SubInfo q = a.subs[j];
+  const int32_t n = q.n;
+  if (n == 0) return;
+  const int32_t ioff = q.int_off, voff = q.vec_off, nbU = q.nbu, nU = q.npad / nbU;
+  const int32_t u0 = chunk_ub(nU, p, c), u1 = chunk_ub(nU, p, c + 1);
+  const int32_t r0 = u0 * nbU, rows = (u1 - u0) * nbU;
+  const int tid = threadIdx.x;
+  double* s = smem;
+  double* part = s + a.maxU;
+  const double* xs = ca.xs + voff;
+  int CG = 0;
+  if (c + 1 < p) {
+    const int32_t utop = chunk_ub(nU, p, p - 1);
+    for (int32_t r = tid; r < nbU; r += blockDim.x) s[r] = xs[utop * nbU + r];
+    __syncthreads();
+    Chunk<T, S> A, B;
+    const Geo gs = make_geo<S>(nbU, nbU);
+    for (int32_t c2 = p - 2; c2 > c; --c2) {
+      const T* Yt = (const T*)ca.ut + ca.off[4 * ((int64_t)j * p + c2) + 3];
+      prefetch_gemv<T, S, 0, false>(A, B, gs, Yt, 0, nullptr);
+      const int CGs = run_gemv<T, S, 0, false>(A, B, gs, Yt, 0, nullptr, s, part);
+      __syncthreads();
+      const int32_t u = chunk_ub(nU, p, c2);
+      for (int32_t r = tid; r < nbU; r += blockDim.x) s[r] = xs[u * nbU + r] + sum_parts(part, nbU, CGs, r);
+      __syncthreads();
+    }
+    const Geo gy = make_geo<S>(rows, nbU);
+    const T* Y = (const T*)ca.uy + ca.off[4 * ((int64_t)j * p + c) + 2];
+    prefetch_gemv<T, S, 0, false>(A, B, gy, Y, 0, nullptr);
+    CG = run_gemv<T, S, 0, false>(A, B, gy, Y, 0, nullptr, s, part);
+    __syncthreads();
+  }
+  for (int32_t r = tid; r < rows; r += blockDim.x) {
+    const int32_t row = r0 + r;
+    if (row >= n) continue;
+    const double x = xs[row] + (c + 1 < p ? sum_parts(part, rows, CG, r) : 0.0);
+    out[ioff + row] = mode == 1 ? z1[ioff + row] - x : x;
+  }
+}
+
 // One workgroup per aggregate: t = y2 - F z1 on the aggregate's rows, then
 // x2 = S_i^{-1} t with S_i^{-1} column-major.  Thread (r, cs) owns row r of
 // the GEMV and column chunk cs (Rp rows, CS = 1024 / Rp chunks); up to 128
@@ -456,13 +711,174 @@ static void run_sweep(const addns_precond* pc, const SweepArgs& a, int grid, con
   }
 }
 
+// ---- chunked sweep ---------------------------------------------------------
+static size_t chunk_smem_bytes(int32_t maxW, int32_t maxU, int S) {
+  return sizeof(double) *
+         (size_t)(2 * maxW + 2 * maxU + std::max<int64_t>((int64_t)kWaves * std::max(maxW, maxU), 1024 * S));
+}
+
+template <class T>
+struct TypeTag {
+  using type = T;
+};
+
+// f(TypeTag<T>, integral_constant<int, S>, integral_constant<bool, Z>) for the
+// handle's storage type, row slots and zero-slot choice
+template <class F>
+static void with_sweep_shape(const addns_precond* pc, F&& f) {
+  const Plan& pl = pc->plan;
+  const int S = std::min(5, (std::max(pl.maxW, pl.nbU) + 63) / 64);
+  auto by_s = [&](auto tt, auto zz) {
+    switch (S) {
+      case 1: f(tt, std::integral_constant<int, 1>{}, zz); break;
+      case 2: f(tt, std::integral_constant<int, 2>{}, zz); break;
+      case 3: f(tt, std::integral_constant<int, 3>{}, zz); break;
+      case 4: f(tt, std::integral_constant<int, 4>{}, zz); break;
+      case 5: f(tt, std::integral_constant<int, 5>{}, zz); break;
+      default: throw ArgError("sweep row slots out of range");
+    }
+  };
+  auto by_z = [&](auto tt) {
+    if (pc->zero_skip) by_s(tt, std::true_type{});
+    else by_s(tt, std::false_type{});
+  };
+  if (pc->interior_prec == P64) by_z(TypeTag<double>{});
+  else by_z(TypeTag<float>{});
+}
+
+template <class K>
+static void raise_lds(K kernel, size_t smem) {
+  if (smem > 64 * 1024)
+    ADDNS_HIP(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+}
+
+static ChunkArgs chunk_args(const addns_precond* pc) {
+  ChunkArgs ca{};
+  ca.p = pc->sweep_chunks;
+  ca.klmax = pc->ch_klmax;
+  ca.off = pc->ch_off.as<int64_t>();
+  ca.lx = pc->ch_lx.p;
+  ca.lt = pc->ch_lt.p;
+  ca.uy = pc->ch_uy.p;
+  ca.ut = pc->ch_ut.p;
+  ca.cz = pc->ch_cz.as<double>();
+  ca.xs = pc->ch_xs.as<double>();
+  ca.uin = pc->ch_uin.as<double>();
+  return ca;
+}
+
+static void run_chunked(const addns_precond* pc, const SweepArgs& a, const double* yin, double* out, int mode,
+                        const double* x2, const double* z1, hipStream_t s) {
+  const Plan& pl = pc->plan;
+  const ChunkArgs ca = chunk_args(pc);
+  const int grid = pl.m * ca.p;
+  with_sweep_shape(pc, [&](auto tt, auto ss, auto zz) {
+    using T = typename decltype(tt)::type;
+    constexpr int S = decltype(ss)::value;
+    constexpr bool Z = decltype(zz)::value;
+    const size_t smem = chunk_smem_bytes(pl.maxW, pl.nbU, S);
+    k_chunk_lower<T, S, Z><<<grid, kSweepThreads, smem, s>>>(a, ca, yin, mode, x2);
+    k_chunk_upper<T, S, Z><<<grid, kSweepThreads, smem, s>>>(a, ca, mode);
+    k_chunk_fix<T, S><<<grid, kSweepThreads, smem, s>>>(a, ca, mode, out, z1);
+  });
+}
+
+int max_sweep_chunks(const Plan& pl) {
+  int32_t p = 0;
+  for (const SubInfo& q : pl.subs)
+    if (q.n > 0) p = p == 0 ? q.npad / q.nbu : std::min(p, q.npad / q.nbu);
+  return std::max(p, 1);
+}
+
+void release_chunked_sweep(addns_precond* pc) {
+  pc->sweep_chunks = 1;
+  for (DevBuf* d : {&pc->ch_off, &pc->ch_lx, &pc->ch_lt, &pc->ch_uy, &pc->ch_ut, &pc->ch_cz, &pc->ch_xs, &pc->ch_uin})
+    d->reset();
+}
+
+// Offsets and response matrices of the chunked sweep with p chunks, swept on
+// the handle's current factors (mode 3 of the chunk kernels).
+void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
+  const Plan& pl = pc->plan;
+  if (p < 2 || p > max_sweep_chunks(pl)) throw ArgError("sweep_chunks exceeds the upper blocks of an interior");
+  const int S = std::min(5, (std::max(pl.maxW, pl.nbU) + 63) / 64);
+  const int m = pl.m;
+  const int fb = pc->interior_prec == P64 ? 8 : 4;
+  std::vector<int64_t> off((size_t)4 * m * p, 0);
+  std::vector<int32_t> jl, ju;
+  int64_t nlx = 0, nlt = 0, nuy = 0, nut = 0;
+  int32_t klmax = 1;
+  for (int32_t j = 0; j < m; ++j) {
+    const SubInfo& q = pl.subs[j];
+    klmax = std::max(klmax, q.kl);
+    if (q.n == 0) continue;
+    const int32_t nU = q.npad / q.nbu;
+    for (int32_t c = 0; c < p; ++c) {
+      const int32_t rows = (int32_t)(((int64_t)nU * (c + 1) / p - (int64_t)nU * c / p) * q.nbu);
+      if (rows > 1024 * S) throw ArgError("sweep chunk too tall for the chunk kernels' GEMVs");
+      int64_t* o = &off[(size_t)4 * ((int64_t)j * p + c)];
+      if (c >= 1) {
+        o[0] = nlx;
+        nlx += (int64_t)rows * q.kl;
+        o[1] = nlt;
+        nlt += (int64_t)q.kl * q.kl;
+        for (int32_t u = 0; u < q.kl; ++u) jl.insert(jl.end(), {j, c, u});
+      }
+      if (c + 1 < p) {
+        o[2] = nuy;
+        nuy += (int64_t)rows * q.nbu;
+        o[3] = nut;
+        nut += (int64_t)q.nbu * q.nbu;
+        for (int32_t u = 0; u < q.nbu; ++u) ju.insert(ju.end(), {j, c, u});
+      }
+    }
+  }
+  pc->sweep_chunks = p;
+  pc->ch_klmax = klmax;
+  pc->ch_off.upload(off, s);
+  // the chunk GEMVs' last row slot may read up to 64 * 5 rows past a
+  // matrix; the zeroed tail keeps that overrun inside the allocation
+  const int64_t tail = kSweepOverrunBytes;
+  DevBuf* mats[4] = {&pc->ch_lx, &pc->ch_lt, &pc->ch_uy, &pc->ch_ut};
+  const int64_t cnt[4] = {nlx, nlt, nuy, nut};
+  for (int i = 0; i < 4; ++i) {
+    mats[i]->alloc((size_t)(fb * cnt[i] + tail));
+    ADDNS_HIP(hipMemsetAsync(static_cast<char*>(mats[i]->p) + mats[i]->bytes - tail, 0, tail, s));
+  }
+  pc->ch_cz.alloc(sizeof(double) * (size_t)m * p * klmax);
+  pc->ch_xs.alloc(sizeof(double) * (size_t)std::max<int64_t>(pl.npad_total, 1));
+  pc->ch_uin.alloc(sizeof(double) * (size_t)std::max<int64_t>(pl.npad_total, 1));
+  DevBuf d_jl, d_ju;
+  d_jl.upload(jl, s);
+  d_ju.upload(ju, s);
+  SweepArgs a = sweep_args(pc);
+  a.ypad = pc->ypad.as<double>();
+  ChunkArgs ca = chunk_args(pc);
+  with_sweep_shape(pc, [&](auto tt, auto ss, auto zz) {
+    using T = typename decltype(tt)::type;
+    constexpr int S2 = decltype(ss)::value;
+    constexpr bool Z = decltype(zz)::value;
+    const size_t smem = chunk_smem_bytes(pl.maxW, pl.nbU, S2);
+    raise_lds(k_chunk_lower<T, S2, Z>, smem);
+    raise_lds(k_chunk_upper<T, S2, Z>, smem);
+    raise_lds(k_chunk_fix<T, S2>, smem);
+    ca.job = d_jl.as<int32_t>();
+    if (!jl.empty()) k_chunk_lower<T, S2, Z><<<(int)(jl.size() / 3), kSweepThreads, smem, s>>>(a, ca, nullptr, 3, nullptr);
+    ca.job = d_ju.as<int32_t>();
+    if (!ju.empty()) k_chunk_upper<T, S2, Z><<<(int)(ju.size() / 3), kSweepThreads, smem, s>>>(a, ca, 3);
+  });
+  ADDNS_HIP(hipGetLastError());
+  ADDNS_HIP(hipStreamSynchronize(s));
+}
+
 void launch_interior_solve(const addns_precond* pc, const double* yin, double* out, int second, const double* x2,
                            const double* z1, hipStream_t s) {
   const Plan& pl = pc->plan;
   if (pl.m == 0 || pl.n_int == 0) return;
   SweepArgs a = sweep_args(pc);
   a.ypad = second ? pc->zpad.as<double>() : pc->ypad.as<double>();
-  run_sweep(pc, a, pl.m, yin, out, second ? 1 : 0, x2, z1, s);
+  if (pc->sweep_chunks > 1) run_chunked(pc, a, yin, out, second ? 1 : 0, x2, z1, s);
+  else run_sweep(pc, a, pl.m, yin, out, second ? 1 : 0, x2, z1, s);
 }
 
 void launch_column_solves(const addns_precond* pc, int32_t npairs, const int32_t* pair_sub, const int32_t* pair_col,

@@ -184,6 +184,12 @@ struct addns_precond {
   int64_t learned_count = 0;
   float tuned_ms = 0.0f;                              // autotuner timing of the interior solve
   int zero_skip = 0;                                  // sweep skips structural-zero row slots (autotuned)
+  // chunked interior sweep: p chunks per interior swept side by side, joined
+  // through each chunk's response to its incoming carry (lower) or state
+  // (upper); per (subdomain, chunk) the offsets of X_c, T_c, Y_c, Yt_c
+  int sweep_chunks = 1, ch_klmax = 0;
+  addns::DevBuf ch_off, ch_lx, ch_lt, ch_uy, ch_ut;   // offsets (int64) and response matrices
+  addns::DevBuf ch_cz, ch_xs, ch_uin;                 // zero-state carries and upper outputs, E x2
   addns::DevBuf g_copy;                               // G blocks before the update (learning targets S - G)
   addns::DevBuf smp_row, smp_nb, smp_loc;             // learned-correction sample table
   // GMRES work space (grown on demand)
@@ -229,6 +235,9 @@ void launch_invert_dense(int32_t k, const int32_t* agg_s, const int64_t* g_off, 
                          int prec, hipStream_t s);
 void launch_interior_solve(const addns_precond* pc, const double* yin, double* out, int second,
                            const double* x2, const double* z1, hipStream_t s);
+int max_sweep_chunks(const Plan& pl);
+void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s);
+void release_chunked_sweep(addns_precond* pc);
 void launch_column_solves(const addns_precond* pc, int32_t npairs, const int32_t* pair_sub, const int32_t* pair_col,
                           const int64_t* pair_off, double* scratch, double* out, hipStream_t s);
 void launch_exact_schur_update(int32_t nsep, const int32_t* pcol_ptr, const int32_t* pair_sub, const int64_t* pair_off,
