@@ -304,11 +304,13 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
    entries of the interior factors (multipliers below the unit diagonal and
    U, real rows and columns), the numerator of the fill factor of section 5
    with or without ILU dropping; sweep_chunks is the chunk count p of the
-   interior sweep in use (1 = one workgroup per interior). */
+   interior sweep in use (1 = one workgroup per interior) and chunk_bytes the
+   size of its response matrices, read once per interior solve (included
+   twice in bytes_apply). */
 int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb_lower,
                        int32_t* nb_upper, int64_t* factor_bytes, int64_t* bytes_apply,
                        int64_t* learned_count, int32_t* block_mult, int64_t* interior_nnz,
-                       int32_t* sweep_chunks);
+                       int32_t* sweep_chunks, int64_t* chunk_bytes);
 
 /* Copy the dense interface blocks S_i (before inversion) into a HOST array
    in aggregate order, row-major per block; `count` must equal the sum of

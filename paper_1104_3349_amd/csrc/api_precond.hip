@@ -798,7 +798,7 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
 
 int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb_lower, int32_t* nb_upper,
                        int64_t* factor_bytes, int64_t* bytes_apply, int64_t* learned_count, int32_t* block_mult,
-                       int64_t* interior_nnz, int32_t* sweep_chunks) {
+                       int64_t* interior_nnz, int32_t* sweep_chunks, int64_t* chunk_bytes) {
   if (!pc) {
     set_error("addns_precond_info: null handle");
     return ADDNS_ERR_ARG;
@@ -808,11 +808,12 @@ int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb
   if (nb_lower) *nb_lower = pc->plan.nbL;
   if (nb_upper) *nb_upper = pc->plan.nbU;
   if (factor_bytes) *factor_bytes = pc->factor_bytes;
-  if (bytes_apply) *bytes_apply = pc->bytes_apply;
+  if (bytes_apply) *bytes_apply = pc->bytes_apply + 2 * pc->chunk_bytes;
   if (learned_count) *learned_count = pc->learned_count;
   if (block_mult) *block_mult = pc->plan.block_mult;
   if (interior_nnz) *interior_nnz = pc->interior_nnz;
   if (sweep_chunks) *sweep_chunks = pc->sweep_chunks;
+  if (chunk_bytes) *chunk_bytes = pc->chunk_bytes;
   return ADDNS_OK;
 }
 

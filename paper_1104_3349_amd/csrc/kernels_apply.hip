@@ -315,49 +315,56 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
 // blocks [u_c, u_{c+1}), u_c = floor(nU c / p), and lower blocks [2u_c,
 // 2u_{c+1})), each chunk is swept side by side from a zero carry or state and
 // then corrected:
-//   lower  y_c = y0_c + X_c d_c,  d_1 = carry of chunk 0,
-//          d_{c+1} = g_c + T_c d_c  (g_c: zero-carry carry out of chunk c)
-//   upper  x_c = x0_c + Y_c s_c,  s_{p-2} = x0_{p-1}[top block],
-//          s_{c-1} = x0_c[first block] + Yt_c s_c
-// X_c, T_c (response of chunk c's outputs and carry out to a unit carry in)
-// and Y_c, Yt_c (response of its outputs and first block to a unit state
-// above) are swept once per factorisation (mode 3, one workgroup per unit).
-// Three launches per solve: zero-carry lower chunks; carry recurrence, lower
-// correction and zero-state upper chunk; state recurrence, upper correction
-// and output.  The chunk that starts a recurrence is exact and needs no
-// response.
+//   lower  y_c = y0_c + X_c d_c,   d_1 = g_0,
+//          d_c = g_{c-1} + sum_i (T_{c-1} ... T_{c-1-i}) g_{c-2-i}
+//   upper  x_c = x0_c + Y_c s_c,   s_{p-2} = f_{p-1},
+//          s_c = f_{c+1} + sum_i (Yt_{c+1} ... Yt_{c+1+i}) f_{c+2+i}
+// with g_c the zero-carry carry out of chunk c, f_c the first block of x0_c,
+// X_c / T_c the response of chunk c's outputs / carry out to a unit carry in,
+// Y_c / Yt_c that of its outputs / first block to a unit state above.  The
+// products over chunk ranges are themselves responses (a sweep over the range
+// from a unit carry or state) and are stored side by side, so each chunk
+// finds its carry and state with one GEMV instead of a chain of dependent
+// ones.  They are swept once per factorisation (mode 3, one workgroup per
+// chunk range and unit).  Three launches per solve: zero-carry lower chunks;
+// carry, lower correction and zero-state upper chunk; state, upper correction
+// and output.
+//   LP_c = [T_{c-1}, T_{c-1}T_{c-2}, ..., T_{c-1}...T_1]   KL x (c-1) KL
+//   UP_c = [Yt_{c+1}, Yt_{c+1}Yt_{c+2}, ..., Yt_{c+1}...Yt_{p-2}]   nbU x (p-2-c) nbU
 // ---------------------------------------------------------------------------
 struct ChunkArgs {
-  int32_t p, klmax;
-  const int64_t* off;  // per (subdomain, chunk): element offsets of X_c, T_c, Y_c, Yt_c
+  int32_t p, klmax, stk;  // chunks, carry stride, LDS words of the stacked recurrence vector
+  const int64_t* off;     // per (subdomain, chunk): element offsets of X_c, LP_c, Y_c, UP_c
   void* lx;
-  void* lt;
+  void* lp;
   void* uy;
-  void* ut;
+  void* up;
   double* cz;          // zero-carry carry out of each chunk (klmax per (subdomain, chunk))
   double* xs;          // zero-state upper outputs, padded interior numbering
   double* uin;         // mode 1: the sweep input E x2, padded interior numbering
-  const int32_t* job;  // mode 3: (subdomain, chunk, unit) per workgroup
+  const int32_t* job;  // mode 3: (subdomain, first chunk, end chunk, unit) per workgroup
 };
 
 __device__ inline int32_t chunk_ub(int32_t nU, int32_t p, int32_t c) { return (int32_t)((int64_t)nU * c / p); }
 
 // Lower chunks.  mode 0: input yin; mode 1: input E x2 (each chunk forms the
-// rows it reads); mode 3: responses X_c, T_c to the unit carry `unit`.
+// rows it reads); mode 3: the response of chunks [c, ce) to the unit carry
+// `unit` into chunk c: X_c (single chunk) and the carry out into LP_ce.
 template <class T, int S, bool Z>
 __global__ void __launch_bounds__(kSweepThreads)
 k_chunk_lower(SweepArgs a, ChunkArgs ca, const double* __restrict__ yin, int mode, const double* __restrict__ x2) {
   extern __shared__ double smem[];
   const int32_t jb = blockIdx.x;
-  const int32_t j = mode == 3 ? ca.job[3 * jb] : jb / ca.p;
-  const int32_t c = mode == 3 ? ca.job[3 * jb + 1] : jb % ca.p;
-  const int32_t unit = mode == 3 ? ca.job[3 * jb + 2] : -1;
+  const int32_t j = mode == 3 ? ca.job[4 * jb] : jb / ca.p;
+  const int32_t c = mode == 3 ? ca.job[4 * jb + 1] : jb % ca.p;
+  const int32_t ce = mode == 3 ? ca.job[4 * jb + 2] : c + 1;
+  const int32_t unit = mode == 3 ? ca.job[4 * jb + 3] : -1;
   const SubInfo q = a.subs[j];
   const int32_t n = q.n;
   if (n == 0) return;
   const int32_t ioff = q.int_off, voff = q.vec_off;
   const int32_t KL = q.kl, nbL = q.nbl, W = nbL + KL, nU = q.npad / q.nbu;
-  const int32_t b0 = 2 * chunk_ub(nU, ca.p, c), b1 = 2 * chunk_ub(nU, ca.p, c + 1);
+  const int32_t b0 = 2 * chunk_ub(nU, ca.p, c), b1 = 2 * chunk_ub(nU, ca.p, ce);
   const int32_t r0 = b0 * nbL, r1 = b1 * nbL, rows = r1 - r0;
   const int tid = threadIdx.x;
   double* wA = smem;
@@ -365,7 +372,6 @@ k_chunk_lower(SweepArgs a, ChunkArgs ca, const double* __restrict__ yin, int mod
   double* part = wB + a.maxW;  // kWaves * maxW
   const T* lmat = (const T*)a.lmat + q.lmat_off;
   const int32_t* lperm = a.lperm + q.lperm_off;
-  const int64_t* off = ca.off + 4 * ((int64_t)j * ca.p + c);
   const Geo gl = make_geo<S>(W, nbL);
   Chunk<T, S> A, B;
   if (b0 < b1) prefetch_gemv<T, S, 4, Z>(A, B, gl, lmat + (int64_t)b0 * W * nbL, nbL, lperm + (int64_t)b0 * W);
@@ -388,7 +394,7 @@ k_chunk_lower(SweepArgs a, ChunkArgs ca, const double* __restrict__ yin, int mod
     wc[r] = (c == 0 || r >= KL) ? input(r0 + r) : (r == unit ? 1.0 : 0.0);
   __syncthreads();
   double* ypad = a.ypad + voff;
-  T* X = mode == 3 ? (T*)ca.lx + off[0] + (int64_t)unit * rows : nullptr;
+  T* X = (mode == 3 && ce == c + 1) ? (T*)ca.lx + ca.off[4 * ((int64_t)j * ca.p + c)] + (int64_t)unit * rows : nullptr;
   for (int32_t b = b0; b < b1; ++b) {
     const int32_t* idx = lperm + (int64_t)b * W;
     const T* M = lmat + (int64_t)b * W * nbL;
@@ -401,8 +407,8 @@ k_chunk_lower(SweepArgs a, ChunkArgs ca, const double* __restrict__ yin, int mod
     for (int32_t r = tid; r < W; r += blockDim.x) {
       const double v = sum_parts(part, W, CG, r);
       if (r < nbL) {
-        if (mode == 3) X[b * nbL + r - r0] = (T)v;
-        else ypad[b * nbL + r] = v;
+        if (mode != 3) ypad[b * nbL + r] = v;
+        else if (X) X[b * nbL + r - r0] = (T)v;
       } else {
         wn[r - nbL] = wc[r == tid ? cidx : idx[r]] - v;
       }
@@ -415,73 +421,89 @@ k_chunk_lower(SweepArgs a, ChunkArgs ca, const double* __restrict__ yin, int mod
   }
   // the carry out of the chunk (the first KL entries of the next window)
   if (mode == 3) {
-    T* Tc = (T*)ca.lt + off[1] + (int64_t)unit * KL;
-    for (int32_t r = tid; r < KL; r += blockDim.x) Tc[r] = (T)wc[r];
+    if (ce < ca.p) {
+      // block ce - 1 - c of LP_ce, column `unit`
+      T* L = (T*)ca.lp + ca.off[4 * ((int64_t)j * ca.p + ce) + 1] + ((int64_t)(ce - 1 - c) * KL + unit) * KL;
+      for (int32_t r = tid; r < KL; r += blockDim.x) L[r] = (T)wc[r];
+    }
   } else if (c + 1 < ca.p) {
     for (int32_t r = tid; r < KL; r += blockDim.x) ca.cz[((int64_t)j * ca.p + c) * ca.klmax + r] = wc[r];
   }
 }
 
-// Carry recurrence and lower correction of chunk c (modes 0/1), then its
-// upper blocks from a zero state above; mode 3: responses Y_c, Yt_c to the
-// unit state `unit` above the chunk.
+// Carry and lower correction of chunk c (modes 0/1), then its upper blocks
+// from a zero state above; mode 3: the response of chunks [c, ce) (swept
+// downwards) to the unit state `unit` above chunk ce - 1: Y_c (single chunk)
+// and the first block of chunk c into UP_{c-1}.
 template <class T, int S, bool Z>
 __global__ void __launch_bounds__(kSweepThreads)
 k_chunk_upper(SweepArgs a, ChunkArgs ca, int mode) {
   extern __shared__ double smem[];
   const int32_t jb = blockIdx.x;
-  const int32_t j = mode == 3 ? ca.job[3 * jb] : jb / ca.p;
-  const int32_t c = mode == 3 ? ca.job[3 * jb + 1] : jb % ca.p;
-  const int32_t unit = mode == 3 ? ca.job[3 * jb + 2] : -1;
+  const int32_t j = mode == 3 ? ca.job[4 * jb] : jb / ca.p;
+  const int32_t c = mode == 3 ? ca.job[4 * jb + 1] : jb % ca.p;
+  const int32_t ce = mode == 3 ? ca.job[4 * jb + 2] : c + 1;
+  const int32_t unit = mode == 3 ? ca.job[4 * jb + 3] : -1;
   const SubInfo q = a.subs[j];
   if (q.n == 0) return;
   const int32_t voff = q.vec_off, KL = q.kl, nbU = q.nbu, KV = q.kl + q.ku, nU = q.npad / nbU;
-  const int32_t u0 = chunk_ub(nU, ca.p, c), u1 = chunk_ub(nU, ca.p, c + 1);
+  const int32_t u0 = chunk_ub(nU, ca.p, c), u1 = chunk_ub(nU, ca.p, ce);
   const int32_t r0 = u0 * nbU, rows = (u1 - u0) * nbU;
   const int tid = threadIdx.x;
   double* t = smem;
   double* xn = t + a.maxU;
   double* dv = xn + a.maxU;
-  double* part = dv + a.maxW;
+  double* stk = dv + a.maxW;
+  double* part = stk + ca.stk;
   const int64_t* off = ca.off + 4 * ((int64_t)j * ca.p + c);
   double* ypad = a.ypad + voff;
   const T* uinv = (const T*)a.uinv + q.u_off;
   const T* u12 = (const T*)a.u12 + q.u_off;
+  const Geo gu = make_geo<S>(nbU, nbU);
+  const bool state_in = mode == 3;
   Chunk<T, S> A, B;
   if (mode != 3 && c >= 1) {
     const double* cz = ca.cz + (int64_t)j * ca.p * ca.klmax;
-    for (int32_t r = tid; r < KL; r += blockDim.x) dv[r] = cz[r];
-    __syncthreads();
-    const Geo gt = make_geo<S>(KL, KL);
-    for (int32_t c2 = 1; c2 < c; ++c2) {
-      const T* Tm = (const T*)ca.lt + ca.off[4 * ((int64_t)j * ca.p + c2) + 1];
-      prefetch_gemv<T, S, 0, false>(A, B, gt, Tm, 0, nullptr);
-      const int CG = run_gemv<T, S, 0, false>(A, B, gt, Tm, 0, nullptr, dv, part);
-      __syncthreads();
-      for (int32_t r = tid; r < KL; r += blockDim.x) dv[r] = cz[(int64_t)c2 * ca.klmax + r] + sum_parts(part, KL, CG, r);
-      __syncthreads();
-    }
     const Geo gx = make_geo<S>(rows, KL);
     const T* X = (const T*)ca.lx + off[0];
-    prefetch_gemv<T, S, 0, false>(A, B, gx, X, 0, nullptr);
+    if (c >= 2) {
+      // d_c = g_{c-1} + LP_c [g_{c-2}; ...; g_0]
+      const int32_t K = (c - 1) * KL;
+      const Geo gp = make_geo<S>(KL, K);
+      const T* LP = (const T*)ca.lp + off[1];
+      prefetch_gemv<T, S, 0, false>(A, B, gp, LP, 0, nullptr);
+      for (int32_t e = tid; e < K; e += blockDim.x) {
+        const int32_t i = e / KL, r = e - i * KL;
+        stk[e] = cz[(int64_t)(c - 2 - i) * ca.klmax + r];
+      }
+      __syncthreads();
+      const int CG = run_gemv<T, S, 0, false>(A, B, gp, LP, 0, nullptr, stk, part);
+      prefetch_gemv<T, S, 0, false>(A, B, gx, X, 0, nullptr);
+      __syncthreads();
+      for (int32_t r = tid; r < KL; r += blockDim.x) dv[r] = cz[(int64_t)(c - 1) * ca.klmax + r] + sum_parts(part, KL, CG, r);
+    } else {
+      prefetch_gemv<T, S, 0, false>(A, B, gx, X, 0, nullptr);
+      for (int32_t r = tid; r < KL; r += blockDim.x) dv[r] = cz[r];
+    }
+    __syncthreads();
+    // y_c += X_c d_c
     const int CG = run_gemv<T, S, 0, false>(A, B, gx, X, 0, nullptr, dv, part);
+    if (u0 < u1) prefetch_gemv<T, S, 2, Z>(A, B, gu, uinv + (int64_t)(u1 - 1) * nbU * nbU, 0, nullptr);
     __syncthreads();
     for (int32_t r = tid; r < rows; r += blockDim.x) ypad[r0 + r] += sum_parts(part, rows, CG, r);
     __syncthreads();
-  }
-  const Geo gu = make_geo<S>(nbU, nbU);
-  const bool state_in = mode == 3;
-  if (state_in) {
+  } else if (state_in) {
     for (int32_t r = tid; r < nbU; r += blockDim.x) xn[r] = r == unit ? 1.0 : 0.0;
+    if (u0 < u1) prefetch_gemv<T, S, 3, Z>(A, B, gu, u12 + (int64_t)(u1 - 1) * nbU * nbU, KV - nbU, nullptr);
     __syncthreads();
+  } else if (u0 < u1) {
+    prefetch_gemv<T, S, 2, Z>(A, B, gu, uinv + (int64_t)(u1 - 1) * nbU * nbU, 0, nullptr);
   }
-  if (u0 < u1) {
-    const int64_t uoff = (int64_t)(u1 - 1) * nbU * nbU;
-    if (state_in) prefetch_gemv<T, S, 3, Z>(A, B, gu, u12 + uoff, KV - nbU, nullptr);
-    else prefetch_gemv<T, S, 2, Z>(A, B, gu, uinv + uoff, 0, nullptr);
-  }
-  T* Y = mode == 3 ? (T*)ca.uy + off[2] + (int64_t)unit * rows : nullptr;
-  T* Yt = mode == 3 ? (T*)ca.ut + off[3] + (int64_t)unit * nbU : nullptr;
+  T* Y = (mode == 3 && ce == c + 1) ? (T*)ca.uy + off[2] + (int64_t)unit * rows : nullptr;
+  // block ce - c - 1 of UP_{c-1}, column `unit`
+  T* Up = (mode == 3 && c >= 1)
+              ? (T*)ca.up + ca.off[4 * ((int64_t)j * ca.p + c - 1) + 3] + ((int64_t)(ce - c - 1) * nbU + unit) * nbU
+              : nullptr;
   double* xs = ca.xs + voff;
   for (int32_t b = u1 - 1; b >= u0; --b) {
     const int64_t uoff = (int64_t)b * nbU * nbU;
@@ -502,19 +524,19 @@ k_chunk_upper(SweepArgs a, ChunkArgs ca, int mode) {
       const double x = sum_parts(part, nbU, CG, tid);
       xn[tid] = x;
       const int32_t row = b * nbU + tid;
-      if (mode == 3) {
-        Y[row - r0] = (T)x;
-        if (b == u0) Yt[tid] = (T)x;
-      } else {
+      if (mode != 3) {
         xs[row] = x;
+      } else {
+        if (Y) Y[row - r0] = (T)x;
+        if (Up && b == u0) Up[tid] = (T)x;
       }
     }
     __syncthreads();
   }
 }
 
-// State recurrence from the top chunk down to chunk c, upper correction and
-// the output: mode 0 out = x, mode 1 out = z1 - x (interior rows).
+// State and upper correction of chunk c, and the output: mode 0 out = x,
+// mode 1 out = z1 - x (interior rows).
 template <class T, int S>
 __global__ void __launch_bounds__(kSweepThreads)
 k_chunk_fix(SweepArgs a, ChunkArgs ca, int mode, double* out, const double* z1) {
@@ -528,27 +550,36 @@ k_chunk_fix(SweepArgs a, ChunkArgs ca, int mode, double* out, const double* z1) 
   const int32_t r0 = u0 * nbU, rows = (u1 - u0) * nbU;
   const int tid = threadIdx.x;
   double* s = smem;
-  double* part = s + a.maxU;
+  double* stk = s + a.maxU;
+  double* part = stk + ca.stk;
   const double* xs = ca.xs + voff;
+  const int64_t* off = ca.off + 4 * ((int64_t)j * p + c);
   int CG = 0;
   if (c + 1 < p) {
-    const int32_t utop = chunk_ub(nU, p, p - 1);
-    for (int32_t r = tid; r < nbU; r += blockDim.x) s[r] = xs[utop * nbU + r];
-    __syncthreads();
     Chunk<T, S> A, B;
-    const Geo gs = make_geo<S>(nbU, nbU);
-    for (int32_t c2 = p - 2; c2 > c; --c2) {
-      const T* Yt = (const T*)ca.ut + ca.off[4 * ((int64_t)j * p + c2) + 3];
-      prefetch_gemv<T, S, 0, false>(A, B, gs, Yt, 0, nullptr);
-      const int CGs = run_gemv<T, S, 0, false>(A, B, gs, Yt, 0, nullptr, s, part);
-      __syncthreads();
-      const int32_t u = chunk_ub(nU, p, c2);
-      for (int32_t r = tid; r < nbU; r += blockDim.x) s[r] = xs[u * nbU + r] + sum_parts(part, nbU, CGs, r);
-      __syncthreads();
-    }
     const Geo gy = make_geo<S>(rows, nbU);
-    const T* Y = (const T*)ca.uy + ca.off[4 * ((int64_t)j * p + c) + 2];
-    prefetch_gemv<T, S, 0, false>(A, B, gy, Y, 0, nullptr);
+    const T* Y = (const T*)ca.uy + off[2];
+    const int32_t uf = chunk_ub(nU, p, c + 1);
+    if (c + 2 < p) {
+      // s_c = f_{c+1} + UP_c [f_{c+2}; ...; f_{p-1}]
+      const int32_t K = (p - 2 - c) * nbU;
+      const Geo gp = make_geo<S>(nbU, K);
+      const T* UP = (const T*)ca.up + off[3];
+      prefetch_gemv<T, S, 0, false>(A, B, gp, UP, 0, nullptr);
+      for (int32_t e = tid; e < K; e += blockDim.x) {
+        const int32_t i = e / nbU, r = e - i * nbU;
+        stk[e] = xs[(int64_t)chunk_ub(nU, p, c + 2 + i) * nbU + r];
+      }
+      __syncthreads();
+      const int CGp = run_gemv<T, S, 0, false>(A, B, gp, UP, 0, nullptr, stk, part);
+      prefetch_gemv<T, S, 0, false>(A, B, gy, Y, 0, nullptr);
+      __syncthreads();
+      for (int32_t r = tid; r < nbU; r += blockDim.x) s[r] = xs[uf * nbU + r] + sum_parts(part, nbU, CGp, r);
+    } else {
+      prefetch_gemv<T, S, 0, false>(A, B, gy, Y, 0, nullptr);
+      for (int32_t r = tid; r < nbU; r += blockDim.x) s[r] = xs[uf * nbU + r];
+    }
+    __syncthreads();
     CG = run_gemv<T, S, 0, false>(A, B, gy, Y, 0, nullptr, s, part);
     __syncthreads();
   }
@@ -558,6 +589,32 @@ k_chunk_fix(SweepArgs a, ChunkArgs ca, int mode, double* out, const double* z1) 
     const double x = xs[row] + (c + 1 < p ? sum_parts(part, rows, CG, r) : 0.0);
     out[ioff + row] = mode == 1 ? z1[ioff + row] - x : x;
   }
+}
+
+// One level of the product responses: for every subdomain, blocks 1.. of
+// P_c are F_c times all blocks of P_nx, where F_c (block 0 of P_c, n x n) is
+// the single-chunk response (upper: P = UP, n = nbU, nx = c + 1; lower:
+// P = LP, n = KL, nx = c - 1, nblk blocks of P_nx).  FP64 accumulation, one
+// thread per output entry, columns of F_c read coalesced.
+template <class T>
+__global__ void k_chunk_products(const SubInfo* __restrict__ subs, const int64_t* __restrict__ off, int32_t p,
+                                 int32_t c, int32_t nx, int upper, T* P) {
+  const int32_t j = blockIdx.y;
+  const SubInfo q = subs[j];
+  if (q.n == 0) return;
+  const int32_t n = upper ? q.nbu : q.kl;
+  const int32_t nblk = upper ? p - 3 - c : nx - 1;  // blocks of P_nx
+  const int64_t total = (int64_t)n * nblk * n;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int32_t r = (int32_t)(e % n);
+  const int64_t col = e / n;  // column of P_nx
+  const int slot = upper ? 3 : 1;
+  T* Pc = P + off[4 * ((int64_t)j * p + c) + slot];
+  const T* Px = P + off[4 * ((int64_t)j * p + nx) + slot];
+  double acc = 0.0;
+  for (int32_t k = 0; k < n; ++k) acc += (double)Pc[(int64_t)k * n + r] * (double)Px[col * n + k];
+  Pc[((int64_t)n + col) * n + r] = (T)acc;
 }
 
 // One workgroup per aggregate: t = y2 - F z1 on the aggregate's rows, then
@@ -712,9 +769,13 @@ static void run_sweep(const addns_precond* pc, const SweepArgs& a, int grid, con
 }
 
 // ---- chunked sweep ---------------------------------------------------------
-static size_t chunk_smem_bytes(int32_t maxW, int32_t maxU, int S) {
-  return sizeof(double) *
-         (size_t)(2 * maxW + 2 * maxU + std::max<int64_t>((int64_t)kWaves * std::max(maxW, maxU), 1024 * S));
+static int32_t chunk_stack_words(int p, int32_t klmax, int32_t maxU) {
+  return std::max(0, p - 2) * std::max(klmax, maxU);
+}
+
+static size_t chunk_smem_bytes(int32_t maxW, int32_t maxU, int S, int32_t stk) {
+  return sizeof(double) * (size_t)(2 * maxW + 2 * maxU + stk +
+                                   std::max<int64_t>((int64_t)kWaves * std::max(maxW, maxU), 1024 * S));
 }
 
 template <class T>
@@ -756,11 +817,12 @@ static ChunkArgs chunk_args(const addns_precond* pc) {
   ChunkArgs ca{};
   ca.p = pc->sweep_chunks;
   ca.klmax = pc->ch_klmax;
+  ca.stk = chunk_stack_words(ca.p, ca.klmax, pc->plan.nbU);
   ca.off = pc->ch_off.as<int64_t>();
   ca.lx = pc->ch_lx.p;
-  ca.lt = pc->ch_lt.p;
+  ca.lp = pc->ch_lp.p;
   ca.uy = pc->ch_uy.p;
-  ca.ut = pc->ch_ut.p;
+  ca.up = pc->ch_up.p;
   ca.cz = pc->ch_cz.as<double>();
   ca.xs = pc->ch_xs.as<double>();
   ca.uin = pc->ch_uin.as<double>();
@@ -776,7 +838,7 @@ static void run_chunked(const addns_precond* pc, const SweepArgs& a, const doubl
     using T = typename decltype(tt)::type;
     constexpr int S = decltype(ss)::value;
     constexpr bool Z = decltype(zz)::value;
-    const size_t smem = chunk_smem_bytes(pl.maxW, pl.nbU, S);
+    const size_t smem = chunk_smem_bytes(pl.maxW, pl.nbU, S, ca.stk);
     k_chunk_lower<T, S, Z><<<grid, kSweepThreads, smem, s>>>(a, ca, yin, mode, x2);
     k_chunk_upper<T, S, Z><<<grid, kSweepThreads, smem, s>>>(a, ca, mode);
     k_chunk_fix<T, S><<<grid, kSweepThreads, smem, s>>>(a, ca, mode, out, z1);
@@ -792,55 +854,69 @@ int max_sweep_chunks(const Plan& pl) {
 
 void release_chunked_sweep(addns_precond* pc) {
   pc->sweep_chunks = 1;
-  for (DevBuf* d : {&pc->ch_off, &pc->ch_lx, &pc->ch_lt, &pc->ch_uy, &pc->ch_ut, &pc->ch_cz, &pc->ch_xs, &pc->ch_uin})
+  pc->chunk_bytes = 0;
+  for (DevBuf* d : {&pc->ch_off, &pc->ch_lx, &pc->ch_lp, &pc->ch_uy, &pc->ch_up, &pc->ch_cz, &pc->ch_xs, &pc->ch_uin})
     d->reset();
 }
 
 // Offsets and response matrices of the chunked sweep with p chunks, swept on
-// the handle's current factors (mode 3 of the chunk kernels).
+// the handle's current factors (mode 3 of the chunk kernels, one workgroup per
+// chunk range and unit).
 void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
   const Plan& pl = pc->plan;
   if (p < 2 || p > max_sweep_chunks(pl)) throw ArgError("sweep_chunks exceeds the upper blocks of an interior");
   const int S = std::min(5, (std::max(pl.maxW, pl.nbU) + 63) / 64);
   const int m = pl.m;
   const int fb = pc->interior_prec == P64 ? 8 : 4;
+  int32_t klmax = 1;
+  for (const SubInfo& q : pl.subs) klmax = std::max(klmax, q.kl);
+  if (chunk_smem_bytes(pl.maxW, pl.nbU, S, chunk_stack_words(p, klmax, pl.nbU)) > 160 * 1024)
+    throw ArgError("sweep_chunks too large for the chunk kernels' LDS");
   std::vector<int64_t> off((size_t)4 * m * p, 0);
   std::vector<int32_t> jl, ju;
-  int64_t nlx = 0, nlt = 0, nuy = 0, nut = 0;
-  int32_t klmax = 1;
+  int64_t nlx = 0, nlp = 0, nuy = 0, nup = 0;
   for (int32_t j = 0; j < m; ++j) {
     const SubInfo& q = pl.subs[j];
-    klmax = std::max(klmax, q.kl);
     if (q.n == 0) continue;
-    const int32_t nU = q.npad / q.nbu;
+    const int32_t nU = q.npad / q.nbu, KL = q.kl, nbU = q.nbu;
     for (int32_t c = 0; c < p; ++c) {
-      const int32_t rows = (int32_t)(((int64_t)nU * (c + 1) / p - (int64_t)nU * c / p) * q.nbu);
+      const int32_t rows = (int32_t)(((int64_t)nU * (c + 1) / p - (int64_t)nU * c / p) * nbU);
       if (rows > 1024 * S) throw ArgError("sweep chunk too tall for the chunk kernels' GEMVs");
       int64_t* o = &off[(size_t)4 * ((int64_t)j * p + c)];
       if (c >= 1) {
         o[0] = nlx;
-        nlx += (int64_t)rows * q.kl;
-        o[1] = nlt;
-        nlt += (int64_t)q.kl * q.kl;
-        for (int32_t u = 0; u < q.kl; ++u) jl.insert(jl.end(), {j, c, u});
+        nlx += (int64_t)rows * KL;
+      }
+      if (c >= 2) {
+        o[1] = nlp;
+        nlp += (int64_t)KL * (c - 1) * KL;
       }
       if (c + 1 < p) {
         o[2] = nuy;
-        nuy += (int64_t)rows * q.nbu;
-        o[3] = nut;
-        nut += (int64_t)q.nbu * q.nbu;
-        for (int32_t u = 0; u < q.nbu; ++u) ju.insert(ju.end(), {j, c, u});
+        nuy += (int64_t)rows * nbU;
+      }
+      if (c + 2 < p) {
+        o[3] = nup;
+        nup += (int64_t)nbU * (p - 2 - c) * nbU;
       }
     }
+    // single chunks: lower c >= 1 (X_c, and T_c into block 0 of LP_{c+1}),
+    // upper c <= p - 2 (Y_c, and Yt_c into block 0 of UP_{c-1}); the longer
+    // products follow from them (k_chunk_products)
+    for (int32_t c = 1; c < p; ++c)
+      for (int32_t u = 0; u < KL; ++u) jl.insert(jl.end(), {j, c, c + 1, u});
+    for (int32_t c = 0; c + 1 < p; ++c)
+      for (int32_t u = 0; u < nbU; ++u) ju.insert(ju.end(), {j, c, c + 1, u});
   }
   pc->sweep_chunks = p;
   pc->ch_klmax = klmax;
+  pc->chunk_bytes = (int64_t)fb * (nlx + nlp + nuy + nup);
   pc->ch_off.upload(off, s);
   // the chunk GEMVs' last row slot may read up to 64 * 5 rows past a
   // matrix; the zeroed tail keeps that overrun inside the allocation
   const int64_t tail = kSweepOverrunBytes;
-  DevBuf* mats[4] = {&pc->ch_lx, &pc->ch_lt, &pc->ch_uy, &pc->ch_ut};
-  const int64_t cnt[4] = {nlx, nlt, nuy, nut};
+  DevBuf* mats[4] = {&pc->ch_lx, &pc->ch_lp, &pc->ch_uy, &pc->ch_up};
+  const int64_t cnt[4] = {nlx, nlp, nuy, nup};
   for (int i = 0; i < 4; ++i) {
     mats[i]->alloc((size_t)(fb * cnt[i] + tail));
     ADDNS_HIP(hipMemsetAsync(static_cast<char*>(mats[i]->p) + mats[i]->bytes - tail, 0, tail, s));
@@ -858,14 +934,26 @@ void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
     using T = typename decltype(tt)::type;
     constexpr int S2 = decltype(ss)::value;
     constexpr bool Z = decltype(zz)::value;
-    const size_t smem = chunk_smem_bytes(pl.maxW, pl.nbU, S2);
+    const size_t smem = chunk_smem_bytes(pl.maxW, pl.nbU, S2, ca.stk);
     raise_lds(k_chunk_lower<T, S2, Z>, smem);
     raise_lds(k_chunk_upper<T, S2, Z>, smem);
     raise_lds(k_chunk_fix<T, S2>, smem);
     ca.job = d_jl.as<int32_t>();
-    if (!jl.empty()) k_chunk_lower<T, S2, Z><<<(int)(jl.size() / 3), kSweepThreads, smem, s>>>(a, ca, nullptr, 3, nullptr);
+    if (!jl.empty()) k_chunk_lower<T, S2, Z><<<(int)(jl.size() / 4), kSweepThreads, smem, s>>>(a, ca, nullptr, 3, nullptr);
     ca.job = d_ju.as<int32_t>();
-    if (!ju.empty()) k_chunk_upper<T, S2, Z><<<(int)(ju.size() / 3), kSweepThreads, smem, s>>>(a, ca, 3);
+    if (!ju.empty()) k_chunk_upper<T, S2, Z><<<(int)(ju.size() / 4), kSweepThreads, smem, s>>>(a, ca, 3);
+    // UP_c = [Yt_{c+1}, Yt_{c+1} UP_{c+1}] for c = p-4 down to 0;
+    // LP_c = [T_{c-1}, T_{c-1} LP_{c-1}] for c = 3 up to p-1
+    for (int32_t c = p - 4; c >= 0; --c) {
+      const int64_t tot = (int64_t)pl.nbU * (p - 3 - c) * pl.nbU;
+      k_chunk_products<T><<<dim3((unsigned)((tot + 255) / 256), m), 256, 0, s>>>(
+          pc->subs.as<SubInfo>(), pc->ch_off.as<int64_t>(), p, c, c + 1, 1, (T*)pc->ch_up.p);
+    }
+    for (int32_t c = 3; c < p; ++c) {
+      const int64_t tot = (int64_t)klmax * (c - 2) * klmax;
+      k_chunk_products<T><<<dim3((unsigned)((tot + 255) / 256), m), 256, 0, s>>>(
+          pc->subs.as<SubInfo>(), pc->ch_off.as<int64_t>(), p, c, c - 1, 0, (T*)pc->ch_lp.p);
+    }
   });
   ADDNS_HIP(hipGetLastError());
   ADDNS_HIP(hipStreamSynchronize(s));

@@ -186,9 +186,10 @@ struct addns_precond {
   int zero_skip = 0;                                  // sweep skips structural-zero row slots (autotuned)
   // chunked interior sweep: p chunks per interior swept side by side, joined
   // through each chunk's response to its incoming carry (lower) or state
-  // (upper); per (subdomain, chunk) the offsets of X_c, T_c, Y_c, Yt_c
+  // (upper); per (subdomain, chunk) the offsets of X_c, LP_c, Y_c, UP_c
   int sweep_chunks = 1, ch_klmax = 0;
-  addns::DevBuf ch_off, ch_lx, ch_lt, ch_uy, ch_ut;   // offsets (int64) and response matrices
+  int64_t chunk_bytes = 0;                            // response matrices, read once per interior solve
+  addns::DevBuf ch_off, ch_lx, ch_lp, ch_uy, ch_up;   // offsets (int64) and response matrices
   addns::DevBuf ch_cz, ch_xs, ch_uin;                 // zero-state carries and upper outputs, E x2
   addns::DevBuf g_copy;                               // G blocks before the update (learning targets S - G)
   addns::DevBuf smp_row, smp_nb, smp_loc;             // learned-correction sample table
