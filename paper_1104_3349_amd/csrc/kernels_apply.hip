@@ -330,7 +330,13 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
 // carry, lower correction and zero-state upper chunk; state, upper correction
 // and output.
 //   LP_c = [T_{c-1}, T_{c-1}T_{c-2}, ..., T_{c-1}...T_1]   KL x (c-1) KL
-//   UP_c = [Yt_{c+1}, Yt_{c+1}Yt_{c+2}, ..., Yt_{c+1}...Yt_{p-2}]   nbU x (p-2-c) nbU
+//   UP_c = [R_{c+1}, R_{c+1}R_{c+2}, ..., R_{c+1}...R_{p-2}]
+// The state above chunk c reaches it only through the nonzero columns of the
+// coupling block U_{b,b+1}, b = u_{c+1} - 1 (found at setup in the stored
+// factors): a unit state in any other column has exactly zero response.  So
+// the upper responses are taken only for those ns_c columns nz_c, the state
+// s_c is carried only in them, Y_c is rows_c x ns_c, and R_c = Yt_c(nz_{c-1}, :)
+// is ns_{c-1} x ns_c (UP_c: ns_c x (ns_{c+1} + ... + ns_{p-2})).
 // ---------------------------------------------------------------------------
 struct ChunkArgs {
   int32_t p, klmax, stk;  // chunks, carry stride, LDS words of the stacked recurrence vector
@@ -342,6 +348,8 @@ struct ChunkArgs {
   double* cz;          // zero-carry carry out of each chunk (klmax per (subdomain, chunk))
   double* xs;          // zero-state upper outputs, padded interior numbering
   double* uin;         // mode 1: the sweep input E x2, padded interior numbering
+  const int32_t* nz;   // coupling columns nz_c of every (subdomain, boundary c) ...
+  const int32_t* nzo;  // ... at nz[nzo[j p + c] .. nzo[j p + c + 1])
   const int32_t* job;  // mode 3: (subdomain, first chunk, end chunk, unit) per workgroup
 };
 
@@ -493,17 +501,14 @@ k_chunk_upper(SweepArgs a, ChunkArgs ca, int mode) {
     for (int32_t r = tid; r < rows; r += blockDim.x) ypad[r0 + r] += sum_parts(part, rows, CG, r);
     __syncthreads();
   } else if (state_in) {
-    for (int32_t r = tid; r < nbU; r += blockDim.x) xn[r] = r == unit ? 1.0 : 0.0;
+    const int32_t col = ca.nz[ca.nzo[(int64_t)j * ca.p + c] + unit];
+    for (int32_t r = tid; r < nbU; r += blockDim.x) xn[r] = r == col ? 1.0 : 0.0;
     if (u0 < u1) prefetch_gemv<T, S, 3, Z>(A, B, gu, u12 + (int64_t)(u1 - 1) * nbU * nbU, KV - nbU, nullptr);
     __syncthreads();
   } else if (u0 < u1) {
     prefetch_gemv<T, S, 2, Z>(A, B, gu, uinv + (int64_t)(u1 - 1) * nbU * nbU, 0, nullptr);
   }
-  T* Y = (mode == 3 && ce == c + 1) ? (T*)ca.uy + off[2] + (int64_t)unit * rows : nullptr;
-  // block ce - c - 1 of UP_{c-1}, column `unit`
-  T* Up = (mode == 3 && c >= 1)
-              ? (T*)ca.up + ca.off[4 * ((int64_t)j * ca.p + c - 1) + 3] + ((int64_t)(ce - c - 1) * nbU + unit) * nbU
-              : nullptr;
+  T* Y = mode == 3 ? (T*)ca.uy + off[2] + (int64_t)unit * rows : nullptr;
   double* xs = ca.xs + voff;
   for (int32_t b = u1 - 1; b >= u0; --b) {
     const int64_t uoff = (int64_t)b * nbU * nbU;
@@ -524,14 +529,16 @@ k_chunk_upper(SweepArgs a, ChunkArgs ca, int mode) {
       const double x = sum_parts(part, nbU, CG, tid);
       xn[tid] = x;
       const int32_t row = b * nbU + tid;
-      if (mode != 3) {
-        xs[row] = x;
-      } else {
-        if (Y) Y[row - r0] = (T)x;
-        if (Up && b == u0) Up[tid] = (T)x;
-      }
+      if (mode != 3) xs[row] = x;
+      else Y[row - r0] = (T)x;
     }
     __syncthreads();
+  }
+  if (mode == 3 && c >= 1) {
+    // R_c column `unit` (block 0 of UP_{c-1}): the first block at nz_{c-1}
+    const int32_t o = ca.nzo[(int64_t)j * ca.p + c - 1], ns = ca.nzo[(int64_t)j * ca.p + c] - o;
+    T* R = (T*)ca.up + ca.off[4 * ((int64_t)j * ca.p + c - 1) + 3] + (int64_t)unit * ns;
+    for (int32_t k = tid; k < ns; k += blockDim.x) R[k] = (T)xn[ca.nz[o + k]];
   }
 }
 
@@ -555,29 +562,34 @@ k_chunk_fix(SweepArgs a, ChunkArgs ca, int mode, double* out, const double* z1) 
   const double* xs = ca.xs + voff;
   const int64_t* off = ca.off + 4 * ((int64_t)j * p + c);
   int CG = 0;
-  if (c + 1 < p) {
+  const int32_t o = ca.nzo[(int64_t)j * p + c], ns = c + 1 < p ? ca.nzo[(int64_t)j * p + c + 1] - o : 0;
+  if (ns > 0) {
     Chunk<T, S> A, B;
-    const Geo gy = make_geo<S>(rows, nbU);
+    const Geo gy = make_geo<S>(rows, ns);
     const T* Y = (const T*)ca.uy + off[2];
     const int32_t uf = chunk_ub(nU, p, c + 1);
-    if (c + 2 < p) {
-      // s_c = f_{c+1} + UP_c [f_{c+2}; ...; f_{p-1}]
-      const int32_t K = (p - 2 - c) * nbU;
-      const Geo gp = make_geo<S>(nbU, K);
+    // K = ns_{c+1} + ... + ns_{p-2}: the stacked restricted first blocks
+    const int32_t K = c + 2 < p ? ca.nzo[(int64_t)j * p + p - 1] - ca.nzo[(int64_t)j * p + c + 1] : 0;
+    if (K > 0) {
+      // s_c = f_{c+1}(nz_c) + UP_c [f_{c+2}(nz_{c+1}); ...; f_{p-1}(nz_{p-2})]
+      const Geo gp = make_geo<S>(ns, K);
       const T* UP = (const T*)ca.up + off[3];
       prefetch_gemv<T, S, 0, false>(A, B, gp, UP, 0, nullptr);
+      const int32_t ob = ca.nzo[(int64_t)j * p + c + 1];
       for (int32_t e = tid; e < K; e += blockDim.x) {
-        const int32_t i = e / nbU, r = e - i * nbU;
-        stk[e] = xs[(int64_t)chunk_ub(nU, p, c + 2 + i) * nbU + r];
+        // entry e belongs to boundary c2 (first block of chunk c2 + 1)
+        int32_t c2 = c + 1;
+        while (ca.nzo[(int64_t)j * p + c2 + 1] <= ob + e) ++c2;
+        stk[e] = xs[(int64_t)chunk_ub(nU, p, c2 + 1) * nbU + ca.nz[ob + e]];
       }
       __syncthreads();
       const int CGp = run_gemv<T, S, 0, false>(A, B, gp, UP, 0, nullptr, stk, part);
       prefetch_gemv<T, S, 0, false>(A, B, gy, Y, 0, nullptr);
       __syncthreads();
-      for (int32_t r = tid; r < nbU; r += blockDim.x) s[r] = xs[uf * nbU + r] + sum_parts(part, nbU, CGp, r);
+      for (int32_t k = tid; k < ns; k += blockDim.x) s[k] = xs[uf * nbU + ca.nz[o + k]] + sum_parts(part, ns, CGp, k);
     } else {
       prefetch_gemv<T, S, 0, false>(A, B, gy, Y, 0, nullptr);
-      for (int32_t r = tid; r < nbU; r += blockDim.x) s[r] = xs[uf * nbU + r];
+      for (int32_t k = tid; k < ns; k += blockDim.x) s[k] = xs[uf * nbU + ca.nz[o + k]];
     }
     __syncthreads();
     CG = run_gemv<T, S, 0, false>(A, B, gy, Y, 0, nullptr, s, part);
@@ -586,35 +598,67 @@ k_chunk_fix(SweepArgs a, ChunkArgs ca, int mode, double* out, const double* z1) 
   for (int32_t r = tid; r < rows; r += blockDim.x) {
     const int32_t row = r0 + r;
     if (row >= n) continue;
-    const double x = xs[row] + (c + 1 < p ? sum_parts(part, rows, CG, r) : 0.0);
+    const double x = xs[row] + (ns > 0 ? sum_parts(part, rows, CG, r) : 0.0);
     out[ioff + row] = mode == 1 ? z1[ioff + row] - x : x;
   }
 }
 
-// One level of the product responses: for every subdomain, blocks 1.. of
-// P_c are F_c times all blocks of P_nx, where F_c (block 0 of P_c, n x n) is
-// the single-chunk response (upper: P = UP, n = nbU, nx = c + 1; lower:
-// P = LP, n = KL, nx = c - 1, nblk blocks of P_nx).  FP64 accumulation, one
-// thread per output entry, columns of F_c read coalesced.
+// One level of the product responses, for every subdomain: P_c(:, w0 ..) =
+// P_c(:, 0 .. w0) P_nx, with P_c(:, 0 .. w0) the single-chunk block
+// (upper: P = UP, nx = c + 1, rows ns_c, w0 = ns_{c+1}, P_nx ns_{c+1} x K_{c+1};
+// lower: P = LP, nx = c - 1, rows KL, w0 = KL, P_nx KL x (c - 2) KL).  FP64
+// accumulation, one thread per output entry.
 template <class T>
-__global__ void k_chunk_products(const SubInfo* __restrict__ subs, const int64_t* __restrict__ off, int32_t p,
-                                 int32_t c, int32_t nx, int upper, T* P) {
+__global__ void k_chunk_products(const SubInfo* __restrict__ subs, const int64_t* __restrict__ off,
+                                 const int32_t* __restrict__ nzo, int32_t p, int32_t c, int upper, T* P) {
   const int32_t j = blockIdx.y;
   const SubInfo q = subs[j];
   if (q.n == 0) return;
-  const int32_t n = upper ? q.nbu : q.kl;
-  const int32_t nblk = upper ? p - 3 - c : nx - 1;  // blocks of P_nx
-  const int64_t total = (int64_t)n * nblk * n;
+  int32_t rows, w0, cols, nx;
+  if (upper) {
+    const int32_t* z = nzo + (int64_t)j * p;
+    rows = z[c + 1] - z[c];
+    w0 = z[c + 2] - z[c + 1];
+    cols = z[p - 1] - z[c + 2];
+    nx = c + 1;
+  } else {
+    rows = w0 = q.kl;
+    cols = (c - 2) * q.kl;
+    nx = c - 1;
+  }
+  const int64_t total = (int64_t)rows * cols;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
-  const int32_t r = (int32_t)(e % n);
-  const int64_t col = e / n;  // column of P_nx
+  const int32_t r = (int32_t)(e % rows);
+  const int64_t col = e / rows;
   const int slot = upper ? 3 : 1;
   T* Pc = P + off[4 * ((int64_t)j * p + c) + slot];
   const T* Px = P + off[4 * ((int64_t)j * p + nx) + slot];
   double acc = 0.0;
-  for (int32_t k = 0; k < n; ++k) acc += (double)Pc[(int64_t)k * n + r] * (double)Px[col * n + k];
-  Pc[((int64_t)n + col) * n + r] = (T)acc;
+  for (int32_t k = 0; k < w0; ++k) acc += (double)Pc[(int64_t)k * rows + r] * (double)Px[col * w0 + k];
+  Pc[((int64_t)w0 + col) * rows + r] = (T)acc;
+}
+
+// Coupling columns of each chunk boundary: flags[(j p + c) nbU + k] = 1 if
+// column k of U_{b,b+1}, b = u_{c+1} - 1, holds a nonzero.
+template <class T>
+__global__ void k_chunk_nzcols(const SubInfo* __restrict__ subs, const T* __restrict__ u12_all, int32_t p,
+                               uint8_t* __restrict__ flags) {
+  const int32_t j = blockIdx.x / (p - 1), c = blockIdx.x % (p - 1);
+  const SubInfo q = subs[j];
+  const int32_t nbU = q.nbu;
+  uint8_t* f = flags + ((int64_t)j * p + c) * nbU;
+  if (q.n == 0) {
+    for (int32_t k = threadIdx.x; k < nbU; k += blockDim.x) f[k] = 0;
+    return;
+  }
+  const int32_t nU = q.npad / nbU, b = chunk_ub(nU, p, c + 1) - 1;
+  const T* M = u12_all + q.u_off + (int64_t)b * nbU * nbU;
+  for (int32_t k = threadIdx.x; k < nbU; k += blockDim.x) {
+    bool nzc = false;
+    for (int32_t r = 0; r < nbU && !nzc; ++r) nzc = M[(int64_t)k * nbU + r] != T(0);
+    f[k] = nzc ? 1 : 0;
+  }
 }
 
 // One workgroup per aggregate: t = y2 - F z1 on the aggregate's rows, then
@@ -826,6 +870,8 @@ static ChunkArgs chunk_args(const addns_precond* pc) {
   ca.cz = pc->ch_cz.as<double>();
   ca.xs = pc->ch_xs.as<double>();
   ca.uin = pc->ch_uin.as<double>();
+  ca.nz = pc->ch_nz.as<int32_t>();
+  ca.nzo = pc->ch_nzo.as<int32_t>();
   return ca;
 }
 
@@ -855,7 +901,8 @@ int max_sweep_chunks(const Plan& pl) {
 void release_chunked_sweep(addns_precond* pc) {
   pc->sweep_chunks = 1;
   pc->chunk_bytes = 0;
-  for (DevBuf* d : {&pc->ch_off, &pc->ch_lx, &pc->ch_lp, &pc->ch_uy, &pc->ch_up, &pc->ch_cz, &pc->ch_xs, &pc->ch_uin})
+  for (DevBuf* d : {&pc->ch_off, &pc->ch_lx, &pc->ch_lp, &pc->ch_uy, &pc->ch_up, &pc->ch_cz, &pc->ch_xs, &pc->ch_uin,
+                    &pc->ch_nz, &pc->ch_nzo})
     d->reset();
 }
 
@@ -872,6 +919,30 @@ void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
   for (const SubInfo& q : pl.subs) klmax = std::max(klmax, q.kl);
   if (chunk_smem_bytes(pl.maxW, pl.nbU, S, chunk_stack_words(p, klmax, pl.nbU)) > 160 * 1024)
     throw ArgError("sweep_chunks too large for the chunk kernels' LDS");
+  // coupling columns of every chunk boundary, from the stored U_{b,b+1}
+  std::vector<uint8_t> flags((size_t)m * p * pl.nbU, 0);
+  {
+    DevBuf d_flags;
+    d_flags.alloc(flags.size());
+    ADDNS_HIP(hipMemsetAsync(d_flags.p, 0, flags.size(), s));
+    if (pc->interior_prec == P64)
+      k_chunk_nzcols<double><<<m * (p - 1), 256, 0, s>>>(pc->subs.as<SubInfo>(), pc->u12.as<double>(), p,
+                                                         d_flags.as<uint8_t>());
+    else
+      k_chunk_nzcols<float><<<m * (p - 1), 256, 0, s>>>(pc->subs.as<SubInfo>(), pc->u12.as<float>(), p,
+                                                        d_flags.as<uint8_t>());
+    ADDNS_HIP(hipMemcpyAsync(flags.data(), d_flags.p, flags.size(), hipMemcpyDeviceToHost, s));
+    ADDNS_HIP(hipStreamSynchronize(s));
+  }
+  std::vector<int32_t> nz, nzo((size_t)m * p + 1, 0);
+  for (int32_t j = 0; j < m; ++j)
+    for (int32_t c = 0; c < p; ++c) {
+      nzo[(size_t)j * p + c] = (int32_t)nz.size();
+      if (c + 1 < p && pl.subs[j].n > 0)
+        for (int32_t k = 0; k < pl.subs[j].nbu; ++k)
+          if (flags[((size_t)j * p + c) * pl.nbU + k]) nz.push_back(k);
+    }
+  nzo[(size_t)m * p] = (int32_t)nz.size();
   std::vector<int64_t> off((size_t)4 * m * p, 0);
   std::vector<int32_t> jl, ju;
   int64_t nlx = 0, nlp = 0, nuy = 0, nup = 0;
@@ -891,13 +962,14 @@ void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
         o[1] = nlp;
         nlp += (int64_t)KL * (c - 1) * KL;
       }
+      const int32_t* z = &nzo[(size_t)j * p];
       if (c + 1 < p) {
         o[2] = nuy;
-        nuy += (int64_t)rows * nbU;
+        nuy += (int64_t)rows * (z[c + 1] - z[c]);
       }
       if (c + 2 < p) {
         o[3] = nup;
-        nup += (int64_t)nbU * (p - 2 - c) * nbU;
+        nup += (int64_t)(z[c + 1] - z[c]) * (z[p - 1] - z[c + 1]);
       }
     }
     // single chunks: lower c >= 1 (X_c, and T_c into block 0 of LP_{c+1}),
@@ -906,7 +978,8 @@ void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
     for (int32_t c = 1; c < p; ++c)
       for (int32_t u = 0; u < KL; ++u) jl.insert(jl.end(), {j, c, c + 1, u});
     for (int32_t c = 0; c + 1 < p; ++c)
-      for (int32_t u = 0; u < nbU; ++u) ju.insert(ju.end(), {j, c, c + 1, u});
+      for (int32_t u = 0; u < nzo[(size_t)j * p + c + 1] - nzo[(size_t)j * p + c]; ++u)
+        ju.insert(ju.end(), {j, c, c + 1, u});
   }
   pc->sweep_chunks = p;
   pc->ch_klmax = klmax;
@@ -924,6 +997,8 @@ void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
   pc->ch_cz.alloc(sizeof(double) * (size_t)m * p * klmax);
   pc->ch_xs.alloc(sizeof(double) * (size_t)std::max<int64_t>(pl.npad_total, 1));
   pc->ch_uin.alloc(sizeof(double) * (size_t)std::max<int64_t>(pl.npad_total, 1));
+  pc->ch_nz.upload(nz, s);
+  pc->ch_nzo.upload(nzo, s);
   DevBuf d_jl, d_ju;
   d_jl.upload(jl, s);
   d_ju.upload(ju, s);
@@ -942,17 +1017,21 @@ void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
     if (!jl.empty()) k_chunk_lower<T, S2, Z><<<(int)(jl.size() / 4), kSweepThreads, smem, s>>>(a, ca, nullptr, 3, nullptr);
     ca.job = d_ju.as<int32_t>();
     if (!ju.empty()) k_chunk_upper<T, S2, Z><<<(int)(ju.size() / 4), kSweepThreads, smem, s>>>(a, ca, 3);
-    // UP_c = [Yt_{c+1}, Yt_{c+1} UP_{c+1}] for c = p-4 down to 0;
+    // UP_c = [R_{c+1}, R_{c+1} UP_{c+1}] for c = p-4 down to 0;
     // LP_c = [T_{c-1}, T_{c-1} LP_{c-1}] for c = 3 up to p-1
     for (int32_t c = p - 4; c >= 0; --c) {
-      const int64_t tot = (int64_t)pl.nbU * (p - 3 - c) * pl.nbU;
+      int64_t tot = 1;
+      for (int32_t j = 0; j < m; ++j) {
+        const int32_t* z = &nzo[(size_t)j * p];
+        tot = std::max<int64_t>(tot, (int64_t)(z[c + 1] - z[c]) * (z[p - 1] - z[c + 2]));
+      }
       k_chunk_products<T><<<dim3((unsigned)((tot + 255) / 256), m), 256, 0, s>>>(
-          pc->subs.as<SubInfo>(), pc->ch_off.as<int64_t>(), p, c, c + 1, 1, (T*)pc->ch_up.p);
+          pc->subs.as<SubInfo>(), pc->ch_off.as<int64_t>(), pc->ch_nzo.as<int32_t>(), p, c, 1, (T*)pc->ch_up.p);
     }
     for (int32_t c = 3; c < p; ++c) {
       const int64_t tot = (int64_t)klmax * (c - 2) * klmax;
       k_chunk_products<T><<<dim3((unsigned)((tot + 255) / 256), m), 256, 0, s>>>(
-          pc->subs.as<SubInfo>(), pc->ch_off.as<int64_t>(), p, c, c - 1, 0, (T*)pc->ch_lp.p);
+          pc->subs.as<SubInfo>(), pc->ch_off.as<int64_t>(), pc->ch_nzo.as<int32_t>(), p, c, 0, (T*)pc->ch_lp.p);
     }
   });
   ADDNS_HIP(hipGetLastError());
