@@ -131,7 +131,9 @@ template <class T, int S, int kind, bool Z>
 __device__ __attribute__((always_inline)) inline void prefetch_gemv(Chunk<T, S>& A, Chunk<T, S>& B, const Geo& g, const T* M, int par,
                                      const int32_t* gidx) {
   constexpr int CB = Chunk<T, S>::CB;
-  if (!g.act) return;
+  // a wave whose column range is empty (K below the column groups) loads
+  // nothing: its first column would be kb - 1, outside the matrix
+  if (!g.act || g.kb >= g.ke) return;
   load_chunk<T, S, kind, Z>(A, g, M, par, gidx, g.kb);
   if (g.kb + CB < g.ke) load_chunk<T, S, kind, Z>(B, g, M, par, gidx, g.kb + CB);
 }
