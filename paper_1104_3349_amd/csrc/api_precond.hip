@@ -571,13 +571,27 @@ int addns_gmres_solve(addns_precond_t pc, const double* d_b, double* d_x, const 
     double relres = beta / bnorm;
     int its = 0;
     bool converged = relres <= opts->tol;
+    struct Events {
+      hipEvent_t e[2] = {nullptr, nullptr};
+      ~Events() {
+        for (hipEvent_t x : e)
+          if (x) (void)hipEventDestroy(x);
+      }
+    } ev;
+    for (hipEvent_t& x : ev.e) ADDNS_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
     while (!converged && its < maxit) {
       res->cycles++;
       launch_scale_copy(g.rp, g.V, g.scal, 3, N, s);
       ADDNS_HIP(hipMemsetAsync(g.g, 0, sizeof(double) * ldh, s));
       ADDNS_HIP(hipMemcpyAsync(g.g, g.scal + 3, sizeof(double), hipMemcpyDeviceToDevice, s));
       int jdone = 0;
-      for (int j = 0; j < restart; ++j) {
+      // Iteration j's residual estimate is read only after iteration j + 1 is
+      // queued, so the GPU never waits for the host between iterations.  An
+      // iteration queued past the one that stops is discarded: it writes only
+      // H(:, j), g[j], g[j+1], V[j+1] and Z[j], which the update below does not
+      // read, so the result is that of stopping in place.
+      double* hbuf = static_cast<double*>(pc->host_pinned) + 2;
+      auto queue_iteration = [&](int j) {
         double* vj = g.V + (int64_t)j * N;
         double* zj = opts->flexible ? g.Z + (int64_t)j * N : g.Z;
         apply_permuted(pc, vj, zj, s);
@@ -604,16 +618,27 @@ int addns_gmres_solve(addns_precond_t pc, const double* d_b, double* d_x, const 
         }
         launch_finalize(g.H, g.g, g.cs, g.sn, pin, pnorm_parts, j, ldh, g.scal, s);
         launch_scale_copy(g.w, g.V + (int64_t)(j + 1) * N, g.scal, 0, N, s);
-        double* h = static_cast<double*>(pc->host_pinned);
-        ADDNS_HIP(hipMemcpyAsync(h, g.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        ADDNS_HIP(hipStreamSynchronize(s));
-        const double hn = h[0], est = h[1];
+        ADDNS_HIP(hipMemcpyAsync(hbuf + 2 * (j & 1), g.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        ADDNS_HIP(hipEventRecord(ev.e[j & 1], s));
+      };
+      // true: the cycle stops after iteration j
+      auto finish_iteration = [&](int j) -> bool {
+        ADDNS_HIP(hipEventSynchronize(ev.e[j & 1]));
+        const double hn = hbuf[2 * (j & 1)], est = hbuf[2 * (j & 1) + 1];
         ++its;
         jdone = j + 1;
         res->est_relres = est / bnorm;
         if (hist) hist[its - 1] = est / bnorm;
         if (!std::isfinite(est)) throw HipError("non-finite residual estimate");
-        if (est <= opts->tol * bnorm || its >= maxit || hn == 0.0) break;
+        return est <= opts->tol * bnorm || its >= maxit || hn == 0.0;
+      };
+      for (int j = 0; j < restart; ++j) {
+        queue_iteration(j);
+        if (j > 0 && finish_iteration(j - 1)) break;
+        if (j == restart - 1) {
+          finish_iteration(j);
+          break;
+        }
       }
       launch_backsolve(g.H, g.g, jdone, ldh, g.y, s);
       if (opts->flexible) {
