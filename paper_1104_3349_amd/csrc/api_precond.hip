@@ -591,6 +591,9 @@ int addns_gmres_solve(addns_precond_t pc, const double* d_b, double* d_x, const 
       // H(:, j), g[j], g[j+1], V[j+1] and Z[j], which the update below does not
       // read, so the result is that of stopping in place.
       double* hbuf = static_cast<double*>(pc->host_pinned) + 2;
+      void* hdev = nullptr;  // the same pinned buffer as the device addresses it
+      ADDNS_HIP(hipHostGetDevicePointer(&hdev, pc->host_pinned, 0));
+      double* hbuf_dev = static_cast<double*>(hdev) + 2;
       auto queue_iteration = [&](int j) {
         double* vj = g.V + (int64_t)j * N;
         double* zj = opts->flexible ? g.Z + (int64_t)j * N : g.Z;
@@ -616,9 +619,9 @@ int addns_gmres_solve(addns_precond_t pc, const double* d_b, double* d_x, const 
             std::swap(pin, pout);
           }
         }
-        launch_finalize(g.H, g.g, g.cs, g.sn, pin, pnorm_parts, j, ldh, g.scal, s);
+        // the estimate goes straight to pinned host memory (no copy launch)
+        launch_finalize(g.H, g.g, g.cs, g.sn, pin, pnorm_parts, j, ldh, g.scal, hbuf_dev + 2 * (j & 1), s);
         launch_scale_copy(g.w, g.V + (int64_t)(j + 1) * N, g.scal, 0, N, s);
-        ADDNS_HIP(hipMemcpyAsync(hbuf + 2 * (j & 1), g.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         ADDNS_HIP(hipEventRecord(ev.e[j & 1], s));
       };
       // true: the cycle stops after iteration j

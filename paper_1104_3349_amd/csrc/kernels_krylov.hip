@@ -142,7 +142,7 @@ k_mgs_step(double* __restrict__ w, const double* __restrict__ vi, const double* 
 // scal[0] = h_{j+1,j}, scal[1] = |g_{j+1}|.
 __global__ void __launch_bounds__(kKT)
 k_finalize(double* __restrict__ H, double* __restrict__ g, double* __restrict__ cs, double* __restrict__ sn,
-           const double* __restrict__ partials, int nparts, int32_t j, int32_t ldh, double* __restrict__ scal) {
+           const double* __restrict__ partials, int nparts, int32_t j, int32_t ldh, double* __restrict__ scal, double* __restrict__ hostout) {
   __shared__ double red[kKT / 64];
   __shared__ double s_col[kMaxRestart + 1], s_cs[kMaxRestart], s_sn[kMaxRestart];
   double* col = H + (int64_t)j * ldh;
@@ -180,6 +180,12 @@ k_finalize(double* __restrict__ H, double* __restrict__ g, double* __restrict__ 
   g[j] = c * g[j];
   scal[0] = hn;
   scal[1] = fabs(g[j + 1]);
+  if (hostout) {
+    // the host reads these after an event recorded behind this kernel
+    hostout[0] = hn;
+    hostout[1] = fabs(g[j + 1]);
+    __threadfence_system();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -586,8 +592,8 @@ void launch_mgs_step(double* w, const double* vi, const double* vnext, int32_t n
   k_mgs_step<<<krylov_grid(n), kKT, 0, s>>>(w, vi, vnext, n, pin, pout, h_out, nparts);
 }
 void launch_finalize(double* H, double* g, double* cs, double* sn, const double* partials, int nparts, int32_t j,
-                     int32_t ldh, double* scal, hipStream_t s) {
-  k_finalize<<<1, kKT, 0, s>>>(H, g, cs, sn, partials, nparts, j, ldh, scal);
+                     int32_t ldh, double* scal, double* hostout, hipStream_t s) {
+  k_finalize<<<1, kKT, 0, s>>>(H, g, cs, sn, partials, nparts, j, ldh, scal, hostout);
 }
 int cgs_parts(int32_t n) { return cgs_grid(n); }
 void launch_spmv_dots(const int32_t* rowptr, const int32_t* colidx, const double* vals, const double* z, double* w,
