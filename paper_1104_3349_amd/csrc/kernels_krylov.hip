@@ -196,7 +196,7 @@ k_finalize(double* __restrict__ H, double* __restrict__ g, double* __restrict__ 
 // workgroup] receives the workgroup's sum in a fixed order.
 // ---------------------------------------------------------------------------
 constexpr int kDotChunk = 16;  // basis vectors per round: independent loads, then interleaved reductions
-constexpr int kCgsRows = 2;    // rows per thread held in registers by the CGS2 kernels
+constexpr int kCgsRows = 1;    // rows per thread held in registers by the CGS2 kernels (more workgroups in flight)
 
 // Grid of the CGS2 kernels: kCgsRows rows per thread, at most kMaxParts
 // workgroups (rows beyond that on a grid-stride tail).
