@@ -1,6 +1,7 @@
 // Apply kernels: Algorithm 2, x = B^{-1} y in the permuted numbering.
 //
-//   interior solve   z1 = D^{-1} y1           (one workgroup per subdomain)
+//   interior solve   z1 = D^{-1} y1           (one workgroup per subdomain, or
+//                                               per chunk of it: see below)
 //   interface solve  x2 = Shat^{-1}(y2 - F z1) (one workgroup per aggregate)
 //   interior solve   x1 = z1 - D^{-1} (E x2)   (E x2 formed in a first pass)
 //
@@ -324,13 +325,13 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
 // with g_c the zero-carry carry out of chunk c, f_c the first block of x0_c,
 // X_c / T_c the response of chunk c's outputs / carry out to a unit carry in,
 // Y_c / Yt_c that of its outputs / first block to a unit state above.  The
-// products over chunk ranges are themselves responses (a sweep over the range
-// from a unit carry or state) and are stored side by side, so each chunk
-// finds its carry and state with one GEMV instead of a chain of dependent
-// ones.  They are swept once per factorisation (mode 3, one workgroup per
-// chunk range and unit).  Three launches per solve: zero-carry lower chunks;
-// carry, lower correction and zero-state upper chunk; state, upper correction
-// and output.
+// single-chunk responses are swept once per factorisation (mode 3, one
+// workgroup per chunk and unit); the products over chunk ranges follow from
+// them by small GEMMs (k_chunk_products) and are stored side by side, so each
+// chunk finds its carry and state with one GEMV instead of a chain of
+// dependent ones.  Three launches per solve: zero-carry lower chunks; carry,
+// lower correction and zero-state upper chunk; state, upper correction and
+// output.
 //   LP_c = [T_{c-1}, T_{c-1}T_{c-2}, ..., T_{c-1}...T_1]   KL x (c-1) KL
 //   UP_c = [R_{c+1}, R_{c+1}R_{c+2}, ..., R_{c+1}...R_{p-2}]
 // The state above chunk c reaches it only through the nonzero columns of the
