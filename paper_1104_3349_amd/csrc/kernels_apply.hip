@@ -340,6 +340,12 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
 // the upper responses are taken only for those ns_c columns nz_c, the state
 // s_c is carried only in them, Y_c is rows_c x ns_c, and R_c = Yt_c(nz_{c-1}, :)
 // is ns_{c-1} x ns_c (UP_c: ns_c x (ns_{c+1} + ... + ns_{p-2})).
+// Likewise a carry position at a lower boundary is "pure" when its value is
+// still one raw input (its row of every block matrix it passed is zero, and
+// it entered the window as an input): the chunk starts it from that input
+// (prow), and only the other nsl_c positions np_c are corrected, so d_c, X_c
+// (rows_c x nsl_c), T_c and LP_c (nsl_c x (nsl_1 + ... + nsl_{c-1})) live on
+// them.
 // ---------------------------------------------------------------------------
 struct ChunkArgs {
   int32_t p, klmax, stk;  // chunks, carry stride, LDS words of the stacked recurrence vector
@@ -353,10 +359,13 @@ struct ChunkArgs {
   double* uin;         // mode 1: the sweep input E x2, padded interior numbering
   const int32_t* nz;   // coupling columns nz_c of every (subdomain, boundary c) ...
   const int32_t* nzo;  // ... at nz[nzo[j p + c] .. nzo[j p + c + 1])
+  const int32_t* prow; // lower boundary c: input row of each pure carry position, else -1 (klmax each)
+  const int32_t* np;   // coupled carry positions np_c of every (subdomain, boundary c) ...
+  const int32_t* npo;  // ... at np[npo[j p + c] .. npo[j p + c + 1]) (empty for c = 0)
   const int32_t* job;  // mode 3: (subdomain, first chunk, end chunk, unit) per workgroup
 };
 
-__device__ inline int32_t chunk_ub(int32_t nU, int32_t p, int32_t c) { return (int32_t)((int64_t)nU * c / p); }
+__host__ __device__ inline int32_t chunk_ub(int32_t nU, int32_t p, int32_t c) { return (int32_t)((int64_t)nU * c / p); }
 
 // Lower chunks.  mode 0: input yin; mode 1: input E x2 (each chunk forms the
 // rows it reads); mode 3: the response of chunks [c, ce) to the unit carry
@@ -399,10 +408,26 @@ k_chunk_lower(SweepArgs a, ChunkArgs ca, const double* __restrict__ yin, int mod
     __syncthreads();
   }
   auto input = [&](int32_t row) -> double { return (mode == 3 || row >= n) ? 0.0 : src[row]; };
+  // a pure carry position starts from its input row (mode 1: E x2 formed here,
+  // the row may belong to the previous chunk)
+  auto pure_input = [&](int32_t row) -> double {
+    if (row < 0 || row >= n) return 0.0;
+    if (mode == 0) return yin[ioff + row];
+    double s = 0.0;
+    for (int32_t e = a.e_rowptr[ioff + row]; e < a.e_rowptr[ioff + row + 1]; ++e) s += a.e_vals[e] * x2[a.e_colidx[e]];
+    return s;
+  };
+  const int32_t* prow = ca.prow + ((int64_t)j * ca.p + c) * ca.klmax;
+  const int32_t o_c = ca.npo[(int64_t)j * ca.p + c];
   double* wc = wA;
   double* wn = wB;
-  for (int32_t r = tid; r < W; r += blockDim.x)
-    wc[r] = (c == 0 || r >= KL) ? input(r0 + r) : (r == unit ? 1.0 : 0.0);
+  for (int32_t r = tid; r < W; r += blockDim.x) {
+    double v;
+    if (c == 0 || r >= KL) v = input(r0 + r);
+    else if (mode == 3) v = r == ca.np[o_c + unit] ? 1.0 : 0.0;
+    else v = pure_input(prow[r]);
+    wc[r] = v;
+  }
   __syncthreads();
   double* ypad = a.ypad + voff;
   T* X = (mode == 3 && ce == c + 1) ? (T*)ca.lx + ca.off[4 * ((int64_t)j * ca.p + c)] + (int64_t)unit * rows : nullptr;
@@ -430,15 +455,16 @@ k_chunk_lower(SweepArgs a, ChunkArgs ca, const double* __restrict__ yin, int mod
     wc = wn;
     wn = tmp;
   }
-  // the carry out of the chunk (the first KL entries of the next window)
-  if (mode == 3) {
-    if (ce < ca.p) {
-      // block ce - 1 - c of LP_ce, column `unit`
-      T* L = (T*)ca.lp + ca.off[4 * ((int64_t)j * ca.p + ce) + 1] + ((int64_t)(ce - 1 - c) * KL + unit) * KL;
-      for (int32_t r = tid; r < KL; r += blockDim.x) L[r] = (T)wc[r];
+  // the carry out of the chunk on the coupled positions of the next boundary
+  if (ce < ca.p) {
+    const int32_t o1 = ca.npo[(int64_t)j * ca.p + ce], n1 = ca.npo[(int64_t)j * ca.p + ce + 1] - o1;
+    if (mode == 3) {
+      // column `unit` of T_c (block 0 of LP_{c+1}: n1 rows)
+      T* L = (T*)ca.lp + ca.off[4 * ((int64_t)j * ca.p + ce) + 1] + (int64_t)unit * n1;
+      for (int32_t k = tid; k < n1; k += blockDim.x) L[k] = (T)wc[ca.np[o1 + k]];
+    } else {
+      for (int32_t k = tid; k < n1; k += blockDim.x) ca.cz[((int64_t)j * ca.p + c) * ca.klmax + k] = wc[ca.np[o1 + k]];
     }
-  } else if (c + 1 < ca.p) {
-    for (int32_t r = tid; r < KL; r += blockDim.x) ca.cz[((int64_t)j * ca.p + c) * ca.klmax + r] = wc[r];
   }
 }
 
@@ -457,7 +483,7 @@ k_chunk_upper(SweepArgs a, ChunkArgs ca, int mode) {
   const int32_t unit = mode == 3 ? ca.job[4 * jb + 3] : -1;
   const SubInfo q = a.subs[j];
   if (q.n == 0) return;
-  const int32_t voff = q.vec_off, KL = q.kl, nbU = q.nbu, KV = q.kl + q.ku, nU = q.npad / nbU;
+  const int32_t voff = q.vec_off, nbU = q.nbu, KV = q.kl + q.ku, nU = q.npad / nbU;
   const int32_t u0 = chunk_ub(nU, ca.p, c), u1 = chunk_ub(nU, ca.p, ce);
   const int32_t r0 = u0 * nbU, rows = (u1 - u0) * nbU;
   const int tid = threadIdx.x;
@@ -473,28 +499,33 @@ k_chunk_upper(SweepArgs a, ChunkArgs ca, int mode) {
   const Geo gu = make_geo<S>(nbU, nbU);
   const bool state_in = mode == 3;
   Chunk<T, S> A, B;
-  if (mode != 3 && c >= 1) {
+  const int32_t* zl = ca.npo + (int64_t)j * ca.p;  // coupled carry positions per boundary
+  const int32_t nsl = zl[c + 1] - zl[c];
+  if (mode != 3 && c >= 1 && nsl > 0) {
     const double* cz = ca.cz + (int64_t)j * ca.p * ca.klmax;
-    const Geo gx = make_geo<S>(rows, KL);
+    const Geo gx = make_geo<S>(rows, nsl);
     const T* X = (const T*)ca.lx + off[0];
-    if (c >= 2) {
+    // K = nsl_1 + ... + nsl_{c-1}: block i of LP_c takes g_{c-2-i} (boundary c-1-i)
+    const int32_t K = zl[c] - zl[1];
+    if (c >= 2 && K > 0) {
       // d_c = g_{c-1} + LP_c [g_{c-2}; ...; g_0]
-      const int32_t K = (c - 1) * KL;
-      const Geo gp = make_geo<S>(KL, K);
+      const Geo gp = make_geo<S>(nsl, K);
       const T* LP = (const T*)ca.lp + off[1];
       prefetch_gemv<T, S, 0, false>(A, B, gp, LP, 0, nullptr);
       for (int32_t e = tid; e < K; e += blockDim.x) {
-        const int32_t i = e / KL, r = e - i * KL;
-        stk[e] = cz[(int64_t)(c - 2 - i) * ca.klmax + r];
+        // entries of boundary bb occupy [zl[c] - zl[bb + 1], zl[c] - zl[bb])
+        int32_t bb = c - 1;
+        while (e >= zl[c] - zl[bb]) --bb;
+        stk[e] = cz[(int64_t)(bb - 1) * ca.klmax + (e - (zl[c] - zl[bb + 1]))];
       }
       __syncthreads();
       const int CG = run_gemv<T, S, 0, false>(A, B, gp, LP, 0, nullptr, stk, part);
       prefetch_gemv<T, S, 0, false>(A, B, gx, X, 0, nullptr);
       __syncthreads();
-      for (int32_t r = tid; r < KL; r += blockDim.x) dv[r] = cz[(int64_t)(c - 1) * ca.klmax + r] + sum_parts(part, KL, CG, r);
+      for (int32_t r = tid; r < nsl; r += blockDim.x) dv[r] = cz[(int64_t)(c - 1) * ca.klmax + r] + sum_parts(part, nsl, CG, r);
     } else {
       prefetch_gemv<T, S, 0, false>(A, B, gx, X, 0, nullptr);
-      for (int32_t r = tid; r < KL; r += blockDim.x) dv[r] = cz[r];
+      for (int32_t r = tid; r < nsl; r += blockDim.x) dv[r] = cz[(int64_t)(c - 1) * ca.klmax + r];
     }
     __syncthreads();
     // y_c += X_c d_c
@@ -609,24 +640,25 @@ k_chunk_fix(SweepArgs a, ChunkArgs ca, int mode, double* out, const double* z1) 
 // One level of the product responses, for every subdomain: P_c(:, w0 ..) =
 // P_c(:, 0 .. w0) P_nx, with P_c(:, 0 .. w0) the single-chunk block
 // (upper: P = UP, nx = c + 1, rows ns_c, w0 = ns_{c+1}, P_nx ns_{c+1} x K_{c+1};
-// lower: P = LP, nx = c - 1, rows KL, w0 = KL, P_nx KL x (c - 2) KL).  FP64
-// accumulation, one thread per output entry.
+// lower: P = LP, nx = c - 1, rows nsl_c, w0 = nsl_{c-1}, P_nx nsl_{c-1} x
+// (nsl_1 + ... + nsl_{c-2})).  FP64 accumulation, one thread per output entry.
 template <class T>
 __global__ void k_chunk_products(const SubInfo* __restrict__ subs, const int64_t* __restrict__ off,
-                                 const int32_t* __restrict__ nzo, int32_t p, int32_t c, int upper, T* P) {
+                                 const int32_t* __restrict__ cnt, int32_t p, int32_t c, int upper, T* P) {
   const int32_t j = blockIdx.y;
   const SubInfo q = subs[j];
   if (q.n == 0) return;
+  const int32_t* z = cnt + (int64_t)j * p;  // upper: coupling columns; lower: coupled carry positions
   int32_t rows, w0, cols, nx;
   if (upper) {
-    const int32_t* z = nzo + (int64_t)j * p;
     rows = z[c + 1] - z[c];
     w0 = z[c + 2] - z[c + 1];
     cols = z[p - 1] - z[c + 2];
     nx = c + 1;
   } else {
-    rows = w0 = q.kl;
-    cols = (c - 2) * q.kl;
+    rows = z[c + 1] - z[c];
+    w0 = z[c] - z[c - 1];
+    cols = z[c - 1] - z[1];
     nx = c - 1;
   }
   const int64_t total = (int64_t)rows * cols;
@@ -661,6 +693,23 @@ __global__ void k_chunk_nzcols(const SubInfo* __restrict__ subs, const T* __rest
     bool nzc = false;
     for (int32_t r = 0; r < nbU && !nzc; ++r) nzc = M[(int64_t)k * nbU + r] != T(0);
     f[k] = nzc ? 1 : 0;
+  }
+}
+
+// Zero rows of the lower block matrices: flags[blk * klmax + r] = 1 if row
+// nbl + r of block blk's [inv(L11); L21 inv(L11)] is zero (its carry entry
+// passes through the block unchanged).
+template <class T>
+__global__ void k_lower_zero_rows(const LBlk* __restrict__ lb, const SubInfo* __restrict__ subs,
+                                  const T* __restrict__ lmat, int32_t klmax, uint8_t* __restrict__ flags) {
+  const LBlk L = lb[blockIdx.x];
+  const SubInfo q = subs[L.sub];
+  const int32_t nbL = q.nbl, W = nbL + q.kl;
+  const T* M = lmat + L.moff;
+  for (int32_t r = threadIdx.x; r < q.kl; r += blockDim.x) {
+    bool zero = true;
+    for (int32_t k = 0; k < nbL && zero; ++k) zero = M[(int64_t)k * W + nbL + r] == T(0);
+    flags[(int64_t)blockIdx.x * klmax + r] = zero ? 1 : 0;
   }
 }
 
@@ -875,6 +924,9 @@ static ChunkArgs chunk_args(const addns_precond* pc) {
   ca.uin = pc->ch_uin.as<double>();
   ca.nz = pc->ch_nz.as<int32_t>();
   ca.nzo = pc->ch_nzo.as<int32_t>();
+  ca.prow = pc->ch_prow.as<int32_t>();
+  ca.np = pc->ch_np.as<int32_t>();
+  ca.npo = pc->ch_npo.as<int32_t>();
   return ca;
 }
 
@@ -905,7 +957,7 @@ void release_chunked_sweep(addns_precond* pc) {
   pc->sweep_chunks = 1;
   pc->chunk_bytes = 0;
   for (DevBuf* d : {&pc->ch_off, &pc->ch_lx, &pc->ch_lp, &pc->ch_uy, &pc->ch_up, &pc->ch_cz, &pc->ch_xs, &pc->ch_uin,
-                    &pc->ch_nz, &pc->ch_nzo})
+                    &pc->ch_nz, &pc->ch_nzo, &pc->ch_prow, &pc->ch_np, &pc->ch_npo})
     d->reset();
 }
 
@@ -946,24 +998,87 @@ void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
           if (flags[((size_t)j * p + c) * pl.nbU + k]) nz.push_back(k);
     }
   nzo[(size_t)m * p] = (int32_t)nz.size();
+  // pure carry positions at every lower chunk boundary: follow each window
+  // position through the blocks (gather indices and zero rows of the block
+  // matrices, from the stored factors)
+  const int32_t nlb = (int32_t)pl.lblks.size();
+  std::vector<uint8_t> zrow((size_t)std::max(nlb, 1) * klmax, 0);
+  std::vector<int32_t> h_lperm((size_t)std::max<int64_t>(pl.lperm_total, 1));
+  {
+    DevBuf d_z;
+    d_z.alloc(zrow.size());
+    if (nlb > 0) {
+      if (pc->interior_prec == P64)
+        k_lower_zero_rows<double><<<nlb, 256, 0, s>>>(pc->lblks.as<LBlk>(), pc->subs.as<SubInfo>(), pc->lmat.as<double>(),
+                                                      klmax, d_z.as<uint8_t>());
+      else
+        k_lower_zero_rows<float><<<nlb, 256, 0, s>>>(pc->lblks.as<LBlk>(), pc->subs.as<SubInfo>(), pc->lmat.as<float>(),
+                                                     klmax, d_z.as<uint8_t>());
+      ADDNS_HIP(hipMemcpyAsync(zrow.data(), d_z.p, zrow.size(), hipMemcpyDeviceToHost, s));
+    }
+    if (pl.lperm_total > 0)
+      ADDNS_HIP(hipMemcpyAsync(h_lperm.data(), pc->lperm.p, sizeof(int32_t) * pl.lperm_total, hipMemcpyDeviceToHost, s));
+    ADDNS_HIP(hipStreamSynchronize(s));
+  }
+  std::vector<int32_t> prow((size_t)m * p * klmax, -1), np, npo((size_t)m * p + 1, 0);
+  for (int32_t j = 0; j < m; ++j) {
+    const SubInfo& q = pl.subs[j];
+    std::vector<std::vector<int32_t>> lists(p);
+    if (q.n > 0) {
+      const int32_t KL = q.kl, nbL = q.nbl, W = nbL + KL, nU = q.npad / q.nbu, nL = q.npad / nbL;
+      std::vector<uint8_t> pure(KL, 1), npure(KL);
+      std::vector<int32_t> row(KL), nrow(KL);
+      for (int32_t r = 0; r < KL; ++r) row[r] = r;
+      int32_t cnext = 1;
+      for (int32_t b = 0; b <= nL; ++b) {
+        // at chunk boundary c (block 2 u_c) record the state before block b
+        while (cnext < p && 2 * chunk_ub(nU, p, cnext) == b) {
+          for (int32_t r = 0; r < KL; ++r) {
+            if (pure[r]) prow[((size_t)j * p + cnext) * klmax + r] = row[r];
+            else lists[cnext].push_back(r);
+          }
+          ++cnext;
+        }
+        if (b == nL) break;
+        const LBlk& L = pl.lblks[(size_t)q.lblk0 + b];
+        const uint8_t* zr = &zrow[((size_t)q.lblk0 + b) * klmax];
+        for (int32_t r = 0; r < KL; ++r) {
+          const int32_t pos = h_lperm[(size_t)L.poff + nbL + r];
+          if (pos < 0 || pos >= W) throw HipError("lower gather index out of range");
+          const bool src_pure = pos >= KL ? true : pure[pos] != 0;
+          npure[r] = (zr[r] && src_pure) ? 1 : 0;
+          nrow[r] = pos >= KL ? b * nbL + pos : row[pos];
+        }
+        pure.swap(npure);
+        row.swap(nrow);
+      }
+    }
+    for (int32_t c = 0; c < p; ++c) {
+      npo[(size_t)j * p + c] = (int32_t)np.size();
+      np.insert(np.end(), lists[c].begin(), lists[c].end());
+    }
+  }
+  npo[(size_t)m * p] = (int32_t)np.size();
   std::vector<int64_t> off((size_t)4 * m * p, 0);
   std::vector<int32_t> jl, ju;
   int64_t nlx = 0, nlp = 0, nuy = 0, nup = 0;
   for (int32_t j = 0; j < m; ++j) {
     const SubInfo& q = pl.subs[j];
     if (q.n == 0) continue;
-    const int32_t nU = q.npad / q.nbu, KL = q.kl, nbU = q.nbu;
+    const int32_t nU = q.npad / q.nbu, nbU = q.nbu;
+    const int32_t* zl = &npo[(size_t)j * p];
     for (int32_t c = 0; c < p; ++c) {
       const int32_t rows = (int32_t)(((int64_t)nU * (c + 1) / p - (int64_t)nU * c / p) * nbU);
       if (rows > 1024 * S) throw ArgError("sweep chunk too tall for the chunk kernels' GEMVs");
       int64_t* o = &off[(size_t)4 * ((int64_t)j * p + c)];
+      const int32_t nsl = zl[c + 1] - zl[c];
       if (c >= 1) {
         o[0] = nlx;
-        nlx += (int64_t)rows * KL;
+        nlx += (int64_t)rows * nsl;
       }
       if (c >= 2) {
         o[1] = nlp;
-        nlp += (int64_t)KL * (c - 1) * KL;
+        nlp += (int64_t)nsl * (zl[c] - zl[1]);
       }
       const int32_t* z = &nzo[(size_t)j * p];
       if (c + 1 < p) {
@@ -979,29 +1094,56 @@ void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
     // upper c <= p - 2 (Y_c, and Yt_c into block 0 of UP_{c-1}); the longer
     // products follow from them (k_chunk_products)
     for (int32_t c = 1; c < p; ++c)
-      for (int32_t u = 0; u < KL; ++u) jl.insert(jl.end(), {j, c, c + 1, u});
+      for (int32_t u = 0; u < npo[(size_t)j * p + c + 1] - npo[(size_t)j * p + c]; ++u) jl.insert(jl.end(), {j, c, c + 1, u});
     for (int32_t c = 0; c + 1 < p; ++c)
       for (int32_t u = 0; u < nzo[(size_t)j * p + c + 1] - nzo[(size_t)j * p + c]; ++u)
         ju.insert(ju.end(), {j, c, c + 1, u});
   }
+  // Every buffer is sized for the largest structure the plan admits (all nbu
+  // columns coupled, no pure carry position), which depends on the plan and
+  // p only: a refactor whose factors couple other columns or rows rebuilds
+  // into the same allocations, so an apply captured before it stays valid.
+  int64_t cap_nz = 0, cap_np = 0, cap[4] = {0, 0, 0, 0};
+  for (const SubInfo& q : pl.subs) {
+    if (q.n == 0) continue;
+    const int64_t nU = q.npad / q.nbu, kl = q.kl, nb = q.nbu;
+    cap_nz += (int64_t)(p - 1) * nb;
+    cap_np += (int64_t)(p - 1) * kl;
+    for (int32_t c = 0; c < p; ++c) {
+      const int64_t rows = (nU * (c + 1) / p - nU * c / p) * nb;
+      if (c >= 1) cap[0] += rows * kl;
+      if (c >= 2) cap[1] += kl * (c - 1) * kl;
+      if (c + 1 < p) cap[2] += rows * nb;
+      if (c + 2 < p) cap[3] += nb * (p - 2 - c) * nb;
+    }
+  }
+  const int64_t cnt[4] = {nlx, nlp, nuy, nup};
+  if ((int64_t)nz.size() > cap_nz || (int64_t)np.size() > cap_np || nlx > cap[0] || nlp > cap[1] || nuy > cap[2] ||
+      nup > cap[3])
+    throw HipError("chunked sweep structure exceeds its plan bound");
+  nz.resize((size_t)cap_nz, 0);
+  np.resize((size_t)cap_np, 0);
   pc->sweep_chunks = p;
   pc->ch_klmax = klmax;
   pc->chunk_bytes = (int64_t)fb * (nlx + nlp + nuy + nup);
   pc->ch_off.upload(off, s);
   // the chunk GEMVs' last row slot may read up to 64 * 5 rows past a
-  // matrix; the zeroed tail keeps that overrun inside the allocation
+  // matrix; the zeroed rest of the allocation (unused capacity and a tail)
+  // keeps that overrun inside it
   const int64_t tail = kSweepOverrunBytes;
   DevBuf* mats[4] = {&pc->ch_lx, &pc->ch_lp, &pc->ch_uy, &pc->ch_up};
-  const int64_t cnt[4] = {nlx, nlp, nuy, nup};
   for (int i = 0; i < 4; ++i) {
-    mats[i]->alloc((size_t)(fb * cnt[i] + tail));
-    ADDNS_HIP(hipMemsetAsync(static_cast<char*>(mats[i]->p) + mats[i]->bytes - tail, 0, tail, s));
+    mats[i]->alloc((size_t)(fb * cap[i] + tail));
+    ADDNS_HIP(hipMemsetAsync(static_cast<char*>(mats[i]->p) + fb * cnt[i], 0, mats[i]->bytes - fb * cnt[i], s));
   }
   pc->ch_cz.alloc(sizeof(double) * (size_t)m * p * klmax);
   pc->ch_xs.alloc(sizeof(double) * (size_t)std::max<int64_t>(pl.npad_total, 1));
   pc->ch_uin.alloc(sizeof(double) * (size_t)std::max<int64_t>(pl.npad_total, 1));
   pc->ch_nz.upload(nz, s);
   pc->ch_nzo.upload(nzo, s);
+  pc->ch_prow.upload(prow, s);
+  pc->ch_np.upload(np, s);
+  pc->ch_npo.upload(npo, s);
   DevBuf d_jl, d_ju;
   d_jl.upload(jl, s);
   d_ju.upload(ju, s);
@@ -1032,9 +1174,13 @@ void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
           pc->subs.as<SubInfo>(), pc->ch_off.as<int64_t>(), pc->ch_nzo.as<int32_t>(), p, c, 1, (T*)pc->ch_up.p);
     }
     for (int32_t c = 3; c < p; ++c) {
-      const int64_t tot = (int64_t)klmax * (c - 2) * klmax;
+      int64_t tot = 1;
+      for (int32_t j = 0; j < m; ++j) {
+        const int32_t* zl = &npo[(size_t)j * p];
+        tot = std::max<int64_t>(tot, (int64_t)(zl[c + 1] - zl[c]) * (zl[c - 1] - zl[1]));
+      }
       k_chunk_products<T><<<dim3((unsigned)((tot + 255) / 256), m), 256, 0, s>>>(
-          pc->subs.as<SubInfo>(), pc->ch_off.as<int64_t>(), pc->ch_nzo.as<int32_t>(), p, c, 0, (T*)pc->ch_lp.p);
+          pc->subs.as<SubInfo>(), pc->ch_off.as<int64_t>(), pc->ch_npo.as<int32_t>(), p, c, 0, (T*)pc->ch_lp.p);
     }
   });
   ADDNS_HIP(hipGetLastError());

@@ -192,6 +192,7 @@ struct addns_precond {
   addns::DevBuf ch_off, ch_lx, ch_lp, ch_uy, ch_up;   // offsets (int64) and response matrices
   addns::DevBuf ch_cz, ch_xs, ch_uin;                 // zero-state carries and upper outputs, E x2
   addns::DevBuf ch_nz, ch_nzo;                        // coupling columns of the chunk boundaries
+  addns::DevBuf ch_prow, ch_np, ch_npo;               // pure carry rows and coupled carry positions
   addns::DevBuf g_copy;                               // G blocks before the update (learning targets S - G)
   addns::DevBuf smp_row, smp_nb, smp_loc;             // learned-correction sample table
   // GMRES work space (grown on demand)

@@ -22,6 +22,7 @@ import numpy as np
 import pytest
 
 from tests.gpu_systems import gpu_precond, make_system, oracle_precond, relerr
+from workloads.mac_oseen import Wind
 
 torch = pytest.importorskip("torch")
 from paper_1104_3349_amd import addns  # noqa: E402
@@ -177,3 +178,38 @@ def test_chunked_apply_captured_in_graph_replays_exactly():
         torch.cuda.synchronize()
         assert np.array_equal(got, ref.cpu().numpy()), rep
         x.zero_()
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_chunked_refactor_keeps_a_captured_apply_valid(p):
+    """The chunk structure (coupling columns and carry positions) follows the
+    factor values, so a refactor with another wind may change it; every chunk
+    buffer is sized for the plan's largest structure, so the apply captured
+    before the refactor replays with the new factors and structure."""
+    S1 = make_system(**CASES["mid"])
+    S2 = make_system(**CASES["mid"], wind=Wind((0.3, -1.0, 0.5, 2.0), 1.5))
+    _, pc = gpu_precond(S1, iprec=addns.F32, sprec=addns.F32, sweep_chunks=p)
+    bytes1 = pc.info()["chunk_bytes"]
+    y = _cuda(np.random.default_rng(13).standard_normal(S1.N))
+    x = torch.zeros_like(y)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        addns.apply_precond(pc, y, x)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        addns.apply_precond(pc, y, x)
+    torch.cuda.synchronize()
+    addns.refactor_precond(pc, _cuda(S1.rp), _cuda(S1.ci), _cuda(S2.v))
+    torch.cuda.synchronize()
+    assert pc.info()["sweep_chunks"] == p
+    # the new wind couples other positions: the structure did change
+    assert pc.info()["chunk_bytes"] != bytes1
+    want = _apply(pc, y.cpu().numpy())
+    for rep in range(3):
+        x.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), want), rep
