@@ -619,9 +619,10 @@ int addns_gmres_solve(addns_precond_t pc, const double* d_b, double* d_x, const 
             std::swap(pin, pout);
           }
         }
-        // the estimate goes straight to pinned host memory (no copy launch)
-        launch_finalize(g.H, g.g, g.cs, g.sn, pin, pnorm_parts, j, ldh, g.scal, hbuf_dev + 2 * (j & 1), s);
-        launch_scale_copy(g.w, g.V + (int64_t)(j + 1) * N, g.scal, 0, N, s);
+        // the estimate goes straight to pinned host memory (no copy launch);
+        // the same launch scales w into v_{j+1}
+        launch_finalize(g.H, g.g, g.cs, g.sn, pin, pnorm_parts, j, ldh, g.scal, hbuf_dev + 2 * (j & 1), g.w,
+                        g.V + (int64_t)(j + 1) * N, N, s);
         ADDNS_HIP(hipEventRecord(ev.e[j & 1], s));
       };
       // true: the cycle stops after iteration j

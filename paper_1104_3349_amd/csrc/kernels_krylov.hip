@@ -138,25 +138,33 @@ k_mgs_step(double* __restrict__ w, const double* __restrict__ vi, const double* 
 
 // h_{j+1,j} = ||w||; rotations 0..j-1 applied to column j of H; rotation j
 // from (h_jj, h_{j+1,j}) with t = hypot(a, b), c = a/t, s = b/t (b = 0 gives
-// c = 1, s = 0); g_{j+1} = -s g_j, g_j = c g_j.
-// scal[0] = h_{j+1,j}, scal[1] = |g_{j+1}|.
+// c = 1, s = 0); g_{j+1} = -s g_j, g_j = c g_j; and the next basis vector
+// v_{j+1} = w / h_{j+1,j} (an unchanged copy when the norm is zero).
+// Every workgroup reduces the norm partials itself (the same fixed order,
+// so the same value) and scales its rows; workgroup 0 also updates H, the
+// rotations and g.  scal[0] = h_{j+1,j}, scal[1] = |g_{j+1}|.
 __global__ void __launch_bounds__(kKT)
 k_finalize(double* __restrict__ H, double* __restrict__ g, double* __restrict__ cs, double* __restrict__ sn,
-           const double* __restrict__ partials, int nparts, int32_t j, int32_t ldh, double* __restrict__ scal, double* __restrict__ hostout) {
+           const double* __restrict__ partials, int nparts, int32_t j, int32_t ldh, double* __restrict__ scal,
+           double* __restrict__ hostout, const double* __restrict__ w, double* __restrict__ v, int32_t n) {
   __shared__ double red[kKT / 64];
   __shared__ double s_col[kMaxRestart + 1], s_cs[kMaxRestart], s_sn[kMaxRestart];
+  const bool lead = blockIdx.x == 0;
   double* col = H + (int64_t)j * ldh;
   // stage column j and the rotations in LDS (parallel loads that overlap the
   // reduction), so the serial rotation loop below reads no global memory
-  for (int32_t i = threadIdx.x; i <= j; i += blockDim.x) {
-    s_col[i] = col[i];
-    if (i < j) {
-      s_cs[i] = cs[i];
-      s_sn[i] = sn[i];
+  if (lead)
+    for (int32_t i = threadIdx.x; i <= j; i += blockDim.x) {
+      s_col[i] = col[i];
+      if (i < j) {
+        s_cs[i] = cs[i];
+        s_sn[i] = sn[i];
+      }
     }
-  }
   const double hn = sqrt(reduce_parts(partials, nparts, red));  // synchronises the block
-  if (threadIdx.x != 0) return;
+  const int32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row < n) v[row] = hn != 0.0 ? w[row] / hn : w[row];
+  if (!lead || threadIdx.x != 0) return;
   for (int32_t i = 0; i < j; ++i) {
     double t = s_cs[i] * s_col[i] + s_sn[i] * s_col[i + 1];
     s_col[i + 1] = -s_sn[i] * s_col[i] + s_cs[i] * s_col[i + 1];
@@ -592,8 +600,9 @@ void launch_mgs_step(double* w, const double* vi, const double* vnext, int32_t n
   k_mgs_step<<<krylov_grid(n), kKT, 0, s>>>(w, vi, vnext, n, pin, pout, h_out, nparts);
 }
 void launch_finalize(double* H, double* g, double* cs, double* sn, const double* partials, int nparts, int32_t j,
-                     int32_t ldh, double* scal, double* hostout, hipStream_t s) {
-  k_finalize<<<1, kKT, 0, s>>>(H, g, cs, sn, partials, nparts, j, ldh, scal, hostout);
+                     int32_t ldh, double* scal, double* hostout, const double* w, double* v, int32_t n,
+                     hipStream_t s) {
+  k_finalize<<<std::max(1u, nb(n, kKT)), kKT, 0, s>>>(H, g, cs, sn, partials, nparts, j, ldh, scal, hostout, w, v, n);
 }
 int cgs_parts(int32_t n) { return cgs_grid(n); }
 void launch_spmv_dots(const int32_t* rowptr, const int32_t* colidx, const double* vals, const double* z, double* w,

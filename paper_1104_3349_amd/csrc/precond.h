@@ -276,7 +276,8 @@ void launch_cgs_update(double* w, const double* V, int nvec, const double* h, in
 void launch_mgs_step(double* w, const double* vi, const double* vnext, int32_t n, const double* partials_in,
                      double* partials_out, double* h_out, int nparts, hipStream_t s);
 void launch_finalize(double* H, double* g, double* cs, double* sn, const double* partials, int nparts,
-                     int32_t j, int32_t ldh, double* scal, double* hostout, hipStream_t s);
+                     int32_t j, int32_t ldh, double* scal, double* hostout, const double* w, double* v,
+                     int32_t n, hipStream_t s);
 void launch_scale_copy(const double* w, double* v, const double* scal, int idx, int32_t n, hipStream_t s);
 void launch_norm_finalize(const double* partials, int nparts, double* scal, int idx, hipStream_t s);
 void launch_backsolve(const double* H, const double* g, int32_t j, int32_t ldh, double* y, hipStream_t s);
