@@ -210,7 +210,7 @@ def bench_learned(args):
     import torch
 
     from paper_1104_3349_amd import addns, learned
-    from workloads.configs import CFG5, F32, Workload, training_workloads
+    from workloads.configs import CAVITY512_STRETCHED, F32, Workload, training_workloads
 
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
@@ -221,7 +221,7 @@ def bench_learned(args):
     t2 = time.perf_counter()
     held = Workload("uniform64_nu0.002_m4_heldout", 64, 1 / 500, None, 4, 64, 50, True, 1e-8, 78, F32, F32)
     out = {}
-    for wl, maxit in ((held, 5000), (CFG5, args.learned_maxit)):
+    for wl, maxit in ((held, 5000), (CAVITY512_STRETCHED, args.learned_maxit)):
         rp, ci, v, b, meta = wl.build()
         N = meta["N"]
         part = addns.build_partition(N, rp, ci, v, wl.m, wl.sz)
@@ -254,7 +254,7 @@ def bench_learned(args):
             if "accepted" in r:
                 res[name]["accepted"] = r["accepted"]
         out[wl.name] = res
-    e = out[CFG5.name]["learned_bf16"]
+    e = out[CAVITY512_STRETCHED.name]["learned_bf16"]
     if "seconds" not in e:
         e = {"seconds": None}
     print(json.dumps({
@@ -263,7 +263,7 @@ def bench_learned(args):
         "ms_per_step": None if e["seconds"] is None else round(e["seconds"] * 1e3, 3),
         "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64 outer / f32 factors / bf16 network", "data": "synthetic",
-        "config": {"workload": "learned512", "eval": CFG5.name, "train_systems": 2000,
+        "config": {"workload": "learned512", "eval": CAVITY512_STRETCHED.name, "train_systems": 2000,
                    "train_rows": int(X.shape[0]), "krylov": "FGMRES(50)", "maxit": args.learned_maxit},
         "data_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
         "loss_first": float(loss[0]), "loss_last": float(loss[-1]), "results": out}))
@@ -302,7 +302,7 @@ def main():
     import torch
 
     from paper_1104_3349_amd import addns
-    from workloads.configs import CFG2 as cfg
+    from workloads.configs import CAVITY128 as cfg
 
     if args.workload == "picard128":
         return bench_picard(args)

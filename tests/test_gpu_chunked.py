@@ -30,9 +30,9 @@ from paper_1104_3349_amd import addns  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 CASES = {
-    "cfg1": dict(n=16, nu=0.1, m=4, sz=64, stretch=None, seed=1001),
+    "cavity16": dict(n=16, nu=0.1, m=4, sz=64, stretch=None, seed=1001),
     "mid": dict(n=48, nu=0.005, m=6, sz=40, stretch=1.05, seed=7),
-    "cfg2": dict(n=128, nu=0.01, m=16, sz=64, stretch=None, seed=1002),
+    "cavity128": dict(n=128, nu=0.01, m=16, sz=64, stretch=None, seed=1002),
 }
 
 
@@ -101,7 +101,7 @@ def test_chunked_apply_matches_oracle(case):
 
 
 def test_chunked_gmres_iterations_unchanged():
-    S = make_system(**CASES["cfg2"])
+    S = make_system(**CASES["cavity128"])
     d_b = _cuda(S.b)
     its = {}
     for p in (1, 4):
@@ -114,7 +114,7 @@ def test_chunked_gmres_iterations_unchanged():
 
 
 def test_sweep_chunks_out_of_range():
-    S = make_system(**CASES["cfg1"])
+    S = make_system(**CASES["cavity16"])
     part, pc = gpu_precond(S, sweep_chunks=1)
     pmax = max_chunks(part, pc)
     for bad in (pmax + 1, -1):
@@ -126,7 +126,7 @@ def test_sweep_chunks_out_of_range():
 def test_auto_chunks_reported_and_exact():
     """The default (0) keeps the chunked form only where it times faster;
     either way the apply matches the oracle."""
-    S = make_system(**CASES["cfg2"])
+    S = make_system(**CASES["cavity128"])
     ora = oracle_precond(S)
     part, pc = gpu_precond(S)
     p = pc.info()["sweep_chunks"]

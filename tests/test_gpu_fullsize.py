@@ -26,7 +26,7 @@ torch = pytest.importorskip("torch")
 from oracle.partition import build_partition as oracle_partition  # noqa: E402
 from oracle.precond import MSCN, Preconditioner, row_scale  # noqa: E402
 from paper_1104_3349_amd import addns  # noqa: E402
-from workloads.configs import CFG3, CFG5  # noqa: E402
+from workloads.configs import CAVITY256_STRETCHED, CAVITY512_STRETCHED  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -38,9 +38,9 @@ def _cuda(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.fixture(scope="module", params=["cfg3", "cfg5"])
+@pytest.fixture(scope="module", params=["cavity256s", "cavity512s"])
 def full(request):
-    cfg = {"cfg3": CFG3, "cfg5": CFG5}[request.param]
+    cfg = {"cavity256s": CAVITY256_STRETCHED, "cavity512s": CAVITY512_STRETCHED}[request.param]
     rp, ci, v, b, meta = cfg.build()
     N = meta["N"]
     P = oracle_partition(N, rp, ci, v, cfg.m, cfg.sz)

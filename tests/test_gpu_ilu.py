@@ -14,9 +14,9 @@ from tests.gpu_systems import gpu_precond, make_system, oracle_precond, relerr  
 pytestmark = pytest.mark.gpu
 
 CASES = {
-    "cfg1": dict(n=16, nu=0.1, m=4, sz=64, seed=1001),
+    "cavity16": dict(n=16, nu=0.1, m=4, sz=64, seed=1001),
     "mid": dict(n=48, nu=0.005, m=6, sz=40, stretch=1.05, seed=7),
-    "cfg2": dict(n=128, nu=0.01, m=16, sz=64, seed=1002),
+    "cavity128": dict(n=128, nu=0.01, m=16, sz=64, seed=1002),
 }
 
 
@@ -32,7 +32,7 @@ def case(request):
 @pytest.mark.parametrize("tau", [1e-4, 1e-2])
 def test_ilu_interior_solve_and_entry_count(case, tau):
     name, S = case
-    if name == "cfg2" and tau == 1e-2:
+    if name == "cavity128" and tau == 1e-2:
         pytest.skip("one tolerance on the large case keeps the oracle's dense factors affordable")
     ora = oracle_precond(S, ilu_tol=tau)
     part, pc = gpu_precond(S, ilu_tol=tau)
@@ -43,7 +43,7 @@ def test_ilu_interior_solve_and_entry_count(case, tau):
     assert relerr(d_z.cpu().numpy(), ora.interior_solve(y1)) <= 1e-9
     want = sum(f.nnz() for (_, _, f) in ora.blocks)
     exact = None
-    if name != "cfg2":
+    if name != "cavity128":
         Cp = ora.C[ora.part.perm][:, ora.part.perm].tocsr()
         exact = sum(BandILU(Cp[a:b, a:b], 0.0).nnz() for (a, b, _) in ora.blocks)
     got = pc.info()["interior_nnz"]
@@ -62,7 +62,7 @@ def test_ilu_apply_and_gmres(case):
     addns.apply_precond(pc, _cuda(y), d_x)
     torch.cuda.synchronize()
     assert relerr(d_x.cpu().numpy(), ora.apply(y)) <= 1e-9
-    k = 12 if name != "cfg2" else 8
+    k = 12 if name != "cavity128" else 8
     ref = gmres(lambda x: ora.C @ x, ora.apply, ora.R * S.b, restart=5, tol=1e-300, maxit=k, flexible=True)
     d_x.zero_()
     r = addns.gmres_solve(pc, _cuda(S.b), d_x, restart=5, maxit=k, tol=1e-300, flexible=True)
@@ -87,7 +87,7 @@ def test_ilu_zero_tolerance_is_the_exact_factorisation():
 def test_ilu_mixed_precision_reaches_tolerance():
     """FP32 factors of the incomplete factorisation still reach 1e-8 on the
     128x128 workload (FGMRES(50))."""
-    S = make_system(**CASES["cfg2"])
+    S = make_system(**CASES["cavity128"])
     part, pc = gpu_precond(S, iprec=addns.F32, sprec=addns.F32, ilu_tol=1e-4)
     d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
     r = addns.gmres_solve(pc, _cuda(S.b), d_x, restart=50, maxit=5000, tol=1e-8, flexible=True)

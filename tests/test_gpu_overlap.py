@@ -14,9 +14,9 @@ from tests.gpu_systems import gpu_precond, make_system, oracle_precond, relerr  
 pytestmark = pytest.mark.gpu
 
 CASES = {
-    "cfg1": dict(n=16, nu=0.1, m=4, sz=24, seed=1001),
+    "cavity16": dict(n=16, nu=0.1, m=4, sz=24, seed=1001),
     "mid": dict(n=48, nu=0.005, m=6, sz=40, stretch=1.05, seed=7),
-    "cfg2": dict(n=128, nu=0.01, m=16, sz=64, seed=1002),
+    "cavity128": dict(n=128, nu=0.01, m=16, sz=64, seed=1002),
     "wide": dict(n=64, nu=0.01, m=8, sz=100, seed=5),   # aggregates over 64 nodes
 }
 MODES = [addns.SCHUR_MSCN, addns.SCHUR_MSCNR, addns.SCHUR_LUM]
@@ -96,7 +96,7 @@ def test_overlap_gmres_equal_iterations(case):
     name, S = case
     ora = oracle_precond(S, addns.SCHUR_MSCN, overlap=_w(S))
     part, pc = gpu_precond(S, addns.SCHUR_MSCN, overlap=_w(S))
-    k = 12 if name != "cfg2" else 8
+    k = 12 if name != "cavity128" else 8
     ref = gmres(lambda x: ora.C @ x, ora.apply, ora.R * S.b, restart=5, tol=1e-300, maxit=k, flexible=True)
     d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
     r = addns.gmres_solve(pc, _cuda(S.b), d_x, restart=5, maxit=k, tol=1e-300, flexible=True, history=True)
@@ -130,7 +130,7 @@ def test_overlap_batched_is_blockwise():
     """Concatenated systems: an extension that crosses into the next system
     meets no coupling, so each system's part equals its own overlapped apply."""
     import scipy.sparse as sp
-    systems = [make_system(**CASES["cfg1"]), make_system(**CASES["mid"])]
+    systems = [make_system(**CASES["cavity16"]), make_system(**CASES["mid"])]
     parts = [addns.build_partition(S.N, S.rp, S.ci, S.v, S.m, S.sz) for S in systems]
     cat = addns.partition_concat(parts)
     big = sp.block_diag([sp.csr_matrix((S.v, S.ci, S.rp), shape=(S.N, S.N)) for S in systems]).tocsr()
@@ -149,7 +149,7 @@ def test_overlap_batched_is_blockwise():
 
 
 def test_overlap_argument_errors():
-    S = make_system(**CASES["cfg1"])
+    S = make_system(**CASES["cavity16"])
     part = addns.build_partition(S.N, S.rp, S.ci, S.v, S.m, S.sz)
     args = (part, S.N, _cuda(S.rp), _cuda(S.ci), _cuda(S.v))
     for kw in (dict(overlap=-1), dict(overlap=4, schur=addns.SCHUR_EXACT_BJ),

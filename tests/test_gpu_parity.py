@@ -45,9 +45,9 @@ def _cuda(a):
 
 
 CASES = {
-    "cfg1": dict(n=16, nu=0.1, m=4, sz=64, stretch=None, seed=1001),
+    "cavity16": dict(n=16, nu=0.1, m=4, sz=64, stretch=None, seed=1001),
     "mid": dict(n=48, nu=0.005, m=6, sz=40, stretch=1.05, seed=7),
-    "cfg2": dict(n=128, nu=0.01, m=16, sz=64, stretch=None, seed=1002),
+    "cavity128": dict(n=128, nu=0.01, m=16, sz=64, stretch=None, seed=1002),
 }
 
 
@@ -153,7 +153,7 @@ def test_gmres_equal_iterations(case, flexible, schur, ortho):
     name, S = case
     ora = oracle_precond(S, schur)
     part, pc = gpu_precond(S, schur)
-    k = 12 if name != "cfg2" else 8
+    k = 12 if name != "cavity128" else 8
     restart = 5
     bt = ora.R * S.b
     ref = gmres(lambda x: ora.C @ x, ora.apply, bt, restart=restart, tol=1e-300, maxit=k,
@@ -170,7 +170,7 @@ def test_gmres_equal_iterations(case, flexible, schur, ortho):
 
 
 def test_gmres_converges_like_oracle():
-    S = make_system(**CASES["cfg1"])
+    S = make_system(**CASES["cavity16"])
     ora = oracle_precond(S)
     part, pc = gpu_precond(S)
     bt = ora.R * S.b
@@ -179,7 +179,7 @@ def test_gmres_converges_like_oracle():
     r = addns.gmres_solve(pc, d_b, d_x, restart=30, maxit=500, tol=1e-8, flexible=False)
     assert r["converged"] and r["true_relres"] <= 1e-8
     assert abs(r["iters"] - ref.iters) <= 1
-    MEASURED["cfg1_its"] = [r["iters"], ref.iters]
+    MEASURED["cavity16_its"] = [r["iters"], ref.iters]
     x = d_x.cpu().numpy()
     assert relerr(x, ref.x) <= 1e-6  # both at residual 1e-8; cond(C~) ~ 1e3
 

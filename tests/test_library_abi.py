@@ -9,7 +9,7 @@ import pytest
 
 from oracle.partition import build_partition as oracle_partition
 from paper_1104_3349_amd import addns
-from workloads.configs import CFG1, CFG2, CFG3
+from workloads.configs import CAVITY16, CAVITY128, CAVITY256_STRETCHED
 from workloads.mac_oseen import Wind, make_oseen_mac
 
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "addns.h")
@@ -40,7 +40,7 @@ def _same(P, A):
                 P.status == A.status])
 
 
-@pytest.mark.parametrize("cfg", [CFG1, CFG2, CFG3], ids=["cfg1", "cfg2", "cfg3"])
+@pytest.mark.parametrize("cfg", [CAVITY16, CAVITY128, CAVITY256_STRETCHED], ids=["cavity16", "cavity128", "cavity256s"])
 def test_partition_bit_exact_configs(cfg):
     rp, ci, v, b, meta = cfg.build()
     P = oracle_partition(meta["N"], rp, ci, v, cfg.m, cfg.sz)

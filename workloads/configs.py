@@ -2,9 +2,9 @@
 
 Each recipe names the grid, viscosity, stretching, wind, number of subdomains,
 aggregate size, Krylov settings and the storage precisions of the
-preconditioner factors.  Seeds: 1000 + config number for single systems,
-4000 + s for system s of the batched workload, 5000 + t for learned-model
-training instance t.
+preconditioner factors.  Seeds: 1001, 1002, 1003 and 1005 for the four
+single systems, 4000 + s for system s of the batched workload, 5000 + t for
+learned-model training instance t.
 """
 from __future__ import annotations
 
@@ -39,14 +39,14 @@ class Workload:
         return make_oseen_mac(self.n, self.nu, wind=w, stretch=self.stretch, seed=self.seed)
 
 
-CFG1 = Workload("cavity16_uniform_nu0.1_m4", 16, 1 / 10, None, 4, 64, 30, False, 1e-8, 1001, F64, F64)
-CFG2 = Workload("cavity128_uniform_nu0.01_m16", 128, 1 / 100, None, 16, 64, 50, True, 1e-8, 1002, F32, F32)
-CFG3 = Workload("cavity256_stretched1.05_nu0.001_m64", 256, 1 / 1000, 1.05, 64, 64, 50, True, 1e-8, 1003,
+CAVITY16 = Workload("cavity16_uniform_nu0.1_m4", 16, 1 / 10, None, 4, 64, 30, False, 1e-8, 1001, F64, F64)
+CAVITY128 = Workload("cavity128_uniform_nu0.01_m16", 128, 1 / 100, None, 16, 64, 50, True, 1e-8, 1002, F32, F32)
+CAVITY256_STRETCHED = Workload("cavity256_stretched1.05_nu0.001_m64", 256, 1 / 1000, 1.05, 64, 64, 50, True, 1e-8, 1003,
                 F32, F16_SCALED)
-CFG5 = Workload("cavity512_stretched1.05_nu0.002_m256", 512, 1 / 500, 1.05, 256, 64, 50, True, 1e-8, 1005,
+CAVITY512_STRETCHED = Workload("cavity512_stretched1.05_nu0.002_m256", 512, 1 / 500, 1.05, 256, 64, 50, True, 1e-8, 1005,
                 F32, F32)
 
-CONFIGS = {1: CFG1, 2: CFG2, 3: CFG3, 5: CFG5}
+WORKLOADS = {w.name: w for w in (CAVITY16, CAVITY128, CAVITY256_STRETCHED, CAVITY512_STRETCHED)}
 
 
 def batched_workloads(count: int = 96, base_seed: int = 4000):
