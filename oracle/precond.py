@@ -172,7 +172,7 @@ class Preconditioner:
     """B of the MSCN definition (section 3.3) built by Algorithm 1."""
 
     def __init__(self, N, rowptr, colidx, vals, part, mode=MSCN, row_scaling=True,
-                 learned_S=None, overlap=0, ilu_tol=0.0):
+                 learned_S=None, overlap=0, ilu_tol=0.0, coarse=0):
         if overlap < 0:
             raise ValueError("overlap must be >= 0")
         if overlap > 0 and mode not in (MSCN, MSCNR, LUM):
@@ -206,9 +206,16 @@ class Preconditioner:
                 self.widths[i] = min(overlap, s[i] - 1, s[i + 1])
         self.S_blocks = self._schur_blocks(mode, learned_S)
         self.S_lu = []
+        self.coarse = None
         if overlap > 0:
             self._assemble_overlapped()
-            return
+        else:
+            self._factor_blocks()
+        if coarse:
+            from .coarse import CoarseCorrection
+            self.coarse = CoarseCorrection.from_pieces(self, N, rowptr, colidx, int(coarse))
+
+    def _factor_blocks(self):
         for i, S in enumerate(self.S_blocks):
             if S.shape[0] == 0:
                 self.S_lu.append(None)
@@ -319,6 +326,11 @@ class Preconditioner:
         return z
 
     def schur_solve(self, t):
+        if self.coarse is not None:
+            return self.coarse.solve(t, self.shat_solve)
+        return self.shat_solve(t)
+
+    def shat_solve(self, t):
         if self.overlap > 0:
             return self.Shat_lu.solve(t) if len(t) else np.zeros_like(t)
         x = np.empty_like(t)

@@ -143,3 +143,29 @@ def test_rhs_seeded():
     b2 = make_oseen_mac(8, 0.1, seed=5)[3]
     b3 = make_oseen_mac(8, 0.1, seed=6)[3]
     assert np.array_equal(b1, b2) and not np.array_equal(b1, b3)
+
+
+def test_hybrid_scheme_is_central_below_peclet_two_and_upwind_above():
+    """The hybrid option: where every face Peclet number |F_f|/a_f is at most 2
+    the matrix equals the central one; at high Peclet numbers every
+    convective off-diagonal entry is the upwind one, -max(-F_f, 0), so the
+    velocity block's off-diagonal entries are <= 0 and its symmetric part is
+    positive semidefinite (diagonally dominant)."""
+    import scipy.sparse as sp
+    rp, ci, v, _, meta = make_oseen_mac(8, 1.0, seed=1)
+    rp2, ci2, v2, _, _ = make_oseen_mac(8, 1.0, seed=1, scheme="hybrid")
+    assert np.array_equal(rp, rp2) and np.array_equal(ci, ci2) and np.array_equal(v, v2)
+    rpc, cic, vc, _, meta = make_oseen_mac(16, 1e-4, seed=1)
+    rph, cih, vh, _, _ = make_oseen_mac(16, 1e-4, seed=1, scheme="hybrid")
+    assert np.array_equal(cic, cih)
+    nvel = meta["n_u"] + meta["n_v"]
+    A = sp.csr_matrix((vh, cih, rph), shape=(meta["N"], meta["N"]))[:nvel, :nvel].toarray()
+    off = A - np.diag(np.diag(A))
+    assert off.max() <= 0.0
+    Sym = 0.5 * (A + A.T)
+    assert np.linalg.eigvalsh(Sym).min() > -1e-12 * np.abs(Sym).max()
+    Ac = sp.csr_matrix((vc, cic, rpc), shape=(meta["N"], meta["N"]))[:nvel, :nvel].toarray()
+    assert np.abs(Ac - A).max() > 0.0
+    # hybrid minus central is symmetric (added diffusion), the skew parts agree
+    Dd = A - Ac
+    assert np.abs(Dd - Dd.T).max() <= 1e-15 * np.abs(A).max()

@@ -33,10 +33,11 @@ class Workload:
     schur_prec: int
     wind_coeffs: tuple = (1.0, 0.0, 0.0, 0.0)
     wind_scale: float = 1.0
+    scheme: str = "central"
 
     def build(self):
         w = Wind(self.wind_coeffs, self.wind_scale)
-        return make_oseen_mac(self.n, self.nu, wind=w, stretch=self.stretch, seed=self.seed)
+        return make_oseen_mac(self.n, self.nu, wind=w, stretch=self.stretch, seed=self.seed, scheme=self.scheme)
 
 
 CAVITY16 = Workload("cavity16_uniform_nu0.1_m4", 16, 1 / 10, None, 4, 64, 30, False, 1e-8, 1001, F64, F64)

@@ -34,6 +34,10 @@ Discretisation:
     the neighbour across face f is F_f/2, F_f the outward face flux computed
     from the stream function as psi(end) - psi(start); the convective
     diagonal is zero, so the convection matrix is exactly skew-symmetric.
+    Optionally (scheme="hybrid") a face whose Peclet number |F_f| / a_f
+    exceeds 2 is differenced upwind instead: its viscous coefficient a_f is
+    raised to |F_f|/2, which adds a symmetric, diagonally dominant
+    (artificial diffusion) part and leaves the skew part unchanged.
   * b: velocity rows = control-volume area * f with f ~ N(0,1) drawn from
     numpy.random.default_rng(seed), plus the lid's Dirichlet contribution;
     pressure rows = 0.
@@ -209,7 +213,7 @@ class _Coo:
 
 
 def make_oseen_mac(n: int, nu: float, wind: Wind | FaceWind | None = None, stretch: float | None = None,
-                   seed: int | None = 0, lid: float = 1.0, forcing=None):
+                   seed: int | None = 0, lid: float = 1.0, forcing=None, scheme: str = "central"):
     """Assemble C (CSR, int32 indices, float64 values), b and metadata.
 
     wind: a stream-function Wind (default Wind()) or a FaceWind (discrete
@@ -217,7 +221,14 @@ def make_oseen_mac(n: int, nu: float, wind: Wind | FaceWind | None = None, stret
           pattern does not depend on the wind.
     forcing: None -> f ~ N(0,1) per velocity unknown from default_rng(seed);
              callable (fu(x,y), fv(x,y)) -> point values at the unknowns.
+    scheme: "central" (skew-symmetric convection) or "hybrid" (central on a
+            face whose Peclet number |F_f| / a_f is at most 2, first-order
+            upwind beyond: the viscous coefficient a_f of the face is replaced
+            by max(a_f, |F_f|/2)).
     """
+    if scheme not in ("central", "hybrid"):
+        raise ValueError(scheme)
+    hyb = scheme == "hybrid"
     wind = wind or Wind()
     dx = cell_widths(n, stretch)
     dy = dx.copy()
@@ -257,12 +268,16 @@ def make_oseen_mac(n: int, nu: float, wind: Wind | FaceWind | None = None, stret
     # east neighbour u(i+1, j), face at xc[i]
     a = nu * hu / dx[I]
     F = flux["uE"]
+    if hyb:
+        a = np.maximum(a, 0.5 * np.abs(F))
     inner = I + 1 <= n - 1
     coo.add(rows, U(np.minimum(I + 1, n - 1), J), -a + 0.5 * F, inner)
     diag += a
     # west neighbour u(i-1, j), face at xc[i-1]
     a = nu * hu / dx[I - 1]
     F = flux["uW"]
+    if hyb:
+        a = np.maximum(a, 0.5 * np.abs(F))
     inner = I - 1 >= 1
     coo.add(rows, U(np.maximum(I - 1, 1), J), -a + 0.5 * F, inner)
     diag += a
@@ -271,6 +286,8 @@ def make_oseen_mac(n: int, nu: float, wind: Wind | FaceWind | None = None, stret
     dist = np.where(top, 0.5 * dy[J], yc[np.minimum(J + 1, n - 1)] - yc[J])
     a = nu * wu / dist
     F = flux["uN"]
+    if hyb:
+        a = np.maximum(a, 0.5 * np.abs(F))
     coo.add(rows, U(I, np.minimum(J + 1, n - 1)), -a + 0.5 * F, ~top)
     diag += a
     lidv = np.where(top, lid, 0.0)
@@ -280,6 +297,8 @@ def make_oseen_mac(n: int, nu: float, wind: Wind | FaceWind | None = None, stret
     dist = np.where(bot, 0.5 * dy[J], yc[J] - yc[np.maximum(J - 1, 0)])
     a = nu * wu / dist
     F = flux["uS"]
+    if hyb:
+        a = np.maximum(a, 0.5 * np.abs(F))
     coo.add(rows, U(I, np.maximum(J - 1, 0)), -a + 0.5 * F, ~bot)
     diag += a
     coo.add(rows, rows, diag)
@@ -298,11 +317,15 @@ def make_oseen_mac(n: int, nu: float, wind: Wind | FaceWind | None = None, stret
     # north v(i, j+1), face at yc[j]
     a = nu * wv / dy[J2]
     F = flux["vN"]
+    if hyb:
+        a = np.maximum(a, 0.5 * np.abs(F))
     coo.add(rows2, V(I2, np.minimum(J2 + 1, n - 1)), -a + 0.5 * F, J2 + 1 <= n - 1)
     diag2 += a
     # south v(i, j-1), face at yc[j-1]
     a = nu * wv / dy[J2 - 1]
     F = flux["vS"]
+    if hyb:
+        a = np.maximum(a, 0.5 * np.abs(F))
     coo.add(rows2, V(I2, np.maximum(J2 - 1, 1)), -a + 0.5 * F, J2 - 1 >= 1)
     diag2 += a
     # east v(i+1, j), face at X[i+1]
@@ -310,6 +333,8 @@ def make_oseen_mac(n: int, nu: float, wind: Wind | FaceWind | None = None, stret
     dist = np.where(right, 0.5 * dx[I2], xc[np.minimum(I2 + 1, n - 1)] - xc[I2])
     a = nu * hv / dist
     F = flux["vE"]
+    if hyb:
+        a = np.maximum(a, 0.5 * np.abs(F))
     coo.add(rows2, V(np.minimum(I2 + 1, n - 1), J2), -a + 0.5 * F, ~right)
     diag2 += a
     # west v(i-1, j), face at X[i]
@@ -317,6 +342,8 @@ def make_oseen_mac(n: int, nu: float, wind: Wind | FaceWind | None = None, stret
     dist = np.where(left, 0.5 * dx[I2], xc[I2] - xc[np.maximum(I2 - 1, 0)])
     a = nu * hv / dist
     F = flux["vW"]
+    if hyb:
+        a = np.maximum(a, 0.5 * np.abs(F))
     coo.add(rows2, V(np.maximum(I2 - 1, 0), J2), -a + 0.5 * F, ~left)
     diag2 += a
     coo.add(rows2, rows2, diag2)
