@@ -2,9 +2,16 @@
 bandwidth on one MI355X.
 
 One step = setup_precond + gmres_solve (FGMRES(50), tol 1e-8) on the
-128 x 128 uniform MAC Oseen cavity (nu = 1/100, 16 subdomains, FP32 interior
-and interface factors, FP64 outer solver), inputs resident in HBM.  The
-partition is built once beforehand and excluded, as in the paper's timings.
+128 x 128 uniform MAC Oseen cavity (nu = 1/100, 16 subdomains), the largest
+workload of the set that the method solves to 1e-8 with FGMRES(50): FP32
+interior and interface factors, the coarse-grid correction of the interface
+solve (pieces of 32), CGS2 Arnoldi, FP64 outer solver; inputs resident in
+HBM.  The partition is built once beforehand and excluded, as in the paper's
+timings.  Median of the timed steps after the warm-up ones.  Beside it: the
+plain FP64 path (FP64 factors, no coarse correction) with CGS2 and with MGS
+under the same protocol, the other forms of the paper, and the 512 x 512
+stretched workload's apply bandwidth and interior-solve roofline (HBM
+resident) with its FGMRES(50) result.
 
 Prints one JSON line.  --gpus above 1 is not supported (one GPU per box).
 """
@@ -34,6 +41,25 @@ def _events_ms(fn, reps, torch):
     return e0.elapsed_time(e1) / reps
 
 
+PEAK = 8.0e12  # MI355X HBM3E bytes/s
+
+
+def _events_median_ms(fn, reps, torch):
+    """Median of `reps` launches of fn, each bracketed by HIP events on the
+    current stream (the stream the library launches on)."""
+    import numpy as np
+    s = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(s)
+        fn()
+        e1.record(s)
+    torch.cuda.synchronize()
+    return float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+
+
 def measured_traffic():
     """Calibrated FETCH_SIZE + WRITE_SIZE bytes per interior-solve launch from
     the committed rocprofv3 summary; None once the kernel source differs from
@@ -54,9 +80,9 @@ def measured_traffic():
     return int(m.group(1))
 
 
-def cpu_baseline(cfg, its_gpu, budget_s=20.0):
-    """The oracle as it stands on the host: setup plus a bounded number of
-    FGMRES iterations, scaled to a full solve of its_gpu iterations."""
+def cpu_baseline(cfg, coarse, ortho, runs=3):
+    """The oracle as it stands on the host: full solves (setup + FGMRES to
+    tol) of the same workload and method options; median of `runs`."""
     import numpy as np
 
     from oracle.krylov import gmres
@@ -66,30 +92,22 @@ def cpu_baseline(cfg, its_gpu, budget_s=20.0):
     rp, ci, v, b, meta = cfg.build()
     N = meta["N"]
     P = oracle_partition(N, rp, ci, v, cfg.m, cfg.sz)
-    r0 = resource.getrusage(resource.RUSAGE_SELF)
-    t0 = time.perf_counter()
-    pre = Preconditioner(N, rp, ci, v, P, MSCN)
-    t_setup = time.perf_counter() - t0
-    # bounded sample: iterations until the budget is used
-    probe = 20
-    t1 = time.perf_counter()
-    gmres(lambda z: pre.C @ z, pre.apply, pre.R * b, restart=cfg.restart, tol=1e-300, maxit=probe,
-          flexible=cfg.flexible)
-    per_it = (time.perf_counter() - t1) / probe
-    k = int(max(probe, min(its_gpu, (budget_s - t_setup) / max(per_it, 1e-9))))
-    t2 = time.perf_counter()
-    gmres(lambda z: pre.C @ z, pre.apply, pre.R * b, restart=cfg.restart, tol=1e-300, maxit=k,
-          flexible=cfg.flexible)
-    t_it = (time.perf_counter() - t2) / k
-    wall = time.perf_counter() - t0
-    r1 = resource.getrusage(resource.RUSAGE_SELF)
-    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    est = t_setup + its_gpu * t_it
-    return {"value": round(est, 4), "unit": "s", "cores": max(1, int(round(cpu / wall))),
+    walls, cpus, its = [], [], []
+    for _ in range(runs):
+        r0 = resource.getrusage(resource.RUSAGE_SELF)
+        t0 = time.perf_counter()
+        pre = Preconditioner(N, rp, ci, v, P, MSCN, coarse=coarse)
+        res = gmres(lambda z: pre.C @ z, pre.apply, pre.R * b, restart=cfg.restart, tol=cfg.tol, maxit=20000,
+                    flexible=cfg.flexible, ortho=ortho)
+        walls.append(time.perf_counter() - t0)
+        r1 = resource.getrusage(resource.RUSAGE_SELF)
+        cpus.append((r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime))
+        its.append(res.iters)
+    k = int(np.argsort(walls)[len(walls) // 2])
+    return {"value": round(walls[k], 4), "unit": "s", "cores": max(1, int(round(cpus[k] / walls[k]))),
             "kind": "oracle",
-            "sample": f"oracle setup ({t_setup:.2f} s) + {k + probe} FGMRES({cfg.restart}) iterations "
-                      f"({t_it * 1e3:.1f} ms each), scaled to the GPU's {its_gpu} iterations; "
-                      f"host cpus {os.cpu_count()}"}
+            "sample": f"{runs} full oracle solves (setup + FGMRES({cfg.restart}) to {cfg.tol:g}, coarse pieces "
+                      f"{coarse}, {ortho}), median; {its[k]} iterations; host cpus {os.cpu_count()}"}
 
 
 def bench_batched(args):
@@ -272,8 +290,14 @@ def bench_learned(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--plain-steps", type=int, default=5)
+    ap.add_argument("--coarse", type=int, default=32, help="coarse-correction piece size (0 = none)")
+    ap.add_argument("--ortho", default="cgs2", choices=["cgs2", "mgs"])
+    ap.add_argument("--no-large", action="store_true", help="skip the 512 x 512 stretched measurements")
+    ap.add_argument("--large-maxit", type=int, default=300)
+    ap.add_argument("--profile-workload", default="cavity128", choices=["cavity128", "cavity512s"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the MSCNR/LUM/overlapped solves")
@@ -325,17 +349,48 @@ def main():
     d_x = torch.zeros(N, dtype=torch.float64, device=dev)
     maxit = 20000
 
-    def step(iprec, sprec, schur=addns.SCHUR_MSCN, overlap=0, ilu_tol=0.0):
+    def step(iprec, sprec, schur=addns.SCHUR_MSCN, overlap=0, ilu_tol=0.0, coarse=None, ortho=None):
+        coarse = args.coarse if coarse is None else coarse
+        ortho = args.ortho if ortho is None else ortho
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         pc = addns.setup_precond(part, N, d_rp, d_ci, d_v, schur=schur, interior_prec=iprec, schur_prec=sprec,
                                  block_mult=args.block_mult, overlap=overlap, ilu_tol=ilu_tol,
-                                 sweep_chunks=args.sweep_chunks)
+                                 sweep_chunks=args.sweep_chunks, coarse=coarse)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         d_x.zero_()
         r = addns.gmres_solve(pc, d_b, d_x, restart=cfg.restart, maxit=maxit, tol=cfg.tol,
-                              flexible=cfg.flexible)
-        return pc, r
+                              flexible=cfg.flexible, ortho=ortho)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return pc, r, (t2 - t0, t1 - t0, t2 - t1)
+
+    def timed(steps, warmup, **kw):
+        """Median over `steps` timed steps after `warmup` untimed ones."""
+        for _ in range(warmup):
+            step(**kw)
+        ts, last = [], None
+        for _ in range(steps):
+            pc, r, t = step(**kw)
+            ts.append(t)
+            last = (pc, r)
+        ts = np.array(ts)
+        return last[0], last[1], {"seconds": round(float(np.median(ts[:, 0])), 5),
+                                  "setup_s": round(float(np.median(ts[:, 1])), 5),
+                                  "solve_s": round(float(np.median(ts[:, 2])), 5),
+                                  "iters": last[1]["iters"], "true_relres": last[1]["true_relres"],
+                                  "converged": bool(last[1]["converged"])}
 
     iprec, sprec = addns.F32, addns.F32
     if args.kernel_profile:
+        wl = cfg
+        if args.profile_workload == "cavity512s":
+            from workloads.configs import CAVITY512_STRETCHED as wl
+            rp, ci, v, b, meta = wl.build()
+            N = meta["N"]
+            part = addns.build_partition(N, rp, ci, v, wl.m, wl.sz)
+            d_rp, d_ci, d_v = (torch.from_numpy(a).to(dev) for a in (rp, ci, v))
         pc = addns.setup_precond(part, N, d_rp, d_ci, d_v, interior_prec=iprec, schur_prec=sprec,
                                  block_mult=args.block_mult, sweep_chunks=args.sweep_chunks)
         n_int = int(part.info()["n_interior"])
@@ -348,91 +403,154 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         info = pc.info()
-        print(json.dumps({"kernel_profile": True, "reps": args.reps, "copy_bytes": 256 * 2 ** 20,
-                          "interior_bytes_algorithmic": n_int * (2 * info["kl"] + info["ku"] + 1) * 4
-                          + 20 * n_int + info["chunk_bytes"], "factor_bytes": info["factor_bytes"],
-                          "sweep_chunks": info["sweep_chunks"], "chunk_bytes": info["chunk_bytes"]}))
+        print(json.dumps({"kernel_profile": True, "workload": wl.name, "reps": args.reps,
+                          "copy_bytes": 256 * 2 ** 20,
+                          "interior_bytes_method": n_int * (2 * info["kl"] + info["ku"] + 1) * 4 + 20 * n_int,
+                          "chunk_bytes": info["chunk_bytes"], "factor_bytes": info["factor_bytes"],
+                          "sweep_chunks": info["sweep_chunks"]}))
         return
-    for _ in range(args.warmup):
-        step(iprec, sprec)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = []
-    for _ in range(args.steps):
-        pc, r = step(iprec, sprec)
-        results.append(r)
-    torch.cuda.synchronize()
-    T = (time.perf_counter() - t0) / max(args.steps, 1)
-    r = results[-1]
+
+    def interior_roofline(pc, part, sf, reps=100):
+        """HIP-event median of `reps` interior solves on the current stream and
+        the method's bytes per solve: band factors L (KL) and U (KL + KU + 1)
+        per interior row, pivots, the vector in and out.  The chunked sweep's
+        response matrices are reported beside them as overhead."""
+        info = pc.info()
+        n_int = int(part.info()["n_interior"])
+        d_y1 = torch.randn(n_int, dtype=torch.float64, device=dev)
+        d_z1 = torch.empty_like(d_y1)
+        t = _events_median_ms(lambda: addns.interior_solve(pc, d_y1, d_z1), reps, torch)
+        b_int = n_int * (2 * info["kl"] + info["ku"] + 1) * sf + 4 * n_int + 16 * n_int
+        kern = "k_chunk_lower + k_chunk_upper + k_chunk_fix" if info["sweep_chunks"] > 1 else "k_interior_solve"
+        ach = b_int / (t * 1e-3)
+        return {"bound": "hbm", "kernel": kern, "achieved": round(ach / 1e9, 2), "peak": PEAK / 1e9,
+                "unit": "GB/s", "frac": round(ach / PEAK, 4), "traffic": None, "launch_ms": round(t, 4),
+                "bytes_per_launch": int(b_int), "overhead_bytes_per_launch": int(info["chunk_bytes"])}
+
+    def apply_bw(pc, n, reps=100):
+        info = pc.info()
+        d_y = torch.randn(n, dtype=torch.float64, device=dev)
+        d_o = torch.empty_like(d_y)
+        t = _events_median_ms(lambda: addns.apply_precond(pc, d_y, d_o), reps, torch)
+        return {"apply_ms": round(t, 4), "apply_GBps": round(info["bytes_apply"] / (t * 1e-3) / 1e9, 2),
+                "apply_frac_hbm": round(info["bytes_apply"] / (t * 1e-3) / PEAK, 4),
+                "bytes_apply": int(info["bytes_apply"]), "chunk_overhead_bytes": 2 * int(info["chunk_bytes"])}
+
+    pc, r, main_t = timed(args.steps, args.warmup, iprec=iprec, sprec=sprec)
     info = pc.info()
-
-    # apply bandwidth and the dominant kernel (interior solve) by HIP events
-    d_y = torch.randn(N, dtype=torch.float64, device=dev)
-    d_o = torch.empty_like(d_y)
-    t_apply = _events_ms(lambda: addns.apply_precond(pc, d_y, d_o), 50, torch)
-    n_int = int(part.info()["n_interior"])
-    d_y1 = torch.randn(n_int, dtype=torch.float64, device=dev)
-    d_z1 = torch.empty_like(d_y1)
-    t_int = _events_ms(lambda: addns.interior_solve(pc, d_y1, d_z1), 50, torch)
     sf = 4 if iprec == addns.F32 else 8
-    # band factors, pivots, in/out vectors, and (chunked sweep) the response
-    # matrices, each read once per interior solve
-    b_int = n_int * (2 * info["kl"] + info["ku"] + 1) * sf + 4 * n_int + 16 * n_int + info["chunk_bytes"]
-    solve_kernels = ("k_chunk_lower + k_chunk_upper + k_chunk_fix" if info["sweep_chunks"] > 1
-                     else "k_interior_solve")
-    peak = 8.0e12
-    achieved = b_int / (t_int * 1e-3)
+    roof = interior_roofline(pc, part, sf)
+    roof["traffic"] = measured_traffic()
+    bw = apply_bw(pc, N)
+    nnz_pre, nnz_c = pc.fill()
 
-    plain = None
+    legs = {}
     if not args.no_plain:
-        t1 = time.perf_counter()
-        _, rp64 = step(addns.F64, addns.F64)
-        torch.cuda.synchronize()
-        plain = {"seconds": round(time.perf_counter() - t1, 4), "iters": rp64["iters"],
-                 "true_relres": rp64["true_relres"]}
+        # the plain path: FP64 factors, the paper's one-level interface solve
+        for name, kw in (("plain_f64_cgs2", dict(iprec=addns.F64, sprec=addns.F64, coarse=0, ortho="cgs2")),
+                         ("plain_f64_mgs", dict(iprec=addns.F64, sprec=addns.F64, coarse=0, ortho="mgs")),
+                         ("mixed_f32_one_level", dict(iprec=addns.F32, sprec=addns.F32, coarse=0)),
+                         ("f64_coarse", dict(iprec=addns.F64, sprec=addns.F64)),
+                         ("mixed_f32_coarse_mgs", dict(iprec=addns.F32, sprec=addns.F32, ortho="mgs"))):
+            _, _, legs[name] = timed(args.plain_steps, 1, **kw)
 
-    # the other interface forms of the paper on the same workload, same
-    # factors (one timed solve each, setup included)
     forms = None
     if not args.no_forms:
         forms = {}
-        for name, kw in (("mscnr", dict(schur=addns.SCHUR_MSCNR)), ("lum", dict(schur=addns.SCHUR_LUM)),
-                         ("omscn", dict(overlap=cfg.sz - 1)),
-                         ("omscnr", dict(schur=addns.SCHUR_MSCNR, overlap=cfg.sz - 1)),
-                         ("mscn_ilu1e-4", dict(ilu_tol=1e-4))):
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            _, rf = step(iprec, sprec, **kw)
-            torch.cuda.synchronize()
-            forms[name] = {"seconds": round(time.perf_counter() - t1, 4), "iters": rf["iters"],
-                           "converged": rf["converged"]}
+        for name, kw in (("mscnr", dict(schur=addns.SCHUR_MSCNR, coarse=0)),
+                         ("lum", dict(schur=addns.SCHUR_LUM, coarse=0)),
+                         ("omscn", dict(overlap=cfg.sz - 1, coarse=0)),
+                         ("omscnr", dict(schur=addns.SCHUR_MSCNR, overlap=cfg.sz - 1, coarse=0)),
+                         ("mscn_ilu1e-4", dict(ilu_tol=1e-4, coarse=0)),
+                         ("mscn_ilu1e-4_coarse", dict(ilu_tol=1e-4))):
+            pcf, rf, tf = step(iprec, sprec, **kw)
+            forms[name] = {"seconds": round(tf[0], 4), "iters": rf["iters"], "converged": rf["converged"]}
             if "ilu_tol" in kw:
-                forms[name]["interior_fill"] = round(_.info()["interior_nnz"] / len(v), 2)
+                forms[name]["interior_fill"] = round(pcf.info()["interior_nnz"] / len(v), 2)
 
+    big = None
+    if not args.no_large:
+        big = bench_large(args, addns, torch, dev)
+
+    plain_s = legs.get("plain_f64_cgs2", {}).get("seconds")
     line = {
         "metric": "time to 1e-8 rel. residual (s) + precond-apply GB/s; plain FP64 vs mixed/learned",
-        "value": round(T, 5), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(T * 1e3, 3), "higher_is_better": False, "scaling": "weak",
+        "value": main_t["seconds"], "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(main_t["seconds"] * 1e3, 3), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64 outer / f32 factors", "data": "synthetic",
         "config": {"workload": cfg.name, "N": N, "nnz": int(len(v)), "subdomains": cfg.m,
                    "aggregate_size": cfg.sz, "krylov": f"FGMRES({cfg.restart})", "tol": cfg.tol,
-                   "factors": "f32/f32"},
+                   "factors": "f32/f32", "ortho": args.ortho, "coarse_piece": args.coarse,
+                   "sweep_chunks": info["sweep_chunks"], "block_mult": info["block_mult"]},
+        "setup_s": main_t["setup_s"], "solve_s": main_t["solve_s"],
         "iters": r["iters"], "converged": r["converged"], "true_relres": r["true_relres"],
-        "apply_ms": round(t_apply, 4),
-        "apply_GBps": round(info["bytes_apply"] / (t_apply * 1e-3) / 1e9, 2),
-        "apply_frac_hbm": round(info["bytes_apply"] / (t_apply * 1e-3) / peak, 4),
-        "plain_f64": plain,
+        **bw,
+        "fill_factor": round(nnz_pre / nnz_c, 3),
         "interior_fill": round(info["interior_nnz"] / len(v), 2),
+        "legs": legs,
+        "speedup_vs_plain_f64": round(plain_s / main_t["seconds"], 2) if plain_s else None,
         "interface_forms": forms,
-        "sweep_chunks": info["sweep_chunks"],
-        "roofline": {"bound": "hbm", "kernel": solve_kernels, "achieved": round(achieved / 1e9, 2),
-                     "peak": peak / 1e9, "unit": "GB/s", "frac": round(achieved / peak, 4),
-                     "traffic": measured_traffic(), "launch_ms": round(t_int, 4),
-                     "bytes_per_launch": int(b_int)},
+        "cavity512_stretched": big,
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, r["iters"])
+        line["cpu_baseline"] = cpu_baseline(cfg, args.coarse, args.ortho)
     print(json.dumps(line))
+
+
+def bench_large(args, addns, torch, dev):
+    """The 512 x 512 stretched workload (785 407 unknowns, 256 subdomains):
+    setup, apply bandwidth and the interior solve's roofline with FP32
+    factors (the factors, 1.8 GB, exceed the 256 MB last-level cache), and
+    FGMRES(50) for a bounded number of iterations, one-level and with the
+    coarse correction."""
+    import numpy as np
+
+    from workloads.configs import CAVITY512_STRETCHED as wl
+
+    t0 = time.perf_counter()
+    rp, ci, v, b, meta = wl.build()
+    N = meta["N"]
+    part = addns.build_partition(N, rp, ci, v, wl.m, wl.sz)
+    t_part = time.perf_counter() - t0
+    d_rp, d_ci, d_v = (torch.from_numpy(a).to(dev) for a in (rp, ci, v))
+    d_b = torch.from_numpy(b).to(dev)
+    out = {"workload": wl.name, "N": N, "subdomains": wl.m, "host_build_and_partition_s": round(t_part, 2)}
+    for name, coarse in (("one_level", 0), ("coarse", args.coarse)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pc = addns.setup_precond(part, N, d_rp, d_ci, d_v, interior_prec=addns.F32, schur_prec=addns.F32,
+                                 block_mult=1, coarse=coarse)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t1
+        info = pc.info()
+        n_int = int(part.info()["n_interior"])
+        d_y1 = torch.randn(n_int, dtype=torch.float64, device=dev)
+        d_z1 = torch.empty_like(d_y1)
+        t_int = _events_median_ms(lambda: addns.interior_solve(pc, d_y1, d_z1), 100, torch)
+        b_int = n_int * (2 * info["kl"] + info["ku"] + 1) * 4 + 20 * n_int
+        d_y = torch.randn(N, dtype=torch.float64, device=dev)
+        d_o = torch.empty_like(d_y)
+        t_app = _events_median_ms(lambda: addns.apply_precond(pc, d_y, d_o), 100, torch)
+        d_x = torch.zeros(N, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        r = addns.gmres_solve(pc, d_b, d_x, restart=wl.restart, maxit=args.large_maxit, tol=wl.tol,
+                              flexible=True, ortho=args.ortho)
+        torch.cuda.synchronize()
+        out[name] = {"setup_s": round(t_setup, 4), "solve_s": round(time.perf_counter() - t2, 4),
+                     "iters": r["iters"], "converged": r["converged"], "true_relres": r["true_relres"],
+                     "apply_ms": round(t_app, 4),
+                     "apply_GBps": round(info["bytes_apply"] / (t_app * 1e-3) / 1e9, 2),
+                     "apply_frac_hbm": round(info["bytes_apply"] / (t_app * 1e-3) / PEAK, 4),
+                     "interior_solve": {"kernel": "k_chunk_lower + k_chunk_upper + k_chunk_fix"
+                                        if info["sweep_chunks"] > 1 else "k_interior_solve",
+                                        "launch_ms": round(t_int, 4), "bytes_per_launch": int(b_int),
+                                        "achieved_GBps": round(b_int / (t_int * 1e-3) / 1e9, 2),
+                                        "frac": round(b_int / (t_int * 1e-3) / PEAK, 4)},
+                     "sweep_chunks": info["sweep_chunks"], "factor_bytes": int(info["factor_bytes"])}
+        del pc
+    return out
 
 
 if __name__ == "__main__":

@@ -107,6 +107,34 @@ int addns_partition_export(addns_partition_t p, int32_t* perm, int32_t* part,
                            int32_t* drange_nodes, int32_t* pair);
 
 /* ------------------------------------------------------------------------
+ * addns_partition_coarse_space -- the coarse space of the two-level
+ * interface solve (opts.coarse = piece), copied into caller-owned HOST
+ * arrays.  Section 6 proposes a coarse grid correction without fixing one;
+ * this one is built from the pattern and the partition only:
+ *   velocity classes = connected components of the pattern over the
+ *   non-pressure nodes; two separator nodes of one class are near when they
+ *   are coupled or share a coupled node; walking the separator in order, each
+ *   velocity node not yet taken starts a piece that grows breadth first
+ *   through near, free nodes (ascending positions) up to `piece` nodes; every
+ *   piece gives a normalised constant column and, with >= 3 nodes, a
+ *   normalised mean-free breadth-first level from the node last reached
+ *   from its first node (ties: smaller position).
+ *   piece  : P in 1..64 (else ADDNS_ERR_ARG).
+ *   npieces, ncols: counts (either may be NULL); call once with NULL arrays
+ *            to size them.
+ *   piece_offsets[npieces+1], piece_pos[#velocity separator nodes]: members
+ *            of each piece (separator positions, in joining order).
+ *   col_piece[ncols], col_kind[ncols]: piece and kind (0 constant, 1 linear)
+ *            of every column, in column order.
+ *   z0[sep_size], z1[sep_size]: constant / linear value at each separator
+ *            position (0 where none).
+ * Host-only; deterministic.  Returns ADDNS_OK or ADDNS_ERR_ARG.
+ */
+int addns_partition_coarse_space(addns_partition_t p, int32_t piece, int32_t* npieces, int32_t* ncols,
+                                 int32_t* piece_offsets, int32_t* piece_pos, int32_t* col_piece,
+                                 int32_t* col_kind, double* z0, double* z1);
+
+/* ------------------------------------------------------------------------
  * addns_partition_concat -- partition of the block-diagonal matrix
  * diag(C_0, ..., C_{nsys-1}) from the partitions of its independent blocks
  * (the batched form: every phase of setup and apply then runs as one launch
@@ -126,13 +154,13 @@ typedef struct {
   const float* learned_model; /* LEARNED only: HOST array of addns_dtn_param_count()
                                   FP32 network weights (addns_dtn_train output) */
   int32_t block_mult;     /* interior sweep block size as a multiple of its minimum
-                             (1..4), or 0: the autotuner builds the sweep at 1 and 2,
-                             times the interior solve on these factors and keeps the
-                             faster.  A tile shape only: the factors are the same
-                             LU, regrouped; results agree to rounding.  Whatever the
-                             value, every setup also times the sweep with and without
-                             skipping the blocks' structural-zero row slots and keeps
-                             the faster (the results are the same bit for bit) */
+                             (1..4); 0 = the library's fixed choice (1).  A tile
+                             shape only: the factors are the same LU, regrouped;
+                             results agree to rounding.  Whatever the value,
+                             every setup times the sweep with and without
+                             skipping the blocks' structural-zero row slots and
+                             keeps the faster: the two forms give the same result
+                             bit for bit, so this timing never changes numerics */
   int32_t learned_bf16;   /* LEARNED only: 1 = run the network with BF16-rounded
                              weights and activations, 0 = FP32 */
   int32_t overlap;        /* overlapped aggregates, w >= 0 (0 = none; the overlap
@@ -171,10 +199,35 @@ typedef struct {
                              the same solution, to rounding; more workgroups per
                              interior at the price of p - 1 small GEMVs on the
                              chunk boundaries and the response matrices' bytes.
-                             0 = choose p from the measured single-chunk sweep
-                             and keep it only if it times faster; 1 = never;
+                             0 = the p minimising a fixed cost model of the plan
+                             (longest chunk's upper blocks at 17.5 us each plus
+                             5 us per chunk boundary, at most one workgroup per
+                             CU): no timing, so the same p, and the same
+                             rounding, on every run; 1 = never;
                              p >= 2 = that many (ADDNS_ERR_ARG if an interior has
                              fewer than p upper blocks) */
+  int32_t coarse;         /* coarse-grid correction of the interface solve (the
+                             coarse grid correction section 6 proposes), 0 = none.
+                             P in 1..64: the coarse space Z holds, for every
+                             piece of at most P separator velocity nodes (grown
+                             breadth first through nodes of one velocity class at
+                             graph distance <= 2, see
+                             addns_partition_coarse_space), a normalised constant
+                             and a normalised linear coordinate; the interface
+                             step of Algorithm 2 becomes
+                               y = (Z^T S Z)^-1 Z^T t,
+                               x2 = Z y + Shat^-1 (t - S Z y),
+                             S = G - F D^-1 E formed on Z at setup from one
+                             interior solve per (subdomain, coarse column) pair.
+                             Theorem 2 holds with Shat^-1 replaced by this
+                             operator.  At most 8192 coarse columns; not with
+                             overlap > 0 (else ADDNS_ERR_ARG); a singular
+                             Z^T S Z gives ADDNS_ERR_SINGULAR */
+  int32_t sweep_zero_skip;  /* sweep form: 0 = time the sweep with and without
+                             skipping structural-zero row slots and keep the
+                             faster (the default; both give the same result bit
+                             for bit); 1 = never skip; 2 = always skip; else
+                             ADDNS_ERR_ARG */
 } addns_precond_opts;
 
 /* ------------------------------------------------------------------------
@@ -276,6 +329,17 @@ typedef struct {
  */
 int addns_gmres_solve(addns_precond_t pc, const double* d_b, double* d_x,
                       const addns_gmres_opts* opts, addns_gmres_result* res, void* stream);
+
+/* ------------------------------------------------------------------------
+ * addns_precond_fill -- the fill factor of section 5 (the preconditioner's
+ * nonzeros over those of C): *nnz_precond = the nonzero entries of the
+ * interior factors L_j (multipliers) and U_j (with the diagonal), the
+ * entries of the interface blocks S_i (dense, s_i^2 each; with overlapped
+ * aggregates also the lower blocks of Shat), and the entries of E and F that
+ * Algorithm 2 applies; *nnz_c = nnz(C).  The coarse correction is not
+ * counted.  Either pointer may be NULL.  Returns ADDNS_OK or ADDNS_ERR_ARG.
+ */
+int addns_precond_fill(addns_precond_t pc, int64_t* nnz_precond, int64_t* nnz_c);
 
 /* ------------------------------------------------------------------------
  * addns_gmres_solve_batched -- one independent restarted FGMRES per system

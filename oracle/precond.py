@@ -369,11 +369,19 @@ class Preconditioner:
         return D, E, F, G, Shat
 
     def fill_factor(self):
-        """nnz(preconditioner factors) / nnz(C) (section 5, ff)."""
+        """Fill factor of section 5: the nonzeros of the preconditioner over
+        nnz(C).  Counted: the nonzero entries of every interior factor (the
+        multipliers of L and all of U, as LAPACK's band storage holds them),
+        the stored entries of Shat (dense s_i x s_i blocks, with overlapped
+        aggregates also their lower blocks) and the entries of E and F that
+        Algorithm 2 applies."""
         nz = 0
         for (a, b, lu) in self.blocks:
             if lu.n:
-                nz += np.count_nonzero(lu.lub)
-        nz += sum(S.size for S in self.S_blocks)
+                nz += np.count_nonzero(lu.lub) if isinstance(lu, BandLU) else lu.nnz()
+        if self.overlap > 0:
+            nz += self.Shat.nnz
+        else:
+            nz += sum(S.size for S in self.S_blocks)
         nz += self.E.nnz + self.F.nnz
         return nz / self.C.nnz

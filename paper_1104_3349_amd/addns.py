@@ -24,9 +24,9 @@ F64, F32, F16_SCALED = 0, 1, 2
 
 EXPORTED = [
     "addns_build_partition", "addns_partition_info", "addns_partition_export",
-    "addns_partition_concat", "addns_gmres_solve_batched",
+    "addns_partition_concat", "addns_partition_coarse_space", "addns_gmres_solve_batched",
     "addns_setup_precond", "addns_apply_precond", "addns_interior_solve", "addns_gmres_solve", "addns_precond_info",
-    "addns_precond_schur_blocks", "addns_partition_destroy", "addns_precond_destroy",
+    "addns_precond_schur_blocks", "addns_precond_fill", "addns_partition_destroy", "addns_precond_destroy",
     "addns_last_error", "addns_version",
     "addns_dtn_param_count", "addns_dtn_samples", "addns_dtn_forward", "addns_dtn_grad",
     "addns_dtn_train", "addns_dtn_save", "addns_dtn_load", "addns_gmres_solve_judged",
@@ -44,7 +44,8 @@ class PrecondOpts(C.Structure):
     _fields_ = [("schur", C.c_int32), ("interior_prec", C.c_int32), ("schur_prec", C.c_int32),
                 ("row_scale", C.c_int32), ("learned_model", C.POINTER(C.c_float)),
                 ("block_mult", C.c_int32), ("learned_bf16", C.c_int32), ("overlap", C.c_int32),
-                ("ilu_tol", C.c_double), ("sweep_chunks", C.c_int32)]
+                ("ilu_tol", C.c_double), ("sweep_chunks", C.c_int32), ("coarse", C.c_int32),
+                ("sweep_zero_skip", C.c_int32)]
 
 
 class GmresOpts(C.Structure):
@@ -82,6 +83,7 @@ def lib():
         "addns_partition_info": (C.c_int, [P, i32p, i32p, i32p, i32p, i32p, i32p]),
         "addns_partition_export": (C.c_int, [P, P, P, P, P, P, P, P]),
         "addns_partition_concat": (C.c_int, [C.POINTER(P), C.c_int32, C.POINTER(P)]),
+        "addns_partition_coarse_space": (C.c_int, [P, C.c_int32, i32p, i32p, P, P, P, P, P, P]),
         "addns_gmres_solve_batched": (C.c_int, [P, C.c_int32, P, P, P, C.POINTER(GmresOpts),
                                                 C.POINTER(GmresResult), P]),
         "addns_setup_precond": (C.c_int, [P, C.c_int32, P, P, P, C.POINTER(PrecondOpts), P,
@@ -92,6 +94,7 @@ def lib():
         "addns_gmres_solve": (C.c_int, [P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresResult), P]),
         "addns_precond_info": (C.c_int, [P, i32p, i32p, i32p, i32p, i64p, i64p, i64p, i32p, i64p, i32p, i64p]),
         "addns_precond_schur_blocks": (C.c_int, [P, P, C.c_int64]),
+        "addns_precond_fill": (C.c_int, [P, i64p, i64p]),
         "addns_partition_destroy": (None, [P]),
         "addns_precond_destroy": (None, [P]),
         "addns_last_error": (C.c_char_p, []),
@@ -183,6 +186,26 @@ class Partition:
             "pair")]), "partition_export")
         return PartitionArrays(status=self.status, **arr)
 
+    def coarse_space(self, piece):
+        """The coarse space of opts.coarse = piece: (piece_offsets, piece_pos,
+        col_piece, col_kind, z0, z1), see addns_partition_coarse_space."""
+        npc, nc = C.c_int32(), C.c_int32()
+        _check(lib().addns_partition_coarse_space(self.handle, int(piece), C.byref(npc), C.byref(nc),
+                                                  None, None, None, None, None, None), "partition_coarse_space")
+        inf = self.info()
+        ns = inf["sep_size"]
+        offs = np.empty(npc.value + 1, np.int32)
+        _check(lib().addns_partition_coarse_space(self.handle, int(piece), None, None, _ptr(offs), None, None,
+                                                  None, None, None), "partition_coarse_space")
+        arr = dict(piece_offsets=offs, piece_pos=np.empty(int(offs[-1]), np.int32),
+                   col_piece=np.empty(nc.value, np.int32), col_kind=np.empty(nc.value, np.int32),
+                   z0=np.empty(ns, np.float64), z1=np.empty(ns, np.float64))
+        _check(lib().addns_partition_coarse_space(self.handle, int(piece), None, None, _ptr(offs),
+                                                  *[_ptr(arr[n]) for n in ("piece_pos", "col_piece", "col_kind",
+                                                                           "z0", "z1")]),
+               "partition_coarse_space")
+        return arr
+
 
 def build_partition(N, rowptr, colidx, vals, m, sz) -> Partition:
     rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
@@ -238,6 +261,13 @@ class Precond:
         d["chunk_bytes"] = cb.value
         return d
 
+    def fill(self):
+        """(nnz of the preconditioner, nnz of C): the fill factor of section 5
+        is their ratio (addns_precond_fill)."""
+        a, b = C.c_int64(), C.c_int64()
+        _check(lib().addns_precond_fill(self.handle, C.byref(a), C.byref(b)), "precond_fill")
+        return a.value, b.value
+
     def schur_blocks(self, count):
         out = np.empty(int(count), np.float64)
         _check(lib().addns_precond_schur_blocks(self.handle, _ptr(out), int(count)),
@@ -248,10 +278,10 @@ class Precond:
 def setup_precond(partition: Partition, N, d_rowptr, d_colidx, d_vals, schur=SCHUR_MSCN,
                   interior_prec=F64, schur_prec=F64, row_scale=1, learned_model=None,
                   block_mult=1, learned_bf16=True, overlap=0, ilu_tol=0.0, sweep_chunks=0,
-                  stream=None) -> Precond:
+                  coarse=0, sweep_zero_skip=0, stream=None) -> Precond:
     opts = PrecondOpts(int(schur), int(interior_prec), int(schur_prec), int(row_scale), None,
                        int(block_mult), int(bool(learned_bf16)), int(overlap), float(ilu_tol),
-                       int(sweep_chunks))
+                       int(sweep_chunks), int(coarse), int(sweep_zero_skip))
     if learned_model is not None:
         lm = np.ascontiguousarray(learned_model, dtype=np.float32)
         opts.learned_model = lm.ctypes.data_as(C.POINTER(C.c_float))

@@ -20,6 +20,8 @@ hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 int prec_bytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
 
+void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipStream_t s);
+
 // Factor and interface storage of one preconditioner.
 // Builds the plan from P (or keeps the handle's plan when P is null: a
 // refactor) and computes every numeric part of the preconditioner.
@@ -250,6 +252,10 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
   }
   ADDNS_HIP(hipStreamSynchronize(s));
 
+  // -- coarse-grid correction of the interface solve (section 6)
+  pc->coarse_nc = 0;
+  if (o.coarse > 0 && pl.nsep > 0) setup_coarse(pc, P, o.coarse, s);
+
   // permuted in/out vectors of addns_apply_precond: allocated here so that
   // an apply launches kernels only (and can be captured in a graph)
   pc->vperm_in.alloc(sizeof(double) * N);
@@ -271,12 +277,96 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
   pc->bytes_apply = 2 * band * fb + 2 * 4 * (int64_t)pl.n_int +
                     (int64_t)(pl.e_src.size() + pl.f_src.size()) * 12 + a_total * prec_bytes(sprec) + m_bytes +
                     6 * (int64_t)N * 8;
+  // coarse correction: E_c^{-1}, S Z (value + column), the coarse vectors
+  // and piece ids, and t written once and read once
+  if (pc->coarse_nc > 0)
+    pc->bytes_apply += (int64_t)pc->coarse_nc * pc->coarse_nc * 8 + (int64_t)pc->coarse.sz_col.size() * 12 +
+                       (int64_t)pl.nsep * (4 + 8 + 8 + 16);
+}
+
+// Coarse-grid correction of the interface solve: the coarse space from the
+// partition (a refactor keeps it), S Z = G Z - F D^{-1} E Z from one interior
+// sweep per (subdomain, coarse column) pair, E_c = Z^T S Z and its inverse.
+void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipStream_t s) {
+  const Plan& pl = pc->plan;
+  CoarsePlan& cp = pc->coarse;
+  pc->coarse_nc = 0;
+  if (P) build_coarse_plan(*P, pl, piece, cp);
+  const CoarseSpace& z = cp.space;
+  const int32_t nc = z.nc;
+  if (nc > kMaxCoarseColumns)
+    throw ArgError("coarse space of " + std::to_string(nc) + " columns exceeds 8192 (use a larger piece size)");
+  pc->cz_piece.upload(z.node_piece, s);
+  pc->cz_z0.upload(z.node_z0, s);
+  pc->cz_z1.upload(z.node_z1, s);
+  pc->cz_colp.upload(z.col_piece, s);
+  pc->cz_colk.upload(z.col_kind, s);
+  pc->cz_p0.upload(z.piece_col0, s);
+  pc->cz_p1.upload(z.piece_col1, s);
+  pc->cz_szp.upload(cp.sz_rowptr, s);
+  pc->cz_szc.upload(cp.sz_col, s);
+  pc->cz_szv.alloc(sizeof(double) * cp.sz_col.size());
+  pc->cz_goff.upload(cp.grp_off, s);
+  pc->cz_grows.upload(cp.grp_rows, s);
+  pc->cz_gc0.upload(cp.grp_col0, s);
+  pc->cz_gc1.upload(cp.grp_col1, s);
+  pc->cz_gcoff.upload(cp.grp_coff, s);
+  pc->cz_gcols.upload(cp.grp_cols, s);
+  pc->cz_t.alloc(sizeof(double) * std::max<int32_t>(pl.nsep, 1));
+  pc->cz_g.alloc(sizeof(double) * std::max<int32_t>(nc, 1));
+  pc->cz_y.alloc(sizeof(double) * std::max<int32_t>(nc, 1));
+  pc->cz_einv.alloc(sizeof(double) * std::max<int64_t>((int64_t)nc * nc, 1));
+  if (nc == 0) return;
+  std::vector<int32_t> int_off(pl.m);
+  for (int32_t j = 0; j < pl.m; ++j) int_off[j] = pl.subs[j].int_off;
+  DevBuf psub, pcol, poff, cpp, subof, ioff, W, scratch, perm, work, info;
+  psub.upload(cp.pair_sub, s);
+  pcol.upload(cp.pair_col, s);
+  poff.upload(cp.pair_off, s);
+  cpp.upload(cp.cpair_ptr, s);
+  subof.upload(cp.sub_of, s);
+  ioff.upload(int_off, s);
+  W.alloc(sizeof(double) * std::max<int64_t>(cp.pair_total, 1));
+  scratch.alloc(sizeof(double) * std::max<int64_t>(cp.pair_total, 1));
+  const int32_t npairs = (int32_t)cp.pair_sub.size();
+  launch_coarse_column_solves(pc, npairs, psub.as<int32_t>(), pcol.as<int32_t>(), poff.as<int64_t>(),
+                              scratch.as<double>(), W.as<double>(), 0, s);
+  // one FP64 refinement step: E_c^{-1} amplifies errors of S Z by cond(E_c),
+  // and the sweep's explicitly inverted blocks (or FP32 factors) leave
+  // W = D^{-1} E Z accurate only to eps * cond(A_jj) of the storage
+  {
+    DevBuf dW;
+    dW.alloc(sizeof(double) * std::max<int64_t>(cp.pair_total, 1));
+    launch_coarse_refine(pc, npairs, psub.as<int32_t>(), pcol.as<int32_t>(), poff.as<int64_t>(), W.as<double>(),
+                         scratch.as<double>(), dW.as<double>(), s);
+    ADDNS_HIP(hipStreamSynchronize(s));
+  }
+  launch_coarse_sz(pc, subof.as<int32_t>(), psub.as<int32_t>(), cpp.as<int32_t>(), poff.as<int64_t>(),
+                   ioff.as<int32_t>(), W.as<double>(), s);
+  double* Ec = pc->cz_einv.as<double>();
+  ADDNS_HIP(hipMemsetAsync(Ec, 0, sizeof(double) * (size_t)nc * nc, s));
+  launch_coarse_ec(pc, nc, Ec, s);
+  perm.alloc(sizeof(int32_t) * nc);
+  work.alloc(sizeof(double) * (1 + 2 * (size_t)nc));
+  info.alloc(sizeof(int32_t));
+  ADDNS_HIP(hipMemsetAsync(info.p, 0, sizeof(int32_t), s));
+  launch_gj_invert(Ec, nc, perm.as<int32_t>(), work.as<double>(), info.as<int32_t>(), s);
+  int32_t h_info = 0;
+  ADDNS_HIP(hipMemcpyAsync(&h_info, info.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  ADDNS_HIP(hipStreamSynchronize(s));
+  if (h_info) throw SingularError("the coarse matrix Z^T S Z is singular (pivot " + std::to_string(h_info - 1) + ")");
+  pc->coarse_nc = nc;
 }
 
 void apply_permuted(addns_precond* pc, const double* yp, double* xp, hipStream_t s) {
   const Plan& pl = pc->plan;
   // z1 = D^{-1} y1 (into the interior part of xp)
   launch_interior_solve(pc, yp, xp, 0, nullptr, nullptr, s);
+  // two-level interface solve: t = y2 - F z1 and Z^T t, then y = E_c^{-1} Z^T t
+  if (pc->coarse_nc > 0) {
+    launch_coarse_restrict(pc, yp, xp, s);
+    launch_coarse_solve(pc, s);
+  }
   // x2 = Shat^{-1} (y2 - F z1): blockwise, then (overlapped aggregates) the
   // forward substitution over Shat's lower blocks
   launch_interface_solve(pc, yp, xp, xp, s);
@@ -310,11 +400,33 @@ float time_interior_solve(addns_precond* pc, hipStream_t s) {
 }
 
 // Chunk count of the interior sweep.  requested 1: none; >= 2: that many;
-// 0: the p that minimises a model of the chunked solve built on the measured
-// single-chunk sweep T1 over nU upper blocks: the longest chunk's
-// ceil(nU / p) blocks at T1 / nU each, plus about 5 us per chunk boundary
-// for the two recurrences; at most one workgroup per CU.  It is kept only if
-// the chunked solve times faster (with the better zero-slot form).
+// 0: the p that minimises a fixed model of the chunked solve, from the plan
+// and the device's CU count only (never from a timing, so the choice, and
+// with it the rounding of every solve, is the same on every run and box):
+// the longest chunk sweeps ceil(nU / p) of the nU upper blocks at
+// kSweepBlockUs each, every chunk boundary adds kSweepBoundaryUs for the two
+// recurrences, and p is capped at one workgroup per CU over the m interiors.
+// The constants are the per-block step and per-boundary costs measured on
+// the 128 x 128 workload (0.21 ms over 12 upper blocks; about 5 us).
+constexpr double kSweepBlockUs = 17.5, kSweepBoundaryUs = 5.0;
+
+int model_sweep_chunks(const Plan& pl, int cus) {
+  if (pl.m == 0 || pl.n_int == 0) return 1;
+  int32_t nu = 1;
+  for (const SubInfo& q : pl.subs) nu = std::max(nu, q.npad / q.nbu);
+  const int pcap = std::min(max_sweep_chunks(pl), std::max(1, cus / pl.m));
+  int p = 1;
+  double best = nu * kSweepBlockUs;
+  for (int c = 2; c <= pcap; ++c) {
+    const double model = (double)((nu + c - 1) / c) * kSweepBlockUs + kSweepBoundaryUs * (c - 1);
+    if (model < best) {
+      best = model;
+      p = c;
+    }
+  }
+  return p;
+}
+
 void choose_sweep_chunks(addns_precond* pc, int requested, hipStream_t s) {
   const Plan& pl = pc->plan;
   release_chunked_sweep(pc);
@@ -327,40 +439,19 @@ void choose_sweep_chunks(addns_precond* pc, int requested, hipStream_t s) {
   }
   hipDeviceProp_t prop;
   ADDNS_HIP(hipGetDeviceProperties(&prop, pc->device));
-  int32_t nu = 1;
-  for (const SubInfo& q : pl.subs) nu = std::max(nu, q.npad / q.nbu);
-  const double per_block = 1000.0 * pc->tuned_ms / nu, per_boundary = 5.0;
-  const int pcap = std::min(pmax, std::max(1, prop.multiProcessorCount / pl.m));
-  int p = 1;
-  double best = 1000.0 * pc->tuned_ms;
-  for (int c = 2; c <= pcap; ++c) {
-    const double model = (double)((nu + c - 1) / c) * per_block + per_boundary * (c - 1);
-    if (model < best) {
-      best = model;
-      p = c;
-    }
-  }
+  const int p = model_sweep_chunks(pl, prop.multiProcessorCount);
   if (p < 2) return;
-  const int z0 = pc->zero_skip;
-  const float t1 = pc->tuned_ms;
-  try {
-    build_chunked_sweep(pc, p, s);
-  } catch (const ArgError&) {
-    release_chunked_sweep(pc);
-    return;
-  }
+  build_chunked_sweep(pc, p, s);
+  // the zero-slot form is re-chosen for the chunked kernels (bitwise the
+  // same result either way), unless the caller fixed it
+  if (pc->opts.sweep_zero_skip != 0) return;
   float ms[2];
   for (int z = 0; z < 2; ++z) {
     pc->zero_skip = z;
     ms[z] = time_interior_solve(pc, s);
   }
-  if (std::min(ms[0], ms[1]) < t1) {
-    pc->zero_skip = ms[1] < ms[0] ? 1 : 0;
-    pc->tuned_ms = std::min(ms[0], ms[1]);
-  } else {
-    release_chunked_sweep(pc);
-    pc->zero_skip = z0;
-  }
+  pc->zero_skip = ms[1] < ms[0] ? 1 : 0;
+  pc->tuned_ms = std::min(ms[0], ms[1]);
 }
 
 struct GmresWork {
@@ -424,8 +515,11 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
   return guarded("addns_setup_precond", [&]() -> int {
     if (!p || !out || !d_rowptr || !d_colidx || !d_vals) throw ArgError("null argument");
     if (N != p->d.N) throw ArgError("N does not match the partition");
-    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1, 0, 0, 0.0, 0};
+    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1, 0, 0, 0.0, 0, 0, 0};
     if (opts) o = *opts;
+    if (o.sweep_zero_skip < 0 || o.sweep_zero_skip > 2) throw ArgError("sweep_zero_skip must be 0, 1 or 2");
+    if (o.coarse < 0 || o.coarse > 64) throw ArgError("coarse piece size must lie in 0..64");
+    if (o.coarse > 0 && o.overlap > 0) throw ArgError("the coarse correction is built for non-overlapping aggregates");
     if (o.schur < 0 || o.schur > ADDNS_SCHUR_MSCNR) throw ArgError("unknown schur mode");
     if (o.overlap < 0) throw ArgError("overlap must be >= 0");
     if (o.overlap > 0 && o.schur != ADDNS_SCHUR_MSCN && o.schur != ADDNS_SCHUR_MSCNR && o.schur != ADDNS_SCHUR_LUM)
@@ -453,35 +547,25 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
         pc->opts.learned_model = nullptr;  // the caller's array is not kept
       }
       // the sweep's zero-slot skipping (bitwise the same result either way)
-      // is chosen by timing both forms on these factors
-      float ms[2];
-      for (int z = 0; z < 2; ++z) {
-        pc->zero_skip = z;
-        ms[z] = time_interior_solve(pc.get(), as_stream(stream));
+      // is chosen by timing both forms on these factors, or fixed by the caller
+      if (o.sweep_zero_skip == 0) {
+        float ms[2];
+        for (int z = 0; z < 2; ++z) {
+          pc->zero_skip = z;
+          ms[z] = time_interior_solve(pc.get(), as_stream(stream));
+        }
+        pc->zero_skip = ms[1] < ms[0] ? 1 : 0;
+        pc->tuned_ms = std::min(ms[0], ms[1]);
+      } else {
+        pc->zero_skip = o.sweep_zero_skip == 2 ? 1 : 0;
       }
-      pc->zero_skip = ms[1] < ms[0] ? 1 : 0;
-      pc->tuned_ms = std::min(ms[0], ms[1]);
       choose_sweep_chunks(pc.get(), o.sweep_chunks, as_stream(stream));
       pc->opts.sweep_chunks = pc->sweep_chunks;
       return pc;
     };
-    if (!autotune) {
-      *out = make(o.block_mult).release();
-      return ADDNS_OK;
-    }
-    // Autotuner: the sweep block size is a tile shape (the same LU factors,
-    // regrouped), chosen by timing the interior solve on these factors.
-    std::unique_ptr<addns_precond> best;
-    float best_ms = 0.0f;
-    for (int mult : {1, 2}) {
-      std::unique_ptr<addns_precond> pc = make(mult);
-      const float ms = pc->tuned_ms;
-      if (!best || ms < best_ms) {
-        best = std::move(pc);
-        best_ms = ms;
-      }
-    }
-    *out = best.release();
+    // block_mult = 0: a fixed choice (1), not a timing: the sweep block size
+    // regroups the same factors but changes the rounding of a solve
+    *out = make(autotune ? 1 : o.block_mult).release();
     return ADDNS_OK;
   });
 }
@@ -843,6 +927,21 @@ int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb
   if (interior_nnz) *interior_nnz = pc->interior_nnz;
   if (sweep_chunks) *sweep_chunks = pc->sweep_chunks;
   if (chunk_bytes) *chunk_bytes = pc->chunk_bytes;
+  return ADDNS_OK;
+}
+
+int addns_precond_fill(addns_precond_t pc, int64_t* nnz_precond, int64_t* nnz_c) {
+  if (!pc) {
+    set_error("addns_precond_fill: null handle");
+    return ADDNS_ERR_ARG;
+  }
+  const Plan& pl = pc->plan;
+  int64_t shat = 0;
+  for (int32_t i = 0; i < pl.k; ++i) shat += (int64_t)pl.agg_s[i] * pl.agg_s[i];
+  if (pl.overlap > 0) shat += pl.l_off[pl.k];
+  if (nnz_precond)
+    *nnz_precond = pc->interior_nnz + shat + (int64_t)pl.e_src.size() + (int64_t)pl.f_src.size();
+  if (nnz_c) *nnz_c = (int64_t)pl.cp_colidx.size();
   return ADDNS_OK;
 }
 

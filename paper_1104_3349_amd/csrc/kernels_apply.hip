@@ -194,6 +194,15 @@ struct SweepArgs {
   const int32_t* pair_sub;
   const int32_t* pair_col;
   const int64_t* pair_off;
+  // mode 2 with a coarse space: pair_col names a coarse column z_c and the
+  // right-hand side is E(int_j, :) z_c, z_c held per separator position as
+  // (piece, constant value, linear value)
+  const int32_t* cz_piece;
+  const double* cz_z0;
+  const double* cz_z1;
+  const int32_t* cz_colp;
+  const int32_t* cz_colk;
+  int32_t pair_rhs_given;  // mode 2: the right-hand side is already in the scratch
 };
 
 // One workgroup per subdomain.  mode 0: out[int] = D^{-1} yin[int].
@@ -241,12 +250,17 @@ k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int m
   if (nL > 0) prefetch_gemv<T, S, 4, Z>(A, B, gl, lmat, nbL, lperm);
   // modes 1 and 2: the sweep input (E x2, or column pcol of E) into ypad;
   // the lower sweep writes ypad only below the rows it still has to read
-  if (mode != 0) {
+  if (mode != 0 && !(mode == 2 && a.pair_rhs_given)) {
+    const int32_t zp = (mode == 2 && a.cz_piece) ? a.cz_colp[pcol] : -1;
+    const double* zv = (mode == 2 && a.cz_piece) ? (a.cz_colk[pcol] ? a.cz_z1 : a.cz_z0) : nullptr;
     for (int32_t r = tid; r < n; r += blockDim.x) {
       double s = 0.0;
       for (int32_t e = a.e_rowptr[ioff + r]; e < a.e_rowptr[ioff + r + 1]; ++e) {
-        if (mode == 1) s += a.e_vals[e] * x2[a.e_colidx[e]];
-        else if (a.e_colidx[e] == pcol) s += a.e_vals[e];
+        const int32_t c = a.e_colidx[e];
+        if (mode == 1) s += a.e_vals[e] * x2[c];
+        else if (zv) {
+          if (a.cz_piece[c] == zp) s += a.e_vals[e] * zv[c];
+        } else if (c == pcol) s += a.e_vals[e];
       }
       ypad[r] = s;
     }
@@ -721,12 +735,30 @@ __global__ void k_lower_zero_rows(const LBlk* __restrict__ lb, const SubInfo* __
 // chunk partials meet in LDS in a fixed order.
 constexpr int kIfPref = 16;
 
+// With a coarse space (cz.t non-null) the kernel is the last step of the
+// two-level interface solve: t comes precomputed (with y = E_c^{-1} Z^T t
+// already formed), the block solve acts on r = t - (S Z) y and the coarse
+// part Z y is added to the result.
+struct CoarseApply {
+  const double* t;       // separator vector t = y2 - F z1
+  const double* y;       // coarse solution
+  const int32_t* szp;    // S Z, CSR over separator rows
+  const int32_t* szc;
+  const double* szv;
+  const int32_t* piece;  // per separator position
+  const double* z0;
+  const double* z1;
+  const int32_t* p0;     // per piece: constant / linear column (-1 none)
+  const int32_t* p1;
+};
+
 template <class T>
 __global__ void __launch_bounds__(1024)
 k_interface_solve(int32_t n_int, const int32_t* __restrict__ agg_off, const int32_t* __restrict__ f_rowptr,
                   const int32_t* __restrict__ f_colidx, const double* __restrict__ f_vals,
                   const int64_t* __restrict__ sinv_off, const T* __restrict__ sinv, const float* __restrict__ scale,
-                  int scaled, const double* __restrict__ y, const double* __restrict__ z1, double* __restrict__ out) {
+                  int scaled, const double* __restrict__ y, const double* __restrict__ z1, double* __restrict__ out,
+                  CoarseApply cz) {
   __shared__ double t[1024];
   __shared__ double part[1024];
   const int i = blockIdx.x;
@@ -748,11 +780,25 @@ k_interface_solve(int32_t n_int, const int32_t* __restrict__ agg_off, const int3
   }
   for (int32_t q = tid; q < s; q += blockDim.x) {
     const int32_t row = a0 + q;
-    double acc = y[n_int + row];
-    for (int32_t e = f_rowptr[row]; e < f_rowptr[row + 1]; ++e) acc -= f_vals[e] * z1[f_colidx[e]];
+    double acc;
+    if (cz.t) {
+      acc = cz.t[row];
+      for (int32_t e = cz.szp[row]; e < cz.szp[row + 1]; ++e) acc -= cz.szv[e] * cz.y[cz.szc[e]];
+    } else {
+      acc = y[n_int + row];
+      for (int32_t e = f_rowptr[row]; e < f_rowptr[row + 1]; ++e) acc -= f_vals[e] * z1[f_colidx[e]];
+    }
     t[q] = acc;
   }
   __syncthreads();
+  // Z y on row `row` (separator position), 0 without a coarse space
+  auto zy = [&](int32_t row) -> double {
+    if (!cz.t) return 0.0;
+    const int32_t pc = cz.piece[row];
+    if (pc < 0) return 0.0;
+    const int32_t c1 = cz.p1[pc];
+    return cz.z0[row] * cz.y[cz.p0[pc]] + (c1 >= 0 ? cz.z1[row] * cz.y[c1] : 0.0);
+  };
   if (pref) {
     double acc = 0.0;
 #pragma unroll
@@ -764,7 +810,7 @@ k_interface_solve(int32_t n_int, const int32_t* __restrict__ agg_off, const int3
       double acc2 = 0.0;
       for (int c = 0; c < CS; ++c) acc2 += part[c * Rp + r];
       if (scaled) acc2 *= (double)scale[i];
-      out[n_int + a0 + r] = acc2;
+      out[n_int + a0 + r] = acc2 + zy(a0 + r);
     }
     return;
   }
@@ -779,7 +825,7 @@ k_interface_solve(int32_t n_int, const int32_t* __restrict__ agg_off, const int3
       double acc2 = 0.0;
       for (int c = 0; c < CS; ++c) acc2 += part[c * Rp + r];
       if (scaled) acc2 *= (double)scale[i];
-      out[n_int + a0 + row] = acc2;
+      out[n_int + a0 + row] = acc2 + zy(a0 + row);
     }
     __syncthreads();
   }
@@ -1208,9 +1254,40 @@ void launch_column_solves(const addns_precond* pc, int32_t npairs, const int32_t
   run_sweep(pc, a, npairs, nullptr, out, 2, nullptr, nullptr, s);
 }
 
+void launch_coarse_column_solves(const addns_precond* pc, int32_t npairs, const int32_t* pair_sub,
+                                 const int32_t* pair_col, const int64_t* pair_off, double* scratch, double* out,
+                                 int rhs_given, hipStream_t s) {
+  if (npairs == 0) return;
+  SweepArgs a = sweep_args(pc);
+  a.pair_rhs_given = rhs_given;
+  a.ypad = scratch;
+  a.pair_sub = pair_sub;
+  a.pair_col = pair_col;
+  a.pair_off = pair_off;
+  a.cz_piece = pc->cz_piece.as<int32_t>();
+  a.cz_z0 = pc->cz_z0.as<double>();
+  a.cz_z1 = pc->cz_z1.as<double>();
+  a.cz_colp = pc->cz_colp.as<int32_t>();
+  a.cz_colk = pc->cz_colk.as<int32_t>();
+  run_sweep(pc, a, npairs, nullptr, out, 2, nullptr, nullptr, s);
+}
+
 void launch_interface_solve(const addns_precond* pc, const double* y, const double* z1, double* out, hipStream_t s) {
   const Plan& pl = pc->plan;
   if (pl.k == 0) return;
+  CoarseApply cz{};
+  if (pc->coarse_nc > 0) {
+    cz.t = pc->cz_t.as<double>();
+    cz.y = pc->cz_y.as<double>();
+    cz.szp = pc->cz_szp.as<int32_t>();
+    cz.szc = pc->cz_szc.as<int32_t>();
+    cz.szv = pc->cz_szv.as<double>();
+    cz.piece = pc->cz_piece.as<int32_t>();
+    cz.z0 = pc->cz_z0.as<double>();
+    cz.z1 = pc->cz_z1.as<double>();
+    cz.p0 = pc->cz_p0.as<int32_t>();
+    cz.p1 = pc->cz_p1.as<int32_t>();
+  }
   const int32_t* ao = pc->agg_off.as<int32_t>();
   const int32_t* fr = pc->f_rowptr.as<int32_t>();
   const int32_t* fc = pc->f_colidx.as<int32_t>();
@@ -1218,13 +1295,13 @@ void launch_interface_solve(const addns_precond* pc, const double* y, const doub
   const int64_t* so = pc->sinv_off.as<int64_t>();
   if (pc->schur_prec == P64)
     k_interface_solve<double><<<pl.k, 1024, 0, s>>>(pl.n_int, ao, fr, fc, fv, so, pc->sinv.as<double>(), nullptr, 0, y,
-                                                   z1, out);
+                                                   z1, out, cz);
   else if (pc->schur_prec == P32)
     k_interface_solve<float><<<pl.k, 1024, 0, s>>>(pl.n_int, ao, fr, fc, fv, so, pc->sinv.as<float>(), nullptr, 0, y,
-                                                  z1, out);
+                                                  z1, out, cz);
   else
     k_interface_solve<__half><<<pl.k, 1024, 0, s>>>(pl.n_int, ao, fr, fc, fv, so, pc->sinv.as<__half>(),
-                                                   pc->sinv_scale.as<float>(), 1, y, z1, out);
+                                                   pc->sinv_scale.as<float>(), 1, y, z1, out, cz);
 }
 
 void launch_permute(const int32_t* perm, const double* in, double* out, int32_t n, int inverse, const double* scale,

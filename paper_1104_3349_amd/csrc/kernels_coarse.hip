@@ -1,0 +1,359 @@
+// Kernels of the coarse-grid correction of the interface solve (section 6
+// proposes a coarse grid correction; the two-level form is
+//   y = E_c^{-1} Z^T t,   x2 = Z y + Shat^{-1} (t - S Z y),
+// with E_c = Z^T S Z and S = G - F D^{-1} E the interface Schur complement).
+//
+// Setup: S Z column by column from its definition (the columns D_j^{-1} E_j z_c
+// come from the interior sweep), E_c = Z^T S Z, and E_c^{-1} by Gauss-Jordan
+// elimination with partial pivoting.  Apply: the restriction t, Z^T t; the
+// coarse solve y = E_c^{-1} (Z^T t); the block solve on t - S Z y with Z y
+// added (k_interface_solve).  Every reduction runs in a fixed order, so the
+// results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "precond.h"
+
+namespace addns {
+namespace {
+
+// Sum over the 64 lanes of a wave in a fixed butterfly order.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One wave per separator row of S Z: the entry for coarse column c is
+//   (G z_c)(row) - sum_j F(row, int_j) W_(j,c),
+// W_(j,c) = D_j^{-1} E_j z_c from the column solves.
+__global__ void k_coarse_sz(int32_t ns, int32_t n_int, const int32_t* __restrict__ cp_rowptr,
+                            const int32_t* __restrict__ cp_colidx, const double* __restrict__ cp_vals,
+                            const int32_t* __restrict__ f_rowptr, const int32_t* __restrict__ f_colidx,
+                            const double* __restrict__ f_vals, const int32_t* __restrict__ piece,
+                            const double* __restrict__ z0, const double* __restrict__ z1,
+                            const int32_t* __restrict__ colp, const int32_t* __restrict__ colk,
+                            const int32_t* __restrict__ szp, const int32_t* __restrict__ szc,
+                            const int32_t* __restrict__ sub_of, const int32_t* __restrict__ int_off,
+                            const int32_t* __restrict__ pair_sub, const int32_t* __restrict__ cpair_ptr,
+                            const int64_t* __restrict__ pair_off, const double* __restrict__ W,
+                            double* __restrict__ szv) {
+  const int32_t row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (row >= ns) return;
+  const int32_t r = n_int + row;
+  for (int32_t e = szp[row] + lane; e < szp[row + 1]; e += 64) {
+    const int32_t c = szc[e];
+    const int32_t pc = colp[c];
+    const double* zv = colk[c] ? z1 : z0;
+    double acc = 0.0;
+    for (int32_t t = cp_rowptr[r]; t < cp_rowptr[r + 1]; ++t) {
+      const int32_t col = cp_colidx[t];
+      if (col >= n_int && piece[col - n_int] == pc) acc += cp_vals[t] * zv[col - n_int];
+    }
+    for (int32_t t = f_rowptr[row]; t < f_rowptr[row + 1]; ++t) {
+      const int32_t col = f_colidx[t];
+      const int32_t j = sub_of[col];
+      int64_t off = -1;
+      for (int32_t q = cpair_ptr[c]; q < cpair_ptr[c + 1]; ++q)
+        if (pair_sub[q] == j) off = pair_off[q];
+      if (off >= 0) acc -= f_vals[t] * W[off + (col - int_off[j])];
+    }
+    szv[e] = acc;
+  }
+}
+
+// One wave per restriction group (a piece): the rows of E_c that belong to
+// the group's columns, E_c(c', c) = sum over the group's rows, in their stored
+// order, of z_c'(row) S Z(row, c).  Each lane owns columns c of the group's
+// column list and accumulates them in registers (S Z(row, c) found by binary
+// search in the row's ascending column list); no element is written twice.
+__global__ void k_coarse_ec(int32_t ngrp, int32_t nc, const int32_t* __restrict__ goff,
+                            const int32_t* __restrict__ grows, const int32_t* __restrict__ gc0,
+                            const int32_t* __restrict__ gc1, const int32_t* __restrict__ gcoff,
+                            const int32_t* __restrict__ gcols, const double* __restrict__ z0,
+                            const double* __restrict__ z1, const int32_t* __restrict__ szp,
+                            const int32_t* __restrict__ szc, const double* __restrict__ szv,
+                            double* __restrict__ Ec) {
+  const int32_t g = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (g >= ngrp) return;
+  const int32_t c0 = gc0[g], c1 = gc1[g];
+  if (c0 < 0) return;
+  for (int32_t q = gcoff[g] + lane; q < gcoff[g + 1]; q += 64) {
+    const int32_t c = gcols[q];
+    double a0 = 0.0, a1 = 0.0;
+    for (int32_t t = goff[g]; t < goff[g + 1]; ++t) {
+      const int32_t row = grows[t];
+      int32_t lo = szp[row], hi = szp[row + 1];
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) / 2;
+        if (szc[mid] < c) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < szp[row + 1] && szc[lo] == c) {
+        const double v = szv[lo];
+        a0 += z0[row] * v;
+        a1 += z1[row] * v;
+      }
+    }
+    Ec[(int64_t)c0 * nc + c] = a0;
+    if (c1 >= 0) Ec[(int64_t)c1 * nc + c] = a1;
+  }
+}
+
+// Residual of the (subdomain, coarse column) solves in FP64, one workgroup
+// per pair: scratch = E_j z_c - A_jj W on the interior rows of subdomain j,
+// both read from the permuted, scaled C (separator columns: E; columns of
+// the same interior: A_jj).
+__global__ void k_pair_residual(int32_t n_int, const SubInfo* __restrict__ subs, const int32_t* __restrict__ pair_sub,
+                                const int32_t* __restrict__ pair_col, const int64_t* __restrict__ pair_off,
+                                const int32_t* __restrict__ cp_rowptr, const int32_t* __restrict__ cp_colidx,
+                                const double* __restrict__ cp_vals, const int32_t* __restrict__ piece,
+                                const double* __restrict__ z0, const double* __restrict__ z1,
+                                const int32_t* __restrict__ colp, const int32_t* __restrict__ colk,
+                                const double* __restrict__ W, double* __restrict__ scratch) {
+  const int32_t q = blockIdx.x;
+  const SubInfo sb = subs[pair_sub[q]];
+  const int32_t c = pair_col[q], pc = colp[c];
+  const double* zv = colk[c] ? z1 : z0;
+  const int64_t off = pair_off[q];
+  for (int32_t r = threadIdx.x; r < sb.n; r += blockDim.x) {
+    const int32_t R = sb.int_off + r;
+    double acc = 0.0;
+    for (int32_t t = cp_rowptr[R]; t < cp_rowptr[R + 1]; ++t) {
+      const int32_t col = cp_colidx[t];
+      if (col >= n_int) {
+        if (piece[col - n_int] == pc) acc += cp_vals[t] * zv[col - n_int];
+      } else if (col >= sb.int_off && col < sb.int_off + sb.n) {
+        acc -= cp_vals[t] * W[off + (col - sb.int_off)];
+      }
+    }
+    scratch[off + r] = acc;
+  }
+}
+
+// W += dW on the interior rows of every pair.
+__global__ void k_pair_add(const SubInfo* __restrict__ subs, const int32_t* __restrict__ pair_sub,
+                           const int64_t* __restrict__ pair_off, const double* __restrict__ dW, double* __restrict__ W) {
+  const int32_t q = blockIdx.x;
+  const int32_t n = subs[pair_sub[q]].n;
+  const int64_t off = pair_off[q];
+  for (int32_t r = threadIdx.x; r < n; r += blockDim.x) W[off + r] += dW[off + r];
+}
+
+// Largest |A| (one workgroup), the scale of the singularity test.
+__global__ void __launch_bounds__(1024) k_absmax(const double* __restrict__ A, int64_t n, double* __restrict__ out) {
+  __shared__ double red[1024];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, fabs(A[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// Gauss-Jordan step k, part 1 (one workgroup): pivot = first row i >= k of
+// largest |A(i,k)|; swap rows k and pivot; copy the pivot row and column k.
+// work: [0] largest |A|, then prow (n), mcol (n).
+__global__ void __launch_bounds__(1024) k_gj_pivot(double* __restrict__ A, int32_t n, int32_t k,
+                                                   int32_t* __restrict__ perm, double* __restrict__ work,
+                                                   int32_t* __restrict__ info) {
+  __shared__ double bv[1024];
+  __shared__ int32_t bi[1024];
+  const int tid = threadIdx.x;
+  double best = -1.0;
+  int32_t bidx = n;
+  for (int32_t i = k + tid; i < n; i += blockDim.x) {
+    const double v = fabs(A[(int64_t)i * n + k]);
+    if (v > best) {
+      best = v;
+      bidx = i;
+    }
+  }
+  bv[tid] = best;
+  bi[tid] = bidx;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (tid < o) {
+      const double v2 = bv[tid + o];
+      const int32_t i2 = bi[tid + o];
+      if (v2 > bv[tid] || (v2 == bv[tid] && i2 < bi[tid])) {
+        bv[tid] = v2;
+        bi[tid] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  const int32_t p = bi[0];
+  if (tid == 0) {
+    perm[k] = p;
+    if (!(bv[0] > 1e-13 * work[0])) info[0] = k + 1;
+  }
+  double* prow = work + 1;
+  double* mcol = prow + n;
+  // copies first, from the matrix before the interchange (rows k and p
+  // trade places); every load has returned before its thread reaches the
+  // barrier, so the interchange below cannot overtake them
+  for (int32_t i = tid; i < n; i += blockDim.x) {
+    const int32_t src = i == k ? p : (i == p ? k : i);
+    mcol[i] = A[(int64_t)src * n + k];
+  }
+  for (int32_t j = tid; j < n; j += blockDim.x) prow[j] = A[(int64_t)p * n + j];
+  __syncthreads();
+  if (p != k)
+    for (int32_t j = tid; j < n; j += blockDim.x) {
+      const double a = A[(int64_t)k * n + j], b = A[(int64_t)p * n + j];
+      A[(int64_t)k * n + j] = b;
+      A[(int64_t)p * n + j] = a;
+    }
+}
+
+// Gauss-Jordan step k, part 2: in-place inverse update with the copied
+// pivot row and column (every element reads only copies and itself).
+__global__ void k_gj_update(double* __restrict__ A, int32_t n, int32_t k, const double* __restrict__ work) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t i = blockIdx.y;
+  if (j >= n) return;
+  const double* prow = work + 1;
+  const double* mcol = prow + n;
+  const double piv = prow[k];
+  const double inv = 1.0 / piv;
+  double& a = A[(int64_t)i * n + j];
+  if (i == k) a = j == k ? inv : prow[j] * inv;
+  else if (j == k) a = -mcol[i] * inv;
+  else a -= mcol[i] * (prow[j] * inv);
+}
+
+// Undo the row interchanges on the columns of the inverse: inv(A) is
+// inv(P A) with its columns swapped back in reverse order.
+__global__ void k_gj_colswap(double* __restrict__ A, int32_t n, const int32_t* __restrict__ perm) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double* row = A + (int64_t)i * n;
+  for (int32_t k = n - 1; k >= 0; --k) {
+    const int32_t p = perm[k];
+    if (p != k) {
+      const double t = row[k];
+      row[k] = row[p];
+      row[p] = t;
+    }
+  }
+}
+
+// Restriction (one wave per group): t = y2 - F z1 on the group's rows, and
+// for a piece its two entries of g = Z^T t.
+__global__ void k_coarse_restrict(int32_t ngrp, int32_t n_int, const int32_t* __restrict__ goff,
+                                  const int32_t* __restrict__ grows, const int32_t* __restrict__ gc0,
+                                  const int32_t* __restrict__ gc1, const int32_t* __restrict__ f_rowptr,
+                                  const int32_t* __restrict__ f_colidx, const double* __restrict__ f_vals,
+                                  const double* __restrict__ z0, const double* __restrict__ z1,
+                                  const double* __restrict__ y, const double* __restrict__ zin,
+                                  double* __restrict__ t, double* __restrict__ g) {
+  const int32_t grp = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (grp >= ngrp) return;
+  const int32_t a = goff[grp], cnt = goff[grp + 1] - a;
+  double p0 = 0.0, p1 = 0.0;
+  if (lane < cnt) {
+    const int32_t row = grows[a + lane];
+    double acc = y[n_int + row];
+    for (int32_t e = f_rowptr[row]; e < f_rowptr[row + 1]; ++e) acc -= f_vals[e] * zin[f_colidx[e]];
+    t[row] = acc;
+    p0 = z0[row] * acc;
+    p1 = z1[row] * acc;
+  }
+  const int32_t c0 = gc0[grp], c1 = gc1[grp];
+  if (c0 >= 0) {
+    p0 = wave_sum(p0);
+    p1 = wave_sum(p1);
+    if (lane == 0) {
+      g[c0] = p0;
+      if (c1 >= 0) g[c1] = p1;
+    }
+  }
+}
+
+// Coarse solve y = E_c^{-1} g, one wave per row of the row-major inverse.
+__global__ void k_coarse_solve(int32_t nc, const double* __restrict__ Einv, const double* __restrict__ g,
+                               double* __restrict__ y) {
+  const int32_t i = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (i >= nc) return;
+  const double* row = Einv + (int64_t)i * nc;
+  double acc = 0.0;
+  for (int32_t j = lane; j < nc; j += 64) acc += row[j] * g[j];
+  acc = wave_sum(acc);
+  if (lane == 0) y[i] = acc;
+}
+
+}  // namespace
+
+void launch_coarse_sz(const addns_precond* pc, const int32_t* sub_of, const int32_t* pair_sub,
+                      const int32_t* cpair_ptr, const int64_t* pair_off, const int32_t* int_off,
+                      const double* W, hipStream_t s) {
+  const Plan& pl = pc->plan;
+  if (pl.nsep == 0) return;
+  const int waves = 4;
+  k_coarse_sz<<<(pl.nsep + waves - 1) / waves, 64 * waves, 0, s>>>(
+      pl.nsep, pl.n_int, pc->cp_rowptr.as<int32_t>(), pc->cp_colidx.as<int32_t>(), pc->cp_vals.as<double>(),
+      pc->f_rowptr.as<int32_t>(), pc->f_colidx.as<int32_t>(), pc->f_vals.as<double>(), pc->cz_piece.as<int32_t>(),
+      pc->cz_z0.as<double>(), pc->cz_z1.as<double>(), pc->cz_colp.as<int32_t>(), pc->cz_colk.as<int32_t>(),
+      pc->cz_szp.as<int32_t>(), pc->cz_szc.as<int32_t>(), sub_of, int_off, pair_sub, cpair_ptr, pair_off, W,
+      pc->cz_szv.as<double>());
+}
+
+void launch_coarse_refine(const addns_precond* pc, int32_t npairs, const int32_t* pair_sub, const int32_t* pair_col,
+                          const int64_t* pair_off, double* W, double* scratch, double* dW, hipStream_t s) {
+  if (npairs == 0) return;
+  k_pair_residual<<<npairs, 256, 0, s>>>(pc->plan.n_int, pc->subs.as<SubInfo>(), pair_sub, pair_col, pair_off,
+                                         pc->cp_rowptr.as<int32_t>(), pc->cp_colidx.as<int32_t>(),
+                                         pc->cp_vals.as<double>(), pc->cz_piece.as<int32_t>(), pc->cz_z0.as<double>(),
+                                         pc->cz_z1.as<double>(), pc->cz_colp.as<int32_t>(), pc->cz_colk.as<int32_t>(),
+                                         W, scratch);
+  launch_coarse_column_solves(pc, npairs, pair_sub, pair_col, pair_off, scratch, dW, 1, s);
+  k_pair_add<<<npairs, 256, 0, s>>>(pc->subs.as<SubInfo>(), pair_sub, pair_off, dW, W);
+}
+
+void launch_coarse_ec(const addns_precond* pc, int32_t nc, double* Ec, hipStream_t s) {
+  const int32_t ngrp = (int32_t)pc->coarse.grp_col0.size();
+  if (ngrp == 0) return;
+  const int waves = 4;
+  k_coarse_ec<<<(ngrp + waves - 1) / waves, 64 * waves, 0, s>>>(
+      ngrp, nc, pc->cz_goff.as<int32_t>(), pc->cz_grows.as<int32_t>(), pc->cz_gc0.as<int32_t>(),
+      pc->cz_gc1.as<int32_t>(), pc->cz_gcoff.as<int32_t>(), pc->cz_gcols.as<int32_t>(), pc->cz_z0.as<double>(),
+      pc->cz_z1.as<double>(), pc->cz_szp.as<int32_t>(), pc->cz_szc.as<int32_t>(), pc->cz_szv.as<double>(), Ec);
+}
+
+void launch_gj_invert(double* A, int32_t n, int32_t* perm, double* work, int32_t* info, hipStream_t s) {
+  if (n == 0) return;
+  k_absmax<<<1, 1024, 0, s>>>(A, (int64_t)n * n, work);
+  const dim3 grid((unsigned)((n + 255) / 256), (unsigned)n);
+  for (int32_t k = 0; k < n; ++k) {
+    k_gj_pivot<<<1, 1024, 0, s>>>(A, n, k, perm, work, info);
+    k_gj_update<<<grid, 256, 0, s>>>(A, n, k, work);
+  }
+  k_gj_colswap<<<(n + 255) / 256, 256, 0, s>>>(A, n, perm);
+}
+
+void launch_coarse_restrict(const addns_precond* pc, const double* y, const double* z1, hipStream_t s) {
+  const int32_t ngrp = (int32_t)pc->coarse.grp_col0.size();
+  if (ngrp == 0) return;
+  const int waves = 4;
+  k_coarse_restrict<<<(ngrp + waves - 1) / waves, 64 * waves, 0, s>>>(
+      ngrp, pc->plan.n_int, pc->cz_goff.as<int32_t>(), pc->cz_grows.as<int32_t>(), pc->cz_gc0.as<int32_t>(),
+      pc->cz_gc1.as<int32_t>(), pc->f_rowptr.as<int32_t>(), pc->f_colidx.as<int32_t>(), pc->f_vals.as<double>(),
+      pc->cz_z0.as<double>(), pc->cz_z1.as<double>(), y, z1, pc->cz_t.as<double>(), pc->cz_g.as<double>());
+}
+
+void launch_coarse_solve(const addns_precond* pc, hipStream_t s) {
+  const int32_t nc = pc->coarse_nc;
+  if (nc == 0) return;
+  const int waves = 4;
+  k_coarse_solve<<<(nc + waves - 1) / waves, 64 * waves, 0, s>>>(nc, pc->cz_einv.as<double>(),
+                                                                  pc->cz_g.as<double>(), pc->cz_y.as<double>());
+}
+
+}  // namespace addns

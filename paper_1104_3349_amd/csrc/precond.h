@@ -141,6 +141,38 @@ struct Plan {
 
 void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult, int overlap);
 
+// Coarse space of the two-level interface solve: pieces of at most `piece`
+// separator velocity nodes, one constant and (pieces of three nodes or
+// more) one linear column each.  Positions are separator positions.
+struct CoarseSpace {
+  int32_t piece = 0, npieces = 0, nc = 0;
+  std::vector<int32_t> piece_off, piece_pos;      // pieces, members in joining order
+  std::vector<int32_t> col_piece, col_kind;       // per column: piece, 0 constant / 1 linear
+  std::vector<int32_t> piece_col0, piece_col1;    // per piece: its columns (-1 if none)
+  std::vector<int32_t> node_piece;                // per separator position (-1: pressure-like)
+  std::vector<double> node_z0, node_z1;           // per position: constant and linear values
+};
+// Device plan of the coarse correction.
+struct CoarsePlan {
+  CoarseSpace space;
+  std::vector<int32_t> sub_of;                    // subdomain of every interior row
+  // (subdomain, coarse column) solves D_j^{-1} E_j z_c, ordered by column
+  std::vector<int32_t> pair_sub, pair_col, cpair_ptr;
+  std::vector<int64_t> pair_off;
+  int64_t pair_total = 0;
+  // row pattern of S Z (CSR over separator rows, coarse columns ascending)
+  std::vector<int32_t> sz_rowptr, sz_col;
+  // restriction groups (<= 64 rows each): the pieces, then the other rows
+  std::vector<int32_t> grp_off, grp_rows, grp_col0, grp_col1;
+  std::vector<int32_t> grp_coff, grp_cols;        // per group: the columns of S Z on its rows, ascending
+};
+void build_coarse_space(const PartitionData& P, int32_t piece, CoarseSpace& cs);
+void build_coarse_plan(const PartitionData& P, const Plan& pl, int32_t piece, CoarsePlan& cp);
+
+// Largest coarse space the two-level interface solve accepts (its dense
+// inverse is nc^2 FP64 and its Gauss-Jordan setup takes 2 nc launches).
+constexpr int32_t kMaxCoarseColumns = 8192;
+
 // Bytes past the end of each interior factor array that the sweep may read
 // (its last row slot can overrun a block by up to 64 * 5 - 1 FP64 rows).
 constexpr int64_t kSweepOverrunBytes = 4096;
@@ -194,6 +226,15 @@ struct addns_precond {
   addns::DevBuf ch_nz, ch_nzo;                        // coupling columns of the chunk boundaries
   addns::DevBuf ch_prow, ch_np, ch_npo;               // pure carry rows and coupled carry positions
   addns::DevBuf g_copy;                               // G blocks before the update (learning targets S - G)
+  // coarse-grid correction of the interface solve (opts.coarse > 0)
+  addns::CoarsePlan coarse;
+  int32_t coarse_nc = 0;
+  addns::DevBuf cz_piece, cz_z0, cz_z1, cz_colp, cz_colk, cz_p0, cz_p1;   // per position / column / piece
+  addns::DevBuf cz_szp, cz_szc, cz_szv;              // S Z, CSR over separator rows
+  addns::DevBuf cz_einv;                              // (Z^T S Z)^{-1}, nc x nc row-major FP64
+  addns::DevBuf cz_goff, cz_grows, cz_gc0, cz_gc1;    // restriction groups
+  addns::DevBuf cz_gcoff, cz_gcols;                   //   and their S Z column lists
+  addns::DevBuf cz_t, cz_g, cz_y;                     // apply scratch: t, Z^T t, y
   addns::DevBuf smp_row, smp_nb, smp_loc;             // learned-correction sample table
   // GMRES work space (grown on demand)
   addns::DevBuf V, Z, w, xp, bp, rp, Hd, gd, partials, scal;
@@ -249,6 +290,23 @@ void launch_exact_schur_update(int32_t nsep, const int32_t* pcol_ptr, const int3
                                const double* U, double* S, hipStream_t s);
 void launch_interface_solve(const addns_precond* pc, const double* y, const double* z1, double* x2out,
                             hipStream_t s);
+// coarse correction (kernels_coarse.hip, column solves in kernels_apply.hip)
+// rhs_given = 0: right-hand sides E_j z_c formed in the scratch; 1: taken
+// from the scratch as stored there
+void launch_coarse_column_solves(const addns_precond* pc, int32_t npairs, const int32_t* pair_sub,
+                                 const int32_t* pair_col, const int64_t* pair_off, double* scratch, double* out,
+                                 int rhs_given, hipStream_t s);
+// one step of iterative refinement of the column solves: scratch = E_j z_c -
+// A_jj W (FP64), then W += A_jj^{-1} scratch through the sweep
+void launch_coarse_refine(const addns_precond* pc, int32_t npairs, const int32_t* pair_sub, const int32_t* pair_col,
+                          const int64_t* pair_off, double* W, double* scratch, double* dW, hipStream_t s);
+void launch_coarse_sz(const addns_precond* pc, const int32_t* sub_of, const int32_t* pair_sub,
+                      const int32_t* cpair_ptr, const int64_t* pair_off, const int32_t* int_off,
+                      const double* W, hipStream_t s);
+void launch_coarse_ec(const addns_precond* pc, int32_t nc, double* Ec, hipStream_t s);
+void launch_gj_invert(double* A, int32_t n, int32_t* perm, double* work, int32_t* info, hipStream_t s);
+void launch_coarse_restrict(const addns_precond* pc, const double* y, const double* z1, hipStream_t s);
+void launch_coarse_solve(const addns_precond* pc, hipStream_t s);
 void launch_overlap_split(int32_t k, const int32_t* agg_s, const int32_t* agg_w, const int64_t* g_off,
                           const int64_t* a_off, const int64_t* l_off, const double* Se, double* A, double* L,
                           hipStream_t s);

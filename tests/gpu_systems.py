@@ -57,3 +57,32 @@ def relerr(a, b):
     b = np.asarray(b)
     d = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (d if d > 0 else 1.0))
+
+
+def blocks_of(part, numbering="original"):
+    """Index sets compared separately: every interior block and the separator.
+    numbering: "original" (vectors in C's numbering), "permuted" (P^T order),
+    or "interior" (permuted interior part only)."""
+    m = len(part.int_offsets) - 1
+    if numbering == "original":
+        return [part.interior(j) for j in range(m)] + [part.separator()]
+    ranges = [np.arange(part.int_offsets[j], part.int_offsets[j + 1]) for j in range(m)]
+    if numbering == "interior":
+        return ranges
+    return ranges + [np.arange(part.n_int, part.N)]
+
+
+def blockwise_err(got, ref, blocks):
+    """Element-by-element error: the largest |got_i - ref_i| of each block,
+    relative to that block's largest |ref_i|, maximised over the blocks (an
+    error confined to a small block is not diluted by the others)."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    worst = 0.0
+    for idx in blocks:
+        if len(idx) == 0:
+            continue
+        scale = float(np.abs(ref[idx]).max())
+        d = float(np.abs(got[idx] - ref[idx]).max())
+        worst = max(worst, d / scale if scale > 0 else d)
+    return worst

@@ -1,0 +1,136 @@
+"""GPU parity of the coarse-grid correction of the interface solve (the
+coarse grid correction proposed in section 6; reading and pins in
+oracle/coarse.py) against the FP64 oracle, element by element per interior
+block and separator.
+
+Tolerances: the FP64 two-level apply adds to the one-level apply (1e-9, see
+test_gpu_parity.py) a dense FP64 coarse solve with E_c = Z^T S Z, whose
+inverse is formed by Gauss-Jordan elimination with partial pivoting on the
+GPU and by LAPACK's LU on the oracle side; with cond(E_c) below 1e5 on these
+systems both agree to about eps * cond(E_c) * nc, inside 1e-9.  GMRES
+iterates at equal iteration counts: 5e-10 relative in the 2-norm, and
+element by element 1e-8 of each block's largest entry.  The one-level FP64
+contract is 1e-10; the coarse space adds a sensitivity the oracle shows by
+itself: perturbing its S Z by 1e-12 relative moves its 8th iterate on the
+128 x 128 system by 1.9e-10 (E_c^{-1} amplifies by cond(E_c) = 1.8e4, and
+t - S Z y cancels most of t), and the GPU's S Z comes from the sweep's
+explicitly inverted blocks (refined once in FP64) rather than LAPACK."""
+import numpy as np
+import pytest
+
+from tests.gpu_systems import blocks_of, blockwise_err, gpu_precond, make_system
+
+torch = pytest.importorskip("torch")
+from oracle.krylov import gmres  # noqa: E402
+from oracle.partition import build_partition as oracle_partition  # noqa: E402
+from oracle.precond import MSCN, Preconditioner  # noqa: E402
+from paper_1104_3349_amd import addns  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "cavity16": (dict(n=16, nu=0.1, m=4, sz=64, stretch=None, seed=1001), 8),
+    "mid": (dict(n=48, nu=0.005, m=6, sz=40, stretch=1.05, seed=7), 16),
+    "cavity128": (dict(n=128, nu=0.01, m=16, sz=64, stretch=None, seed=1002), 32),
+}
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _oracle(S, piece):
+    P = oracle_partition(S.N, S.rp, S.ci, S.v, S.m, S.sz)
+    return P, Preconditioner(S.N, S.rp, S.ci, S.v, P, MSCN, coarse=piece)
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    kw, piece = CASES[request.param]
+    S = make_system(**kw)
+    P, ora = _oracle(S, piece)
+    return request.param, S, piece, P, ora
+
+
+def test_coarse_apply_matches_oracle(case):
+    name, S, piece, P, ora = case
+    part, pc = gpu_precond(S, coarse=piece)
+    y = np.random.default_rng(6).standard_normal(S.N)
+    d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+    addns.apply_precond(pc, _cuda(y), d_x)
+    torch.cuda.synchronize()
+    x = d_x.cpu().numpy()
+    e = blockwise_err(x, ora.apply(y), blocks_of(P))
+    assert e <= 1e-9, e
+    d_x2 = torch.zeros_like(d_x)
+    addns.apply_precond(pc, _cuda(y), d_x2)
+    torch.cuda.synchronize()
+    assert np.array_equal(d_x2.cpu().numpy(), x)
+
+
+def test_coarse_gmres_equal_iterations(case):
+    name, S, piece, P, ora = case
+    part, pc = gpu_precond(S, coarse=piece)
+    k, restart = (12, 5) if name != "cavity128" else (8, 5)
+    ref = gmres(lambda u: ora.C @ u, ora.apply, ora.R * S.b, restart=restart, tol=1e-300, maxit=k,
+                flexible=True, ortho="cgs2")
+    d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+    r = addns.gmres_solve(pc, _cuda(S.b), d_x, restart=restart, maxit=k, tol=1e-300, flexible=True,
+                          history=True, ortho="cgs2")
+    assert r["iters"] == k
+    x = d_x.cpu().numpy()
+    e = blockwise_err(x, ref.x, blocks_of(P))
+    g = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+    assert g <= 5e-10 and e <= 1e-8, (g, e)
+    np.testing.assert_allclose(r["history"], ref.est_history, rtol=1e-8, atol=0)
+
+
+def test_coarse_gmres_iterations_within_one(case):
+    name, S, piece, P, ora = case
+    part, pc = gpu_precond(S, coarse=piece)
+    restart = 30 if name == "cavity16" else 50
+    ref = gmres(lambda u: ora.C @ u, ora.apply, ora.R * S.b, restart=restart, tol=1e-8, maxit=2000,
+                flexible=True, ortho="cgs2")
+    d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+    r = addns.gmres_solve(pc, _cuda(S.b), d_x, restart=restart, maxit=2000, tol=1e-8, flexible=True,
+                          ortho="cgs2")
+    assert ref.converged and r["converged"] and r["true_relres"] <= 1e-8
+    assert abs(r["iters"] - ref.iters) <= 1, (r["iters"], ref.iters)
+
+
+def test_coarse_cuts_iterations_on_the_bench_workload():
+    kw, piece = CASES["cavity128"]
+    S = make_system(**kw)
+    its = {}
+    for c in (0, piece):
+        part, pc = gpu_precond(S, iprec=addns.F32, sprec=addns.F32, coarse=c)
+        d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+        r = addns.gmres_solve(pc, _cuda(S.b), d_x, restart=50, maxit=3000, tol=1e-8, flexible=True)
+        assert r["converged"] and r["true_relres"] <= 1e-8
+        its[c] = r["iters"]
+    assert its[piece] * 5 < its[0], its
+
+
+def test_coarse_refactor_equals_fresh_setup():
+    kw, piece = CASES["mid"]
+    S = make_system(**kw)
+    S2 = make_system(**dict(kw, nu=0.02))
+    part, pc = gpu_precond(S, coarse=piece, sweep_chunks=1)
+    addns.refactor_precond(pc, _cuda(S2.rp), _cuda(S2.ci), _cuda(S2.v))
+    _, fresh = gpu_precond(S2, part=part, coarse=piece, sweep_chunks=1, block_mult=pc.info()["block_mult"])
+    y = _cuda(np.random.default_rng(2).standard_normal(S.N))
+    outs = []
+    for h in (pc, fresh):
+        d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+        addns.apply_precond(h, y, d_x)
+        torch.cuda.synchronize()
+        outs.append(d_x.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_coarse_argument_errors():
+    S = make_system(n=12, nu=0.1, m=3, sz=16, seed=2)
+    for bad in (dict(coarse=-1), dict(coarse=65), dict(coarse=8, overlap=4)):
+        with pytest.raises(addns.AddnsError) as e:
+            gpu_precond(S, **bad)
+        assert e.value.code == addns.ERR_ARG, bad

@@ -7,7 +7,12 @@ blocks of the same LU factors, so its rounding error is a small multiple of
 eps * cond(A_jj) * nb; for the interior blocks here cond(A_jj) < 1e5, giving
 the 1e-9 relative bound on interior solves and applies.  Mini Schur blocks
 S_i are O(d) flops of FP64 Gaussian elimination: 1e-11 relative to max|S_i|.
-GMRES iterates at equal iteration counts: 1e-10 relative (the stated target).
+GMRES iterates at equal iteration counts: 1e-10 relative in the 2-norm (the
+stated target), and element by element 1e-8 of each interior block's and the
+separator's largest entry (an iterate combines applies with cancelling
+coefficients, so a block of small entries carries a larger share of their
+error).  Interior solves and applies are compared element by element, per
+interior block and separator, against the 1e-9 bound.
 Mixed storage: FP32 factors carry a relative storage error of 2^-24 ~ 6e-8
 per entry, amplified by the same cond factor: 1e-4 on an apply; FP16 interface
 inverses (11-bit mantissa, per-block scale) perturb the interface part by
@@ -20,7 +25,7 @@ import os
 import numpy as np
 import pytest
 
-from tests.gpu_systems import gpu_precond, make_system, oracle_precond, relerr
+from tests.gpu_systems import blocks_of, blockwise_err, gpu_precond, make_system, oracle_precond, relerr
 
 torch = pytest.importorskip("torch")
 from paper_1104_3349_amd import addns  # noqa: E402
@@ -84,7 +89,7 @@ def test_interior_solve(case):
     d_y, d_z = _cuda(y1), torch.zeros(ora.ni, dtype=torch.float64, device="cuda")
     addns.interior_solve(pc, d_y, d_z)
     torch.cuda.synchronize()
-    e = relerr(d_z.cpu().numpy(), z_ref)
+    e = blockwise_err(d_z.cpu().numpy(), z_ref, blocks_of(ora.part, "interior"))
     MEASURED[f"interior_{name}"] = e
     assert e <= 1e-9
 
@@ -101,7 +106,7 @@ def test_apply(case, schur):
     addns.apply_precond(pc, d_y, d_x)
     torch.cuda.synchronize()
     x1 = d_x.cpu().numpy()
-    e = relerr(x1, x_ref)
+    e = blockwise_err(x1, x_ref, blocks_of(ora.part))
     MEASURED[f"apply_{name}_{schur}"] = e
     assert e <= 1e-9
     # bitwise reproducible
@@ -123,7 +128,7 @@ def test_block_multiplier_same_operator(case, mult):
     d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
     addns.apply_precond(pc, _cuda(y), d_x)
     torch.cuda.synchronize()
-    e = relerr(d_x.cpu().numpy(), ora.apply(y))
+    e = blockwise_err(d_x.cpu().numpy(), ora.apply(y), blocks_of(ora.part))
     MEASURED[f"apply_mult{mult}_{name}"] = e
     assert e <= 1e-9
 
@@ -162,9 +167,11 @@ def test_gmres_equal_iterations(case, flexible, schur, ortho):
     r = addns.gmres_solve(pc, d_b, d_x, restart=restart, maxit=k, tol=1e-300, flexible=flexible,
                           history=True, ortho=ortho)
     assert r["iters"] == k and not r["converged"]
-    e = relerr(d_x.cpu().numpy(), ref.x)
-    MEASURED[f"gmres_equal_its_{name}_{flexible}_{schur}_{ortho}"] = e
-    assert e <= 1e-10
+    x = d_x.cpu().numpy()
+    e = relerr(x, ref.x)
+    eb = blockwise_err(x, ref.x, blocks_of(ora.part))
+    MEASURED[f"gmres_equal_its_{name}_{flexible}_{schur}_{ortho}"] = [e, eb]
+    assert e <= 1e-10 and eb <= 1e-8
     assert abs(r["true_relres"] - ref.true_relres) <= 1e-8 * max(ref.true_relres, 1e-300) + 1e-14
     np.testing.assert_allclose(r["history"], ref.est_history, rtol=1e-8, atol=0)
 
@@ -409,3 +416,65 @@ def test_apply_captured_in_graph_replays_exactly():
         torch.cuda.synchronize()
         assert np.array_equal(got, ref.cpu().numpy()), rep
         x.zero_()  # eager work between replays
+
+
+def test_bench_workload_fp64_iterations_within_one():
+    """The 128 x 128 workload, FP64 factors, FGMRES(50) with modified
+    Gram-Schmidt (the Arnoldi form of the contract): the GPU's iteration
+    count to 1e-8 is within one of the oracle's."""
+    S = make_system(**CASES["cavity128"])
+    ora = oracle_precond(S)
+    ref = gmres(lambda x: ora.C @ x, ora.apply, ora.R * S.b, restart=50, tol=1e-8, maxit=3000, flexible=True,
+                ortho="mgs")
+    part, pc = gpu_precond(S)
+    d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+    r = addns.gmres_solve(pc, _cuda(S.b), d_x, restart=50, maxit=3000, tol=1e-8, flexible=True, ortho="mgs")
+    MEASURED["cavity128_fp64_its"] = [r["iters"], ref.iters]
+    assert ref.converged and r["converged"] and r["true_relres"] <= 1e-8
+    assert abs(r["iters"] - ref.iters) <= 1, (r["iters"], ref.iters)
+
+
+@pytest.mark.parametrize("chunks", [1, 2, 6])
+@pytest.mark.parametrize("zero_skip", [1, 2])
+def test_every_sweep_form_matches_oracle(chunks, zero_skip):
+    """Each interior-sweep form the setup can choose (chunk count, with and
+    without skipping structural-zero slots), forced, against the oracle."""
+    S = make_system(**CASES["cavity128"])
+    ora = oracle_precond(S)
+    part, pc = gpu_precond(S, sweep_chunks=chunks, sweep_zero_skip=zero_skip)
+    assert pc.info()["sweep_chunks"] == chunks
+    y = np.random.default_rng(12).standard_normal(S.N)
+    d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+    addns.apply_precond(pc, _cuda(y), d_x)
+    torch.cuda.synchronize()
+    e = blockwise_err(d_x.cpu().numpy(), ora.apply(y), blocks_of(ora.part))
+    MEASURED[f"sweep_form_{chunks}_{zero_skip}"] = e
+    assert e <= 1e-9
+
+
+def test_two_default_setups_solve_bit_for_bit():
+    """The setup's choices (chunk count, block size, zero-slot form) never
+    depend on a timing that could change the rounding: two setups of the
+    same input with default options give the same iterates bit for bit."""
+    S = make_system(**CASES["cavity128"])
+    xs, its = [], []
+    for _ in range(2):
+        part, pc = gpu_precond(S, iprec=addns.F32, sprec=addns.F32, block_mult=0, sweep_chunks=0)
+        d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+        r = addns.gmres_solve(pc, _cuda(S.b), d_x, restart=50, maxit=200, tol=1e-8, flexible=True)
+        xs.append(d_x.cpu().numpy())
+        its.append(r["iters"])
+    assert its[0] == its[1] and np.array_equal(xs[0], xs[1])
+
+
+def test_fill_factor_matches_oracle():
+    """Section 5's fill factor from the library's counts equals the oracle's
+    on the 16 x 16 system (exact FP64 band LU on both sides)."""
+    S = make_system(**CASES["cavity16"])
+    ora = oracle_precond(S)
+    part, pc = gpu_precond(S)
+    a, c = pc.fill()
+    assert c == len(S.v)
+    ff = a / c
+    MEASURED["fill_cavity16"] = [ff, ora.fill_factor()]
+    assert abs(ff - ora.fill_factor()) <= 1e-3 * ora.fill_factor()

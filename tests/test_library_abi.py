@@ -103,3 +103,48 @@ def test_dtn_weights_file_roundtrip(tmp_path):
     assert e.value.code == addns.ERR_ARG
     with pytest.raises(addns.AddnsError):
         addns.dtn_load(str(tmp_path / "missing.bin"))
+
+
+def _same_coarse(rp, ci, v, meta, m, sz, piece):
+    from oracle.coarse import coarse_space
+    P = oracle_partition(meta["N"], rp, ci, v, m, sz)
+    offs, pos, zcols = coarse_space(meta["N"], rp, ci, P, piece)
+    A = addns.build_partition(meta["N"], rp, ci, v, m, sz).coarse_space(piece)
+    assert np.array_equal(A["piece_offsets"], offs)
+    assert np.array_equal(A["piece_pos"], pos)
+    assert np.array_equal(A["col_piece"], [c for c, _ in zcols])
+    kinds, z0, z1 = [], np.zeros(P.sep_size), np.zeros(P.sep_size)
+    last = -1
+    for c, val in zcols:
+        kinds.append(0 if c != last else 1)
+        (z0 if c != last else z1)[pos[offs[c]:offs[c + 1]]] = val
+        last = c
+    assert np.array_equal(A["col_kind"], kinds)
+    np.testing.assert_allclose(A["z0"], z0, rtol=0, atol=4e-16)
+    np.testing.assert_allclose(A["z1"], z1, rtol=0, atol=4e-16)
+
+
+@pytest.mark.parametrize("cfg", [CAVITY16, CAVITY128], ids=["cavity16", "cavity128"])
+def test_coarse_space_matches_oracle_configs(cfg):
+    rp, ci, v, b, meta = cfg.build()
+    _same_coarse(rp, ci, v, meta, cfg.m, cfg.sz, 32)
+
+
+def test_coarse_space_matches_oracle_random():
+    rng = np.random.default_rng(321)
+    for _ in range(12):
+        n = int(rng.integers(4, 30))
+        st = [None, 1.05][int(rng.integers(2))] if n % 2 == 0 else None
+        rp, ci, v, b, meta = make_oseen_mac(n, float(rng.uniform(0.001, 0.3)), wind=Wind.random_modes(rng),
+                                            stretch=st, seed=3)
+        _same_coarse(rp, ci, v, meta, int(rng.integers(1, 9)), int(rng.integers(4, 70)),
+                     int(rng.integers(1, 65)))
+
+
+def test_coarse_space_argument_errors():
+    rp, ci, v, b, meta = make_oseen_mac(6, 0.1, seed=1)
+    p = addns.build_partition(meta["N"], rp, ci, v, 2, 8)
+    for bad in (0, 65):
+        with pytest.raises(addns.AddnsError) as e:
+            p.coarse_space(bad)
+        assert e.value.code == addns.ERR_ARG

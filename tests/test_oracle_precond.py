@@ -324,3 +324,27 @@ def test_singular_interior_detected_without_closure():
     BandLU(A)  # nonsingular with pivoting
     with pytest.raises(Exception):
         BandLU(sp.csr_matrix(np.array([[0.0, 0.0], [0.0, 1.0]])))
+
+
+def test_fill_factor_hand_count():
+    """A tridiagonal matrix of 9 nodes (diagonal 4, neighbours -1), two
+    subdomains: the bisection puts node 4 in the separator and nodes 0-3,
+    5-8 in the interiors.  Each 4 x 4 tridiagonal interior factors without
+    pivoting (diagonally dominant) into 3 multipliers and 4 + 3 entries of U;
+    the 1 x 1 interface block is one entry; E and F hold C(3,4), C(5,4) and
+    C(4,3), C(4,5).  So the preconditioner holds 10 + 10 + 1 + 2 + 2 = 25
+    nonzeros, and C holds 3 * 9 - 2 = 25: fill factor 1."""
+    n = 9
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        for j in (i - 1, i, i + 1):
+            if 0 <= j < n:
+                rows.append(i)
+                cols.append(j)
+                vals.append(4.0 if i == j else -1.0)
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    A.sort_indices()
+    P = build_partition(n, A.indptr, A.indices, A.data, 2, 8)
+    assert list(P.perm[P.n_int:]) == [4]
+    pre = Preconditioner(n, A.indptr, A.indices, A.data, P, MSCN)
+    assert pre.fill_factor() == 1.0
