@@ -282,6 +282,24 @@ int addns_precond_refactor(addns_precond_t pc, const int32_t* d_rowptr, const in
 int addns_apply_precond(addns_precond_t pc, const double* d_y, double* d_x, void* stream);
 
 /* ------------------------------------------------------------------------
+ * addns_apply_precond_static -- addns_apply_precond for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and the same result bit
+ * for bit, with the permuted in/out vectors and the interior sweeps' padded
+ * work vectors in a library-static device array instead of the handle's.
+ * The call allocates and frees nothing.
+ *   pc, d_y, d_x, stream: as for addns_apply_precond (d_x must not alias d_y).
+ * Limit: the array holds 4 Mi doubles (32 MiB); a system needing more than
+ * 2 N + 2 (padded interior rows) doubles gives ADDNS_ERR_ARG, as does a
+ * current device other than the handle's.  Every GPU holds one copy of the
+ * array until the process ends, shared by all calls on that GPU: calls on
+ * one GPU whose execution overlaps (different streams, threads or handles)
+ * race on it and must be serialised by the caller.  Nothing in the array
+ * needs to start at zero (every entry read is first written by the call).
+ */
+int addns_apply_precond_static(addns_precond_t pc, const double* d_y, double* d_x, void* stream);
+
+/* ------------------------------------------------------------------------
  * addns_interior_solve -- the interior block solve of Algorithm 2 on its
  * own: z1 = D^{-1} y1 with D = blkDiag(A_11..A_mm), for DEVICE vectors of
  * length n_interior in the PERMUTED interior order (perm[0..n_interior) of

@@ -25,7 +25,7 @@ F64, F32, F16_SCALED = 0, 1, 2
 EXPORTED = [
     "addns_build_partition", "addns_partition_info", "addns_partition_export",
     "addns_partition_concat", "addns_partition_coarse_space", "addns_gmres_solve_batched",
-    "addns_setup_precond", "addns_apply_precond", "addns_interior_solve", "addns_gmres_solve", "addns_precond_info",
+    "addns_setup_precond", "addns_apply_precond", "addns_apply_precond_static", "addns_interior_solve", "addns_gmres_solve", "addns_precond_info",
     "addns_precond_schur_blocks", "addns_precond_fill", "addns_partition_destroy", "addns_precond_destroy",
     "addns_last_error", "addns_version",
     "addns_dtn_param_count", "addns_dtn_samples", "addns_dtn_forward", "addns_dtn_grad",
@@ -89,6 +89,7 @@ def lib():
         "addns_setup_precond": (C.c_int, [P, C.c_int32, P, P, P, C.POINTER(PrecondOpts), P,
                                           C.POINTER(P)]),
         "addns_apply_precond": (C.c_int, [P, P, P, P]),
+        "addns_apply_precond_static": (C.c_int, [P, P, P, P]),
         "addns_precond_refactor": (C.c_int, [P, P, P, P, P]),
         "addns_interior_solve": (C.c_int, [P, P, P, P]),
         "addns_gmres_solve": (C.c_int, [P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresResult), P]),
@@ -302,6 +303,13 @@ def refactor_precond(pc: Precond, d_rowptr, d_colidx, d_vals, stream=None):
 def apply_precond(pc: Precond, d_y, d_x, stream=None):
     _check(lib().addns_apply_precond(pc.handle, _ptr(d_y), _ptr(d_x), _stream(stream)),
            "apply_precond")
+
+
+def apply_precond_static(pc: Precond, d_y, d_x, stream=None):
+    """addns_apply_precond_static: the apply with its work vectors in the
+    library's static device array (no allocation)."""
+    _check(lib().addns_apply_precond_static(pc.handle, _ptr(d_y), _ptr(d_x), _stream(stream)),
+           "apply_precond_static")
 
 
 def interior_solve(pc: Precond, d_y1, d_z1, stream=None):

@@ -8,11 +8,21 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 
 #include "precond.h"
 
 using namespace addns;
+
+// Scratch of addns_apply_precond_static, for callers that cannot allocate:
+// the permuted input and output vectors and the interior sweeps' two padded
+// work vectors (2 N + 2 npad doubles), at most 32 MiB.  Every GPU the
+// library runs on holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns on that
+// device (the array's name is a host-side stand-in, not a device address).
+constexpr int64_t kStaticScratchDoubles = int64_t(4) << 20;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
 
 namespace {
 
@@ -358,10 +368,13 @@ void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipS
   pc->coarse_nc = nc;
 }
 
-void apply_permuted(addns_precond* pc, const double* yp, double* xp, hipStream_t s) {
+// ypad, zpad: the two padded vectors of the interior sweeps (NULL: the
+// handle's own)
+void apply_permuted(addns_precond* pc, const double* yp, double* xp, hipStream_t s, double* ypad = nullptr,
+                    double* zpad = nullptr) {
   const Plan& pl = pc->plan;
   // z1 = D^{-1} y1 (into the interior part of xp)
-  launch_interior_solve(pc, yp, xp, 0, nullptr, nullptr, s);
+  launch_interior_solve(pc, yp, xp, 0, nullptr, nullptr, s, ypad);
   // two-level interface solve: t = y2 - F z1 and Z^T t, then y = E_c^{-1} Z^T t
   if (pc->coarse_nc > 0) {
     launch_coarse_restrict(pc, yp, xp, s);
@@ -372,7 +385,7 @@ void apply_permuted(addns_precond* pc, const double* yp, double* xp, hipStream_t
   launch_interface_solve(pc, yp, xp, xp, s);
   launch_overlap_chain(pc, xp + pl.n_int, s);
   // x1 = z1 - D^{-1} (E x2), in place
-  if (pl.k > 0) launch_interior_solve(pc, nullptr, xp, 1, xp + pl.n_int, xp, s);
+  if (pl.k > 0) launch_interior_solve(pc, nullptr, xp, 1, xp + pl.n_int, xp, s, zpad);
 }
 
 // Mean duration (ms) of a few interior solves on the handle's own factors.
@@ -595,6 +608,53 @@ int addns_apply_precond(addns_precond_t pc, const double* d_y, double* d_x, void
     launch_permute(pc->perm.as<int32_t>(), d_y, pc->vperm_in.as<double>(), N, 0, nullptr, s);
     apply_permuted(pc, pc->vperm_in.as<double>(), pc->vperm_out.as<double>(), s);
     launch_permute(pc->perm.as<int32_t>(), pc->vperm_out.as<double>(), d_x, N, 1, nullptr, s);
+    ADDNS_HIP(hipGetLastError());
+    return ADDNS_OK;
+  });
+}
+
+// Device address of `scratch` on device dev, looked up once per device
+// with that device current.
+static double* static_scratch(int dev) {
+  static std::mutex mu;
+  static double* ptr[256] = {};
+  if (dev < 0 || dev >= 256) throw ArgError("device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    ADDNS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw HipError("hipGetSymbolAddress returned a null address for the static scratch");
+    ptr[dev] = static_cast<double*>(p);
+  }
+  return ptr[dev];
+}
+
+int addns_apply_precond_static(addns_precond_t pc, const double* d_y, double* d_x, void* stream) {
+  return guarded("addns_apply_precond_static", [&]() -> int {
+    if (!pc || !d_y || !d_x) throw ArgError("null argument");
+    require_factors(pc);
+    if (d_y == d_x) throw ArgError("y and x must not alias");
+    const Plan& pl = pc->plan;
+    const int32_t N = pl.N;
+    const int64_t npad = std::max<int64_t>(pl.npad_total, 1);
+    const int64_t need = 2 * (int64_t)N + 2 * npad;
+    if (need > kStaticScratchDoubles)
+      throw ArgError("this system needs " + std::to_string(need) + " doubles of scratch; the static array holds " +
+                     std::to_string(kStaticScratchDoubles) + " (use addns_apply_precond)");
+    int dev = -1;
+    ADDNS_HIP(hipGetDevice(&dev));
+    if (dev != pc->device)
+      throw ArgError("the current device (" + std::to_string(dev) + ") is not the handle's (" +
+                     std::to_string(pc->device) + ")");
+    double* w = static_scratch(dev);
+    double* vin = w;
+    double* vout = w + N;
+    double* ypad = w + 2 * (int64_t)N;
+    double* zpad = ypad + npad;
+    hipStream_t s = as_stream(stream);
+    launch_permute(pc->perm.as<int32_t>(), d_y, vin, N, 0, nullptr, s);
+    apply_permuted(pc, vin, vout, s, ypad, zpad);
+    launch_permute(pc->perm.as<int32_t>(), vout, d_x, N, 1, nullptr, s);
     ADDNS_HIP(hipGetLastError());
     return ADDNS_OK;
   });

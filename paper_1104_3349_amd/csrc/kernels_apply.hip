@@ -1234,11 +1234,11 @@ void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
 }
 
 void launch_interior_solve(const addns_precond* pc, const double* yin, double* out, int second, const double* x2,
-                           const double* z1, hipStream_t s) {
+                           const double* z1, hipStream_t s, double* work) {
   const Plan& pl = pc->plan;
   if (pl.m == 0 || pl.n_int == 0) return;
   SweepArgs a = sweep_args(pc);
-  a.ypad = second ? pc->zpad.as<double>() : pc->ypad.as<double>();
+  a.ypad = work ? work : (second ? pc->zpad.as<double>() : pc->ypad.as<double>());
   if (pc->sweep_chunks > 1) run_chunked(pc, a, yin, out, second ? 1 : 0, x2, z1, s);
   else run_sweep(pc, a, pl.m, yin, out, second ? 1 : 0, x2, z1, s);
 }

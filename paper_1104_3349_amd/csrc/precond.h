@@ -277,8 +277,9 @@ void launch_schur_blocks(int32_t k, const int32_t* agg_s, const int32_t* agg_d, 
 void launch_invert_dense(int32_t k, const int32_t* agg_s, const int64_t* g_off, const double* S,
                          double* work, int32_t* info, const int64_t* sinv_off, void* sinv, float* scale,
                          int prec, hipStream_t s);
+// work: the padded vector the sweep uses (NULL: the handle's ypad / zpad)
 void launch_interior_solve(const addns_precond* pc, const double* yin, double* out, int second,
-                           const double* x2, const double* z1, hipStream_t s);
+                           const double* x2, const double* z1, hipStream_t s, double* work = nullptr);
 int max_sweep_chunks(const Plan& pl);
 void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s);
 void release_chunked_sweep(addns_precond* pc);
