@@ -30,15 +30,32 @@ hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 int prec_bytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
 
-void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipStream_t s);
+void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipStream_t s, PlanCache* cache);
 
 // Factor and interface storage of one preconditioner.
 // Builds the plan from P (or keeps the handle's plan when P is null: a
 // refactor) and computes every numeric part of the preconditioner.
 void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_rowptr, const int32_t* d_colidx,
-                  const double* d_vals, const addns_precond_opts& o, hipStream_t s) {
+                  const double* d_vals, const addns_precond_opts& o, hipStream_t s, PlanCache* cache = nullptr) {
   Plan& pl = pc->plan;
-  if (P) build_plan(*P, pl, o.schur, o.block_mult, o.overlap);
+  if (P) {
+    // the host plan depends on the partition and on (schur, block_mult,
+    // overlap) only: reuse the partition's copy when those match
+    if (cache && cache->have_plan && cache->schur == o.schur && cache->block_mult == std::max(1, o.block_mult) &&
+        cache->overlap == o.overlap) {
+      pl = cache->plan;
+    } else {
+      build_plan(*P, pl, o.schur, o.block_mult, o.overlap);
+      if (cache) {
+        cache->plan = pl;
+        cache->have_plan = true;
+        cache->have_coarse = false;
+        cache->schur = o.schur;
+        cache->block_mult = std::max(1, o.block_mult);
+        cache->overlap = o.overlap;
+      }
+    }
+  }
   const int32_t N = pl.N;
   const int64_t nnz = (int64_t)pl.cp_colidx.size();
 
@@ -264,7 +281,7 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
 
   // -- coarse-grid correction of the interface solve (section 6)
   pc->coarse_nc = 0;
-  if (o.coarse > 0 && pl.nsep > 0) setup_coarse(pc, P, o.coarse, s);
+  if (o.coarse > 0 && pl.nsep > 0) setup_coarse(pc, P, o.coarse, s, cache);
 
   // permuted in/out vectors of addns_apply_precond: allocated here so that
   // an apply launches kernels only (and can be captured in a graph)
@@ -297,11 +314,22 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
 // Coarse-grid correction of the interface solve: the coarse space from the
 // partition (a refactor keeps it), S Z = G Z - F D^{-1} E Z from one interior
 // sweep per (subdomain, coarse column) pair, E_c = Z^T S Z and its inverse.
-void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipStream_t s) {
+void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipStream_t s, PlanCache* cache) {
   const Plan& pl = pc->plan;
   CoarsePlan& cp = pc->coarse;
   pc->coarse_nc = 0;
-  if (P) build_coarse_plan(*P, pl, piece, cp);
+  if (P) {
+    if (cache && cache->have_coarse && cache->piece == piece) {
+      cp = cache->coarse;
+    } else {
+      build_coarse_plan(*P, pl, piece, cp);
+      if (cache && cache->have_plan) {
+        cache->coarse = cp;
+        cache->have_coarse = true;
+        cache->piece = piece;
+      }
+    }
+  }
   const CoarseSpace& z = cp.space;
   const int32_t nc = z.nc;
   if (nc > kMaxCoarseColumns)
@@ -455,9 +483,16 @@ void choose_sweep_chunks(addns_precond* pc, int requested, hipStream_t s) {
   const int p = model_sweep_chunks(pl, prop.multiProcessorCount);
   if (p < 2) return;
   build_chunked_sweep(pc, p, s);
-  // the zero-slot form is re-chosen for the chunked kernels (bitwise the
-  // same result either way), unless the caller fixed it
-  if (pc->opts.sweep_zero_skip != 0) return;
+}
+
+// Zero-slot form of the sweep in use (single-workgroup or chunked): the
+// caller's choice, or the faster of the two by timing.  Both give the same
+// result bit for bit, so the timing never changes numerics.
+void choose_zero_skip(addns_precond* pc, int requested, hipStream_t s) {
+  if (requested != 0) {
+    pc->zero_skip = requested == 2 ? 1 : 0;
+    return;
+  }
   float ms[2];
   for (int z = 0; z < 2; ++z) {
     pc->zero_skip = z;
@@ -553,26 +588,17 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
       ADDNS_HIP(hipGetDevice(&pc->device));
       addns_precond_opts oo = o;
       oo.block_mult = mult;
-      setup_device(pc.get(), &p->d, d_rowptr, d_colidx, d_vals, oo, as_stream(stream));
+      if (!p->cache) p->cache = std::make_shared<PlanCache>();
+      setup_device(pc.get(), &p->d, d_rowptr, d_colidx, d_vals, oo, as_stream(stream), p->cache.get());
       pc->opts = oo;
       if (o.schur == ADDNS_SCHUR_LEARNED) {
         pc->learned_w.assign(o.learned_model, o.learned_model + mlp_param_count());
         pc->opts.learned_model = nullptr;  // the caller's array is not kept
       }
-      // the sweep's zero-slot skipping (bitwise the same result either way)
-      // is chosen by timing both forms on these factors, or fixed by the caller
-      if (o.sweep_zero_skip == 0) {
-        float ms[2];
-        for (int z = 0; z < 2; ++z) {
-          pc->zero_skip = z;
-          ms[z] = time_interior_solve(pc.get(), as_stream(stream));
-        }
-        pc->zero_skip = ms[1] < ms[0] ? 1 : 0;
-        pc->tuned_ms = std::min(ms[0], ms[1]);
-      } else {
-        pc->zero_skip = o.sweep_zero_skip == 2 ? 1 : 0;
-      }
+      // chunk count from the plan model, then the zero-slot form of the
+      // sweep that will run
       choose_sweep_chunks(pc.get(), o.sweep_chunks, as_stream(stream));
+      choose_zero_skip(pc.get(), o.sweep_zero_skip, as_stream(stream));
       pc->opts.sweep_chunks = pc->sweep_chunks;
       return pc;
     };

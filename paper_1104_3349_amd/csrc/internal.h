@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -34,6 +35,15 @@ int build_partition(int32_t N, const int32_t* rowptr, const int32_t* colidx, con
 
 }  // namespace addns
 
+namespace addns {
+struct PlanCache;  // host plans built from this partition (precond.h)
+}
+
 struct addns_partition {
   addns::PartitionData d;
+  // Integer setup plans derived from the partition and the options (the
+  // gather maps, sweep geometry and coarse-space structure), kept so that a
+  // new setup on the same partition with the same options does not redo
+  // them.  Not shared between threads, like the handle itself.
+  std::shared_ptr<addns::PlanCache> cache;
 };

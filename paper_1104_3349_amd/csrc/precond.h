@@ -169,6 +169,14 @@ struct CoarsePlan {
 void build_coarse_space(const PartitionData& P, int32_t piece, CoarseSpace& cs);
 void build_coarse_plan(const PartitionData& P, const Plan& pl, int32_t piece, CoarsePlan& cp);
 
+// Host plans of one partition, keyed by the options they depend on.
+struct PlanCache {
+  bool have_plan = false, have_coarse = false;
+  int schur = -1, block_mult = -1, overlap = -1, piece = -1;
+  Plan plan;
+  CoarsePlan coarse;
+};
+
 // Largest coarse space the two-level interface solve accepts (its dense
 // inverse is nc^2 FP64 and its Gauss-Jordan setup takes 2 nc launches).
 constexpr int32_t kMaxCoarseColumns = 8192;
