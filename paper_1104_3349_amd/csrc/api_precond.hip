@@ -307,7 +307,7 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
   // coarse correction: E_c^{-1}, S Z (value + column), the coarse vectors
   // and piece ids, and t written once and read once
   if (pc->coarse_nc > 0)
-    pc->bytes_apply += (int64_t)pc->coarse_nc * pc->coarse_nc * 8 + (int64_t)pc->coarse.sz_col.size() * 12 +
+    pc->bytes_apply += pc->coarse.blk_eoff.back() * 8 + (int64_t)pc->coarse.sz_col.size() * 12 +
                        (int64_t)pl.nsep * (4 + 8 + 8 + 16);
 }
 
@@ -353,7 +353,11 @@ void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipS
   pc->cz_t.alloc(sizeof(double) * std::max<int32_t>(pl.nsep, 1));
   pc->cz_g.alloc(sizeof(double) * std::max<int32_t>(nc, 1));
   pc->cz_y.alloc(sizeof(double) * std::max<int32_t>(nc, 1));
-  pc->cz_einv.alloc(sizeof(double) * std::max<int64_t>((int64_t)nc * nc, 1));
+  pc->cz_boff.upload(cp.blk_off, s);
+  pc->cz_cblk.upload(cp.col_blk, s);
+  pc->cz_beoff.upload(cp.blk_eoff, s);
+  const int64_t ec_total = cp.blk_eoff.empty() ? 0 : cp.blk_eoff.back();
+  pc->cz_einv.alloc(sizeof(double) * std::max<int64_t>(ec_total, 1));
   if (nc == 0) return;
   std::vector<int32_t> int_off(pl.m);
   for (int32_t j = 0; j < pl.m; ++j) int_off[j] = pl.subs[j].int_off;
@@ -382,13 +386,13 @@ void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipS
   launch_coarse_sz(pc, subof.as<int32_t>(), psub.as<int32_t>(), cpp.as<int32_t>(), poff.as<int64_t>(),
                    ioff.as<int32_t>(), W.as<double>(), s);
   double* Ec = pc->cz_einv.as<double>();
-  ADDNS_HIP(hipMemsetAsync(Ec, 0, sizeof(double) * (size_t)nc * nc, s));
+  ADDNS_HIP(hipMemsetAsync(Ec, 0, sizeof(double) * (size_t)ec_total, s));
   launch_coarse_ec(pc, nc, Ec, s);
   perm.alloc(sizeof(int32_t) * nc);
-  work.alloc(sizeof(double) * (1 + 2 * (size_t)nc));
+  work.alloc(sizeof(double) * (cp.blk_off.size() + 2 * (size_t)nc));
   info.alloc(sizeof(int32_t));
   ADDNS_HIP(hipMemsetAsync(info.p, 0, sizeof(int32_t), s));
-  launch_gj_invert(Ec, nc, perm.as<int32_t>(), work.as<double>(), info.as<int32_t>(), s);
+  launch_gj_invert(pc, Ec, perm.as<int32_t>(), work.as<double>(), info.as<int32_t>(), s);
   int32_t h_info = 0;
   ADDNS_HIP(hipMemcpyAsync(&h_info, info.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   ADDNS_HIP(hipStreamSynchronize(s));
@@ -881,6 +885,29 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
     d_ch.upload(chunks, s);
     d_coff.upload(coff, s);
     d_live.alloc(sizeof(int32_t) * nsys);
+    // the apply skips the subdomains, aggregates and coarse groups of the
+    // systems that have converged: their system ids, and the live flags
+    // below, stay on the handle for the duration of the solve
+    {
+      std::vector<int32_t> sub_sys(std::max(pl.m, 1), 0), agg_sys(std::max(pl.k, 1), 0);
+      for (int32_t j = 0; j < pl.m; ++j)
+        if (pl.subs[j].n > 0) sub_sys[j] = sys_of[pl.subs[j].int_off];
+      for (int32_t i = 0; i < pl.k; ++i)
+        if (pl.agg_off[i + 1] > pl.agg_off[i]) agg_sys[i] = sys_of[pl.n_int + pl.agg_off[i]];
+      const CoarsePlan& cp = pc->coarse;
+      std::vector<int32_t> grp_sys(std::max<size_t>(cp.grp_col0.size(), 1), 0);
+      for (size_t g = 0; g + 1 < cp.grp_off.size(); ++g)
+        if (cp.grp_off[g + 1] > cp.grp_off[g]) grp_sys[g] = sys_of[pl.n_int + cp.grp_rows[cp.grp_off[g]]];
+      pc->mask_sub.upload(sub_sys, s);
+      pc->mask_agg.upload(agg_sys, s);
+      pc->mask_grp.upload(grp_sys, s);
+      ADDNS_HIP(hipStreamSynchronize(s));  // the host vectors end with this block
+    }
+    struct MaskGuard {
+      addns_precond* pc;
+      ~MaskGuard() { pc->mask_live = nullptr; }
+    } mask_guard{pc};
+    pc->mask_live = d_live.as<int32_t>();
     d_jdone.alloc(sizeof(int32_t) * nsys);
     const int ldh = restart + 1;
     const int64_t st = (int64_t)ldh * restart + 4 * ldh;

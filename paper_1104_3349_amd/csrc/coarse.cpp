@@ -275,7 +275,8 @@ void build_coarse_plan(const PartitionData& P, const Plan& pl, int32_t piece, Co
     cp.grp_col0.push_back(-1);
     cp.grp_col1.push_back(-1);
   }
-  // per group, the union of the S Z columns on its rows
+  // per group, the union of the S Z columns on its rows (and the blocks of
+  // E_c below)
   cp.grp_coff.assign(1, 0);
   cp.grp_cols.clear();
   std::vector<int32_t> u;
@@ -290,6 +291,42 @@ void build_coarse_plan(const PartitionData& P, const Plan& pl, int32_t piece, Co
     u.erase(std::unique(u.begin(), u.end()), u.end());
     cp.grp_cols.insert(cp.grp_cols.end(), u.begin(), u.end());
     cp.grp_coff.push_back((int32_t)cp.grp_cols.size());
+  }
+  // blocks of E_c: columns joined when an entry E_c(c', c) can be nonzero
+  // (c' a column of a group, c in the group's list), then every component
+  // widened to the contiguous run of columns it spans, overlapping runs merged
+  std::vector<int32_t> parent(nc);
+  std::iota(parent.begin(), parent.end(), 0);
+  auto find = [&](int32_t x) {
+    while (parent[x] != x) x = parent[x] = parent[parent[x]];
+    return x;
+  };
+  auto unite = [&](int32_t a, int32_t b) {
+    a = find(a);
+    b = find(b);
+    if (a != b) parent[std::max(a, b)] = std::min(a, b);
+  };
+  for (size_t g = 0; g + 1 < cp.grp_off.size(); ++g) {
+    const int32_t c0 = cp.grp_col0[g], c1 = cp.grp_col1[g];
+    if (c0 < 0) continue;
+    if (c1 >= 0) unite(c0, c1);
+    for (int32_t t = cp.grp_coff[g]; t < cp.grp_coff[g + 1]; ++t) unite(c0, cp.grp_cols[t]);
+  }
+  std::vector<int32_t> hi(nc, -1);  // last column of each component, at its root
+  for (int32_t c = 0; c < nc; ++c) hi[find(c)] = std::max(hi[find(c)], c);
+  cp.blk_off.assign(1, 0);
+  cp.blk_eoff.assign(1, 0);
+  cp.col_blk.assign(nc, 0);
+  cp.blk_max = 0;
+  for (int32_t c = 0, end = -1; c < nc; ++c) {
+    end = std::max(end, hi[find(c)]);
+    if (c == end) {  // the run [blk_off.back(), c] closes here
+      const int32_t b = (int32_t)cp.blk_off.size() - 1, a = cp.blk_off.back(), sz = c + 1 - a;
+      for (int32_t x = a; x <= c; ++x) cp.col_blk[x] = b;
+      cp.blk_off.push_back(c + 1);
+      cp.blk_eoff.push_back(cp.blk_eoff.back() + (int64_t)sz * sz);
+      cp.blk_max = std::max(cp.blk_max, sz);
+    }
   }
 }
 

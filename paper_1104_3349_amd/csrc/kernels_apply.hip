@@ -203,6 +203,10 @@ struct SweepArgs {
   const int32_t* cz_colp;
   const int32_t* cz_colk;
   int32_t pair_rhs_given;  // mode 2: the right-hand side is already in the scratch
+  // modes 0 and 1 of a batched solve: workgroups of subdomains whose system
+  // has converged (live[unit_sys[sub]] == 0) do nothing
+  const int32_t* live;
+  const int32_t* unit_sys;
 };
 
 // One workgroup per subdomain.  mode 0: out[int] = D^{-1} yin[int].
@@ -224,6 +228,7 @@ __global__ void __launch_bounds__(kSweepThreads)
 k_interior_solve(SweepArgs a, const double* __restrict__ yin, double* out, int mode, const double* x2,
                  const double* z1) {
   extern __shared__ double smem[];
+  if (mode != 2 && a.live && !a.live[a.unit_sys[blockIdx.x]]) return;
   const SubInfo q = a.subs[mode == 2 ? a.pair_sub[blockIdx.x] : blockIdx.x];
   const int32_t pcol = mode == 2 ? a.pair_col[blockIdx.x] : -1;
   const int64_t poff = mode == 2 ? a.pair_off[blockIdx.x] : 0;
@@ -758,10 +763,11 @@ k_interface_solve(int32_t n_int, const int32_t* __restrict__ agg_off, const int3
                   const int32_t* __restrict__ f_colidx, const double* __restrict__ f_vals,
                   const int64_t* __restrict__ sinv_off, const T* __restrict__ sinv, const float* __restrict__ scale,
                   int scaled, const double* __restrict__ y, const double* __restrict__ z1, double* __restrict__ out,
-                  CoarseApply cz) {
+                  CoarseApply cz, const int32_t* __restrict__ live, const int32_t* __restrict__ agg_sys) {
   __shared__ double t[1024];
   __shared__ double part[1024];
   const int i = blockIdx.x;
+  if (live && !live[agg_sys[i]]) return;
   const int32_t a0 = agg_off[i], s = agg_off[i + 1] - a0;
   const int tid = threadIdx.x;
   const T* M = sinv + sinv_off[i];
@@ -1239,6 +1245,10 @@ void launch_interior_solve(const addns_precond* pc, const double* yin, double* o
   if (pl.m == 0 || pl.n_int == 0) return;
   SweepArgs a = sweep_args(pc);
   a.ypad = work ? work : (second ? pc->zpad.as<double>() : pc->ypad.as<double>());
+  if (pc->mask_live && pc->sweep_chunks <= 1) {
+    a.live = pc->mask_live;
+    a.unit_sys = pc->mask_sub.as<int32_t>();
+  }
   if (pc->sweep_chunks > 1) run_chunked(pc, a, yin, out, second ? 1 : 0, x2, z1, s);
   else run_sweep(pc, a, pl.m, yin, out, second ? 1 : 0, x2, z1, s);
 }
@@ -1295,13 +1305,14 @@ void launch_interface_solve(const addns_precond* pc, const double* y, const doub
   const int64_t* so = pc->sinv_off.as<int64_t>();
   if (pc->schur_prec == P64)
     k_interface_solve<double><<<pl.k, 1024, 0, s>>>(pl.n_int, ao, fr, fc, fv, so, pc->sinv.as<double>(), nullptr, 0, y,
-                                                   z1, out, cz);
+                                                   z1, out, cz, pc->mask_live, pc->mask_agg.as<int32_t>());
   else if (pc->schur_prec == P32)
     k_interface_solve<float><<<pl.k, 1024, 0, s>>>(pl.n_int, ao, fr, fc, fv, so, pc->sinv.as<float>(), nullptr, 0, y,
-                                                  z1, out, cz);
+                                                  z1, out, cz, pc->mask_live, pc->mask_agg.as<int32_t>());
   else
     k_interface_solve<__half><<<pl.k, 1024, 0, s>>>(pl.n_int, ao, fr, fc, fv, so, pc->sinv.as<__half>(),
-                                                   pc->sinv_scale.as<float>(), 1, y, z1, out, cz);
+                                                   pc->sinv_scale.as<float>(), 1, y, z1, out, cz, pc->mask_live,
+                                                   pc->mask_agg.as<int32_t>());
 }
 
 void launch_permute(const int32_t* perm, const double* in, double* out, int32_t n, int inverse, const double* scale,

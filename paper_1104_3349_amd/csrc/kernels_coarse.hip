@@ -67,18 +67,22 @@ __global__ void k_coarse_sz(int32_t ns, int32_t n_int, const int32_t* __restrict
 // order, of z_c'(row) S Z(row, c).  Each lane owns columns c of the group's
 // column list and accumulates them in registers (S Z(row, c) found by binary
 // search in the row's ascending column list); no element is written twice.
-__global__ void k_coarse_ec(int32_t ngrp, int32_t nc, const int32_t* __restrict__ goff,
-                            const int32_t* __restrict__ grows, const int32_t* __restrict__ gc0,
-                            const int32_t* __restrict__ gc1, const int32_t* __restrict__ gcoff,
-                            const int32_t* __restrict__ gcols, const double* __restrict__ z0,
-                            const double* __restrict__ z1, const int32_t* __restrict__ szp,
-                            const int32_t* __restrict__ szc, const double* __restrict__ szv,
+__global__ void k_coarse_ec(int32_t ngrp, const int32_t* __restrict__ goff, const int32_t* __restrict__ grows,
+                            const int32_t* __restrict__ gc0, const int32_t* __restrict__ gc1,
+                            const int32_t* __restrict__ gcoff, const int32_t* __restrict__ gcols,
+                            const double* __restrict__ z0, const double* __restrict__ z1,
+                            const int32_t* __restrict__ szp, const int32_t* __restrict__ szc,
+                            const double* __restrict__ szv, const int32_t* __restrict__ boff,
+                            const int32_t* __restrict__ cblk, const int64_t* __restrict__ beoff,
                             double* __restrict__ Ec) {
   const int32_t g = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (g >= ngrp) return;
   const int32_t c0 = gc0[g], c1 = gc1[g];
   if (c0 < 0) return;
+  // the group's columns and all columns it couples to share one block
+  const int32_t b = cblk[c0], o = boff[b], n = boff[b + 1] - o;
+  double* E = Ec + beoff[b];
   for (int32_t q = gcoff[g] + lane; q < gcoff[g + 1]; q += 64) {
     const int32_t c = gcols[q];
     double a0 = 0.0, a1 = 0.0;
@@ -96,8 +100,8 @@ __global__ void k_coarse_ec(int32_t ngrp, int32_t nc, const int32_t* __restrict_
         a1 += z1[row] * v;
       }
     }
-    Ec[(int64_t)c0 * nc + c] = a0;
-    if (c1 >= 0) Ec[(int64_t)c1 * nc + c] = a1;
+    E[(int64_t)(c0 - o) * n + (c - o)] = a0;
+    if (c1 >= 0) E[(int64_t)(c1 - o) * n + (c - o)] = a1;
   }
 }
 
@@ -141,33 +145,44 @@ __global__ void k_pair_add(const SubInfo* __restrict__ subs, const int32_t* __re
   for (int32_t r = threadIdx.x; r < n; r += blockDim.x) W[off + r] += dW[off + r];
 }
 
-// Largest |A| (one workgroup), the scale of the singularity test.
-__global__ void __launch_bounds__(1024) k_absmax(const double* __restrict__ A, int64_t n, double* __restrict__ out) {
+// Largest |A| of every diagonal block (one workgroup per block), the scale
+// of the singularity test.
+__global__ void __launch_bounds__(1024) k_absmax(const double* __restrict__ A, const int32_t* __restrict__ boff,
+                                                 const int64_t* __restrict__ beoff, double* __restrict__ out) {
   __shared__ double red[1024];
+  const int32_t b = blockIdx.x;
+  const int64_t n2 = beoff[b + 1] - beoff[b];
+  const double* E = A + beoff[b];
   double m = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, fabs(A[i]));
+  for (int64_t i = threadIdx.x; i < n2; i += blockDim.x) m = fmax(m, fabs(E[i]));
   red[threadIdx.x] = m;
   __syncthreads();
   for (int o = 512; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0];
+  if (threadIdx.x == 0) out[b] = red[0];
 }
 
-// Gauss-Jordan step k, part 1 (one workgroup): pivot = first row i >= k of
-// largest |A(i,k)|; swap rows k and pivot; copy the pivot row and column k.
-// work: [0] largest |A|, then prow (n), mcol (n).
-__global__ void __launch_bounds__(1024) k_gj_pivot(double* __restrict__ A, int32_t n, int32_t k,
-                                                   int32_t* __restrict__ perm, double* __restrict__ work,
-                                                   int32_t* __restrict__ info) {
+// Gauss-Jordan step k on every block of more than k columns, part 1 (one
+// workgroup per block): pivot = first row i >= k of largest |A(i,k)|; copies
+// of the pivot row and of column k (after the interchange), then the swap of
+// rows k and pivot.  work: amax[nb], prow[nc], mcol[nc] (block b at boff[b]).
+__global__ void __launch_bounds__(1024) k_gj_pivot(double* __restrict__ A, int32_t nb, int32_t k,
+                                                   const int32_t* __restrict__ boff,
+                                                   const int64_t* __restrict__ beoff, int32_t* __restrict__ perm,
+                                                   double* __restrict__ work, int32_t nc, int32_t* __restrict__ info) {
   __shared__ double bv[1024];
   __shared__ int32_t bi[1024];
+  const int32_t b = blockIdx.x;
+  const int32_t o = boff[b], n = boff[b + 1] - o;
+  if (k >= n) return;
+  double* E = A + beoff[b];
   const int tid = threadIdx.x;
   double best = -1.0;
   int32_t bidx = n;
   for (int32_t i = k + tid; i < n; i += blockDim.x) {
-    const double v = fabs(A[(int64_t)i * n + k]);
+    const double v = fabs(E[(int64_t)i * n + k]);
     if (v > best) {
       best = v;
       bidx = i;
@@ -176,10 +191,10 @@ __global__ void __launch_bounds__(1024) k_gj_pivot(double* __restrict__ A, int32
   bv[tid] = best;
   bi[tid] = bidx;
   __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
-    if (tid < o) {
-      const double v2 = bv[tid + o];
-      const int32_t i2 = bi[tid + o];
+  for (int s = 512; s > 0; s >>= 1) {
+    if (tid < s) {
+      const double v2 = bv[tid + s];
+      const int32_t i2 = bi[tid + s];
       if (v2 > bv[tid] || (v2 == bv[tid] && i2 < bi[tid])) {
         bv[tid] = v2;
         bi[tid] = i2;
@@ -189,52 +204,63 @@ __global__ void __launch_bounds__(1024) k_gj_pivot(double* __restrict__ A, int32
   }
   const int32_t p = bi[0];
   if (tid == 0) {
-    perm[k] = p;
-    if (!(bv[0] > 1e-13 * work[0])) info[0] = k + 1;
+    perm[o + k] = p;
+    if (!(bv[0] > 1e-13 * work[b]) && info[0] == 0) info[0] = o + k + 1;
   }
-  double* prow = work + 1;
-  double* mcol = prow + n;
+  double* prow = work + nb + o;
+  double* mcol = work + nb + nc + o;
   // copies first, from the matrix before the interchange (rows k and p
   // trade places); every load has returned before its thread reaches the
   // barrier, so the interchange below cannot overtake them
   for (int32_t i = tid; i < n; i += blockDim.x) {
     const int32_t src = i == k ? p : (i == p ? k : i);
-    mcol[i] = A[(int64_t)src * n + k];
+    mcol[i] = E[(int64_t)src * n + k];
   }
-  for (int32_t j = tid; j < n; j += blockDim.x) prow[j] = A[(int64_t)p * n + j];
+  for (int32_t j = tid; j < n; j += blockDim.x) prow[j] = E[(int64_t)p * n + j];
   __syncthreads();
   if (p != k)
     for (int32_t j = tid; j < n; j += blockDim.x) {
-      const double a = A[(int64_t)k * n + j], b = A[(int64_t)p * n + j];
-      A[(int64_t)k * n + j] = b;
-      A[(int64_t)p * n + j] = a;
+      const double x = E[(int64_t)k * n + j], y = E[(int64_t)p * n + j];
+      E[(int64_t)k * n + j] = y;
+      E[(int64_t)p * n + j] = x;
     }
 }
 
-// Gauss-Jordan step k, part 2: in-place inverse update with the copied
-// pivot row and column (every element reads only copies and itself).
-__global__ void k_gj_update(double* __restrict__ A, int32_t n, int32_t k, const double* __restrict__ work) {
+// Gauss-Jordan step k, part 2: in-place inverse update of every block with
+// more than k columns, from the copied pivot row and column (every element
+// reads only the copies and itself).  Grid: x over columns, y over the
+// coarse rows of all blocks.
+__global__ void k_gj_update(double* __restrict__ A, int32_t nb, int32_t nc, int32_t k,
+                            const int32_t* __restrict__ boff, const int32_t* __restrict__ cblk,
+                            const int64_t* __restrict__ beoff, const double* __restrict__ work) {
+  const int32_t r = blockIdx.y;
+  const int32_t b = cblk[r];
+  const int32_t o = boff[b], n = boff[b + 1] - o;
   const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t i = blockIdx.y;
-  if (j >= n) return;
-  const double* prow = work + 1;
-  const double* mcol = prow + n;
+  if (k >= n || j >= n) return;
+  const int32_t i = r - o;
+  const double* prow = work + nb + o;
+  const double* mcol = work + nb + nc + o;
   const double piv = prow[k];
   const double inv = 1.0 / piv;
-  double& a = A[(int64_t)i * n + j];
+  double& a = A[beoff[b] + (int64_t)i * n + j];
   if (i == k) a = j == k ? inv : prow[j] * inv;
   else if (j == k) a = -mcol[i] * inv;
   else a -= mcol[i] * (prow[j] * inv);
 }
 
-// Undo the row interchanges on the columns of the inverse: inv(A) is
-// inv(P A) with its columns swapped back in reverse order.
-__global__ void k_gj_colswap(double* __restrict__ A, int32_t n, const int32_t* __restrict__ perm) {
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double* row = A + (int64_t)i * n;
+// Undo the row interchanges on the columns of each block's inverse: inv(A)
+// is inv(P A) with its columns swapped back in reverse order.  One thread
+// per coarse row.
+__global__ void k_gj_colswap(double* __restrict__ A, int32_t nc, const int32_t* __restrict__ boff,
+                             const int32_t* __restrict__ cblk, const int64_t* __restrict__ beoff,
+                             const int32_t* __restrict__ perm) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nc) return;
+  const int32_t b = cblk[r], o = boff[b], n = boff[b + 1] - o;
+  double* row = A + beoff[b] + (int64_t)(r - o) * n;
   for (int32_t k = n - 1; k >= 0; --k) {
-    const int32_t p = perm[k];
+    const int32_t p = perm[o + k];
     if (p != k) {
       const double t = row[k];
       row[k] = row[p];
@@ -251,10 +277,14 @@ __global__ void k_coarse_restrict(int32_t ngrp, int32_t n_int, const int32_t* __
                                   const int32_t* __restrict__ f_colidx, const double* __restrict__ f_vals,
                                   const double* __restrict__ z0, const double* __restrict__ z1,
                                   const double* __restrict__ y, const double* __restrict__ zin,
-                                  double* __restrict__ t, double* __restrict__ g) {
+                                  double* __restrict__ t, double* __restrict__ g, const int32_t* __restrict__ live,
+                                  const int32_t* __restrict__ grp_sys) {
   const int32_t grp = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (grp >= ngrp) return;
+  // a piece lies inside one system; the groups of pressure-like rows that
+  // hold no coarse column may span systems and are always computed
+  if (live && gc0[grp] >= 0 && !live[grp_sys[grp]]) return;
   const int32_t a = goff[grp], cnt = goff[grp + 1] - a;
   double p0 = 0.0, p1 = 0.0;
   if (lane < cnt) {
@@ -276,15 +306,19 @@ __global__ void k_coarse_restrict(int32_t ngrp, int32_t n_int, const int32_t* __
   }
 }
 
-// Coarse solve y = E_c^{-1} g, one wave per row of the row-major inverse.
-__global__ void k_coarse_solve(int32_t nc, const double* __restrict__ Einv, const double* __restrict__ g,
-                               double* __restrict__ y) {
+// Coarse solve y = E_c^{-1} g blockwise, one wave per coarse row (a row of
+// its block's row-major inverse).
+__global__ void k_coarse_solve(int32_t nc, const double* __restrict__ Einv, const int32_t* __restrict__ boff,
+                               const int32_t* __restrict__ cblk, const int64_t* __restrict__ beoff,
+                               const double* __restrict__ g, double* __restrict__ y) {
   const int32_t i = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (i >= nc) return;
-  const double* row = Einv + (int64_t)i * nc;
+  const int32_t b = cblk[i], o = boff[b], n = boff[b + 1] - o;
+  const double* row = Einv + beoff[b] + (int64_t)(i - o) * n;
+  const double* gb = g + o;
   double acc = 0.0;
-  for (int32_t j = lane; j < nc; j += 64) acc += row[j] * g[j];
+  for (int32_t j = lane; j < n; j += 64) acc += row[j] * gb[j];
   acc = wave_sum(acc);
   if (lane == 0) y[i] = acc;
 }
@@ -319,23 +353,29 @@ void launch_coarse_refine(const addns_precond* pc, int32_t npairs, const int32_t
 
 void launch_coarse_ec(const addns_precond* pc, int32_t nc, double* Ec, hipStream_t s) {
   const int32_t ngrp = (int32_t)pc->coarse.grp_col0.size();
-  if (ngrp == 0) return;
+  if (ngrp == 0 || nc == 0) return;
   const int waves = 4;
   k_coarse_ec<<<(ngrp + waves - 1) / waves, 64 * waves, 0, s>>>(
-      ngrp, nc, pc->cz_goff.as<int32_t>(), pc->cz_grows.as<int32_t>(), pc->cz_gc0.as<int32_t>(),
+      ngrp, pc->cz_goff.as<int32_t>(), pc->cz_grows.as<int32_t>(), pc->cz_gc0.as<int32_t>(),
       pc->cz_gc1.as<int32_t>(), pc->cz_gcoff.as<int32_t>(), pc->cz_gcols.as<int32_t>(), pc->cz_z0.as<double>(),
-      pc->cz_z1.as<double>(), pc->cz_szp.as<int32_t>(), pc->cz_szc.as<int32_t>(), pc->cz_szv.as<double>(), Ec);
+      pc->cz_z1.as<double>(), pc->cz_szp.as<int32_t>(), pc->cz_szc.as<int32_t>(), pc->cz_szv.as<double>(),
+      pc->cz_boff.as<int32_t>(), pc->cz_cblk.as<int32_t>(), pc->cz_beoff.as<int64_t>(), Ec);
 }
 
-void launch_gj_invert(double* A, int32_t n, int32_t* perm, double* work, int32_t* info, hipStream_t s) {
-  if (n == 0) return;
-  k_absmax<<<1, 1024, 0, s>>>(A, (int64_t)n * n, work);
-  const dim3 grid((unsigned)((n + 255) / 256), (unsigned)n);
-  for (int32_t k = 0; k < n; ++k) {
-    k_gj_pivot<<<1, 1024, 0, s>>>(A, n, k, perm, work, info);
-    k_gj_update<<<grid, 256, 0, s>>>(A, n, k, work);
+void launch_gj_invert(const addns_precond* pc, double* A, int32_t* perm, double* work, int32_t* info, hipStream_t s) {
+  const CoarsePlan& cp = pc->coarse;
+  const int32_t nb = (int32_t)cp.blk_off.size() - 1, nc = cp.space.nc;
+  if (nb <= 0 || nc == 0) return;
+  const int32_t* boff = pc->cz_boff.as<int32_t>();
+  const int32_t* cblk = pc->cz_cblk.as<int32_t>();
+  const int64_t* beoff = pc->cz_beoff.as<int64_t>();
+  k_absmax<<<nb, 1024, 0, s>>>(A, boff, beoff, work);
+  const dim3 grid((unsigned)((cp.blk_max + 255) / 256), (unsigned)nc);
+  for (int32_t k = 0; k < cp.blk_max; ++k) {
+    k_gj_pivot<<<nb, 1024, 0, s>>>(A, nb, k, boff, beoff, perm, work, nc, info);
+    k_gj_update<<<grid, 256, 0, s>>>(A, nb, nc, k, boff, cblk, beoff, work);
   }
-  k_gj_colswap<<<(n + 255) / 256, 256, 0, s>>>(A, n, perm);
+  k_gj_colswap<<<(nc + 255) / 256, 256, 0, s>>>(A, nc, boff, cblk, beoff, perm);
 }
 
 void launch_coarse_restrict(const addns_precond* pc, const double* y, const double* z1, hipStream_t s) {
@@ -345,15 +385,17 @@ void launch_coarse_restrict(const addns_precond* pc, const double* y, const doub
   k_coarse_restrict<<<(ngrp + waves - 1) / waves, 64 * waves, 0, s>>>(
       ngrp, pc->plan.n_int, pc->cz_goff.as<int32_t>(), pc->cz_grows.as<int32_t>(), pc->cz_gc0.as<int32_t>(),
       pc->cz_gc1.as<int32_t>(), pc->f_rowptr.as<int32_t>(), pc->f_colidx.as<int32_t>(), pc->f_vals.as<double>(),
-      pc->cz_z0.as<double>(), pc->cz_z1.as<double>(), y, z1, pc->cz_t.as<double>(), pc->cz_g.as<double>());
+      pc->cz_z0.as<double>(), pc->cz_z1.as<double>(), y, z1, pc->cz_t.as<double>(), pc->cz_g.as<double>(),
+      pc->mask_live, pc->mask_grp.as<int32_t>());
 }
 
 void launch_coarse_solve(const addns_precond* pc, hipStream_t s) {
   const int32_t nc = pc->coarse_nc;
   if (nc == 0) return;
   const int waves = 4;
-  k_coarse_solve<<<(nc + waves - 1) / waves, 64 * waves, 0, s>>>(nc, pc->cz_einv.as<double>(),
-                                                                  pc->cz_g.as<double>(), pc->cz_y.as<double>());
+  k_coarse_solve<<<(nc + waves - 1) / waves, 64 * waves, 0, s>>>(
+      nc, pc->cz_einv.as<double>(), pc->cz_boff.as<int32_t>(), pc->cz_cblk.as<int32_t>(), pc->cz_beoff.as<int64_t>(),
+      pc->cz_g.as<double>(), pc->cz_y.as<double>());
 }
 
 }  // namespace addns

@@ -165,6 +165,13 @@ struct CoarsePlan {
   // restriction groups (<= 64 rows each): the pieces, then the other rows
   std::vector<int32_t> grp_off, grp_rows, grp_col0, grp_col1;
   std::vector<int32_t> grp_coff, grp_cols;        // per group: the columns of S Z on its rows, ascending
+  // E_c is block diagonal over runs of coarse columns that no entry couples
+  // (for concatenated systems, at least one block per system): block b holds
+  // columns [blk_off[b], blk_off[b+1]) and its dense inverse starts at
+  // element blk_eoff[b]
+  std::vector<int32_t> blk_off, col_blk;
+  std::vector<int64_t> blk_eoff;
+  int32_t blk_max = 0;
 };
 void build_coarse_space(const PartitionData& P, int32_t piece, CoarseSpace& cs);
 void build_coarse_plan(const PartitionData& P, const Plan& pl, int32_t piece, CoarsePlan& cp);
@@ -242,7 +249,13 @@ struct addns_precond {
   addns::DevBuf cz_einv;                              // (Z^T S Z)^{-1}, nc x nc row-major FP64
   addns::DevBuf cz_goff, cz_grows, cz_gc0, cz_gc1;    // restriction groups
   addns::DevBuf cz_gcoff, cz_gcols;                   //   and their S Z column lists
+  addns::DevBuf cz_boff, cz_cblk, cz_beoff;            // blocks of E_c
   addns::DevBuf cz_t, cz_g, cz_y;                     // apply scratch: t, Z^T t, y
+  // while a batched solve runs: per-system live flags (device) and the
+  // system of every subdomain, aggregate and restriction group; the apply
+  // kernels then skip the work units of systems that have converged
+  const int32_t* mask_live = nullptr;
+  addns::DevBuf mask_sub, mask_agg, mask_grp;
   addns::DevBuf smp_row, smp_nb, smp_loc;             // learned-correction sample table
   // GMRES work space (grown on demand)
   addns::DevBuf V, Z, w, xp, bp, rp, Hd, gd, partials, scal;
@@ -313,7 +326,9 @@ void launch_coarse_sz(const addns_precond* pc, const int32_t* sub_of, const int3
                       const int32_t* cpair_ptr, const int64_t* pair_off, const int32_t* int_off,
                       const double* W, hipStream_t s);
 void launch_coarse_ec(const addns_precond* pc, int32_t nc, double* Ec, hipStream_t s);
-void launch_gj_invert(double* A, int32_t n, int32_t* perm, double* work, int32_t* info, hipStream_t s);
+// Gauss-Jordan inverses of the diagonal blocks of E_c in place (blockwise
+// storage); work: nb + 2 nc doubles; info: first failing step + 1 (0 = ok)
+void launch_gj_invert(const addns_precond* pc, double* A, int32_t* perm, double* work, int32_t* info, hipStream_t s);
 void launch_coarse_restrict(const addns_precond* pc, const double* y, const double* z1, hipStream_t s);
 void launch_coarse_solve(const addns_precond* pc, hipStream_t s);
 void launch_overlap_split(int32_t k, const int32_t* agg_s, const int32_t* agg_w, const int64_t* g_off,
