@@ -221,6 +221,37 @@ def bench_picard(args):
         "runs": runs}))
 
 
+# Network arithmetic per sample: 7 -> 64 -> 64 -> 5 multiply-adds, forward;
+# the backward pass costs twice the forward (input and weight gradients).
+MLP_FWD_FLOP = 2 * (7 * 64 + 64 * 64 + 64 * 5)
+
+
+def network_timing(addns, torch, X, Y, M, w, reps):
+    """Whole-call medians of the network entry points over every training
+    row: the BF16 and FP32 forward passes and the full-data gradient (each
+    call also uploads the weights and synchronises)."""
+    import numpy as np
+    n = int(X.shape[0])
+    P = torch.empty((n, 5), dtype=torch.float32, device=X.device)
+    out = {"rows": n, "fwd_flop_per_row": MLP_FWD_FLOP}
+    for name, fn in (("forward_bf16", lambda: addns.dtn_forward(w, X, P, bf16=True)),
+                     ("forward_f32", lambda: addns.dtn_forward(w, X, P, bf16=False)),
+                     ("gradient_f32", lambda: addns.dtn_grad(w, X, Y, M))):
+        fn()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        ms = float(np.median(ts)) * 1e3
+        flop = MLP_FWD_FLOP * (3 if name.startswith("gradient") else 1) * n
+        out[name] = {"call_ms": round(ms, 4), "rows_per_s": round(n / ms * 1e3),
+                     "tflops": round(flop / ms / 1e9, 3)}
+    return out
+
+
 def bench_learned(args):
     """Learned interface correction: samples from 2000 seeded 64 x 64 systems
     (MSCN teacher), GPU training, then the judged FGMRES(50) on the 512 x 512
@@ -234,11 +265,17 @@ def bench_learned(args):
 
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    X, Y, M = learned.collect_samples(training_workloads(2000), 100)
+    nsys, epochs = (200, 3) if args.mlp_profile else (2000, 30)
+    X, Y, M = learned.collect_samples(training_workloads(nsys), 100)
     t1 = time.perf_counter()
-    w, loss = addns.dtn_train(X, Y, M, epochs=30, batch=1024, lr=2e-3, seed=0)
+    w, loss = addns.dtn_train(X, Y, M, epochs=epochs, batch=1024, lr=2e-3, seed=0)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    net = network_timing(addns, torch, X, Y, M, w, reps=args.reps if args.mlp_profile else 5)
+    if args.mlp_profile:
+        print(json.dumps({"mlp_profile": True, "rows": int(X.shape[0]), "train_s": round(t2 - t1, 3),
+                          "network": net}))
+        return
     held = Workload("uniform64_nu0.002_m4_heldout", 64, 1 / 500, None, 4, 64, 50, True, 1e-8, 78, F32, F32)
     out = {}
     for wl, maxit in ((held, 5000), (CAVITY512_STRETCHED, args.learned_maxit)):
@@ -285,7 +322,7 @@ def bench_learned(args):
         "vs_baseline": None, "dtype": "f64 outer / f32 factors / bf16 network", "data": "synthetic",
         "config": {"workload": "learned512", "eval": CAVITY512_STRETCHED.name, "train_systems": 2000,
                    "train_rows": int(X.shape[0]), "krylov": "FGMRES(50)", "maxit": args.learned_maxit},
-        "data_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
+        "data_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2), "network": net,
         "loss_first": float(loss[0]), "loss_last": float(loss[-1]), "results": out}))
 
 
@@ -315,9 +352,11 @@ def main():
                          "systems solved together; learned512: train the interface network and "
                          "judge it on the 512 x 512 stretched cavity (both reported separately)")
     ap.add_argument("--learned-maxit", type=int, default=1000)
+    ap.add_argument("--mlp-profile", action="store_true",
+                    help="learned512 only: samples from 200 systems, 3 epochs, then the network "
+                         "kernels x reps (for a kernel trace or counters)")
     ap.add_argument("--block-mult", type=int, default=None,
-                    help="sweep tile multiplier; 0 = autotune (default for batched96), 1 = the "
-                         "autotuner's choice for cavity128 (default there)")
+                    help="sweep tile multiplier (0 is taken as 1)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the multi-GPU path is a design, not a build "

@@ -89,122 +89,342 @@ __global__ void k_dtn_correct(int64_t count, const int64_t* __restrict__ smp_loc
 }
 
 // ---------------------------------------------------------------------------
-// network
+// network on the matrix cores
 // ---------------------------------------------------------------------------
-template <bool BF>
-__device__ inline void mlp_fwd(const float* __restrict__ w, const float* x, float* h1, float* h2, float* p) {
-  for (int i = 0; i < kH; ++i) {
-    float a = w[oB1 + i];
-#pragma unroll
-    for (int j = 0; j < kIn; ++j) a += w[oW1 + i * kIn + j] * x[j];
-    a = a > 0.0f ? a : 0.0f;
-    h1[i] = BF ? bf16_round(a) : a;
+// One wave evaluates a tile of 16 samples.  Features are the row dimension
+// of every product and samples the column dimension, so each layer is
+//   Out (F_out x 16) = W (F_out x F_in) In (F_in x 16) + b
+// on 16 x 16 MFMA tiles (FP32: v_mfma_f32_16x16x4f32; BF16 inference:
+// v_mfma_f32_16x16x16bf16_1k, FP32 accumulation).  Lane l = 16 g + c holds
+// rows 4 g + r (r = 0..3) of column c of an accumulator tile, which is the
+// B operand of the next product if that product's K index runs over
+// {4 g + r} for a fixed r (FP32) or over 4 g + r, r = 0..3 (BF16): the
+// matching A operand (a weight row) is read with the same K order, so the
+// layers chain in registers.  The first layer carries its bias as an
+// eighth input fixed to 1; the others start from the bias.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+
+// LDS copy of the weights, rows padded by one word (W1 with its bias as
+// column 7, W3 padded to 16 rows of zeros).
+constexpr int kLd1 = 9, kLd2 = kH + 1, kLd3 = kH + 1;
+constexpr int kLdsW1 = kH * kLd1, kLdsW2 = kH * kLd2, kLdsW3 = 16 * kLd3;
+struct WLds {
+  float w1[kLdsW1];  // [64][9]: W1 | b1 | 0
+  float w2[kLdsW2];  // [64][65]
+  float w3[kLdsW3];  // [16][65], rows 5..15 zero
+  float b2[kH];
+  float b3[16];      // 5..15 zero
+};
+
+__device__ void stage_weights(WLds& L, const float* __restrict__ wts, bool bf) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  auto rd = [&](int i) { return bf ? bf16_round(wts[i]) : wts[i]; };
+  for (int i = t; i < kH * 8; i += nt) {
+    const int r = i >> 3, k = i & 7;
+    L.w1[r * kLd1 + k] = k < kIn ? rd(oW1 + r * kIn + k) : rd(oB1 + r);
   }
-  for (int i = 0; i < kH; ++i) {
-    float a = w[oB2 + i];
-    for (int j = 0; j < kH; ++j) a += w[oW2 + i * kH + j] * h1[j];
-    a = a > 0.0f ? a : 0.0f;
-    h2[i] = BF ? bf16_round(a) : a;
-  }
-  for (int i = 0; i < kOut; ++i) {
-    float a = w[oB3 + i];
-    for (int j = 0; j < kH; ++j) a += w[oW3 + i * kH + j] * h2[j];
-    p[i] = a;
-  }
+  for (int i = t; i < kH * kH; i += nt) L.w2[(i / kH) * kLd2 + i % kH] = rd(oW2 + i);
+  for (int i = t; i < 16 * kH; i += nt) L.w3[(i / kH) * kLd3 + i % kH] = i < kOut * kH ? rd(oW3 + i) : 0.0f;
+  for (int i = t; i < kH; i += nt) L.b2[i] = rd(oB2 + i);
+  for (int i = t; i < 16; i += nt) L.b3[i] = i < kOut ? rd(oB3 + i) : 0.0f;
 }
 
-// one thread per sample; weights staged in LDS (rounded to BF16 when asked)
-__global__ void __launch_bounds__(256)
+__device__ inline f32x4 relu4(f32x4 a) {
+  f32x4 o;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) o[r] = a[r] > 0.0f ? a[r] : 0.0f;
+  return o;
+}
+
+// FP32 forward of one tile.  x[q] = input k = 4 q + g of sample c (k = 7:
+// the constant 1 of a present sample).  h1, h2: hidden tiles; returns the
+// output tile (rows 4 g + r < 5 meaningful).
+__device__ inline f32x4 fwd_f32(const WLds& L, const float (&x)[2], f32x4 (&h1)[4], f32x4 (&h2)[4]) {
+  const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(L.w1[(16 * mt + c) * kLd1 + 4 * q + g], x[q], acc, 0, 0, 0);
+    h1[mt] = relu4(acc);
+  }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = L.b2[16 * mt + 4 * g + r];
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(L.w2[(16 * mt + c) * kLd2 + 16 * kt + 4 * g + r], h1[kt][r], acc,
+                                                   0, 0, 0);
+    h2[mt] = relu4(acc);
+  }
+  f32x4 acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = L.b3[4 * g + r];
+#pragma unroll
+  for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(L.w3[c * kLd3 + 16 * kt + 4 * g + r], h2[kt][r], acc, 0, 0, 0);
+  return acc;
+}
+
+__device__ inline short bf16_bits(float x) { return (short)(__builtin_bit_cast(uint32_t, x) >> 16); }
+
+// BF16 forward of one tile (weights in L already rounded to BF16; the
+// inputs and the hidden activations are rounded here).  x[e] = input
+// k = 4 g + e of sample c.
+__device__ inline f32x4 fwd_bf16(const WLds& L, const float (&x)[4]) {
+  const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+  i16x4 xb;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) xb[e] = bf16_bits(bf16_round(x[e]));
+  i16x4 hb[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    i16x4 a;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a[e] = g < 2 ? bf16_bits(L.w1[(16 * mt + c) * kLd1 + 4 * g + e]) : (short)0;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, xb, acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) hb[mt][r] = bf16_bits(bf16_round(acc[r] > 0.0f ? acc[r] : 0.0f));
+  }
+  i16x4 h2b[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = L.b2[16 * mt + 4 * g + r];
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) {
+      i16x4 a;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[e] = bf16_bits(L.w2[(16 * mt + c) * kLd2 + 16 * kt + 4 * g + e]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, hb[kt], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h2b[mt][r] = bf16_bits(bf16_round(acc[r] > 0.0f ? acc[r] : 0.0f));
+  }
+  f32x4 acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = L.b3[4 * g + r];
+#pragma unroll
+  for (int kt = 0; kt < 4; ++kt) {
+    i16x4 a;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a[e] = bf16_bits(L.w3[c * kLd3 + 16 * kt + 4 * g + e]);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, h2b[kt], acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// Inference: 4 waves per workgroup, each wave one tile of 16 samples at a
+// time (grid-stride over tiles); weights staged once per workgroup.
+constexpr int kFwdWaves = 4;
+__global__ void __launch_bounds__(64 * kFwdWaves)
 k_mlp_forward(const float* __restrict__ wts, const float* __restrict__ X, float* __restrict__ P, int64_t count,
               int bf16) {
-  __shared__ float w[kNP];
-  for (int i = threadIdx.x; i < kNP; i += blockDim.x) w[i] = bf16 ? bf16_round(wts[i]) : wts[i];
+  __shared__ WLds L;
+  stage_weights(L, wts, bf16 != 0);
   __syncthreads();
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= count) return;
-  float x[kIn], h1[kH], h2[kH], p[kOut];
-  for (int j = 0; j < kIn; ++j) x[j] = bf16 ? bf16_round(X[kIn * k + j]) : X[kIn * k + j];
-  if (bf16) mlp_fwd<true>(w, x, h1, h2, p);
-  else mlp_fwd<false>(w, x, h1, h2, p);
-  for (int i = 0; i < kOut; ++i) P[kOut * k + i] = p[i];
+  const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+  const int64_t tiles = (count + 15) / 16;
+  for (int64_t t = (int64_t)blockIdx.x * kFwdWaves + (threadIdx.x >> 6); t < tiles;
+       t += (int64_t)gridDim.x * kFwdWaves) {
+    const int64_t k = 16 * t + c;
+    const bool ok = k < count;
+    f32x4 p;
+    if (bf16) {
+      float x[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = 4 * g + e;
+        x[e] = !ok || j > kIn ? 0.0f : (j == kIn ? 1.0f : X[kIn * k + j]);
+      }
+      p = fwd_bf16(L, x);
+    } else {
+      float x[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int j = 4 * q + g;
+        x[q] = !ok ? 0.0f : (j == kIn ? 1.0f : X[kIn * k + j]);
+      }
+      f32x4 h1[4], h2[4];
+      p = fwd_f32(L, x, h1, h2);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = 4 * g + r;
+      if (ok && o < kOut) P[kOut * k + o] = p[r];
+    }
+  }
 }
 
-// Partial gradient of one workgroup's samples (32 per workgroup, 64 threads):
-// forward and backward per sample, then parameter-wise sums over the
-// workgroup's samples in sample order.  gpart[wg][kNP], lpart[wg] = loss sum.
+// Partial gradient of one workgroup's samples (kGS per workgroup, one wave,
+// kGS / 16 tiles in order): forward and backward per tile on the matrix
+// cores, then the parameter gradients, which sum over samples, as products
+// whose K index is the sample: the tiles are transposed through LDS
+// (features on the lane's column, samples on its K slot) and accumulated in
+// registers across the tiles.  gpart[wg][kNP] and lpart[wg] = loss sum.
 constexpr int kGS = 32;
+constexpr int kLT = 17;  // LDS row stride of a transposed tile [feature][sample]
+struct GLds {
+  float h1[kH * kLT], h2[kH * kLT], d1[kH * kLT], d2[kH * kLT];
+  float x[8 * kLT], dp[8 * kLT];
+  float loss[64];
+};
+
 __global__ void __launch_bounds__(64)
 k_mlp_grad(const float* __restrict__ wts, const float* __restrict__ X, const float* __restrict__ Y,
            const float* __restrict__ M, const int32_t* __restrict__ idx, int64_t count, float scale,
            float* __restrict__ gpart, float* __restrict__ lpart) {
-  __shared__ float w[kNP];
-  __shared__ float sx[kGS][kIn], sh1[kGS][kH], sh2[kGS][kH], sd1[kGS][kH], sd2[kGS][kH], sdp[kGS][kOut];
-  __shared__ float sl[kGS];
-  for (int i = threadIdx.x; i < kNP; i += blockDim.x) w[i] = wts[i];
+  __shared__ WLds L;
+  __shared__ GLds T;
+  stage_weights(L, wts, false);
+  const int l = threadIdx.x, g = l >> 4, c = l & 15;
+  const f32x4 z4 = {0.0f, 0.0f, 0.0f, 0.0f};
+  f32x4 gw1[4], gw2[4][4], gw3[4], gb2[4], gb3 = z4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    gw1[i] = z4;
+    gw3[i] = z4;
+    gb2[i] = z4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) gw2[i][j] = z4;
+  }
+  float loss = 0.0f;
   __syncthreads();
-  const int t = threadIdx.x;
-  const int64_t k = (int64_t)blockIdx.x * kGS + t;
-  if (t < kGS) {
-    float x[kIn], h1[kH], h2[kH], p[kOut], dp[kOut];
+  for (int tile = 0; tile < kGS / 16; ++tile) {
+    const int64_t k = (int64_t)blockIdx.x * kGS + 16 * tile + c;
     const bool ok = k < count;
     const int64_t sk = ok ? (idx ? idx[k] : k) : 0;
-    for (int j = 0; j < kIn; ++j) x[j] = ok ? X[kIn * sk + j] : 0.0f;
-    mlp_fwd<false>(w, x, h1, h2, p);
-    float loss = 0.0f;
-    for (int i = 0; i < kOut; ++i) {
-      const float m = ok ? M[kOut * sk + i] : 0.0f;
-      const float d = p[i] - (ok ? Y[kOut * sk + i] : 0.0f);
-      loss += m * d * d;
-      dp[i] = 2.0f * m * d * scale;
+    float x[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int j = 4 * q + g;
+      x[q] = !ok ? 0.0f : (j == kIn ? 1.0f : X[kIn * sk + j]);
     }
-    sl[t] = loss;
-    for (int i = 0; i < kOut; ++i) sdp[t][i] = dp[i];
-    for (int j = 0; j < kIn; ++j) sx[t][j] = x[j];
-    for (int i = 0; i < kH; ++i) {
-      sh1[t][i] = h1[i];
-      sh2[t][i] = h2[i];
+    f32x4 h1[4], h2[4];
+    const f32x4 p = fwd_f32(L, x, h1, h2);
+    // output error (rows 4 g + r < 5)
+    f32x4 dp;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = 4 * g + r;
+      dp[r] = 0.0f;
+      if (ok && o < kOut) {
+        const float m = M[kOut * sk + o];
+        const float d = p[r] - Y[kOut * sk + o];
+        loss += m * d * d;
+        dp[r] = 2.0f * m * d * scale;
+      }
     }
-    // dh2 = W3^T dp, through ReLU
-    for (int j = 0; j < kH; ++j) {
-      float a = 0.0f;
-      for (int i = 0; i < kOut; ++i) a += w[oW3 + i * kH + j] * dp[i];
-      sd2[t][j] = h2[j] > 0.0f ? a : 0.0f;
+    // dH2 = W3^T dp through the ReLU (K over the outputs 4 g + r)
+    f32x4 d2[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 acc = z4;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(L.w3[(4 * g + r) * kLd3 + 16 * mt + c], dp[r], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) d2[mt][r] = h2[mt][r] > 0.0f ? acc[r] : 0.0f;
     }
-    // dh1 = W2^T dh2, through ReLU
-    for (int j = 0; j < kH; ++j) {
-      float a = 0.0f;
-      for (int i = 0; i < kH; ++i) a += w[oW2 + i * kH + j] * sd2[t][i];
-      sd1[t][j] = h1[j] > 0.0f ? a : 0.0f;
+    // dH1 = W2^T dH2 through the ReLU
+    f32x4 d1[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 acc = z4;
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(L.w2[(16 * kt + 4 * g + r) * kLd2 + 16 * mt + c], d2[kt][r],
+                                                     acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) d1[mt][r] = h1[mt][r] > 0.0f ? acc[r] : 0.0f;
     }
+    // transpose the tile through LDS: [feature][sample]
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int f = (16 * mt + 4 * g + r) * kLT + c;
+        T.h1[f] = h1[mt][r];
+        T.h2[f] = h2[mt][r];
+        T.d1[f] = d1[mt][r];
+        T.d2[f] = d2[mt][r];
+      }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) T.x[(4 * q + g) * kLT + c] = x[q];
+    if (g < 2) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) T.dp[(4 * g + r) * kLT + c] = dp[r];
+    }
+    __syncthreads();
+    // parameter gradients, K = the 16 samples in 4 steps of 4
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int sc = 4 * q + g;  // this lane's sample slot in step q
+      float a2[4], b1[4], a1[4], b2[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a2[t] = T.d2[(16 * t + c) * kLT + sc];
+        b1[t] = T.h1[(16 * t + c) * kLT + sc];
+        a1[t] = T.d1[(16 * t + c) * kLT + sc];
+        b2[t] = T.h2[(16 * t + c) * kLT + sc];
+      }
+      const float bx = c < 8 ? T.x[c * kLT + sc] : 0.0f;
+      const float ap = c < kOut ? T.dp[c * kLT + sc] : 0.0f;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) gw2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[mt], b1[nt], gw2[mt][nt], 0, 0, 0);
+        gb2[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[mt], 1.0f, gb2[mt], 0, 0, 0);
+        gw1[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[mt], bx, gw1[mt], 0, 0, 0);
+        gw3[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ap, b2[mt], gw3[mt], 0, 0, 0);
+      }
+      gb3 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap, 1.0f, gb3, 0, 0, 0);
+    }
+    __syncthreads();  // the next tile overwrites T
   }
+  // every parameter written once: lane (g, c) holds rows 4 g + r of column c
+  float* gout = gpart + (int64_t)blockIdx.x * kNP;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int f = 16 * mt + 4 * g + r;
+      if (c < kIn) gout[oW1 + f * kIn + c] = gw1[mt][r];
+      else if (c == kIn) gout[oB1 + f] = gw1[mt][r];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) gout[oW2 + f * kH + 16 * nt + c] = gw2[mt][nt][r];
+      if (c == 0) gout[oB2 + f] = gb2[mt][r];
+    }
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = 4 * g + r;
+      if (o < kOut) gout[oW3 + o * kH + 16 * nt + c] = gw3[nt][r];
+    }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int o = 4 * g + r;
+    if (c == 0 && o < kOut) gout[oB3 + o] = gb3[r];
+  }
+  // loss: fixed-order sum over the lanes
+  T.loss[l] = loss;
   __syncthreads();
-  float* g = gpart + (int64_t)blockIdx.x * kNP;
-  for (int prm = t; prm < kNP; prm += blockDim.x) {
+  if (l == 0) {
     float a = 0.0f;
-    if (prm < oB1) {
-      const int i = prm / kIn, j = prm % kIn;
-      for (int q = 0; q < kGS; ++q) a += sd1[q][i] * sx[q][j];
-    } else if (prm < oW2) {
-      const int i = prm - oB1;
-      for (int q = 0; q < kGS; ++q) a += sd1[q][i];
-    } else if (prm < oB2) {
-      const int i = (prm - oW2) / kH, j = (prm - oW2) % kH;
-      for (int q = 0; q < kGS; ++q) a += sd2[q][i] * sh1[q][j];
-    } else if (prm < oW3) {
-      const int i = prm - oB2;
-      for (int q = 0; q < kGS; ++q) a += sd2[q][i];
-    } else if (prm < oB3) {
-      const int i = (prm - oW3) / kH, j = (prm - oW3) % kH;
-      for (int q = 0; q < kGS; ++q) a += sdp[q][i] * sh2[q][j];
-    } else {
-      const int i = prm - oB3;
-      for (int q = 0; q < kGS; ++q) a += sdp[q][i];
-    }
-    g[prm] = a;
-  }
-  if (t == 0) {
-    float a = 0.0f;
-    for (int q = 0; q < kGS; ++q) a += sl[q];
+    for (int q = 0; q < 64; ++q) a += T.loss[q];
     lpart[blockIdx.x] = a;
   }
 }
@@ -246,7 +466,10 @@ void launch_dtn_correct(int64_t count, const int64_t* smp_loc, const float* D, d
   if (count > 0) k_dtn_correct<<<nb(count, 256), 256, 0, s>>>(count, smp_loc, D, G);
 }
 void launch_mlp_forward(const float* wts, const float* X, float* P, int64_t count, int bf16, hipStream_t s) {
-  if (count > 0) k_mlp_forward<<<nb(count, 256), 256, 0, s>>>(wts, X, P, count, bf16);
+  if (count <= 0) return;
+  const int64_t tiles = (count + 15) / 16;
+  const unsigned grid = (unsigned)std::min<int64_t>((tiles + kFwdWaves - 1) / kFwdWaves, 2048);
+  k_mlp_forward<<<grid, 64 * kFwdWaves, 0, s>>>(wts, X, P, count, bf16);
 }
 void launch_mlp_grad(const float* wts, const float* X, const float* Y, const float* M, const int32_t* idx,
                      int64_t count, float scale, float* gpart, float* lpart, hipStream_t s) {
