@@ -22,14 +22,14 @@ hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 constexpr char kTag[8] = {'A', 'D', 'D', 'N', 'S', 'D', 'T', 'N'};
 
 // Full-data gradient (scale 1/count) and loss sum, FP32, fixed order.
-double full_grad(const float* d_w, const float* X, const float* Y, const float* M, int64_t count, float* d_grad,
+double full_grad(const float* d_img, const float* X, const float* Y, const float* M, int64_t count, float* d_grad,
                  DevBuf& gpart, DevBuf& lpart, hipStream_t s) {
-  const int G = mlp_grad_group(), NP = mlp_param_count();
-  const int nwg = (int)((count + G - 1) / G);
+  const int NP = mlp_param_count();
+  const int nwg = mlp_grad_groups(count);
   if (gpart.bytes < sizeof(float) * (size_t)nwg * NP) gpart.alloc(sizeof(float) * (size_t)nwg * NP);
   if (lpart.bytes < sizeof(float) * (size_t)nwg) lpart.alloc(sizeof(float) * nwg);
-  launch_mlp_grad(d_w, X, Y, M, nullptr, count, 1.0f / (float)count, gpart.as<float>(), lpart.as<float>(), s);
-  launch_mlp_reduce_adam(gpart.as<float>(), nwg, d_grad, nullptr, nullptr, nullptr, 0, 0, 0, 0, 0, 1, 1, s);
+  launch_mlp_grad(d_img, X, Y, M, nullptr, count, 1.0f / (float)count, gpart.as<float>(), lpart.as<float>(), s);
+  launch_mlp_reduce_adam(gpart.as<float>(), nwg, d_grad, nullptr, nullptr, nullptr, nullptr, 0, 0, 0, 0, 0, 1, 1, s);
   std::vector<float> l(nwg);
   ADDNS_HIP(hipMemcpyAsync(l.data(), lpart.p, sizeof(float) * nwg, hipMemcpyDeviceToHost, s));
   ADDNS_HIP(hipStreamSynchronize(s));
@@ -78,10 +78,12 @@ int addns_dtn_forward(const float* h_weights, const float* d_X, float* d_P, int6
   return guarded("addns_dtn_forward", [&]() -> int {
     if (!h_weights || !d_X || !d_P || count < 0) throw ArgError("null argument");
     hipStream_t s = as_stream(stream);
-    DevBuf w;
+    DevBuf w, img;
     w.alloc(sizeof(float) * mlp_param_count());
+    img.alloc(sizeof(float) * mlp_image_floats());
     ADDNS_HIP(hipMemcpyAsync(w.p, h_weights, sizeof(float) * mlp_param_count(), hipMemcpyHostToDevice, s));
-    launch_mlp_forward(w.as<float>(), d_X, d_P, count, bf16, s);
+    launch_mlp_image(w.as<float>(), img.as<float>(), s);
+    launch_mlp_forward(img.as<float>(), d_X, d_P, count, bf16, s);
     ADDNS_HIP(hipStreamSynchronize(s));
     return ADDNS_OK;
   });
@@ -93,11 +95,13 @@ int addns_dtn_grad(const float* h_weights, const float* d_X, const float* d_Y, c
     if (!h_weights || !d_X || !d_Y || !d_M || !h_grad || count < 1) throw ArgError("null argument");
     hipStream_t s = as_stream(stream);
     const int NP = mlp_param_count();
-    DevBuf w, g, gp, lp;
+    DevBuf w, img, g, gp, lp;
     w.alloc(sizeof(float) * NP);
+    img.alloc(sizeof(float) * mlp_image_floats());
     g.alloc(sizeof(float) * NP);
     ADDNS_HIP(hipMemcpyAsync(w.p, h_weights, sizeof(float) * NP, hipMemcpyHostToDevice, s));
-    const double l = full_grad(w.as<float>(), d_X, d_Y, d_M, count, g.as<float>(), gp, lp, s);
+    launch_mlp_image(w.as<float>(), img.as<float>(), s);
+    const double l = full_grad(img.as<float>(), d_X, d_Y, d_M, count, g.as<float>(), gp, lp, s);
     ADDNS_HIP(hipMemcpyAsync(h_grad, g.p, sizeof(float) * NP, hipMemcpyDeviceToHost, s));
     ADDNS_HIP(hipStreamSynchronize(s));
     if (loss) *loss = l / (double)count;
@@ -111,7 +115,7 @@ int addns_dtn_train(const float* d_X, const float* d_Y, const float* d_M, int64_
     if (!d_X || !d_Y || !d_M || !hp || !h_weights || count < 1) throw ArgError("null argument");
     if (hp->epochs < 0 || hp->batch < 1 || !(hp->lr > 0.0f)) throw ArgError("epochs >= 0, batch >= 1, lr > 0");
     hipStream_t s = as_stream(stream);
-    const int NP = mlp_param_count(), G = mlp_grad_group();
+    const int NP = mlp_param_count();
     std::mt19937_64 rng((uint64_t)hp->seed);
     std::vector<float> w0(NP, 0.0f);
     if (hp->init_given) {
@@ -126,16 +130,18 @@ int addns_dtn_train(const float* d_X, const float* d_Y, const float* d_M, int64_
       fill(64 * 7 + 64, 64, 64, std::sqrt(2.0f));
       fill(64 * 7 + 64 + 64 * 64 + 64, 5, 64, 1.0f);
     }
-    DevBuf w, m1, m2, grad, gp, lp, idx;
+    DevBuf w, img, m1, m2, grad, gp, lp, idx;
     w.alloc(sizeof(float) * NP);
+    img.alloc(sizeof(float) * mlp_image_floats());
     m1.alloc(sizeof(float) * NP);
     m2.alloc(sizeof(float) * NP);
     grad.alloc(sizeof(float) * NP);
     ADDNS_HIP(hipMemcpyAsync(w.p, w0.data(), sizeof(float) * NP, hipMemcpyHostToDevice, s));
+    launch_mlp_image(w.as<float>(), img.as<float>(), s);
     ADDNS_HIP(hipMemsetAsync(m1.p, 0, sizeof(float) * NP, s));
     ADDNS_HIP(hipMemsetAsync(m2.p, 0, sizeof(float) * NP, s));
     const int64_t B = hp->batch;
-    const int nwg_max = (int)((B + G - 1) / G);
+    const int nwg_max = mlp_grad_groups(B);
     gp.alloc(sizeof(float) * (size_t)nwg_max * NP);
     lp.alloc(sizeof(float) * nwg_max);
     std::vector<int32_t> perm(count);
@@ -149,18 +155,19 @@ int addns_dtn_train(const float* d_X, const float* d_Y, const float* d_M, int64_
       ADDNS_HIP(hipStreamSynchronize(s));  // perm is reused next epoch
       for (int64_t off = 0; off < count; off += B) {
         const int64_t nb = std::min(B, count - off);
-        const int nwg = (int)((nb + G - 1) / G);
+        const int nwg = mlp_grad_groups(nb);
         ++step;
-        launch_mlp_grad(w.as<float>(), d_X, d_Y, d_M, idx.as<int32_t>() + off, nb, 1.0f / (float)nb, gp.as<float>(),
+        launch_mlp_grad(img.as<float>(), d_X, d_Y, d_M, idx.as<int32_t>() + off, nb, 1.0f / (float)nb, gp.as<float>(),
                         lp.as<float>(), s);
-        launch_mlp_reduce_adam(gp.as<float>(), nwg, grad.as<float>(), w.as<float>(), m1.as<float>(), m2.as<float>(), 1,
+        launch_mlp_reduce_adam(gp.as<float>(), nwg, grad.as<float>(), w.as<float>(), img.as<float>(), m1.as<float>(),
+                               m2.as<float>(), 1,
                                hp->lr, b1, b2, eps, 1.0f - std::pow(b1, (float)step),
                                1.0f - std::pow(b2, (float)step), s);
       }
       if (h_loss) {
         DevBuf g2, gp2, lp2;
         g2.alloc(sizeof(float) * NP);
-        h_loss[ep] = full_grad(w.as<float>(), d_X, d_Y, d_M, count, g2.as<float>(), gp2, lp2, s) / (double)count;
+        h_loss[ep] = full_grad(img.as<float>(), d_X, d_Y, d_M, count, g2.as<float>(), gp2, lp2, s) / (double)count;
       }
     }
     ADDNS_HIP(hipMemcpyAsync(h_weights, w.p, sizeof(float) * NP, hipMemcpyDeviceToHost, s));

@@ -202,15 +202,17 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
       // S_i ~ G_i + Delta_i: features of each separator velocity row, the
       // network's corrections on G's stencil slots inside the aggregate
       const int np = mlp_param_count();
-      DevBuf wts, X, Dl;
+      DevBuf wts, img, X, Dl;
       wts.alloc(sizeof(float) * np);
+      img.alloc(sizeof(float) * mlp_image_floats());
       ADDNS_HIP(hipMemcpyAsync(wts.p, o.learned_model, sizeof(float) * np, hipMemcpyHostToDevice, s));
+      launch_mlp_image(wts.as<float>(), img.as<float>(), s);
       X.alloc(sizeof(float) * 7 * nsmp);
       Dl.alloc(sizeof(float) * 5 * nsmp);
       launch_dtn_features(nsmp, pc->smp_row.as<int32_t>(), pc->smp_nb.as<int32_t>(), pc->cp_rowptr.as<int32_t>(),
                           pc->cp_colidx.as<int32_t>(), cpv, pc->perm.as<int32_t>(), pc->R.as<double>(),
                           X.as<float>(), s);
-      launch_mlp_forward(wts.as<float>(), X.as<float>(), Dl.as<float>(), nsmp, o.learned_bf16 ? 1 : 0, s);
+      launch_mlp_forward(img.as<float>(), X.as<float>(), Dl.as<float>(), nsmp, o.learned_bf16 ? 1 : 0, s);
       launch_dtn_correct(nsmp, pc->smp_loc.as<int64_t>(), Dl.as<float>(), G, s);
       ADDNS_HIP(hipStreamSynchronize(s));
     }

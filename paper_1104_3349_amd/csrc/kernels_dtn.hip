@@ -14,6 +14,8 @@
 // inference optionally rounds weights and activations to BF16.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "precond.h"
 
 namespace addns {
@@ -109,25 +111,52 @@ typedef short i16x4 __attribute__((ext_vector_type(4)));
 // column 7, W3 padded to 16 rows of zeros).
 constexpr int kLd1 = 9, kLd2 = kH + 1, kLd3 = kH + 1;
 constexpr int kLdsW1 = kH * kLd1, kLdsW2 = kH * kLd2, kLdsW3 = 16 * kLd3;
-struct WLds {
+struct alignas(16) WLds {
   float w1[kLdsW1];  // [64][9]: W1 | b1 | 0
   float w2[kLdsW2];  // [64][65]
   float w3[kLdsW3];  // [16][65], rows 5..15 zero
   float b2[kH];
   float b3[16];      // 5..15 zero
 };
+// The same layout in device memory (the weight image): built from the packed
+// parameters once (k_mlp_image) and kept current by the Adam step, so that a
+// workgroup stages it with wide, independent loads.
+constexpr int kImgW1 = 0, kImgW2 = kImgW1 + kLdsW1, kImgW3 = kImgW2 + kLdsW2, kImgB2 = kImgW3 + kLdsW3,
+              kImgB3 = kImgB2 + kH, kImg = kImgB3 + 16;
+static_assert(sizeof(WLds) == sizeof(float) * kImg && kImg % 4 == 0, "weight image layout");
 
-__device__ void stage_weights(WLds& L, const float* __restrict__ wts, bool bf) {
-  const int t = threadIdx.x, nt = blockDim.x;
-  auto rd = [&](int i) { return bf ? bf16_round(wts[i]) : wts[i]; };
-  for (int i = t; i < kH * 8; i += nt) {
-    const int r = i >> 3, k = i & 7;
-    L.w1[r * kLd1 + k] = k < kIn ? rd(oW1 + r * kIn + k) : rd(oB1 + r);
+// image position of packed parameter prm
+__device__ inline int img_pos(int prm) {
+  if (prm < oB1) return kImgW1 + (prm / kIn) * kLd1 + prm % kIn;
+  if (prm < oW2) return kImgW1 + (prm - oB1) * kLd1 + kIn;
+  if (prm < oB2) return kImgW2 + ((prm - oW2) / kH) * kLd2 + (prm - oW2) % kH;
+  if (prm < oW3) return kImgB2 + (prm - oB2);
+  if (prm < oB3) return kImgW3 + ((prm - oW3) / kH) * kLd3 + (prm - oW3) % kH;
+  return kImgB3 + (prm - oB3);
+}
+
+// one workgroup: zero the image (its padding stays zero), then place every
+// parameter
+__global__ void __launch_bounds__(256) k_mlp_image(const float* __restrict__ wts, float* __restrict__ img) {
+  for (int i = threadIdx.x; i < kImg; i += blockDim.x) img[i] = 0.0f;
+  __syncthreads();
+  for (int i = threadIdx.x; i < kNP; i += blockDim.x) img[img_pos(i)] = wts[i];
+}
+
+__device__ void stage_weights(WLds& L, const float* __restrict__ img, bool bf) {
+  const float4* src = reinterpret_cast<const float4*>(img);
+  float4* dst = reinterpret_cast<float4*>(&L);
+#pragma unroll 8
+  for (int i = threadIdx.x; i < kImg / 4; i += blockDim.x) {
+    float4 v = src[i];
+    if (bf) {
+      v.x = bf16_round(v.x);
+      v.y = bf16_round(v.y);
+      v.z = bf16_round(v.z);
+      v.w = bf16_round(v.w);
+    }
+    dst[i] = v;
   }
-  for (int i = t; i < kH * kH; i += nt) L.w2[(i / kH) * kLd2 + i % kH] = rd(oW2 + i);
-  for (int i = t; i < 16 * kH; i += nt) L.w3[(i / kH) * kLd3 + i % kH] = i < kOut * kH ? rd(oW3 + i) : 0.0f;
-  for (int i = t; i < kH; i += nt) L.b2[i] = rd(oB2 + i);
-  for (int i = t; i < 16; i += nt) L.b3[i] = i < kOut ? rd(oB3 + i) : 0.0f;
 }
 
 __device__ inline f32x4 relu4(f32x4 a) {
@@ -228,10 +257,10 @@ __device__ inline f32x4 fwd_bf16(const WLds& L, const float (&x)[4]) {
 // time (grid-stride over tiles); weights staged once per workgroup.
 constexpr int kFwdWaves = 4;
 __global__ void __launch_bounds__(64 * kFwdWaves)
-k_mlp_forward(const float* __restrict__ wts, const float* __restrict__ X, float* __restrict__ P, int64_t count,
+k_mlp_forward(const float* __restrict__ img, const float* __restrict__ X, float* __restrict__ P, int64_t count,
               int bf16) {
   __shared__ WLds L;
-  stage_weights(L, wts, bf16 != 0);
+  stage_weights(L, img, bf16 != 0);
   __syncthreads();
   const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
   const int64_t tiles = (count + 15) / 16;
@@ -266,13 +295,16 @@ k_mlp_forward(const float* __restrict__ wts, const float* __restrict__ X, float*
   }
 }
 
-// Partial gradient of one workgroup's samples (kGS per workgroup, one wave,
-// kGS / 16 tiles in order): forward and backward per tile on the matrix
-// cores, then the parameter gradients, which sum over samples, as products
-// whose K index is the sample: the tiles are transposed through LDS
-// (features on the lane's column, samples on its K slot) and accumulated in
-// registers across the tiles.  gpart[wg][kNP] and lpart[wg] = loss sum.
-constexpr int kGS = 32;
+// Partial gradient of one workgroup's samples (one wave; workgroup w takes
+// the contiguous samples [w per, (w + 1) per), per a multiple of 16, in
+// tiles of 16 in order): forward and backward per tile on the matrix cores,
+// then the parameter gradients, which sum over samples, as products whose K
+// index is the sample: the tiles are transposed through LDS (features on the
+// lane's column, samples on its K slot) and accumulated in registers across
+// the tiles.  gpart[wg][kNP] and lpart[wg] = loss sum.  The number of
+// workgroups depends on the sample count only (mlp_grad_groups), so the
+// summation order, and the result, is fixed for a given count.
+constexpr int kMaxGradGroups = 1024;
 constexpr int kLT = 17;  // LDS row stride of a transposed tile [feature][sample]
 struct GLds {
   float h1[kH * kLT], h2[kH * kLT], d1[kH * kLT], d2[kH * kLT];
@@ -281,12 +313,12 @@ struct GLds {
 };
 
 __global__ void __launch_bounds__(64)
-k_mlp_grad(const float* __restrict__ wts, const float* __restrict__ X, const float* __restrict__ Y,
-           const float* __restrict__ M, const int32_t* __restrict__ idx, int64_t count, float scale,
-           float* __restrict__ gpart, float* __restrict__ lpart) {
+k_mlp_grad(const float* __restrict__ img, const float* __restrict__ X, const float* __restrict__ Y,
+           const float* __restrict__ M, const int32_t* __restrict__ idx, int64_t count, int64_t per,
+           float scale, float* __restrict__ gpart, float* __restrict__ lpart) {
   __shared__ WLds L;
   __shared__ GLds T;
-  stage_weights(L, wts, false);
+  stage_weights(L, img, false);
   const int l = threadIdx.x, g = l >> 4, c = l & 15;
   const f32x4 z4 = {0.0f, 0.0f, 0.0f, 0.0f};
   f32x4 gw1[4], gw2[4][4], gw3[4], gb2[4], gb3 = z4;
@@ -300,9 +332,10 @@ k_mlp_grad(const float* __restrict__ wts, const float* __restrict__ X, const flo
   }
   float loss = 0.0f;
   __syncthreads();
-  for (int tile = 0; tile < kGS / 16; ++tile) {
-    const int64_t k = (int64_t)blockIdx.x * kGS + 16 * tile + c;
-    const bool ok = k < count;
+  const int64_t k0 = (int64_t)blockIdx.x * per, k1 = min(count, k0 + per);
+  for (int64_t kt0 = k0; kt0 < k1; kt0 += 16) {
+    const int64_t k = kt0 + c;
+    const bool ok = k < k1;
     const int64_t sk = ok ? (idx ? idx[k] : k) : 0;
     float x[2];
 #pragma unroll
@@ -431,19 +464,31 @@ k_mlp_grad(const float* __restrict__ wts, const float* __restrict__ X, const flo
 
 // fixed-order sum of the workgroup partials, then (optionally) one Adam step
 __global__ void k_mlp_reduce_adam(const float* __restrict__ gpart, int nwg, float* __restrict__ grad,
-                                  float* __restrict__ wts, float* __restrict__ m1, float* __restrict__ m2, int adam,
-                                  float lr, float b1, float b2, float eps, float bc1, float bc2) {
+                                  float* __restrict__ wts, float* __restrict__ img, float* __restrict__ m1,
+                                  float* __restrict__ m2, int adam, float lr, float b1, float b2, float eps, float bc1,
+                                  float bc2) {
   const int prm = blockIdx.x * blockDim.x + threadIdx.x;
   if (prm >= kNP) return;
+  // loads in batches of 8 (independent), added in partial order
   float g = 0.0f;
-  for (int q = 0; q < nwg; ++q) g += gpart[(int64_t)q * kNP + prm];
+  int q = 0;
+  for (; q + 8 <= nwg; q += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = gpart[(int64_t)(q + u) * kNP + prm];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) g += v[u];
+  }
+  for (; q < nwg; ++q) g += gpart[(int64_t)q * kNP + prm];
   grad[prm] = g;
   if (!adam) return;
   const float a = b1 * m1[prm] + (1.0f - b1) * g;
   const float v = b2 * m2[prm] + (1.0f - b2) * g * g;
   m1[prm] = a;
   m2[prm] = v;
-  wts[prm] -= lr * (a / bc1) / (sqrtf(v / bc2) + eps);
+  const float wn = wts[prm] - lr * (a / bc1) / (sqrtf(v / bc2) + eps);
+  wts[prm] = wn;
+  img[img_pos(prm)] = wn;
 }
 
 inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -451,7 +496,9 @@ inline unsigned nb(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 }  // namespace
 
 int mlp_param_count() { return kNP; }
-int mlp_grad_group() { return kGS; }
+int mlp_grad_groups(int64_t count) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((count + 15) / 16, kMaxGradGroups));
+}
 
 void launch_dtn_features(int64_t count, const int32_t* smp_row, const int32_t* smp_nb, const int32_t* rp,
                          const int32_t* ci, const double* cv, const int32_t* perm, const double* R, float* X,
@@ -465,19 +512,24 @@ void launch_dtn_targets(int64_t count, const int64_t* smp_loc, const double* S, 
 void launch_dtn_correct(int64_t count, const int64_t* smp_loc, const float* D, double* G, hipStream_t s) {
   if (count > 0) k_dtn_correct<<<nb(count, 256), 256, 0, s>>>(count, smp_loc, D, G);
 }
-void launch_mlp_forward(const float* wts, const float* X, float* P, int64_t count, int bf16, hipStream_t s) {
+int mlp_image_floats() { return kImg; }
+void launch_mlp_image(const float* wts, float* img, hipStream_t s) { k_mlp_image<<<1, 256, 0, s>>>(wts, img); }
+void launch_mlp_forward(const float* img, const float* X, float* P, int64_t count, int bf16, hipStream_t s) {
   if (count <= 0) return;
   const int64_t tiles = (count + 15) / 16;
   const unsigned grid = (unsigned)std::min<int64_t>((tiles + kFwdWaves - 1) / kFwdWaves, 2048);
-  k_mlp_forward<<<grid, 64 * kFwdWaves, 0, s>>>(wts, X, P, count, bf16);
+  k_mlp_forward<<<grid, 64 * kFwdWaves, 0, s>>>(img, X, P, count, bf16);
 }
-void launch_mlp_grad(const float* wts, const float* X, const float* Y, const float* M, const int32_t* idx,
+void launch_mlp_grad(const float* img, const float* X, const float* Y, const float* M, const int32_t* idx,
                      int64_t count, float scale, float* gpart, float* lpart, hipStream_t s) {
-  if (count > 0) k_mlp_grad<<<nb(count, kGS), 64, 0, s>>>(wts, X, Y, M, idx, count, scale, gpart, lpart);
+  if (count <= 0) return;
+  const int nwg = mlp_grad_groups(count);
+  const int64_t per = ((count + nwg - 1) / nwg + 15) / 16 * 16;
+  k_mlp_grad<<<nwg, 64, 0, s>>>(img, X, Y, M, idx, count, per, scale, gpart, lpart);
 }
-void launch_mlp_reduce_adam(const float* gpart, int nwg, float* grad, float* wts, float* m1, float* m2, int adam,
-                            float lr, float b1, float b2, float eps, float bc1, float bc2, hipStream_t s) {
-  k_mlp_reduce_adam<<<nb(kNP, 256), 256, 0, s>>>(gpart, nwg, grad, wts, m1, m2, adam, lr, b1, b2, eps, bc1, bc2);
+void launch_mlp_reduce_adam(const float* gpart, int nwg, float* grad, float* wts, float* img, float* m1, float* m2,
+                            int adam, float lr, float b1, float b2, float eps, float bc1, float bc2, hipStream_t s) {
+  k_mlp_reduce_adam<<<nb(kNP, 256), 256, 0, s>>>(gpart, nwg, grad, wts, img, m1, m2, adam, lr, b1, b2, eps, bc1, bc2);
 }
 
 }  // namespace addns

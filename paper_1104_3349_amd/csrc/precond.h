@@ -390,18 +390,23 @@ void launch_seg_combine(const double* Z, int64_t ldz, const double* state, int64
                         int32_t ldh, int32_t restart, const Chunk* ch, int nch, double* x, hipStream_t s);
 // learned interface correction (kernels_dtn.hip)
 int mlp_param_count();
-int mlp_grad_group();
+int mlp_grad_groups(int64_t count);  // workgroups (partials) of launch_mlp_grad
 void launch_dtn_features(int64_t count, const int32_t* smp_row, const int32_t* smp_nb, const int32_t* rp,
                          const int32_t* ci, const double* cv, const int32_t* perm, const double* R, float* X,
                          hipStream_t s);
 void launch_dtn_targets(int64_t count, const int64_t* smp_loc, const double* S, const double* G, float* Y, float* M,
                         hipStream_t s);
 void launch_dtn_correct(int64_t count, const int64_t* smp_loc, const float* D, double* G, hipStream_t s);
-void launch_mlp_forward(const float* wts, const float* X, float* P, int64_t count, int bf16, hipStream_t s);
-void launch_mlp_grad(const float* wts, const float* X, const float* Y, const float* M, const int32_t* idx,
+// The network kernels read the weights as an image (the LDS layout of the
+// padded weight tiles, mlp_image_floats() floats), built by
+// launch_mlp_image from the packed parameters and updated by every Adam step.
+int mlp_image_floats();
+void launch_mlp_image(const float* wts, float* img, hipStream_t s);
+void launch_mlp_forward(const float* img, const float* X, float* P, int64_t count, int bf16, hipStream_t s);
+void launch_mlp_grad(const float* img, const float* X, const float* Y, const float* M, const int32_t* idx,
                      int64_t count, float scale, float* gpart, float* lpart, hipStream_t s);
-void launch_mlp_reduce_adam(const float* gpart, int nwg, float* grad, float* wts, float* m1, float* m2, int adam,
-                            float lr, float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
+void launch_mlp_reduce_adam(const float* gpart, int nwg, float* grad, float* wts, float* img, float* m1, float* m2,
+                            int adam, float lr, float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
 
 // Runs an entry point's body, turning exceptions into status codes and a
 // thread-local message: no C++ exception crosses the C boundary.

@@ -158,7 +158,7 @@ def test_forward_fp32_and_bf16():
 def test_gradient_matches_oracle_backprop():
     S, ora, smp = _oracle_data()
     n = min(len(smp.rows), 1000)
-    assert n > 64  # several workgroups of 32 samples
+    assert n > 64  # several workgroups
     X, Y, M = (a[:n].astype(np.float32) for a in (smp.X, smp.Y, smp.M))
     # scale targets to O(1) so that the loss is not dominated by rounding
     Y = (Y / max(np.abs(Y).max(), 1e-30)).astype(np.float32)
