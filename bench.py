@@ -60,13 +60,13 @@ def _events_median_ms(fn, reps, torch):
     return float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
 
 
-def measured_traffic():
+def measured_traffic(workload="cavity128"):
     """Calibrated FETCH_SIZE + WRITE_SIZE bytes per interior-solve launch from
-    the committed rocprofv3 summary; None once the kernel source differs from
-    the one that was profiled."""
+    the committed rocprofv3 summary of `workload`; None once the kernel source
+    differs from the one that was profiled."""
     import hashlib
     import re
-    prof = os.path.join(ROOT, "profiles", "interior_solve_cavity128_pmc.md")
+    prof = os.path.join(ROOT, "profiles", f"interior_solve_{workload}_pmc.md")
     src = os.path.join(ROOT, "paper_1104_3349_amd", "csrc", "kernels_apply.hip")
     try:
         text = open(prof).read()
@@ -446,22 +446,22 @@ def main():
         info = pc.info()
         print(json.dumps({"kernel_profile": True, "workload": wl.name, "reps": args.reps,
                           "copy_bytes": 256 * 2 ** 20,
-                          "interior_bytes_method": n_int * (2 * info["kl"] + info["ku"] + 1) * 4 + 20 * n_int,
+                          "interior_bytes_method": info["band_words"] * 4 + 20 * n_int,
                           "chunk_bytes": info["chunk_bytes"], "factor_bytes": info["factor_bytes"],
                           "sweep_chunks": info["sweep_chunks"]}))
         return
 
     def interior_roofline(pc, part, sf, reps=100):
         """HIP-event median of `reps` interior solves on the current stream and
-        the method's bytes per solve: band factors L (KL) and U (KL + KU + 1)
-        per interior row, pivots, the vector in and out.  The chunked sweep's
+        the method's bytes per solve: band factors L (kl_j) and U (kl_j + ku_j
+        + 1) per row of interior j, pivots, the vector in and out.  The chunked sweep's
         response matrices are reported beside them as overhead."""
         info = pc.info()
         n_int = int(part.info()["n_interior"])
         d_y1 = torch.randn(n_int, dtype=torch.float64, device=dev)
         d_z1 = torch.empty_like(d_y1)
         t = _events_median_ms(lambda: addns.interior_solve(pc, d_y1, d_z1), reps, torch)
-        b_int = n_int * (2 * info["kl"] + info["ku"] + 1) * sf + 4 * n_int + 16 * n_int
+        b_int = info["band_words"] * sf + 4 * n_int + 16 * n_int
         kern = "k_chunk_lower + k_chunk_upper + k_chunk_fix" if info["sweep_chunks"] > 1 else "k_interior_solve"
         ach = b_int / (t * 1e-3)
         return {"bound": "hbm", "kernel": kern, "achieved": round(ach / 1e9, 2), "peak": PEAK / 1e9,
@@ -584,7 +584,7 @@ def bench_large(args, addns, torch, dev):
         d_y1 = torch.randn(n_int, dtype=torch.float64, device=dev)
         d_z1 = torch.empty_like(d_y1)
         t_int = _events_median_ms(lambda: addns.interior_solve(pc, d_y1, d_z1), 100, torch)
-        b_int = n_int * (2 * info["kl"] + info["ku"] + 1) * 4 + 20 * n_int
+        b_int = info["band_words"] * 4 + 20 * n_int
         d_y = torch.randn(N, dtype=torch.float64, device=dev)
         d_o = torch.empty_like(d_y)
         t_app = _events_median_ms(lambda: addns.apply_precond(pc, d_y, d_o), 100, torch)
@@ -603,7 +603,8 @@ def bench_large(args, addns, torch, dev):
                                         if info["sweep_chunks"] > 1 else "k_interior_solve",
                                         "launch_ms": round(t_int, 4), "bytes_per_launch": int(b_int),
                                         "achieved_GBps": round(b_int / (t_int * 1e-3) / 1e9, 2),
-                                        "frac": round(b_int / (t_int * 1e-3) / PEAK, 4)},
+                                        "frac": round(b_int / (t_int * 1e-3) / PEAK, 4),
+                                        "traffic": measured_traffic("cavity512s")},
                      "sweep_chunks": info["sweep_chunks"], "factor_bytes": int(info["factor_bytes"])}
         del pc
     return out

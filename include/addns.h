@@ -380,19 +380,22 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
 /* Sizes of a preconditioner: any pointer may be NULL.  bytes_apply is the
    algorithmic byte count of one apply (band factors read once per sweep,
    pivots, coupling blocks, interface inverses, vector passes); block_mult
-   is the sweep tile multiplier in use (chosen by the autotuner when the
-   options asked for 0); learned_count is the number of learned-correction
+   is the sweep tile multiplier in use (0 in the options is taken as 1);
+   learned_count is the number of learned-correction
    samples (separator velocity rows); interior_nnz is the number of stored
    entries of the interior factors (multipliers below the unit diagonal and
    U, real rows and columns), the numerator of the fill factor of section 5
    with or without ILU dropping; sweep_chunks is the chunk count p of the
    interior sweep in use (1 = one workgroup per interior) and chunk_bytes the
    size of its response matrices, read once per interior solve (included
-   twice in bytes_apply). */
+   twice in bytes_apply).  kl and ku are the largest band widths over the
+   interiors; band_words is sum_j n_j (2 kl_j + ku_j + 1), the entries of the
+   interior band factors with each interior's own widths (the factors one
+   interior solve reads, section 4, Algorithm 2). */
 int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb_lower,
                        int32_t* nb_upper, int64_t* factor_bytes, int64_t* bytes_apply,
                        int64_t* learned_count, int32_t* block_mult, int64_t* interior_nnz,
-                       int32_t* sweep_chunks, int64_t* chunk_bytes);
+                       int32_t* sweep_chunks, int64_t* chunk_bytes, int64_t* band_words);
 
 /* Copy the dense interface blocks S_i (before inversion) into a HOST array
    in aggregate order, row-major per block; `count` must equal the sum of

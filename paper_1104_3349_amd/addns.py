@@ -93,7 +93,7 @@ def lib():
         "addns_precond_refactor": (C.c_int, [P, P, P, P, P]),
         "addns_interior_solve": (C.c_int, [P, P, P, P]),
         "addns_gmres_solve": (C.c_int, [P, P, P, C.POINTER(GmresOpts), C.POINTER(GmresResult), P]),
-        "addns_precond_info": (C.c_int, [P, i32p, i32p, i32p, i32p, i64p, i64p, i64p, i32p, i64p, i32p, i64p]),
+        "addns_precond_info": (C.c_int, [P, i32p, i32p, i32p, i32p, i64p, i64p, i64p, i32p, i64p, i32p, i64p, i64p]),
         "addns_precond_schur_blocks": (C.c_int, [P, P, C.c_int64]),
         "addns_precond_fill": (C.c_int, [P, i64p, i64p]),
         "addns_partition_destroy": (None, [P]),
@@ -252,14 +252,16 @@ class Precond:
         nz = C.c_int64()
         ch = C.c_int32()
         cb = C.c_int64()
+        bw = C.c_int64()
         _check(lib().addns_precond_info(self.handle, *[C.byref(x) for x in i32 + i64], C.byref(bm),
-                                        C.byref(nz), C.byref(ch), C.byref(cb)), "precond_info")
+                                        C.byref(nz), C.byref(ch), C.byref(cb), C.byref(bw)), "precond_info")
         d = dict(zip(("kl", "ku", "nb_lower", "nb_upper", "factor_bytes", "bytes_apply",
                       "learned_count"), (x.value for x in i32 + i64)))
         d["block_mult"] = bm.value
         d["interior_nnz"] = nz.value
         d["sweep_chunks"] = ch.value
         d["chunk_bytes"] = cb.value
+        d["band_words"] = bw.value
         return d
 
     def fill(self):

@@ -1026,7 +1026,7 @@ int addns_gmres_solve_batched(addns_precond_t pc, int32_t nsys, const int32_t* s
 
 int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb_lower, int32_t* nb_upper,
                        int64_t* factor_bytes, int64_t* bytes_apply, int64_t* learned_count, int32_t* block_mult,
-                       int64_t* interior_nnz, int32_t* sweep_chunks, int64_t* chunk_bytes) {
+                       int64_t* interior_nnz, int32_t* sweep_chunks, int64_t* chunk_bytes, int64_t* band_words) {
   if (!pc) {
     set_error("addns_precond_info: null handle");
     return ADDNS_ERR_ARG;
@@ -1042,6 +1042,11 @@ int addns_precond_info(addns_precond_t pc, int32_t* kl, int32_t* ku, int32_t* nb
   if (interior_nnz) *interior_nnz = pc->interior_nnz;
   if (sweep_chunks) *sweep_chunks = pc->sweep_chunks;
   if (chunk_bytes) *chunk_bytes = pc->chunk_bytes;
+  if (band_words) {
+    int64_t w = 0;
+    for (const SubInfo& q : pc->plan.subs) w += (int64_t)q.n * (2 * q.kl + q.ku + 1);
+    *band_words = w;
+  }
   return ADDNS_OK;
 }
 

@@ -78,20 +78,22 @@ __device__ __attribute__((always_inline)) inline Geo make_geo(int R, int K) {
 }
 
 // Loads columns k0 .. k0+CB-1 of M (column-major, leading dimension R).
-// The blocks store their structural zeros, so no per-lane mask is needed:
-// each column's base address is wave-uniform (scalar registers) and the
-// lane's row is the only per-lane part of an address.  With Z, a row slot
-// that lies wholly in a column's structural zeros is skipped by a
-// wave-uniform branch: fewer bytes, more instructions.  Few subdomains leave
-// the sweep bound by per-CU issue and latency, many subdomains by HBM, so the
-// setup times both forms on the actual factors and keeps the faster:
+// The blocks store their structural zeros, so the plain form needs no
+// per-lane mask: each column's base address is wave-uniform (scalar
+// registers) and the lane's row is the only per-lane part of an address.
+// With Z, each lane loads only rows inside its column's nonzero range (and
+// below R); the others keep an exact zero: fewer bytes (no slot or row past
+// the structure is fetched), more instructions.  Few subdomains leave the
+// sweep bound by per-CU issue and latency, many subdomains by HBM, so the
+// setup times both forms on the actual factors and keeps the faster (they
+// give the same result bit for bit):
 //   kind 2: upper        M(r,k) = 0 for r > k
 //   kind 3: band-shifted M(r,k) = 0 for r < k - par
 //   kind 4: [lower; full] M(r,k) = 0 for r < min(k, par)
-// The last slot may run past row R - 1 (at most 63 rows): those products
-// land in rows that are never stored, and every factor allocation is padded
-// so that the overrun stays inside it.  Columns past the wave's range repeat
-// its last column (their vector weight is 0).
+// In the plain form the last slot may run past row R - 1 (at most 64 S - 1
+// rows): those products land in rows that are never stored, and every
+// factor allocation is padded so that the overrun stays inside it.  Columns
+// past the wave's range repeat its last column (their vector weight is 0).
 template <class T, int S, int kind, bool Z>
 __device__ __attribute__((always_inline)) inline void load_chunk(Chunk<T, S>& c, const Geo& g, const T* M, int par,
                                                                  const int32_t* gidx, int k0) {
@@ -105,9 +107,9 @@ __device__ __attribute__((always_inline)) inline void load_chunk(Chunk<T, S>& c,
     const int lo = kind == 3 ? max(0, k - par) : (kind == 4 ? min(k, par) : 0);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const int rs0 = g.r0 + 64 * s;
+      const int r = g.r0 + 64 * s + (int)lane;
       T x = T(0);
-      if (!Z || (rs0 < hi && rs0 + 64 > lo)) x = col[(uint32_t)g.r0 + lane + 64u * s];  // wave-uniform
+      if (!Z || (r >= lo && r < hi)) x = col[(uint32_t)r];
       c.v[j][s] = x;
     }
     if (gidx) c.gi[j] = gidx[k];
@@ -903,7 +905,7 @@ static void run_sweep(const addns_precond* pc, const SweepArgs& a, int grid, con
   const size_t smem = sweep_smem_bytes(pl.maxW, pl.nbU);
   if (smem > 160 * 1024 || pl.nbU > kSweepThreads)
     throw ArgError("interior bandwidth too large for the LDS-staged sweep");
-  const int S = std::min(5, (std::max(pl.maxW, pl.nbU) + 63) / 64);
+  const int S = std::min(kSweepMaxSlots, (std::max(pl.maxW, pl.nbU) + 63) / 64);
   // zero-slot skipping is a tile choice of the autotuner: skipped slots hold
   // exact zeros, so both forms give bitwise the same result
   const bool z = pc->zero_skip != 0;
@@ -936,7 +938,7 @@ struct TypeTag {
 template <class F>
 static void with_sweep_shape(const addns_precond* pc, F&& f) {
   const Plan& pl = pc->plan;
-  const int S = std::min(5, (std::max(pl.maxW, pl.nbU) + 63) / 64);
+  const int S = std::min(kSweepMaxSlots, (std::max(pl.maxW, pl.nbU) + 63) / 64);
   auto by_s = [&](auto tt, auto zz) {
     switch (S) {
       case 1: f(tt, std::integral_constant<int, 1>{}, zz); break;
@@ -1019,7 +1021,7 @@ void release_chunked_sweep(addns_precond* pc) {
 void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
   const Plan& pl = pc->plan;
   if (p < 2 || p > max_sweep_chunks(pl)) throw ArgError("sweep_chunks exceeds the upper blocks of an interior");
-  const int S = std::min(5, (std::max(pl.maxW, pl.nbU) + 63) / 64);
+  const int S = std::min(kSweepMaxSlots, (std::max(pl.maxW, pl.nbU) + 63) / 64);
   const int m = pl.m;
   const int fb = pc->interior_prec == P64 ? 8 : 4;
   int32_t klmax = 1;

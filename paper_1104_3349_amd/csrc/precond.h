@@ -191,6 +191,9 @@ constexpr int32_t kMaxCoarseColumns = 8192;
 // Bytes past the end of each interior factor array that the sweep may read
 // (its last row slot can overrun a block by up to 64 * 5 - 1 FP64 rows).
 constexpr int64_t kSweepOverrunBytes = 4096;
+constexpr int kSweepMaxSlots = 5;  // row slots of 64 rows per wave in a sweep GEMV
+static_assert(kSweepOverrunBytes >= (64 * kSweepMaxSlots - 1) * (int64_t)sizeof(double),
+              "the zeroed tail must cover the largest row-slot overrun");
 
 // Largest aggregate count of the overlapped interface solve (its chain
 // keeps 12 bytes per aggregate in LDS).
