@@ -141,6 +141,7 @@ def bench_batched(args):
 
     def step():
         pc = addns.setup_precond(cat, N, d_rp, d_ci, d_v, interior_prec=addns.F32, schur_prec=addns.F32,
+                                 block_sizing=args.block_sizing,
                                  block_mult=args.block_mult, coarse=args.coarse)
         d_x.zero_()
         res, code = addns.gmres_solve_batched(pc, offs, d_b, d_x, restart=50, maxit=20000, tol=1e-8)
@@ -346,6 +347,8 @@ def main():
                     help="only the dominant kernel (interior solve) x reps, plus a 256 MiB device "
                          "copy of known size to calibrate memory counters")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--block-sizing", type=int, default=0, choices=[0, 1, 2],
+                    help="sweep block sizes: 0 = the library's rule, 1 = one for all, 2 = per interior")
     ap.add_argument("--workload", default="cavity128",
                     choices=["cavity128", "batched96", "learned512", "picard128"],
                     help="cavity128: the headline single system; batched96: 96 independent "
@@ -396,6 +399,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         pc = addns.setup_precond(part, N, d_rp, d_ci, d_v, schur=schur, interior_prec=iprec, schur_prec=sprec,
+                                 block_sizing=args.block_sizing,
                                  block_mult=args.block_mult, overlap=overlap, ilu_tol=ilu_tol,
                                  sweep_chunks=args.sweep_chunks, coarse=coarse)
         torch.cuda.synchronize()
@@ -433,6 +437,7 @@ def main():
             part = addns.build_partition(N, rp, ci, v, wl.m, wl.sz)
             d_rp, d_ci, d_v = (torch.from_numpy(a).to(dev) for a in (rp, ci, v))
         pc = addns.setup_precond(part, N, d_rp, d_ci, d_v, interior_prec=iprec, schur_prec=sprec,
+                                 block_sizing=args.block_sizing,
                                  block_mult=args.block_mult, sweep_chunks=args.sweep_chunks)
         n_int = int(part.info()["n_interior"])
         d_y1 = torch.randn(n_int, dtype=torch.float64, device=dev)
@@ -487,6 +492,7 @@ def main():
     torch.cuda.synchronize()
     t_cold = time.perf_counter()
     pc_cold = addns.setup_precond(part_fresh, N, d_rp, d_ci, d_v, interior_prec=iprec, schur_prec=sprec,
+                                  block_sizing=args.block_sizing,
                                   block_mult=args.block_mult, sweep_chunks=args.sweep_chunks, coarse=args.coarse)
     torch.cuda.synchronize()
     first_setup_s = time.perf_counter() - t_cold
@@ -576,6 +582,7 @@ def bench_large(args, addns, torch, dev):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         pc = addns.setup_precond(part, N, d_rp, d_ci, d_v, interior_prec=addns.F32, schur_prec=addns.F32,
+                                 block_sizing=args.block_sizing,
                                  block_mult=1, coarse=coarse)
         torch.cuda.synchronize()
         t_setup = time.perf_counter() - t1

@@ -224,10 +224,19 @@ typedef struct {
                              overlap > 0 (else ADDNS_ERR_ARG); a singular
                              Z^T S Z gives ADDNS_ERR_SINGULAR */
   int32_t sweep_zero_skip;  /* sweep form: 0 = time the sweep with and without
-                             skipping structural-zero row slots and keep the
-                             faster (the default; both give the same result bit
-                             for bit); 1 = never skip; 2 = always skip; else
-                             ADDNS_ERR_ARG */
+                             loading only each stored column's nonzero rows and
+                             keep the faster (the default; both give the same
+                             result bit for bit); 1 = never skip; 2 = always
+                             skip; else ADDNS_ERR_ARG */
+  int32_t block_sizing;   /* sweep block sizes: 1 = one size for every interior
+                             (the widest band sets it: fewest dependent steps);
+                             2 = each interior its own (fewest bytes and least
+                             work); 0 = 2 when the interiors outnumber the
+                             device's compute units (their workgroups then queue
+                             and the total work counts), else 1: a rule of the
+                             plan and the device, no timing.  The two regroup
+                             the same factors into different blocks, so their
+                             solves agree to rounding only; else ADDNS_ERR_ARG */
 } addns_precond_opts;
 
 /* ------------------------------------------------------------------------

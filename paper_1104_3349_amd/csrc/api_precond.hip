@@ -41,11 +41,12 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
   if (P) {
     // the host plan depends on the partition and on (schur, block_mult,
     // overlap) only: reuse the partition's copy when those match
+    const bool per = o.block_sizing == 2;
     if (cache && cache->have_plan && cache->schur == o.schur && cache->block_mult == std::max(1, o.block_mult) &&
-        cache->overlap == o.overlap) {
+        cache->overlap == o.overlap && cache->per_interior == (int)per) {
       pl = cache->plan;
     } else {
-      build_plan(*P, pl, o.schur, o.block_mult, o.overlap);
+      build_plan(*P, pl, o.schur, o.block_mult, o.overlap, per);
       if (cache) {
         cache->plan = pl;
         cache->have_plan = true;
@@ -53,6 +54,7 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
         cache->schur = o.schur;
         cache->block_mult = std::max(1, o.block_mult);
         cache->overlap = o.overlap;
+        cache->per_interior = (int)per;
       }
     }
   }
@@ -569,8 +571,20 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
   return guarded("addns_setup_precond", [&]() -> int {
     if (!p || !out || !d_rowptr || !d_colidx || !d_vals) throw ArgError("null argument");
     if (N != p->d.N) throw ArgError("N does not match the partition");
-    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1, 0, 0, 0.0, 0, 0, 0};
+    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1, 0, 0, 0.0, 0, 0, 0, 0};
     if (opts) o = *opts;
+    if (o.block_sizing < 0 || o.block_sizing > 2) throw ArgError("block_sizing must be 0, 1 or 2");
+    if (o.block_sizing == 0) {
+      // With at most one interior per compute unit the sweep takes as long as
+      // its longest chain of dependent steps, which a shared block size keeps
+      // short; with more interiors than compute units the workgroups queue,
+      // and the total work, which each interior's own size keeps small, counts.
+      hipDeviceProp_t prop;
+      int dev = 0;
+      ADDNS_HIP(hipGetDevice(&dev));
+      ADDNS_HIP(hipGetDeviceProperties(&prop, dev));
+      o.block_sizing = p->d.m > prop.multiProcessorCount ? 2 : 1;
+    }
     if (o.sweep_zero_skip < 0 || o.sweep_zero_skip > 2) throw ArgError("sweep_zero_skip must be 0, 1 or 2");
     if (o.coarse < 0 || o.coarse > 64) throw ArgError("coarse piece size must lie in 0..64");
     if (o.coarse > 0 && o.overlap > 0) throw ArgError("the coarse correction is built for non-overlapping aggregates");

@@ -695,15 +695,16 @@ __global__ void k_chunk_products(const SubInfo* __restrict__ subs, const int64_t
   Pc[((int64_t)w0 + col) * rows + r] = (T)acc;
 }
 
-// Coupling columns of each chunk boundary: flags[(j p + c) nbU + k] = 1 if
-// column k of U_{b,b+1}, b = u_{c+1} - 1, holds a nonzero.
+// Coupling columns of each chunk boundary: flags[(j p + c) ld + k] = 1 if
+// column k of U_{b,b+1}, b = u_{c+1} - 1, holds a nonzero (ld: the largest
+// upper block size, a stride shared by every interior).
 template <class T>
 __global__ void k_chunk_nzcols(const SubInfo* __restrict__ subs, const T* __restrict__ u12_all, int32_t p,
-                               uint8_t* __restrict__ flags) {
+                               int32_t ld, uint8_t* __restrict__ flags) {
   const int32_t j = blockIdx.x / (p - 1), c = blockIdx.x % (p - 1);
   const SubInfo q = subs[j];
   const int32_t nbU = q.nbu;
-  uint8_t* f = flags + ((int64_t)j * p + c) * nbU;
+  uint8_t* f = flags + ((int64_t)j * p + c) * ld;
   if (q.n == 0) {
     for (int32_t k = threadIdx.x; k < nbU; k += blockDim.x) f[k] = 0;
     return;
@@ -1036,10 +1037,10 @@ void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
     ADDNS_HIP(hipMemsetAsync(d_flags.p, 0, flags.size(), s));
     if (pc->interior_prec == P64)
       k_chunk_nzcols<double><<<m * (p - 1), 256, 0, s>>>(pc->subs.as<SubInfo>(), pc->u12.as<double>(), p,
-                                                         d_flags.as<uint8_t>());
+                                                         pl.nbU, d_flags.as<uint8_t>());
     else
       k_chunk_nzcols<float><<<m * (p - 1), 256, 0, s>>>(pc->subs.as<SubInfo>(), pc->u12.as<float>(), p,
-                                                        d_flags.as<uint8_t>());
+                                                        pl.nbU, d_flags.as<uint8_t>());
     ADDNS_HIP(hipMemcpyAsync(flags.data(), d_flags.p, flags.size(), hipMemcpyDeviceToHost, s));
     ADDNS_HIP(hipStreamSynchronize(s));
   }

@@ -12,7 +12,8 @@ namespace addns {
 
 static int32_t round_up(int32_t a, int32_t b) { return (a + b - 1) / b * b; }
 
-void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult, int overlap) {
+void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult, int overlap,
+                bool per_interior) {
   const int32_t N = P.N;
   pl.N = N;
   pl.m = P.m;
@@ -67,11 +68,15 @@ void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult
   // block bidiagonal); nbu = 2 nbl lets one padding serve both sweeps
   // One block size for every subdomain: each sweep step costs about one
   // memory round trip whatever its size, so a subdomain with a narrower band
-  // must not get more (smaller) steps than the widest one.
+  // must not get more (smaller) steps than the widest one.  Per interior:
+  // each its own minimum, fewer stored entries (the inverted diagonal blocks
+  // grow with the block) for a sweep bound by memory traffic.
   pl.block_mult = std::max(1, block_mult);
+  pl.per_interior = per_interior;
+  auto min_nbl = [&](int32_t j) { return round_up(std::max({1, kl[j], (kl[j] + ku[j] + 1) / 2}), 8); };
   int32_t nbl_all = 1;
-  for (int32_t j = 0; j < m; ++j) nbl_all = std::max({nbl_all, kl[j], (kl[j] + ku[j] + 1) / 2});
-  nbl_all = round_up(nbl_all, 8) * pl.block_mult;
+  for (int32_t j = 0; j < m; ++j) nbl_all = std::max(nbl_all, min_nbl(j));
+  nbl_all *= pl.block_mult;
   pl.subs.assign(m, SubInfo{});
   pl.lblks.clear();
   pl.ublks.clear();
@@ -82,7 +87,7 @@ void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult
     q.n = P.int_offsets[j + 1] - P.int_offsets[j];
     q.kl = kl[j];
     q.ku = ku[j];
-    q.nbl = nbl_all;
+    q.nbl = per_interior ? min_nbl(j) * pl.block_mult : nbl_all;
     q.nbu = 2 * q.nbl;
     q.npad = q.n == 0 ? 0 : round_up(q.n, q.nbu);
     q.ldab = 2 * q.kl + q.ku + 1;

@@ -101,6 +101,7 @@ struct Plan {
   int32_t nbL = 0, nbU = 0;   // largest block sizes
   int32_t maxW = 0;           // largest lower window nbl + kl
   int32_t block_mult = 1;     // lower block size = block_mult x its minimum
+  bool per_interior = false;  // block sizes per interior (else one for all)
   // permuted CSR of C~ (new numbering) and the source entry of each value
   std::vector<int32_t> cp_rowptr, cp_colidx, cp_src, cp_orow;
   std::vector<int32_t> perm, iperm;
@@ -139,7 +140,10 @@ struct Plan {
   std::vector<int64_t> smp_loc;                  // 5 per sample: element of the dense G/S block or -1
 };
 
-void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult, int overlap);
+// per_interior: each interior's own lower block size (else the widest band's
+// for all)
+void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult, int overlap,
+                bool per_interior);
 
 // Coarse space of the two-level interface solve: pieces of at most `piece`
 // separator velocity nodes, one constant and (pieces of three nodes or
@@ -179,7 +183,7 @@ void build_coarse_plan(const PartitionData& P, const Plan& pl, int32_t piece, Co
 // Host plans of one partition, keyed by the options they depend on.
 struct PlanCache {
   bool have_plan = false, have_coarse = false;
-  int schur = -1, block_mult = -1, overlap = -1, piece = -1;
+  int schur = -1, block_mult = -1, overlap = -1, piece = -1, per_interior = -1;
   Plan plan;
   CoarsePlan coarse;
 };

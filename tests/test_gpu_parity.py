@@ -309,6 +309,10 @@ def test_setup_argument_errors():
         with pytest.raises(addns.AddnsError) as e:
             addns.setup_precond(part, S.N, _cuda(S.rp), _cuda(S.ci), _cuda(S.v), schur=mode)
         assert e.value.code == addns.ERR_ARG and "schur mode" in str(e.value)
+    for bad in (-1, 3):
+        with pytest.raises(addns.AddnsError) as e:
+            addns.setup_precond(part, S.N, _cuda(S.rp), _cuda(S.ci), _cuda(S.v), block_sizing=bad)
+        assert e.value.code == addns.ERR_ARG and "block_sizing" in str(e.value)
     part2, pc = gpu_precond(S)
     d = torch.zeros(S.N, dtype=torch.float64, device="cuda")
     with pytest.raises(addns.AddnsError):
@@ -329,7 +333,7 @@ BATCH = [dict(n=12, nu=0.05, m=3, sz=16, seed=41), dict(n=20, nu=0.01, m=5, sz=2
          dict(n=8, nu=0.2, m=2, sz=8, seed=43), dict(n=16, nu=0.02, m=4, sz=32, stretch=1.05, seed=44)]
 
 
-def _batched():
+def _batched(**kw):
     import scipy.sparse as sp
     systems = [make_system(**c) for c in BATCH]
     parts = [addns.build_partition(S.N, S.rp, S.ci, S.v, S.m, S.sz) for S in systems]
@@ -339,20 +343,24 @@ def _batched():
     b = np.concatenate([S.b for S in systems])
     offs = np.concatenate([[0], np.cumsum([S.N for S in systems])])
     pc = addns.setup_precond(cat, big.shape[0], _cuda(big.indptr.astype(np.int32)),
-                             _cuda(big.indices.astype(np.int32)), _cuda(big.data))
+                             _cuda(big.indices.astype(np.int32)), _cuda(big.data), **kw)
     return systems, pc, b, offs
 
 
-def test_batched_apply_is_blockwise():
-    systems, pc, b, offs = _batched()
+@pytest.mark.parametrize("sizing", [1, 2])
+def test_batched_apply_is_blockwise(sizing):
+    """The concatenated systems (bands 11 to 27 wide) with one block size for
+    every interior or each its own, element by element per system."""
+    systems, pc, b, offs = _batched(block_sizing=sizing)
     y = np.random.default_rng(3).standard_normal(offs[-1])
     d_x = torch.zeros(offs[-1], dtype=torch.float64, device="cuda")
     addns.apply_precond(pc, _cuda(y), d_x)
     torch.cuda.synchronize()
     x = d_x.cpu().numpy()
     for q, S in enumerate(systems):
-        ref = oracle_precond(S).apply(y[offs[q]:offs[q + 1]])
-        assert relerr(x[offs[q]:offs[q + 1]], ref) <= 1e-9
+        ora = oracle_precond(S)
+        ref = ora.apply(y[offs[q]:offs[q + 1]])
+        assert blockwise_err(x[offs[q]:offs[q + 1]], ref, blocks_of(ora.part)) <= 1e-9
 
 
 def test_batched_gmres_equal_iterations():
@@ -434,22 +442,52 @@ def test_bench_workload_fp64_iterations_within_one():
     assert abs(r["iters"] - ref.iters) <= 1, (r["iters"], ref.iters)
 
 
+_FORM_REF = {}
+
+
+def _bench_apply_reference():
+    """The bench workload, a seeded vector and the oracle's apply of it
+    (computed once for every forced sweep form)."""
+    if not _FORM_REF:
+        S = make_system(**CASES["cavity128"])
+        ora = oracle_precond(S)
+        y = np.random.default_rng(12).standard_normal(S.N)
+        _FORM_REF.update(S=S, y=y, ref=ora.apply(y), blocks=blocks_of(ora.part))
+    return _FORM_REF
+
+
 @pytest.mark.parametrize("chunks", [1, 2, 6])
 @pytest.mark.parametrize("zero_skip", [1, 2])
-def test_every_sweep_form_matches_oracle(chunks, zero_skip):
+@pytest.mark.parametrize("sizing", [1, 2])
+def test_every_sweep_form_matches_oracle(chunks, zero_skip, sizing):
     """Each interior-sweep form the setup can choose (chunk count, with and
-    without skipping structural-zero slots), forced, against the oracle."""
+    without loading only the nonzero rows, one block size for every interior
+    or each its own: the bench workload's bands differ, 93 to 130), forced,
+    against the oracle."""
+    R = _bench_apply_reference()
+    S = R["S"]
+    part, pc = gpu_precond(S, sweep_chunks=chunks, sweep_zero_skip=zero_skip, block_sizing=sizing)
+    assert pc.info()["sweep_chunks"] == chunks
+    d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+    addns.apply_precond(pc, _cuda(R["y"]), d_x)
+    torch.cuda.synchronize()
+    e = blockwise_err(d_x.cpu().numpy(), R["ref"], R["blocks"])
+    MEASURED[f"sweep_form_{chunks}_{zero_skip}_{sizing}"] = e
+    assert e <= 1e-9
+
+
+def test_per_interior_blocks_gmres_matches_oracle():
+    """Per-interior block sizes in the FP64 solve of the bench workload: the
+    iteration count within one of the oracle's (MGS), the true residual met."""
     S = make_system(**CASES["cavity128"])
     ora = oracle_precond(S)
-    part, pc = gpu_precond(S, sweep_chunks=chunks, sweep_zero_skip=zero_skip)
-    assert pc.info()["sweep_chunks"] == chunks
-    y = np.random.default_rng(12).standard_normal(S.N)
+    ref = gmres(lambda x: ora.C @ x, ora.apply, ora.R * S.b, restart=50, tol=1e-8, maxit=3000, flexible=True,
+                ortho="mgs")
+    part, pc = gpu_precond(S, block_sizing=2)
     d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
-    addns.apply_precond(pc, _cuda(y), d_x)
-    torch.cuda.synchronize()
-    e = blockwise_err(d_x.cpu().numpy(), ora.apply(y), blocks_of(ora.part))
-    MEASURED[f"sweep_form_{chunks}_{zero_skip}"] = e
-    assert e <= 1e-9
+    r = addns.gmres_solve(pc, _cuda(S.b), d_x, restart=50, maxit=3000, tol=1e-8, flexible=True, ortho="mgs")
+    assert r["converged"] and r["true_relres"] <= 1e-8
+    assert abs(r["iters"] - ref.iters) <= 1, (r["iters"], ref.iters)
 
 
 def test_two_default_setups_solve_bit_for_bit():
