@@ -199,6 +199,10 @@ k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const Sub
 // the unblocked kernel.
 // ---------------------------------------------------------------------------
 constexpr int kPanel = 8;
+// Threads of the blocked band LU: 8 waves leave each lane the registers that
+// the lookahead needs (the panel in wave 0's registers next to the update
+// tiles of the others) without spilling.
+constexpr int kLuThreads = 512;
 
 __device__ inline double readlane_d(double x, int32_t l) {
   const int64_t bits = __double_as_longlong(x);
@@ -207,15 +211,39 @@ __device__ inline double readlane_d(double x, int32_t l) {
   return __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
 }
 
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_max_step(double v) {
+  const int64_t bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, ROW_MASK, 0xf, false);
+  return fmax(v, __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo)));
+}
+
+// Largest value over the wave of non-negative x (0 is the identity): a
+// prefix maximum within each row of 16 lanes by DPP row shifts, then the row
+// maxima combined by row broadcasts, read from lane 63.  Lanes whose DPP
+// source does not exist receive 0.  The maximum is exact, so the order of
+// the comparisons does not matter.
+__device__ inline double wave_max_nonneg(double x) {
+  x = dpp_max_step<0x111, 0xf>(x);  // row_shr:1
+  x = dpp_max_step<0x112, 0xf>(x);  // row_shr:2
+  x = dpp_max_step<0x114, 0xf>(x);  // row_shr:4
+  x = dpp_max_step<0x118, 0xf>(x);  // row_shr:8
+  x = dpp_max_step<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x = dpp_max_step<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return readlane_d(x, 63);
+}
+
 // The same panel factorisation with the panel in registers: lane l holds
 // rows l + 64k (k < NS) of the nb columns, the pivot row and row c are
 // broadcast with readlane, and the pivot search uses one max reduction and
 // ballots.  Each entry sees the same operations in the same order as in the
 // LDS form, so the results are identical.
 template <int NS>
-__device__ void panel_regs(double* s_pan, int32_t prmax, int32_t prows, int32_t j0, int32_t nb, int32_t n,
-                           int32_t KL, int32_t KU, int lane, double tau, const double* cn, int32_t* ipiv,
-                           int32_t* s_pv, int32_t* s_ok, int32_t* s_juc, int32_t& s_ju, int32_t& s_info) {
+__device__ __attribute__((always_inline)) inline void panel_regs(
+    double* s_pan, int32_t prmax, int32_t prows, int32_t j0, int32_t nb, int32_t n, int32_t KL, int32_t KU, int lane,
+    double tau, const double* cn, int32_t* ipiv, int32_t* s_pv, int32_t* s_ok, int32_t* s_juc, int32_t& s_ju,
+    int32_t& s_info) {
   double a[NS][kPanel];
 #pragma unroll
   for (int k = 0; k < NS; ++k)
@@ -240,7 +268,7 @@ __device__ void panel_regs(double* s_pan, int32_t prmax, int32_t prows, int32_t 
       const int32_t r = lane + 64 * k;
       if (r >= c && r <= c + km) best = fmax(best, fabs(a[k][c]));
     }
-    for (int off = 32; off >= 1; off >>= 1) best = fmax(best, __shfl_xor(best, off));
+    best = wave_max_nonneg(best);
     const double thr = (1.0 - kPivotTie) * best;
     int32_t prow = c;
     bool found = false;
@@ -324,15 +352,74 @@ __device__ void panel_regs(double* s_pan, int32_t prmax, int32_t prows, int32_t 
   }
 }
 
+// Rank-nb update of rows j0+nb .. rmax of the trailing columns tcol in
+// [t_lo, t_hi) (tcol counts from column j0+nb): lane l keeps the multipliers
+// of rows rc0 + l + 64k (k < 3) in registers, wave w of W takes columns
+// t_lo + w, t_lo + w + W, ... four at a time; U12 of a column is a broadcast
+// LDS read (its skipped steps hold zero).
+__device__ __attribute__((always_inline)) inline void lu_rank_update(
+    double* ab, int32_t ldab, int32_t KV, const double* s_pan, const double* s_u12, int32_t prmax, int32_t ntmax,
+    int32_t j0, int32_t nb, int32_t nrows, int32_t t_lo, int32_t t_hi, int w, int W, int lane) {
+  auto at = [&](int32_t r, int32_t c) -> double& { return ab[(int64_t)c * ldab + KV + r - c]; };
+  for (int32_t rc0 = 0; rc0 < nrows && t_lo < t_hi; rc0 += 3 * 64) {
+    double L[3][kPanel];
+    int32_t rr[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      rr[k] = rc0 + lane + 64 * k;
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) L[k][c] = (rr[k] < nrows && c < nb) ? s_pan[c * prmax + nb + rr[k]] : 0.0;
+    }
+    for (int32_t t0 = t_lo + w; t0 < t_hi; t0 += 4 * W) {
+      double a[4][3];
+#pragma unroll
+      for (int bq = 0; bq < 4; ++bq) {
+        const int32_t tcol = t0 + bq * W;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          a[bq][k] = (tcol < t_hi && rr[k] < nrows) ? at(j0 + nb + rr[k], j0 + nb + tcol) : 0.0;
+      }
+#pragma unroll
+      for (int bq = 0; bq < 4; ++bq) {
+        const int32_t tcol = t0 + bq * W;
+        if (tcol >= t_hi) continue;
+        double u[kPanel];
+#pragma unroll
+        for (int c = 0; c < kPanel; ++c) u[c] = c < nb ? s_u12[c * ntmax + tcol] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          if (rr[k] >= nrows) continue;
+          double x = a[bq][k];
+#pragma unroll
+          for (int c = 0; c < kPanel; ++c)
+            if (c < nb) x -= L[k][c] * u[c];
+          at(j0 + nb + rr[k], j0 + nb + tcol) = x;
+        }
+      }
+    }
+  }
+}
+
+// Lookahead: panel k+1 is factored by wave 0 while the other waves apply
+// panel k's rank-nb update to the columns after panel k+1.  Per panel k:
+//   (1) all threads: interchanges and unit lower solve of every trailing
+//       column (U12 of the panel);
+//   (2) all waves: the rank-nb update of the next panel's columns;
+//   (3) the previous panel's multipliers back to band order and to memory,
+//       then panel k+1 loaded (buffers alternate between panels);
+//   (4) wave 0 factors panel k+1; waves 1.. update the remaining columns.
+// Every entry receives the same operations in the same order as without
+// lookahead, so pivots and factors are unchanged bit for bit.
 template <int NS>
-__global__ void __launch_bounds__(kSetupThreads)
+__global__ void __launch_bounds__(kLuThreads)
 k_band_lu_blocked(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const SubInfo* __restrict__ subs,
                   int32_t* __restrict__ info, const double* __restrict__ colnorm_all, double tau, int32_t prmax,
                   int32_t ntmax) {
   extern __shared__ double s_dyn[];
-  double* s_pan = s_dyn;                         // column c of the panel at c * prmax (rows j0 ..)
-  double* s_u12 = s_dyn + kPanel * prmax;        // U12 row c at c * ntmax (trailing column t)
-  __shared__ int32_t s_pv[kPanel], s_juc[kPanel], s_ok[kPanel];
+  // buffer b: panel column c at s_pan[b] + c * prmax, U12 row c at s_u12[b] + c * ntmax
+  double* const s_pan0 = s_dyn;
+  double* const s_u120 = s_dyn + 2 * kPanel * prmax;
+  __shared__ int32_t s_pv[2][kPanel], s_juc[2][kPanel], s_ok[2][kPanel];
   __shared__ int32_t s_ju, s_info;
   const int sub = blockIdx.x;
   const SubInfo q = subs[sub];
@@ -340,38 +427,72 @@ k_band_lu_blocked(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, c
   double* ab = ab_all + q.band_off;
   int32_t* ipiv = ipiv_all + q.vec_off;
   const double* cn = colnorm_all + q.vec_off;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = (int)(blockDim.x >> 6);
   // entry (r, c) of the block lives at ab[c * ldab + KV + r - c] for -KV <= r - c <= KL
   auto at = [&](int32_t r, int32_t c) -> double& { return ab[(int64_t)c * ldab + KV + r - c]; };
+  auto pan = [&](int b) { return s_pan0 + b * kPanel * prmax; };
+  auto u12 = [&](int b) { return s_u120 + b * kPanel * ntmax; };
+  auto load_panel = [&](int b, int32_t j0) {
+    const int32_t nb = min(kPanel, n - j0), prows = min(KL + nb, n - j0);
+    double* P = pan(b);
+    for (int32_t e = tid; e < nb * prows; e += blockDim.x) {
+      const int32_t c = e / prows, rr = e % prows, d = rr - c;
+      P[c * prmax + rr] = (d <= KL && d >= -KV) ? at(j0 + rr, j0 + c) : 0.0;
+    }
+  };
+  // multipliers of panel j0 (buffer b) back to band storage order (the later
+  // interchanges of the same panel undone), then the panel to memory
+  auto store_panel = [&](int b, int32_t j0) {
+    const int32_t nb = min(kPanel, n - j0), prows = min(KL + nb, n - j0);
+    double* P = pan(b);
+    if (tid < nb) {
+      double* pc = P + tid * prmax;
+      for (int32_t c2 = nb - 1; c2 > tid; --c2) {
+        const int32_t p2 = s_ok[b][c2] ? s_pv[b][c2] : 0;
+        if (p2 != 0) {
+          const double x = pc[c2];
+          pc[c2] = pc[c2 + p2];
+          pc[c2 + p2] = x;
+        }
+      }
+    }
+    __syncthreads();
+    for (int32_t e = tid; e < nb * prows; e += blockDim.x) {
+      const int32_t c = e / prows, rr = e % prows, d = rr - c;
+      if (d <= KL && d >= -KV) at(j0 + rr, j0 + c) = P[c * prmax + rr];
+    }
+  };
   if (tid == 0) {
     s_ju = 0;
     s_info = 0;
   }
-  for (int32_t j0 = 0; j0 < n; j0 += kPanel) {
+  // panel 0
+  load_panel(0, 0);
+  __syncthreads();
+  if (wave == 0)
+    panel_regs<NS>(pan(0), prmax, min(KL + min(kPanel, n), n), 0, min(kPanel, n), n, KL, KU, lane, tau, cn, ipiv,
+                   s_pv[0], s_ok[0], s_juc[0], s_ju, s_info);
+  __syncthreads();
+  for (int32_t k = 0;; ++k) {
+    const int b = k & 1;
+    const int32_t j0 = k * kPanel;
+    if (j0 >= n) break;
     const int32_t nb = min(kPanel, n - j0);
-    const int32_t prows = min(KL + nb, n - j0);
-    for (int32_t e = tid; e < nb * prows; e += blockDim.x) {
-      const int32_t c = e / prows, rr = e % prows, d = j0 + rr - (j0 + c);
-      s_pan[c * prmax + rr] = (d <= KL && d >= -KV) ? at(j0 + rr, j0 + c) : 0.0;
-    }
-    __syncthreads();
-    // ---- panel factorisation, by wave 0 alone
-    if (wave == 0)
-      panel_regs<NS>(s_pan, prmax, prows, j0, nb, n, KL, KU, lane, tau, cn, ipiv, s_pv, s_ok, s_juc, s_ju, s_info);
-    __syncthreads();
-    // ---- trailing columns j0+nb .. ju: interchanges, then the panel rows
-    // (unit lower triangular solve), in registers, one column per thread
     const int32_t ju = s_ju, nt = ju - (j0 + nb) + 1;
+    const double* P = pan(b);
+    double* U = u12(b);
+    // ---- (1) trailing columns j0+nb .. ju: interchanges, then the panel rows
+    // (unit lower triangular solve), in registers, one column per thread
     for (int32_t tcol = tid; tcol < nt; tcol += blockDim.x) {
       const int32_t jc = j0 + nb + tcol;
       const double drop_u = tau * cn[jc];
       double v[kPanel];
 #pragma unroll
-      for (int c = 0; c < kPanel; ++c) v[c] = (c < nb && jc <= s_juc[c]) ? at(j0 + c, jc) : 0.0;
+      for (int c = 0; c < kPanel; ++c) v[c] = (c < nb && jc <= s_juc[b][c]) ? at(j0 + c, jc) : 0.0;
 #pragma unroll
       for (int c = 0; c < kPanel; ++c) {
-        if (c >= nb || !s_ok[c] || jc > s_juc[c]) continue;
-        const int32_t p = s_pv[c];
+        if (c >= nb || !s_ok[b][c] || jc > s_juc[b][c]) continue;
+        const int32_t p = s_pv[b][c];
         if (p == 0) continue;
         if (c + p < nb) {
           // both rows inside the panel
@@ -392,84 +513,55 @@ k_band_lu_blocked(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, c
 #pragma unroll
       for (int c = 0; c < kPanel; ++c) {
         double u = 0.0;
-        if (c < nb && s_ok[c] && jc <= s_juc[c]) {
+        if (c < nb && s_ok[b][c] && jc <= s_juc[b][c]) {
           u = v[c];
           if (fabs(u) < drop_u) u = 0.0;
           v[c] = u;
 #pragma unroll
           for (int i = 1; i < kPanel; ++i)
-            if (c + i < nb) v[c + i] -= s_pan[c * prmax + c + i] * u;
+            if (c + i < nb) v[c + i] -= P[c * prmax + c + i] * u;
         }
-        if (c < nb) s_u12[c * ntmax + tcol] = u;
+        if (c < nb) U[c * ntmax + tcol] = u;
       }
 #pragma unroll
       for (int c = 0; c < kPanel; ++c)
-        if (c < nb && jc <= s_juc[c]) at(j0 + c, jc) = v[c];
+        if (c < nb && jc <= s_juc[b][c]) at(j0 + c, jc) = v[c];
     }
     __syncthreads();
-    // ---- rank-nb update of rows j0+nb .. rmax of the trailing columns: lane
-    // l keeps the multipliers of rows rc0 + l + 64k (k < 3) in registers, wave
-    // w takes columns w, w+16, ... four at a time; U12 of a column is a
-    // broadcast LDS read (its skipped steps hold zero).
+    // ---- (2) rank-nb update of the next panel's columns
     const int32_t rmax = min(j0 + nb - 1 + KL, n - 1), nrows = rmax - (j0 + nb) + 1;
-    const int nwaves = (int)(blockDim.x >> 6);
-    for (int32_t rc0 = 0; rc0 < nrows && nt > 0; rc0 += 3 * 64) {
-      double L[3][kPanel];
-      int32_t rr[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        rr[k] = rc0 + lane + 64 * k;
-#pragma unroll
-        for (int c = 0; c < kPanel; ++c)
-          L[k][c] = (rr[k] < nrows && c < nb) ? s_pan[c * prmax + nb + rr[k]] : 0.0;
-      }
-      for (int32_t t0 = wave; t0 < nt; t0 += 4 * nwaves) {
-        double a[4][3];
-#pragma unroll
-        for (int bq = 0; bq < 4; ++bq) {
-          const int32_t tcol = t0 + bq * nwaves;
-#pragma unroll
-          for (int k = 0; k < 3; ++k)
-            a[bq][k] = (tcol < nt && rr[k] < nrows) ? at(j0 + nb + rr[k], j0 + nb + tcol) : 0.0;
-        }
-#pragma unroll
-        for (int bq = 0; bq < 4; ++bq) {
-          const int32_t tcol = t0 + bq * nwaves;
-          if (tcol >= nt) continue;
-          double u[kPanel];
-#pragma unroll
-          for (int c = 0; c < kPanel; ++c) u[c] = c < nb ? s_u12[c * ntmax + tcol] : 0.0;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            if (rr[k] >= nrows) continue;
-            double x = a[bq][k];
-#pragma unroll
-            for (int c = 0; c < kPanel; ++c)
-              if (c < nb) x -= L[k][c] * u[c];
-            at(j0 + nb + rr[k], j0 + nb + tcol) = x;
-          }
-        }
-      }
+    const int32_t jn = j0 + nb;
+    const bool next = nb == kPanel && jn < n;
+    const int32_t nlook = next ? min(min(kPanel, n - jn), max(nt, 0)) : 0;
+    if (nlook > 0) {
+      lu_rank_update(ab, ldab, KV, P, U, prmax, ntmax, j0, nb, nrows, 0, nlook, wave, nwaves, lane);
+      __syncthreads();
+    }
+    // ---- (3) the previous panel to memory, the next panel in
+    if (k > 0) {
+      store_panel(1 - b, j0 - kPanel);
+      __syncthreads();
+    }
+    if (next) {
+      load_panel(1 - b, jn);
+      __syncthreads();
+    }
+    // ---- (4) wave 0: factor the next panel; the other waves: the rest of
+    // this panel's update
+    if (wave == 0) {
+      if (next)
+        panel_regs<NS>(pan(1 - b), prmax, min(KL + min(kPanel, n - jn), n - jn), jn, min(kPanel, n - jn), n, KL, KU,
+                       lane, tau, cn, ipiv, s_pv[1 - b], s_ok[1 - b], s_juc[1 - b], s_ju, s_info);
+    } else {
+      lu_rank_update(ab, ldab, KV, P, U, prmax, ntmax, j0, nb, nrows, nlook, max(nt, 0), wave - 1, nwaves - 1, lane);
     }
     __syncthreads();
-    // ---- multipliers back to band storage order, then the panel to memory
-    if (tid < nb) {
-      double* pc = s_pan + tid * prmax;
-      for (int c2 = nb - 1; c2 > tid; --c2) {
-        const int32_t p2 = s_ok[c2] ? s_pv[c2] : 0;
-        if (p2 != 0) {
-          const double x = pc[c2];
-          pc[c2] = pc[c2 + p2];
-          pc[c2 + p2] = x;
-        }
-      }
+    if (!next) {
+      // the last panel: no panel after it to overlap with
+      store_panel(b, j0);
+      __syncthreads();
+      break;
     }
-    __syncthreads();
-    for (int32_t e = tid; e < nb * prows; e += blockDim.x) {
-      const int32_t c = e / prows, rr = e % prows, d = rr - c;
-      if (d <= KL && d >= -KV) at(j0 + rr, j0 + c) = s_pan[c * prmax + rr];
-    }
-    __syncthreads();
   }
   if (tid == 0) info[sub] = s_info;
 }
@@ -1049,14 +1141,14 @@ void launch_band_nnz(const double* ab, const SubInfo* subs, int32_t m, int64_t* 
 template <int NS>
 void run_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, const double* colnorm,
                  double tau, int32_t prmax, int32_t ntmax, hipStream_t s) {
-  const size_t smem = sizeof(double) * (size_t)kPanel * (prmax + ntmax);
+  const size_t smem = sizeof(double) * (size_t)2 * kPanel * (prmax + ntmax);
   static size_t raised = 64 * 1024;
   if (smem > raised) {
     ADDNS_HIP(hipFuncSetAttribute((const void*)k_band_lu_blocked<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)smem));
     raised = smem;
   }
-  k_band_lu_blocked<NS><<<m, kSetupThreads, smem, s>>>(ab, ipiv, subs, info, colnorm, tau, prmax, ntmax);
+  k_band_lu_blocked<NS><<<m, kLuThreads, smem, s>>>(ab, ipiv, subs, info, colnorm, tau, prmax, ntmax);
 }
 void launch_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, const double* colnorm,
                     double tau, int32_t kl_max, int32_t kv_max, hipStream_t s) {
