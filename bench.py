@@ -347,6 +347,9 @@ def main():
                     help="only the dominant kernel (interior solve) x reps, plus a 256 MiB device "
                          "copy of known size to calibrate memory counters")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--profile-overlap", type=int, default=0,
+                    help="with --kernel-profile: also run reps applies with overlapped aggregates of this "
+                         "width (OMSCN), for the share of the chain kernels in the apply")
     ap.add_argument("--block-sizing", type=int, default=0, choices=[0, 1, 2],
                     help="sweep block sizes: 0 = the library's rule, 1 = one for all, 2 = per interior")
     ap.add_argument("--workload", default="cavity128",
@@ -444,6 +447,17 @@ def main():
         d_z1 = torch.empty_like(d_y1)
         for _ in range(args.reps):
             addns.interior_solve(pc, d_y1, d_z1)
+        if args.profile_overlap > 0:
+            # the chain in segments (the default), then as one chain
+            d_y = torch.randn(N, dtype=torch.float64, device=dev)
+            d_o = torch.empty_like(d_y)
+            for seg in (0, 1 << 30):
+                po = addns.setup_precond(part, N, d_rp, d_ci, d_v, interior_prec=iprec, schur_prec=sprec,
+                                         block_mult=args.block_mult, overlap=args.profile_overlap,
+                                         overlap_segment=seg)
+                for _ in range(args.reps):
+                    addns.apply_precond(po, d_y, d_o)
+                del po
         src = torch.ones(256 * 2 ** 20 // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)

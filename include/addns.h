@@ -237,6 +237,17 @@ typedef struct {
                              plan and the device, no timing.  The two regroup
                              the same factors into different blocks, so their
                              solves agree to rounding only; else ADDNS_ERR_ARG */
+  int32_t overlap_segment; /* overlap > 0: the forward substitution over the
+                             aggregates, x_i = u_i - M_i x_{i-1}, runs in
+                             segments of L aggregates: each segment from a zero
+                             start side by side, a chain over the segments'
+                             last aggregates with the responses
+                             Q_i = -M_i Q_{i-1} (Q = M at a segment's first
+                             aggregate, formed at setup), and x_i = z_i -
+                             Q_i x_(previous segment's last) for the rest.  The
+                             same Shat^-1, to rounding.  0 = L = ceil(sqrt(k))
+                             (the default); L >= k = one chain; < 0:
+                             ADDNS_ERR_ARG */
 } addns_precond_opts;
 
 /* ------------------------------------------------------------------------

@@ -45,7 +45,7 @@ class PrecondOpts(C.Structure):
                 ("row_scale", C.c_int32), ("learned_model", C.POINTER(C.c_float)),
                 ("block_mult", C.c_int32), ("learned_bf16", C.c_int32), ("overlap", C.c_int32),
                 ("ilu_tol", C.c_double), ("sweep_chunks", C.c_int32), ("coarse", C.c_int32),
-                ("sweep_zero_skip", C.c_int32), ("block_sizing", C.c_int32)]
+                ("sweep_zero_skip", C.c_int32), ("block_sizing", C.c_int32), ("overlap_segment", C.c_int32)]
 
 
 class GmresOpts(C.Structure):
@@ -281,10 +281,11 @@ class Precond:
 def setup_precond(partition: Partition, N, d_rowptr, d_colidx, d_vals, schur=SCHUR_MSCN,
                   interior_prec=F64, schur_prec=F64, row_scale=1, learned_model=None,
                   block_mult=1, learned_bf16=True, overlap=0, ilu_tol=0.0, sweep_chunks=0,
-                  coarse=0, sweep_zero_skip=0, block_sizing=0, stream=None) -> Precond:
+                  coarse=0, sweep_zero_skip=0, block_sizing=0, overlap_segment=0, stream=None) -> Precond:
     opts = PrecondOpts(int(schur), int(interior_prec), int(schur_prec), int(row_scale), None,
                        int(block_mult), int(bool(learned_bf16)), int(overlap), float(ilu_tol),
-                       int(sweep_chunks), int(coarse), int(sweep_zero_skip), int(block_sizing))
+                       int(sweep_chunks), int(coarse), int(sweep_zero_skip), int(block_sizing),
+                       int(overlap_segment))
     if learned_model is not None:
         lm = np.ascontiguousarray(learned_model, dtype=np.float32)
         opts.learned_model = lm.ctypes.data_as(C.POINTER(C.c_float))

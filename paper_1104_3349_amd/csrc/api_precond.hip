@@ -130,7 +130,9 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
     launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), m, info.as<int32_t>(),
                    colnorm.as<double>(), o.ilu_tol, kl_max, kv_max, s);
     nnz.alloc(sizeof(int64_t) * m);
-    launch_band_nnz(ab.as<double>(), pc->subs.as<SubInfo>(), m, nnz.as<int64_t>(), s);
+    int32_t n_max = 0;
+    for (const SubInfo& q : pl.subs) n_max = std::max(n_max, q.n);
+    launch_band_nnz(ab.as<double>(), pc->subs.as<SubInfo>(), m, n_max, nnz.as<int64_t>(), s);
     std::vector<int32_t> h_info(m + 4);
     std::vector<int64_t> h_nnz(m);
     ADDNS_HIP(hipMemcpyAsync(h_info.data(), info.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
@@ -273,6 +275,15 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
                        l_off.as<int64_t>(), pc->ovl_moff.as<int64_t>(), pl.ovl_width, work.as<double>(),
                        L.as<double>(), pc->ovl_m.p, mdbl, s);
       pc->overlap_chain = k > 1 ? pl.ovl_width : 0;
+      // the chain in segments: responses of each segment's aggregates to the
+      // previous segment's last one
+      pc->ovl_seg = overlap_segment_length(k, o.overlap_segment);
+      if (pc->overlap_chain && (k + pc->ovl_seg - 1) / pc->ovl_seg > 1) {
+        pc->ovl_q.alloc((mdbl ? 8 : 4) * std::max<int64_t>(pl.m_off[k], 1));
+        launch_overlap_q(pc, s);
+      } else {
+        pc->ovl_q.reset();
+      }
       ADDNS_HIP(hipStreamSynchronize(s));
     }
     int32_t h2[2];
@@ -297,7 +308,11 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
   fbytes += pl.lmat_total * fb + pl.lperm_total * 4;
   fbytes += 2 * pl.u_total * fb;
   const int64_t a_total = k > 0 ? pl.sinv_off[k] : 0;
-  const int64_t m_bytes = pc->overlap_chain ? pl.m_off[k] * (sprec == P64 ? 8 : 4) : 0;
+  // chain matrices read once, and the responses once more when the chain
+  // runs in segments
+  const int64_t m_bytes = pc->overlap_chain ? pl.m_off[k] * (sprec == P64 ? 8 : 4) *
+                                                  ((k + pc->ovl_seg - 1) / pc->ovl_seg > 1 ? 2 : 1)
+                                            : 0;
   fbytes += a_total * prec_bytes(sprec) + m_bytes;
   pc->factor_bytes = fbytes;
   // algorithmic bytes of one apply: band factors L (KL) and U (KL+KU+1) per
@@ -571,8 +586,9 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
   return guarded("addns_setup_precond", [&]() -> int {
     if (!p || !out || !d_rowptr || !d_colidx || !d_vals) throw ArgError("null argument");
     if (N != p->d.N) throw ArgError("N does not match the partition");
-    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1, 0, 0, 0.0, 0, 0, 0, 0};
+    addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1, 0, 0, 0.0, 0, 0, 0, 0, 0};
     if (opts) o = *opts;
+    if (o.overlap_segment < 0) throw ArgError("overlap_segment must be >= 0");
     if (o.block_sizing < 0 || o.block_sizing > 2) throw ArgError("block_sizing must be 0, 1 or 2");
     if (o.block_sizing == 0) {
       // With at most one interior per compute unit the sweep takes as long as

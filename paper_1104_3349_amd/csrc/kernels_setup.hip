@@ -580,26 +580,31 @@ __global__ void k_band_colnorm(const double* __restrict__ ab_all, const SubInfo*
 }
 
 // Stored entries of the factors of every block (multipliers below the unit
-// diagonal and U, real rows and columns only): counts[sub].
-__global__ void __launch_bounds__(kSetupThreads)
-k_band_nnz(const double* __restrict__ ab_all, const SubInfo* __restrict__ subs, int64_t* __restrict__ counts) {
-  const SubInfo q = subs[blockIdx.x];
+// diagonal and U, real rows and columns only): counts[sub] += the count of
+// this workgroup's kNnzCols columns (grid: column chunks x subdomains;
+// counts zeroed first; integer sums, so the order does not matter).
+constexpr int kNnzCols = 64;
+__global__ void __launch_bounds__(256)
+k_band_nnz(const double* __restrict__ ab_all, const SubInfo* __restrict__ subs, unsigned long long* __restrict__ counts) {
+  const SubInfo q = subs[blockIdx.y];
   const int32_t n = q.n, ldab = q.ldab, KV = q.kl + q.ku;
-  const double* ab = ab_all + q.band_off;
-  int64_t cnt = 0;
-  for (int64_t t = threadIdx.x; t < (int64_t)n * ldab; t += blockDim.x) {
-    const int32_t c = (int32_t)(t / ldab), r = (int32_t)(t % ldab);
+  const int32_t c0 = blockIdx.x * kNnzCols, c1 = min(n, c0 + kNnzCols);
+  if (c0 >= c1) return;
+  const double* ab = ab_all + q.band_off + (int64_t)c0 * ldab;
+  unsigned long long cnt = 0;
+  for (int32_t t = threadIdx.x; t < (c1 - c0) * ldab; t += blockDim.x) {
+    const int32_t c = c0 + t / ldab, r = t % ldab;
     const int32_t row = c + r - KV;  // U rows r <= KV, multiplier rows r > KV
     if (row >= 0 && row < n && (r <= KV || row <= c + q.kl) && ab[t] != 0.0) ++cnt;
   }
-  __shared__ int64_t s_cnt[kSetupThreads / 64];
+  __shared__ unsigned long long s_cnt[256 / 64];
   for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
   if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
   __syncthreads();
   if (threadIdx.x == 0) {
-    int64_t s = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += s_cnt[w];
-    counts[blockIdx.x] = s;
+    unsigned long long v = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += s_cnt[w];
+    atomicAdd(counts + blockIdx.y, v);
   }
 }
 
@@ -1135,8 +1140,13 @@ void launch_band_colnorm(const double* ab, const SubInfo* subs, int32_t m, int32
                          hipStream_t s) {
   if (m > 0 && npad_max > 0) k_band_colnorm<<<dim3((npad_max + 255) / 256, m), 256, 0, s>>>(ab, subs, colnorm);
 }
-void launch_band_nnz(const double* ab, const SubInfo* subs, int32_t m, int64_t* counts, hipStream_t s) {
-  if (m > 0) k_band_nnz<<<m, kSetupThreads, 0, s>>>(ab, subs, counts);
+void launch_band_nnz(const double* ab, const SubInfo* subs, int32_t m, int32_t n_max, int64_t* counts,
+                     hipStream_t s) {
+  if (m == 0) return;
+  ADDNS_HIP(hipMemsetAsync(counts, 0, sizeof(int64_t) * m, s));
+  if (n_max > 0)
+    k_band_nnz<<<dim3((n_max + kNnzCols - 1) / kNnzCols, m), 256, 0, s>>>(ab, subs,
+                                                                         reinterpret_cast<unsigned long long*>(counts));
 }
 template <int NS>
 void run_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, const double* colnorm,

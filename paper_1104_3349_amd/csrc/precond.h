@@ -230,6 +230,8 @@ struct addns_precond {
   // storage, else FP32) applied by the block forward substitution over Shat
   addns::DevBuf ovl_m, ovl_moff;
   int overlap_chain = 0;                              // 0: none, else the chain matrices' row width (64, 80, 128)
+  addns::DevBuf ovl_q;                                // segment responses Q_i (same layout as M_i)
+  int32_t ovl_seg = 1;                                // chain segment length L
   // scratch
   addns::DevBuf ypad, zpad, z1, x2tmp;                // padded interior work vectors
   addns::DevBuf vperm_in, vperm_out;                  // permuted apply in/out
@@ -292,7 +294,8 @@ void launch_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, i
                     double tau, int32_t kl_max, int32_t kv_max, hipStream_t s);
 void launch_band_colnorm(const double* ab, const SubInfo* subs, int32_t m, int32_t npad_max, double* colnorm,
                          hipStream_t s);
-void launch_band_nnz(const double* ab, const SubInfo* subs, int32_t m, int64_t* counts, hipStream_t s);
+void launch_band_nnz(const double* ab, const SubInfo* subs, int32_t m, int32_t n_max, int64_t* counts,
+                     hipStream_t s);
 void launch_convert_lower(const double* ab, const int32_t* ipiv, const SubInfo* subs, const LBlk* lb, int32_t nblk,
                           double* work, int32_t* lperm, void* lmat, int prec, hipStream_t s);
 void launch_convert_upper(const double* ab, const SubInfo* subs, const UBlk* ub, int32_t nblk, double* work,
@@ -345,6 +348,8 @@ void launch_overlap_m(int32_t k, const int32_t* agg_s, const int32_t* agg_w, con
                       const int64_t* l_off, const int64_t* m_off, int32_t width, const double* winv, const double* L,
                       void* M, int m_double, hipStream_t s);
 void launch_overlap_chain(const addns_precond* pc, double* x2, hipStream_t s);
+void launch_overlap_q(const addns_precond* pc, hipStream_t s);
+int32_t overlap_segment_length(int32_t k, int32_t requested);
 int overlap_chain_width(int32_t smax);
 void launch_permute(const int32_t* perm, const double* in, double* out, int32_t n, int inverse,
                     const double* scale, hipStream_t s);

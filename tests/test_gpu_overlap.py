@@ -9,7 +9,7 @@ import pytest
 torch = pytest.importorskip("torch")
 from oracle.krylov import gmres  # noqa: E402
 from paper_1104_3349_amd import addns  # noqa: E402
-from tests.gpu_systems import gpu_precond, make_system, oracle_precond, relerr  # noqa: E402
+from tests.gpu_systems import blocks_of, blockwise_err, gpu_precond, make_system, oracle_precond, relerr  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -61,7 +61,7 @@ def test_overlap_apply(case, schur):
     addns.apply_precond(pc, _cuda(y), d_x)
     torch.cuda.synchronize()
     x1 = d_x.cpu().numpy()
-    assert relerr(x1, ora.apply(y)) <= 1e-9
+    assert blockwise_err(x1, ora.apply(y), blocks_of(ora.part)) <= 1e-9
     d_x2 = torch.zeros_like(d_x)
     addns.apply_precond(pc, _cuda(y), d_x2)
     torch.cuda.synchronize()
@@ -77,7 +77,7 @@ def test_overlap_small_widths(w):
     d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
     addns.apply_precond(pc, _cuda(y), d_x)
     torch.cuda.synchronize()
-    assert relerr(d_x.cpu().numpy(), ora.apply(y)) <= 1e-9
+    assert blockwise_err(d_x.cpu().numpy(), ora.apply(y), blocks_of(ora.part)) <= 1e-9
 
 
 def test_overlap_mixed_precision(case):
@@ -89,7 +89,7 @@ def test_overlap_mixed_precision(case):
     d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
     addns.apply_precond(pc, _cuda(y), d_x)
     torch.cuda.synchronize()
-    assert relerr(d_x.cpu().numpy(), ora.apply(y)) <= 1e-4
+    assert blockwise_err(d_x.cpu().numpy(), ora.apply(y), blocks_of(ora.part)) <= 1e-4
 
 
 def test_overlap_gmres_equal_iterations(case):
@@ -102,7 +102,32 @@ def test_overlap_gmres_equal_iterations(case):
     r = addns.gmres_solve(pc, _cuda(S.b), d_x, restart=5, maxit=k, tol=1e-300, flexible=True, history=True)
     assert r["iters"] == k
     assert relerr(d_x.cpu().numpy(), ref.x) <= 1e-10
+    assert blockwise_err(d_x.cpu().numpy(), ref.x, blocks_of(ora.part)) <= 1e-8
     np.testing.assert_allclose(r["history"], ref.est_history, rtol=1e-8, atol=0)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 7])
+def test_overlap_segmented_chain(L):
+    """The forward substitution over the aggregates in segments of L (each
+    from a zero start, the segment ends chained through the responses Q_i,
+    then the corrections) against the oracle's sparse solve of Shat, element
+    by element; L = 1 (every aggregate its own segment: the end chain is the
+    whole chain with Q_i = M_i) equals one chain bit for bit."""
+    S = make_system(**CASES["cavity128"])
+    ora = oracle_precond(S, addns.SCHUR_MSCN, overlap=_w(S))
+    y = np.random.default_rng(17).standard_normal(S.N)
+    part, pc = gpu_precond(S, addns.SCHUR_MSCN, overlap=_w(S), overlap_segment=L)
+    d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+    addns.apply_precond(pc, _cuda(y), d_x)
+    torch.cuda.synchronize()
+    x = d_x.cpu().numpy()
+    assert blockwise_err(x, ora.apply(y), blocks_of(ora.part)) <= 1e-9
+    if L == 1:
+        _, one = gpu_precond(S, addns.SCHUR_MSCN, part=part, overlap=_w(S), overlap_segment=100000)
+        d_1 = torch.zeros_like(d_x)
+        addns.apply_precond(one, _cuda(y), d_1)
+        torch.cuda.synchronize()
+        assert np.array_equal(d_1.cpu().numpy(), x)
 
 
 def test_overlap_iterations_match_oracle():
@@ -144,15 +169,16 @@ def test_overlap_batched_is_blockwise():
     torch.cuda.synchronize()
     x = d_x.cpu().numpy()
     for q, S in enumerate(systems):
-        ref = oracle_precond(S, addns.SCHUR_MSCN, overlap=20).apply(y[offs[q]:offs[q + 1]])
-        assert relerr(x[offs[q]:offs[q + 1]], ref) <= 1e-9
+        ora = oracle_precond(S, addns.SCHUR_MSCN, overlap=20)
+        ref = ora.apply(y[offs[q]:offs[q + 1]])
+        assert blockwise_err(x[offs[q]:offs[q + 1]], ref, blocks_of(ora.part)) <= 1e-9
 
 
 def test_overlap_argument_errors():
     S = make_system(**CASES["cavity16"])
     part = addns.build_partition(S.N, S.rp, S.ci, S.v, S.m, S.sz)
     args = (part, S.N, _cuda(S.rp), _cuda(S.ci), _cuda(S.v))
-    for kw in (dict(overlap=-1), dict(overlap=4, schur=addns.SCHUR_EXACT_BJ),
+    for kw in (dict(overlap=-1), dict(overlap=4, overlap_segment=-1), dict(overlap=4, schur=addns.SCHUR_EXACT_BJ),
                dict(overlap=4, schur=addns.SCHUR_MSCN_LITERAL)):
         with pytest.raises(addns.AddnsError) as e:
             addns.setup_precond(*args, **kw)
@@ -170,4 +196,4 @@ def test_overlap_argument_errors():
     d_x = torch.zeros(one.N, dtype=torch.float64, device="cuda")
     addns.apply_precond(pc1, _cuda(y), d_x)
     torch.cuda.synchronize()
-    assert relerr(d_x.cpu().numpy(), ora.apply(y)) <= 1e-9
+    assert blockwise_err(d_x.cpu().numpy(), ora.apply(y), blocks_of(ora.part)) <= 1e-9
