@@ -122,6 +122,7 @@ class BandILU:
         n = A.shape[0]
         self.n = n
         self.tau = float(tau)
+        self.compensated = []
         if n == 0:
             return
         coo = A.tocoo()
@@ -135,7 +136,17 @@ class BandILU:
             mag = np.abs(W[j:hi, j])
             p = j + int(np.argmax(mag >= (1.0 - self.PIVOT_TIE) * mag.max()))
             if W[p, j] == 0.0:
-                raise SingularBlock(f"zero pivot at column {j}")
+                # every candidate of column j is zero (the dropped fill took
+                # what would have been the pivot): with dropping, the pivot
+                # becomes tau ||A(:, j)||, a diagonal compensation of the
+                # size of the largest entry dropped in that column (reading
+                # of the incomplete factorisation); the exact LU refuses
+                if tau > 0.0 and cn[j] > 0.0:
+                    p = j
+                    W[j, j] = tau * cn[j]
+                    self.compensated.append(j)
+                else:
+                    raise SingularBlock(f"zero pivot at column {j}")
             if p != j:
                 W[[j, p], :] = W[[p, j], :]
                 perm[[j, p]] = perm[[p, j]]

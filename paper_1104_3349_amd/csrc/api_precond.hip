@@ -155,12 +155,15 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
       ADDNS_HIP(hipMemsetAsync(static_cast<char*>(d->p) + d->bytes - tail, 0, tail, s));
     work.alloc(sizeof(double) * std::max(pl.lwork_total, pl.u_total));
     launch_convert_lower(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), pc->lblks.as<LBlk>(), nL,
-                         work.as<double>(), pc->lperm.as<int32_t>(), pc->lmat.p, iprec, s);
+                         work.as<double>(), pc->lperm.as<int32_t>(), pc->lmat.p, iprec, info.as<int32_t>() + m, s);
     launch_convert_upper(ab.as<double>(), pc->subs.as<SubInfo>(), pc->ublks.as<UBlk>(), nU, work.as<double>(),
                          pc->uinv.p, pc->u12.p, iprec, info.as<int32_t>() + m, s);
     ADDNS_HIP(hipMemcpyAsync(h_info.data(), info.as<int32_t>() + m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     ADDNS_HIP(hipStreamSynchronize(s));
-    if (h_info[0] != 0) throw SingularError("an interior U factor has a zero diagonal");
+    if (h_info[0] == 1) throw SingularError("an interior U factor has a zero diagonal");
+    if (h_info[0] == 2)
+      throw SingularError("the interior block factors are not finite in the storage type (overflow of the "
+                          "inverted diagonal blocks)");
   }
 
   // -- interface: dense blocks, mini Schur complements, inverses

@@ -116,11 +116,16 @@ k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const Sub
       for (int off = 32; off >= 1; off >>= 1) bi = min(bi, __shfl_xor(bi, off));
       if (bi > km) bi = 0;  // an all-zero column: a zero pivot at row j
       if (lane == 0) {
+        // a column without a nonzero candidate: with dropping (tau > 0) the
+        // pivot becomes tau ||A(:, j)|| (compensation of the dropped fill);
+        // the exact LU reports it
+        double pv = colj[bi];
+        if (pv == 0.0 && tau > 0.0) pv = tau * cn[j];
         s_p = bi;
-        s_piv = colj[bi];
+        s_piv = pv;
         s_top = colj[0];
         ipiv[j] = j + bi;
-        if (colj[bi] == 0.0 && s_info == 0) s_info = j + 1;
+        if (pv == 0.0 && s_info == 0) s_info = j + 1;
         int32_t ju = max(s_ju, min(j + KU + bi, n - 1));
         s_ju = ju;
       }
@@ -195,7 +200,7 @@ k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const Sub
 // panel column's multipliers are returned to band storage order (the later
 // interchanges of the same panel undone), which is what the sweep conversion
 // reads.  The trailing window is read and written once per panel instead of
-// once per column.  Bands whose panel does not fit 3 x 64 rows per lane use
+// once per column.  Bands whose panel does not fit 4 x 64 rows per lane use
 // the unblocked kernel.
 // ---------------------------------------------------------------------------
 constexpr int kPanel = 8;
@@ -287,6 +292,9 @@ __device__ __attribute__((always_inline)) inline void panel_regs(
     for (int k = 0; k < NS; ++k)
       if (k == pk) piv = readlane_d(a[k][c], pl);
     const double top = readlane_d(a[0][c], c);
+    // no nonzero candidate: the compensated pivot tau ||A(:, j)|| of the
+    // incomplete factorisation (zero, so reported, for the exact LU)
+    if (piv == 0.0) piv = dropc[c];
     const bool ok = piv != 0.0;
     ju = max(ju, min(jj + KU + p, n - 1));
     if (lane == 0) {
@@ -641,7 +649,7 @@ template <class T>
 __global__ void __launch_bounds__(kSetupThreads)
 k_convert_lower(const double* __restrict__ ab_all, const int32_t* __restrict__ ipiv_all,
                 const SubInfo* __restrict__ subs, const LBlk* __restrict__ lb, double* __restrict__ work_all,
-                int32_t* __restrict__ lperm_all, T* __restrict__ lmat_all) {
+                int32_t* __restrict__ lperm_all, T* __restrict__ lmat_all, int32_t* __restrict__ info) {
   const LBlk B = lb[blockIdx.x];
   const SubInfo q = subs[B.sub];
   const int32_t nbL = q.nbl, KL = q.kl, ldab = q.ldab;
@@ -697,6 +705,7 @@ k_convert_lower(const double* __restrict__ ab_all, const int32_t* __restrict__ i
     }
     __syncthreads();
   }
+  bool bad = false;
   T* lm = lmat_all + B.moff;
   for (int64_t t = tid; t < (int64_t)W * nbL; t += blockDim.x) {
     int32_t c = (int32_t)(t / W), r = (int32_t)(t % W);
@@ -707,8 +716,12 @@ k_convert_lower(const double* __restrict__ ab_all, const int32_t* __restrict__ i
       v = 0.0;
       for (int32_t k = c; k < nbL; ++k) v += Lw[(int64_t)k * W + r] * X[(int64_t)c * nbL + k];
     }
-    lm[t] = to_store<T>(v);
+    const T st = to_store<T>(v);
+    if (!isfinite((double)st)) bad = true;
+    lm[t] = st;
   }
+  // a block matrix not finite in the storage type (overflow): reported as 2
+  if (bad) atomicMax(info, 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -757,11 +770,16 @@ k_convert_upper(const double* __restrict__ ab_all, const SubInfo* __restrict__ s
   }
   T* ui = uinv_all + B.off;
   T* u12 = u12_all + B.off;
+  bool bad = false;
   for (int64_t t = tid; t < (int64_t)nbU * nbU; t += blockDim.x) {
     int32_t c = (int32_t)(t / nbU), r = (int32_t)(t % nbU);
-    ui[t] = to_store<T>(X[t]);
-    u12[t] = to_store<T>(U(r0 + r, r0 + nbU + c));
+    const T a = to_store<T>(X[t]), b = to_store<T>(U(r0 + r, r0 + nbU + c));
+    if (!isfinite((double)a) || !isfinite((double)b)) bad = true;
+    ui[t] = a;
+    u12[t] = b;
   }
+  // an inverse not finite in the storage type (overflow): reported as 2
+  if (bad) atomicMax(info, 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -1170,16 +1188,17 @@ void launch_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, i
     case 1: run_band_lu<1>(ab, ipiv, subs, m, info, colnorm, tau, prmax, ntmax, s); break;
     case 2: run_band_lu<2>(ab, ipiv, subs, m, info, colnorm, tau, prmax, ntmax, s); break;
     case 3: run_band_lu<3>(ab, ipiv, subs, m, info, colnorm, tau, prmax, ntmax, s); break;
+    case 4: run_band_lu<4>(ab, ipiv, subs, m, info, colnorm, tau, prmax, ntmax, s); break;
     default: k_band_lu<<<m, kSetupThreads, 0, s>>>(ab, ipiv, subs, info, colnorm, tau); break;
   }
 }
 void launch_convert_lower(const double* ab, const int32_t* ipiv, const SubInfo* subs, const LBlk* lb, int32_t nblk,
-                          double* work, int32_t* lperm, void* lmat, int prec, hipStream_t s) {
+                          double* work, int32_t* lperm, void* lmat, int prec, int32_t* info, hipStream_t s) {
   if (nblk == 0) return;
   if (prec == P64)
-    k_convert_lower<double><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, subs, lb, work, lperm, (double*)lmat);
+    k_convert_lower<double><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, subs, lb, work, lperm, (double*)lmat, info);
   else
-    k_convert_lower<float><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, subs, lb, work, lperm, (float*)lmat);
+    k_convert_lower<float><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, subs, lb, work, lperm, (float*)lmat, info);
 }
 void launch_convert_upper(const double* ab, const SubInfo* subs, const UBlk* ub, int32_t nblk, double* work,
                           void* uinv, void* u12, int prec, int32_t* info, hipStream_t s) {

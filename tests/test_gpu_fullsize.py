@@ -137,3 +137,41 @@ def test_gmres_reports_true_residual(full):
     # checked is that the reported residual is the true one of the iterate
     assert r["iters"] == 60 or r["converged"]
     assert abs(true - r["true_relres"]) <= 1e-10 * max(true, 1e-300) + 1e-15
+
+
+def test_ilu_setup_compensates_instead_of_refusing(full):
+    """ILU(1e-4) interiors (the tolerance of section 5) on the stretched
+    workloads.  The dropped fill leaves some columns without a nonzero pivot
+    candidate; with the compensated pivot of reading R24 the setups no longer
+    refuse with a zero pivot.  On the 256 x 256 workload the factors and the
+    interior solve are finite in FP64 and FP32, with fewer stored entries than
+    the exact factors.  On the 512 x 512 workload (cells 2e-7 high) the
+    incomplete factors are numerically useless, and the library says so
+    instead of returning garbage: in FP32 storage the inverted diagonal
+    blocks overflow and the setup refuses (ADDNS_ERR_SINGULAR); in FP64 the
+    interior solve overflows and GMRES reports a non-finite estimate."""
+    cfg, N, pc0 = full["cfg"], full["N"], full["pc"]
+    part = addns.build_partition(N, full["rp"], full["ci"], full["v"], cfg.m, cfg.sz)
+    args = (part, N, _cuda(full["rp"]), _cuda(full["ci"]), _cuda(full["v"]))
+    ni = full["ora"].ni
+    y1 = _cuda(np.random.default_rng(4).standard_normal(ni))
+    big = cfg is CAVITY512_STRETCHED
+    for iprec in (addns.F64, addns.F32):
+        if big and iprec == addns.F32:
+            with pytest.raises(addns.AddnsError) as e:
+                addns.setup_precond(*args, interior_prec=iprec, schur_prec=full["sprec"], block_mult=1, ilu_tol=1e-4)
+            assert e.value.code == addns.ERR_SINGULAR and "not finite" in str(e.value)
+            continue
+        pc = addns.setup_precond(*args, interior_prec=iprec, schur_prec=full["sprec"], block_mult=1, ilu_tol=1e-4)
+        assert pc.info()["interior_nnz"] < pc0.info()["interior_nnz"]
+        d_z = torch.zeros(ni, dtype=torch.float64, device="cuda")
+        addns.interior_solve(pc, y1, d_z)
+        torch.cuda.synchronize()
+        if not big:
+            assert bool(torch.isfinite(d_z).all())
+        else:
+            assert not bool(torch.isfinite(d_z).all())
+            d_x = torch.zeros(N, dtype=torch.float64, device="cuda")
+            with pytest.raises(addns.AddnsError) as e:
+                addns.gmres_solve(pc, _cuda(full["b"]), d_x, restart=50, maxit=20, tol=1e-8)
+            assert "non-finite" in str(e.value)

@@ -9,7 +9,8 @@ torch = pytest.importorskip("torch")
 from oracle.krylov import gmres  # noqa: E402
 from oracle.precond import BandILU  # noqa: E402
 from paper_1104_3349_amd import addns  # noqa: E402
-from tests.gpu_systems import gpu_precond, make_system, oracle_precond, relerr  # noqa: E402
+from tests.gpu_systems import (blocks_of, blockwise_err, gpu_precond, make_system, oracle_precond,  # noqa: E402
+                               relerr)
 
 pytestmark = pytest.mark.gpu
 
@@ -40,7 +41,7 @@ def test_ilu_interior_solve_and_entry_count(case, tau):
     d_z = torch.zeros(ora.ni, dtype=torch.float64, device="cuda")
     addns.interior_solve(pc, _cuda(y1), d_z)
     torch.cuda.synchronize()
-    assert relerr(d_z.cpu().numpy(), ora.interior_solve(y1)) <= 1e-9
+    assert blockwise_err(d_z.cpu().numpy(), ora.interior_solve(y1), blocks_of(ora.part, "interior")) <= 1e-9
     want = sum(f.nnz() for (_, _, f) in ora.blocks)
     exact = None
     if name != "cavity128":
@@ -61,13 +62,36 @@ def test_ilu_apply_and_gmres(case):
     d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
     addns.apply_precond(pc, _cuda(y), d_x)
     torch.cuda.synchronize()
-    assert relerr(d_x.cpu().numpy(), ora.apply(y)) <= 1e-9
+    assert blockwise_err(d_x.cpu().numpy(), ora.apply(y), blocks_of(ora.part)) <= 1e-9
     k = 12 if name != "cavity128" else 8
     ref = gmres(lambda x: ora.C @ x, ora.apply, ora.R * S.b, restart=5, tol=1e-300, maxit=k, flexible=True)
     d_x.zero_()
     r = addns.gmres_solve(pc, _cuda(S.b), d_x, restart=5, maxit=k, tol=1e-300, flexible=True)
     assert r["iters"] == k
     assert relerr(d_x.cpu().numpy(), ref.x) <= 1e-10
+    assert blockwise_err(d_x.cpu().numpy(), ref.x, blocks_of(ora.part)) <= 1e-8
+
+
+def test_ilu_zero_pivot_is_compensated():
+    """A 16 x 16 cavity stretched 1.3 (nu = 1/100, m = 8): with tau = 1e-2 the
+    dropped fill leaves a column of interior 0 without a nonzero candidate;
+    the pivot becomes tau ||A(:, j)|| on both sides (reading R24), so the
+    setup succeeds and the interior solve and apply match the oracle's."""
+    S = make_system(n=16, nu=0.01, m=8, sz=64, stretch=1.3, seed=1)
+    tau = 1e-2
+    ora = oracle_precond(S, ilu_tol=tau)
+    assert ora.blocks[0][2].compensated == [79]
+    part, pc = gpu_precond(S, ilu_tol=tau)
+    assert pc.info()["interior_nnz"] == sum(f.nnz() for (_, _, f) in ora.blocks)
+    y1 = np.random.default_rng(5).standard_normal(ora.ni)
+    d_z = torch.zeros(ora.ni, dtype=torch.float64, device="cuda")
+    addns.interior_solve(pc, _cuda(y1), d_z)
+    y = np.random.default_rng(6).standard_normal(S.N)
+    d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+    addns.apply_precond(pc, _cuda(y), d_x)
+    torch.cuda.synchronize()
+    assert blockwise_err(d_z.cpu().numpy(), ora.interior_solve(y1), blocks_of(ora.part, "interior")) <= 1e-9
+    assert blockwise_err(d_x.cpu().numpy(), ora.apply(y), blocks_of(ora.part)) <= 1e-9
 
 
 def test_ilu_zero_tolerance_is_the_exact_factorisation():

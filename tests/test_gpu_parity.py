@@ -476,6 +476,26 @@ def test_every_sweep_form_matches_oracle(chunks, zero_skip, sizing):
     assert e <= 1e-9
 
 
+def test_wide_band_interiors():
+    """Interiors with bands of 188 to 190 (a 128 x 128 cavity in 4
+    subdomains): the blocked band LU with four 64-row slots per lane, then
+    the sweep; interior solve and apply element by element against the
+    oracle."""
+    S = make_system(n=128, nu=0.01, m=4, sz=64, seed=1)
+    ora = oracle_precond(S)
+    part, pc = gpu_precond(S)
+    assert pc.info()["kl"] >= 185
+    y = np.random.default_rng(31).standard_normal(S.N)
+    d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+    addns.apply_precond(pc, _cuda(y), d_x)
+    y1 = y[:ora.ni].copy()
+    d_z = torch.zeros(ora.ni, dtype=torch.float64, device="cuda")
+    addns.interior_solve(pc, _cuda(y1), d_z)
+    torch.cuda.synchronize()
+    assert blockwise_err(d_z.cpu().numpy(), ora.interior_solve(y1), blocks_of(ora.part, "interior")) <= 1e-9
+    assert blockwise_err(d_x.cpu().numpy(), ora.apply(y), blocks_of(ora.part)) <= 1e-9
+
+
 def test_per_interior_blocks_gmres_matches_oracle():
     """Per-interior block sizes in the FP64 solve of the bench workload: the
     iteration count within one of the oracle's (MGS), the true residual met."""

@@ -204,6 +204,43 @@ def test_band_ilu_error_lives_on_the_dropped_positions(tau):
     assert np.abs(R).max() > 0     # something was dropped
 
 
+def _zero_pivot_block():
+    """Interior 0 of a 16 x 16 cavity stretched 1.3 (nu = 1/100, m = 8): with
+    tau = 1e-2 the dropped fill leaves column 79 without a nonzero candidate."""
+    rp, ci, v, b, meta, P = _system(16, 0.01, 1.3, 8, 64)
+    R, sv = row_scale(rp, ci, v)
+    C = sp.csr_matrix((sv, ci, rp), shape=(meta["N"], meta["N"]))
+    Cp = C[P.perm][:, P.perm]
+    return Cp[:P.int_offsets[1], :P.int_offsets[1]].tocsr()
+
+
+def test_band_ilu_zero_pivot_compensation():
+    """Reading R24: a column whose every pivot candidate is zero after the
+    drops takes tau ||A(:, j)|| as its pivot.  P A = L U + R still holds with
+    R on the dropped positions (below tau ||A(:, k)||), and at a compensated
+    pivot R_jj = -tau ||A(:, j)|| exactly; the exact LU refuses the block as
+    singular only where it is (here it is not)."""
+    A = _zero_pivot_block()
+    tau = 1e-2
+    f = BandILU(A, tau)
+    assert f.compensated == [79]
+    Ad = A.toarray()
+    cn = np.sqrt((Ad * Ad).sum(axis=0))
+    R = Ad[f.perm] - f.L @ f.U
+    scale = np.abs(Ad).max()
+    for j in f.compensated:
+        assert f.U[j, j] == tau * cn[j]
+        assert abs(R[j, j] + tau * cn[j]) <= 1e-13 * scale
+        R[j, j] = 0.0
+    kept = (np.tril(f.L, -1) != 0) | (f.U != 0)
+    assert np.abs(R[kept]).max() <= 1e-13 * scale
+    assert np.all(np.abs(R) <= tau * cn[None, :] * (1 + 1e-12) + 1e-13 * scale)
+    # the exact factorisation of the same block exists, and a smaller tau
+    # leaves no column without a candidate
+    BandLU(A)
+    assert BandILU(A, 1e-4).compensated == []
+
+
 def test_band_ilu_drops_more_with_larger_tau():
     A = _interior_block()
     nz = [BandILU(A, tau).nnz() for tau in (0.0, 1e-4, 1e-2, 1e-1)]
