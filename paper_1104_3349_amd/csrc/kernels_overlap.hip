@@ -208,10 +208,6 @@ void run_overlap_chain(int32_t k, int32_t L, const int32_t* ao, const int64_t* m
   }
 }
 
-// Row width of the chain matrices for aggregates of at most smax nodes (0:
-// too large for the chain kernel).
-int overlap_chain_width(int32_t smax) { return smax <= 64 ? 64 : (smax <= 80 ? 80 : (smax <= 128 ? 128 : 0)); }
-
 // Segment length of the chain: the requested one, else the L that balances
 // the segment sweeps (L steps) against the chain of segment ends (k / L).
 int32_t overlap_segment_length(int32_t k, int32_t requested) {

@@ -12,6 +12,10 @@ namespace addns {
 
 static int32_t round_up(int32_t a, int32_t b) { return (a + b - 1) / b * b; }
 
+// Row width of the overlap chain matrices for aggregates of at most smax
+// nodes (0: too large for the chain kernel).
+int overlap_chain_width(int32_t smax) { return smax <= 64 ? 64 : (smax <= 80 ? 80 : (smax <= 128 ? 128 : 0)); }
+
 void build_plan(const PartitionData& P, Plan& pl, int schur_mode, int block_mult, int overlap,
                 bool per_interior) {
   const int32_t N = P.N;
