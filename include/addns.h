@@ -506,6 +506,19 @@ int addns_gmres_solve_judged(addns_precond_t learned, addns_precond_t plain, con
 void addns_partition_destroy(addns_partition_t p);
 void addns_precond_destroy(addns_precond_t pc);
 
+/* Device memory of the library.  Every device buffer that a handle or a call
+   owns comes from a per-device cache: a released buffer is kept, not freed,
+   and is handed out again (for a request of at most its size and at least
+   half of it) once a device synchronisation has followed its release (each
+   addns_setup_precond begins with one when there are released buffers), so
+   repeated setups and solves do not pay hipMalloc/hipFree, which also
+   synchronises the device, per buffer.  At most a quarter of the device
+   memory is kept; beyond that a release frees at once.  This call
+   synchronises every device that holds cached buffers, frees them all and
+   returns the number of bytes freed (0 if none).  Buffers of live handles
+   are not touched.  No stream argument: it waits for all work on the device. */
+int64_t addns_release_cached_memory(void);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char* addns_last_error(void);
 

@@ -30,7 +30,7 @@ EXPORTED = [
     "addns_last_error", "addns_version",
     "addns_dtn_param_count", "addns_dtn_samples", "addns_dtn_forward", "addns_dtn_grad",
     "addns_dtn_train", "addns_dtn_save", "addns_dtn_load", "addns_gmres_solve_judged",
-    "addns_precond_refactor",
+    "addns_precond_refactor", "addns_release_cached_memory",
 ]
 
 
@@ -98,6 +98,7 @@ def lib():
         "addns_precond_fill": (C.c_int, [P, i64p, i64p]),
         "addns_partition_destroy": (None, [P]),
         "addns_precond_destroy": (None, [P]),
+        "addns_release_cached_memory": (C.c_int64, []),
         "addns_last_error": (C.c_char_p, []),
         "addns_version": (C.c_char_p, []),
         "addns_dtn_param_count": (C.c_int, []),
@@ -457,6 +458,12 @@ def dtn_load(path):
     w = np.empty(dtn_param_count(), np.float32)
     _check(lib().addns_dtn_load(os.fsencode(path), _ptr(w)), "dtn_load")
     return w
+
+
+def release_cached_memory() -> int:
+    """Free the device buffers that released handles left in the library's
+    cache; returns the bytes freed."""
+    return int(lib().addns_release_cached_memory())
 
 
 def version() -> str:

@@ -589,6 +589,8 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
   return guarded("addns_setup_precond", [&]() -> int {
     if (!p || !out || !d_rowptr || !d_colidx || !d_vals) throw ArgError("null argument");
     if (N != p->d.N) throw ArgError("N does not match the partition");
+    // buffers released since the last setup become reusable
+    pool_sync();
     addns_precond_opts o{ADDNS_SCHUR_MSCN, ADDNS_F64, ADDNS_F64, 1, nullptr, 1, 0, 0, 0.0, 0, 0, 0, 0, 0};
     if (opts) o = *opts;
     if (o.overlap_segment < 0) throw ArgError("overlap_segment must be >= 0");
@@ -1109,5 +1111,7 @@ int addns_precond_schur_blocks(addns_precond_t pc, double* h_out, int64_t count)
 }
 
 void addns_precond_destroy(addns_precond_t pc) { delete pc; }
+
+int64_t addns_release_cached_memory(void) { return (int64_t)pool_trim(); }
 
 }  // extern "C"

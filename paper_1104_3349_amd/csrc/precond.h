@@ -32,17 +32,28 @@ struct ArgError : std::runtime_error {
 };
 
 // Owning device buffer.
+// Caching device allocator (device_pool.cpp): blocks released to a
+// per-device pool are reused only after a device synchronisation that
+// followed their release (pool_sync, at the start of every allocating entry
+// point); pool_trim gives every cached block back (returns the bytes).
+void* pool_alloc(size_t n, size_t* cap, int* dev);
+void pool_free(void* p, size_t cap, int dev);
+void pool_sync();
+size_t pool_trim();
+
 struct DevBuf {
   void* p = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;  // requested size
+  size_t cap = 0;    // size of the block behind p (>= bytes)
+  int dev = 0;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { reset(); }
   void reset() {
-    if (p) (void)hipFree(p);
+    if (p) pool_free(p, cap, dev);
     p = nullptr;
-    bytes = 0;
+    bytes = cap = 0;
   }
   // keeps the allocation (and its address) when the size is unchanged, so
   // that a refactor on the same plan leaves every device pointer in place
@@ -50,7 +61,7 @@ struct DevBuf {
     if (n == 0) n = 8;
     if (p && bytes == n) return;
     reset();
-    ADDNS_HIP(hipMalloc(&p, n));
+    p = pool_alloc(n, &cap, &dev);
     bytes = n;
   }
   template <class T>
