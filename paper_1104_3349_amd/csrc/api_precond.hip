@@ -124,6 +124,8 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
     launch_band_colnorm(ab.as<double>(), pc->subs.as<SubInfo>(), m, npad_max, colnorm.as<double>(), s);
     int32_t kl_max = 0, kv_max = 0;
     for (const SubInfo& q : pl.subs) {
+      // the blocked band LU factors whole panels
+      if (q.npad % kNpadMultiple != 0) throw std::logic_error("padded interior size is not a multiple of 16");
       kl_max = std::max(kl_max, q.kl);
       kv_max = std::max(kv_max, q.kl + q.ku);
     }

@@ -204,6 +204,7 @@ k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const Sub
 // the unblocked kernel.
 // ---------------------------------------------------------------------------
 constexpr int kPanel = 8;
+static_assert(kNpadMultiple % kPanel == 0, "panels must tile every padded block");
 // Threads of the blocked band LU: 8 waves leave each lane the registers that
 // the lookahead needs (the panel in wave 0's registers next to the update
 // tiles of the others) without spilling.
@@ -240,13 +241,18 @@ __device__ inline double wave_max_nonneg(double x) {
 }
 
 // The same panel factorisation with the panel in registers: lane l holds
-// rows l + 64k (k < NS) of the nb columns, the pivot row and row c are
-// broadcast with readlane, and the pivot search uses one max reduction and
-// ballots.  Each entry sees the same operations in the same order as in the
-// LDS form, so the results are identical.
+// rows l + 64k (k < NS) of the kPanel columns (every padded block holds a
+// multiple of kPanel columns, so panels are always full); the pivot search
+// uses one max reduction and ballots, and the pivot row and row c reach
+// every lane by readlane.  Per column c only the later columns are interchanged in
+// registers: the earlier ones hold finished multipliers that the panel no
+// longer reads, so their interchanges are applied afterwards in LDS (lane c
+// replays the steps after c on its column, in order).  Each entry sees the
+// same operations in the same order as with every interchange applied at
+// its step, so the results are identical.
 template <int NS>
 __device__ __attribute__((always_inline)) inline void panel_regs(
-    double* s_pan, int32_t prmax, int32_t prows, int32_t j0, int32_t nb, int32_t n, int32_t KL, int32_t KU, int lane,
+    double* s_pan, int32_t prmax, int32_t prows, int32_t j0, int32_t n, int32_t KL, int32_t KU, int lane,
     double tau, const double* cn, int32_t* ipiv, int32_t* s_pv, int32_t* s_ok, int32_t* s_juc, int32_t& s_ju,
     int32_t& s_info) {
   double a[NS][kPanel];
@@ -255,16 +261,15 @@ __device__ __attribute__((always_inline)) inline void panel_regs(
 #pragma unroll
     for (int c = 0; c < kPanel; ++c) {
       const int32_t r = lane + 64 * k;
-      a[k][c] = (c < nb && r < prows) ? s_pan[c * prmax + r] : 0.0;
+      a[k][c] = r < prows ? s_pan[c * prmax + r] : 0.0;
     }
   // drop thresholds of the panel columns, loaded once
   double dropc[kPanel];
 #pragma unroll
-  for (int c = 0; c < kPanel; ++c) dropc[c] = c < nb ? tau * cn[j0 + c] : 0.0;
+  for (int c = 0; c < kPanel; ++c) dropc[c] = tau * cn[j0 + c];
   int32_t ju = s_ju, info = s_info;
 #pragma unroll
   for (int c = 0; c < kPanel; ++c) {
-    if (c >= nb) break;
     const int32_t jj = j0 + c, km = min(KL, n - 1 - jj);
     // pivot: the first row of c .. c+km within the tie tolerance of the largest
     double best = 0.0;
@@ -286,11 +291,21 @@ __device__ __attribute__((always_inline)) inline void panel_regs(
         found = true;
       }
     }
-    const int32_t p = prow - c, pl = prow & 63, pk = prow >> 6;
-    double piv = 0.0;
+    const int32_t p = __builtin_amdgcn_readfirstlane(prow - c);
+    const int32_t pl = (c + p) & 63, pk = (c + p) >> 6;
+    // the pivot row in columns c.. (slot pk chosen uniformly, then read from
+    // lane pl) and row c of column c
+    double vp[kPanel];
 #pragma unroll
-    for (int k = 0; k < NS; ++k)
-      if (k == pk) piv = readlane_d(a[k][c], pl);
+    for (int cc = 0; cc < kPanel; ++cc) {
+      if (cc < c) continue;
+      double v = a[0][cc];
+#pragma unroll
+      for (int k = 1; k < NS; ++k)
+        if (pk == k) v = a[k][cc];
+      vp[cc] = readlane_d(v, pl);
+    }
+    double piv = vp[c];
     const double top = readlane_d(a[0][c], c);
     // no nonzero candidate: the compensated pivot tau ||A(:, j)|| of the
     // incomplete factorisation (zero, so reported, for the exact LU)
@@ -307,19 +322,14 @@ __device__ __attribute__((always_inline)) inline void panel_regs(
       if (info == 0) info = jj + 1;
       continue;
     }
-    // the interchange of rows c and prow in the other panel columns; row c
-    // of the later columns becomes U (dropped below the threshold)
+    // the interchange of rows c and c + p in the later columns; row c becomes
+    // U (dropped below the threshold)
     double u[kPanel];
 #pragma unroll
-    for (int cc = 0; cc < kPanel; ++cc) {
-      if (cc == c || cc >= nb) continue;
-      double rp = 0.0;
-#pragma unroll
-      for (int k = 0; k < NS; ++k)
-        if (k == pk) rp = readlane_d(a[k][cc], pl);
+    for (int cc = c + 1; cc < kPanel; ++cc) {
       const double rc = readlane_d(a[0][cc], c);
-      u[cc] = rp;
-      if (cc > c && j0 + cc <= ju && fabs(rp) < dropc[cc]) u[cc] = 0.0;
+      u[cc] = vp[cc];
+      if (j0 + cc <= ju && fabs(vp[cc]) < dropc[cc]) u[cc] = 0.0;
 #pragma unroll
       for (int k = 0; k < NS; ++k)
         if (k == pk && lane == pl) a[k][cc] = rc;
@@ -331,7 +341,7 @@ __device__ __attribute__((always_inline)) inline void panel_regs(
     for (int k = 0; k < NS; ++k) {
       const int32_t r = lane + 64 * k;
       if (r > c && r <= c + km) {
-        const double v = (r == prow) ? top : a[k][c];
+        const double v = (r == c + p) ? top : a[k][c];
         a[k][c] = fabs(v) < drop_l ? 0.0 : v * rinv;
       }
     }
@@ -339,7 +349,7 @@ __device__ __attribute__((always_inline)) inline void panel_regs(
     // rank-1 update of the later panel columns
 #pragma unroll
     for (int cc = c + 1; cc < kPanel; ++cc) {
-      if (cc >= nb || j0 + cc > ju) continue;
+      if (j0 + cc > ju) continue;
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
         const int32_t r = lane + 64 * k;
@@ -352,56 +362,75 @@ __device__ __attribute__((always_inline)) inline void panel_regs(
 #pragma unroll
     for (int c = 0; c < kPanel; ++c) {
       const int32_t r = lane + 64 * k;
-      if (c < nb && r < prows) s_pan[c * prmax + r] = a[k][c];
+      if (r < prows) s_pan[c * prmax + r] = a[k][c];
     }
+  // the later steps' interchanges in the multiplier columns (same wave: the
+  // stores above are seen by these reads in program order)
+  if (lane < kPanel) {
+    double* pc = s_pan + lane * prmax;
+    for (int32_t c2 = lane + 1; c2 < kPanel; ++c2) {
+      const int32_t p2 = s_ok[c2] ? s_pv[c2] : 0;
+      if (p2 != 0) {
+        const double x = pc[c2];
+        pc[c2] = pc[c2 + p2];
+        pc[c2 + p2] = x;
+      }
+    }
+  }
   if (lane == 0) {
     s_ju = ju;
     s_info = info;
   }
 }
 
-// Rank-nb update of rows j0+nb .. rmax of the trailing columns tcol in
-// [t_lo, t_hi) (tcol counts from column j0+nb): lane l keeps the multipliers
-// of rows rc0 + l + 64k (k < 3) in registers, wave w of W takes columns
-// t_lo + w, t_lo + w + W, ... four at a time; U12 of a column is a broadcast
-// LDS read (its skipped steps hold zero).
+// Rank-kPanel update of rows j0+kPanel .. rmax of the trailing columns tcol
+// in [t_lo, t_hi) (tcol counts from column j0+kPanel): lane l keeps the
+// multipliers of rows rc0 + l + 64k (k < 3) in registers, wave w of W takes
+// columns t_lo + w, t_lo + w + W, ... four at a time; U12 of a column is a
+// broadcast LDS read (its skipped steps hold zero).  Rows past nrows and
+// columns past t_hi read the last valid row or column instead (every load is
+// unconditional) and store nothing.
 __device__ __attribute__((always_inline)) inline void lu_rank_update(
     double* ab, int32_t ldab, int32_t KV, const double* s_pan, const double* s_u12, int32_t prmax, int32_t ntmax,
-    int32_t j0, int32_t nb, int32_t nrows, int32_t t_lo, int32_t t_hi, int w, int W, int lane) {
-  auto at = [&](int32_t r, int32_t c) -> double& { return ab[(int64_t)c * ldab + KV + r - c]; };
-  for (int32_t rc0 = 0; rc0 < nrows && t_lo < t_hi; rc0 += 3 * 64) {
+    int32_t j0, int32_t nrows, int32_t t_lo, int32_t t_hi, int w, int W, int lane) {
+  if (nrows <= 0 || t_lo >= t_hi) return;
+  const int32_t c0 = j0 + kPanel;  // first trailing column (and first row below the panel)
+  for (int32_t rc0 = 0; rc0 < nrows; rc0 += 3 * 64) {
     double L[3][kPanel];
-    int32_t rr[3];
+    int32_t ro[3];
+    bool rv[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      rr[k] = rc0 + lane + 64 * k;
+      const int32_t r = rc0 + lane + 64 * k;
+      rv[k] = r < nrows;
+      ro[k] = min(r, nrows - 1);
 #pragma unroll
-      for (int c = 0; c < kPanel; ++c) L[k][c] = (rr[k] < nrows && c < nb) ? s_pan[c * prmax + nb + rr[k]] : 0.0;
+      for (int c = 0; c < kPanel; ++c) L[k][c] = s_pan[c * prmax + kPanel + ro[k]];
     }
     for (int32_t t0 = t_lo + w; t0 < t_hi; t0 += 4 * W) {
       double a[4][3];
+      int32_t tc[4];
 #pragma unroll
       for (int bq = 0; bq < 4; ++bq) {
-        const int32_t tcol = t0 + bq * W;
+        tc[bq] = min(t0 + bq * W, t_hi - 1);
+        // entry (c0 + ro, c0 + tc) of the band
+        const double* col = ab + (int64_t)(c0 + tc[bq]) * ldab + KV - tc[bq];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-          a[bq][k] = (tcol < t_hi && rr[k] < nrows) ? at(j0 + nb + rr[k], j0 + nb + tcol) : 0.0;
+        for (int k = 0; k < 3; ++k) a[bq][k] = col[ro[k]];
       }
 #pragma unroll
       for (int bq = 0; bq < 4; ++bq) {
-        const int32_t tcol = t0 + bq * W;
-        if (tcol >= t_hi) continue;
+        const bool cv = t0 + bq * W < t_hi;
         double u[kPanel];
 #pragma unroll
-        for (int c = 0; c < kPanel; ++c) u[c] = c < nb ? s_u12[c * ntmax + tcol] : 0.0;
+        for (int c = 0; c < kPanel; ++c) u[c] = s_u12[c * ntmax + tc[bq]];
+        double* col = ab + (int64_t)(c0 + tc[bq]) * ldab + KV - tc[bq];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          if (rr[k] >= nrows) continue;
           double x = a[bq][k];
 #pragma unroll
-          for (int c = 0; c < kPanel; ++c)
-            if (c < nb) x -= L[k][c] * u[c];
-          at(j0 + nb + rr[k], j0 + nb + tcol) = x;
+          for (int c = 0; c < kPanel; ++c) x -= L[k][c] * u[c];
+          if (cv && rv[k]) col[ro[k]] = x;
         }
       }
     }
@@ -436,12 +465,14 @@ k_band_lu_blocked(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, c
   int32_t* ipiv = ipiv_all + q.vec_off;
   const double* cn = colnorm_all + q.vec_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = (int)(blockDim.x >> 6);
+  if (n == 0) return;  // an empty interior (info stays 0)
   // entry (r, c) of the block lives at ab[c * ldab + KV + r - c] for -KV <= r - c <= KL
   auto at = [&](int32_t r, int32_t c) -> double& { return ab[(int64_t)c * ldab + KV + r - c]; };
   auto pan = [&](int b) { return s_pan0 + b * kPanel * prmax; };
   auto u12 = [&](int b) { return s_u120 + b * kPanel * ntmax; };
   auto load_panel = [&](int b, int32_t j0) {
-    const int32_t nb = min(kPanel, n - j0), prows = min(KL + nb, n - j0);
+    constexpr int32_t nb = kPanel;
+    const int32_t prows = min(KL + nb, n - j0);
     double* P = pan(b);
     for (int32_t e = tid; e < nb * prows; e += blockDim.x) {
       const int32_t c = e / prows, rr = e % prows, d = rr - c;
@@ -451,7 +482,8 @@ k_band_lu_blocked(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, c
   // multipliers of panel j0 (buffer b) back to band storage order (the later
   // interchanges of the same panel undone), then the panel to memory
   auto store_panel = [&](int b, int32_t j0) {
-    const int32_t nb = min(kPanel, n - j0), prows = min(KL + nb, n - j0);
+    constexpr int32_t nb = kPanel;
+    const int32_t prows = min(KL + nb, n - j0);
     double* P = pan(b);
     if (tid < nb) {
       double* pc = P + tid * prmax;
@@ -478,14 +510,14 @@ k_band_lu_blocked(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, c
   load_panel(0, 0);
   __syncthreads();
   if (wave == 0)
-    panel_regs<NS>(pan(0), prmax, min(KL + min(kPanel, n), n), 0, min(kPanel, n), n, KL, KU, lane, tau, cn, ipiv,
-                   s_pv[0], s_ok[0], s_juc[0], s_ju, s_info);
+    panel_regs<NS>(pan(0), prmax, min(KL + kPanel, n), 0, n, KL, KU, lane, tau, cn, ipiv, s_pv[0], s_ok[0], s_juc[0],
+                   s_ju, s_info);
   __syncthreads();
   for (int32_t k = 0;; ++k) {
     const int b = k & 1;
     const int32_t j0 = k * kPanel;
     if (j0 >= n) break;
-    const int32_t nb = min(kPanel, n - j0);
+    constexpr int32_t nb = kPanel;  // n is a multiple of kPanel
     const int32_t ju = s_ju, nt = ju - (j0 + nb) + 1;
     const double* P = pan(b);
     double* U = u12(b);
@@ -496,10 +528,10 @@ k_band_lu_blocked(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, c
       const double drop_u = tau * cn[jc];
       double v[kPanel];
 #pragma unroll
-      for (int c = 0; c < kPanel; ++c) v[c] = (c < nb && jc <= s_juc[b][c]) ? at(j0 + c, jc) : 0.0;
+      for (int c = 0; c < kPanel; ++c) v[c] = jc <= s_juc[b][c] ? at(j0 + c, jc) : 0.0;
 #pragma unroll
       for (int c = 0; c < kPanel; ++c) {
-        if (c >= nb || !s_ok[b][c] || jc > s_juc[b][c]) continue;
+        if (!s_ok[b][c] || jc > s_juc[b][c]) continue;
         const int32_t p = s_pv[b][c];
         if (p == 0) continue;
         if (c + p < nb) {
@@ -521,28 +553,28 @@ k_band_lu_blocked(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, c
 #pragma unroll
       for (int c = 0; c < kPanel; ++c) {
         double u = 0.0;
-        if (c < nb && s_ok[b][c] && jc <= s_juc[b][c]) {
+        if (s_ok[b][c] && jc <= s_juc[b][c]) {
           u = v[c];
           if (fabs(u) < drop_u) u = 0.0;
           v[c] = u;
 #pragma unroll
           for (int i = 1; i < kPanel; ++i)
-            if (c + i < nb) v[c + i] -= P[c * prmax + c + i] * u;
+            if (c + i < kPanel) v[c + i] -= P[c * prmax + c + i] * u;
         }
-        if (c < nb) U[c * ntmax + tcol] = u;
+        U[c * ntmax + tcol] = u;
       }
 #pragma unroll
       for (int c = 0; c < kPanel; ++c)
-        if (c < nb && jc <= s_juc[b][c]) at(j0 + c, jc) = v[c];
+        if (jc <= s_juc[b][c]) at(j0 + c, jc) = v[c];
     }
     __syncthreads();
     // ---- (2) rank-nb update of the next panel's columns
     const int32_t rmax = min(j0 + nb - 1 + KL, n - 1), nrows = rmax - (j0 + nb) + 1;
     const int32_t jn = j0 + nb;
-    const bool next = nb == kPanel && jn < n;
-    const int32_t nlook = next ? min(min(kPanel, n - jn), max(nt, 0)) : 0;
+    const bool next = jn < n;
+    const int32_t nlook = next ? min(kPanel, max(nt, 0)) : 0;
     if (nlook > 0) {
-      lu_rank_update(ab, ldab, KV, P, U, prmax, ntmax, j0, nb, nrows, 0, nlook, wave, nwaves, lane);
+      lu_rank_update(ab, ldab, KV, P, U, prmax, ntmax, j0, nrows, 0, nlook, wave, nwaves, lane);
       __syncthreads();
     }
     // ---- (3) the previous panel to memory, the next panel in
@@ -558,10 +590,10 @@ k_band_lu_blocked(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, c
     // this panel's update
     if (wave == 0) {
       if (next)
-        panel_regs<NS>(pan(1 - b), prmax, min(KL + min(kPanel, n - jn), n - jn), jn, min(kPanel, n - jn), n, KL, KU,
-                       lane, tau, cn, ipiv, s_pv[1 - b], s_ok[1 - b], s_juc[1 - b], s_ju, s_info);
+        panel_regs<NS>(pan(1 - b), prmax, min(KL + kPanel, n - jn), jn, n, KL, KU, lane, tau, cn, ipiv, s_pv[1 - b],
+                       s_ok[1 - b], s_juc[1 - b], s_ju, s_info);
     } else {
-      lu_rank_update(ab, ldab, KV, P, U, prmax, ntmax, j0, nb, nrows, nlook, max(nt, 0), wave - 1, nwaves - 1, lane);
+      lu_rank_update(ab, ldab, KV, P, U, prmax, ntmax, j0, nrows, nlook, max(nt, 0), wave - 1, nwaves - 1, lane);
     }
     __syncthreads();
     if (!next) {

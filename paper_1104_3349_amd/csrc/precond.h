@@ -301,6 +301,10 @@ void launch_gather(const int32_t* src, const double* in, int64_t n, double* out,
 void launch_scatter_band(const int64_t* dst, const int32_t* src, const double* cpv, int64_t n, double* ab,
                          hipStream_t s);
 void launch_band_pad_identity(const SubInfo* subs, int32_t m, double* ab, hipStream_t s);
+// Every padded interior size is a multiple of this (block sizes are multiples
+// of 8 and the upper block is twice the lower one); the blocked band LU's
+// panels of 8 columns rely on it.
+constexpr int32_t kNpadMultiple = 16;
 void launch_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, const double* colnorm,
                     double tau, int32_t kl_max, int32_t kv_max, hipStream_t s);
 void launch_band_colnorm(const double* ab, const SubInfo* subs, int32_t m, int32_t npad_max, double* colnorm,
