@@ -156,10 +156,15 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
     for (DevBuf* d : {&pc->lmat, &pc->uinv, &pc->u12})
       ADDNS_HIP(hipMemsetAsync(static_cast<char*>(d->p) + d->bytes - tail, 0, tail, s));
     work.alloc(sizeof(double) * std::max(pl.lwork_total, pl.u_total));
+    int32_t nbl_max = 0;
+    for (const SubInfo& q : pl.subs) nbl_max = std::max(nbl_max, q.nbl);
     launch_convert_lower(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), pc->lblks.as<LBlk>(), nL,
-                         work.as<double>(), pc->lperm.as<int32_t>(), pc->lmat.p, iprec, info.as<int32_t>() + m, s);
+                         work.as<double>(), pc->lperm.as<int32_t>(), pc->lmat.p, iprec, info.as<int32_t>() + m,
+                         nbl_max, kl_max, s);
+    int32_t nbu_max = 0;
+    for (const SubInfo& q : pl.subs) nbu_max = std::max(nbu_max, q.nbu);
     launch_convert_upper(ab.as<double>(), pc->subs.as<SubInfo>(), pc->ublks.as<UBlk>(), nU, work.as<double>(),
-                         pc->uinv.p, pc->u12.p, iprec, info.as<int32_t>() + m, s);
+                         pc->uinv.p, pc->u12.p, iprec, info.as<int32_t>() + m, nbu_max, kv_max, s);
     ADDNS_HIP(hipMemcpyAsync(h_info.data(), info.as<int32_t>() + m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     ADDNS_HIP(hipStreamSynchronize(s));
     if (h_info[0] == 1) throw SingularError("an interior U factor has a zero diagonal");

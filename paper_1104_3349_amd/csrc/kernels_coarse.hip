@@ -249,6 +249,104 @@ __global__ void k_gj_update(double* __restrict__ A, int32_t nb, int32_t nc, int3
   else a -= mcol[i] * (prow[j] * inv);
 }
 
+// The same Gauss-Jordan inversion for blocks of at most kGjFused columns,
+// every step in one workgroup per block with the block in LDS: the block's
+// largest |entry|, then per step k the pivot (first row of largest |A(i,k)|
+// among rows >= k, by one wave), the copies of pivot row and column, the
+// interchange and the update, and finally the column interchanges undone.
+// Each element receives the operations of k_gj_pivot, k_gj_update and
+// k_gj_colswap in the same order, so the inverse is the same bit for bit;
+// one launch instead of two per step.
+constexpr int kGjFused = 88;
+__global__ void __launch_bounds__(1024) k_gj_fused(double* __restrict__ A, const int32_t* __restrict__ boff,
+                                                   const int64_t* __restrict__ beoff, int32_t* __restrict__ perm,
+                                                   int32_t* __restrict__ info) {
+  __shared__ double E[kGjFused * kGjFused];
+  __shared__ double prow[kGjFused], mcol[kGjFused];
+  __shared__ double red[16];
+  __shared__ int32_t s_p[kGjFused];
+  const int32_t b = blockIdx.x;
+  const int32_t o = boff[b], n = boff[b + 1] - o;
+  double* G = A + beoff[b];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (int)(blockDim.x >> 6);
+  double m = 0.0;
+  for (int32_t e = tid; e < n * n; e += blockDim.x) {
+    E[e] = G[e];
+    m = fmax(m, fabs(E[e]));
+  }
+  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if (lane == 0) red[wave] = m;
+  __syncthreads();
+  double amax = 0.0;
+  for (int w = 0; w < nw; ++w) amax = fmax(amax, red[w]);
+  for (int32_t k = 0; k < n; ++k) {
+    if (wave == 0) {
+      // pivot: largest |A(i,k)|, the smallest such row on ties
+      double best = -1.0;
+      int32_t bidx = n;
+      for (int32_t i = k + lane; i < n; i += 64) {
+        const double v = fabs(E[i * n + k]);
+        if (v > best) {
+          best = v;
+          bidx = i;
+        }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double v2 = __shfl_xor(best, off);
+        const int32_t i2 = __shfl_xor(bidx, off);
+        if (v2 > best || (v2 == best && i2 < bidx)) {
+          best = v2;
+          bidx = i2;
+        }
+      }
+      if (lane == 0) {
+        s_p[k] = bidx;
+        perm[o + k] = bidx;
+        if (!(best > 1e-13 * amax) && info[0] == 0) info[0] = o + k + 1;
+      }
+    }
+    __syncthreads();
+    const int32_t p = s_p[k];
+    // copies from the matrix before the interchange
+    for (int32_t i = tid; i < n; i += blockDim.x) {
+      const int32_t src = i == k ? p : (i == p ? k : i);
+      mcol[i] = E[src * n + k];
+      prow[i] = E[p * n + i];
+    }
+    __syncthreads();
+    if (p != k)
+      for (int32_t j = tid; j < n; j += blockDim.x) {
+        const double x = E[k * n + j], y = E[p * n + j];
+        E[k * n + j] = y;
+        E[p * n + j] = x;
+      }
+    __syncthreads();
+    const double inv = 1.0 / prow[k];
+    for (int32_t e = tid; e < n * n; e += blockDim.x) {
+      const int32_t i = e / n, j = e % n;
+      double& a = E[e];
+      if (i == k) a = j == k ? inv : prow[j] * inv;
+      else if (j == k) a = -mcol[i] * inv;
+      else a -= mcol[i] * (prow[j] * inv);
+    }
+    __syncthreads();
+  }
+  // column interchanges undone, one thread per row
+  for (int32_t r = tid; r < n; r += blockDim.x) {
+    double* row = E + r * n;
+    for (int32_t k = n - 1; k >= 0; --k) {
+      const int32_t p = s_p[k];
+      if (p != k) {
+        const double t = row[k];
+        row[k] = row[p];
+        row[p] = t;
+      }
+    }
+  }
+  __syncthreads();
+  for (int32_t e = tid; e < n * n; e += blockDim.x) G[e] = E[e];
+}
+
 // Undo the row interchanges on the columns of each block's inverse: inv(A)
 // is inv(P A) with its columns swapped back in reverse order.  One thread
 // per coarse row.
@@ -369,6 +467,10 @@ void launch_gj_invert(const addns_precond* pc, double* A, int32_t* perm, double*
   const int32_t* boff = pc->cz_boff.as<int32_t>();
   const int32_t* cblk = pc->cz_cblk.as<int32_t>();
   const int64_t* beoff = pc->cz_beoff.as<int64_t>();
+  if (cp.blk_max <= kGjFused) {
+    k_gj_fused<<<nb, 1024, 0, s>>>(A, boff, beoff, perm, info);
+    return;
+  }
   k_absmax<<<nb, 1024, 0, s>>>(A, boff, beoff, work);
   const dim3 grid((unsigned)((cp.blk_max + 255) / 256), (unsigned)nc);
   for (int32_t k = 0; k < cp.blk_max; ++k) {

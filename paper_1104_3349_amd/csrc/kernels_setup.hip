@@ -218,26 +218,34 @@ __device__ inline double readlane_d(double x, int32_t l) {
 }
 
 template <int CTRL, int ROW_MASK>
-__device__ inline double dpp_max_step(double v) {
-  const int64_t bits = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, CTRL, ROW_MASK, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, ROW_MASK, 0xf, false);
-  return fmax(v, __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo)));
+__device__ inline uint32_t dpp_umax_step(uint32_t v) {
+  return max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, false));
 }
 
-// Largest value over the wave of non-negative x (0 is the identity): a
-// prefix maximum within each row of 16 lanes by DPP row shifts, then the row
-// maxima combined by row broadcasts, read from lane 63.  Lanes whose DPP
-// source does not exist receive 0.  The maximum is exact, so the order of
-// the comparisons does not matter.
+// Largest unsigned value over the wave (0 is the identity): a prefix maximum
+// within each row of 16 lanes by DPP row shifts, then the row maxima
+// combined by row broadcasts, read from lane 63.  Lanes whose DPP source
+// does not exist receive 0.
+__device__ inline uint32_t wave_umax(uint32_t x) {
+  x = dpp_umax_step<0x111, 0xf>(x);  // row_shr:1
+  x = dpp_umax_step<0x112, 0xf>(x);  // row_shr:2
+  x = dpp_umax_step<0x114, 0xf>(x);  // row_shr:4
+  x = dpp_umax_step<0x118, 0xf>(x);  // row_shr:8
+  x = dpp_umax_step<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x = dpp_umax_step<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// Largest value over the wave of non-negative, non-NaN doubles x, exactly:
+// such doubles order as their bit patterns, so the maximum is the largest
+// high word, then the largest low word among the lanes that hold it (32-bit
+// integer steps instead of double ones).
 __device__ inline double wave_max_nonneg(double x) {
-  x = dpp_max_step<0x111, 0xf>(x);  // row_shr:1
-  x = dpp_max_step<0x112, 0xf>(x);  // row_shr:2
-  x = dpp_max_step<0x114, 0xf>(x);  // row_shr:4
-  x = dpp_max_step<0x118, 0xf>(x);  // row_shr:8
-  x = dpp_max_step<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
-  x = dpp_max_step<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
-  return readlane_d(x, 63);
+  const uint64_t bits = (uint64_t)__double_as_longlong(x);
+  const uint32_t hi = (uint32_t)(bits >> 32), lo = (uint32_t)bits;
+  const uint32_t hmax = wave_umax(hi);
+  const uint32_t lmax = wave_umax(hi == hmax ? lo : 0u);
+  return __longlong_as_double((int64_t)(((uint64_t)hmax << 32) | lmax));
 }
 
 // The same panel factorisation with the panel in registers: lane l holds
@@ -389,10 +397,12 @@ __device__ __attribute__((always_inline)) inline void panel_regs(
 // columns t_lo + w, t_lo + w + W, ... four at a time; U12 of a column is a
 // broadcast LDS read (its skipped steps hold zero).  Rows past nrows and
 // columns past t_hi read the last valid row or column instead (every load is
-// unconditional) and store nothing.
+// unconditional) and store nothing.  With s_dst the results go to the panel
+// buffer s_dst (column tcol, panel row = row - (j0 + kPanel)) instead of the
+// band.
 __device__ __attribute__((always_inline)) inline void lu_rank_update(
     double* ab, int32_t ldab, int32_t KV, const double* s_pan, const double* s_u12, int32_t prmax, int32_t ntmax,
-    int32_t j0, int32_t nrows, int32_t t_lo, int32_t t_hi, int w, int W, int lane) {
+    int32_t j0, int32_t nrows, int32_t t_lo, int32_t t_hi, int w, int W, int lane, double* s_dst) {
   if (nrows <= 0 || t_lo >= t_hi) return;
   const int32_t c0 = j0 + kPanel;  // first trailing column (and first row below the panel)
   for (int32_t rc0 = 0; rc0 < nrows; rc0 += 3 * 64) {
@@ -430,7 +440,10 @@ __device__ __attribute__((always_inline)) inline void lu_rank_update(
           double x = a[bq][k];
 #pragma unroll
           for (int c = 0; c < kPanel; ++c) x -= L[k][c] * u[c];
-          if (cv && rv[k]) col[ro[k]] = x;
+          if (cv && rv[k]) {
+            if (s_dst) s_dst[tc[bq] * prmax + ro[k]] = x;
+            else col[ro[k]] = x;
+          }
         }
       }
     }
@@ -438,14 +451,18 @@ __device__ __attribute__((always_inline)) inline void lu_rank_update(
 }
 
 // Lookahead: panel k+1 is factored by wave 0 while the other waves apply
-// panel k's rank-nb update to the columns after panel k+1.  Per panel k:
+// panel k's rank-kPanel update to the columns after panel k+1 and store
+// panel k-1.  Per panel k:
 //   (1) all threads: interchanges and unit lower solve of every trailing
 //       column (U12 of the panel);
-//   (2) all waves: the rank-nb update of the next panel's columns;
-//   (3) the previous panel's multipliers back to band order and to memory,
-//       then panel k+1 loaded (buffers alternate between panels);
-//   (4) wave 0 factors panel k+1; waves 1.. update the remaining columns.
-// Every entry receives the same operations in the same order as without
+//   (2) all waves: the rank-kPanel update of the next panel's columns,
+//       written to its LDS buffer, and its other entries from memory;
+//   (3) wave 0 factors panel k+1; waves 1.. update the remaining columns and
+//       return panel k-1 to memory with its multipliers in band order.
+// Three panel buffers rotate (panel k+1 factored, k applied, k-1 stored).
+// A panel's columns stay in LDS from the update that forms them until they
+// are stored, and no other step reads them from memory in between.  Every
+// entry receives the same operations in the same order as without
 // lookahead, so pivots and factors are unchanged bit for bit.
 template <int NS>
 __global__ void __launch_bounds__(kLuThreads)
@@ -453,10 +470,10 @@ k_band_lu_blocked(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, c
                   int32_t* __restrict__ info, const double* __restrict__ colnorm_all, double tau, int32_t prmax,
                   int32_t ntmax) {
   extern __shared__ double s_dyn[];
-  // buffer b: panel column c at s_pan[b] + c * prmax, U12 row c at s_u12[b] + c * ntmax
-  double* const s_pan0 = s_dyn;
-  double* const s_u120 = s_dyn + 2 * kPanel * prmax;
-  __shared__ int32_t s_pv[2][kPanel], s_juc[2][kPanel], s_ok[2][kPanel];
+  // panel buffer b: column c at s_dyn + (b * kPanel + c) * prmax; U12 row c
+  // at s_u12 + c * ntmax
+  double* const s_u12 = s_dyn + 3 * kPanel * prmax;
+  __shared__ int32_t s_pv[3][kPanel], s_juc[3][kPanel], s_ok[3][kPanel];
   __shared__ int32_t s_ju, s_info;
   const int sub = blockIdx.x;
   const SubInfo q = subs[sub];
@@ -468,38 +485,36 @@ k_band_lu_blocked(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, c
   if (n == 0) return;  // an empty interior (info stays 0)
   // entry (r, c) of the block lives at ab[c * ldab + KV + r - c] for -KV <= r - c <= KL
   auto at = [&](int32_t r, int32_t c) -> double& { return ab[(int64_t)c * ldab + KV + r - c]; };
-  auto pan = [&](int b) { return s_pan0 + b * kPanel * prmax; };
-  auto u12 = [&](int b) { return s_u120 + b * kPanel * ntmax; };
-  auto load_panel = [&](int b, int32_t j0) {
-    constexpr int32_t nb = kPanel;
-    const int32_t prows = min(KL + nb, n - j0);
+  auto pan = [&](int b) { return s_dyn + b * kPanel * prmax; };
+  // entries (c, rr) of panel j0 from memory, except those with c < c_upd and
+  // rr < r_upd (written by the update), by threads t0, t0 + nth, ...
+  auto load_panel = [&](int b, int32_t j0, int32_t c_upd, int32_t r_upd, int t0, int nth) {
+    const int32_t prows = min(KL + kPanel, n - j0);
     double* P = pan(b);
-    for (int32_t e = tid; e < nb * prows; e += blockDim.x) {
+    for (int32_t e = t0; e < kPanel * prows; e += nth) {
       const int32_t c = e / prows, rr = e % prows, d = rr - c;
+      if (c < c_upd && rr < r_upd) continue;
       P[c * prmax + rr] = (d <= KL && d >= -KV) ? at(j0 + rr, j0 + c) : 0.0;
     }
   };
-  // multipliers of panel j0 (buffer b) back to band storage order (the later
-  // interchanges of the same panel undone), then the panel to memory
-  auto store_panel = [&](int b, int32_t j0) {
-    constexpr int32_t nb = kPanel;
-    const int32_t prows = min(KL + nb, n - j0);
-    double* P = pan(b);
-    if (tid < nb) {
-      double* pc = P + tid * prmax;
-      for (int32_t c2 = nb - 1; c2 > tid; --c2) {
+  // panel j0 (buffer b) to memory, its multipliers in band storage order: the
+  // panel's later interchanges undone, each entry's row traced through them
+  // (the undo swaps, for c2 from the last column down to c + 1, rows c2 and
+  // c2 + p_c2 of column c), by threads t0, t0 + nth, ...
+  auto store_panel = [&](int b, int32_t j0, int t0, int nth) {
+    const int32_t prows = min(KL + kPanel, n - j0);
+    const double* P = pan(b);
+    for (int32_t e = t0; e < kPanel * prows; e += nth) {
+      const int32_t c = e / prows, rr = e % prows;
+      int32_t pos = rr;
+      for (int32_t c2 = kPanel - 1; c2 > c; --c2) {
         const int32_t p2 = s_ok[b][c2] ? s_pv[b][c2] : 0;
-        if (p2 != 0) {
-          const double x = pc[c2];
-          pc[c2] = pc[c2 + p2];
-          pc[c2 + p2] = x;
-        }
+        if (p2 == 0) continue;
+        if (pos == c2) pos = c2 + p2;
+        else if (pos == c2 + p2) pos = c2;
       }
-    }
-    __syncthreads();
-    for (int32_t e = tid; e < nb * prows; e += blockDim.x) {
-      const int32_t c = e / prows, rr = e % prows, d = rr - c;
-      if (d <= KL && d >= -KV) at(j0 + rr, j0 + c) = P[c * prmax + rr];
+      const int32_t d = pos - c;
+      if (d <= KL && d >= -KV) at(j0 + pos, j0 + c) = P[c * prmax + rr];
     }
   };
   if (tid == 0) {
@@ -507,20 +522,19 @@ k_band_lu_blocked(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, c
     s_info = 0;
   }
   // panel 0
-  load_panel(0, 0);
+  load_panel(0, 0, 0, 0, tid, blockDim.x);
   __syncthreads();
   if (wave == 0)
     panel_regs<NS>(pan(0), prmax, min(KL + kPanel, n), 0, n, KL, KU, lane, tau, cn, ipiv, s_pv[0], s_ok[0], s_juc[0],
                    s_ju, s_info);
   __syncthreads();
   for (int32_t k = 0;; ++k) {
-    const int b = k & 1;
-    const int32_t j0 = k * kPanel;
-    if (j0 >= n) break;
-    constexpr int32_t nb = kPanel;  // n is a multiple of kPanel
+    const int b = k % 3, bn = (k + 1) % 3, bp = (k + 2) % 3;  // panels k, k+1, k-1
+    const int32_t j0 = k * kPanel;  // < n: n is a multiple of kPanel
+    constexpr int32_t nb = kPanel;
     const int32_t ju = s_ju, nt = ju - (j0 + nb) + 1;
     const double* P = pan(b);
-    double* U = u12(b);
+    double* U = s_u12;
     // ---- (1) trailing columns j0+nb .. ju: interchanges, then the panel rows
     // (unit lower triangular solve), in registers, one column per thread
     for (int32_t tcol = tid; tcol < nt; tcol += blockDim.x) {
@@ -568,38 +582,32 @@ k_band_lu_blocked(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, c
         if (jc <= s_juc[b][c]) at(j0 + c, jc) = v[c];
     }
     __syncthreads();
-    // ---- (2) rank-nb update of the next panel's columns
     const int32_t rmax = min(j0 + nb - 1 + KL, n - 1), nrows = rmax - (j0 + nb) + 1;
     const int32_t jn = j0 + nb;
     const bool next = jn < n;
     const int32_t nlook = next ? min(kPanel, max(nt, 0)) : 0;
-    if (nlook > 0) {
-      lu_rank_update(ab, ldab, KV, P, U, prmax, ntmax, j0, nrows, 0, nlook, wave, nwaves, lane);
-      __syncthreads();
-    }
-    // ---- (3) the previous panel to memory, the next panel in
-    if (k > 0) {
-      store_panel(1 - b, j0 - kPanel);
-      __syncthreads();
-    }
+    // ---- (2) the next panel into its buffer: the update of its first nlook
+    // columns (rows below this panel), everything else from memory
     if (next) {
-      load_panel(1 - b, jn);
+      lu_rank_update(ab, ldab, KV, P, U, prmax, ntmax, j0, nrows, 0, nlook, wave, nwaves, lane, pan(bn));
+      load_panel(bn, jn, nlook, max(nrows, 0), tid, blockDim.x);
       __syncthreads();
     }
-    // ---- (4) wave 0: factor the next panel; the other waves: the rest of
-    // this panel's update
+    // ---- (3) wave 0: factor the next panel; the other waves: the rest of
+    // this panel's update, then the previous panel to memory
     if (wave == 0) {
       if (next)
-        panel_regs<NS>(pan(1 - b), prmax, min(KL + kPanel, n - jn), jn, n, KL, KU, lane, tau, cn, ipiv, s_pv[1 - b],
-                       s_ok[1 - b], s_juc[1 - b], s_ju, s_info);
+        panel_regs<NS>(pan(bn), prmax, min(KL + kPanel, n - jn), jn, n, KL, KU, lane, tau, cn, ipiv, s_pv[bn],
+                       s_ok[bn], s_juc[bn], s_ju, s_info);
     } else {
-      lu_rank_update(ab, ldab, KV, P, U, prmax, ntmax, j0, nrows, nlook, max(nt, 0), wave - 1, nwaves - 1, lane);
+      lu_rank_update(ab, ldab, KV, P, U, prmax, ntmax, j0, nrows, nlook, max(nt, 0), wave - 1, nwaves - 1, lane,
+                     nullptr);
+      if (k > 0) store_panel(bp, j0 - kPanel, tid - 64, (int)blockDim.x - 64);
     }
     __syncthreads();
     if (!next) {
-      // the last panel: no panel after it to overlap with
-      store_panel(b, j0);
-      __syncthreads();
+      // the last panel
+      store_panel(b, j0, tid, blockDim.x);
       break;
     }
   }
@@ -756,6 +764,134 @@ k_convert_lower(const double* __restrict__ ab_all, const int32_t* __restrict__ i
   if (bad) atomicMax(info, 2);
 }
 
+// The same conversion in two launches.  k_convert_lower_prep (one
+// workgroup per block): the multipliers with the block's later swaps, each
+// band entry's row traced through those swaps (a permutation of its column,
+// so the entries land where the swaps in order would put them), and the
+// window indices permuted in LDS.  k_convert_lower_slab (grid: slabs x
+// blocks): columns c0 .. c0+sw-1 of inv(L11) in LDS (column c receives the
+// elimination steps i >= c only, row r the multiplier Lw(r, i) of column i,
+// read into LDS one step ahead), then the rows below as dot products over
+// k = c .. nbL-1 in increasing k.  Every element receives the operations of
+// k_convert_lower in the same order, so the result is the same bit for bit.
+__global__ void __launch_bounds__(kSetupThreads)
+k_convert_lower_prep(const double* __restrict__ ab_all, const int32_t* __restrict__ ipiv_all,
+                     const SubInfo* __restrict__ subs, const LBlk* __restrict__ lb, double* __restrict__ work_all,
+                     int32_t* __restrict__ lperm_all) {
+  extern __shared__ int32_t s_i[];  // piv[nbL], idx[W]
+  const LBlk B = lb[blockIdx.x];
+  const SubInfo q = subs[B.sub];
+  const int32_t nbL = q.nbl, KL = q.kl, ldab = q.ldab, KV = q.kl + q.ku;
+  const int32_t c0 = B.idx * nbL, W = nbL + KL;
+  const double* ab = ab_all + q.band_off;
+  const int32_t* ipiv = ipiv_all + q.vec_off;
+  double* Lw = work_all + B.woff;
+  int32_t* piv = s_i;
+  int32_t* idx = s_i + nbL;
+  const int tid = threadIdx.x;
+  for (int32_t s = tid; s < nbL; s += blockDim.x) piv[s] = ipiv[c0 + s] - c0;
+  for (int64_t t = tid; t < (int64_t)W * nbL; t += blockDim.x) Lw[t] = 0.0;
+  __syncthreads();
+  if (tid == 0) {
+    for (int32_t r = 0; r < W; ++r) idx[r] = r;
+    for (int32_t s = 0; s < nbL; ++s) {
+      const int32_t p = piv[s], a = idx[s];
+      idx[s] = idx[p];
+      idx[p] = a;
+    }
+  }
+  // band entries (c + i, c), 1 <= i <= KL, to their rows after the swaps
+  // s = c+1 .. nbL-1
+  for (int64_t t = tid; t < (int64_t)KL * nbL; t += blockDim.x) {
+    const int32_t c = (int32_t)(t / KL), i = 1 + (int32_t)(t % KL);
+    int32_t pos = c + i;
+    for (int32_t s = c + 1; s < nbL; ++s) {
+      const int32_t p = piv[s];
+      if (p == s) continue;
+      if (pos == s) pos = p;
+      else if (pos == p) pos = s;
+    }
+    Lw[(int64_t)c * W + pos] = ab[(int64_t)(c0 + c) * ldab + KV + i];
+  }
+  __syncthreads();
+  int32_t* op = lperm_all + B.poff;
+  for (int32_t r = tid; r < W; r += blockDim.x) op[r] = idx[r];
+}
+
+constexpr int kLSlabThreads = 256;
+template <class T>
+__global__ void __launch_bounds__(kLSlabThreads)
+k_convert_lower_slab(const SubInfo* __restrict__ subs, const LBlk* __restrict__ lb, const double* __restrict__ work_all,
+                     int32_t slab, T* __restrict__ lmat_all, int32_t* __restrict__ info) {
+  extern __shared__ double s_x[];
+  const LBlk B = lb[blockIdx.y];
+  const SubInfo q = subs[B.sub];
+  const int32_t nbL = q.nbl, KL = q.kl, W = nbL + KL;
+  const int32_t a0 = blockIdx.x * slab;
+  if (a0 >= nbL) return;
+  const int32_t sw = min(slab, nbL - a0), ldx = nbL + 1;
+  const double* Lw = work_all + B.woff;  // W x nbL, column-major
+  double* X = s_x;                        // slab column cc at X + cc * ldx (rows 0 .. nbL-1)
+  double* lcol = s_x + (int64_t)slab * ldx;  // two buffers of nbL: Lw(0 .. nbL-1, i)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = kLSlabThreads / 64;
+  for (int32_t e = tid; e < sw * nbL; e += kLSlabThreads) {
+    const int32_t cc = e / nbL, r = e % nbL;
+    X[cc * ldx + r] = r == a0 + cc ? 1.0 : 0.0;
+  }
+  auto put = [&](int32_t i) {
+    if (i > nbL - 2) return;
+    double* buf = lcol + (i & 1) * nbL;
+    for (int32_t r = tid; r < nbL; r += kLSlabThreads) buf[r] = r > i ? Lw[(int64_t)i * W + r] : 0.0;
+  };
+  put(a0);
+  __syncthreads();
+  // forward elimination: rows r > i of the slab columns c <= i
+  for (int32_t i = a0; i < nbL - 1; ++i) {
+    const double* lc = lcol + (i & 1) * nbL;
+    for (int32_t r = i + 1 + lane; r < nbL; r += 64) {
+      const double l = lc[r];
+      for (int32_t cc = wave; cc < sw; cc += nw)
+        if (a0 + cc <= i) X[cc * ldx + r] -= l * X[cc * ldx + i];
+    }
+    put(i + 1);
+    __syncthreads();
+  }
+  // rows below: sum over k = c .. nbL-1 of Lw(r, k) X(k, c), in increasing k
+  T* lm = lmat_all + B.moff;
+  bool bad = false;
+  constexpr int kCols = 8;  // slab columns per wave at a time
+  for (int32_t cb = wave * kCols; cb < sw; cb += nw * kCols) {
+    for (int32_t rb = nbL; rb < W; rb += 64) {
+      const int32_t r = rb + lane;
+      const int32_t rr = min(r, W - 1);
+      double acc[kCols];
+#pragma unroll
+      for (int j = 0; j < kCols; ++j) acc[j] = 0.0;
+      for (int32_t k = a0 + cb; k < nbL; ++k) {
+        const double l = Lw[(int64_t)k * W + rr];
+#pragma unroll
+        for (int j = 0; j < kCols; ++j)
+          if (cb + j < sw && a0 + cb + j <= k) acc[j] += l * X[(cb + j) * ldx + k];
+      }
+      if (r < W)
+#pragma unroll
+        for (int j = 0; j < kCols; ++j)
+          if (cb + j < sw) {
+            const T st = to_store<T>(acc[j]);
+            if (!isfinite((double)st)) bad = true;
+            lm[(int64_t)(a0 + cb + j) * W + r] = st;
+          }
+    }
+  }
+  for (int32_t e = tid; e < sw * nbL; e += kLSlabThreads) {
+    const int32_t cc = e / nbL, r = e % nbL;
+    const T st = to_store<T>(X[cc * ldx + r]);
+    if (!isfinite((double)st)) bad = true;
+    lm[(int64_t)(a0 + cc) * W + r] = st;
+  }
+  if (bad) atomicMax(info, 2);
+}
+
 // ---------------------------------------------------------------------------
 // Upper sweep blocks (rows r0 = b*nbU .. r0+nbU-1, nbU >= KL+KU so that U is
 // block bidiagonal): inv(U_bb) (column-major) and U_{b,b+1} (column-major).
@@ -811,6 +947,101 @@ k_convert_upper(const double* __restrict__ ab_all, const SubInfo* __restrict__ s
     u12[t] = b;
   }
   // an inverse not finite in the storage type (overflow): reported as 2
+  if (bad) atomicMax(info, 2);
+}
+
+// The same inverse by slabs of columns (grid: slabs x blocks), the slab in
+// LDS.  Column c of inv(U_bb) receives steps i <= c only, and step i touches
+// rows i - KV .. i - 1 (U is banded), so a slab of columns c0 .. c0+sw-1
+// runs steps c0+sw-1 .. 0 on its own.  U's column i is read into LDS one
+// step ahead.  Wave w takes columns w, w + 4, ... of the slab, lane l rows
+// l, l + 64, ... of a step; every element receives the same operations in
+// the same order as in k_convert_upper (a zero U(r, i) skipped), so the
+// result is the same bit for bit.
+constexpr int kUSlabThreads = 256;
+template <class T>
+__global__ void __launch_bounds__(kUSlabThreads)
+k_convert_upper_slab(const double* __restrict__ ab_all, const SubInfo* __restrict__ subs,
+                     const UBlk* __restrict__ ub, int32_t slab, int32_t kv_max, T* __restrict__ uinv_all,
+                     T* __restrict__ u12_all, int32_t* __restrict__ info) {
+  extern __shared__ double s_x[];
+  const UBlk B = ub[blockIdx.y];
+  const SubInfo q = subs[B.sub];
+  const int32_t nbU = q.nbu, ldab = q.ldab, n = q.npad, KV = q.kl + q.ku;
+  const int32_t c0 = blockIdx.x * slab;
+  if (c0 >= nbU) return;
+  const int32_t sw = min(slab, nbU - c0), ldx = nbU + 1;
+  const int32_t r0 = B.idx * nbU;
+  const double* ab = ab_all + q.band_off;
+  double* X = s_x;                                  // column cc of the slab at X + cc * ldx
+  double* ucol = s_x + (int64_t)slab * ldx;         // two buffers of kv_max + 1: U(i - KV .. i, i)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = kUSlabThreads / 64;
+  auto U = [&](int32_t r, int32_t c) -> double {  // subdomain-local (r, c)
+    const int32_t d = c - r;
+    return (d >= 0 && d <= KV && c < n) ? ab[(int64_t)c * ldab + KV + r - c] : 0.0;
+  };
+  // buffer entry j of step i holds U(i - KV + j, i), j = 0 .. KV (the last
+  // is the diagonal)
+  auto fetch = [&](int32_t i, double (&v)[4]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int32_t j = tid + t * kUSlabThreads, r = i - KV + j;
+      v[t] = (i >= 0 && j <= KV && r >= 0) ? U(r0 + r, r0 + i) : 0.0;
+    }
+  };
+  auto put = [&](int32_t i, const double (&v)[4]) {
+    double* buf = ucol + (i & 1) * (kv_max + 1);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int32_t j = tid + t * kUSlabThreads;
+      if (j <= KV) buf[j] = v[t];
+    }
+  };
+  for (int32_t e = tid; e < sw * nbU; e += kUSlabThreads) {
+    const int32_t cc = e / nbU, r = e % nbU;
+    X[cc * ldx + r] = r == c0 + cc ? 1.0 : 0.0;
+  }
+  const int32_t itop = c0 + sw - 1;
+  {
+    double v[4];
+    fetch(itop, v);
+    put(itop, v);
+  }
+  __syncthreads();
+  for (int32_t i = itop; i >= 0; --i) {
+    const double* uc = ucol + (i & 1) * (kv_max + 1);  // uc[KV + r - i] = U(r, i)
+    double v[4];
+    fetch(i - 1, v);  // the next step's column, in flight during this one
+    const double d = uc[KV];
+    if (d == 0.0) {
+      if (tid == 0) atomicMax(info, 1);
+      return;
+    }
+    const double dinv = 1.0 / d;
+    if (tid < sw && c0 + tid >= i) X[tid * ldx + i] *= dinv;
+    __syncthreads();
+    const int32_t rlo = max(0, i - KV);
+    for (int32_t rb = rlo; rb < i; rb += 64) {
+      const int32_t r = rb + lane;
+      const double u = r < i ? uc[KV + r - i] : 0.0;
+      if (u != 0.0)
+        for (int32_t cc = wave; cc < sw; cc += nw)
+          if (c0 + cc >= i) X[cc * ldx + r] -= u * X[cc * ldx + i];
+    }
+    if (i > 0) put(i - 1, v);
+    __syncthreads();
+  }
+  T* ui = uinv_all + B.off;
+  T* u12 = u12_all + B.off;
+  bool bad = false;
+  for (int32_t e = tid; e < sw * nbU; e += kUSlabThreads) {
+    const int32_t cc = e / nbU, r = e % nbU, c = c0 + cc;
+    const int64_t t = (int64_t)c * nbU + r;
+    const T a = to_store<T>(X[cc * ldx + r]), b = to_store<T>(U(r0 + r, r0 + nbU + c));
+    if (!isfinite((double)a) || !isfinite((double)b)) bad = true;
+    ui[t] = a;
+    u12[t] = b;
+  }
   if (bad) atomicMax(info, 2);
 }
 
@@ -1201,7 +1432,7 @@ void launch_band_nnz(const double* ab, const SubInfo* subs, int32_t m, int32_t n
 template <int NS>
 void run_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, const double* colnorm,
                  double tau, int32_t prmax, int32_t ntmax, hipStream_t s) {
-  const size_t smem = sizeof(double) * (size_t)2 * kPanel * (prmax + ntmax);
+  const size_t smem = sizeof(double) * ((size_t)3 * kPanel * prmax + (size_t)kPanel * ntmax);
   static size_t raised = 64 * 1024;
   if (smem > raised) {
     ADDNS_HIP(hipFuncSetAttribute((const void*)k_band_lu_blocked<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1224,17 +1455,66 @@ void launch_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, i
     default: k_band_lu<<<m, kSetupThreads, 0, s>>>(ab, ipiv, subs, info, colnorm, tau); break;
   }
 }
+template <class T>
+void run_convert_lower_slab(const SubInfo* subs, const LBlk* lb, int32_t nblk, int32_t slab, int32_t nbl_max,
+                            const double* work, T* lmat, int32_t* info, hipStream_t s) {
+  const size_t smem = sizeof(double) * ((size_t)slab * (nbl_max + 1) + 2 * (size_t)nbl_max);
+  static size_t raised = 64 * 1024;
+  if (smem > raised) {
+    ADDNS_HIP(hipFuncSetAttribute((const void*)k_convert_lower_slab<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)smem));
+    raised = smem;
+  }
+  const dim3 grid((unsigned)((nbl_max + slab - 1) / slab), (unsigned)nblk);
+  k_convert_lower_slab<T><<<grid, kLSlabThreads, smem, s>>>(subs, lb, work, slab, lmat, info);
+}
 void launch_convert_lower(const double* ab, const int32_t* ipiv, const SubInfo* subs, const LBlk* lb, int32_t nblk,
-                          double* work, int32_t* lperm, void* lmat, int prec, int32_t* info, hipStream_t s) {
+                          double* work, int32_t* lperm, void* lmat, int prec, int32_t* info, int32_t nbl_max,
+                          int32_t kl_max, hipStream_t s) {
   if (nblk == 0) return;
+  // slabs of up to 32 columns within 96 KB of LDS
+  const int32_t slab = (int32_t)std::min<int64_t>(32, (96 * 1024 / 8 - 2 * (int64_t)nbl_max) / ((int64_t)nbl_max + 1));
+  const size_t prep_smem = sizeof(int32_t) * (2 * (size_t)nbl_max + kl_max);
+  if (slab >= 1 && prep_smem <= 64 * 1024) {
+    k_convert_lower_prep<<<nblk, kSetupThreads, prep_smem, s>>>(ab, ipiv, subs, lb, work, lperm);
+    if (prec == P64)
+      run_convert_lower_slab<double>(subs, lb, nblk, slab, nbl_max, work, (double*)lmat, info, s);
+    else
+      run_convert_lower_slab<float>(subs, lb, nblk, slab, nbl_max, work, (float*)lmat, info, s);
+    return;
+  }
   if (prec == P64)
     k_convert_lower<double><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, subs, lb, work, lperm, (double*)lmat, info);
   else
     k_convert_lower<float><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, subs, lb, work, lperm, (float*)lmat, info);
 }
+template <class T>
+void run_convert_upper_slab(const double* ab, const SubInfo* subs, const UBlk* ub, int32_t nblk, int32_t slab,
+                            int32_t nbu_max, int32_t kv_max, T* uinv, T* u12, int32_t* info, hipStream_t s) {
+  const size_t smem = sizeof(double) * ((size_t)slab * (nbu_max + 1) + 2 * (size_t)(kv_max + 1));
+  static size_t raised = 64 * 1024;
+  if (smem > raised) {
+    ADDNS_HIP(hipFuncSetAttribute((const void*)k_convert_upper_slab<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)smem));
+    raised = smem;
+  }
+  const dim3 grid((unsigned)((nbu_max + slab - 1) / slab), (unsigned)nblk);
+  k_convert_upper_slab<T><<<grid, kUSlabThreads, smem, s>>>(ab, subs, ub, slab, kv_max, uinv, u12, info);
+}
 void launch_convert_upper(const double* ab, const SubInfo* subs, const UBlk* ub, int32_t nblk, double* work,
-                          void* uinv, void* u12, int prec, int32_t* info, hipStream_t s) {
+                          void* uinv, void* u12, int prec, int32_t* info, int32_t nbu_max, int32_t kv_max,
+                          hipStream_t s) {
   if (nblk == 0) return;
+  // slabs of up to 32 columns within 96 KB of LDS; U's column fits the four
+  // values per thread of the step buffer when KV < 1024
+  const int32_t slab = (int32_t)std::min<int64_t>(32, (96 * 1024 / 8) / ((int64_t)nbu_max + 1));
+  if (slab >= 1 && kv_max < 4 * kUSlabThreads) {
+    if (prec == P64)
+      run_convert_upper_slab<double>(ab, subs, ub, nblk, slab, nbu_max, kv_max, (double*)uinv, (double*)u12, info, s);
+    else
+      run_convert_upper_slab<float>(ab, subs, ub, nblk, slab, nbu_max, kv_max, (float*)uinv, (float*)u12, info, s);
+    return;
+  }
   if (prec == P64)
     k_convert_upper<double><<<nblk, kSetupThreads, 0, s>>>(ab, subs, ub, work, (double*)uinv, (double*)u12, info);
   else

@@ -314,9 +314,11 @@ void launch_band_nnz(const double* ab, const SubInfo* subs, int32_t m, int32_t n
 // The conversions raise *info to 1 for a zero diagonal of U and to 2 for a
 // block not finite in the storage type.
 void launch_convert_lower(const double* ab, const int32_t* ipiv, const SubInfo* subs, const LBlk* lb, int32_t nblk,
-                          double* work, int32_t* lperm, void* lmat, int prec, int32_t* info, hipStream_t s);
+                          double* work, int32_t* lperm, void* lmat, int prec, int32_t* info, int32_t nbl_max,
+                          int32_t kl_max, hipStream_t s);
 void launch_convert_upper(const double* ab, const SubInfo* subs, const UBlk* ub, int32_t nblk, double* work,
-                          void* uinv, void* u12, int prec, int32_t* info, hipStream_t s);
+                          void* uinv, void* u12, int prec, int32_t* info, int32_t nbu_max, int32_t kv_max,
+                          hipStream_t s);
 void launch_dense_scatter(const int64_t* dst, const int32_t* src, const double* cpv, int64_t n, double* out,
                           hipStream_t s);
 void launch_schur_blocks(int32_t k, const int32_t* agg_s, const int32_t* agg_d, const int64_t* g_off,
