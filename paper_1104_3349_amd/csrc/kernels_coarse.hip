@@ -249,30 +249,34 @@ __global__ void k_gj_update(double* __restrict__ A, int32_t nb, int32_t nc, int3
   else a -= mcol[i] * (prow[j] * inv);
 }
 
-// The same Gauss-Jordan inversion for blocks of at most kGjFused columns,
-// every step in one workgroup per block with the block in LDS: the block's
-// largest |entry|, then per step k the pivot (first row of largest |A(i,k)|
-// among rows >= k, by one wave), the copies of pivot row and column, the
-// interchange and the update, and finally the column interchanges undone.
-// Each element receives the operations of k_gj_pivot, k_gj_update and
-// k_gj_colswap in the same order, so the inverse is the same bit for bit;
-// one launch instead of two per step.
-constexpr int kGjFused = 88;
+// The same Gauss-Jordan inversion with every step in one workgroup per
+// block (one launch instead of two per step): the block's largest |entry|,
+// then per step k the pivot (first row of largest |A(i,k)| among rows >= k,
+// by one wave), the copies of pivot row and column, the interchange and the
+// update, and finally the column interchanges undone.  Blocks of at most
+// kGjLds columns are worked in LDS, larger ones in place in memory.  Each
+// element receives the operations of k_gj_pivot, k_gj_update and
+// k_gj_colswap in the same order, so the inverse is the same bit for bit.
+constexpr int kGjLds = 88;
+constexpr int kGjFusedMax = 1024;
+template <bool LDS>
 __global__ void __launch_bounds__(1024) k_gj_fused(double* __restrict__ A, const int32_t* __restrict__ boff,
                                                    const int64_t* __restrict__ beoff, int32_t* __restrict__ perm,
                                                    int32_t* __restrict__ info) {
-  __shared__ double E[kGjFused * kGjFused];
-  __shared__ double prow[kGjFused], mcol[kGjFused];
+  __shared__ double s_E[LDS ? kGjLds * kGjLds : 1];
+  __shared__ double prow[kGjFusedMax], mcol[kGjFusedMax];
   __shared__ double red[16];
-  __shared__ int32_t s_p[kGjFused];
+  __shared__ int32_t s_p[kGjFusedMax];
   const int32_t b = blockIdx.x;
   const int32_t o = boff[b], n = boff[b + 1] - o;
   double* G = A + beoff[b];
+  double* E = LDS ? s_E : G;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (int)(blockDim.x >> 6);
   double m = 0.0;
   for (int32_t e = tid; e < n * n; e += blockDim.x) {
-    E[e] = G[e];
-    m = fmax(m, fabs(E[e]));
+    const double x = G[e];
+    if (LDS) E[e] = x;
+    m = fmax(m, fabs(x));
   }
   for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
   if (lane == 0) red[wave] = m;
@@ -343,8 +347,118 @@ __global__ void __launch_bounds__(1024) k_gj_fused(double* __restrict__ A, const
       }
     }
   }
+  if (LDS) {
+    __syncthreads();
+    for (int32_t e = tid; e < n * n; e += blockDim.x) G[e] = E[e];
+  }
+}
+
+// The same again with the block in registers: thread t holds column t % n,
+// rows t / n + R m (m < M) with R = 1024 / n row groups, for blocks with
+// n <= R M.  A step moves only column k, rows k and p and the pivot through
+// LDS, so the matrix is read from and written to memory once.  Same
+// operations on every element in the same order, so the same inverse bit
+// for bit.
+constexpr int kGjRegs = 26;
+template <int M>
+__global__ void __launch_bounds__(1024) k_gj_regs(double* __restrict__ A, const int32_t* __restrict__ boff,
+                                                  const int64_t* __restrict__ beoff, int32_t* __restrict__ perm,
+                                                  int32_t* __restrict__ info) {
+  __shared__ double colk[kGjFusedMax], rowp[kGjFusedMax], rowk[kGjFusedMax];
+  __shared__ double red[16];
+  __shared__ int32_t s_p[kGjFusedMax];
+  const int32_t b = blockIdx.x;
+  const int32_t o = boff[b], n = boff[b + 1] - o;
+  double* G = A + beoff[b];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (int)(blockDim.x >> 6);
+  const int32_t R = 1024 / n, j = tid % n, g = tid / n;
+  const bool jv = g < R;
+  double a[M];
+  double m = 0.0;
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    const int32_t i = g + R * q;
+    a[q] = (jv && i < n) ? G[i * n + j] : 0.0;
+    m = fmax(m, fabs(a[q]));
+  }
+  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if (lane == 0) red[wave] = m;
   __syncthreads();
-  for (int32_t e = tid; e < n * n; e += blockDim.x) G[e] = E[e];
+  double amax = 0.0;
+  for (int w = 0; w < nw; ++w) amax = fmax(amax, red[w]);
+  for (int32_t k = 0; k < n; ++k) {
+    if (jv && j == k)
+#pragma unroll
+      for (int q = 0; q < M; ++q)
+        if (g + R * q < n) colk[g + R * q] = a[q];
+    __syncthreads();
+    if (wave == 0) {
+      double best = -1.0;
+      int32_t bidx = n;
+      for (int32_t i = k + lane; i < n; i += 64) {
+        const double v = fabs(colk[i]);
+        if (v > best) {
+          best = v;
+          bidx = i;
+        }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double v2 = __shfl_xor(best, off);
+        const int32_t i2 = __shfl_xor(bidx, off);
+        if (v2 > best || (v2 == best && i2 < bidx)) {
+          best = v2;
+          bidx = i2;
+        }
+      }
+      if (lane == 0) {
+        s_p[k] = bidx;
+        perm[o + k] = bidx;
+        if (!(best > 1e-13 * amax) && info[0] == 0) info[0] = o + k + 1;
+      }
+    }
+    __syncthreads();
+    const int32_t p = s_p[k];
+    if (jv)
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        const int32_t i = g + R * q;
+        if (i == p) rowp[j] = a[q];
+        if (i == k) rowk[j] = a[q];
+      }
+    __syncthreads();
+    // mcol(i) = column k after the interchange, prow = row p before it
+    const double inv = 1.0 / rowp[k];
+    if (jv) {
+      const double pj = rowp[j], kj = rowk[j];
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        const int32_t i = g + R * q;
+        if (i >= n) continue;
+        const int32_t src = i == k ? p : (i == p ? k : i);
+        const double x = i == p ? kj : (i == k ? pj : a[q]);  // the interchange
+        if (i == k) a[q] = j == k ? inv : pj * inv;
+        else if (j == k) a[q] = -colk[src] * inv;
+        else a[q] = x - colk[src] * (pj * inv);
+      }
+    }
+    __syncthreads();
+  }
+  // column interchanges undone: column j ends where the swaps k = n-1 .. 0,
+  // applied in order, move it
+  if (jv) {
+    int32_t c = j;
+    for (int32_t k = n - 1; k >= 0; --k) {
+      const int32_t p = s_p[k];
+      if (p == k) continue;
+      if (c == k) c = p;
+      else if (c == p) c = k;
+    }
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      const int32_t i = g + R * q;
+      if (i < n) G[i * n + c] = a[q];
+    }
+  }
 }
 
 // Undo the row interchanges on the columns of each block's inverse: inv(A)
@@ -467,8 +581,16 @@ void launch_gj_invert(const addns_precond* pc, double* A, int32_t* perm, double*
   const int32_t* boff = pc->cz_boff.as<int32_t>();
   const int32_t* cblk = pc->cz_cblk.as<int32_t>();
   const int64_t* beoff = pc->cz_beoff.as<int64_t>();
-  if (cp.blk_max <= kGjFused) {
-    k_gj_fused<<<nb, 1024, 0, s>>>(A, boff, beoff, perm, info);
+  if (cp.blk_max <= kGjLds) {
+    k_gj_fused<true><<<nb, 1024, 0, s>>>(A, boff, beoff, perm, info);
+    return;
+  }
+  if (cp.blk_max <= 1024 && (1024 / cp.blk_max) * kGjRegs >= cp.blk_max) {
+    k_gj_regs<kGjRegs><<<nb, 1024, 0, s>>>(A, boff, beoff, perm, info);
+    return;
+  }
+  if (cp.blk_max <= kGjFusedMax) {
+    k_gj_fused<false><<<nb, 1024, 0, s>>>(A, boff, beoff, perm, info);
     return;
   }
   k_absmax<<<nb, 1024, 0, s>>>(A, boff, beoff, work);
