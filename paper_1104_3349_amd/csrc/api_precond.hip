@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -29,6 +30,23 @@ namespace {
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 int prec_bytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
+
+// A second stream per device for setup work that can run beside the
+// interior factorisation (default priority; created once, kept until the
+// process ends).
+hipStream_t side_stream() {
+  static std::mutex mu;
+  static std::map<int, hipStream_t>* streams = new std::map<int, hipStream_t>();
+  int dev = 0;
+  ADDNS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams->find(dev);
+  if (it != streams->end()) return it->second;
+  hipStream_t st;
+  ADDNS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  (*streams)[dev] = st;
+  return st;
+}
 
 void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipStream_t s, PlanCache* cache);
 
@@ -108,8 +126,20 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
   ADDNS_HIP(hipMemsetAsync(info.p, 0, sizeof(int32_t) * (m + 4), s));
   if (pl.KL + pl.KU > 1024 || pl.nbU > 1024)
     throw ArgError("interior bandwidth too large (the band LU and the sweep take KL + KU up to 1024)");
-  if (m > 0 && npad_total > 0) {
-    DevBuf ab, ipiv, bdst, bsrc, work;
+  // the point the interface setup may start from (the info reset and the
+  // permuted matrix done), before the interior work is queued
+  hipEvent_t ready;
+  ADDNS_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t e;
+    ~EvGuard() { (void)hipEventDestroy(e); }
+  } ready_guard{ready};
+  ADDNS_HIP(hipEventRecord(ready, s));
+  // device buffers of the interior factorisation: kept to the end of the
+  // setup, since its work runs while the interface is set up
+  DevBuf ab, ipiv, bdst, bsrc, work, colnorm, d_nnz;
+  const bool interior = m > 0 && npad_total > 0;
+  if (interior) {
     ab.alloc(sizeof(double) * pl.band_total);
     ADDNS_HIP(hipMemsetAsync(ab.p, 0, sizeof(double) * pl.band_total, s));
     ipiv.alloc(sizeof(int32_t) * npad_total);
@@ -117,7 +147,6 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
     bsrc.upload(pl.band_src, s);
     launch_scatter_band(bdst.as<int64_t>(), bsrc.as<int32_t>(), cpv, (int64_t)pl.band_dst.size(), ab.as<double>(), s);
     launch_band_pad_identity(pc->subs.as<SubInfo>(), m, ab.as<double>(), s);
-    DevBuf colnorm, nnz;
     colnorm.alloc(sizeof(double) * npad_total);
     int32_t npad_max = 0;
     for (const SubInfo& q : pl.subs) npad_max = std::max(npad_max, q.npad);
@@ -131,21 +160,10 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
     }
     launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), m, info.as<int32_t>(),
                    colnorm.as<double>(), o.ilu_tol, kl_max, kv_max, s);
-    nnz.alloc(sizeof(int64_t) * m);
+    d_nnz.alloc(sizeof(int64_t) * m);
     int32_t n_max = 0;
     for (const SubInfo& q : pl.subs) n_max = std::max(n_max, q.n);
-    launch_band_nnz(ab.as<double>(), pc->subs.as<SubInfo>(), m, n_max, nnz.as<int64_t>(), s);
-    std::vector<int32_t> h_info(m + 4);
-    std::vector<int64_t> h_nnz(m);
-    ADDNS_HIP(hipMemcpyAsync(h_info.data(), info.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
-    ADDNS_HIP(hipMemcpyAsync(h_nnz.data(), nnz.p, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s));
-    ADDNS_HIP(hipStreamSynchronize(s));
-    for (int32_t j = 0; j < m; ++j)
-      if (h_info[j] != 0)
-        throw SingularError("interior block " + std::to_string(j) + " has a zero pivot at column " +
-                            std::to_string(h_info[j] - 1));
-    pc->interior_nnz = 0;
-    for (int64_t c : h_nnz) pc->interior_nnz += c;
+    launch_band_nnz(ab.as<double>(), pc->subs.as<SubInfo>(), m, n_max, d_nnz.as<int64_t>(), s);
     pc->lperm.alloc(sizeof(int32_t) * pl.lperm_total);
     // the sweep's last row slot may read up to 64 * 5 rows past a block's
     // end; the zeroed tail keeps that overrun inside the allocation
@@ -156,6 +174,8 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
     for (DevBuf* d : {&pc->lmat, &pc->uinv, &pc->u12})
       ADDNS_HIP(hipMemsetAsync(static_cast<char*>(d->p) + d->bytes - tail, 0, tail, s));
     work.alloc(sizeof(double) * std::max(pl.lwork_total, pl.u_total));
+    // a zero pivot of the LU is reported below; the conversions of such
+    // factors run but are discarded
     int32_t nbl_max = 0;
     for (const SubInfo& q : pl.subs) nbl_max = std::max(nbl_max, q.nbl);
     launch_convert_lower(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), pc->lblks.as<LBlk>(), nL,
@@ -165,144 +185,171 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
     for (const SubInfo& q : pl.subs) nbu_max = std::max(nbu_max, q.nbu);
     launch_convert_upper(ab.as<double>(), pc->subs.as<SubInfo>(), pc->ublks.as<UBlk>(), nU, work.as<double>(),
                          pc->uinv.p, pc->u12.p, iprec, info.as<int32_t>() + m, nbu_max, kv_max, s);
-    ADDNS_HIP(hipMemcpyAsync(h_info.data(), info.as<int32_t>() + m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  }
+  // reads the interior's results once its work has finished
+  auto finish_interior = [&]() {
+    if (!interior) return;
+    std::vector<int32_t> h_info(m + 1);
+    std::vector<int64_t> h_nnz(m);
+    ADDNS_HIP(hipMemcpyAsync(h_info.data(), info.p, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToHost, s));
+    ADDNS_HIP(hipMemcpyAsync(h_nnz.data(), d_nnz.p, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s));
     ADDNS_HIP(hipStreamSynchronize(s));
-    if (h_info[0] == 1) throw SingularError("an interior U factor has a zero diagonal");
-    if (h_info[0] == 2)
+    for (int32_t j = 0; j < m; ++j)
+      if (h_info[j] != 0)
+        throw SingularError("interior block " + std::to_string(j) + " has a zero pivot at column " +
+                            std::to_string(h_info[j] - 1));
+    if (h_info[m] == 1) throw SingularError("an interior U factor has a zero diagonal");
+    if (h_info[m] == 2)
       throw SingularError("the interior block factors are not finite in the storage type (overflow of the "
                           "inverted diagonal blocks)");
-  }
+    pc->interior_nnz = 0;
+    for (int64_t c : h_nnz) pc->interior_nnz += c;
+  };
 
-  // -- interface: dense blocks, mini Schur complements, inverses
+  // -- interface: dense blocks, mini Schur complements, inverses.  Except
+  // for the exact block Jacobi form (which needs the interior factors) it
+  // runs on a second stream while the interior factorisation, which fills
+  // only one compute unit per subdomain, runs on the first.
   const int32_t k = pl.k;
-  pc->agg_off.upload(pl.agg_off, s);
-  pc->agg_s.upload(pl.agg_s, s);
-  pc->sinv_off.upload(pl.sinv_off, s);
   const int sprec = o.schur_prec == ADDNS_F64 ? P64 : (o.schur_prec == ADDNS_F32 ? P32 : P16S);
-  pc->schur_prec = sprec;
-  pc->interior_prec = iprec;
-  if (k > 0) {
-    int32_t smax = 0;
-    for (int32_t i = 0; i < k; ++i) smax = std::max(smax, pl.agg_s[i]);
-    if (smax > 1024) throw ArgError("aggregates larger than 1024 nodes are not supported");
-    if (o.overlap > 0 && smax > 128) throw ArgError("overlapped aggregates need aggregates of at most 128 nodes");
-    if (o.overlap > 0 && k > kMaxOverlapAggregates)
-      throw ArgError("overlapped aggregates: at most 12000 aggregates");
-    const int64_t dense_n = pl.g_total + pl.dd_total + pl.de_total + pl.df_total;
-    DevBuf dense, ddst, dsrc, agg_d, g_off, dd_off, de_off, df_off, work;
-    dense.alloc(sizeof(double) * dense_n);
-    ADDNS_HIP(hipMemsetAsync(dense.p, 0, sizeof(double) * dense_n, s));
-    ddst.upload(pl.dense_dst, s);
-    dsrc.upload(pl.dense_src, s);
-    launch_dense_scatter(ddst.as<int64_t>(), dsrc.as<int32_t>(), cpv, (int64_t)pl.dense_dst.size(), dense.as<double>(),
-                         s);
-    agg_d.upload(pl.agg_d, s);
-    g_off.upload(pl.g_off, s);
-    dd_off.upload(pl.dd_off, s);
-    de_off.upload(pl.de_off, s);
-    df_off.upload(pl.df_off, s);
-    double* G = dense.as<double>();
-    const int64_t nsmp = (int64_t)pl.smp_row.size();
-    pc->learned_count = nsmp;
-    if (o.schur == ADDNS_SCHUR_LEARNED) {
-      pc->smp_row.upload(pl.smp_row, s);
-      pc->smp_nb.upload(pl.smp_nb, s);
-      pc->smp_loc.upload(pl.smp_loc, s);
-    } else {  // keep G: learning targets are S_i - G_i of this (teacher) mode
-      pc->g_copy.alloc(sizeof(double) * pl.g_total);
-      ADDNS_HIP(hipMemcpyAsync(pc->g_copy.p, G, sizeof(double) * pl.g_total, hipMemcpyDeviceToDevice, s));
-    }
-    if (o.schur == ADDNS_SCHUR_LEARNED && nsmp > 0) {
-      // S_i ~ G_i + Delta_i: features of each separator velocity row, the
-      // network's corrections on G's stencil slots inside the aggregate
-      const int np = mlp_param_count();
-      DevBuf wts, img, X, Dl;
-      wts.alloc(sizeof(float) * np);
-      img.alloc(sizeof(float) * mlp_image_floats());
-      ADDNS_HIP(hipMemcpyAsync(wts.p, o.learned_model, sizeof(float) * np, hipMemcpyHostToDevice, s));
-      launch_mlp_image(wts.as<float>(), img.as<float>(), s);
-      X.alloc(sizeof(float) * 7 * nsmp);
-      Dl.alloc(sizeof(float) * 5 * nsmp);
-      launch_dtn_features(nsmp, pc->smp_row.as<int32_t>(), pc->smp_nb.as<int32_t>(), pc->cp_rowptr.as<int32_t>(),
-                          pc->cp_colidx.as<int32_t>(), cpv, pc->perm.as<int32_t>(), pc->R.as<double>(),
-                          X.as<float>(), s);
-      launch_mlp_forward(img.as<float>(), X.as<float>(), Dl.as<float>(), nsmp, o.learned_bf16 ? 1 : 0, s);
-      launch_dtn_correct(nsmp, pc->smp_loc.as<int64_t>(), Dl.as<float>(), G, s);
-      ADDNS_HIP(hipStreamSynchronize(s));
-    }
-    if (o.schur == ADDNS_SCHUR_EXACT_BJ) {
-      const int32_t np = (int32_t)pl.pair_sub.size();
-      DevBuf psub, pcol, poff, pptr, aggof, U, scratch;
-      psub.upload(pl.pair_sub, s);
-      pcol.upload(pl.pair_col, s);
-      poff.upload(pl.pair_off, s);
-      pptr.upload(pl.pcol_ptr, s);
-      aggof.upload(pl.agg_of, s);
-      U.alloc(sizeof(double) * std::max<int64_t>(pl.pair_total, 1));
-      scratch.alloc(sizeof(double) * std::max<int64_t>(pl.pair_total, 1));
-      launch_column_solves(pc, np, psub.as<int32_t>(), pcol.as<int32_t>(), poff.as<int64_t>(), scratch.as<double>(),
-                           U.as<double>(), s);
-      launch_exact_schur_update(pl.nsep, pptr.as<int32_t>(), psub.as<int32_t>(), poff.as<int64_t>(),
-                                pc->subs.as<SubInfo>(), aggof.as<int32_t>(), pc->agg_off.as<int32_t>(),
-                                g_off.as<int64_t>(), pc->f_rowptr.as<int32_t>(), pc->f_colidx.as<int32_t>(),
-                                pc->f_vals.as<double>(), U.as<double>(), G, s);
-      ADDNS_HIP(hipStreamSynchronize(s));
-    }
-    DevBuf agg_e;  // extended aggregate sizes (= agg_s without overlap)
-    agg_e.upload(pl.agg_e, s);
-    if (o.schur == ADDNS_SCHUR_MSCN || o.schur == ADDNS_SCHUR_MSCN_LITERAL || o.schur == ADDNS_SCHUR_MSCNR)
-      launch_schur_blocks(k, agg_e.as<int32_t>(), agg_d.as<int32_t>(), g_off.as<int64_t>(), dd_off.as<int64_t>(),
-                          de_off.as<int64_t>(), df_off.as<int64_t>(), G, G + pl.g_total,
-                          G + pl.g_total + pl.dd_total, G + pl.g_total + pl.dd_total + pl.de_total,
-                          info.as<int32_t>() + m + 1, o.schur == ADDNS_SCHUR_MSCNR ? 1 : 0, s);
-    pc->schur_S.alloc(sizeof(double) * pl.g_total);
-    ADDNS_HIP(hipMemcpyAsync(pc->schur_S.p, G, sizeof(double) * pl.g_total, hipMemcpyDeviceToDevice, s));
-    const int64_t a_total = pl.sinv_off[k];
-    pc->sinv.alloc((int64_t)prec_bytes(sprec) * a_total);
-    pc->sinv_scale.alloc(sizeof(float) * k);
-    work.alloc(sizeof(double) * 2 * a_total);
-    if (o.overlap == 0) {
-      launch_invert_dense(k, pc->agg_s.as<int32_t>(), g_off.as<int64_t>(), G, work.as<double>(),
-                          info.as<int32_t>() + m + 2, pc->sinv_off.as<int64_t>(), pc->sinv.p,
-                          pc->sinv_scale.as<float>(), sprec, s);
-    } else {
-      // Shat block lower bidiagonal: invert its diagonal blocks A_i, then
-      // form the chain matrices M_i from the FP64 inverses
-      DevBuf agg_w, l_off, A, L;
-      agg_w.upload(pl.agg_w, s);
-      l_off.upload(pl.l_off, s);
-      A.alloc(sizeof(double) * std::max<int64_t>(a_total, 1));
-      L.alloc(sizeof(double) * std::max<int64_t>(pl.l_off[k], 1));
-      launch_overlap_split(k, pc->agg_s.as<int32_t>(), agg_w.as<int32_t>(), g_off.as<int64_t>(),
-                           pc->sinv_off.as<int64_t>(), l_off.as<int64_t>(), G, A.as<double>(), L.as<double>(), s);
-      launch_invert_dense(k, pc->agg_s.as<int32_t>(), pc->sinv_off.as<int64_t>(), A.as<double>(), work.as<double>(),
-                          info.as<int32_t>() + m + 2, pc->sinv_off.as<int64_t>(), pc->sinv.p,
-                          pc->sinv_scale.as<float>(), sprec, s);
-      const int mdbl = sprec == P64 ? 1 : 0;
-      pc->ovl_moff.upload(pl.m_off, s);
-      pc->ovl_m.alloc((mdbl ? 8 : 4) * std::max<int64_t>(pl.m_off[k], 1));
-      launch_overlap_m(k, pc->agg_s.as<int32_t>(), agg_w.as<int32_t>(), pc->sinv_off.as<int64_t>(),
-                       l_off.as<int64_t>(), pc->ovl_moff.as<int64_t>(), pl.ovl_width, work.as<double>(),
-                       L.as<double>(), pc->ovl_m.p, mdbl, s);
-      pc->overlap_chain = k > 1 ? pl.ovl_width : 0;
-      // the chain in segments: responses of each segment's aggregates to the
-      // previous segment's last one
-      pc->ovl_seg = overlap_segment_length(k, o.overlap_segment);
-      if (pc->overlap_chain && (k + pc->ovl_seg - 1) / pc->ovl_seg > 1) {
-        pc->ovl_q.alloc((mdbl ? 8 : 4) * std::max<int64_t>(pl.m_off[k], 1));
-        launch_overlap_q(pc, s);
-      } else {
-        pc->ovl_q.reset();
+  auto interface_setup = [&](hipStream_t s) {
+    pc->agg_off.upload(pl.agg_off, s);
+    pc->agg_s.upload(pl.agg_s, s);
+    pc->sinv_off.upload(pl.sinv_off, s);
+    pc->schur_prec = sprec;
+    pc->interior_prec = iprec;
+    if (k > 0) {
+      int32_t smax = 0;
+      for (int32_t i = 0; i < k; ++i) smax = std::max(smax, pl.agg_s[i]);
+      if (smax > 1024) throw ArgError("aggregates larger than 1024 nodes are not supported");
+      if (o.overlap > 0 && smax > 128) throw ArgError("overlapped aggregates need aggregates of at most 128 nodes");
+      if (o.overlap > 0 && k > kMaxOverlapAggregates)
+        throw ArgError("overlapped aggregates: at most 12000 aggregates");
+      const int64_t dense_n = pl.g_total + pl.dd_total + pl.de_total + pl.df_total;
+      DevBuf dense, ddst, dsrc, agg_d, g_off, dd_off, de_off, df_off, work;
+      dense.alloc(sizeof(double) * dense_n);
+      ADDNS_HIP(hipMemsetAsync(dense.p, 0, sizeof(double) * dense_n, s));
+      ddst.upload(pl.dense_dst, s);
+      dsrc.upload(pl.dense_src, s);
+      launch_dense_scatter(ddst.as<int64_t>(), dsrc.as<int32_t>(), cpv, (int64_t)pl.dense_dst.size(), dense.as<double>(),
+                           s);
+      agg_d.upload(pl.agg_d, s);
+      g_off.upload(pl.g_off, s);
+      dd_off.upload(pl.dd_off, s);
+      de_off.upload(pl.de_off, s);
+      df_off.upload(pl.df_off, s);
+      double* G = dense.as<double>();
+      const int64_t nsmp = (int64_t)pl.smp_row.size();
+      pc->learned_count = nsmp;
+      if (o.schur == ADDNS_SCHUR_LEARNED) {
+        pc->smp_row.upload(pl.smp_row, s);
+        pc->smp_nb.upload(pl.smp_nb, s);
+        pc->smp_loc.upload(pl.smp_loc, s);
+      } else {  // keep G: learning targets are S_i - G_i of this (teacher) mode
+        pc->g_copy.alloc(sizeof(double) * pl.g_total);
+        ADDNS_HIP(hipMemcpyAsync(pc->g_copy.p, G, sizeof(double) * pl.g_total, hipMemcpyDeviceToDevice, s));
       }
+      if (o.schur == ADDNS_SCHUR_LEARNED && nsmp > 0) {
+        // S_i ~ G_i + Delta_i: features of each separator velocity row, the
+        // network's corrections on G's stencil slots inside the aggregate
+        const int np = mlp_param_count();
+        DevBuf wts, img, X, Dl;
+        wts.alloc(sizeof(float) * np);
+        img.alloc(sizeof(float) * mlp_image_floats());
+        ADDNS_HIP(hipMemcpyAsync(wts.p, o.learned_model, sizeof(float) * np, hipMemcpyHostToDevice, s));
+        launch_mlp_image(wts.as<float>(), img.as<float>(), s);
+        X.alloc(sizeof(float) * 7 * nsmp);
+        Dl.alloc(sizeof(float) * 5 * nsmp);
+        launch_dtn_features(nsmp, pc->smp_row.as<int32_t>(), pc->smp_nb.as<int32_t>(), pc->cp_rowptr.as<int32_t>(),
+                            pc->cp_colidx.as<int32_t>(), cpv, pc->perm.as<int32_t>(), pc->R.as<double>(),
+                            X.as<float>(), s);
+        launch_mlp_forward(img.as<float>(), X.as<float>(), Dl.as<float>(), nsmp, o.learned_bf16 ? 1 : 0, s);
+        launch_dtn_correct(nsmp, pc->smp_loc.as<int64_t>(), Dl.as<float>(), G, s);
+        ADDNS_HIP(hipStreamSynchronize(s));
+      }
+      if (o.schur == ADDNS_SCHUR_EXACT_BJ) {
+        const int32_t np = (int32_t)pl.pair_sub.size();
+        DevBuf psub, pcol, poff, pptr, aggof, U, scratch;
+        psub.upload(pl.pair_sub, s);
+        pcol.upload(pl.pair_col, s);
+        poff.upload(pl.pair_off, s);
+        pptr.upload(pl.pcol_ptr, s);
+        aggof.upload(pl.agg_of, s);
+        U.alloc(sizeof(double) * std::max<int64_t>(pl.pair_total, 1));
+        scratch.alloc(sizeof(double) * std::max<int64_t>(pl.pair_total, 1));
+        launch_column_solves(pc, np, psub.as<int32_t>(), pcol.as<int32_t>(), poff.as<int64_t>(), scratch.as<double>(),
+                             U.as<double>(), s);
+        launch_exact_schur_update(pl.nsep, pptr.as<int32_t>(), psub.as<int32_t>(), poff.as<int64_t>(),
+                                  pc->subs.as<SubInfo>(), aggof.as<int32_t>(), pc->agg_off.as<int32_t>(),
+                                  g_off.as<int64_t>(), pc->f_rowptr.as<int32_t>(), pc->f_colidx.as<int32_t>(),
+                                  pc->f_vals.as<double>(), U.as<double>(), G, s);
+        ADDNS_HIP(hipStreamSynchronize(s));
+      }
+      DevBuf agg_e;  // extended aggregate sizes (= agg_s without overlap)
+      agg_e.upload(pl.agg_e, s);
+      if (o.schur == ADDNS_SCHUR_MSCN || o.schur == ADDNS_SCHUR_MSCN_LITERAL || o.schur == ADDNS_SCHUR_MSCNR)
+        launch_schur_blocks(k, agg_e.as<int32_t>(), agg_d.as<int32_t>(), g_off.as<int64_t>(), dd_off.as<int64_t>(),
+                            de_off.as<int64_t>(), df_off.as<int64_t>(), G, G + pl.g_total,
+                            G + pl.g_total + pl.dd_total, G + pl.g_total + pl.dd_total + pl.de_total,
+                            info.as<int32_t>() + m + 1, o.schur == ADDNS_SCHUR_MSCNR ? 1 : 0, s);
+      pc->schur_S.alloc(sizeof(double) * pl.g_total);
+      ADDNS_HIP(hipMemcpyAsync(pc->schur_S.p, G, sizeof(double) * pl.g_total, hipMemcpyDeviceToDevice, s));
+      const int64_t a_total = pl.sinv_off[k];
+      pc->sinv.alloc((int64_t)prec_bytes(sprec) * a_total);
+      pc->sinv_scale.alloc(sizeof(float) * k);
+      work.alloc(sizeof(double) * 2 * a_total);
+      if (o.overlap == 0) {
+        launch_invert_dense(k, pc->agg_s.as<int32_t>(), g_off.as<int64_t>(), G, work.as<double>(),
+                            info.as<int32_t>() + m + 2, pc->sinv_off.as<int64_t>(), pc->sinv.p,
+                            pc->sinv_scale.as<float>(), sprec, s);
+      } else {
+        // Shat block lower bidiagonal: invert its diagonal blocks A_i, then
+        // form the chain matrices M_i from the FP64 inverses
+        DevBuf agg_w, l_off, A, L;
+        agg_w.upload(pl.agg_w, s);
+        l_off.upload(pl.l_off, s);
+        A.alloc(sizeof(double) * std::max<int64_t>(a_total, 1));
+        L.alloc(sizeof(double) * std::max<int64_t>(pl.l_off[k], 1));
+        launch_overlap_split(k, pc->agg_s.as<int32_t>(), agg_w.as<int32_t>(), g_off.as<int64_t>(),
+                             pc->sinv_off.as<int64_t>(), l_off.as<int64_t>(), G, A.as<double>(), L.as<double>(), s);
+        launch_invert_dense(k, pc->agg_s.as<int32_t>(), pc->sinv_off.as<int64_t>(), A.as<double>(), work.as<double>(),
+                            info.as<int32_t>() + m + 2, pc->sinv_off.as<int64_t>(), pc->sinv.p,
+                            pc->sinv_scale.as<float>(), sprec, s);
+        const int mdbl = sprec == P64 ? 1 : 0;
+        pc->ovl_moff.upload(pl.m_off, s);
+        pc->ovl_m.alloc((mdbl ? 8 : 4) * std::max<int64_t>(pl.m_off[k], 1));
+        launch_overlap_m(k, pc->agg_s.as<int32_t>(), agg_w.as<int32_t>(), pc->sinv_off.as<int64_t>(),
+                         l_off.as<int64_t>(), pc->ovl_moff.as<int64_t>(), pl.ovl_width, work.as<double>(),
+                         L.as<double>(), pc->ovl_m.p, mdbl, s);
+        pc->overlap_chain = k > 1 ? pl.ovl_width : 0;
+        // the chain in segments: responses of each segment's aggregates to the
+        // previous segment's last one
+        pc->ovl_seg = overlap_segment_length(k, o.overlap_segment);
+        if (pc->overlap_chain && (k + pc->ovl_seg - 1) / pc->ovl_seg > 1) {
+          pc->ovl_q.alloc((mdbl ? 8 : 4) * std::max<int64_t>(pl.m_off[k], 1));
+          launch_overlap_q(pc, s);
+        } else {
+          pc->ovl_q.reset();
+        }
+        ADDNS_HIP(hipStreamSynchronize(s));
+      }
+      int32_t h2[2];
+      ADDNS_HIP(hipMemcpyAsync(h2, info.as<int32_t>() + m + 1, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
       ADDNS_HIP(hipStreamSynchronize(s));
+      if (h2[0]) throw SingularError("a D-range block D_{r_i} is singular");
+      if (h2[1]) throw SingularError("an interface block S_i is singular");
     }
-    int32_t h2[2];
-    ADDNS_HIP(hipMemcpyAsync(h2, info.as<int32_t>() + m + 1, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
     ADDNS_HIP(hipStreamSynchronize(s));
-    if (h2[0]) throw SingularError("a D-range block D_{r_i} is singular");
-    if (h2[1]) throw SingularError("an interface block S_i is singular");
+  };
+  if (o.schur == ADDNS_SCHUR_EXACT_BJ) {
+    finish_interior();
+    interface_setup(s);
+  } else {
+    hipStream_t s2 = side_stream();
+    ADDNS_HIP(hipStreamWaitEvent(s2, ready, 0));
+    interface_setup(s2);
+    finish_interior();
   }
-  ADDNS_HIP(hipStreamSynchronize(s));
 
   // -- coarse-grid correction of the interface solve (section 6)
   pc->coarse_nc = 0;

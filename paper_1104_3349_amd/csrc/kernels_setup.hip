@@ -205,10 +205,11 @@ k_band_lu(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const Sub
 // ---------------------------------------------------------------------------
 constexpr int kPanel = 8;
 static_assert(kNpadMultiple % kPanel == 0, "panels must tile every padded block");
-// Threads of the blocked band LU: 8 waves leave each lane the registers that
-// the lookahead needs (the panel in wave 0's registers next to the update
-// tiles of the others) without spilling.
-constexpr int kLuThreads = 512;
+// Threads of the blocked band LU: 12 waves (three a SIMD) leave each lane
+// the registers that the lookahead needs (the panel in wave 0's registers
+// next to the update tiles of the others) without spilling, and give the
+// trailing update 11 waves.
+constexpr int kLuThreads = 768;
 
 __device__ inline double readlane_d(double x, int32_t l) {
   const int64_t bits = __double_as_longlong(x);
