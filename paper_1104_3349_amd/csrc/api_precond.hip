@@ -31,20 +31,20 @@ hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 int prec_bytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
 
-// A second stream per device for setup work that can run beside the
-// interior factorisation (default priority; created once, kept until the
-// process ends).
-hipStream_t side_stream() {
+// Extra streams per device (index idx) for setup work that can run beside
+// the interior factorisation (default priority; created once, kept until
+// the process ends).
+hipStream_t side_stream(int idx) {
   static std::mutex mu;
-  static std::map<int, hipStream_t>* streams = new std::map<int, hipStream_t>();
+  static std::map<std::pair<int, int>, hipStream_t>* streams = new std::map<std::pair<int, int>, hipStream_t>();
   int dev = 0;
   ADDNS_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(mu);
-  auto it = streams->find(dev);
+  auto it = streams->find({dev, idx});
   if (it != streams->end()) return it->second;
   hipStream_t st;
   ADDNS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-  (*streams)[dev] = st;
+  (*streams)[{dev, idx}] = st;
   return st;
 }
 
@@ -151,19 +151,15 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
     int32_t npad_max = 0;
     for (const SubInfo& q : pl.subs) npad_max = std::max(npad_max, q.npad);
     launch_band_colnorm(ab.as<double>(), pc->subs.as<SubInfo>(), m, npad_max, colnorm.as<double>(), s);
-    int32_t kl_max = 0, kv_max = 0;
+    int32_t kl_max = 0, kv_max = 0, nbl_max = 0, nbu_max = 0;
     for (const SubInfo& q : pl.subs) {
       // the blocked band LU factors whole panels
       if (q.npad % kNpadMultiple != 0) throw std::logic_error("padded interior size is not a multiple of 16");
       kl_max = std::max(kl_max, q.kl);
       kv_max = std::max(kv_max, q.kl + q.ku);
+      nbl_max = std::max(nbl_max, q.nbl);
+      nbu_max = std::max(nbu_max, q.nbu);
     }
-    launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), m, info.as<int32_t>(),
-                   colnorm.as<double>(), o.ilu_tol, kl_max, kv_max, s);
-    d_nnz.alloc(sizeof(int64_t) * m);
-    int32_t n_max = 0;
-    for (const SubInfo& q : pl.subs) n_max = std::max(n_max, q.n);
-    launch_band_nnz(ab.as<double>(), pc->subs.as<SubInfo>(), m, n_max, d_nnz.as<int64_t>(), s);
     pc->lperm.alloc(sizeof(int32_t) * pl.lperm_total);
     // the sweep's last row slot may read up to 64 * 5 rows past a block's
     // end; the zeroed tail keeps that overrun inside the allocation
@@ -174,17 +170,79 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
     for (DevBuf* d : {&pc->lmat, &pc->uinv, &pc->u12})
       ADDNS_HIP(hipMemsetAsync(static_cast<char*>(d->p) + d->bytes - tail, 0, tail, s));
     work.alloc(sizeof(double) * std::max(pl.lwork_total, pl.u_total));
-    // a zero pivot of the LU is reported below; the conversions of such
-    // factors run but are discarded
-    int32_t nbl_max = 0;
-    for (const SubInfo& q : pl.subs) nbl_max = std::max(nbl_max, q.nbl);
-    launch_convert_lower(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), pc->lblks.as<LBlk>(), nL,
-                         work.as<double>(), pc->lperm.as<int32_t>(), pc->lmat.p, iprec, info.as<int32_t>() + m,
-                         nbl_max, kl_max, s);
-    int32_t nbu_max = 0;
-    for (const SubInfo& q : pl.subs) nbu_max = std::max(nbu_max, q.nbu);
-    launch_convert_upper(ab.as<double>(), pc->subs.as<SubInfo>(), pc->ublks.as<UBlk>(), nU, work.as<double>(),
-                         pc->uinv.p, pc->u12.p, iprec, info.as<int32_t>() + m, nbu_max, kv_max, s);
+    // The band LU takes as long as its widest bands: their panels hold the
+    // most rows per lane.  The subdomains that need fewer register rows go
+    // to a second stream with a launch of their own (fewer rows per lane),
+    // and the conversion of their blocks starts as soon as they are done,
+    // beside the widest bands' elimination.  A zero pivot of the LU is
+    // reported below; the conversions of such factors run but are discarded.
+    auto rows_of = [](int32_t kl) { return (kl + 8 + 63) / 64; };  // panel rows per lane
+    const int32_t rows_max = rows_of(kl_max);
+    std::vector<int32_t> wide, narrow;
+    for (int32_t j = 0; j < m; ++j) (rows_of(pl.subs[j].kl) == rows_max ? wide : narrow).push_back(j);
+    const bool split = !narrow.empty() && band_lu_blocked(kl_max) && convert_slabs(nbl_max, kl_max, nbu_max, kv_max);
+    if (!split) {
+      launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), m, info.as<int32_t>(),
+                     colnorm.as<double>(), o.ilu_tol, kl_max, kv_max, nullptr, s);
+      launch_convert_lower(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), pc->lblks.as<LBlk>(), nL,
+                           work.as<double>(), pc->lperm.as<int32_t>(), pc->lmat.p, iprec, info.as<int32_t>() + m,
+                           nbl_max, kl_max, nullptr, s);
+      launch_convert_upper(ab.as<double>(), pc->subs.as<SubInfo>(), pc->ublks.as<UBlk>(), nU, work.as<double>(),
+                           pc->uinv.p, pc->u12.p, iprec, info.as<int32_t>() + m, nbu_max, kv_max, nullptr, s);
+    } else {
+      struct Group {
+        std::vector<int32_t> subs, lbl, ubl;
+        int32_t kl_max = 0, kv_max = 0;
+        DevBuf d_subs, d_lbl, d_ubl;
+      } grp[2];
+      std::vector<int8_t> gof(m);
+      for (int32_t j : wide) gof[j] = 0;
+      for (int32_t j : narrow) gof[j] = 1;
+      for (int32_t j = 0; j < m; ++j) {
+        Group& g = grp[gof[j]];
+        g.subs.push_back(j);
+        g.kl_max = std::max(g.kl_max, pl.subs[j].kl);
+        g.kv_max = std::max(g.kv_max, pl.subs[j].kl + pl.subs[j].ku);
+      }
+      for (int32_t i = 0; i < nL; ++i) grp[gof[pl.lblks[i].sub]].lbl.push_back(i);
+      for (int32_t i = 0; i < nU; ++i) grp[gof[pl.ublks[i].sub]].ubl.push_back(i);
+      for (Group& g : grp) {
+        g.d_subs.upload(g.subs, s);
+        g.d_lbl.upload(g.lbl, s);
+        g.d_ubl.upload(g.ubl, s);
+      }
+      hipStream_t s1 = side_stream(1);
+      hipEvent_t ev[2];
+      for (hipEvent_t& e : ev) ADDNS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      struct EvGuard2 {
+        hipEvent_t* e;
+        ~EvGuard2() {
+          (void)hipEventDestroy(e[0]);
+          (void)hipEventDestroy(e[1]);
+        }
+      } ev_guard{ev};
+      ADDNS_HIP(hipEventRecord(ev[0], s));  // the band, its norms, the lists and the tails ready
+      ADDNS_HIP(hipStreamWaitEvent(s1, ev[0], 0));
+      for (int gi = 1; gi >= 0; --gi) {
+        Group& g = grp[gi];
+        hipStream_t sg = gi == 0 ? s : s1;
+        launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), (int32_t)g.subs.size(),
+                       info.as<int32_t>(), colnorm.as<double>(), o.ilu_tol, g.kl_max, g.kv_max, g.d_subs.as<int32_t>(),
+                       sg);
+        launch_convert_lower(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), pc->lblks.as<LBlk>(),
+                             (int32_t)g.lbl.size(), work.as<double>(), pc->lperm.as<int32_t>(), pc->lmat.p, iprec,
+                             info.as<int32_t>() + m, nbl_max, kl_max, g.d_lbl.as<int32_t>(), sg);
+        launch_convert_upper(ab.as<double>(), pc->subs.as<SubInfo>(), pc->ublks.as<UBlk>(), (int32_t)g.ubl.size(),
+                             work.as<double>(), pc->uinv.p, pc->u12.p, iprec, info.as<int32_t>() + m, nbu_max, kv_max,
+                             g.d_ubl.as<int32_t>(), sg);
+      }
+      ADDNS_HIP(hipEventRecord(ev[1], s1));
+      ADDNS_HIP(hipStreamWaitEvent(s, ev[1], 0));
+    }
+    d_nnz.alloc(sizeof(int64_t) * m);
+    int32_t n_max = 0;
+    for (const SubInfo& q : pl.subs) n_max = std::max(n_max, q.n);
+    launch_band_nnz(ab.as<double>(), pc->subs.as<SubInfo>(), m, n_max, d_nnz.as<int64_t>(), s);
   }
   // reads the interior's results once its work has finished
   auto finish_interior = [&]() {
@@ -345,7 +403,7 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
     finish_interior();
     interface_setup(s);
   } else {
-    hipStream_t s2 = side_stream();
+    hipStream_t s2 = side_stream(0);
     ADDNS_HIP(hipStreamWaitEvent(s2, ready, 0));
     interface_setup(s2);
     finish_interior();

@@ -13,6 +13,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <stdexcept>
+
 #include "precond.h"
 
 namespace addns {
@@ -469,14 +471,14 @@ template <int NS>
 __global__ void __launch_bounds__(kLuThreads)
 k_band_lu_blocked(double* __restrict__ ab_all, int32_t* __restrict__ ipiv_all, const SubInfo* __restrict__ subs,
                   int32_t* __restrict__ info, const double* __restrict__ colnorm_all, double tau, int32_t prmax,
-                  int32_t ntmax) {
+                  int32_t ntmax, const int32_t* __restrict__ sub_list) {
   extern __shared__ double s_dyn[];
   // panel buffer b: column c at s_dyn + (b * kPanel + c) * prmax; U12 row c
   // at s_u12 + c * ntmax
   double* const s_u12 = s_dyn + 3 * kPanel * prmax;
   __shared__ int32_t s_pv[3][kPanel], s_juc[3][kPanel], s_ok[3][kPanel];
   __shared__ int32_t s_ju, s_info;
-  const int sub = blockIdx.x;
+  const int sub = sub_list ? sub_list[blockIdx.x] : (int)blockIdx.x;
   const SubInfo q = subs[sub];
   const int32_t n = q.npad, ldab = q.ldab, KL = q.kl, KU = q.ku, KV = KL + KU;
   double* ab = ab_all + q.band_off;
@@ -778,9 +780,9 @@ k_convert_lower(const double* __restrict__ ab_all, const int32_t* __restrict__ i
 __global__ void __launch_bounds__(kSetupThreads)
 k_convert_lower_prep(const double* __restrict__ ab_all, const int32_t* __restrict__ ipiv_all,
                      const SubInfo* __restrict__ subs, const LBlk* __restrict__ lb, double* __restrict__ work_all,
-                     int32_t* __restrict__ lperm_all) {
+                     int32_t* __restrict__ lperm_all, const int32_t* __restrict__ blk_list) {
   extern __shared__ int32_t s_i[];  // piv[nbL], idx[W]
-  const LBlk B = lb[blockIdx.x];
+  const LBlk B = lb[blk_list ? blk_list[blockIdx.x] : blockIdx.x];
   const SubInfo q = subs[B.sub];
   const int32_t nbL = q.nbl, KL = q.kl, ldab = q.ldab, KV = q.kl + q.ku;
   const int32_t c0 = B.idx * nbL, W = nbL + KL;
@@ -823,9 +825,10 @@ constexpr int kLSlabThreads = 256;
 template <class T>
 __global__ void __launch_bounds__(kLSlabThreads)
 k_convert_lower_slab(const SubInfo* __restrict__ subs, const LBlk* __restrict__ lb, const double* __restrict__ work_all,
-                     int32_t slab, T* __restrict__ lmat_all, int32_t* __restrict__ info) {
+                     int32_t slab, T* __restrict__ lmat_all, int32_t* __restrict__ info,
+                     const int32_t* __restrict__ blk_list) {
   extern __shared__ double s_x[];
-  const LBlk B = lb[blockIdx.y];
+  const LBlk B = lb[blk_list ? blk_list[blockIdx.y] : blockIdx.y];
   const SubInfo q = subs[B.sub];
   const int32_t nbL = q.nbl, KL = q.kl, W = nbL + KL;
   const int32_t a0 = blockIdx.x * slab;
@@ -964,9 +967,9 @@ template <class T>
 __global__ void __launch_bounds__(kUSlabThreads)
 k_convert_upper_slab(const double* __restrict__ ab_all, const SubInfo* __restrict__ subs,
                      const UBlk* __restrict__ ub, int32_t slab, int32_t kv_max, T* __restrict__ uinv_all,
-                     T* __restrict__ u12_all, int32_t* __restrict__ info) {
+                     T* __restrict__ u12_all, int32_t* __restrict__ info, const int32_t* __restrict__ blk_list) {
   extern __shared__ double s_x[];
-  const UBlk B = ub[blockIdx.y];
+  const UBlk B = ub[blk_list ? blk_list[blockIdx.y] : blockIdx.y];
   const SubInfo q = subs[B.sub];
   const int32_t nbU = q.nbu, ldab = q.ldab, n = q.npad, KV = q.kl + q.ku;
   const int32_t c0 = blockIdx.x * slab;
@@ -1432,7 +1435,7 @@ void launch_band_nnz(const double* ab, const SubInfo* subs, int32_t m, int32_t n
 }
 template <int NS>
 void run_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, const double* colnorm,
-                 double tau, int32_t prmax, int32_t ntmax, hipStream_t s) {
+                 double tau, int32_t prmax, int32_t ntmax, const int32_t* sub_list, hipStream_t s) {
   const size_t smem = sizeof(double) * ((size_t)3 * kPanel * prmax + (size_t)kPanel * ntmax);
   static size_t raised = 64 * 1024;
   if (smem > raised) {
@@ -1440,25 +1443,27 @@ void run_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int3
                                   (int)smem));
     raised = smem;
   }
-  k_band_lu_blocked<NS><<<m, kLuThreads, smem, s>>>(ab, ipiv, subs, info, colnorm, tau, prmax, ntmax);
+  k_band_lu_blocked<NS><<<m, kLuThreads, smem, s>>>(ab, ipiv, subs, info, colnorm, tau, prmax, ntmax, sub_list);
 }
+bool band_lu_blocked(int32_t kl_max) { return (kl_max + kPanel + 63) / 64 <= 4; }
 void launch_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, const double* colnorm,
-                    double tau, int32_t kl_max, int32_t kv_max, hipStream_t s) {
+                    double tau, int32_t kl_max, int32_t kv_max, const int32_t* sub_list, hipStream_t s) {
   if (m == 0) return;
+  if (sub_list && !band_lu_blocked(kl_max)) throw std::logic_error("a subdomain list needs the blocked band LU");
   const int32_t prmax = kl_max + kPanel, ntmax = std::max(kv_max, 1);
   // panel rows per lane in registers (64 * NS >= prmax); wider bands take the
   // unblocked elimination
   switch ((prmax + 63) / 64) {
-    case 1: run_band_lu<1>(ab, ipiv, subs, m, info, colnorm, tau, prmax, ntmax, s); break;
-    case 2: run_band_lu<2>(ab, ipiv, subs, m, info, colnorm, tau, prmax, ntmax, s); break;
-    case 3: run_band_lu<3>(ab, ipiv, subs, m, info, colnorm, tau, prmax, ntmax, s); break;
-    case 4: run_band_lu<4>(ab, ipiv, subs, m, info, colnorm, tau, prmax, ntmax, s); break;
+    case 1: run_band_lu<1>(ab, ipiv, subs, m, info, colnorm, tau, prmax, ntmax, sub_list, s); break;
+    case 2: run_band_lu<2>(ab, ipiv, subs, m, info, colnorm, tau, prmax, ntmax, sub_list, s); break;
+    case 3: run_band_lu<3>(ab, ipiv, subs, m, info, colnorm, tau, prmax, ntmax, sub_list, s); break;
+    case 4: run_band_lu<4>(ab, ipiv, subs, m, info, colnorm, tau, prmax, ntmax, sub_list, s); break;
     default: k_band_lu<<<m, kSetupThreads, 0, s>>>(ab, ipiv, subs, info, colnorm, tau); break;
   }
 }
 template <class T>
 void run_convert_lower_slab(const SubInfo* subs, const LBlk* lb, int32_t nblk, int32_t slab, int32_t nbl_max,
-                            const double* work, T* lmat, int32_t* info, hipStream_t s) {
+                            const double* work, T* lmat, int32_t* info, const int32_t* blk_list, hipStream_t s) {
   const size_t smem = sizeof(double) * ((size_t)slab * (nbl_max + 1) + 2 * (size_t)nbl_max);
   static size_t raised = 64 * 1024;
   if (smem > raised) {
@@ -1467,23 +1472,34 @@ void run_convert_lower_slab(const SubInfo* subs, const LBlk* lb, int32_t nblk, i
     raised = smem;
   }
   const dim3 grid((unsigned)((nbl_max + slab - 1) / slab), (unsigned)nblk);
-  k_convert_lower_slab<T><<<grid, kLSlabThreads, smem, s>>>(subs, lb, work, slab, lmat, info);
+  k_convert_lower_slab<T><<<grid, kLSlabThreads, smem, s>>>(subs, lb, work, slab, lmat, info, blk_list);
+}
+// slabs of up to 32 columns within 96 KB of LDS
+static int32_t lower_slab(int32_t nbl_max) {
+  return (int32_t)std::min<int64_t>(32, (96 * 1024 / 8 - 2 * (int64_t)nbl_max) / ((int64_t)nbl_max + 1));
+}
+static int32_t upper_slab(int32_t nbu_max) {
+  return (int32_t)std::min<int64_t>(32, (96 * 1024 / 8) / ((int64_t)nbu_max + 1));
+}
+bool convert_slabs(int32_t nbl_max, int32_t kl_max, int32_t nbu_max, int32_t kv_max) {
+  return lower_slab(nbl_max) >= 1 && sizeof(int32_t) * (2 * (size_t)nbl_max + kl_max) <= 64 * 1024 &&
+         upper_slab(nbu_max) >= 1 && kv_max < 4 * kUSlabThreads;
 }
 void launch_convert_lower(const double* ab, const int32_t* ipiv, const SubInfo* subs, const LBlk* lb, int32_t nblk,
                           double* work, int32_t* lperm, void* lmat, int prec, int32_t* info, int32_t nbl_max,
-                          int32_t kl_max, hipStream_t s) {
+                          int32_t kl_max, const int32_t* blk_list, hipStream_t s) {
   if (nblk == 0) return;
-  // slabs of up to 32 columns within 96 KB of LDS
-  const int32_t slab = (int32_t)std::min<int64_t>(32, (96 * 1024 / 8 - 2 * (int64_t)nbl_max) / ((int64_t)nbl_max + 1));
+  const int32_t slab = lower_slab(nbl_max);
   const size_t prep_smem = sizeof(int32_t) * (2 * (size_t)nbl_max + kl_max);
   if (slab >= 1 && prep_smem <= 64 * 1024) {
-    k_convert_lower_prep<<<nblk, kSetupThreads, prep_smem, s>>>(ab, ipiv, subs, lb, work, lperm);
+    k_convert_lower_prep<<<nblk, kSetupThreads, prep_smem, s>>>(ab, ipiv, subs, lb, work, lperm, blk_list);
     if (prec == P64)
-      run_convert_lower_slab<double>(subs, lb, nblk, slab, nbl_max, work, (double*)lmat, info, s);
+      run_convert_lower_slab<double>(subs, lb, nblk, slab, nbl_max, work, (double*)lmat, info, blk_list, s);
     else
-      run_convert_lower_slab<float>(subs, lb, nblk, slab, nbl_max, work, (float*)lmat, info, s);
+      run_convert_lower_slab<float>(subs, lb, nblk, slab, nbl_max, work, (float*)lmat, info, blk_list, s);
     return;
   }
+  if (blk_list) throw std::logic_error("a block list needs the slab conversion");
   if (prec == P64)
     k_convert_lower<double><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, subs, lb, work, lperm, (double*)lmat, info);
   else
@@ -1491,7 +1507,8 @@ void launch_convert_lower(const double* ab, const int32_t* ipiv, const SubInfo* 
 }
 template <class T>
 void run_convert_upper_slab(const double* ab, const SubInfo* subs, const UBlk* ub, int32_t nblk, int32_t slab,
-                            int32_t nbu_max, int32_t kv_max, T* uinv, T* u12, int32_t* info, hipStream_t s) {
+                            int32_t nbu_max, int32_t kv_max, T* uinv, T* u12, int32_t* info, const int32_t* blk_list,
+                            hipStream_t s) {
   const size_t smem = sizeof(double) * ((size_t)slab * (nbu_max + 1) + 2 * (size_t)(kv_max + 1));
   static size_t raised = 64 * 1024;
   if (smem > raised) {
@@ -1500,22 +1517,25 @@ void run_convert_upper_slab(const double* ab, const SubInfo* subs, const UBlk* u
     raised = smem;
   }
   const dim3 grid((unsigned)((nbu_max + slab - 1) / slab), (unsigned)nblk);
-  k_convert_upper_slab<T><<<grid, kUSlabThreads, smem, s>>>(ab, subs, ub, slab, kv_max, uinv, u12, info);
+  k_convert_upper_slab<T><<<grid, kUSlabThreads, smem, s>>>(ab, subs, ub, slab, kv_max, uinv, u12, info, blk_list);
 }
 void launch_convert_upper(const double* ab, const SubInfo* subs, const UBlk* ub, int32_t nblk, double* work,
                           void* uinv, void* u12, int prec, int32_t* info, int32_t nbu_max, int32_t kv_max,
-                          hipStream_t s) {
+                          const int32_t* blk_list, hipStream_t s) {
   if (nblk == 0) return;
   // slabs of up to 32 columns within 96 KB of LDS; U's column fits the four
   // values per thread of the step buffer when KV < 1024
-  const int32_t slab = (int32_t)std::min<int64_t>(32, (96 * 1024 / 8) / ((int64_t)nbu_max + 1));
+  const int32_t slab = upper_slab(nbu_max);
   if (slab >= 1 && kv_max < 4 * kUSlabThreads) {
     if (prec == P64)
-      run_convert_upper_slab<double>(ab, subs, ub, nblk, slab, nbu_max, kv_max, (double*)uinv, (double*)u12, info, s);
+      run_convert_upper_slab<double>(ab, subs, ub, nblk, slab, nbu_max, kv_max, (double*)uinv, (double*)u12, info,
+                                     blk_list, s);
     else
-      run_convert_upper_slab<float>(ab, subs, ub, nblk, slab, nbu_max, kv_max, (float*)uinv, (float*)u12, info, s);
+      run_convert_upper_slab<float>(ab, subs, ub, nblk, slab, nbu_max, kv_max, (float*)uinv, (float*)u12, info,
+                                    blk_list, s);
     return;
   }
+  if (blk_list) throw std::logic_error("a block list needs the slab conversion");
   if (prec == P64)
     k_convert_upper<double><<<nblk, kSetupThreads, 0, s>>>(ab, subs, ub, work, (double*)uinv, (double*)u12, info);
   else

@@ -306,7 +306,12 @@ void launch_band_pad_identity(const SubInfo* subs, int32_t m, double* ab, hipStr
 // panels of 8 columns rely on it.
 constexpr int32_t kNpadMultiple = 16;
 void launch_band_lu(double* ab, int32_t* ipiv, const SubInfo* subs, int32_t m, int32_t* info, const double* colnorm,
-                    double tau, int32_t kl_max, int32_t kv_max, hipStream_t s);
+                    double tau, int32_t kl_max, int32_t kv_max, const int32_t* sub_list, hipStream_t s);
+// true when bands of at most kl_max take the blocked LU (which takes subdomain
+// lists: m workgroups for sub_list[0 .. m))
+bool band_lu_blocked(int32_t kl_max);
+// true when the slab conversions (which take block lists) apply
+bool convert_slabs(int32_t nbl_max, int32_t kl_max, int32_t nbu_max, int32_t kv_max);
 void launch_band_colnorm(const double* ab, const SubInfo* subs, int32_t m, int32_t npad_max, double* colnorm,
                          hipStream_t s);
 void launch_band_nnz(const double* ab, const SubInfo* subs, int32_t m, int32_t n_max, int64_t* counts,
@@ -315,10 +320,10 @@ void launch_band_nnz(const double* ab, const SubInfo* subs, int32_t m, int32_t n
 // block not finite in the storage type.
 void launch_convert_lower(const double* ab, const int32_t* ipiv, const SubInfo* subs, const LBlk* lb, int32_t nblk,
                           double* work, int32_t* lperm, void* lmat, int prec, int32_t* info, int32_t nbl_max,
-                          int32_t kl_max, hipStream_t s);
+                          int32_t kl_max, const int32_t* blk_list, hipStream_t s);
 void launch_convert_upper(const double* ab, const SubInfo* subs, const UBlk* ub, int32_t nblk, double* work,
                           void* uinv, void* u12, int prec, int32_t* info, int32_t nbu_max, int32_t kv_max,
-                          hipStream_t s);
+                          const int32_t* blk_list, hipStream_t s);
 void launch_dense_scatter(const int64_t* dst, const int32_t* src, const double* cpv, int64_t n, double* out,
                           hipStream_t s);
 void launch_schur_blocks(int32_t k, const int32_t* agg_s, const int32_t* agg_d, const int64_t* g_off,
