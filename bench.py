@@ -139,17 +139,25 @@ def bench_batched(args):
     d_b = torch.from_numpy(np.concatenate([bd[3] for bd in built])).to(dev)
     d_x = torch.zeros(N, dtype=torch.float64, device=dev)
 
+    split = []
+
     def step():
+        ts = time.perf_counter()
         pc = addns.setup_precond(cat, N, d_rp, d_ci, d_v, interior_prec=addns.F32, schur_prec=addns.F32,
-                                 block_sizing=args.block_sizing,
+                                 block_sizing=args.block_sizing, sweep_chunks=args.sweep_chunks,
                                  block_mult=args.block_mult, coarse=args.coarse)
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
         d_x.zero_()
         res, code = addns.gmres_solve_batched(pc, offs, d_b, d_x, restart=50, maxit=20000, tol=1e-8)
+        torch.cuda.synchronize()
+        split.append((tm - ts, time.perf_counter() - tm))
         return pc, res
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    split.clear()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         pc, res = step()
@@ -178,7 +186,10 @@ def bench_batched(args):
         "vs_baseline": None, "dtype": "f64 outer / f32 factors", "data": "synthetic",
         "config": {"workload": "batched96", "systems": len(wls), "N_total": N,
                    "subdomains_total": int(sum(w.m for w in wls)), "krylov": "FGMRES(50)", "ortho": "mgs",
-                   "coarse_piece": args.coarse, "block_mult": info["block_mult"]},
+                   "coarse_piece": args.coarse, "block_mult": info["block_mult"],
+                   "sweep_chunks": info["sweep_chunks"]},
+        "setup_s": round(float(np.median([x[0] for x in split])), 4),
+        "solve_s": round(float(np.median([x[1] for x in split])), 4),
         "converged": int(sum(r["converged"] for r in res)), "iters_max": max(its),
         "iters_median": float(np.median(its)), "sequential_same_library_s": round(T_seq, 3),
         "sequential_iters_max": max(seq_its), "speedup_vs_sequential": round(T_seq / T, 2)}))

@@ -222,7 +222,13 @@ typedef struct {
                              Theorem 2 holds with Shat^-1 replaced by this
                              operator.  At most 8192 coarse columns; not with
                              overlap > 0 (else ADDNS_ERR_ARG); a singular
-                             Z^T S Z gives ADDNS_ERR_SINGULAR */
+                             Z^T S Z gives ADDNS_ERR_SINGULAR.  (Z^T S Z)^-1 is
+                             formed by Gauss-Jordan elimination in one of four
+                             kernel forms that give the same inverse bit for
+                             bit; the environment variable ADDNS_COARSE_GJ
+                             (lds, registers, memory, steps) forces one, for
+                             tests: a form too small for the coarse blocks gives
+                             ADDNS_ERR_ARG */
   int32_t sweep_zero_skip;  /* sweep form: 0 = time the sweep with and without
                              loading only each stored column's nonzero rows and
                              keep the faster (the default; both give the same

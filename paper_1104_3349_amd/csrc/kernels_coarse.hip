@@ -11,6 +11,11 @@
 // results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+#include <stdexcept>
+#include <string>
+
+
 #include "precond.h"
 
 namespace addns {
@@ -581,15 +586,29 @@ void launch_gj_invert(const addns_precond* pc, double* A, int32_t* perm, double*
   const int32_t* boff = pc->cz_boff.as<int32_t>();
   const int32_t* cblk = pc->cz_cblk.as<int32_t>();
   const int64_t* beoff = pc->cz_beoff.as<int64_t>();
-  if (cp.blk_max <= kGjLds) {
+  // the form: the block in LDS, in registers, in memory, or one launch
+  // pair per step; every form gives the same inverse bit for bit.  The
+  // ADDNS_COARSE_GJ environment variable (lds, registers, memory, steps)
+  // forces one, for tests; a form too small for the blocks is an error.
+  const bool lds_ok = cp.blk_max <= kGjLds;
+  const bool regs_ok = cp.blk_max <= 1024 && (1024 / cp.blk_max) * kGjRegs >= cp.blk_max;
+  const bool mem_ok = cp.blk_max <= kGjFusedMax;
+  const char* force = std::getenv("ADDNS_COARSE_GJ");
+  std::string form = force ? force : "";
+  if (form.empty()) form = lds_ok ? "lds" : (regs_ok ? "registers" : (mem_ok ? "memory" : "steps"));
+  if ((form == "lds" && !lds_ok) || (form == "registers" && !regs_ok) || (form == "memory" && !mem_ok) ||
+      (form != "lds" && form != "registers" && form != "memory" && form != "steps"))
+    throw ArgError("ADDNS_COARSE_GJ=" + form + " does not fit coarse blocks of " +
+                                std::to_string(cp.blk_max) + " columns");
+  if (form == "lds") {
     k_gj_fused<true><<<nb, 1024, 0, s>>>(A, boff, beoff, perm, info);
     return;
   }
-  if (cp.blk_max <= 1024 && (1024 / cp.blk_max) * kGjRegs >= cp.blk_max) {
+  if (form == "registers") {
     k_gj_regs<kGjRegs><<<nb, 1024, 0, s>>>(A, boff, beoff, perm, info);
     return;
   }
-  if (cp.blk_max <= kGjFusedMax) {
+  if (form == "memory") {
     k_gj_fused<false><<<nb, 1024, 0, s>>>(A, boff, beoff, perm, info);
     return;
   }

@@ -687,96 +687,18 @@ __device__ inline __half to_store<__half>(double v) { return __float2half((float
 //     x_b = inv(L11) v_top,   carry = v_bot - (L21 inv(L11)) v_top.
 // Stored per block: the gather indices of P (W = nbL+KL) and one column-major
 // W x nbL matrix [inv(L11); L21 inv(L11)], applied to v_top as one GEMV.
-// ---------------------------------------------------------------------------
-template <class T>
-__global__ void __launch_bounds__(kSetupThreads)
-k_convert_lower(const double* __restrict__ ab_all, const int32_t* __restrict__ ipiv_all,
-                const SubInfo* __restrict__ subs, const LBlk* __restrict__ lb, double* __restrict__ work_all,
-                int32_t* __restrict__ lperm_all, T* __restrict__ lmat_all, int32_t* __restrict__ info) {
-  const LBlk B = lb[blockIdx.x];
-  const SubInfo q = subs[B.sub];
-  const int32_t nbL = q.nbl, KL = q.kl, ldab = q.ldab;
-  const int32_t c0 = B.idx * nbL;
-  const int32_t W = nbL + KL;
-  const int32_t KV = q.kl + q.ku;
-  const double* ab = ab_all + q.band_off;
-  const int32_t* ipiv = ipiv_all + q.vec_off;
-  double* Lw = work_all + B.woff;  // W x nbL, col-major
-  double* X = Lw + (int64_t)W * nbL;                                                  // nbL x nbL, col-major
-  const int tid = threadIdx.x;
-  // multipliers of each column at their window rows (diagonal implicit)
-  for (int64_t t = tid; t < (int64_t)W * nbL; t += blockDim.x) {
-    int32_t c = (int32_t)(t / W), r = (int32_t)(t % W);
-    int32_t i = r - c;
-    Lw[t] = (i >= 1 && i <= KL) ? ab[(int64_t)(c0 + c) * ldab + KV + i] : 0.0;
-  }
-  __syncthreads();
-  // later swaps of the block act on earlier columns: one thread per column
-  for (int32_t c = tid; c < nbL; c += blockDim.x) {
-    double* col = Lw + (int64_t)c * W;
-    for (int32_t s = c + 1; s < nbL; ++s) {
-      int32_t p = ipiv[c0 + s] - c0;
-      if (p != s) {
-        double a = col[s];
-        col[s] = col[p];
-        col[p] = a;
-      }
-    }
-  }
-  if (tid == 0) {
-    int32_t* idx = lperm_all + B.poff;
-    for (int32_t r = 0; r < W; ++r) idx[r] = r;
-    for (int32_t s = 0; s < nbL; ++s) {
-      int32_t p = ipiv[c0 + s] - c0;
-      int32_t a = idx[s];
-      idx[s] = idx[p];
-      idx[p] = a;
-    }
-  }
-  // X = I
-  for (int64_t t = tid; t < (int64_t)nbL * nbL; t += blockDim.x) {
-    int32_t c = (int32_t)(t / nbL), r = (int32_t)(t % nbL);
-    X[t] = r == c ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  // forward elimination of the unit lower L11: rows r > i receive -L(r,i) X(i,:)
-  for (int32_t i = 0; i < nbL - 1; ++i) {
-    const int32_t rows = nbL - 1 - i, cols = i + 1;
-    for (int32_t t = tid; t < rows * cols; t += blockDim.x) {
-      int32_t r = i + 1 + t % rows, c = t / rows;
-      X[(int64_t)c * nbL + r] -= Lw[(int64_t)i * W + r] * X[(int64_t)c * nbL + i];
-    }
-    __syncthreads();
-  }
-  bool bad = false;
-  T* lm = lmat_all + B.moff;
-  for (int64_t t = tid; t < (int64_t)W * nbL; t += blockDim.x) {
-    int32_t c = (int32_t)(t / W), r = (int32_t)(t % W);
-    double v;
-    if (r < nbL) {
-      v = X[(int64_t)c * nbL + r];
-    } else {  // (L21 inv(L11))(r - nbL, c), inv(L11) lower: k >= c
-      v = 0.0;
-      for (int32_t k = c; k < nbL; ++k) v += Lw[(int64_t)k * W + r] * X[(int64_t)c * nbL + k];
-    }
-    const T st = to_store<T>(v);
-    if (!isfinite((double)st)) bad = true;
-    lm[t] = st;
-  }
-  // a block matrix not finite in the storage type (overflow): reported as 2
-  if (bad) atomicMax(info, 2);
-}
-
-// The same conversion in two launches.  k_convert_lower_prep (one
-// workgroup per block): the multipliers with the block's later swaps, each
-// band entry's row traced through those swaps (a permutation of its column,
-// so the entries land where the swaps in order would put them), and the
-// window indices permuted in LDS.  k_convert_lower_slab (grid: slabs x
-// blocks): columns c0 .. c0+sw-1 of inv(L11) in LDS (column c receives the
-// elimination steps i >= c only, row r the multiplier Lw(r, i) of column i,
-// read into LDS one step ahead), then the rows below as dot products over
-// k = c .. nbL-1 in increasing k.  Every element receives the operations of
-// k_convert_lower in the same order, so the result is the same bit for bit.
+// Two launches.  k_convert_lower_prep (one workgroup per block): the
+// multipliers with the block's later swaps applied, each band entry's row
+// traced through those swaps (a permutation of its column, so the entries
+// land where the swaps in order put them), and the window indices permuted
+// in LDS.  k_convert_lower_slab (grid: slabs x blocks): columns c0 ..
+// c0+sw-1 of inv(L11) in LDS by forward elimination of the unit lower L11
+// (column c receives the steps i >= c only: rows r > i lose Lw(r, i) X(i, c),
+// Lw's column i read into LDS one step ahead), then the rows below as dot
+// products of Lw's rows with the slab's columns over k = c .. nbL-1 in
+// increasing k.  Every element's operations and their order depend only on
+// the block, not on the slab split, so any slab width gives the same result
+// bit for bit.
 __global__ void __launch_bounds__(kSetupThreads)
 k_convert_lower_prep(const double* __restrict__ ab_all, const int32_t* __restrict__ ipiv_all,
                      const SubInfo* __restrict__ subs, const LBlk* __restrict__ lb, double* __restrict__ work_all,
@@ -900,69 +822,17 @@ k_convert_lower_slab(const SubInfo* __restrict__ subs, const LBlk* __restrict__ 
 // Upper sweep blocks (rows r0 = b*nbU .. r0+nbU-1, nbU >= KL+KU so that U is
 // block bidiagonal): inv(U_bb) (column-major) and U_{b,b+1} (column-major).
 // ---------------------------------------------------------------------------
-template <class T>
-__global__ void __launch_bounds__(kSetupThreads)
-k_convert_upper(const double* __restrict__ ab_all, const SubInfo* __restrict__ subs, const UBlk* __restrict__ ub,
-                double* __restrict__ work_all, T* __restrict__ uinv_all, T* __restrict__ u12_all,
-                int32_t* __restrict__ info) {
-  const UBlk B = ub[blockIdx.x];
-  const SubInfo q = subs[B.sub];
-  const int32_t nbU = q.nbu, ldab = q.ldab;
-  const int32_t r0 = B.idx * nbU;
-  const int32_t n = q.npad;
-  const int32_t KV = q.kl + q.ku;
-  const double* ab = ab_all + q.band_off;
-  double* X = work_all + B.off;  // column-major
-  const int tid = threadIdx.x;
-  auto U = [&](int32_t r, int32_t c) -> double {   // subdomain-local (r, c)
-    int32_t d = c - r;
-    return (d >= 0 && d <= KV && c < n) ? ab[(int64_t)c * ldab + KV + r - c] : 0.0;
-  };
-  for (int64_t t = tid; t < (int64_t)nbU * nbU; t += blockDim.x) {
-    int32_t c = (int32_t)(t / nbU), r = (int32_t)(t % nbU);
-    X[t] = r == c ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int32_t i = nbU - 1; i >= 0; --i) {
-    const double d = U(r0 + i, r0 + i);
-    if (d == 0.0) {
-      if (tid == 0) atomicMax(info, 1);
-      return;
-    }
-    const double dinv = 1.0 / d;
-    for (int32_t c = i + tid; c < nbU; c += blockDim.x) X[(int64_t)c * nbU + i] *= dinv;
-    __syncthreads();
-    const int32_t rows = i, cols = nbU - i;
-    for (int32_t t = tid; t < rows * cols; t += blockDim.x) {
-      int32_t r = t % rows, c = i + t / rows;
-      double u = U(r0 + r, r0 + i);
-      if (u != 0.0) X[(int64_t)c * nbU + r] -= u * X[(int64_t)c * nbU + i];
-    }
-    __syncthreads();
-  }
-  T* ui = uinv_all + B.off;
-  T* u12 = u12_all + B.off;
-  bool bad = false;
-  for (int64_t t = tid; t < (int64_t)nbU * nbU; t += blockDim.x) {
-    int32_t c = (int32_t)(t / nbU), r = (int32_t)(t % nbU);
-    const T a = to_store<T>(X[t]), b = to_store<T>(U(r0 + r, r0 + nbU + c));
-    if (!isfinite((double)a) || !isfinite((double)b)) bad = true;
-    ui[t] = a;
-    u12[t] = b;
-  }
-  // an inverse not finite in the storage type (overflow): reported as 2
-  if (bad) atomicMax(info, 2);
-}
-
-// The same inverse by slabs of columns (grid: slabs x blocks), the slab in
-// LDS.  Column c of inv(U_bb) receives steps i <= c only, and step i touches
-// rows i - KV .. i - 1 (U is banded), so a slab of columns c0 .. c0+sw-1
-// runs steps c0+sw-1 .. 0 on its own.  U's column i is read into LDS one
-// step ahead.  Wave w takes columns w, w + 4, ... of the slab, lane l rows
-// l, l + 64, ... of a step; every element receives the same operations in
-// the same order as in k_convert_upper (a zero U(r, i) skipped), so the
-// result is the same bit for bit.
+// inv(U_bb) by back substitution on all columns at once: steps i = nbU-1 ..
+// 0 scale row i by 1 / U(i, i) and take U(r, i) X(i, :) from the rows r < i
+// (a zero U(r, i) skipped).  By slabs of columns (grid: slabs x blocks), the
+// slab in LDS: column c receives steps i <= c only, and step i touches rows
+// i - KV .. i - 1 (U is banded), so a slab of columns c0 .. c0+sw-1 runs
+// steps c0+sw-1 .. 0 on its own.  U's column i is read into LDS one step
+// ahead.  Wave w takes columns w, w + 4, ... of the slab, lane l rows l,
+// l + 64, ... of a step; every element's operations and their order depend
+// only on the block, so any slab width gives the same result bit for bit.
 constexpr int kUSlabThreads = 256;
+constexpr int kUFetch = 5;  // entries of U's column per thread: KV + 1 <= 5 * 256
 template <class T>
 __global__ void __launch_bounds__(kUSlabThreads)
 k_convert_upper_slab(const double* __restrict__ ab_all, const SubInfo* __restrict__ subs,
@@ -986,17 +856,17 @@ k_convert_upper_slab(const double* __restrict__ ab_all, const SubInfo* __restric
   };
   // buffer entry j of step i holds U(i - KV + j, i), j = 0 .. KV (the last
   // is the diagonal)
-  auto fetch = [&](int32_t i, double (&v)[4]) {
+  auto fetch = [&](int32_t i, double (&v)[kUFetch]) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < kUFetch; ++t) {
       const int32_t j = tid + t * kUSlabThreads, r = i - KV + j;
       v[t] = (i >= 0 && j <= KV && r >= 0) ? U(r0 + r, r0 + i) : 0.0;
     }
   };
-  auto put = [&](int32_t i, const double (&v)[4]) {
+  auto put = [&](int32_t i, const double (&v)[kUFetch]) {
     double* buf = ucol + (i & 1) * (kv_max + 1);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < kUFetch; ++t) {
       const int32_t j = tid + t * kUSlabThreads;
       if (j <= KV) buf[j] = v[t];
     }
@@ -1007,14 +877,14 @@ k_convert_upper_slab(const double* __restrict__ ab_all, const SubInfo* __restric
   }
   const int32_t itop = c0 + sw - 1;
   {
-    double v[4];
+    double v[kUFetch];
     fetch(itop, v);
     put(itop, v);
   }
   __syncthreads();
   for (int32_t i = itop; i >= 0; --i) {
     const double* uc = ucol + (i & 1) * (kv_max + 1);  // uc[KV + r - i] = U(r, i)
-    double v[4];
+    double v[kUFetch];
     fetch(i - 1, v);  // the next step's column, in flight during this one
     const double d = uc[KV];
     if (d == 0.0) {
@@ -1483,7 +1353,7 @@ static int32_t upper_slab(int32_t nbu_max) {
 }
 bool convert_slabs(int32_t nbl_max, int32_t kl_max, int32_t nbu_max, int32_t kv_max) {
   return lower_slab(nbl_max) >= 1 && sizeof(int32_t) * (2 * (size_t)nbl_max + kl_max) <= 64 * 1024 &&
-         upper_slab(nbu_max) >= 1 && kv_max < 4 * kUSlabThreads;
+         upper_slab(nbu_max) >= 1 && kv_max < kUFetch * kUSlabThreads;
 }
 void launch_convert_lower(const double* ab, const int32_t* ipiv, const SubInfo* subs, const LBlk* lb, int32_t nblk,
                           double* work, int32_t* lperm, void* lmat, int prec, int32_t* info, int32_t nbl_max,
@@ -1499,11 +1369,7 @@ void launch_convert_lower(const double* ab, const int32_t* ipiv, const SubInfo* 
       run_convert_lower_slab<float>(subs, lb, nblk, slab, nbl_max, work, (float*)lmat, info, blk_list, s);
     return;
   }
-  if (blk_list) throw std::logic_error("a block list needs the slab conversion");
-  if (prec == P64)
-    k_convert_lower<double><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, subs, lb, work, lperm, (double*)lmat, info);
-  else
-    k_convert_lower<float><<<nblk, kSetupThreads, 0, s>>>(ab, ipiv, subs, lb, work, lperm, (float*)lmat, info);
+  throw std::logic_error("lower block too wide for the slab conversion");
 }
 template <class T>
 void run_convert_upper_slab(const double* ab, const SubInfo* subs, const UBlk* ub, int32_t nblk, int32_t slab,
@@ -1523,10 +1389,10 @@ void launch_convert_upper(const double* ab, const SubInfo* subs, const UBlk* ub,
                           void* uinv, void* u12, int prec, int32_t* info, int32_t nbu_max, int32_t kv_max,
                           const int32_t* blk_list, hipStream_t s) {
   if (nblk == 0) return;
-  // slabs of up to 32 columns within 96 KB of LDS; U's column fits the four
-  // values per thread of the step buffer when KV < 1024
+  // slabs of up to 32 columns within 96 KB of LDS; U's column fits the
+  // values per thread of the step buffer
   const int32_t slab = upper_slab(nbu_max);
-  if (slab >= 1 && kv_max < 4 * kUSlabThreads) {
+  if (slab >= 1 && kv_max < kUFetch * kUSlabThreads) {
     if (prec == P64)
       run_convert_upper_slab<double>(ab, subs, ub, nblk, slab, nbu_max, kv_max, (double*)uinv, (double*)u12, info,
                                      blk_list, s);
@@ -1535,11 +1401,7 @@ void launch_convert_upper(const double* ab, const SubInfo* subs, const UBlk* ub,
                                     blk_list, s);
     return;
   }
-  if (blk_list) throw std::logic_error("a block list needs the slab conversion");
-  if (prec == P64)
-    k_convert_upper<double><<<nblk, kSetupThreads, 0, s>>>(ab, subs, ub, work, (double*)uinv, (double*)u12, info);
-  else
-    k_convert_upper<float><<<nblk, kSetupThreads, 0, s>>>(ab, subs, ub, work, (float*)uinv, (float*)u12, info);
+  throw std::logic_error("upper block too wide for the slab conversion");
 }
 void launch_schur_blocks(int32_t k, const int32_t* agg_s, const int32_t* agg_d, const int64_t* g_off,
                          const int64_t* dd_off, const int64_t* de_off, const int64_t* df_off, double* G, double* Dd,

@@ -163,3 +163,34 @@ def test_coarse_on_concatenated_systems_is_blockwise():
     b = np.concatenate([S.b for S in systems])
     res, code = addns.gmres_solve_batched(pc, offs, _cuda(b), d_x, restart=20, maxit=2000, tol=1e-8)
     assert code == addns.OK and all(r["converged"] for r in res)
+
+
+@pytest.mark.parametrize("name,forms", [("cavity16", ("lds", "registers", "memory", "steps")),
+                                        ("cavity128", ("registers", "memory", "steps"))])
+def test_coarse_inverse_forms_are_bitwise_identical(name, forms, monkeypatch):
+    """The coarse inverse E_c^{-1} has four kernel forms (the block in LDS, in
+    registers, in memory, or one launch pair per elimination step) that do the
+    same operations on every entry in the same order: the applies must agree
+    bit for bit (the automatic choice is compared with the oracle above)."""
+    kw, piece = CASES[name]
+    S = make_system(**kw)
+    y = _cuda(np.random.default_rng(8).standard_normal(S.N))
+    part = addns.build_partition(S.N, S.rp, S.ci, S.v, S.m, S.sz)
+    out = {}
+    for form in forms:
+        monkeypatch.setenv("ADDNS_COARSE_GJ", form)
+        _, pc = gpu_precond(S, part=part, coarse=piece)
+        d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+        addns.apply_precond(pc, y, d_x)
+        torch.cuda.synchronize()
+        out[form] = d_x.cpu().numpy()
+        del pc
+    ref = out[forms[0]]
+    for form in forms[1:]:
+        assert np.array_equal(out[form], ref), form
+    if name == "cavity128":
+        # the LDS form holds at most 88 columns: forcing it is an argument error
+        monkeypatch.setenv("ADDNS_COARSE_GJ", "lds")
+        with pytest.raises(addns.AddnsError) as e:
+            gpu_precond(S, part=part, coarse=piece)
+        assert e.value.code == addns.ERR_ARG
