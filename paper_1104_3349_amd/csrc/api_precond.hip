@@ -178,64 +178,92 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
     // reported below; the conversions of such factors run but are discarded.
     auto rows_of = [](int32_t kl) { return (kl + 8 + 63) / 64; };  // panel rows per lane
     const int32_t rows_max = rows_of(kl_max);
-    std::vector<int32_t> wide, narrow;
-    for (int32_t j = 0; j < m; ++j) (rows_of(pl.subs[j].kl) == rows_max ? wide : narrow).push_back(j);
-    const bool split = !narrow.empty() && band_lu_blocked(kl_max) && convert_slabs(nbl_max, kl_max, nbu_max, kv_max);
-    if (!split) {
-      launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), m, info.as<int32_t>(),
-                     colnorm.as<double>(), o.ilu_tol, kl_max, kv_max, nullptr, s);
-      launch_convert_lower(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), pc->lblks.as<LBlk>(), nL,
-                           work.as<double>(), pc->lperm.as<int32_t>(), pc->lmat.p, iprec, info.as<int32_t>() + m,
-                           nbl_max, kl_max, nullptr, s);
-      launch_convert_upper(ab.as<double>(), pc->subs.as<SubInfo>(), pc->ublks.as<UBlk>(), nU, work.as<double>(),
-                           pc->uinv.p, pc->u12.p, iprec, info.as<int32_t>() + m, nbu_max, kv_max, nullptr, s);
-    } else {
-      struct Group {
-        std::vector<int32_t> subs, lbl, ubl;
-        int32_t kl_max = 0, kv_max = 0;
-        DevBuf d_subs, d_lbl, d_ubl;
-      } grp[2];
-      std::vector<int8_t> gof(m);
-      for (int32_t j : wide) gof[j] = 0;
-      for (int32_t j : narrow) gof[j] = 1;
-      for (int32_t j = 0; j < m; ++j) {
-        Group& g = grp[gof[j]];
-        g.subs.push_back(j);
-        g.kl_max = std::max(g.kl_max, pl.subs[j].kl);
-        g.kv_max = std::max(g.kv_max, pl.subs[j].kl + pl.subs[j].ku);
-      }
-      for (int32_t i = 0; i < nL; ++i) grp[gof[pl.lblks[i].sub]].lbl.push_back(i);
-      for (int32_t i = 0; i < nU; ++i) grp[gof[pl.ublks[i].sub]].ubl.push_back(i);
-      for (Group& g : grp) {
-        g.d_subs.upload(g.subs, s);
-        g.d_lbl.upload(g.lbl, s);
-        g.d_ubl.upload(g.ubl, s);
-      }
-      hipStream_t s1 = side_stream(1);
-      hipEvent_t ev[2];
-      for (hipEvent_t& e : ev) ADDNS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      struct EvGuard2 {
-        hipEvent_t* e;
-        ~EvGuard2() {
-          (void)hipEventDestroy(e[0]);
-          (void)hipEventDestroy(e[1]);
+    if (!band_lu_blocked(kl_max) || !convert_slabs(nbl_max, kl_max, nbu_max, kv_max))
+      throw std::logic_error("interior blocks beyond the blocked band LU or the slab conversions");
+    // group 0: the widest bands (on the caller's stream); group 1: the rest
+    // (on a second stream), empty when every band needs the same rows
+    std::vector<int8_t> gof(m);
+    for (int32_t j = 0; j < m; ++j) gof[j] = rows_of(pl.subs[j].kl) == rows_max ? 0 : 1;
+    struct Launch {
+      std::vector<int32_t> list;
+      int32_t kl_max = 0, kv_max = 0, nb_max = 0;
+      DevBuf d;
+    };
+    struct Group {
+      Launch lu;
+      std::vector<std::unique_ptr<Launch>> lower, upper;  // by block size class
+    } grp[2];
+    for (int32_t j = 0; j < m; ++j) {
+      Launch& L = grp[gof[j]].lu;
+      L.list.push_back(j);
+      L.kl_max = std::max(L.kl_max, pl.subs[j].kl);
+      L.kv_max = std::max(L.kv_max, pl.subs[j].kl + pl.subs[j].ku);
+    }
+    // the slab conversions size their LDS for the largest block of a launch:
+    // one launch per size class (blocks of up to 32, 64, 128, ... rows), so
+    // that small blocks of per-interior sizing keep many workgroups per CU
+    auto classify = [&](std::vector<std::unique_ptr<Launch>>& out, int32_t nblk, bool upper) {
+      std::map<int, Launch*> byc;
+      for (int32_t i = 0; i < nblk; ++i) {
+        const SubInfo& q = pl.subs[upper ? pl.ublks[i].sub : pl.lblks[i].sub];
+        const int32_t nb = upper ? q.nbu : q.nbl;
+        int c = 0;
+        while ((32 << c) < nb) ++c;
+        Launch*& L = byc[gof[upper ? pl.ublks[i].sub : pl.lblks[i].sub] * 64 + c];
+        if (!L) {
+          out.emplace_back(new Launch());
+          L = out.back().get();
         }
-      } ev_guard{ev};
+        L->list.push_back(i);
+        L->nb_max = std::max(L->nb_max, nb);
+        L->kl_max = std::max(L->kl_max, q.kl);
+        L->kv_max = std::max(L->kv_max, q.kl + q.ku);
+      }
+    };
+    std::vector<std::unique_ptr<Launch>> lower_all, upper_all;
+    classify(lower_all, nL, false);
+    classify(upper_all, nU, true);
+    for (auto& L : lower_all) grp[gof[pl.lblks[L->list[0]].sub]].lower.push_back(std::move(L));
+    for (auto& L : upper_all) grp[gof[pl.ublks[L->list[0]].sub]].upper.push_back(std::move(L));
+    // lists uploaded before any stream forks (a copy from pageable memory
+    // waits for its stream's earlier work)
+    for (Group& g : grp) {
+      g.lu.d.upload(g.lu.list, s);
+      for (auto& L : g.lower) L->d.upload(L->list, s);
+      for (auto& L : g.upper) L->d.upload(L->list, s);
+    }
+    const bool split = !grp[1].lu.list.empty();
+    hipStream_t s1 = split ? side_stream(1) : s;
+    hipEvent_t ev[2];
+    for (hipEvent_t& e : ev) ADDNS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    struct EvGuard2 {
+      hipEvent_t* e;
+      ~EvGuard2() {
+        (void)hipEventDestroy(e[0]);
+        (void)hipEventDestroy(e[1]);
+      }
+    } ev_guard{ev};
+    if (split) {
       ADDNS_HIP(hipEventRecord(ev[0], s));  // the band, its norms, the lists and the tails ready
       ADDNS_HIP(hipStreamWaitEvent(s1, ev[0], 0));
-      for (int gi = 1; gi >= 0; --gi) {
-        Group& g = grp[gi];
-        hipStream_t sg = gi == 0 ? s : s1;
-        launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), (int32_t)g.subs.size(),
-                       info.as<int32_t>(), colnorm.as<double>(), o.ilu_tol, g.kl_max, g.kv_max, g.d_subs.as<int32_t>(),
-                       sg);
+    }
+    for (int gi = 1; gi >= 0; --gi) {
+      Group& g = grp[gi];
+      if (g.lu.list.empty()) continue;
+      hipStream_t sg = gi == 0 ? s : s1;
+      launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), (int32_t)g.lu.list.size(),
+                     info.as<int32_t>(), colnorm.as<double>(), o.ilu_tol, g.lu.kl_max, g.lu.kv_max,
+                     g.lu.d.as<int32_t>(), sg);
+      for (auto& L : g.lower)
         launch_convert_lower(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), pc->lblks.as<LBlk>(),
-                             (int32_t)g.lbl.size(), work.as<double>(), pc->lperm.as<int32_t>(), pc->lmat.p, iprec,
-                             info.as<int32_t>() + m, nbl_max, kl_max, g.d_lbl.as<int32_t>(), sg);
-        launch_convert_upper(ab.as<double>(), pc->subs.as<SubInfo>(), pc->ublks.as<UBlk>(), (int32_t)g.ubl.size(),
-                             work.as<double>(), pc->uinv.p, pc->u12.p, iprec, info.as<int32_t>() + m, nbu_max, kv_max,
-                             g.d_ubl.as<int32_t>(), sg);
-      }
+                             (int32_t)L->list.size(), work.as<double>(), pc->lperm.as<int32_t>(), pc->lmat.p, iprec,
+                             info.as<int32_t>() + m, L->nb_max, L->kl_max, L->d.as<int32_t>(), sg);
+      for (auto& L : g.upper)
+        launch_convert_upper(ab.as<double>(), pc->subs.as<SubInfo>(), pc->ublks.as<UBlk>(), (int32_t)L->list.size(),
+                             work.as<double>(), pc->uinv.p, pc->u12.p, iprec, info.as<int32_t>() + m, L->nb_max,
+                             L->kv_max, L->d.as<int32_t>(), sg);
+    }
+    if (split) {
       ADDNS_HIP(hipEventRecord(ev[1], s1));
       ADDNS_HIP(hipStreamWaitEvent(s, ev[1], 0));
     }
