@@ -67,6 +67,7 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
       build_plan(*P, pl, o.schur, o.block_mult, o.overlap, per);
       if (cache) {
         cache->plan = pl;
+        cache->maps_dev = -1;
         cache->have_plan = true;
         cache->have_coarse = false;
         cache->schur = o.schur;
@@ -79,10 +80,25 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
   const int32_t N = pl.N;
   const int64_t nnz = (int64_t)pl.cp_colidx.size();
 
+  // the plan's maps: kept on the partition's cache for later setups
+  PlanMaps local_maps;
+  PlanMaps* maps = &local_maps;
+  {
+    int dev = 0;
+    ADDNS_HIP(hipGetDevice(&dev));
+    if (cache) {
+      maps = &cache->maps;
+      if (cache->maps_dev != dev) {
+        cache->maps.upload(pl, s);
+        cache->maps_dev = dev;
+      }
+    } else {
+      local_maps.upload(pl, s);
+    }
+  }
   // -- permuted, row-scaled C~
-  DevBuf d_src, d_orow;
-  d_src.upload(pl.cp_src, s);
-  d_orow.upload(pl.cp_orow, s);
+  const DevBuf& d_src = maps->cp_src;
+  const DevBuf& d_orow = maps->cp_orow;
   pc->perm.upload(pl.perm, s);
   pc->iperm.upload(pl.iperm, s);
   pc->R.alloc(sizeof(double) * N);
@@ -96,9 +112,8 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
 
   // -- E and F
   {
-    DevBuf es, fs;
-    es.upload(pl.e_src, s);
-    fs.upload(pl.f_src, s);
+    const DevBuf& es = maps->e_src;
+    const DevBuf& fs = maps->f_src;
     pc->e_rowptr.upload(pl.e_rowptr, s);
     pc->e_colidx.upload(pl.e_colidx, s);
     pc->e_vals.alloc(sizeof(double) * pl.e_src.size());
@@ -137,20 +152,25 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
   ADDNS_HIP(hipEventRecord(ready, s));
   // device buffers of the interior factorisation: kept to the end of the
   // setup, since its work runs while the interface is set up
-  DevBuf ab, ipiv, bdst, bsrc, work, colnorm, d_nnz;
+  DevBuf ab, ipiv, work, colnorm, d_nnz;
+  const DevBuf& bdst = maps->band_dst;
+  const DevBuf& bsrc = maps->band_src;
   const bool interior = m > 0 && npad_total > 0;
   if (interior) {
     ab.alloc(sizeof(double) * pl.band_total);
     ADDNS_HIP(hipMemsetAsync(ab.p, 0, sizeof(double) * pl.band_total, s));
     ipiv.alloc(sizeof(int32_t) * npad_total);
-    bdst.upload(pl.band_dst, s);
-    bsrc.upload(pl.band_src, s);
     launch_scatter_band(bdst.as<int64_t>(), bsrc.as<int32_t>(), cpv, (int64_t)pl.band_dst.size(), ab.as<double>(), s);
     launch_band_pad_identity(pc->subs.as<SubInfo>(), m, ab.as<double>(), s);
     colnorm.alloc(sizeof(double) * npad_total);
     int32_t npad_max = 0;
     for (const SubInfo& q : pl.subs) npad_max = std::max(npad_max, q.npad);
-    launch_band_colnorm(ab.as<double>(), pc->subs.as<SubInfo>(), m, npad_max, colnorm.as<double>(), s);
+    // the column norms scale the incomplete factorisation's drops only: the
+    // exact LU (tau = 0) multiplies them by zero
+    if (o.ilu_tol > 0.0)
+      launch_band_colnorm(ab.as<double>(), pc->subs.as<SubInfo>(), m, npad_max, colnorm.as<double>(), s);
+    else
+      ADDNS_HIP(hipMemsetAsync(colnorm.p, 0, sizeof(double) * npad_total, s));
     int32_t kl_max = 0, kv_max = 0, nbl_max = 0, nbu_max = 0;
     for (const SubInfo& q : pl.subs) {
       // the blocked band LU factors whole panels
@@ -312,11 +332,11 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
       if (o.overlap > 0 && k > kMaxOverlapAggregates)
         throw ArgError("overlapped aggregates: at most 12000 aggregates");
       const int64_t dense_n = pl.g_total + pl.dd_total + pl.de_total + pl.df_total;
-      DevBuf dense, ddst, dsrc, agg_d, g_off, dd_off, de_off, df_off, work;
+      DevBuf dense, agg_d, g_off, dd_off, de_off, df_off, work;
+      const DevBuf& ddst = maps->dense_dst;
+      const DevBuf& dsrc = maps->dense_src;
       dense.alloc(sizeof(double) * dense_n);
       ADDNS_HIP(hipMemsetAsync(dense.p, 0, sizeof(double) * dense_n, s));
-      ddst.upload(pl.dense_dst, s);
-      dsrc.upload(pl.dense_src, s);
       launch_dense_scatter(ddst.as<int64_t>(), dsrc.as<int32_t>(), cpv, (int64_t)pl.dense_dst.size(), dense.as<double>(),
                            s);
       agg_d.upload(pl.agg_d, s);

@@ -192,11 +192,31 @@ void build_coarse_space(const PartitionData& P, int32_t piece, CoarseSpace& cs);
 void build_coarse_plan(const PartitionData& P, const Plan& pl, int32_t piece, CoarsePlan& cp);
 
 // Host plans of one partition, keyed by the options they depend on.
+// Device copies of a plan's gather and scatter maps (the setup's index
+// arrays that do not depend on the matrix values).
+struct PlanMaps {
+  DevBuf cp_src, cp_orow, e_src, f_src, band_dst, band_src, dense_dst, dense_src;
+  void upload(const Plan& pl, hipStream_t s) {
+    cp_src.upload(pl.cp_src, s);
+    cp_orow.upload(pl.cp_orow, s);
+    e_src.upload(pl.e_src, s);
+    f_src.upload(pl.f_src, s);
+    band_dst.upload(pl.band_dst, s);
+    band_src.upload(pl.band_src, s);
+    dense_dst.upload(pl.dense_dst, s);
+    dense_src.upload(pl.dense_src, s);
+  }
+};
+
 struct PlanCache {
   bool have_plan = false, have_coarse = false;
   int schur = -1, block_mult = -1, overlap = -1, piece = -1, per_interior = -1;
   Plan plan;
   CoarsePlan coarse;
+  // the plan's maps on device maps_dev (-1: none yet, or the plan changed):
+  // a repeated setup of the same partition does not upload them again
+  int maps_dev = -1;
+  PlanMaps maps;
 };
 
 // Largest coarse space the two-level interface solve accepts (its dense
