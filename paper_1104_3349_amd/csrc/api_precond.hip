@@ -198,12 +198,15 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
     // reported below; the conversions of such factors run but are discarded.
     auto rows_of = [](int32_t kl) { return (kl + 8 + 63) / 64; };  // panel rows per lane
     const int32_t rows_max = rows_of(kl_max);
-    if (!band_lu_blocked(kl_max) || !convert_slabs(nbl_max, kl_max, nbu_max, kv_max))
-      throw std::logic_error("interior blocks beyond the blocked band LU or the slab conversions");
+    if (!convert_slabs(nbl_max, kl_max, nbu_max, kv_max))
+      throw std::logic_error("interior blocks beyond the slab conversions");
+    // bands too wide for the blocked LU take the unblocked elimination, one
+    // launch over every subdomain
+    const bool blocked = band_lu_blocked(kl_max);
     // group 0: the widest bands (on the caller's stream); group 1: the rest
     // (on a second stream), empty when every band needs the same rows
     std::vector<int8_t> gof(m);
-    for (int32_t j = 0; j < m; ++j) gof[j] = rows_of(pl.subs[j].kl) == rows_max ? 0 : 1;
+    for (int32_t j = 0; j < m; ++j) gof[j] = (!blocked || rows_of(pl.subs[j].kl) == rows_max) ? 0 : 1;
     struct Launch {
       std::vector<int32_t> list;
       int32_t kl_max = 0, kv_max = 0, nb_max = 0;
@@ -271,9 +274,13 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
       Group& g = grp[gi];
       if (g.lu.list.empty()) continue;
       hipStream_t sg = gi == 0 ? s : s1;
-      launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), (int32_t)g.lu.list.size(),
-                     info.as<int32_t>(), colnorm.as<double>(), o.ilu_tol, g.lu.kl_max, g.lu.kv_max,
-                     g.lu.d.as<int32_t>(), sg);
+      if (blocked)
+        launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), (int32_t)g.lu.list.size(),
+                       info.as<int32_t>(), colnorm.as<double>(), o.ilu_tol, g.lu.kl_max, g.lu.kv_max,
+                       g.lu.d.as<int32_t>(), sg);
+      else
+        launch_band_lu(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), m, info.as<int32_t>(),
+                       colnorm.as<double>(), o.ilu_tol, kl_max, kv_max, nullptr, sg);
       for (auto& L : g.lower)
         launch_convert_lower(ab.as<double>(), ipiv.as<int32_t>(), pc->subs.as<SubInfo>(), pc->lblks.as<LBlk>(),
                              (int32_t)L->list.size(), work.as<double>(), pc->lperm.as<int32_t>(), pc->lmat.p, iprec,

@@ -496,6 +496,22 @@ def test_wide_band_interiors():
     assert blockwise_err(d_x.cpu().numpy(), ora.apply(y), blocks_of(ora.part)) <= 1e-9
 
 
+def test_unblocked_band_lu_interiors():
+    """A band too wide for the blocked LU's register panel (a 96 x 96 cavity
+    as one subdomain, KL = 287 > 248): the unblocked elimination, then the
+    block conversions and the sweep; interior solve element by element
+    against the oracle."""
+    S = make_system(n=96, nu=0.05, m=1, sz=64, seed=5)
+    ora = oracle_precond(S)
+    part, pc = gpu_precond(S)
+    assert pc.info()["kl"] > 248
+    y1 = np.random.default_rng(33).standard_normal(ora.ni)
+    d_z = torch.zeros(ora.ni, dtype=torch.float64, device="cuda")
+    addns.interior_solve(pc, _cuda(y1), d_z)
+    torch.cuda.synchronize()
+    assert blockwise_err(d_z.cpu().numpy(), ora.interior_solve(y1), blocks_of(ora.part, "interior")) <= 1e-9
+
+
 def test_per_interior_blocks_gmres_matches_oracle():
     """Per-interior block sizes in the FP64 solve of the bench workload: the
     iteration count within one of the oracle's (MGS), the true residual met."""
