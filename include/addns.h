@@ -509,6 +509,11 @@ int addns_gmres_solve_judged(addns_precond_t learned, addns_precond_t plain, con
                              double* d_x, const addns_gmres_opts* opts, addns_gmres_result* res,
                              int32_t* accepted, void* stream);
 
+/* A partition keeps the host plans of its setups and, after a first setup on
+   a device, that setup's index maps on the device (gathers and scatters of
+   the matrix entries, about 16 bytes per nonzero), so that a repeated setup
+   of the same partition uploads none of them; destroying the partition
+   releases both. */
 void addns_partition_destroy(addns_partition_t p);
 void addns_precond_destroy(addns_precond_t pc);
 
