@@ -29,6 +29,15 @@ constexpr int kWaves = kSweepThreads / 64;
 
 template <class T>
 __device__ inline double ld(const T* p) { return (double)(*p); }
+
+// Lane l's value of x in every lane (a uniform value).
+__device__ inline double bcast_lane(double x, int32_t l) {
+  const int64_t bits = __double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)bits, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(bits >> 32), l);
+  return __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+}
+constexpr int kIfRows = 4;  // rows a wave loads together in the interface solve
 template <>
 __device__ inline double ld<__half>(const __half* p) { return (double)__half2float(*p); }
 
@@ -787,17 +796,49 @@ k_interface_solve(int32_t n_int, const int32_t* __restrict__ agg_off, const int3
       mv[q] = (r < s && k < ke) ? ld(M + (int64_t)k * s + r) : 0.0;
     }
   }
-  for (int32_t q = tid; q < s; q += blockDim.x) {
-    const int32_t row = a0 + q;
-    double acc;
-    if (cz.t) {
-      acc = cz.t[row];
-      for (int32_t e = cz.szp[row]; e < cz.szp[row + 1]; ++e) acc -= cz.szv[e] * cz.y[cz.szc[e]];
-    } else {
-      acc = y[n_int + row];
-      for (int32_t e = f_rowptr[row]; e < f_rowptr[row + 1]; ++e) acc -= f_vals[e] * z1[f_colidx[e]];
+  // t = y2 - F z1 (or t - S Z y with a coarse space) on the aggregate's
+  // rows: each wave takes kIfRows rows at a time, its lanes load the rows'
+  // entries and their vector values together (two memory rounds for all of
+  // them), and each row's terms are summed by a fixed butterfly over the
+  // wave's lanes before they are subtracted
+  {
+    const int lane = tid & 63, wave = tid >> 6, nw = (int)(blockDim.x >> 6);
+    const int32_t* rp = cz.t ? cz.szp : f_rowptr;
+    const int32_t* cix = cz.t ? cz.szc : f_colidx;
+    const double* val = cz.t ? cz.szv : f_vals;
+    const double* vec = cz.t ? cz.y : z1;
+    for (int32_t q0 = wave; q0 < s; q0 += nw * kIfRows) {
+      int32_t e0[kIfRows], e1[kIfRows];
+      double w[kIfRows], x[kIfRows], acc[kIfRows];
+#pragma unroll
+      for (int g = 0; g < kIfRows; ++g) {
+        const int32_t q = q0 + g * nw;
+        const int32_t row = a0 + min(q, s - 1);
+        e0[g] = q < s ? rp[row] : 0;
+        e1[g] = q < s ? rp[row + 1] : 0;
+        acc[g] = q < s ? (cz.t ? cz.t[row] : y[n_int + row]) : 0.0;
+      }
+#pragma unroll
+      for (int g = 0; g < kIfRows; ++g) {
+        const int32_t e = e0[g] + lane;
+        const bool in = e < e1[g];
+        w[g] = in ? val[e] : 0.0;
+        x[g] = in ? vec[cix[e]] : 0.0;
+      }
+#pragma unroll
+      for (int g = 0; g < kIfRows; ++g) {
+        const int32_t q = q0 + g * nw;
+        if (q >= s) continue;
+        double sum = w[g] * x[g];
+        // entries past the first 64 (rare): the next ones, 64 at a time
+        for (int32_t eb = e0[g] + 64; eb < e1[g]; eb += 64) {
+          const int32_t e = eb + lane;
+          if (e < e1[g]) sum += val[e] * vec[cix[e]];
+        }
+        for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off);
+        if (lane == 0) t[q] = acc[g] - sum;
+      }
     }
-    t[q] = acc;
   }
   __syncthreads();
   // Z y on row `row` (separator position), 0 without a coarse space
