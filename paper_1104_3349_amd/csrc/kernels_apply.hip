@@ -29,14 +29,6 @@ constexpr int kWaves = kSweepThreads / 64;
 
 template <class T>
 __device__ inline double ld(const T* p) { return (double)(*p); }
-
-// Lane l's value of x in every lane (a uniform value).
-__device__ inline double bcast_lane(double x, int32_t l) {
-  const int64_t bits = __double_as_longlong(x);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)bits, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(bits >> 32), l);
-  return __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
-}
 constexpr int kIfRows = 4;  // rows a wave loads together in the interface solve
 template <>
 __device__ inline double ld<__half>(const __half* p) { return (double)__half2float(*p); }
