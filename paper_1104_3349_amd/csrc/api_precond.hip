@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -48,13 +49,18 @@ hipStream_t side_stream(int idx) {
   return st;
 }
 
-void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipStream_t s, PlanCache* cache);
+void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipStream_t s, PlanCache* cache,
+                  const std::function<void()>& side_work);
 
 // Factor and interface storage of one preconditioner.
 // Builds the plan from P (or keeps the handle's plan when P is null: a
 // refactor) and computes every numeric part of the preconditioner.
+// side_work, if given, is called once, with a stream of its own that has
+// seen the final interior factors, while the coarse column solves (when
+// there are any) are in flight on s; it must leave that stream drained.
 void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_rowptr, const int32_t* d_colidx,
-                  const double* d_vals, const addns_precond_opts& o, hipStream_t s, PlanCache* cache = nullptr) {
+                  const double* d_vals, const addns_precond_opts& o, hipStream_t s, PlanCache* cache = nullptr,
+                  const std::function<void(hipStream_t)>& side_work = {}) {
   Plan& pl = pc->plan;
   if (P) {
     // the host plan depends on the partition and on (schur, block_mult,
@@ -464,9 +470,18 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
     finish_interior();
   }
 
-  // -- coarse-grid correction of the interface solve (section 6)
+  // -- coarse-grid correction of the interface solve (section 6), with the
+  // caller's side work on another stream beside its column solves
+  ADDNS_HIP(hipEventRecord(ready, s));  // the interior factors are final
+  auto side = [&]() {
+    if (!side_work) return;
+    hipStream_t cs = side_stream(0);
+    ADDNS_HIP(hipStreamWaitEvent(cs, ready, 0));
+    side_work(cs);
+  };
   pc->coarse_nc = 0;
-  if (o.coarse > 0 && pl.nsep > 0) setup_coarse(pc, P, o.coarse, s, cache);
+  if (o.coarse > 0 && pl.nsep > 0) setup_coarse(pc, P, o.coarse, s, cache, side);
+  else side();
 
   // permuted in/out vectors of addns_apply_precond: allocated here so that
   // an apply launches kernels only (and can be captured in a graph)
@@ -503,7 +518,8 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
 // Coarse-grid correction of the interface solve: the coarse space from the
 // partition (a refactor keeps it), S Z = G Z - F D^{-1} E Z from one interior
 // sweep per (subdomain, coarse column) pair, E_c = Z^T S Z and its inverse.
-void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipStream_t s, PlanCache* cache) {
+void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipStream_t s, PlanCache* cache,
+                  const std::function<void()>& side_work) {
   const Plan& pl = pc->plan;
   CoarsePlan& cp = pc->coarse;
   pc->coarse_nc = 0;
@@ -547,7 +563,10 @@ void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipS
   pc->cz_beoff.upload(cp.blk_eoff, s);
   const int64_t ec_total = cp.blk_eoff.empty() ? 0 : cp.blk_eoff.back();
   pc->cz_einv.alloc(sizeof(double) * std::max<int64_t>(ec_total, 1));
-  if (nc == 0) return;
+  if (nc == 0) {
+    side_work();
+    return;
+  }
   std::vector<int32_t> int_off(pl.m);
   for (int32_t j = 0; j < pl.m; ++j) int_off[j] = pl.subs[j].int_off;
   DevBuf psub, pcol, poff, cpp, subof, ioff, W, scratch, perm, work, info;
@@ -565,13 +584,10 @@ void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipS
   // one FP64 refinement step: E_c^{-1} amplifies errors of S Z by cond(E_c),
   // and the sweep's explicitly inverted blocks (or FP32 factors) leave
   // W = D^{-1} E Z accurate only to eps * cond(A_jj) of the storage
-  {
-    DevBuf dW;
-    dW.alloc(sizeof(double) * std::max<int64_t>(cp.pair_total, 1));
-    launch_coarse_refine(pc, npairs, psub.as<int32_t>(), pcol.as<int32_t>(), poff.as<int64_t>(), W.as<double>(),
-                         scratch.as<double>(), dW.as<double>(), s);
-    ADDNS_HIP(hipStreamSynchronize(s));
-  }
+  DevBuf dW;
+  dW.alloc(sizeof(double) * std::max<int64_t>(cp.pair_total, 1));
+  launch_coarse_refine(pc, npairs, psub.as<int32_t>(), pcol.as<int32_t>(), poff.as<int64_t>(), W.as<double>(),
+                       scratch.as<double>(), dW.as<double>(), s);
   launch_coarse_sz(pc, subof.as<int32_t>(), psub.as<int32_t>(), cpp.as<int32_t>(), poff.as<int64_t>(),
                    ioff.as<int32_t>(), W.as<double>(), s);
   double* Ec = pc->cz_einv.as<double>();
@@ -582,6 +598,9 @@ void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipS
   info.alloc(sizeof(int32_t));
   ADDNS_HIP(hipMemsetAsync(info.p, 0, sizeof(int32_t), s));
   launch_gj_invert(pc, Ec, perm.as<int32_t>(), work.as<double>(), info.as<int32_t>(), s);
+  // the whole chain is queued: the side work runs beside it (before the
+  // read of the pivot flag, which waits for the chain)
+  side_work();
   int32_t h_info = 0;
   ADDNS_HIP(hipMemcpyAsync(&h_info, info.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   ADDNS_HIP(hipStreamSynchronize(s));
@@ -797,15 +816,16 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
       addns_precond_opts oo = o;
       oo.block_mult = mult;
       if (!p->cache) p->cache = std::make_shared<PlanCache>();
-      setup_device(pc.get(), &p->d, d_rowptr, d_colidx, d_vals, oo, as_stream(stream), p->cache.get());
+      // the chunk count from the plan model, and the chunked sweep's
+      // responses built beside the coarse setup
+      auto chunks = [&](hipStream_t cs) { choose_sweep_chunks(pc.get(), o.sweep_chunks, cs); };
+      setup_device(pc.get(), &p->d, d_rowptr, d_colidx, d_vals, oo, as_stream(stream), p->cache.get(), chunks);
       pc->opts = oo;
       if (o.schur == ADDNS_SCHUR_LEARNED) {
         pc->learned_w.assign(o.learned_model, o.learned_model + mlp_param_count());
         pc->opts.learned_model = nullptr;  // the caller's array is not kept
       }
-      // chunk count from the plan model, then the zero-slot form of the
-      // sweep that will run
-      choose_sweep_chunks(pc.get(), o.sweep_chunks, as_stream(stream));
+      // then the zero-slot form of the sweep that will run
       choose_zero_skip(pc.get(), o.sweep_zero_skip, as_stream(stream));
       pc->opts.sweep_chunks = pc->sweep_chunks;
       return pc;
@@ -824,9 +844,10 @@ int addns_precond_refactor(addns_precond_t pc, const int32_t* d_rowptr, const in
     addns_precond_opts o = pc->opts;
     if (o.schur == ADDNS_SCHUR_LEARNED) o.learned_model = pc->learned_w.data();
     pc->valid = 0;
-    setup_device(pc, nullptr, d_rowptr, d_colidx, d_vals, o, as_stream(stream));
     // the chunk responses belong to the factors
-    if (pc->sweep_chunks > 1) build_chunked_sweep(pc, pc->sweep_chunks, as_stream(stream));
+    setup_device(pc, nullptr, d_rowptr, d_colidx, d_vals, o, as_stream(stream), nullptr, [&](hipStream_t cs) {
+      if (pc->sweep_chunks > 1) build_chunked_sweep(pc, pc->sweep_chunks, cs);
+    });
     pc->valid = 1;
     return ADDNS_OK;
   });

@@ -1062,11 +1062,17 @@ void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
   for (const SubInfo& q : pl.subs) klmax = std::max(klmax, q.kl);
   if (chunk_smem_bytes(pl.maxW, pl.nbU, S, chunk_stack_words(p, klmax, pl.nbU)) > 160 * 1024)
     throw ArgError("sweep_chunks too large for the chunk kernels' LDS");
-  // coupling columns of every chunk boundary, from the stored U_{b,b+1}
+  // coupling columns of every chunk boundary, from the stored U_{b,b+1},
+  // and the zero rows of the lower block matrices with the gather indices
+  // (for the pure carry positions below): one wait for both
+  const int32_t nlb = (int32_t)pl.lblks.size();
   std::vector<uint8_t> flags((size_t)m * p * pl.nbU, 0);
+  std::vector<uint8_t> zrow((size_t)std::max(nlb, 1) * klmax, 0);
+  std::vector<int32_t> h_lperm((size_t)std::max<int64_t>(pl.lperm_total, 1));
   {
-    DevBuf d_flags;
+    DevBuf d_flags, d_z;
     d_flags.alloc(flags.size());
+    d_z.alloc(zrow.size());
     ADDNS_HIP(hipMemsetAsync(d_flags.p, 0, flags.size(), s));
     if (pc->interior_prec == P64)
       k_chunk_nzcols<double><<<m * (p - 1), 256, 0, s>>>(pc->subs.as<SubInfo>(), pc->u12.as<double>(), p,
@@ -1074,7 +1080,18 @@ void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
     else
       k_chunk_nzcols<float><<<m * (p - 1), 256, 0, s>>>(pc->subs.as<SubInfo>(), pc->u12.as<float>(), p,
                                                         pl.nbU, d_flags.as<uint8_t>());
+    if (nlb > 0) {
+      if (pc->interior_prec == P64)
+        k_lower_zero_rows<double><<<nlb, 256, 0, s>>>(pc->lblks.as<LBlk>(), pc->subs.as<SubInfo>(), pc->lmat.as<double>(),
+                                                      klmax, d_z.as<uint8_t>());
+      else
+        k_lower_zero_rows<float><<<nlb, 256, 0, s>>>(pc->lblks.as<LBlk>(), pc->subs.as<SubInfo>(), pc->lmat.as<float>(),
+                                                     klmax, d_z.as<uint8_t>());
+    }
     ADDNS_HIP(hipMemcpyAsync(flags.data(), d_flags.p, flags.size(), hipMemcpyDeviceToHost, s));
+    if (nlb > 0) ADDNS_HIP(hipMemcpyAsync(zrow.data(), d_z.p, zrow.size(), hipMemcpyDeviceToHost, s));
+    if (pl.lperm_total > 0)
+      ADDNS_HIP(hipMemcpyAsync(h_lperm.data(), pc->lperm.p, sizeof(int32_t) * pl.lperm_total, hipMemcpyDeviceToHost, s));
     ADDNS_HIP(hipStreamSynchronize(s));
   }
   std::vector<int32_t> nz, nzo((size_t)m * p + 1, 0);
@@ -1087,27 +1104,7 @@ void build_chunked_sweep(addns_precond* pc, int p, hipStream_t s) {
     }
   nzo[(size_t)m * p] = (int32_t)nz.size();
   // pure carry positions at every lower chunk boundary: follow each window
-  // position through the blocks (gather indices and zero rows of the block
-  // matrices, from the stored factors)
-  const int32_t nlb = (int32_t)pl.lblks.size();
-  std::vector<uint8_t> zrow((size_t)std::max(nlb, 1) * klmax, 0);
-  std::vector<int32_t> h_lperm((size_t)std::max<int64_t>(pl.lperm_total, 1));
-  {
-    DevBuf d_z;
-    d_z.alloc(zrow.size());
-    if (nlb > 0) {
-      if (pc->interior_prec == P64)
-        k_lower_zero_rows<double><<<nlb, 256, 0, s>>>(pc->lblks.as<LBlk>(), pc->subs.as<SubInfo>(), pc->lmat.as<double>(),
-                                                      klmax, d_z.as<uint8_t>());
-      else
-        k_lower_zero_rows<float><<<nlb, 256, 0, s>>>(pc->lblks.as<LBlk>(), pc->subs.as<SubInfo>(), pc->lmat.as<float>(),
-                                                     klmax, d_z.as<uint8_t>());
-      ADDNS_HIP(hipMemcpyAsync(zrow.data(), d_z.p, zrow.size(), hipMemcpyDeviceToHost, s));
-    }
-    if (pl.lperm_total > 0)
-      ADDNS_HIP(hipMemcpyAsync(h_lperm.data(), pc->lperm.p, sizeof(int32_t) * pl.lperm_total, hipMemcpyDeviceToHost, s));
-    ADDNS_HIP(hipStreamSynchronize(s));
-  }
+  // position through the blocks
   std::vector<int32_t> prow((size_t)m * p * klmax, -1), np, npo((size_t)m * p + 1, 0);
   for (int32_t j = 0; j < m; ++j) {
     const SubInfo& q = pl.subs[j];
