@@ -71,6 +71,11 @@ struct DevBuf {
     alloc(v.size() * sizeof(T));
     if (!v.empty()) ADDNS_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
   }
+  // a device-side copy of another buffer (same size)
+  void copy_from(const DevBuf& o, hipStream_t s) {
+    alloc(o.bytes);
+    ADDNS_HIP(hipMemcpyAsync(p, o.p, o.bytes, hipMemcpyDeviceToDevice, s));
+  }
 };
 
 // Per-subdomain sweep geometry (POD, shared by host and device).
@@ -196,7 +201,20 @@ void build_coarse_plan(const PartitionData& P, const Plan& pl, int32_t piece, Co
 // arrays that do not depend on the matrix values).
 struct PlanMaps {
   DevBuf cp_src, cp_orow, e_src, f_src, band_dst, band_src, dense_dst, dense_src;
+  // the plan's structure that every handle keeps a copy of
+  DevBuf perm, iperm, cp_rowptr, cp_colidx, e_rowptr, e_colidx, f_rowptr, f_colidx, subs, lblks, ublks;
   void upload(const Plan& pl, hipStream_t s) {
+    perm.upload(pl.perm, s);
+    iperm.upload(pl.iperm, s);
+    cp_rowptr.upload(pl.cp_rowptr, s);
+    cp_colidx.upload(pl.cp_colidx, s);
+    e_rowptr.upload(pl.e_rowptr, s);
+    e_colidx.upload(pl.e_colidx, s);
+    f_rowptr.upload(pl.f_rowptr, s);
+    f_colidx.upload(pl.f_colidx, s);
+    subs.upload(pl.subs, s);
+    lblks.upload(pl.lblks, s);
+    ublks.upload(pl.ublks, s);
     cp_src.upload(pl.cp_src, s);
     cp_orow.upload(pl.cp_orow, s);
     e_src.upload(pl.e_src, s);
