@@ -361,15 +361,17 @@ __global__ void __launch_bounds__(1024) k_gj_fused(double* __restrict__ A, const
 // The same again with the block in registers: thread t holds column t % n,
 // rows t / n + R m (m < M) with R = 1024 / n row groups, for blocks with
 // n <= R M.  A step moves only column k, rows k and p and the pivot through
-// LDS, so the matrix is read from and written to memory once.  Same
-// operations on every element in the same order, so the same inverse bit
-// for bit.
+// LDS, so the matrix is read from and written to memory once.  Every wave
+// finds the pivot itself (the same search over the same column, so the same
+// row), and the update of step k leaves column k + 1 in the other of two
+// column buffers: two barriers a step.  Same operations on every element in
+// the same order, so the same inverse bit for bit.
 constexpr int kGjRegs = 26;
 template <int M>
 __global__ void __launch_bounds__(1024) k_gj_regs(double* __restrict__ A, const int32_t* __restrict__ boff,
                                                   const int64_t* __restrict__ beoff, int32_t* __restrict__ perm,
                                                   int32_t* __restrict__ info) {
-  __shared__ double colk[kGjFusedMax], rowp[kGjFusedMax], rowk[kGjFusedMax];
+  __shared__ double colk[2][kGjFusedMax], rowp[kGjFusedMax], rowk[kGjFusedMax];
   __shared__ double red[16];
   __shared__ int32_t s_p[kGjFusedMax];
   const int32_t b = blockIdx.x;
@@ -385,6 +387,7 @@ __global__ void __launch_bounds__(1024) k_gj_regs(double* __restrict__ A, const 
     const int32_t i = g + R * q;
     a[q] = (jv && i < n) ? G[i * n + j] : 0.0;
     m = fmax(m, fabs(a[q]));
+    if (jv && j == 0 && i < n) colk[0][i] = a[q];
   }
   for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
   if (lane == 0) red[wave] = m;
@@ -392,37 +395,32 @@ __global__ void __launch_bounds__(1024) k_gj_regs(double* __restrict__ A, const 
   double amax = 0.0;
   for (int w = 0; w < nw; ++w) amax = fmax(amax, red[w]);
   for (int32_t k = 0; k < n; ++k) {
-    if (jv && j == k)
-#pragma unroll
-      for (int q = 0; q < M; ++q)
-        if (g + R * q < n) colk[g + R * q] = a[q];
-    __syncthreads();
-    if (wave == 0) {
-      double best = -1.0;
-      int32_t bidx = n;
-      for (int32_t i = k + lane; i < n; i += 64) {
-        const double v = fabs(colk[i]);
-        if (v > best) {
-          best = v;
-          bidx = i;
-        }
-      }
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double v2 = __shfl_xor(best, off);
-        const int32_t i2 = __shfl_xor(bidx, off);
-        if (v2 > best || (v2 == best && i2 < bidx)) {
-          best = v2;
-          bidx = i2;
-        }
-      }
-      if (lane == 0) {
-        s_p[k] = bidx;
-        perm[o + k] = bidx;
-        if (!(best > 1e-13 * amax) && info[0] == 0) info[0] = o + k + 1;
+    const double* ck = colk[k & 1];
+    double* cn = colk[(k + 1) & 1];
+    double best = -1.0;
+    int32_t bidx = n;
+    for (int32_t i = k + lane; i < n; i += 64) {
+      const double v = fabs(ck[i]);
+      if (v > best) {
+        best = v;
+        bidx = i;
       }
     }
-    __syncthreads();
-    const int32_t p = s_p[k];
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double v2 = __shfl_xor(best, off);
+      const int32_t i2 = __shfl_xor(bidx, off);
+      if (v2 > best || (v2 == best && i2 < bidx)) {
+        best = v2;
+        bidx = i2;
+      }
+    }
+    // lane 0's row, as one search would give it
+    const int32_t p = __shfl(bidx, 0);
+    if (tid == 0) {
+      s_p[k] = p;
+      perm[o + k] = p;
+      if (!(best > 1e-13 * amax) && info[0] == 0) info[0] = o + k + 1;
+    }
     if (jv)
 #pragma unroll
       for (int q = 0; q < M; ++q) {
@@ -442,8 +440,9 @@ __global__ void __launch_bounds__(1024) k_gj_regs(double* __restrict__ A, const 
         const int32_t src = i == k ? p : (i == p ? k : i);
         const double x = i == p ? kj : (i == k ? pj : a[q]);  // the interchange
         if (i == k) a[q] = j == k ? inv : pj * inv;
-        else if (j == k) a[q] = -colk[src] * inv;
-        else a[q] = x - colk[src] * (pj * inv);
+        else if (j == k) a[q] = -ck[src] * inv;
+        else a[q] = x - ck[src] * (pj * inv);
+        if (j == k + 1) cn[i] = a[q];
       }
     }
     __syncthreads();
