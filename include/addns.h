@@ -232,8 +232,11 @@ typedef struct {
   int32_t sweep_zero_skip;  /* sweep form: 0 = time the sweep with and without
                              loading only each stored column's nonzero rows and
                              keep the faster (the default; both give the same
-                             result bit for bit); 1 = never skip; 2 = always
-                             skip; else ADDNS_ERR_ARG */
+                             result bit for bit; a later setup on the same
+                             partition and device with the same interior_prec,
+                             sweep_chunks and ilu_tol reuses the first timing);
+                             1 = never skip; 2 = always skip; else
+                             ADDNS_ERR_ARG */
   int32_t block_sizing;   /* sweep block sizes: 1 = one size for every interior
                              (the widest band sets it: fewest dependent steps);
                              2 = each interior its own (fewest bytes and least

@@ -74,6 +74,7 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
       if (cache) {
         cache->plan = pl;
         cache->maps_dev = -1;
+        cache->zs_choice = -1;
         cache->have_plan = true;
         cache->have_coarse = false;
         cache->schur = o.schur;
@@ -698,10 +699,18 @@ void choose_sweep_chunks(addns_precond* pc, int requested, hipStream_t s) {
 
 // Zero-slot form of the sweep in use (single-workgroup or chunked): the
 // caller's choice, or the faster of the two by timing.  Both give the same
-// result bit for bit, so the timing never changes numerics.
-void choose_zero_skip(addns_precond* pc, int requested, hipStream_t s) {
+// result bit for bit, so the timing never changes numerics.  A later setup
+// on the same plan (the partition's cache) and device with the same interior
+// precision, chunk count and drop tolerance takes the choice timed before.
+void choose_zero_skip(addns_precond* pc, int requested, double ilu_tol, hipStream_t s, PlanCache* cache) {
   if (requested != 0) {
     pc->zero_skip = requested == 2 ? 1 : 0;
+    return;
+  }
+  if (cache && cache->zs_choice >= 0 && cache->zs_dev == pc->device && cache->zs_prec == pc->interior_prec &&
+      cache->zs_chunks == pc->sweep_chunks && cache->zs_ilu == ilu_tol) {
+    pc->zero_skip = cache->zs_choice;
+    pc->tuned_ms = cache->zs_ms;
     return;
   }
   float ms[2];
@@ -711,6 +720,14 @@ void choose_zero_skip(addns_precond* pc, int requested, hipStream_t s) {
   }
   pc->zero_skip = ms[1] < ms[0] ? 1 : 0;
   pc->tuned_ms = std::min(ms[0], ms[1]);
+  if (cache) {
+    cache->zs_choice = pc->zero_skip;
+    cache->zs_dev = pc->device;
+    cache->zs_prec = pc->interior_prec;
+    cache->zs_chunks = pc->sweep_chunks;
+    cache->zs_ilu = ilu_tol;
+    cache->zs_ms = pc->tuned_ms;
+  }
 }
 
 struct GmresWork {
@@ -825,7 +842,7 @@ int addns_setup_precond(addns_partition_t p, int32_t N, const int32_t* d_rowptr,
         pc->opts.learned_model = nullptr;  // the caller's array is not kept
       }
       // then the zero-slot form of the sweep that will run
-      choose_zero_skip(pc.get(), o.sweep_zero_skip, as_stream(stream));
+      choose_zero_skip(pc.get(), o.sweep_zero_skip, o.ilu_tol, as_stream(stream), p->cache.get());
       pc->opts.sweep_chunks = pc->sweep_chunks;
       return pc;
     };

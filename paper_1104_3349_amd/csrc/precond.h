@@ -235,6 +235,12 @@ struct PlanCache {
   // a repeated setup of the same partition does not upload them again
   int maps_dev = -1;
   PlanMaps maps;
+  // the timed zero-slot choice of the sweep on this plan (-1: none yet),
+  // with the interior precision, chunk count and ILU drop tolerance it was
+  // timed for
+  int zs_choice = -1, zs_prec = -1, zs_chunks = -1, zs_dev = -1;
+  double zs_ilu = -1.0;
+  float zs_ms = 0.0f;
 };
 
 // Largest coarse space the two-level interface solve accepts (its dense
