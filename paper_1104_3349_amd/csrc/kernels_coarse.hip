@@ -310,7 +310,6 @@ __global__ void __launch_bounds__(1024) k_gj_fused(double* __restrict__ A, const
       }
       if (lane == 0) {
         s_p[k] = bidx;
-        perm[o + k] = bidx;
         if (!(best > 1e-13 * amax) && info[0] == 0) info[0] = o + k + 1;
       }
     }
@@ -340,6 +339,8 @@ __global__ void __launch_bounds__(1024) k_gj_fused(double* __restrict__ A, const
     }
     __syncthreads();
   }
+  // the pivot rows go to memory once, after the loop
+  for (int32_t k = tid; k < n; k += blockDim.x) perm[o + k] = s_p[k];
   // column interchanges undone, one thread per row
   for (int32_t r = tid; r < n; r += blockDim.x) {
     double* row = E + r * n;
@@ -418,7 +419,6 @@ __global__ void __launch_bounds__(1024) k_gj_regs(double* __restrict__ A, const 
     const int32_t p = __shfl(bidx, 0);
     if (tid == 0) {
       s_p[k] = p;
-      perm[o + k] = p;
       if (!(best > 1e-13 * amax) && info[0] == 0) info[0] = o + k + 1;
     }
     if (jv)
@@ -447,6 +447,9 @@ __global__ void __launch_bounds__(1024) k_gj_regs(double* __restrict__ A, const 
     }
     __syncthreads();
   }
+  // the pivot rows go to memory once, after the loop: a store in a step
+  // would hold the step's barrier until it completes
+  for (int32_t k = tid; k < n; k += blockDim.x) perm[o + k] = s_p[k];
   // column interchanges undone: column j ends where the swaps k = n-1 .. 0,
   // applied in order, move it
   if (jv) {
