@@ -128,6 +128,50 @@ def test_coarse_refactor_equals_fresh_setup():
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_coarse_with_chunks_repeated_setups_refactor_and_errors():
+    """The chunked sweep's responses are built on a second stream while the
+    coarse chain runs; later setups on the same partition reuse its cached
+    plan and timed zero-slot choice.  Every route gives the same apply bit
+    for bit: a second setup on the partition, a setup on a fresh partition,
+    a setup after one that failed inside the chunk build (too many chunks,
+    raised while the coarse kernels were queued), and a refactor against a
+    fresh setup of the new matrix."""
+    kw, piece = CASES["mid"]
+    S = make_system(**kw)
+    S2 = make_system(**dict(kw, nu=0.02))
+    part, pc = gpu_precond(S, coarse=piece, sweep_chunks=1)
+    nbu = pc.info()["nb_upper"]
+    pmax = int(min(-(-int(n) // nbu) for n in np.diff(part.export().int_offsets) if n > 0))
+    if pmax < 2:
+        pytest.skip("interiors too short for two chunks")
+    p = min(3, pmax)
+    y = _cuda(np.random.default_rng(5).standard_normal(S.N))
+
+    def apply(h):
+        d_x = torch.zeros(S.N, dtype=torch.float64, device="cuda")
+        addns.apply_precond(h, y, d_x)
+        torch.cuda.synchronize()
+        return d_x.cpu().numpy()
+
+    _, first = gpu_precond(S, part=part, coarse=piece, sweep_chunks=p)
+    assert first.info()["sweep_chunks"] == p
+    x1 = apply(first)
+    _, again = gpu_precond(S, part=part, coarse=piece, sweep_chunks=p)
+    assert np.array_equal(apply(again), x1)
+    _, fresh = gpu_precond(S, coarse=piece, sweep_chunks=p)
+    assert np.array_equal(apply(fresh), x1)
+    with pytest.raises(addns.AddnsError) as e:
+        gpu_precond(S, part=part, coarse=piece, sweep_chunks=pmax + 1)
+    assert e.value.code == addns.ERR_ARG
+    _, after = gpu_precond(S, part=part, coarse=piece, sweep_chunks=p)
+    assert np.array_equal(apply(after), x1)
+    bm = first.info()["block_mult"]
+    addns.refactor_precond(first, _cuda(S2.rp), _cuda(S2.ci), _cuda(S2.v))
+    _, fresh2 = gpu_precond(S2, part=part, coarse=piece, sweep_chunks=p, block_mult=bm)
+    assert np.array_equal(apply(first), apply(fresh2))
+    assert not np.array_equal(apply(fresh2), x1)
+
+
 def test_coarse_argument_errors():
     S = make_system(n=12, nu=0.1, m=3, sz=16, seed=2)
     for bad in (dict(coarse=-1), dict(coarse=65), dict(coarse=8, overlap=4)):
