@@ -56,8 +56,8 @@ void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipS
 // Builds the plan from P (or keeps the handle's plan when P is null: a
 // refactor) and computes every numeric part of the preconditioner.
 // side_work, if given, is called once, with a stream of its own that has
-// seen the final interior factors, while the coarse column solves (when
-// there are any) are in flight on s; it must leave that stream drained.
+// seen the final interior factors, while the coarse setup's kernels (when
+// there are any) are queued on s; it must leave that stream drained.
 void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_rowptr, const int32_t* d_colidx,
                   const double* d_vals, const addns_precond_opts& o, hipStream_t s, PlanCache* cache = nullptr,
                   const std::function<void(hipStream_t)>& side_work = {}) {
@@ -471,7 +471,7 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
   }
 
   // -- coarse-grid correction of the interface solve (section 6), with the
-  // caller's side work on another stream beside its column solves
+  // caller's side work on another stream beside its kernels
   ADDNS_HIP(hipEventRecord(ready, s));  // the interior factors are final
   auto side = [&]() {
     if (!side_work) return;
@@ -518,6 +518,8 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
 // Coarse-grid correction of the interface solve: the coarse space from the
 // partition (a refactor keeps it), S Z = G Z - F D^{-1} E Z from one interior
 // sweep per (subdomain, coarse column) pair, E_c = Z^T S Z and its inverse.
+// side_work is called once, after all of that is queued on s and before the
+// host waits for it.
 void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipStream_t s, PlanCache* cache,
                   const std::function<void()>& side_work) {
   const Plan& pl = pc->plan;
