@@ -77,6 +77,7 @@ void setup_device(addns_precond* pc, const PartitionData* P, const int32_t* d_ro
         cache->zs_choice = -1;
         cache->have_plan = true;
         cache->have_coarse = false;
+        cache->cmaps_dev = -1;
         cache->schur = o.schur;
         cache->block_mult = std::max(1, o.block_mult);
         cache->overlap = o.overlap;
@@ -534,6 +535,7 @@ void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipS
         cache->coarse = cp;
         cache->have_coarse = true;
         cache->piece = piece;
+        cache->cmaps_dev = -1;
       }
     }
   }
@@ -541,43 +543,53 @@ void setup_coarse(addns_precond* pc, const PartitionData* P, int32_t piece, hipS
   const int32_t nc = z.nc;
   if (nc > kMaxCoarseColumns)
     throw ArgError("coarse space of " + std::to_string(nc) + " columns exceeds 8192 (use a larger piece size)");
-  pc->cz_piece.upload(z.node_piece, s);
-  pc->cz_z0.upload(z.node_z0, s);
-  pc->cz_z1.upload(z.node_z1, s);
-  pc->cz_colp.upload(z.col_piece, s);
-  pc->cz_colk.upload(z.col_kind, s);
-  pc->cz_p0.upload(z.piece_col0, s);
-  pc->cz_p1.upload(z.piece_col1, s);
-  pc->cz_szp.upload(cp.sz_rowptr, s);
-  pc->cz_szc.upload(cp.sz_col, s);
+  // the coarse plan's arrays: kept on the partition's cache for later setups
+  CoarseMaps local_maps;
+  CoarseMaps* cm = &local_maps;
+  {
+    int dev = 0;
+    ADDNS_HIP(hipGetDevice(&dev));
+    if (P && cache && cache->have_coarse && cache->piece == piece) {
+      cm = &cache->cmaps;
+      if (cache->cmaps_dev != dev) {
+        cache->cmaps.upload(cp, pl, s);
+        cache->cmaps_dev = dev;
+      }
+    } else {
+      local_maps.upload(cp, pl, s);
+    }
+  }
+  pc->cz_piece.copy_from(cm->piece, s);
+  pc->cz_z0.copy_from(cm->z0, s);
+  pc->cz_z1.copy_from(cm->z1, s);
+  pc->cz_colp.copy_from(cm->colp, s);
+  pc->cz_colk.copy_from(cm->colk, s);
+  pc->cz_p0.copy_from(cm->p0, s);
+  pc->cz_p1.copy_from(cm->p1, s);
+  pc->cz_szp.copy_from(cm->szp, s);
+  pc->cz_szc.copy_from(cm->szc, s);
   pc->cz_szv.alloc(sizeof(double) * cp.sz_col.size());
-  pc->cz_goff.upload(cp.grp_off, s);
-  pc->cz_grows.upload(cp.grp_rows, s);
-  pc->cz_gc0.upload(cp.grp_col0, s);
-  pc->cz_gc1.upload(cp.grp_col1, s);
-  pc->cz_gcoff.upload(cp.grp_coff, s);
-  pc->cz_gcols.upload(cp.grp_cols, s);
+  pc->cz_goff.copy_from(cm->goff, s);
+  pc->cz_grows.copy_from(cm->grows, s);
+  pc->cz_gc0.copy_from(cm->gc0, s);
+  pc->cz_gc1.copy_from(cm->gc1, s);
+  pc->cz_gcoff.copy_from(cm->gcoff, s);
+  pc->cz_gcols.copy_from(cm->gcols, s);
   pc->cz_t.alloc(sizeof(double) * std::max<int32_t>(pl.nsep, 1));
   pc->cz_g.alloc(sizeof(double) * std::max<int32_t>(nc, 1));
   pc->cz_y.alloc(sizeof(double) * std::max<int32_t>(nc, 1));
-  pc->cz_boff.upload(cp.blk_off, s);
-  pc->cz_cblk.upload(cp.col_blk, s);
-  pc->cz_beoff.upload(cp.blk_eoff, s);
+  pc->cz_boff.copy_from(cm->boff, s);
+  pc->cz_cblk.copy_from(cm->cblk, s);
+  pc->cz_beoff.copy_from(cm->beoff, s);
   const int64_t ec_total = cp.blk_eoff.empty() ? 0 : cp.blk_eoff.back();
   pc->cz_einv.alloc(sizeof(double) * std::max<int64_t>(ec_total, 1));
   if (nc == 0) {
     side_work();
     return;
   }
-  std::vector<int32_t> int_off(pl.m);
-  for (int32_t j = 0; j < pl.m; ++j) int_off[j] = pl.subs[j].int_off;
-  DevBuf psub, pcol, poff, cpp, subof, ioff, W, scratch, perm, work, info;
-  psub.upload(cp.pair_sub, s);
-  pcol.upload(cp.pair_col, s);
-  poff.upload(cp.pair_off, s);
-  cpp.upload(cp.cpair_ptr, s);
-  subof.upload(cp.sub_of, s);
-  ioff.upload(int_off, s);
+  const DevBuf &psub = cm->psub, &pcol = cm->pcol, &poff = cm->poff, &cpp = cm->cpp, &subof = cm->subof,
+               &ioff = cm->ioff;
+  DevBuf W, scratch, perm, work, info;
   W.alloc(sizeof(double) * std::max<int64_t>(cp.pair_total, 1));
   scratch.alloc(sizeof(double) * std::max<int64_t>(cp.pair_total, 1));
   const int32_t npairs = (int32_t)cp.pair_sub.size();

@@ -226,6 +226,42 @@ struct PlanMaps {
   }
 };
 
+// Device copies of a coarse plan's arrays: those every handle keeps a copy
+// of, and the (subdomain, column) pair lists of the setup's column solves.
+struct CoarseMaps {
+  DevBuf piece, z0, z1, colp, colk, p0, p1, szp, szc, goff, grows, gc0, gc1, gcoff, gcols, boff, cblk, beoff;
+  DevBuf psub, pcol, poff, cpp, subof, ioff;
+  void upload(const CoarsePlan& cp, const Plan& pl, hipStream_t s) {
+    const CoarseSpace& z = cp.space;
+    piece.upload(z.node_piece, s);
+    z0.upload(z.node_z0, s);
+    z1.upload(z.node_z1, s);
+    colp.upload(z.col_piece, s);
+    colk.upload(z.col_kind, s);
+    p0.upload(z.piece_col0, s);
+    p1.upload(z.piece_col1, s);
+    szp.upload(cp.sz_rowptr, s);
+    szc.upload(cp.sz_col, s);
+    goff.upload(cp.grp_off, s);
+    grows.upload(cp.grp_rows, s);
+    gc0.upload(cp.grp_col0, s);
+    gc1.upload(cp.grp_col1, s);
+    gcoff.upload(cp.grp_coff, s);
+    gcols.upload(cp.grp_cols, s);
+    boff.upload(cp.blk_off, s);
+    cblk.upload(cp.col_blk, s);
+    beoff.upload(cp.blk_eoff, s);
+    psub.upload(cp.pair_sub, s);
+    pcol.upload(cp.pair_col, s);
+    poff.upload(cp.pair_off, s);
+    cpp.upload(cp.cpair_ptr, s);
+    subof.upload(cp.sub_of, s);
+    std::vector<int32_t> int_off(pl.m);
+    for (int32_t j = 0; j < pl.m; ++j) int_off[j] = pl.subs[j].int_off;
+    ioff.upload(int_off, s);
+  }
+};
+
 struct PlanCache {
   bool have_plan = false, have_coarse = false;
   int schur = -1, block_mult = -1, overlap = -1, piece = -1, per_interior = -1;
@@ -238,6 +274,10 @@ struct PlanCache {
   // the timed zero-slot choice of the sweep on this plan (-1: none yet),
   // with the interior precision, chunk count and ILU drop tolerance it was
   // timed for
+  // the coarse plan's arrays on device cmaps_dev (-1: none yet, or the
+  // coarse plan changed)
+  int cmaps_dev = -1;
+  CoarseMaps cmaps;
   int zs_choice = -1, zs_prec = -1, zs_chunks = -1, zs_dev = -1;
   double zs_ilu = -1.0;
   float zs_ms = 0.0f;
